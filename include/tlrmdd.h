@@ -1,0 +1,189 @@
+/*
+ * tlrmdd.h - C ABI of the MI355X (gfx950) tile low-rank multidimensional
+ * deconvolution (TLR-MDD) library.
+ *
+ * Method: Chen, Ravasi, Keyes, "Reciprocity-aware adaptive tile low-rank
+ * factorization for large-scale 3D multidimensional deconvolution"
+ * (arXiv 2412.14973). For one frequency the library evaluates
+ *     f(theta) = 1/2 || D C(theta) - U ||_F^2            (ADMM solver, eq. X2LQR_lst)
+ * and its gradient with respect to every tile factor (ADMM solver, eqs. DXLR),
+ * where X = C(theta) is the complex-symmetric Green's function assembled from
+ * tiles (Tile Low-rank MDD section):
+ *     X_ii = Q_ii Q_ii^T  (low-rank diagonal)  or  X_ii = (Z_ii + Z_ii^T)/2  (dense),
+ *     X_ij = L_ij R_ij  (i > j),   X_ji = X_ij^T.
+ * Columns of D and U are expected in Hilbert order (Receivers re-ordering
+ * section, eq. axb_sd); hilbert_order() and tlrmdd_permute_columns() produce it.
+ *
+ * Conventions shared by every entry point
+ *  - Complex data is complex64 interleaved (re, im float pairs), row-major and
+ *    contiguous: D and U are ns x nr, X is nr x nr, theta is a flat vector.
+ *  - "device" pointers are HIP device memory; "host" pointers are host memory.
+ *    The caller owns every buffer; the library never frees caller memory and
+ *    keeps no pointer to it after the call returns (work is stream ordered).
+ *  - Device calls enqueue work on `stream` and return without synchronising;
+ *    scalar results are written to device FP64 memory (synchronise the stream
+ *    before reading them on the host).
+ *  - No C++ exception crosses the ABI. Every int-returning call returns one of
+ *    the TLRMDD_* status codes; tlrmdd_last_error() gives a thread-local
+ *    message for the most recent failure on the calling thread.
+ *  - Gradient convention: grad = df/dRe(theta) + i df/dIm(theta)
+ *    (= 2 df/d conj(theta)); with W = D^H (D X - U) this is the convention in
+ *    which the paper writes grad L = W' R^H, grad R = L^H W', grad Q = W' conj(Q),
+ *    grad Z = W'/2 with W' = W + W^T.
+ *
+ * theta packing (stacks Zbar, Lbar, Rbar of the Tile Low-rank MDD section):
+ *   all diagonal blocks in tile order (Q_ii: d_i x k_ii, or Z_ii: d_i x d_i),
+ *   then every L_t (d_i x k_t), then every R_t (k_t x d_j), each row-major,
+ *   with sub-diagonal tiles (i > j) numbered t = i(i-1)/2 + j (0-based).
+ */
+#ifndef TLRMDD_H
+#define TLRMDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define TLRMDD_OK               0
+#define TLRMDD_INVALID_ARGUMENT 1  /* bad pointer, size, layout or option        */
+#define TLRMDD_WORKSPACE        2  /* workspace too small / allocation failed    */
+#define TLRMDD_HIP_ERROR        3  /* a HIP runtime call failed                  */
+#define TLRMDD_NONFINITE        4  /* non-finite value met (solve)               */
+#define TLRMDD_UNSUPPORTED      5  /* e.g. unknown precision                     */
+
+/* ---- precisions of the bulk complex products ------------------------------ */
+#define TLRMDD_FP32      0  /* FP32 MFMA, complex as a real 2x2 block (4 real products) */
+#define TLRMDD_BF16X3    1  /* BF16 hi+lo split (hi*hi + hi*lo + lo*hi), FP32 accumulate */
+
+/* ---- optimisers ------------------------------------------------------------ */
+#define TLRMDD_LBFGS 0
+#define TLRMDD_GD    1
+
+/* Tile layout of one frequency (Tile Low-rank MDD section).
+ * tile_size: host, ntiles entries d_i >= 1 with sum d_i == nr (a ragged last
+ *            tile is allowed; the paper notes equal sizes are not required).
+ * rank_off:  host, ntiles(ntiles-1)/2 entries, k_t for tile (i, j), i > j,
+ *            t = i(i-1)/2 + j, 1 <= k_t <= min(d_i, d_j).
+ * rank_diag: host, ntiles entries: k_ii in [1, d_i] -> Q_ii Q_ii^T, or -1 ->
+ *            dense symmetrised Z_ii.
+ * ns:        number of sources (rows of D and U). */
+typedef struct {
+    int64_t nr;
+    int64_t ns;
+    int32_t ntiles;
+    const int32_t *tile_size;
+    const int32_t *rank_off;
+    const int32_t *rank_diag;
+} tlrmdd_layout;
+
+/* Options of tlrmdd_solve (ADMM solver section: the X-update uses limited-
+ * memory BFGS; here with an exact line search on the quartic f(theta+a p)). */
+typedef struct {
+    int32_t iters;          /* fixed iteration count T >= 0                        */
+    int32_t optimizer;      /* TLRMDD_LBFGS or TLRMDD_GD                           */
+    int32_t lbfgs_m;        /* L-BFGS memory, 1..32 (default 5)                     */
+    int32_t precision;      /* TLRMDD_FP32 or TLRMDD_BF16X3                         */
+    double  lambda;         /* Frobenius regulariser lambda ||theta||^2 (0 = none)  */
+    int32_t resid_refresh;  /* recompute r = D C(theta) - U every this many iters (0 = never) */
+    int32_t reserved;
+} tlrmdd_opts;
+
+/* Opaque plan: validated layout plus device-side tile tables. */
+typedef struct tlrmdd_plan_s *tlrmdd_plan;
+
+/* Message for a status code (static storage). */
+const char *tlrmdd_status_string(int status);
+/* Thread-local detail for the last failing call on this thread ("" if none). */
+const char *tlrmdd_last_error(void);
+
+/* Number of complex unknowns in theta for `layout`; < 0 if the layout is
+ * invalid (same checks as tlrmdd_plan_create). Host only. */
+int64_t tlrmdd_theta_size(const tlrmdd_layout *layout);
+
+/* Validate `layout` and build a plan on the current HIP device: host tables
+ * plus a small device allocation holding the tile tables (freed by
+ * tlrmdd_plan_destroy). Status 1 on any of: null pointer, nr/ns/ntiles <= 0,
+ * sum d_i != nr, off-diagonal rank outside [1, min(d_i, d_j)], diagonal rank
+ * neither -1 nor in [1, d_i]. */
+int tlrmdd_plan_create(const tlrmdd_layout *layout, tlrmdd_plan *plan_out);
+int tlrmdd_plan_destroy(tlrmdd_plan plan);
+
+/* Workspace (device bytes) needed by an operation on this plan.
+ * op: 0 = forward, 1 = grad, 2 = solve (opts required for solve, may be NULL
+ * otherwise). The workspace need not be zeroed and is reused by the library
+ * as scratch; it may be shared between calls that do not overlap in time. */
+#define TLRMDD_OP_FORWARD 0
+#define TLRMDD_OP_GRAD    1
+#define TLRMDD_OP_SOLVE   2
+int tlrmdd_workspace_bytes(tlrmdd_plan plan, int op, const tlrmdd_opts *opts, size_t *bytes);
+
+/* Objective (eq. X2LQR_lst): f = 1/2 || D C(theta) - U ||_F^2.
+ * D, U:    device, ns x nr complex64 (Hilbert column order).
+ * theta:   device, tlrmdd_theta_size complex64.
+ * f_dev:   device, one double (accumulated in FP64 from FP32 residuals).
+ * r_out:   device or NULL; receives r = D X - U (ns x nr complex64).
+ * X_out:   device or NULL; receives X = C(theta) (nr x nr complex64, exactly
+ *          symmetric bit for bit).
+ * precision: TLRMDD_FP32 or TLRMDD_BF16X3. */
+int tlrmdd_forward(tlrmdd_plan plan, const void *D, const void *U, const void *theta,
+                   double *f_dev, void *r_out, void *X_out, int precision,
+                   void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Objective and gradient (eqs. DXLR): W = D^H r, W' = W + W^T,
+ * grad L_ij = W'_ij R_ij^H, grad R_ij = L_ij^H W'_ij, grad Q_ii = W'_ii conj(Q_ii),
+ * grad Z_ii = W'_ii / 2. The assembled X is recomputed here, never read from
+ * a previous call. grad_out: device, packed like theta. f_dev may be NULL. */
+int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *theta,
+                double *f_dev, void *grad_out, int precision,
+                void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Fixed-count solve of min f(theta) (+ lambda ||theta||^2) from theta_inout
+ * (overwritten with theta_T). Each iteration: gradient from the tracked
+ * residual, L-BFGS two-loop direction (real inner product Re<a,b>, pairs
+ * kept only when Re<s,y> > 0, steepest-descent restart when Re<g,p> >= 0),
+ * exact line search along the quartic phi(a) = f(theta + a p) using
+ * a = D C1(theta;p), b = D C2(p) (one product D [X1 | X2]), then
+ * theta += a* p and r += a* a + a*^2 b. All scalars stay on the device in
+ * FP64; the host only enqueues work.
+ * f_hist_dev: device, iters+1 doubles: f_hist[t] = tracked objective after t
+ * iterations. Returns TLRMDD_OK once everything is enqueued; a non-finite
+ * step length freezes theta for the remaining iterations (f_hist repeats). */
+int tlrmdd_solve(tlrmdd_plan plan, const void *D, const void *U, void *theta_inout,
+                 const tlrmdd_opts *opts, double *f_hist_dev,
+                 void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Batched solve of independent frequencies (the paper solves each frequency
+ * independently, Theory section, eq. standard_solver). Arrays have `count`
+ * entries; every problem uses the same opts. Work of all problems is fused
+ * into shared launches per phase. workspace: sized by
+ * tlrmdd_workspace_bytes_batched. */
+int tlrmdd_workspace_bytes_batched(int count, const tlrmdd_plan *plans,
+                                   const tlrmdd_opts *opts, size_t *bytes);
+int tlrmdd_solve_batched(int count, const tlrmdd_plan *plans, const void *const *D,
+                         const void *const *U, void *const *theta_inout,
+                         const tlrmdd_opts *opts, double *const *f_hist_dev,
+                         void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Hilbert ordering of receivers (Receivers re-ordering section, eq. hilbert).
+ * ix, iy: host, n non-negative 0-based grid coordinates (x = station along a
+ * line, y = line). perm_out: host, n entries: perm_out[k] is the natural
+ * index (input position) of the k-th receiver along the Hilbert curve on the
+ * smallest 2^m x 2^m grid enclosing all points (start (0,0), end (2^m-1,0));
+ * equal cells keep input order. Status 1 on NULL pointers with n > 0,
+ * n < 0 or negative coordinates. Host only, no GPU needed. */
+int hilbert_order(const int32_t *ix, const int32_t *iy, int64_t n, int64_t *perm_out);
+
+/* Column gather Dhat = D S (eq. axb_sd): out[s, k] = in[s, perm[k]].
+ * in, out: device, rows x cols complex64 (must not overlap);
+ * perm: device int64, cols entries, each in [0, cols). */
+int tlrmdd_permute_columns(const void *in, const int64_t *perm, void *out,
+                           int64_t rows, int64_t cols, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TLRMDD_H */

@@ -1,0 +1,220 @@
+"""MI355X (gfx950) tile low-rank multidimensional deconvolution (TLR-MDD).
+
+Python binding of the C ABI in include/tlrmdd.h: arguments are torch device
+tensors (complex64, contiguous) and the current torch stream; every step of
+the computation runs in the library's HIP kernels. Method: Chen, Ravasi,
+Keyes, arXiv 2412.14973 (objective eq. X2LQR_lst, gradients eqs. DXLR,
+Hilbert receiver re-ordering eq. axb_sd).
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BF16X3, FP32, GD, LBFGS, TLRMDDError  # noqa: F401
+
+__all__ = ["Plan", "hilbert_order", "permute_columns", "forward", "grad", "solve", "solve_batched",
+           "TLRMDDError", "FP32", "BF16X3", "LBFGS", "GD"]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_tensor(t, name, dtype=torch.complex64):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Plan:
+    """Validated tile layout of one frequency (tile sizes d_i, ranks k) plus device tables.
+
+    tile_size: d_i (sum = nr); rank_off: k_t of tile (i, j), i > j, t = i(i-1)/2 + j;
+    rank_diag: k_ii >= 1 (Q Q^T) or -1 (dense); ns: number of sources.
+    """
+
+    def __init__(self, tile_size, rank_off, rank_diag, ns):
+        lib = _lib.load()
+        self.tile_size = np.ascontiguousarray(tile_size, dtype=np.int32)
+        self.rank_off = np.ascontiguousarray(rank_off, dtype=np.int32)
+        self.rank_diag = np.ascontiguousarray(rank_diag, dtype=np.int32)
+        self.nr = int(self.tile_size.sum())
+        self.ns = int(ns)
+        P = ctypes.POINTER(ctypes.c_int32)
+        self._c = _lib.c_layout(self.nr, self.ns, int(self.tile_size.shape[0]),
+                                self.tile_size.ctypes.data_as(P),
+                                self.rank_off.ctypes.data_as(P) if self.rank_off.size else None,
+                                self.rank_diag.ctypes.data_as(P))
+        h = ctypes.c_void_p()
+        _lib.check(lib.tlrmdd_plan_create(ctypes.byref(self._c), ctypes.byref(h)), "tlrmdd_plan_create")
+        self._h = h
+        self.theta_size = int(lib.tlrmdd_theta_size(ctypes.byref(self._c)))
+
+    @classmethod
+    def from_layout(cls, layout, ns):
+        return cls(layout.tile_size, layout.rank_off, layout.rank_diag, ns)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_bytes(self, op, opts=None):
+        n = ctypes.c_size_t()
+        _lib.check(_lib.load().tlrmdd_workspace_bytes(self._h, op, ctypes.byref(opts) if opts else None,
+                                                      ctypes.byref(n)), "tlrmdd_workspace_bytes")
+        return int(n.value)
+
+    def workspace(self, op, opts=None, device=None):
+        return torch.empty(max(self.workspace_bytes(op, opts), 1), dtype=torch.uint8,
+                           device=device or torch.device("cuda"))
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and _lib._lib is not None:
+                _lib._lib.tlrmdd_plan_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def hilbert_order(ix, iy):
+    """perm[k] = natural index of the k-th receiver along the Hilbert curve (host)."""
+    ix = np.ascontiguousarray(ix, dtype=np.int32)
+    iy = np.ascontiguousarray(iy, dtype=np.int32)
+    if ix.shape != iy.shape or ix.ndim != 1:
+        raise ValueError("ix and iy must be 1-D arrays of equal length")
+    out = np.empty(ix.shape[0], dtype=np.int64)
+    _lib.check(_lib.load().hilbert_order(ix.ctypes.data, iy.ctypes.data, ix.shape[0], out.ctypes.data),
+               "hilbert_order")
+    return out
+
+
+def permute_columns(A, perm):
+    """out[:, k] = A[:, perm[k]] on the device (Dhat = D S)."""
+    _dev_tensor(A, "A")
+    _dev_tensor(perm, "perm", torch.int64)
+    rows, cols = A.shape
+    if perm.shape != (cols,):
+        raise ValueError("perm must have one entry per column")
+    out = torch.empty_like(A)
+    _lib.check(_lib.load().tlrmdd_permute_columns(_ptr(A), _ptr(perm), _ptr(out), rows, cols, _stream()),
+               "tlrmdd_permute_columns")
+    return out
+
+
+def _check_problem(plan, D, U, theta):
+    _dev_tensor(D, "D")
+    _dev_tensor(U, "U")
+    _dev_tensor(theta, "theta")
+    if tuple(D.shape) != (plan.ns, plan.nr) or tuple(U.shape) != (plan.ns, plan.nr):
+        raise ValueError(f"D and U must be {plan.ns} x {plan.nr}")
+    if theta.numel() != plan.theta_size:
+        raise ValueError(f"theta must hold {plan.theta_size} complex entries")
+
+
+def forward(plan, D, U, theta, precision=FP32, want_r=False, want_X=False, workspace=None):
+    """f = 1/2 ||D C(theta) - U||^2 (device FP64 0-dim tensor), optionally r and X."""
+    _check_problem(plan, D, U, theta)
+    f = torch.empty((), dtype=torch.float64, device=D.device)
+    r = torch.empty((plan.ns, plan.nr), dtype=torch.complex64, device=D.device) if want_r else None
+    X = torch.empty((plan.nr, plan.nr), dtype=torch.complex64, device=D.device) if want_X else None
+    ws = workspace if workspace is not None else plan.workspace(_lib.OP_FORWARD, device=D.device)
+    _lib.check(_lib.load().tlrmdd_forward(plan.handle, _ptr(D), _ptr(U), _ptr(theta), _ptr(f), _ptr(r), _ptr(X),
+                                          precision, _ptr(ws), ws.numel(), _stream()), "tlrmdd_forward")
+    return f, r, X
+
+
+def grad(plan, D, U, theta, precision=FP32, workspace=None):
+    """(f, grad) with grad = df/dRe + i df/dIm of every packed factor."""
+    _check_problem(plan, D, U, theta)
+    f = torch.empty((), dtype=torch.float64, device=D.device)
+    g = torch.empty_like(theta)
+    ws = workspace if workspace is not None else plan.workspace(_lib.OP_GRAD, device=D.device)
+    _lib.check(_lib.load().tlrmdd_grad(plan.handle, _ptr(D), _ptr(U), _ptr(theta), _ptr(f), _ptr(g), precision,
+                                       _ptr(ws), ws.numel(), _stream()), "tlrmdd_grad")
+    return f, g
+
+
+def make_opts(iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0, resid_refresh=0):
+    return _lib.c_opts(int(iters), int(optimizer), int(lbfgs_m), int(precision), float(lam), int(resid_refresh), 0)
+
+
+def solve(plan, D, U, theta0, iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0, resid_refresh=0,
+          workspace=None):
+    """Fixed-count solve from theta0; returns (theta_T, f_hist) with f_hist[t] (FP64, device)."""
+    _check_problem(plan, D, U, theta0)
+    opts = make_opts(iters, optimizer, lbfgs_m, precision, lam, resid_refresh)
+    theta = theta0.clone()
+    fh = torch.empty(iters + 1, dtype=torch.float64, device=D.device)
+    ws = workspace if workspace is not None else plan.workspace(_lib.OP_SOLVE, opts, device=D.device)
+    _lib.check(_lib.load().tlrmdd_solve(plan.handle, _ptr(D), _ptr(U), _ptr(theta), ctypes.byref(opts), _ptr(fh),
+                                        _ptr(ws), ws.numel(), _stream()), "tlrmdd_solve")
+    return theta, fh
+
+
+def batched_workspace_bytes(plans, opts):
+    arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    n = ctypes.c_size_t()
+    _lib.check(_lib.load().tlrmdd_workspace_bytes_batched(len(plans), arr, ctypes.byref(opts), ctypes.byref(n)),
+               "tlrmdd_workspace_bytes_batched")
+    return int(n.value)
+
+
+def solve_batched(plans, Ds, Us, thetas0, iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0,
+                  resid_refresh=0, workspace=None, out_thetas=None, out_fhist=None):
+    """Solve independent frequencies of equal nr, ns with fused launches per phase."""
+    n = len(plans)
+    for p, D, U, th in zip(plans, Ds, Us, thetas0):
+        _check_problem(p, D, U, th)
+    opts = make_opts(iters, optimizer, lbfgs_m, precision, lam, resid_refresh)
+    thetas = out_thetas if out_thetas is not None else [t.clone() for t in thetas0]
+    if out_thetas is not None:
+        for dst, src in zip(thetas, thetas0):
+            dst.copy_(src)
+    fh = out_fhist if out_fhist is not None else [torch.empty(iters + 1, dtype=torch.float64, device=Ds[0].device)
+                                                  for _ in range(n)]
+    V = ctypes.c_void_p * n
+    ws = workspace if workspace is not None else torch.empty(batched_workspace_bytes(plans, opts),
+                                                             dtype=torch.uint8, device=Ds[0].device)
+    _lib.check(_lib.load().tlrmdd_solve_batched(
+        n, V(*[p.handle.value for p in plans]), V(*[d.data_ptr() for d in Ds]), V(*[u.data_ptr() for u in Us]),
+        V(*[t.data_ptr() for t in thetas]), ctypes.byref(opts), V(*[f.data_ptr() for f in fh]),
+        _ptr(ws), ws.numel(), _stream()), "tlrmdd_solve_batched")
+    return thetas, fh
+
+
+class TLRMDDObjective(torch.autograd.Function):
+    """f(theta) = 1/2 ||D C(theta) - U||^2 with a hand-written HIP backward.
+
+    forward saves theta and references to D and U (never X); backward
+    re-assembles X inside tlrmdd_grad and returns grad_output * grad, where
+    grad = df/dRe + i df/dIm is torch's convention for complex leaves.
+    """
+
+    @staticmethod
+    def forward(ctx, theta, D, U, plan, precision=FP32):
+        f, _, _ = forward(plan, D, U, theta, precision)
+        ctx.save_for_backward(theta)
+        ctx.D, ctx.U, ctx.plan, ctx.precision = D, U, plan, precision
+        return f
+
+    @staticmethod
+    def backward(ctx, gout):
+        (theta,) = ctx.saved_tensors
+        _, g = grad(ctx.plan, ctx.D, ctx.U, theta, ctx.precision)
+        return (gout.to(torch.float32) * g), None, None, None, None
+
+
+def objective(theta, D, U, plan, precision=FP32):
+    """Differentiable TLR-MDD objective (see TLRMDDObjective)."""
+    return TLRMDDObjective.apply(theta, D, U, plan, precision)

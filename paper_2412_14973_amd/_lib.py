@@ -1,0 +1,93 @@
+"""ctypes view of the C ABI in include/tlrmdd.h (argument marshalling only).
+
+The library must be built (``python -m paper_2412_14973_amd.build`` or
+``__graft_entry__.build()``); loading fails loudly when it is missing. torch
+is imported first so the library binds to the HIP runtime torch already
+loaded (one runtime per process).
+"""
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library links)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libtlrmdd.so")
+
+OK, INVALID_ARGUMENT, WORKSPACE, HIP_ERROR, NONFINITE, UNSUPPORTED = 0, 1, 2, 3, 4, 5
+FP32, BF16X3 = 0, 1
+LBFGS, GD = 0, 1
+OP_FORWARD, OP_GRAD, OP_SOLVE = 0, 1, 2
+
+
+class TLRMDDError(RuntimeError):
+    def __init__(self, status, func, detail):
+        super().__init__(f"{func} failed with status {status}: {detail}")
+        self.status = status
+
+
+class c_layout(ctypes.Structure):
+    _fields_ = [("nr", ctypes.c_int64), ("ns", ctypes.c_int64), ("ntiles", ctypes.c_int32),
+                ("tile_size", ctypes.POINTER(ctypes.c_int32)),
+                ("rank_off", ctypes.POINTER(ctypes.c_int32)),
+                ("rank_diag", ctypes.POINTER(ctypes.c_int32))]
+
+
+class c_opts(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("optimizer", ctypes.c_int32), ("lbfgs_m", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("lam", ctypes.c_double), ("resid_refresh", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+_SIGS = {
+    "tlrmdd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "tlrmdd_last_error": (ctypes.c_char_p, []),
+    "tlrmdd_theta_size": (ctypes.c_int64, [ctypes.POINTER(c_layout)]),
+    "tlrmdd_plan_create": (ctypes.c_int, [ctypes.POINTER(c_layout), ctypes.POINTER(ctypes.c_void_p)]),
+    "tlrmdd_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "tlrmdd_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(c_opts),
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+    "tlrmdd_forward": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                                                ctypes.c_void_p]),
+    "tlrmdd_grad": (ctypes.c_int, [ctypes.c_void_p] * 6 + [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                                             ctypes.c_void_p]),
+    "tlrmdd_solve": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.POINTER(c_opts), ctypes.c_void_p,
+                                                              ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "tlrmdd_workspace_bytes_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                                      ctypes.POINTER(c_opts), ctypes.POINTER(ctypes.c_size_t)]),
+    "tlrmdd_solve_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(c_opts),
+                                            ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_size_t,
+                                            ctypes.c_void_p]),
+    "hilbert_order": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "tlrmdd_permute_columns": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                              ctypes.c_int64, ctypes.c_void_p]),
+}
+
+EXPORTS = tuple(_SIGS)
+
+
+def load():
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"TLR-MDD HIP library not built: {LIB_PATH} is missing "
+                           "(run __graft_entry__.build() or python -m paper_2412_14973_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status, func):
+    if status != OK:
+        lib = load()
+        detail = lib.tlrmdd_last_error().decode() or lib.tlrmdd_status_string(status).decode()
+        raise TLRMDDError(status, func, detail)

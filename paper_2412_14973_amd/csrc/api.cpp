@@ -1,0 +1,847 @@
+// C ABI of the TLR-MDD library: validation, plans, workspace carving and the
+// stream-ordered orchestration of the HIP kernels. No C++ exception crosses
+// the ABI; every entry point returns a status code.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "tlrmdd.h"
+#include "vec.hpp"
+
+using namespace tlr;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string &msg) {
+    g_last_error = msg;
+    return status;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(TLRMDD_HIP_ERROR, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// layout validation and tables
+// ---------------------------------------------------------------------------
+struct HostLayout {
+    int64_t nr = 0, ns = 0;
+    int N = 0;
+    std::vector<int> d, start, kdiag;
+    std::vector<int> koff;          // t order
+    std::vector<TileDesc> tiles;    // diagonal tiles first, then sub-diagonal tiles in t order
+    int64_t theta_size = 0;
+};
+
+int build_layout(const tlrmdd_layout *L, HostLayout &H) {
+    if (!L) return fail(TLRMDD_INVALID_ARGUMENT, "layout is NULL");
+    if (L->nr <= 0 || L->ns <= 0 || L->ntiles <= 0)
+        return fail(TLRMDD_INVALID_ARGUMENT, "nr, ns and ntiles must be positive");
+    if (L->nr > (int64_t)1 << 30 || L->ns > (int64_t)1 << 30)
+        return fail(TLRMDD_INVALID_ARGUMENT, "nr / ns too large");
+    if (!L->tile_size || !L->rank_diag || (L->ntiles > 1 && !L->rank_off))
+        return fail(TLRMDD_INVALID_ARGUMENT, "tile_size / rank_off / rank_diag is NULL");
+    H = HostLayout();
+    H.nr = L->nr;
+    H.ns = L->ns;
+    H.N = L->ntiles;
+    int64_t sum = 0;
+    for (int i = 0; i < H.N; ++i) {
+        const int di = L->tile_size[i];
+        if (di <= 0) return fail(TLRMDD_INVALID_ARGUMENT, "tile size must be positive");
+        H.start.push_back((int)sum);
+        H.d.push_back(di);
+        sum += di;
+    }
+    if (sum != H.nr) return fail(TLRMDD_INVALID_ARGUMENT, "sum of tile sizes differs from nr");
+    for (int i = 0; i < H.N; ++i) {
+        const int k = L->rank_diag[i];
+        if (!(k == -1 || (k >= 1 && k <= H.d[i])))
+            return fail(TLRMDD_INVALID_ARGUMENT, "diagonal rank must be -1 or in [1, d_i]");
+        H.kdiag.push_back(k);
+    }
+    int t = 0;
+    for (int i = 0; i < H.N; ++i)
+        for (int j = 0; j < i; ++j, ++t) {
+            const int k = L->rank_off[t];
+            if (k < 1 || k > std::min(H.d[i], H.d[j]))
+                return fail(TLRMDD_INVALID_ARGUMENT, "off-diagonal rank must be in [1, min(d_i, d_j)]");
+            H.koff.push_back(k);
+        }
+    // theta packing: diagonal blocks, then all L_t, then all R_t
+    int64_t pos = 0;
+    for (int i = 0; i < H.N; ++i) {
+        TileDesc td{};
+        td.kind = H.kdiag[i] < 0 ? TILE_DENSE : TILE_QQ;
+        td.di = td.dj = H.d[i];
+        td.k = H.kdiag[i] < 0 ? H.d[i] : H.kdiag[i];
+        td.row0 = td.col0 = H.start[i];
+        td.offA = pos;
+        td.offB = 0;
+        pos += (int64_t)H.d[i] * td.k;
+        H.tiles.push_back(td);
+    }
+    t = 0;
+    for (int i = 0; i < H.N; ++i)
+        for (int j = 0; j < i; ++j, ++t) {
+            TileDesc td{};
+            td.kind = TILE_LR;
+            td.di = H.d[i];
+            td.dj = H.d[j];
+            td.k = H.koff[t];
+            td.row0 = H.start[i];
+            td.col0 = H.start[j];
+            td.offA = pos;
+            pos += (int64_t)td.di * td.k;
+            H.tiles.push_back(td);
+        }
+    t = 0;
+    for (int i = 0; i < H.N; ++i)
+        for (int j = 0; j < i; ++j, ++t) {
+            TileDesc &td = H.tiles[H.N + t];
+            td.offB = pos;
+            pos += (int64_t)td.k * td.dj;
+        }
+    H.theta_size = pos;
+    return TLRMDD_OK;
+}
+
+// Work tables of one launch group (one problem, or a batch of problems).
+struct Tables {
+    std::vector<TileDesc> tiles;
+    std::vector<AsmItem> asm_items;
+    std::vector<GradItem> grad_items;
+    std::vector<ProbOff> probs;
+    std::vector<VecSeg> tsegs;      // theta-space segments
+    std::vector<int32_t> tseg_count;
+    std::vector<VecSeg> rsegs;      // residual-space segments (uniform per problem)
+    int rseg_per_prob = 0;
+    int tseg_max = 0;
+    int64_t theta_total = 0;        // complex elements over all problems
+};
+
+void append_problem(Tables &T, const HostLayout &H, int prob, int64_t x_off, int64_t ldk) {
+    const int tile_base = (int)T.tiles.size();
+    for (const TileDesc &td : H.tiles) T.tiles.push_back(td);
+    for (int q = 0; q < (int)H.tiles.size(); ++q) {
+        const TileDesc &td = H.tiles[q];
+        for (int r0 = 0; r0 < td.di; r0 += ASM_BR)
+            for (int c0 = 0; c0 < td.dj; c0 += ASM_BC) T.asm_items.push_back(AsmItem{tile_base + q, r0, c0, prob});
+        auto gi = [&](int kind, int a0, int b0) { T.grad_items.push_back(GradItem{tile_base + q, kind, a0, b0, prob, 0}); };
+        if (td.kind == TILE_DENSE) {
+            for (int a0 = 0; a0 < td.di; a0 += GZ_BR)
+                for (int b0 = 0; b0 < td.dj; b0 += GZ_BC) gi(G_Z, a0, b0);
+        } else if (td.kind == TILE_QQ) {
+            for (int a0 = 0; a0 < td.di; a0 += GR_ROWS)
+                for (int b0 = 0; b0 < td.k; b0 += GR_KK) gi(G_Q, a0, b0);
+        } else {
+            for (int a0 = 0; a0 < td.di; a0 += GR_ROWS)
+                for (int b0 = 0; b0 < td.k; b0 += GR_KK) gi(G_L, a0, b0);
+            for (int a0 = 0; a0 < td.dj; a0 += GR_ROWS)
+                for (int b0 = 0; b0 < td.k; b0 += GR_KK) gi(G_R, a0, b0);
+        }
+    }
+    ProbOff po{};
+    po.theta = T.theta_total;
+    po.x = x_off;
+    po.ldx = ldk;
+    T.probs.push_back(po);
+    T.theta_total += H.theta_size;
+}
+
+// segments: called after all problems are appended
+void build_segments(Tables &T, const std::vector<const HostLayout *> &Hs, int64_t ns, int64_t ldk) {
+    const int np = (int)Hs.size();
+    T.tseg_count.assign(np, 0);
+    int maxseg = 0;
+    for (int p = 0; p < np; ++p) {
+        const int64_t n2 = 2 * Hs[p]->theta_size;
+        maxseg = std::max<int>(maxseg, (int)((n2 + VEC_CH - 1) / VEC_CH));
+    }
+    const int64_t r2 = 2 * ns * ldk;
+    T.rseg_per_prob = (int)((r2 + VEC_CH - 1) / VEC_CH);
+    T.tseg_max = maxseg;
+    for (int p = 0; p < np; ++p) {
+        const int64_t base = 2 * T.probs[p].theta;
+        const int64_t n2 = 2 * Hs[p]->theta_size;
+        int local = 0;
+        for (int64_t o = 0; o < n2; o += VEC_CH, ++local)
+            T.tsegs.push_back(VecSeg{base + o, (int32_t)std::min<int64_t>(VEC_CH, n2 - o), p, 0, 0});
+        T.tseg_count[p] = local;
+    }
+    for (int p = 0; p < np; ++p) {
+        int local = 0;
+        for (int64_t o = 0; o < r2; o += VEC_CH, ++local)
+            T.rsegs.push_back(VecSeg{p * r2 + o, (int32_t)std::min<int64_t>(VEC_CH, r2 - o), p, 0, 0});
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+namespace {
+// Device tables of one launch group, carved from one buffer.
+struct DevTables {
+    TileDesc *tiles;
+    AsmItem *asm_items;
+    GradItem *grad_items;
+    ProbOff *probs;
+    VecSeg *tsegs;
+    int32_t *tcount;
+    VecSeg *rsegs;
+    double **fhist;
+    int n_asm, n_grad, n_tseg, n_rseg;
+};
+}  // namespace
+
+struct tlrmdd_plan_s {
+    HostLayout H;
+    int64_t ldk = 0, lds = 0;   // padded leading dimensions (complex) of nr- and ns-long rows
+    Tables T;
+    int device = 0;
+    DevTables D{};              // single-problem tables, uploaded once at plan creation
+    void *d_block = nullptr;
+};
+
+namespace {
+
+size_t tables_bytes(const Tables &T, int nprob) {
+    size_t b = 0;
+    b += align256(T.tiles.size() * sizeof(TileDesc));
+    b += align256(T.asm_items.size() * sizeof(AsmItem));
+    b += align256(T.grad_items.size() * sizeof(GradItem));
+    b += align256(T.probs.size() * sizeof(ProbOff));
+    b += align256(T.tsegs.size() * sizeof(VecSeg));
+    b += align256(T.tseg_count.size() * sizeof(int32_t));
+    b += align256(T.rsegs.size() * sizeof(VecSeg));
+    b += align256(nprob * sizeof(double *));
+    return b;
+}
+
+// Host image of the tables + their device addresses inside `dev`.
+void pack_tables(const Tables &T, int nprob, char *dev, std::vector<char> &img, DevTables &D,
+                 double *const *fhist) {
+    img.assign(tables_bytes(T, nprob), 0);
+    size_t o = 0;
+    auto put = [&](const void *src, size_t bytes) -> char * {
+        if (bytes) std::memcpy(img.data() + o, src, bytes);
+        char *p = dev + o;
+        o += align256(bytes);
+        return p;
+    };
+    D.tiles = (TileDesc *)put(T.tiles.data(), T.tiles.size() * sizeof(TileDesc));
+    D.asm_items = (AsmItem *)put(T.asm_items.data(), T.asm_items.size() * sizeof(AsmItem));
+    D.grad_items = (GradItem *)put(T.grad_items.data(), T.grad_items.size() * sizeof(GradItem));
+    D.probs = (ProbOff *)put(T.probs.data(), T.probs.size() * sizeof(ProbOff));
+    D.tsegs = (VecSeg *)put(T.tsegs.data(), T.tsegs.size() * sizeof(VecSeg));
+    D.tcount = (int32_t *)put(T.tseg_count.data(), T.tseg_count.size() * sizeof(int32_t));
+    D.rsegs = (VecSeg *)put(T.rsegs.data(), T.rsegs.size() * sizeof(VecSeg));
+    std::vector<double *> fh(nprob, nullptr);
+    if (fhist)
+        for (int p = 0; p < nprob; ++p) fh[p] = fhist[p];
+    D.fhist = (double **)put(fh.data(), nprob * sizeof(double *));
+    D.n_asm = (int)T.asm_items.size();
+    D.n_grad = (int)T.grad_items.size();
+    D.n_tseg = (int)T.tsegs.size();
+    D.n_rseg = (int)T.rsegs.size();
+}
+
+// assign partial slots: part = prob * pstride + local
+void assign_parts(Tables &T, int pstride) {
+    std::vector<int> local(T.probs.size(), 0);
+    for (VecSeg &s : T.tsegs) s.part = s.prob * pstride + local[s.prob]++;
+    std::fill(local.begin(), local.end(), 0);
+    for (VecSeg &s : T.rsegs) s.part = s.prob * pstride + local[s.prob]++;
+}
+
+int partial_stride(const Tables &T, int64_t nr, int64_t ns) {
+    int ps = std::max(T.tseg_max, T.rseg_per_prob);
+    ps = std::max(ps, gemm_partials_per_problem(GM_LINE, (int)ns, (int)nr) / 5);
+    ps = std::max(ps, gemm_partials_per_problem(GM_RESID, (int)ns, (int)nr));
+    return std::max(ps, 1);
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+struct Ws {
+    float2 *Ds = nullptr, *DHs = nullptr, *Us = nullptr, *XW = nullptr, *r = nullptr, *a = nullptr, *b = nullptr;
+    float *th = nullptr, *g0 = nullptr, *g1 = nullptr, *q = nullptr, *p = nullptr, *S = nullptr, *Y = nullptr;
+    double *partials = nullptr;
+    SolveScalars *sc = nullptr;
+    char *tables = nullptr;
+    size_t bytes = 0;
+};
+
+// op: 0 forward, 1 grad, 2 solve. Sizes for `nprob` problems of the same nr, ns.
+Ws carve(char *base, int op, int nprob, int64_t nr, int64_t ns, int64_t ldk, int64_t lds, int64_t theta_total,
+         int m1, int pstride, size_t tbytes) {
+    Ws w;
+    size_t o = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + o : nullptr;
+        o += align256(bytes);
+        return p;
+    };
+    const size_t c8 = sizeof(float2);
+    const size_t xsz = (size_t)nprob * nr * ldk * c8;
+    const size_t rsz = (size_t)nprob * ns * ldk * c8;
+    w.Ds = (float2 *)take(rsz);
+    if (op >= 1) w.DHs = (float2 *)take((size_t)nprob * nr * lds * c8);
+    w.XW = (float2 *)take(op == 2 ? 2 * xsz : xsz);
+    w.r = (float2 *)take(rsz);
+    if (op == 2) {
+        w.Us = (float2 *)take(rsz);
+        w.a = (float2 *)take(rsz);
+        w.b = (float2 *)take(rsz);
+        const size_t tz = (size_t)theta_total * c8;
+        w.th = (float *)take(tz);
+        w.g0 = (float *)take(tz);
+        w.g1 = (float *)take(tz);
+        w.q = (float *)take(tz);
+        w.p = (float *)take(tz);
+        w.S = (float *)take(tz * m1);
+        w.Y = (float *)take(tz * m1);
+    }
+    w.partials = (double *)take((size_t)nprob * pstride * 5 * sizeof(double));
+    w.sc = (SolveScalars *)take((size_t)nprob * sizeof(SolveScalars));
+    w.tables = take(tbytes);
+    w.bytes = o;
+    return w;
+}
+
+int check_opts(const tlrmdd_opts *o) {
+    if (!o) return fail(TLRMDD_INVALID_ARGUMENT, "opts is NULL");
+    if (o->iters < 0) return fail(TLRMDD_INVALID_ARGUMENT, "iters must be >= 0");
+    if (o->optimizer != TLRMDD_LBFGS && o->optimizer != TLRMDD_GD)
+        return fail(TLRMDD_INVALID_ARGUMENT, "unknown optimizer");
+    if (o->optimizer == TLRMDD_LBFGS && (o->lbfgs_m < 1 || o->lbfgs_m > MAX_LBFGS_M))
+        return fail(TLRMDD_INVALID_ARGUMENT, "lbfgs_m must be in [1, 32]");
+    if (o->precision != TLRMDD_FP32)
+        return fail(o->precision == TLRMDD_BF16X3 ? TLRMDD_UNSUPPORTED : TLRMDD_INVALID_ARGUMENT,
+                    "precision not supported");
+    if (!(o->lambda >= 0.0)) return fail(TLRMDD_INVALID_ARGUMENT, "lambda must be >= 0");
+    if (o->resid_refresh < 0) return fail(TLRMDD_INVALID_ARGUMENT, "resid_refresh must be >= 0");
+    return TLRMDD_OK;
+}
+
+int check_precision(int precision) {
+    if (precision == TLRMDD_FP32) return TLRMDD_OK;
+    if (precision == TLRMDD_BF16X3) return fail(TLRMDD_UNSUPPORTED, "BF16x3 precision not available");
+    return fail(TLRMDD_INVALID_ARGUMENT, "unknown precision");
+}
+
+GemmArgs gemm_args() {
+    GemmArgs g;
+    std::memset(&g, 0, sizeof(g));
+    return g;
+}
+
+FinArgs fin_args(int op, SolveScalars *sc) {
+    FinArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.op = op;
+    f.sc = sc;
+    f.m1 = 1;
+    return f;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *tlrmdd_status_string(int status) {
+    switch (status) {
+        case TLRMDD_OK: return "ok";
+        case TLRMDD_INVALID_ARGUMENT: return "invalid argument";
+        case TLRMDD_WORKSPACE: return "workspace too small or allocation failed";
+        case TLRMDD_HIP_ERROR: return "HIP runtime error";
+        case TLRMDD_NONFINITE: return "non-finite value";
+        case TLRMDD_UNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+const char *tlrmdd_last_error(void) { return g_last_error.c_str(); }
+
+int64_t tlrmdd_theta_size(const tlrmdd_layout *layout) {
+    HostLayout H;
+    if (build_layout(layout, H) != TLRMDD_OK) return -1;
+    return H.theta_size;
+}
+
+int tlrmdd_plan_create(const tlrmdd_layout *layout, tlrmdd_plan *plan_out) {
+    g_last_error.clear();
+    if (!plan_out) return fail(TLRMDD_INVALID_ARGUMENT, "plan_out is NULL");
+    *plan_out = nullptr;
+    tlrmdd_plan P = new (std::nothrow) tlrmdd_plan_s();
+    if (!P) return fail(TLRMDD_WORKSPACE, "host allocation failed");
+    int st = build_layout(layout, P->H);
+    if (st != TLRMDD_OK) { delete P; return st; }
+    P->ldk = round_up(P->H.nr, 2);
+    P->lds = round_up(P->H.ns, 2);
+    append_problem(P->T, P->H, 0, 0, P->ldk);
+    build_segments(P->T, {&P->H}, P->H.ns, P->ldk);
+    assign_parts(P->T, partial_stride(P->T, P->H.nr, P->H.ns));
+    hipError_t e = hipGetDevice(&P->device);
+    if (e == hipSuccess) e = hipMalloc(&P->d_block, tables_bytes(P->T, 1));
+    if (e == hipSuccess) {
+        std::vector<char> img;
+        pack_tables(P->T, 1, (char *)P->d_block, img, P->D, nullptr);
+        e = hipMemcpy(P->d_block, img.data(), img.size(), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        if (P->d_block) (void)hipFree(P->d_block);
+        delete P;
+        return fail(TLRMDD_HIP_ERROR, std::string("plan tables: ") + hipGetErrorString(e));
+    }
+    *plan_out = P;
+    return TLRMDD_OK;
+}
+
+int tlrmdd_plan_destroy(tlrmdd_plan plan) {
+    if (!plan) return TLRMDD_OK;
+    if (plan->d_block) (void)hipFree(plan->d_block);
+    delete plan;
+    return TLRMDD_OK;
+}
+
+static size_t ws_bytes_single(const tlrmdd_plan P, int op, int m1) {
+    const Tables &T = P->T;
+    const int ps = partial_stride(T, P->H.nr, P->H.ns);
+    return carve(nullptr, op, 1, P->H.nr, P->H.ns, P->ldk, P->lds, P->H.theta_size, m1, ps, 0).bytes;
+}
+
+int tlrmdd_workspace_bytes(tlrmdd_plan plan, int op, const tlrmdd_opts *opts, size_t *bytes) {
+    g_last_error.clear();
+    if (!plan || !bytes) return fail(TLRMDD_INVALID_ARGUMENT, "plan / bytes is NULL");
+    if (op < 0 || op > 2) return fail(TLRMDD_INVALID_ARGUMENT, "unknown op");
+    int m1 = 1;
+    if (op == TLRMDD_OP_SOLVE) {
+        int st = check_opts(opts);
+        if (st != TLRMDD_OK) return st;
+        m1 = (opts->optimizer == TLRMDD_LBFGS) ? opts->lbfgs_m + 1 : 1;
+    }
+    *bytes = ws_bytes_single(plan, op, m1);
+    return TLRMDD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// shared pieces of forward / grad / solve
+// ---------------------------------------------------------------------------
+namespace {
+
+// upload the tables into the workspace (blocking until the copy is done, so
+// the host image may be freed)
+int upload_tables(const Tables &T, int nprob, const Ws &w, DevTables &D, double *const *fhist, hipStream_t s) {
+    std::vector<char> img;
+    pack_tables(T, nprob, w.tables, img, D, fhist);
+    HIP_TRY(hipMemcpyAsync(w.tables, img.data(), img.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return TLRMDD_OK;
+}
+
+struct Ctx {
+    int nprob;
+    int64_t nr, ns, ldk, lds;
+    int pstride;
+    Ws w;
+    DevTables D;
+    hipStream_t s;
+};
+
+int fin(const Ctx &c, FinArgs f, const int32_t *counts, int ucount, int nsum) {
+    f.partials = c.w.partials;
+    f.pstride = c.pstride;
+    f.counts = counts;
+    f.ucount = ucount;
+    f.nsum = nsum;
+    HIP_TRY(launch_finalize(f, c.nprob, c.s));
+    return TLRMDD_OK;
+}
+
+int gemm_resid(const Ctx &c, const float2 *X, int64_t sX, const float2 *U, int64_t ldu, int64_t sU, float2 *r) {
+    GemmArgs g = gemm_args();
+    g.A = c.w.Ds; g.lda = c.ldk; g.sA = c.ns * c.ldk;
+    g.B = X; g.ldb = c.ldk; g.sB = sX;
+    g.C = r; g.ldc = c.ldk; g.sC = c.ns * c.ldk;
+    g.E = U; g.lde = ldu; g.sE = sU;
+    g.partials = c.w.partials; g.sP = (int64_t)c.pstride;   // one sum per workgroup
+    g.M = (int)c.ns; g.N = (int)c.nr; g.K = (int)c.nr;
+    HIP_TRY(launch_cgemm(GM_RESID, g, c.nprob, c.s));
+    return TLRMDD_OK;
+}
+
+int gemm_adjoint(const Ctx &c, const float2 *r, float2 *W, int64_t sW) {
+    GemmArgs g = gemm_args();
+    g.A = c.w.DHs; g.lda = c.lds; g.sA = c.nr * c.lds;
+    g.B = r; g.ldb = c.ldk; g.sB = c.ns * c.ldk;
+    g.C = W; g.ldc = c.ldk; g.sC = sW;
+    g.M = (int)c.nr; g.N = (int)c.nr; g.K = (int)c.ns;
+    HIP_TRY(launch_cgemm(GM_STORE, g, c.nprob, c.s));
+    return TLRMDD_OK;
+}
+
+int gemm_line(const Ctx &c, const float2 *X1, const float2 *X2, int64_t sX) {
+    GemmArgs g = gemm_args();
+    g.A = c.w.Ds; g.lda = c.ldk; g.sA = c.ns * c.ldk;
+    g.B = X1; g.B2 = X2; g.ldb = c.ldk; g.sB = sX;
+    g.C = c.w.a; g.C2 = c.w.b; g.ldc = c.ldk; g.sC = c.ns * c.ldk;
+    g.E = c.w.r; g.lde = c.ldk; g.sE = c.ns * c.ldk;
+    g.partials = c.w.partials; g.sP = (int64_t)c.pstride * 5;
+    g.M = (int)c.ns; g.N = (int)c.nr; g.K = (int)c.nr;
+    HIP_TRY(launch_cgemm(GM_LINE, g, c.nprob, c.s));
+    return TLRMDD_OK;
+}
+
+int resid_tiles(const Ctx &c) { return gemm_partials_per_problem(GM_RESID, (int)c.ns, (int)c.nr); }
+int line_tiles(const Ctx &c) { return gemm_partials_per_problem(GM_LINE, (int)c.ns, (int)c.nr) / 5; }
+
+// The whole solve, for one problem or a batch of equal-shape problems.
+int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const void *const *U,
+               void *const *theta, const tlrmdd_opts *opts, double *const *fhist, void *workspace,
+               size_t ws_bytes, hipStream_t s) {
+    int st = check_opts(opts);
+    if (st != TLRMDD_OK) return st;
+    const int64_t nr = plans[0]->H.nr, ns = plans[0]->H.ns;
+    for (int p = 0; p < nprob; ++p) {
+        if (!plans[p]) return fail(TLRMDD_INVALID_ARGUMENT, "plan is NULL");
+        if (plans[p]->H.nr != nr || plans[p]->H.ns != ns)
+            return fail(TLRMDD_INVALID_ARGUMENT, "batched problems must share nr and ns");
+        if (!D[p] || !U[p] || !theta[p] || !fhist[p]) return fail(TLRMDD_INVALID_ARGUMENT, "NULL data pointer");
+    }
+    if (!workspace) return fail(TLRMDD_INVALID_ARGUMENT, "workspace is NULL");
+    const bool lbfgs = opts->optimizer == TLRMDD_LBFGS;
+    const int m = lbfgs ? opts->lbfgs_m : 0;
+    const int m1 = lbfgs ? m + 1 : 1;
+    const double lam = opts->lambda;
+
+    Ctx c;
+    c.nprob = nprob;
+    c.nr = nr;
+    c.ns = ns;
+    c.ldk = round_up(nr, 2);
+    c.lds = round_up(ns, 2);
+    c.s = s;
+    Tables T;
+    std::vector<const HostLayout *> Hs;
+    for (int p = 0; p < nprob; ++p) {
+        append_problem(T, plans[p]->H, p, (int64_t)p * 2 * nr * c.ldk, c.ldk);
+        Hs.push_back(&plans[p]->H);
+    }
+    build_segments(T, Hs, ns, c.ldk);
+    c.pstride = partial_stride(T, nr, ns);
+    assign_parts(T, c.pstride);
+    const bool single = (nprob == 1);
+    c.w = carve((char *)workspace, 2, nprob, nr, ns, c.ldk, c.lds, T.theta_total, m1, c.pstride,
+                single ? 0 : tables_bytes(T, nprob));
+    if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
+    if (single) {
+        c.D = plans[0]->D;
+    } else {
+        st = upload_tables(T, nprob, c.w, c.D, fhist, s);
+        if (st != TLRMDD_OK) return st;
+    }
+    double *fhist0 = single ? fhist[0] : nullptr;
+
+    const int64_t xstride = 2 * nr * c.ldk;      // per-problem X-space stride
+    const int64_t rstride = ns * c.ldk;
+    float2 *X1 = c.w.XW, *X2 = c.w.XW + nr * c.ldk;
+    const int64_t stride2 = 2 * T.theta_total;   // floats between ring slots
+    const int nt = c.D.n_tseg, nrs = c.D.n_rseg;
+
+    // ---- setup: stage D, U, theta; zero the residual-space buffers (their padding stays 0) ----
+    HIP_TRY(hipMemsetAsync(c.w.r, 0, (size_t)nprob * rstride * sizeof(float2), s));
+    HIP_TRY(hipMemsetAsync(c.w.a, 0, (size_t)nprob * rstride * sizeof(float2), s));
+    HIP_TRY(hipMemsetAsync(c.w.b, 0, (size_t)nprob * rstride * sizeof(float2), s));
+    for (int p = 0; p < nprob; ++p) {
+        HIP_TRY(launch_stage_d((const float2 *)D[p], ns, nr, c.w.Ds + p * rstride, c.ldk,
+                               c.w.DHs + (int64_t)p * nr * c.lds, c.lds, s));
+        HIP_TRY(launch_copy2d((const float2 *)U[p], nr, c.w.Us + p * rstride, c.ldk, ns, nr, s));
+        HIP_TRY(hipMemcpyAsync(c.w.th + 2 * T.probs[p].theta, theta[p],
+                               plans[p]->H.theta_size * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    }
+    FinArgs f0 = fin_args(FIN_INIT, c.w.sc);
+    if ((st = fin(c, f0, nullptr, 0, 1))) return st;
+
+    auto objective_fresh = [&](int t) -> int {
+        HIP_TRY(launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)c.w.th,
+                                nullptr, X1, nullptr, s));
+        int e = gemm_resid(c, X1, xstride, c.w.Us, c.ldk, rstride, c.w.r);
+        if (e) return e;
+        FinArgs f = fin_args(FIN_F, c.w.sc);
+        f.fhist = single ? nullptr : c.D.fhist;
+        f.fhist0 = fhist0;
+        f.t = t;
+        f.lam = lam;
+        return fin(c, f, nullptr, resid_tiles(c), 1);
+    };
+    if (lam != 0.0) {
+        HIP_TRY(launch_dot2(c.D.tsegs, nt, c.w.th, c.w.th, c.w.th, c.w.th, c.w.partials, s));
+        if ((st = fin(c, fin_args(FIN_THNORM, c.w.sc), c.D.tcount, 0, 2))) return st;
+    }
+    if ((st = objective_fresh(0))) return st;
+
+    float *gcur = c.w.g0, *gprev = c.w.g1;
+    for (int t = 0; t < opts->iters; ++t) {
+        // gradient from the tracked residual (eqs. DXLR)
+        if ((st = gemm_adjoint(c, c.w.r, X1, xstride))) return st;
+        HIP_TRY(launch_grad(c.D.tiles, c.D.grad_items, c.D.n_grad, c.D.probs, X1, (const float2 *)c.w.th,
+                            (float2 *)gcur, s));
+        if (lam != 0.0) HIP_TRY(launch_reg_grad(c.D.tsegs, nt, gcur, c.w.th, (float)(2.0 * lam), s));
+        // direction
+        if (!lbfgs) {
+            HIP_TRY(launch_restart(c.D.tsegs, nt, 1, c.w.p, gcur, c.w.sc, s));
+        } else {
+            if (t > 0) {
+                HIP_TRY(launch_pair(c.D.tsegs, nt, gcur, gprev, c.w.Y, c.w.S, stride2, c.w.sc, c.w.partials, s));
+                FinArgs f = fin_args(FIN_PAIR, c.w.sc);
+                f.m1 = m1;
+                if ((st = fin(c, f, c.D.tcount, 0, 2))) return st;
+            }
+            const int L = std::min(t, m);
+            for (int i = 0; i <= L; ++i) {
+                HIP_TRY(launch_twoloop1(c.D.tsegs, nt, i, m1, c.w.q, gcur, c.w.S, c.w.Y, stride2, c.w.sc,
+                                        c.w.partials, s));
+                if (i < L) {
+                    FinArgs f = fin_args(FIN_ALPHA, c.w.sc);
+                    f.m1 = m1;
+                    f.i = i;
+                    if ((st = fin(c, f, c.D.tcount, 0, 1))) return st;
+                }
+            }
+            HIP_TRY(launch_twoloop2(c.D.tsegs, nt, 1, L == 0 ? 1 : 0, -1, L - 1, m1, c.w.q, c.w.q, c.w.p, gcur,
+                                    c.w.S, c.w.Y, stride2, c.w.sc, c.w.partials, s));
+            for (int i = L - 1; i >= 0; --i) {
+                FinArgs f = fin_args(FIN_BETA, c.w.sc);
+                f.m1 = m1;
+                f.i = i;
+                if ((st = fin(c, f, c.D.tcount, 0, 1))) return st;
+                HIP_TRY(launch_twoloop2(c.D.tsegs, nt, 0, i == 0 ? 1 : 0, i, i - 1, m1, c.w.q, c.w.q, c.w.p,
+                                        gcur, c.w.S, c.w.Y, stride2, c.w.sc, c.w.partials, s));
+            }
+            FinArgs f = fin_args(FIN_GP, c.w.sc);
+            f.m1 = m1;
+            if ((st = fin(c, f, c.D.tcount, 0, 1))) return st;
+            HIP_TRY(launch_restart(c.D.tsegs, nt, 0, c.w.p, gcur, c.w.sc, s));
+        }
+        // exact line search: a = D C1(theta;p), b = D C2(p)
+        HIP_TRY(launch_assemble(true, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)c.w.th,
+                                (const float2 *)c.w.p, X1, X2, s));
+        if (lam != 0.0) {
+            HIP_TRY(launch_dot2(c.D.tsegs, nt, c.w.th, c.w.p, c.w.p, c.w.p, c.w.partials, s));
+            if ((st = fin(c, fin_args(FIN_LAMTERMS, c.w.sc), c.D.tcount, 0, 2))) return st;
+        }
+        if ((st = gemm_line(c, X1, X2, xstride))) return st;
+        {
+            FinArgs f = fin_args(FIN_LINE, c.w.sc);
+            f.lam = lam;
+            if ((st = fin(c, f, nullptr, line_tiles(c), 5))) return st;
+        }
+        // updates
+        HIP_TRY(launch_theta_update(c.D.tsegs, nt, c.w.th, c.w.p, lbfgs ? c.w.S : nullptr, stride2, c.w.sc,
+                                    c.w.partials, s));
+        if (lam != 0.0)
+            if ((st = fin(c, fin_args(FIN_THNORM, c.w.sc), c.D.tcount, 0, 1))) return st;
+        HIP_TRY(launch_resid_update(c.D.rsegs, nrs, (float *)c.w.r, (const float *)c.w.a, (const float *)c.w.b,
+                                    c.w.sc, c.w.partials, s));
+        {
+            FinArgs f = fin_args(FIN_F, c.w.sc);
+            f.fhist = single ? nullptr : c.D.fhist;
+            f.fhist0 = fhist0;
+            f.t = t + 1;
+            f.lam = lam;
+            if ((st = fin(c, f, nullptr, T.rseg_per_prob, 1))) return st;
+        }
+        if (opts->resid_refresh > 0 && (t + 1) % opts->resid_refresh == 0)
+            if ((st = objective_fresh(t + 1))) return st;
+        std::swap(gcur, gprev);
+    }
+    for (int p = 0; p < nprob; ++p)
+        HIP_TRY(hipMemcpyAsync(theta[p], c.w.th + 2 * T.probs[p].theta, plans[p]->H.theta_size * sizeof(float2),
+                               hipMemcpyDeviceToDevice, s));
+    return TLRMDD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tlrmdd_forward(tlrmdd_plan plan, const void *D, const void *U, const void *theta, double *f_dev, void *r_out,
+                   void *X_out, int precision, void *workspace, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (!plan || !D || !U || !theta || !f_dev || !workspace)
+        return fail(TLRMDD_INVALID_ARGUMENT, "NULL argument");
+    int st = check_precision(precision);
+    if (st) return st;
+    Ctx c;
+    c.nprob = 1;
+    c.nr = plan->H.nr;
+    c.ns = plan->H.ns;
+    c.ldk = plan->ldk;
+    c.lds = plan->lds;
+    c.s = stream;
+    c.pstride = partial_stride(plan->T, c.nr, c.ns);
+    c.w = carve((char *)workspace, 0, 1, c.nr, c.ns, c.ldk, c.lds, plan->H.theta_size, 1, c.pstride, 0);
+    if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
+    c.D = plan->D;
+    HIP_TRY(launch_stage_d((const float2 *)D, c.ns, c.nr, c.w.Ds, c.ldk, nullptr, 0, stream));
+    HIP_TRY(launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
+                            c.w.XW, nullptr, stream));
+    if ((st = gemm_resid(c, c.w.XW, 0, (const float2 *)U, c.nr, 0, c.w.r))) return st;
+    FinArgs f = fin_args(FIN_F_OUT, c.w.sc);
+    f.fout = f_dev;
+    if ((st = fin(c, f, nullptr, resid_tiles(c), 1))) return st;
+    if (r_out) HIP_TRY(launch_copy2d(c.w.r, c.ldk, (float2 *)r_out, c.nr, c.ns, c.nr, stream));
+    if (X_out) HIP_TRY(launch_copy2d(c.w.XW, c.ldk, (float2 *)X_out, c.nr, c.nr, c.nr, stream));
+    return TLRMDD_OK;
+}
+
+int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *theta, double *f_dev, void *grad_out,
+                int precision, void *workspace, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (!plan || !D || !U || !theta || !grad_out || !workspace)
+        return fail(TLRMDD_INVALID_ARGUMENT, "NULL argument");
+    int st = check_precision(precision);
+    if (st) return st;
+    Ctx c;
+    c.nprob = 1;
+    c.nr = plan->H.nr;
+    c.ns = plan->H.ns;
+    c.ldk = plan->ldk;
+    c.lds = plan->lds;
+    c.s = stream;
+    c.pstride = partial_stride(plan->T, c.nr, c.ns);
+    c.w = carve((char *)workspace, 1, 1, c.nr, c.ns, c.ldk, c.lds, plan->H.theta_size, 1, c.pstride, 0);
+    if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
+    c.D = plan->D;
+    HIP_TRY(launch_stage_d((const float2 *)D, c.ns, c.nr, c.w.Ds, c.ldk, c.w.DHs, c.lds, stream));
+    HIP_TRY(launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
+                            c.w.XW, nullptr, stream));
+    if ((st = gemm_resid(c, c.w.XW, 0, (const float2 *)U, c.nr, 0, c.w.r))) return st;
+    if (f_dev) {
+        FinArgs f = fin_args(FIN_F_OUT, c.w.sc);
+        f.fout = f_dev;
+        if ((st = fin(c, f, nullptr, resid_tiles(c), 1))) return st;
+    }
+    // the assembled X is dead once r exists: W = D^H r reuses its storage
+    if ((st = gemm_adjoint(c, c.w.r, c.w.XW, 0))) return st;
+    HIP_TRY(launch_grad(c.D.tiles, c.D.grad_items, c.D.n_grad, c.D.probs, c.w.XW, (const float2 *)theta,
+                        (float2 *)grad_out, stream));
+    return TLRMDD_OK;
+}
+
+int tlrmdd_solve(tlrmdd_plan plan, const void *D, const void *U, void *theta_inout, const tlrmdd_opts *opts,
+                 double *f_hist_dev, void *workspace, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (!plan) return fail(TLRMDD_INVALID_ARGUMENT, "plan is NULL");
+    const void *Dp[1] = {D};
+    const void *Up[1] = {U};
+    void *Tp[1] = {theta_inout};
+    double *Fp[1] = {f_hist_dev};
+    return solve_impl(1, &plan, Dp, Up, Tp, opts, Fp, workspace, ws_bytes, stream);
+}
+
+int tlrmdd_workspace_bytes_batched(int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, size_t *bytes) {
+    g_last_error.clear();
+    if (count <= 0 || !plans || !bytes) return fail(TLRMDD_INVALID_ARGUMENT, "bad arguments");
+    int st = check_opts(opts);
+    if (st) return st;
+    for (int p = 0; p < count; ++p)
+        if (!plans[p]) return fail(TLRMDD_INVALID_ARGUMENT, "plan is NULL");
+    const int64_t nr = plans[0]->H.nr, ns = plans[0]->H.ns;
+    const int64_t ldk = round_up(nr, 2), lds = round_up(ns, 2);
+    Tables T;
+    std::vector<const HostLayout *> Hs;
+    for (int p = 0; p < count; ++p) {
+        if (plans[p]->H.nr != nr || plans[p]->H.ns != ns)
+            return fail(TLRMDD_INVALID_ARGUMENT, "batched problems must share nr and ns");
+        append_problem(T, plans[p]->H, p, (int64_t)p * 2 * nr * ldk, ldk);
+        Hs.push_back(&plans[p]->H);
+    }
+    build_segments(T, Hs, ns, ldk);
+    const int m1 = opts->optimizer == TLRMDD_LBFGS ? opts->lbfgs_m + 1 : 1;
+    *bytes = carve(nullptr, 2, count, nr, ns, ldk, lds, T.theta_total, m1, partial_stride(T, nr, ns),
+                   count == 1 ? 0 : tables_bytes(T, count)).bytes;
+    return TLRMDD_OK;
+}
+
+int tlrmdd_solve_batched(int count, const tlrmdd_plan *plans, const void *const *D, const void *const *U,
+                         void *const *theta_inout, const tlrmdd_opts *opts, double *const *f_hist_dev,
+                         void *workspace, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (count <= 0 || !plans || !D || !U || !theta_inout || !f_hist_dev)
+        return fail(TLRMDD_INVALID_ARGUMENT, "bad arguments");
+    return solve_impl(count, plans, D, U, theta_inout, opts, f_hist_dev, workspace, ws_bytes, stream);
+}
+
+int hilbert_order(const int32_t *ix, const int32_t *iy, int64_t n, int64_t *perm_out) {
+    g_last_error.clear();
+    if (n < 0) return fail(TLRMDD_INVALID_ARGUMENT, "n must be >= 0");
+    if (n == 0) return TLRMDD_OK;
+    if (!ix || !iy || !perm_out) return fail(TLRMDD_INVALID_ARGUMENT, "NULL pointer");
+    int32_t mx = 0;
+    for (int64_t q = 0; q < n; ++q) {
+        if (ix[q] < 0 || iy[q] < 0) return fail(TLRMDD_INVALID_ARGUMENT, "negative grid coordinate");
+        mx = std::max(mx, std::max(ix[q], iy[q]));
+    }
+    int m = 1;
+    while (m < 31 && (int64_t(1) << m) <= mx) ++m;   // smallest 2^m > max coordinate
+    const int64_t side = int64_t(1) << m;
+    std::vector<int64_t> h(n);
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t x = ix[q], y = iy[q], d = 0;
+        for (int64_t s = side / 2; s > 0; s /= 2) {
+            const int64_t rx = (x & s) ? 1 : 0;
+            const int64_t ry = (y & s) ? 1 : 0;
+            d += s * s * ((3 * rx) ^ ry);
+            if (ry == 0) {   // rotate the quadrant into canonical orientation
+                if (rx == 1) {
+                    x = side - 1 - x;
+                    y = side - 1 - y;
+                }
+                std::swap(x, y);
+            }
+        }
+        h[q] = d;
+    }
+    std::vector<int64_t> idx(n);
+    for (int64_t q = 0; q < n; ++q) idx[q] = q;
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return h[a] < h[b]; });
+    std::memcpy(perm_out, idx.data(), n * sizeof(int64_t));
+    return TLRMDD_OK;
+}
+
+int tlrmdd_permute_columns(const void *in, const int64_t *perm, void *out, int64_t rows, int64_t cols,
+                           hipStream_t stream) {
+    g_last_error.clear();
+    if (rows < 0 || cols < 0) return fail(TLRMDD_INVALID_ARGUMENT, "negative size");
+    if (rows == 0 || cols == 0) return TLRMDD_OK;
+    if (!in || !perm || !out) return fail(TLRMDD_INVALID_ARGUMENT, "NULL pointer");
+    if (in == out) return fail(TLRMDD_INVALID_ARGUMENT, "in and out must not overlap");
+    HIP_TRY(launch_permute_cols((const float2 *)in, perm, (float2 *)out, rows, cols, stream));
+    return TLRMDD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace tlr {
+
+// ---- tile tables (Tile Low-rank MDD section: diagonal Q Q^T / P Z, sub-diagonal L R) ----
+enum TileKind : int32_t { TILE_LR = 0, TILE_QQ = 1, TILE_DENSE = 2 };
+
+struct TileDesc {
+    int32_t kind;   // TileKind
+    int32_t di;     // rows of the tile (tile i)
+    int32_t dj;     // cols of the tile (tile j); == di on the diagonal
+    int32_t k;      // rank (LR: k_ij, QQ: k_ii, DENSE: d_i)
+    int64_t row0;   // first row of the tile in X
+    int64_t col0;   // first col of the tile in X
+    int64_t offA;   // theta offset of L_ij / Q_ii / Z_ii
+    int64_t offB;   // theta offset of R_ij (LR only)
+};
+
+// Per-problem offsets (a batch of frequencies shares one launch per phase).
+struct ProbOff {
+    int64_t theta;  // offset (complex elements) of this problem's theta / p / g vectors
+    int64_t x;      // offset of its X / X1 / X2 / W matrices
+    int64_t ldx;    // leading dimension (complex) of those matrices
+    int64_t pad;
+};
+
+// Assembly work item: one 32 x 64 block of a tile (rows r0.., cols c0.. inside the tile).
+struct AsmItem {
+    int32_t tile;   // index into the tile table
+    int32_t r0;
+    int32_t c0;
+    int32_t prob;   // index into the ProbOff table
+};
+constexpr int ASM_BR = 32;
+constexpr int ASM_BC = 64;
+constexpr int ASM_KC = 32;
+
+// Gradient work item.
+enum GradKind : int32_t { G_L = 0, G_Q = 1, G_R = 2, G_Z = 3 };
+struct GradItem {
+    int32_t tile;
+    int32_t kind;   // GradKind
+    int32_t a0;     // G_L/G_Q: first row; G_R: first col; G_Z: first row
+    int32_t b0;     // G_L/G_Q/G_R: first rank index; G_Z: first col
+    int32_t prob;
+    int32_t pad;
+};
+constexpr int GR_ROWS = 32;   // rows (G_L/G_Q) or cols (G_R) per item
+constexpr int GR_KK = 32;     // rank entries per item
+constexpr int GR_CH = 64;     // contraction chunk
+constexpr int GZ_BR = 32, GZ_BC = 64;
+
+// ---- complex GEMM on MFMA ----
+enum GemmMode : int32_t { GM_STORE = 0, GM_RESID = 1, GM_LINE = 2 };
+
+struct GemmArgs {
+    const float2 *A;  int64_t lda;   // M x K complex, row-major
+    const float2 *B;  int64_t ldb;   // K x N complex, row-major
+    const float2 *B2;                // GM_LINE: second B (same ldb)
+    float2 *C;        int64_t ldc;   // M x N output
+    float2 *C2;                      // GM_LINE: second output (same ldc)
+    const float2 *E;  int64_t lde;   // GM_RESID: U (C = AB - U); GM_LINE: residual r
+    double *partials;                // per-workgroup FP64 sums (GM_RESID: 1, GM_LINE: 5)
+    int32_t M, N, K;
+    int32_t tiles_m, tiles_n;
+    // uniform batch (grid.y): element strides between problems
+    int64_t sA, sB, sC, sE;
+    int64_t sP;                      // partial stride (doubles) between problems
+};
+constexpr int GEMM_BM = 128;
+constexpr int GEMM_BN = 128;   // complex columns per workgroup (64 of a + 64 of b in GM_LINE)
+constexpr int GEMM_BK = 16;    // complex k per stage
+
+// ---- vector / scalar kernels ----
+constexpr int RED_THREADS = 256;
+constexpr int MAX_LBFGS_M = 32;
+
+struct SolveScalars {
+    double f;
+    double sy, yy, gamma;
+    double gp;
+    double coef[4];
+    double step;
+    double pnorm2, tp;           // lambda terms: ||p||^2, Re<theta,p>
+    double thnorm2;              // ||theta||^2 after update (lambda term of f)
+    double rho[MAX_LBFGS_M + 1];
+    double alpha[MAX_LBFGS_M];
+    double beta_coef;
+    int32_t head, count, restart, frozen;
+};
+
+// host launchers (stream ordered)
+hipError_t launch_cgemm(int mode, const GemmArgs &a, int batch, hipStream_t s);
+int gemm_partials_per_problem(int mode, int M, int N);
+
+hipError_t launch_assemble(bool dir, const TileDesc *tiles, const AsmItem *items, int nitems,
+                           const ProbOff *probs, const float2 *theta, const float2 *p,
+                           float2 *X, float2 *X2, hipStream_t s);
+hipError_t launch_grad(const TileDesc *tiles, const GradItem *items, int nitems,
+                       const ProbOff *probs, const float2 *W, const float2 *theta, float2 *g,
+                       hipStream_t s);
+
+hipError_t launch_stage_d(const float2 *D, int64_t ns, int64_t nr, float2 *Ds, int64_t ldk,
+                          float2 *DHs, int64_t lds, hipStream_t s);
+hipError_t launch_copy2d(const float2 *src, int64_t lds, float2 *dst, int64_t ldd,
+                         int64_t rows, int64_t cols, hipStream_t s);
+hipError_t launch_permute_cols(const float2 *in, const int64_t *perm, float2 *out,
+                               int64_t rows, int64_t cols, hipStream_t s);
+
+}  // namespace tlr

@@ -1,0 +1,355 @@
+// Tile kernels: assembly of X = C(Zbar, Lbar, Rbar) and the per-tile gradient
+// contractions.
+//
+// Assembly (Tile Low-rank MDD section): X_ij = L_ij R_ij for i > j and
+// X_ji = X_ij^T; X_ii = Q_ii Q_ii^T or (Z_ii + Z_ii^T)/2. The directional
+// form used by the exact line search expands C(theta + a p) = C(theta) +
+// a X1 + a^2 X2, tile by tile: X1 = P_L R + L P_R, X2 = P_L P_R (and the
+// Q Q^T / dense analogues). Each workgroup builds one 32 x 64 block from
+// factors staged in LDS 32 rank entries at a time; sub-diagonal blocks are
+// written twice (directly and transposed through LDS, both coalesced), so
+// X = X^T holds bit for bit. Q Q^T entries are computed with the operands
+// ordered by (max(a,b), min(a,b)) so the (a,b) and (b,a) entries follow the
+// same rounding path.
+//
+// Gradient (ADMM solver section, eqs. DXLR): with W = D^H r and W' = W + W^T,
+// grad L = W' R^H, grad R = L^H W', grad Q = W' conj(Q), grad Z = W'/2.
+// W' is never formed: each block of W'_ij is built in LDS from a block of
+// W_ij plus the transposed block of W_ji, both read coalesced.
+#include "common.hpp"
+
+namespace tlr {
+namespace {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+
+constexpr int SL_P = ASM_KC + 1;   // pitch of the row-factor stage
+constexpr int SR_P = ASM_BC + 1;   // pitch of the column-factor stage
+constexpr int ST_P = ASM_BR + 1;   // pitch of the transpose stage
+
+template <bool DIR>
+__global__ __launch_bounds__(256) void assemble_kernel(const TileDesc *__restrict__ tiles,
+                                                       const AsmItem *__restrict__ items,
+                                                       const ProbOff *__restrict__ probs,
+                                                       const float2 *__restrict__ theta_base,
+                                                       const float2 *__restrict__ p_base,
+                                                       float2 *__restrict__ X_base,
+                                                       float2 *__restrict__ X2_base) {
+    // stage buffers: [row factor][col factor] (x2 for the directional form), reused for the transpose
+    constexpr int NSTAGE = DIR ? 2 : 1;
+    __shared__ float2 sL[NSTAGE][ASM_BR * SL_P];
+    __shared__ float2 sR[NSTAGE][ASM_KC * SR_P];
+    __shared__ float2 sT[ASM_BC * ST_P];
+
+    const AsmItem it = items[blockIdx.x];
+    const TileDesc td = tiles[it.tile];
+    const ProbOff po = probs[it.prob];
+    const float2 *theta = theta_base + po.theta;
+    const float2 *pv = DIR ? p_base + po.theta : nullptr;
+    float2 *X = X_base + po.x;
+    float2 *X2 = DIR ? X2_base + po.x : nullptr;
+    const int64_t ldx = po.ldx;
+
+    const int t = threadIdx.x;
+    const int col = t & 63;
+    const int rg = t >> 6;
+    const int r0 = it.r0, c0 = it.c0;
+    const int nrow = min(ASM_BR, td.di - r0);
+    const int ncol = min(ASM_BC, td.dj - c0);
+
+    float2 acc[8], acc2[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { acc[i] = make_float2(0.f, 0.f); acc2[i] = acc[i]; }
+
+    if (td.kind == TILE_DENSE) {
+        // X = (Z + Z^T)/2 ; X1 = (P + P^T)/2 ; X2 = 0
+        const float2 *Z = DIR ? pv + td.offA : theta + td.offA;
+        const int d = td.di;
+        // transposed block Z[c0+cc][r0+rr] through LDS
+        for (int e = t; e < ASM_BC * ASM_BR; e += 256) {
+            const int cc = e >> 5, rr = e & 31;
+            float2 v = make_float2(0.f, 0.f);
+            if (cc < ncol && rr < nrow) v = Z[(int64_t)(c0 + cc) * d + r0 + rr];
+            sT[cc * ST_P + rr] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int rr = rg * 8 + i;
+            if (rr < nrow && col < ncol) {
+                const float2 zd = Z[(int64_t)(r0 + rr) * d + c0 + col];
+                const float2 zt = sT[col * ST_P + rr];
+                acc[i] = make_float2(0.5f * (zd.x + zt.x), 0.5f * (zd.y + zt.y));
+            }
+        }
+    } else {
+        const bool qq = (td.kind == TILE_QQ);
+        const int k = td.k;
+        const float2 *Lf = theta + td.offA;                 // L (di x k) or Q (d x k)
+        const float2 *Rf = qq ? Lf : theta + td.offB;       // R (k x dj) or Q again
+        const float2 *PLf = DIR ? pv + td.offA : nullptr;
+        const float2 *PRf = DIR ? (qq ? PLf : pv + td.offB) : nullptr;
+        for (int kc0 = 0; kc0 < k; kc0 += ASM_KC) {
+            const int kn = min(ASM_KC, k - kc0);
+            // row factor rows r0.. : [rr][kk]
+            for (int e = t; e < ASM_BR * ASM_KC; e += 256) {
+                const int rr = e >> 5, kk = e & 31;
+                const bool ok = rr < nrow && kk < kn;
+                const int64_t o = (int64_t)(r0 + rr) * k + kc0 + kk;
+                sL[0][rr * SL_P + kk] = ok ? Lf[o] : make_float2(0.f, 0.f);
+                if (DIR) sL[NSTAGE - 1][rr * SL_P + kk] = ok ? PLf[o] : make_float2(0.f, 0.f);
+            }
+            // column factor: R[kc0+kk][c0+cc]  or  Q[c0+cc][kc0+kk]
+            for (int e = t; e < ASM_KC * ASM_BC; e += 256) {
+                int kk, cc;
+                int64_t o;
+                if (qq) { cc = e >> 5; kk = e & 31; o = (int64_t)(c0 + cc) * k + kc0 + kk; }
+                else { kk = e >> 6; cc = e & 63; o = (int64_t)(kc0 + kk) * td.dj + c0 + cc; }
+                const bool ok = cc < ncol && kk < kn;
+                sR[0][kk * SR_P + cc] = ok ? Rf[o] : make_float2(0.f, 0.f);
+                if (DIR) sR[NSTAGE - 1][kk * SR_P + cc] = ok ? PRf[o] : make_float2(0.f, 0.f);
+            }
+            __syncthreads();
+            for (int kk = 0; kk < kn; ++kk) {
+                const float2 rv = sR[0][kk * SR_P + col];
+                const float2 prv = DIR ? sR[NSTAGE - 1][kk * SR_P + col] : rv;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int rr = rg * 8 + i;
+                    const float2 lv = sL[0][rr * SL_P + kk];
+                    if (!qq) {
+                        if (!DIR) {
+                            acc[i] = cadd(acc[i], cmul(lv, rv));
+                        } else {
+                            const float2 plv = sL[NSTAGE - 1][rr * SL_P + kk];
+                            acc[i] = cadd(acc[i], cadd(cmul(plv, rv), cmul(lv, prv)));
+                            acc2[i] = cadd(acc2[i], cmul(plv, prv));
+                        }
+                    } else {
+                        // operands ordered by (max(a,b), min(a,b)) for bitwise symmetry
+                        const bool lo_first = (r0 + rr) >= (c0 + col);
+                        const float2 qh = lo_first ? lv : rv;
+                        const float2 ql = lo_first ? rv : lv;
+                        if (!DIR) {
+                            acc[i] = cadd(acc[i], cmul(qh, ql));
+                        } else {
+                            const float2 plv = sL[NSTAGE - 1][rr * SL_P + kk];
+                            const float2 ph = lo_first ? plv : prv;
+                            const float2 pl = lo_first ? prv : plv;
+                            acc[i] = cadd(acc[i], cadd(cmul(ph, ql), cmul(qh, pl)));
+                            acc2[i] = cadd(acc2[i], cmul(ph, pl));
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // direct block
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int rr = rg * 8 + i;
+        if (rr < nrow && col < ncol) {
+            const int64_t o = (td.row0 + r0 + rr) * ldx + td.col0 + c0 + col;
+            X[o] = acc[i];
+            if (DIR) X2[o] = acc2[i];
+        }
+    }
+    if (td.kind != TILE_LR) return;
+    // transposed block X_ji = X_ij^T, staged through LDS for coalesced rows
+    for (int pass = 0; pass < (DIR ? 2 : 1); ++pass) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 8; ++i) sT[col * ST_P + rg * 8 + i] = (pass == 0) ? acc[i] : acc2[i];
+        __syncthreads();
+        float2 *dst = (pass == 0) ? X : X2;
+        for (int e = t; e < ASM_BC * ASM_BR; e += 256) {
+            const int cc = e >> 5, rr = e & 31;
+            if (cc < ncol && rr < nrow)
+                dst[(td.col0 + c0 + cc) * ldx + td.row0 + r0 + rr] = sT[cc * ST_P + rr];
+        }
+    }
+}
+
+constexpr int GW_P = GR_CH + 1;
+constexpr int GF_P = GR_CH + 1;
+
+__global__ __launch_bounds__(256) void grad_kernel(const TileDesc *__restrict__ tiles,
+                                                   const GradItem *__restrict__ items,
+                                                   const ProbOff *__restrict__ probs,
+                                                   const float2 *__restrict__ W_base,
+                                                   const float2 *__restrict__ theta_base,
+                                                   float2 *__restrict__ g_base) {
+    __shared__ float2 sW[GR_CH * GW_P];   // 32 x 65 (G_L/G_Q) or 64 x 33 (G_R) or 32 x 65 (G_Z)
+    __shared__ float2 sF[GR_CH * (GR_KK + 1)];   // factor chunk: 32 x 65 (G_L/G_Q) or 64 x 33 (G_R)
+    const GradItem it = items[blockIdx.x];
+    const TileDesc td = tiles[it.tile];
+    const ProbOff po = probs[it.prob];
+    const float2 *W = W_base + po.x;
+    const int64_t ldw = po.ldx;
+    const float2 *theta = theta_base + po.theta;
+    float2 *g = g_base + po.theta;
+    const int t = threadIdx.x;
+
+    if (it.kind == G_Z) {
+        // grad Z = (W_ii + W_ii^T)/2 on the block rows a0.., cols b0..
+        const int d = td.di;
+        const int a0 = it.a0, b0 = it.b0;
+        const int nrow = min(GZ_BR, d - a0), ncol = min(GZ_BC, d - b0);
+        for (int e = t; e < GZ_BC * GZ_BR; e += 256) {
+            const int cc = e >> 5, rr = e & 31;
+            float2 v = make_float2(0.f, 0.f);
+            if (cc < ncol && rr < nrow) v = W[(td.row0 + b0 + cc) * ldw + td.col0 + a0 + rr];
+            sW[cc * (GZ_BR + 1) + rr] = v;
+        }
+        __syncthreads();
+        for (int e = t; e < GZ_BR * GZ_BC; e += 256) {
+            const int rr = e >> 6, cc = e & 63;
+            if (rr < nrow && cc < ncol) {
+                const float2 wd = W[(td.row0 + a0 + rr) * ldw + td.col0 + b0 + cc];
+                const float2 wt = sW[cc * (GZ_BR + 1) + rr];
+                g[td.offA + (int64_t)(a0 + rr) * d + b0 + cc] =
+                    make_float2(0.5f * (wd.x + wt.x), 0.5f * (wd.y + wt.y));
+            }
+        }
+        return;
+    }
+
+    const int k = td.k;
+    const int b0 = it.b0;
+    const int kn = min(GR_KK, k - b0);
+    float2 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = make_float2(0.f, 0.f);
+
+    if (it.kind == G_L || it.kind == G_Q) {
+        // grad[r][kk] = sum_c W'[r][c] conj(F[kk][c]);  F = R (k x dj) or Q^T
+        const int a0 = it.a0;
+        const int nrow = min(GR_ROWS, td.di - a0);
+        const int ncols = td.dj;
+        const float2 *F = (it.kind == G_L) ? theta + td.offB : theta + td.offA;
+        const int r = t >> 3, kq = (t & 7) * 4;
+        for (int c0 = 0; c0 < ncols; c0 += GR_CH) {
+            const int cn = min(GR_CH, ncols - c0);
+            for (int e = t; e < GR_ROWS * GR_CH; e += 256) {
+                const int rr = e >> 6, cc = e & 63;
+                float2 v = make_float2(0.f, 0.f);
+                if (rr < nrow && cc < cn) v = W[(td.row0 + a0 + rr) * ldw + td.col0 + c0 + cc];
+                sW[rr * GW_P + cc] = v;
+            }
+            for (int e = t; e < GR_KK * GR_CH; e += 256) {
+                int kk, cc;
+                int64_t o;
+                if (it.kind == G_L) { kk = e >> 6; cc = e & 63; o = (int64_t)(b0 + kk) * ncols + c0 + cc; }
+                else { cc = e >> 5; kk = e & 31; o = (int64_t)(c0 + cc) * k + b0 + kk; }
+                sF[kk * GF_P + cc] = (kk < kn && cc < cn) ? F[o] : make_float2(0.f, 0.f);
+            }
+            __syncthreads();
+            for (int e = t; e < GR_CH * GR_ROWS; e += 256) {
+                const int cc = e >> 5, rr = e & 31;
+                if (rr < nrow && cc < cn) {
+                    const float2 wt = W[(td.col0 + c0 + cc) * ldw + td.row0 + a0 + rr];
+                    sW[rr * GW_P + cc] = cadd(sW[rr * GW_P + cc], wt);
+                }
+            }
+            __syncthreads();
+            for (int cc = 0; cc < cn; ++cc) {
+                const float2 w = sW[r * GW_P + cc];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = cadd(acc[q], cmulc(w, sF[(kq + q) * GF_P + cc]));
+            }
+            __syncthreads();
+        }
+        if (r < nrow) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int kk = kq + q;
+                if (kk < kn) {
+                    // grad L (di x k) sits at the offset of L, grad Q (d x k) at that of Q
+                    g[td.offA + (int64_t)(a0 + r) * k + b0 + kk] = acc[q];
+                }
+            }
+        }
+        return;
+    }
+
+    // G_R: grad R[kk][c] = sum_r conj(L[r][kk]) W'[r][c], columns a0.. of tile j
+    {
+        const int a0 = it.a0;
+        const int ncol = min(GR_ROWS, td.dj - a0);
+        const int nrows = td.di;
+        const float2 *L = theta + td.offA;
+        const int c = t >> 3, kq = (t & 7) * 4;
+        constexpr int WP = GR_ROWS + 1;  // sW as [r][c] 64 x 33
+        constexpr int LP = GR_KK + 1;    // sF as [r][kk] 64 x 33
+        for (int q0 = 0; q0 < nrows; q0 += GR_CH) {
+            const int rn = min(GR_CH, nrows - q0);
+            for (int e = t; e < GR_CH * GR_ROWS; e += 256) {
+                const int rr = e >> 5, cc = e & 31;
+                float2 v = make_float2(0.f, 0.f);
+                if (rr < rn && cc < ncol) v = W[(td.row0 + q0 + rr) * ldw + td.col0 + a0 + cc];
+                sW[rr * WP + cc] = v;
+            }
+            for (int e = t; e < GR_CH * GR_KK; e += 256) {
+                const int rr = e >> 5, kk = e & 31;
+                sF[rr * LP + kk] = (rr < rn && kk < kn) ? L[(int64_t)(q0 + rr) * k + b0 + kk]
+                                                        : make_float2(0.f, 0.f);
+            }
+            __syncthreads();
+            for (int e = t; e < GR_ROWS * GR_CH; e += 256) {
+                const int cc = e >> 6, rr = e & 63;
+                if (rr < rn && cc < ncol) {
+                    const float2 wt = W[(td.col0 + a0 + cc) * ldw + td.row0 + q0 + rr];
+                    sW[rr * WP + cc] = cadd(sW[rr * WP + cc], wt);
+                }
+            }
+            __syncthreads();
+            for (int rr = 0; rr < rn; ++rr) {
+                const float2 w = sW[rr * WP + c];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = cadd(acc[q], cmulc(w, sF[rr * LP + kq + q]));
+            }
+            __syncthreads();
+        }
+        // acc = sum W' conj(L) -> grad R = L^H W' has exactly these entries
+        if (c < ncol) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int kk = kq + q;
+                if (kk < kn) g[td.offB + (int64_t)(b0 + kk) * td.dj + a0 + c] = acc[q];
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_assemble(bool dir, const TileDesc *tiles, const AsmItem *items, int nitems,
+                           const ProbOff *probs, const float2 *theta, const float2 *p,
+                           float2 *X, float2 *X2, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    if (dir)
+        hipLaunchKernelGGL(assemble_kernel<true>, dim3(nitems), dim3(256), 0, s, tiles, items, probs,
+                           theta, p, X, X2);
+    else
+        hipLaunchKernelGGL(assemble_kernel<false>, dim3(nitems), dim3(256), 0, s, tiles, items, probs,
+                           theta, p, X, X2);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(const TileDesc *tiles, const GradItem *items, int nitems,
+                       const ProbOff *probs, const float2 *W, const float2 *theta, float2 *g,
+                       hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(grad_kernel, dim3(nitems), dim3(256), 0, s, tiles, items, probs, W, theta, g);
+    return hipGetLastError();
+}
+
+}  // namespace tlr

@@ -1,0 +1,58 @@
+// Segmented vector kernels of the optimiser (internal).
+#pragma once
+#include "common.hpp"
+
+namespace tlr {
+
+// A contiguous run of at most VEC_CH floats belonging to one problem.
+struct VecSeg {
+    int64_t off;    // first float
+    int32_t n;      // floats in the run
+    int32_t prob;   // problem index
+    int32_t part;   // partial-sum slot (prob * pstride + local index)
+    int32_t pad;
+};
+constexpr int VEC_CH = 8192;
+
+enum FinOp : int32_t {
+    FIN_INIT = 0, FIN_F, FIN_F_OUT, FIN_THNORM, FIN_PAIR, FIN_ALPHA, FIN_BETA, FIN_GP, FIN_LAMTERMS, FIN_LINE
+};
+
+struct FinArgs {
+    int32_t op;
+    int32_t nsum;          // sums per partial entry
+    const double *partials;
+    int64_t pstride;       // entries per problem
+    const int32_t *counts; // entries used per problem (NULL -> ucount)
+    int32_t ucount;
+    int32_t i;             // loop index (FIN_ALPHA / FIN_BETA)
+    int32_t m1;            // ring slots (lbfgs_m + 1)
+    int32_t t;             // f-history index (FIN_F)
+    SolveScalars *sc;
+    double *const *fhist;  // device table of per-problem f-history pointers (FIN_F, batches)
+    double *fhist0;        // f-history of a single problem (FIN_F)
+    double *fout;          // FIN_F_OUT: per-problem objective
+    double lam;
+};
+
+hipError_t launch_pair(const VecSeg *segs, int nseg, const float *gnew, const float *gprev, float *Yb,
+                       const float *Sb, int64_t stride2, const SolveScalars *sc, double *part, hipStream_t s);
+hipError_t launch_twoloop1(const VecSeg *segs, int nseg, int i, int m1, float *q, const float *g,
+                           const float *Sb, const float *Yb, int64_t stride2, const SolveScalars *sc,
+                           double *part, hipStream_t s);
+hipError_t launch_twoloop2(const VecSeg *segs, int nseg, int start, int last, int iu, int inext, int m1,
+                           const float *q, float *z, float *p, const float *g, const float *Sb,
+                           const float *Yb, int64_t stride2, const SolveScalars *sc, double *part,
+                           hipStream_t s);
+hipError_t launch_restart(const VecSeg *segs, int nseg, int force, float *p, const float *g,
+                          const SolveScalars *sc, hipStream_t s);
+hipError_t launch_reg_grad(const VecSeg *segs, int nseg, float *g, const float *th, float lam2, hipStream_t s);
+hipError_t launch_dot2(const VecSeg *segs, int nseg, const float *x0, const float *y0, const float *x1,
+                       const float *y1, double *part, hipStream_t s);
+hipError_t launch_theta_update(const VecSeg *segs, int nseg, float *th, const float *p, float *Sb,
+                               int64_t stride2, const SolveScalars *sc, double *part, hipStream_t s);
+hipError_t launch_resid_update(const VecSeg *segs, int nseg, float *r, const float *a, const float *b,
+                               const SolveScalars *sc, double *part, hipStream_t s);
+hipError_t launch_finalize(const FinArgs &fa, int nprob, hipStream_t s);
+
+}  // namespace tlr

@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+  * the built library loads and exports every function include/tlrmdd.h declares;
+  * hilbert_order (host C++) equals the oracle bit for bit on many grids;
+  * layout validation: tlrmdd_theta_size rejects every malformed layout and
+    otherwise equals the oracle's packed size.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tlrmdd.h")
+
+lib_mod = pytest.importorskip("paper_2412_14973_amd._lib")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return lib_mod.load()
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tlrmdd_\w+|hilbert_order)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert "tlrmdd_solve" in names and "hilbert_order" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(lib_mod.EXPORTS)
+
+
+def test_status_strings(lib):
+    for s in range(6):
+        assert lib.tlrmdd_status_string(s)
+    assert lib.tlrmdd_status_string(0) == b"ok"
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (2, 2), (3, 3), (4, 4), (8, 8), (5, 7), (32, 32), (48, 48),
+                                   (64, 64), (90, 17), (96, 96), (177, 90)])
+def test_hilbert_bit_exact_vs_oracle(nx, ny):
+    import paper_2412_14973_amd as tl
+    g = synth.make_geometry(nx, ny)
+    got = tl.hilbert_order(g.rec_ix, g.rec_iy)
+    ref = O.hilbert_order(g.rec_ix, g.rec_iy)
+    assert got.dtype == np.int64
+    assert np.array_equal(got, ref)
+
+
+def test_hilbert_duplicates_and_scattered_points():
+    import paper_2412_14973_amd as tl
+    rng = np.random.default_rng(5)
+    ix = rng.integers(0, 37, 500).astype(np.int32)
+    iy = rng.integers(0, 11, 500).astype(np.int32)
+    assert np.array_equal(tl.hilbert_order(ix, iy), O.hilbert_order(ix, iy))
+
+
+def test_hilbert_rejects_bad_input(lib):
+    import paper_2412_14973_amd as tl
+    with pytest.raises(tl.TLRMDDError):
+        tl.hilbert_order(np.array([0, -1]), np.array([0, 0]))
+    assert lib.hilbert_order(None, None, -1, None) == 1
+    assert lib.hilbert_order(None, None, 0, None) == 0
+    assert lib.hilbert_order(None, None, 3, None) == 1
+
+
+def _theta_size(lib, tile_size, rank_off, rank_diag, ns=4, nr=None):
+    ts = np.ascontiguousarray(tile_size, dtype=np.int32)
+    ro = np.ascontiguousarray(rank_off, dtype=np.int32)
+    rd = np.ascontiguousarray(rank_diag, dtype=np.int32)
+    P = ctypes.POINTER(ctypes.c_int32)
+    lay = lib_mod.c_layout(int(ts.sum()) if nr is None else nr, ns, int(ts.shape[0]), ts.ctypes.data_as(P),
+                           ro.ctypes.data_as(P) if ro.size else None, rd.ctypes.data_as(P))
+    return lib.tlrmdd_theta_size(ctypes.byref(lay))
+
+
+@pytest.mark.parametrize("layout", [
+    synth.uniform_layout(64, 16, 4, 8),
+    synth.uniform_layout(64, 16, 4, -1),
+    synth.uniform_layout(2304, 512, 33, -1),
+    synth.adaptive_layout(1024, 40),
+    synth.uniform_layout(30, 8, 3, 2),
+])
+def test_theta_size_matches_oracle(lib, layout):
+    T = O.tiling(layout.tile_size, layout.rank_off, layout.rank_diag)
+    assert _theta_size(lib, layout.tile_size, layout.rank_off, layout.rank_diag) == T.size
+
+
+@pytest.mark.parametrize("ts,ro,rd,nr", [
+    ([4, 4], [5], [2, 2], None),        # off rank > min(d_i, d_j)
+    ([4, 4], [0], [2, 2], None),        # off rank 0
+    ([4, 4], [2], [5, 2], None),        # diag rank > d_i
+    ([4, 4], [2], [0, 2], None),        # diag rank 0
+    ([4, 4], [2], [-2, 2], None),       # diag rank neither -1 nor >= 1
+    ([4, 0], [1], [2, 1], None),        # empty tile
+    ([4, 4], [2], [2, 2], 9),           # sum d_i != nr
+])
+def test_invalid_layouts_rejected(lib, ts, ro, rd, nr):
+    assert _theta_size(lib, ts, ro, rd, nr=nr) < 0
+    assert lib.tlrmdd_last_error()
+
+
+def test_null_layout(lib):
+    assert lib.tlrmdd_theta_size(None) < 0
+    h = ctypes.c_void_p()
+    assert lib.tlrmdd_plan_create(None, ctypes.byref(h)) == 1

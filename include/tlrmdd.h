@@ -183,6 +183,24 @@ int hilbert_order(const int32_t *ix, const int32_t *iy, int64_t n, int64_t *perm
 int tlrmdd_permute_columns(const void *in, const int64_t *perm, void *out,
                            int64_t rows, int64_t cols, hipStream_t stream);
 
+/* ---- kernel timing (instrumentation) -------------------------------------
+ * Between tlrmdd_timing_begin() and tlrmdd_timing_end(), every launch of the
+ * kernel kinds below made by this library (any thread, any stream) is
+ * bracketed by two HIP events recorded on its own stream. timing_end waits
+ * for the last event, then writes the summed elapsed milliseconds and the
+ * launch count of each kind into ms[TLRMDD_K_NKINDS] and
+ * launches[TLRMDD_K_NKINDS] (host arrays, either may be NULL). Calls that
+ * run while timing is active are serialised with the recorder by a mutex. */
+#define TLRMDD_K_GEMM_RESID    0  /* r = D X - U with FP64 |r|^2 partials      */
+#define TLRMDD_K_GEMM_ADJOINT  1  /* W = D^H r                                 */
+#define TLRMDD_K_GEMM_LINE     2  /* [a | b] = D [X1 | X2] + line-search sums  */
+#define TLRMDD_K_ASSEMBLE      3  /* X = C(theta)                              */
+#define TLRMDD_K_ASSEMBLE_DIR  4  /* X1, X2 of the line search                 */
+#define TLRMDD_K_GRAD          5  /* per-tile gradient contractions            */
+#define TLRMDD_K_NKINDS        6
+int tlrmdd_timing_begin(void);
+int tlrmdd_timing_end(double *ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -193,6 +193,22 @@ def solve_batched(plans, Ds, Us, thetas0, iters, optimizer=LBFGS, lbfgs_m=5, pre
     return thetas, fh
 
 
+class KernelTimer:
+    """Context manager: per-kind summed kernel milliseconds and launch counts (HIP events)."""
+
+    def __enter__(self):
+        _lib.check(_lib.load().tlrmdd_timing_begin(), "tlrmdd_timing_begin")
+        return self
+
+    def __exit__(self, *exc):
+        ms = (ctypes.c_double * _lib.K_NKINDS)()
+        n = (ctypes.c_int64 * _lib.K_NKINDS)()
+        _lib.check(_lib.load().tlrmdd_timing_end(ms, n), "tlrmdd_timing_end")
+        self.ms = {k: ms[i] for i, k in enumerate(_lib.KIND_NAMES)}
+        self.launches = {k: n[i] for i, k in enumerate(_lib.KIND_NAMES)}
+        return False
+
+
 class TLRMDDObjective(torch.autograd.Function):
     """f(theta) = 1/2 ||D C(theta) - U||^2 with a hand-written HIP backward.
 

@@ -64,7 +64,11 @@ _SIGS = {
     "hilbert_order": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "tlrmdd_permute_columns": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                               ctypes.c_int64, ctypes.c_void_p]),
+    "tlrmdd_timing_begin": (ctypes.c_int, []),
+    "tlrmdd_timing_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
 }
+K_GEMM_RESID, K_GEMM_ADJOINT, K_GEMM_LINE, K_ASSEMBLE, K_ASSEMBLE_DIR, K_GRAD, K_NKINDS = range(7)
+KIND_NAMES = ("gemm_resid", "gemm_adjoint", "gemm_line", "assemble", "assemble_dir", "grad")
 
 EXPORTS = tuple(_SIGS)
 

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -34,6 +35,43 @@ int fail(int status, const std::string &msg) {
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// kernel timing: HIP events around launches of selected kinds
+// ---------------------------------------------------------------------------
+struct TimedLaunch {
+    int kind;
+    hipEvent_t a, b;
+};
+struct Recorder {
+    std::mutex mu;
+    bool on = false;
+    std::vector<TimedLaunch> ev;
+    std::vector<hipEvent_t> pool;
+} g_rec;
+
+hipEvent_t rec_event() {
+    if (!g_rec.pool.empty()) {
+        hipEvent_t e = g_rec.pool.back();
+        g_rec.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+template <class F>
+hipError_t timed(int kind, hipStream_t s, F &&launch) {
+    if (!g_rec.on) return launch();
+    std::lock_guard<std::mutex> lk(g_rec.mu);
+    hipEvent_t a = rec_event(), b = rec_event();
+    if (a) (void)hipEventRecord(a, s);
+    hipError_t e = launch();
+    if (b) (void)hipEventRecord(b, s);
+    if (a && b) g_rec.ev.push_back(TimedLaunch{kind, a, b});
+    return e;
+}
 
 // ---------------------------------------------------------------------------
 // layout validation and tables
@@ -489,7 +527,7 @@ int gemm_resid(const Ctx &c, const float2 *X, int64_t sX, const float2 *U, int64
     g.E = U; g.lde = ldu; g.sE = sU;
     g.partials = c.w.partials; g.sP = (int64_t)c.pstride;   // one sum per workgroup
     g.M = (int)c.ns; g.N = (int)c.nr; g.K = (int)c.nr;
-    HIP_TRY(launch_cgemm(GM_RESID, g, c.nprob, c.s));
+    HIP_TRY(timed(TLRMDD_K_GEMM_RESID, c.s, [&] { return launch_cgemm(GM_RESID, g, c.nprob, c.s); }));
     return TLRMDD_OK;
 }
 
@@ -499,7 +537,7 @@ int gemm_adjoint(const Ctx &c, const float2 *r, float2 *W, int64_t sW) {
     g.B = r; g.ldb = c.ldk; g.sB = c.ns * c.ldk;
     g.C = W; g.ldc = c.ldk; g.sC = sW;
     g.M = (int)c.nr; g.N = (int)c.nr; g.K = (int)c.ns;
-    HIP_TRY(launch_cgemm(GM_STORE, g, c.nprob, c.s));
+    HIP_TRY(timed(TLRMDD_K_GEMM_ADJOINT, c.s, [&] { return launch_cgemm(GM_STORE, g, c.nprob, c.s); }));
     return TLRMDD_OK;
 }
 
@@ -511,7 +549,7 @@ int gemm_line(const Ctx &c, const float2 *X1, const float2 *X2, int64_t sX) {
     g.E = c.w.r; g.lde = c.ldk; g.sE = c.ns * c.ldk;
     g.partials = c.w.partials; g.sP = (int64_t)c.pstride * 5;
     g.M = (int)c.ns; g.N = (int)c.nr; g.K = (int)c.nr;
-    HIP_TRY(launch_cgemm(GM_LINE, g, c.nprob, c.s));
+    HIP_TRY(timed(TLRMDD_K_GEMM_LINE, c.s, [&] { return launch_cgemm(GM_LINE, g, c.nprob, c.s); }));
     return TLRMDD_OK;
 }
 
@@ -586,8 +624,8 @@ int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const 
     if ((st = fin(c, f0, nullptr, 0, 1))) return st;
 
     auto objective_fresh = [&](int t) -> int {
-        HIP_TRY(launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)c.w.th,
-                                nullptr, X1, nullptr, s));
+        HIP_TRY(timed(TLRMDD_K_ASSEMBLE, s, [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)c.w.th,
+                                nullptr, X1, nullptr, s); }));
         int e = gemm_resid(c, X1, xstride, c.w.Us, c.ldk, rstride, c.w.r);
         if (e) return e;
         FinArgs f = fin_args(FIN_F, c.w.sc);
@@ -607,8 +645,8 @@ int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const 
     for (int t = 0; t < opts->iters; ++t) {
         // gradient from the tracked residual (eqs. DXLR)
         if ((st = gemm_adjoint(c, c.w.r, X1, xstride))) return st;
-        HIP_TRY(launch_grad(c.D.tiles, c.D.grad_items, c.D.n_grad, c.D.probs, X1, (const float2 *)c.w.th,
-                            (float2 *)gcur, s));
+        HIP_TRY(timed(TLRMDD_K_GRAD, s, [&] { return launch_grad(c.D.tiles, c.D.grad_items, c.D.n_grad, c.D.probs, X1, (const float2 *)c.w.th,
+                            (float2 *)gcur, s); }));
         if (lam != 0.0) HIP_TRY(launch_reg_grad(c.D.tsegs, nt, gcur, c.w.th, (float)(2.0 * lam), s));
         // direction
         if (!lbfgs) {
@@ -647,8 +685,8 @@ int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const 
             HIP_TRY(launch_restart(c.D.tsegs, nt, 0, c.w.p, gcur, c.w.sc, s));
         }
         // exact line search: a = D C1(theta;p), b = D C2(p)
-        HIP_TRY(launch_assemble(true, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)c.w.th,
-                                (const float2 *)c.w.p, X1, X2, s));
+        HIP_TRY(timed(TLRMDD_K_ASSEMBLE_DIR, s, [&] { return launch_assemble(true, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)c.w.th,
+                                (const float2 *)c.w.p, X1, X2, s); }));
         if (lam != 0.0) {
             HIP_TRY(launch_dot2(c.D.tsegs, nt, c.w.th, c.w.p, c.w.p, c.w.p, c.w.partials, s));
             if ((st = fin(c, fin_args(FIN_LAMTERMS, c.w.sc), c.D.tcount, 0, 2))) return st;
@@ -707,8 +745,8 @@ int tlrmdd_forward(tlrmdd_plan plan, const void *D, const void *U, const void *t
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     c.D = plan->D;
     HIP_TRY(launch_stage_d((const float2 *)D, c.ns, c.nr, c.w.Ds, c.ldk, nullptr, 0, stream));
-    HIP_TRY(launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
-                            c.w.XW, nullptr, stream));
+    HIP_TRY(timed(TLRMDD_K_ASSEMBLE, stream, [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
+                            c.w.XW, nullptr, stream); }));
     if ((st = gemm_resid(c, c.w.XW, 0, (const float2 *)U, c.nr, 0, c.w.r))) return st;
     FinArgs f = fin_args(FIN_F_OUT, c.w.sc);
     f.fout = f_dev;
@@ -737,8 +775,8 @@ int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *thet
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     c.D = plan->D;
     HIP_TRY(launch_stage_d((const float2 *)D, c.ns, c.nr, c.w.Ds, c.ldk, c.w.DHs, c.lds, stream));
-    HIP_TRY(launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
-                            c.w.XW, nullptr, stream));
+    HIP_TRY(timed(TLRMDD_K_ASSEMBLE, stream, [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
+                            c.w.XW, nullptr, stream); }));
     if ((st = gemm_resid(c, c.w.XW, 0, (const float2 *)U, c.nr, 0, c.w.r))) return st;
     if (f_dev) {
         FinArgs f = fin_args(FIN_F_OUT, c.w.sc);
@@ -747,8 +785,8 @@ int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *thet
     }
     // the assembled X is dead once r exists: W = D^H r reuses its storage
     if ((st = gemm_adjoint(c, c.w.r, c.w.XW, 0))) return st;
-    HIP_TRY(launch_grad(c.D.tiles, c.D.grad_items, c.D.n_grad, c.D.probs, c.w.XW, (const float2 *)theta,
-                        (float2 *)grad_out, stream));
+    HIP_TRY(timed(TLRMDD_K_GRAD, stream, [&] { return launch_grad(c.D.tiles, c.D.grad_items, c.D.n_grad, c.D.probs, c.w.XW, (const float2 *)theta,
+                        (float2 *)grad_out, stream); }));
     return TLRMDD_OK;
 }
 
@@ -794,6 +832,48 @@ int tlrmdd_solve_batched(int count, const tlrmdd_plan *plans, const void *const 
     if (count <= 0 || !plans || !D || !U || !theta_inout || !f_hist_dev)
         return fail(TLRMDD_INVALID_ARGUMENT, "bad arguments");
     return solve_impl(count, plans, D, U, theta_inout, opts, f_hist_dev, workspace, ws_bytes, stream);
+}
+
+int tlrmdd_timing_begin(void) {
+    g_last_error.clear();
+    std::lock_guard<std::mutex> lk(g_rec.mu);
+    for (TimedLaunch &t : g_rec.ev) {
+        g_rec.pool.push_back(t.a);
+        g_rec.pool.push_back(t.b);
+    }
+    g_rec.ev.clear();
+    g_rec.on = true;
+    return TLRMDD_OK;
+}
+
+int tlrmdd_timing_end(double *ms, int64_t *launches) {
+    g_last_error.clear();
+    std::lock_guard<std::mutex> lk(g_rec.mu);
+    g_rec.on = false;
+    double acc[TLRMDD_K_NKINDS] = {0};
+    int64_t cnt[TLRMDD_K_NKINDS] = {0};
+    int status = TLRMDD_OK;
+    for (TimedLaunch &t : g_rec.ev) {
+        float v = 0.f;
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&v, t.a, t.b);
+        if (e != hipSuccess) {
+            status = fail(TLRMDD_HIP_ERROR, std::string("timing events: ") + hipGetErrorString(e));
+            continue;
+        }
+        if (t.kind >= 0 && t.kind < TLRMDD_K_NKINDS) {
+            acc[t.kind] += v;
+            cnt[t.kind] += 1;
+        }
+        g_rec.pool.push_back(t.a);
+        g_rec.pool.push_back(t.b);
+    }
+    g_rec.ev.clear();
+    for (int k = 0; k < TLRMDD_K_NKINDS; ++k) {
+        if (ms) ms[k] = acc[k];
+        if (launches) launches[k] = cnt[k];
+    }
+    return status;
 }
 
 int hilbert_order(const int32_t *ix, const int32_t *iy, int64_t n, int64_t *perm_out) {

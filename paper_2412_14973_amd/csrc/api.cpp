@@ -201,8 +201,8 @@ void append_problem(Tables &T, const HostLayout &H, int prob, int64_t x_off, int
     T.theta_total += H.theta_size;
 }
 
-// segments: called after all problems are appended
-void build_segments(Tables &T, const std::vector<const HostLayout *> &Hs, int64_t ns, int64_t ldk) {
+// segments: called after all problems are appended; residual space is nsp x ldk per problem
+void build_segments(Tables &T, const std::vector<const HostLayout *> &Hs, int64_t nsp, int64_t ldk) {
     const int np = (int)Hs.size();
     T.tseg_count.assign(np, 0);
     int maxseg = 0;
@@ -210,7 +210,7 @@ void build_segments(Tables &T, const std::vector<const HostLayout *> &Hs, int64_
         const int64_t n2 = 2 * Hs[p]->theta_size;
         maxseg = std::max<int>(maxseg, (int)((n2 + VEC_CH - 1) / VEC_CH));
     }
-    const int64_t r2 = 2 * ns * ldk;
+    const int64_t r2 = 2 * nsp * ldk;
     T.rseg_per_prob = (int)((r2 + VEC_CH - 1) / VEC_CH);
     T.tseg_max = maxseg;
     for (int p = 0; p < np; ++p) {
@@ -250,7 +250,7 @@ struct DevTables {
 
 struct tlrmdd_plan_s {
     HostLayout H;
-    int64_t ldk = 0, lds = 0;   // padded leading dimensions (complex) of nr- and ns-long rows
+    int64_t ldk = 0, lds = 0;   // padded sizes (complex): nr and ns rounded up to GEMM_PAD
     Tables T;
     int device = 0;
     DevTables D{};              // single-problem tables, uploaded once at plan creation
@@ -308,10 +308,10 @@ void assign_parts(Tables &T, int pstride) {
     for (VecSeg &s : T.rsegs) s.part = s.prob * pstride + local[s.prob]++;
 }
 
-int partial_stride(const Tables &T, int64_t nr, int64_t ns) {
+int partial_stride(const Tables &T, int64_t nrp, int64_t nsp) {
     int ps = std::max(T.tseg_max, T.rseg_per_prob);
-    ps = std::max(ps, gemm_partials_per_problem(GM_LINE, (int)ns, (int)nr) / 5);
-    ps = std::max(ps, gemm_partials_per_problem(GM_RESID, (int)ns, (int)nr));
+    ps = std::max(ps, gemm_partials_per_problem(GM_LINE, (int)nsp, (int)nrp) / 5);
+    ps = std::max(ps, gemm_partials_per_problem(GM_RESID, (int)nsp, (int)nrp));
     return std::max(ps, 1);
 }
 
@@ -327,9 +327,10 @@ struct Ws {
     size_t bytes = 0;
 };
 
-// op: 0 forward, 1 grad, 2 solve. Sizes for `nprob` problems of the same nr, ns.
-Ws carve(char *base, int op, int nprob, int64_t nr, int64_t ns, int64_t ldk, int64_t lds, int64_t theta_total,
-         int m1, int pstride, size_t tbytes) {
+// op: 0 forward, 1 grad, 2 solve. Sizes for `nprob` problems of the same shape; every matrix is
+// padded to whole GEMM tiles: ns x nr operands are lds x ldk (rows x cols), nr x nr ones ldk x ldk.
+Ws carve(char *base, int op, int nprob, int64_t ldk, int64_t lds, int64_t theta_total, int m1, int pstride,
+         size_t tbytes) {
     Ws w;
     size_t o = 0;
     auto take = [&](size_t bytes) -> char * {
@@ -338,10 +339,10 @@ Ws carve(char *base, int op, int nprob, int64_t nr, int64_t ns, int64_t ldk, int
         return p;
     };
     const size_t c8 = sizeof(float2);
-    const size_t xsz = (size_t)nprob * nr * ldk * c8;
-    const size_t rsz = (size_t)nprob * ns * ldk * c8;
+    const size_t xsz = (size_t)nprob * ldk * ldk * c8;
+    const size_t rsz = (size_t)nprob * lds * ldk * c8;
     w.Ds = (float2 *)take(rsz);
-    if (op >= 1) w.DHs = (float2 *)take((size_t)nprob * nr * lds * c8);
+    if (op >= 1) w.DHs = (float2 *)take((size_t)nprob * ldk * lds * c8);
     w.XW = (float2 *)take(op == 2 ? 2 * xsz : xsz);
     w.r = (float2 *)take(rsz);
     if (op == 2) {
@@ -435,11 +436,11 @@ int tlrmdd_plan_create(const tlrmdd_layout *layout, tlrmdd_plan *plan_out) {
     if (!P) return fail(TLRMDD_WORKSPACE, "host allocation failed");
     int st = build_layout(layout, P->H);
     if (st != TLRMDD_OK) { delete P; return st; }
-    P->ldk = round_up(P->H.nr, 2);
-    P->lds = round_up(P->H.ns, 2);
+    P->ldk = round_up(P->H.nr, GEMM_PAD);
+    P->lds = round_up(P->H.ns, GEMM_PAD);
     append_problem(P->T, P->H, 0, 0, P->ldk);
-    build_segments(P->T, {&P->H}, P->H.ns, P->ldk);
-    assign_parts(P->T, partial_stride(P->T, P->H.nr, P->H.ns));
+    build_segments(P->T, {&P->H}, P->lds, P->ldk);
+    assign_parts(P->T, partial_stride(P->T, P->ldk, P->lds));
     hipError_t e = hipGetDevice(&P->device);
     if (e == hipSuccess) e = hipMalloc(&P->d_block, tables_bytes(P->T, 1));
     if (e == hipSuccess) {
@@ -465,8 +466,8 @@ int tlrmdd_plan_destroy(tlrmdd_plan plan) {
 
 static size_t ws_bytes_single(const tlrmdd_plan P, int op, int m1) {
     const Tables &T = P->T;
-    const int ps = partial_stride(T, P->H.nr, P->H.ns);
-    return carve(nullptr, op, 1, P->H.nr, P->H.ns, P->ldk, P->lds, P->H.theta_size, m1, ps, 0).bytes;
+    const int ps = partial_stride(T, P->ldk, P->lds);
+    return carve(nullptr, op, 1, P->ldk, P->lds, P->H.theta_size, m1, ps, 0).bytes;
 }
 
 int tlrmdd_workspace_bytes(tlrmdd_plan plan, int op, const tlrmdd_opts *opts, size_t *bytes) {
@@ -502,7 +503,7 @@ int upload_tables(const Tables &T, int nprob, const Ws &w, DevTables &D, double 
 
 struct Ctx {
     int nprob;
-    int64_t nr, ns, ldk, lds;
+    int64_t nr, ns, ldk, lds;   // true sizes and padded sizes (ldk >= nr, lds >= ns)
     int pstride;
     Ws w;
     DevTables D;
@@ -521,40 +522,41 @@ int fin(const Ctx &c, FinArgs f, const int32_t *counts, int ucount, int nsum) {
 
 int gemm_resid(const Ctx &c, const float2 *X, int64_t sX, const float2 *U, int64_t ldu, int64_t sU, float2 *r) {
     GemmArgs g = gemm_args();
-    g.A = c.w.Ds; g.lda = c.ldk; g.sA = c.ns * c.ldk;
+    g.A = c.w.Ds; g.lda = c.ldk; g.sA = c.lds * c.ldk;
     g.B = X; g.ldb = c.ldk; g.sB = sX;
-    g.C = r; g.ldc = c.ldk; g.sC = c.ns * c.ldk;
+    g.C = r; g.ldc = c.ldk; g.sC = c.lds * c.ldk;
     g.E = U; g.lde = ldu; g.sE = sU;
     g.partials = c.w.partials; g.sP = (int64_t)c.pstride;   // one sum per workgroup
-    g.M = (int)c.ns; g.N = (int)c.nr; g.K = (int)c.nr;
+    g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
+    g.Me = (int)c.ns; g.Ne = (int)c.nr;
     HIP_TRY(timed(TLRMDD_K_GEMM_RESID, c.s, [&] { return launch_cgemm(GM_RESID, g, c.nprob, c.s); }));
     return TLRMDD_OK;
 }
 
 int gemm_adjoint(const Ctx &c, const float2 *r, float2 *W, int64_t sW) {
     GemmArgs g = gemm_args();
-    g.A = c.w.DHs; g.lda = c.lds; g.sA = c.nr * c.lds;
-    g.B = r; g.ldb = c.ldk; g.sB = c.ns * c.ldk;
+    g.A = c.w.DHs; g.lda = c.lds; g.sA = c.ldk * c.lds;
+    g.B = r; g.ldb = c.ldk; g.sB = c.lds * c.ldk;
     g.C = W; g.ldc = c.ldk; g.sC = sW;
-    g.M = (int)c.nr; g.N = (int)c.nr; g.K = (int)c.ns;
+    g.M = (int)c.ldk; g.N = (int)c.ldk; g.K = (int)c.lds;
     HIP_TRY(timed(TLRMDD_K_GEMM_ADJOINT, c.s, [&] { return launch_cgemm(GM_STORE, g, c.nprob, c.s); }));
     return TLRMDD_OK;
 }
 
 int gemm_line(const Ctx &c, const float2 *X1, const float2 *X2, int64_t sX) {
     GemmArgs g = gemm_args();
-    g.A = c.w.Ds; g.lda = c.ldk; g.sA = c.ns * c.ldk;
+    g.A = c.w.Ds; g.lda = c.ldk; g.sA = c.lds * c.ldk;
     g.B = X1; g.B2 = X2; g.ldb = c.ldk; g.sB = sX;
-    g.C = c.w.a; g.C2 = c.w.b; g.ldc = c.ldk; g.sC = c.ns * c.ldk;
-    g.E = c.w.r; g.lde = c.ldk; g.sE = c.ns * c.ldk;
+    g.C = c.w.a; g.C2 = c.w.b; g.ldc = c.ldk; g.sC = c.lds * c.ldk;
+    g.E = c.w.r; g.lde = c.ldk; g.sE = c.lds * c.ldk;
     g.partials = c.w.partials; g.sP = (int64_t)c.pstride * 5;
-    g.M = (int)c.ns; g.N = (int)c.nr; g.K = (int)c.nr;
+    g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
     HIP_TRY(timed(TLRMDD_K_GEMM_LINE, c.s, [&] { return launch_cgemm(GM_LINE, g, c.nprob, c.s); }));
     return TLRMDD_OK;
 }
 
-int resid_tiles(const Ctx &c) { return gemm_partials_per_problem(GM_RESID, (int)c.ns, (int)c.nr); }
-int line_tiles(const Ctx &c) { return gemm_partials_per_problem(GM_LINE, (int)c.ns, (int)c.nr) / 5; }
+int resid_tiles(const Ctx &c) { return gemm_partials_per_problem(GM_RESID, (int)c.lds, (int)c.ldk); }
+int line_tiles(const Ctx &c) { return gemm_partials_per_problem(GM_LINE, (int)c.lds, (int)c.ldk) / 5; }
 
 // The whole solve, for one problem or a batch of equal-shape problems.
 int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const void *const *U,
@@ -579,20 +581,20 @@ int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const 
     c.nprob = nprob;
     c.nr = nr;
     c.ns = ns;
-    c.ldk = round_up(nr, 2);
-    c.lds = round_up(ns, 2);
+    c.ldk = round_up(nr, GEMM_PAD);
+    c.lds = round_up(ns, GEMM_PAD);
     c.s = s;
     Tables T;
     std::vector<const HostLayout *> Hs;
     for (int p = 0; p < nprob; ++p) {
-        append_problem(T, plans[p]->H, p, (int64_t)p * 2 * nr * c.ldk, c.ldk);
+        append_problem(T, plans[p]->H, p, (int64_t)p * 2 * c.ldk * c.ldk, c.ldk);
         Hs.push_back(&plans[p]->H);
     }
-    build_segments(T, Hs, ns, c.ldk);
-    c.pstride = partial_stride(T, nr, ns);
+    build_segments(T, Hs, c.lds, c.ldk);
+    c.pstride = partial_stride(T, c.ldk, c.lds);
     assign_parts(T, c.pstride);
     const bool single = (nprob == 1);
-    c.w = carve((char *)workspace, 2, nprob, nr, ns, c.ldk, c.lds, T.theta_total, m1, c.pstride,
+    c.w = carve((char *)workspace, 2, nprob, c.ldk, c.lds, T.theta_total, m1, c.pstride,
                 single ? 0 : tables_bytes(T, nprob));
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     if (single) {
@@ -603,19 +605,18 @@ int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const 
     }
     double *fhist0 = single ? fhist[0] : nullptr;
 
-    const int64_t xstride = 2 * nr * c.ldk;      // per-problem X-space stride
-    const int64_t rstride = ns * c.ldk;
-    float2 *X1 = c.w.XW, *X2 = c.w.XW + nr * c.ldk;
+    const int64_t xstride = 2 * c.ldk * c.ldk;   // per-problem X-space stride
+    const int64_t rstride = c.lds * c.ldk;
+    float2 *X1 = c.w.XW, *X2 = c.w.XW + c.ldk * c.ldk;
     const int64_t stride2 = 2 * T.theta_total;   // floats between ring slots
     const int nt = c.D.n_tseg, nrs = c.D.n_rseg;
 
     // ---- setup: stage D, U, theta; zero the residual-space buffers (their padding stays 0) ----
-    HIP_TRY(hipMemsetAsync(c.w.r, 0, (size_t)nprob * rstride * sizeof(float2), s));
-    HIP_TRY(hipMemsetAsync(c.w.a, 0, (size_t)nprob * rstride * sizeof(float2), s));
-    HIP_TRY(hipMemsetAsync(c.w.b, 0, (size_t)nprob * rstride * sizeof(float2), s));
+    // padding of the X space must read as zero (the assembly writes only the true nr x nr block)
+    if (c.ldk != nr) HIP_TRY(hipMemsetAsync(c.w.XW, 0, (size_t)nprob * xstride * sizeof(float2), s));
     for (int p = 0; p < nprob; ++p) {
         HIP_TRY(launch_stage_d((const float2 *)D[p], ns, nr, c.w.Ds + p * rstride, c.ldk,
-                               c.w.DHs + (int64_t)p * nr * c.lds, c.lds, s));
+                               c.w.DHs + (int64_t)p * c.ldk * c.lds, c.lds, s));
         HIP_TRY(launch_copy2d((const float2 *)U[p], nr, c.w.Us + p * rstride, c.ldk, ns, nr, s));
         HIP_TRY(hipMemcpyAsync(c.w.th + 2 * T.probs[p].theta, theta[p],
                                plans[p]->H.theta_size * sizeof(float2), hipMemcpyDeviceToDevice, s));
@@ -740,11 +741,12 @@ int tlrmdd_forward(tlrmdd_plan plan, const void *D, const void *U, const void *t
     c.ldk = plan->ldk;
     c.lds = plan->lds;
     c.s = stream;
-    c.pstride = partial_stride(plan->T, c.nr, c.ns);
-    c.w = carve((char *)workspace, 0, 1, c.nr, c.ns, c.ldk, c.lds, plan->H.theta_size, 1, c.pstride, 0);
+    c.pstride = partial_stride(plan->T, c.ldk, c.lds);
+    c.w = carve((char *)workspace, 0, 1, c.ldk, c.lds, plan->H.theta_size, 1, c.pstride, 0);
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     c.D = plan->D;
-    HIP_TRY(launch_stage_d((const float2 *)D, c.ns, c.nr, c.w.Ds, c.ldk, nullptr, 0, stream));
+    if (c.ldk != c.nr) HIP_TRY(hipMemsetAsync(c.w.XW, 0, (size_t)c.ldk * c.ldk * sizeof(float2), stream));
+    HIP_TRY(launch_stage_d((const float2 *)D, c.ns, c.nr, c.w.Ds, c.ldk, nullptr, c.lds, stream));
     HIP_TRY(timed(TLRMDD_K_ASSEMBLE, stream, [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
                             c.w.XW, nullptr, stream); }));
     if ((st = gemm_resid(c, c.w.XW, 0, (const float2 *)U, c.nr, 0, c.w.r))) return st;
@@ -770,10 +772,11 @@ int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *thet
     c.ldk = plan->ldk;
     c.lds = plan->lds;
     c.s = stream;
-    c.pstride = partial_stride(plan->T, c.nr, c.ns);
-    c.w = carve((char *)workspace, 1, 1, c.nr, c.ns, c.ldk, c.lds, plan->H.theta_size, 1, c.pstride, 0);
+    c.pstride = partial_stride(plan->T, c.ldk, c.lds);
+    c.w = carve((char *)workspace, 1, 1, c.ldk, c.lds, plan->H.theta_size, 1, c.pstride, 0);
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     c.D = plan->D;
+    if (c.ldk != c.nr) HIP_TRY(hipMemsetAsync(c.w.XW, 0, (size_t)c.ldk * c.ldk * sizeof(float2), stream));
     HIP_TRY(launch_stage_d((const float2 *)D, c.ns, c.nr, c.w.Ds, c.ldk, c.w.DHs, c.lds, stream));
     HIP_TRY(timed(TLRMDD_K_ASSEMBLE, stream, [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
                             c.w.XW, nullptr, stream); }));
@@ -809,18 +812,18 @@ int tlrmdd_workspace_bytes_batched(int count, const tlrmdd_plan *plans, const tl
     for (int p = 0; p < count; ++p)
         if (!plans[p]) return fail(TLRMDD_INVALID_ARGUMENT, "plan is NULL");
     const int64_t nr = plans[0]->H.nr, ns = plans[0]->H.ns;
-    const int64_t ldk = round_up(nr, 2), lds = round_up(ns, 2);
+    const int64_t ldk = round_up(nr, GEMM_PAD), lds = round_up(ns, GEMM_PAD);
     Tables T;
     std::vector<const HostLayout *> Hs;
     for (int p = 0; p < count; ++p) {
         if (plans[p]->H.nr != nr || plans[p]->H.ns != ns)
             return fail(TLRMDD_INVALID_ARGUMENT, "batched problems must share nr and ns");
-        append_problem(T, plans[p]->H, p, (int64_t)p * 2 * nr * ldk, ldk);
+        append_problem(T, plans[p]->H, p, (int64_t)p * 2 * ldk * ldk, ldk);
         Hs.push_back(&plans[p]->H);
     }
-    build_segments(T, Hs, ns, ldk);
+    build_segments(T, Hs, lds, ldk);
     const int m1 = opts->optimizer == TLRMDD_LBFGS ? opts->lbfgs_m + 1 : 1;
-    *bytes = carve(nullptr, 2, count, nr, ns, ldk, lds, T.theta_total, m1, partial_stride(T, nr, ns),
+    *bytes = carve(nullptr, 2, count, ldk, lds, T.theta_total, m1, partial_stride(T, ldk, lds),
                    count == 1 ? 0 : tables_bytes(T, count)).bytes;
     return TLRMDD_OK;
 }

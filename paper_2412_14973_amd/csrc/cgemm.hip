@@ -26,6 +26,7 @@
 namespace tlr {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -57,7 +58,6 @@ __global__ __launch_bounds__(256, 2) void cgemm_f32_kernel(GemmArgs g) {
     const int z = blockIdx.y;
     const float2 *A = g.A + z * g.sA;
     const float2 *B = g.B + z * g.sB;
-    const float2 *B2 = (MODE == GM_LINE) ? g.B2 + z * g.sB : nullptr;
 
     // workgroup -> tile: contiguous tile ranges per XCD, grouped by 8 tile rows
     const int nb = gridDim.x;
@@ -78,47 +78,50 @@ __global__ __launch_bounds__(256, 2) void cgemm_f32_kernel(GemmArgs g) {
     const int lane = t & 63;
     const int wave = t >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int M = g.M, N = g.N, K = g.K;
+    const int K = g.K;
 
     // ---- global -> register loaders ----
     float4 ra[4], rb[4];
     const int a_row = t >> 3, a_fq = t & 7;     // A: 8 lanes per row, 4 floats each
     const int b_row = t >> 6, b_cq = t & 63;    // B: 64 lanes per k row, 2 complex each
 
-    auto load_a = [&](int k0) {
+    // The host pads every operand to whole tiles (M, N multiples of 128, K of 16)
+    // with zeros, so the loads carry no bounds checks. They are buffer loads: a
+    // uniform resource (base, byte size) plus a per-lane 32-bit offset that stays
+    // fixed across stages (the stage advance is the uniform soffset), so all eight
+    // 16-byte loads of a stage are in flight together while the previous stage
+    // runs on the matrix cores, and any access outside an operand reads zero.
+    const __amdgpu_buffer_rsrc_t rsA =
+        __builtin_amdgcn_make_buffer_rsrc((void *)A, (short)0, (int)g.bytesA, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsB =
+        __builtin_amdgcn_make_buffer_rsrc((void *)B, (short)0, (int)g.bytesB, 0x00020000);
+    uint32_t offA[4], offB[4];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int row = m0 + a_row + 32 * p;
-            const int kc = k0 + 2 * a_fq;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (row < M && kc < K) {
-                v = *reinterpret_cast<const float4 *>(A + (int64_t)row * g.lda + kc);
-                if (kc + 1 >= K) { v.z = 0.f; v.w = 0.f; }
-            }
-            ra[p] = v;
+    for (int p = 0; p < 4; ++p)
+        offA[p] = (uint32_t)(((int64_t)(m0 + a_row + 32 * p) * g.lda + 2 * a_fq) * 8);
+    {
+        const int c = 2 * b_cq;  // complex column inside the LDS tile
+        int64_t base = n0 + c;
+        if (MODE == GM_LINE) {
+            const int grp2 = c >> 5;
+            base = n0 + (grp2 >> 1) * 32 + (c & 31) + ((grp2 & 1) ? g.b2_off : 0);
         }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) offB[p] = (uint32_t)((base + (int64_t)(b_row + 4 * p) * g.ldb) * 8);
+    }
+    auto ld16 = [](__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+        return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
+    };
+    auto load_a = [&](int k0) {
+        const uint32_t so = (uint32_t)k0 * 8u;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) ra[p] = ld16(rsA, offA[p], so);
     };
     auto load_b = [&](int k0) {
+        const uint32_t so = (uint32_t)((int64_t)k0 * g.ldb * 8);
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int kr = k0 + b_row + 4 * p;
-            const int c = 2 * b_cq;  // complex column inside the LDS tile
-            const float2 *src = B;
-            int col;
-            if (MODE == GM_LINE) {
-                const int grp2 = c >> 5;
-                src = (grp2 & 1) ? B2 : B;
-                col = n0 + (grp2 >> 1) * 32 + (c & 31);
-            } else {
-                col = n0 + c;
-            }
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (kr < K && col < N) {
-                v = *reinterpret_cast<const float4 *>(src + (int64_t)kr * g.ldb + col);
-                if (col + 1 >= N) { v.z = 0.f; v.w = 0.f; }
-            }
-            rb[p] = v;
-        }
+        for (int p = 0; p < 4; ++p) rb[p] = ld16(rsB, offB[p], so);
     };
     auto store_lds = [&](int buf) {
         float *as = As[buf];
@@ -162,20 +165,32 @@ __global__ __launch_bounds__(256, 2) void cgemm_f32_kernel(GemmArgs g) {
             load_a((kt + 1) * BK);
             load_b((kt + 1) * BK);
         }
-        const float *as = As[buf];
-        const float *bs = Bs[buf];
-#pragma unroll 4
+        const float *as = As[buf] + half * A_PITCH + wm * 64 + j32;
+        const float *bs = Bs[buf] + 2 * (wn * 64) + bswz;
+        // operand fragments double-buffered in registers: the reads of step kc+1
+        // are issued before the eight MFMAs of step kc
+        float a_cur[2], b_cur[4], a_nxt[2], b_nxt[4];
+        auto frag = [&](int kc, float *af, float *bf) {
+            af[0] = as[2 * kc * A_PITCH];
+            af[1] = as[2 * kc * A_PITCH + 32];
+#pragma unroll
+            for (int bn = 0; bn < 4; ++bn)
+                bf[bn] = __uint_as_float(__float_as_uint(bs[kc * B_PITCH + 32 * bn]) ^ bsign);
+        };
+        frag(0, a_cur, b_cur);
+#pragma unroll
         for (int kc = 0; kc < BK; ++kc) {
-            const float *arow = as + (2 * kc + half) * A_PITCH + wm * 64 + j32;
-            const float a0 = arow[0];
-            const float a1 = arow[32];
-            const float *brow = bs + kc * B_PITCH + 2 * (wn * 64) + bswz;
+            if (kc + 1 < BK) frag(kc + 1, a_nxt, b_nxt);
 #pragma unroll
             for (int bn = 0; bn < 4; ++bn) {
-                const float braw = brow[32 * bn];
-                const float bv = __uint_as_float(__float_as_uint(braw) ^ bsign);
-                acc[0][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bv, acc[0][bn], 0, 0, 0);
-                acc[1][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bv, acc[1][bn], 0, 0, 0);
+                acc[0][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[0], b_cur[bn], acc[0][bn], 0, 0, 0);
+                acc[1][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[1], b_cur[bn], acc[1][bn], 0, 0, 0);
+            }
+            if (kc + 1 < BK) {
+                a_cur[0] = a_nxt[0];
+                a_cur[1] = a_nxt[1];
+#pragma unroll
+                for (int bn = 0; bn < 4; ++bn) b_cur[bn] = b_nxt[bn];
             }
         }
         if (kt + 1 < nk) store_lds(buf ^ 1);
@@ -184,25 +199,25 @@ __global__ __launch_bounds__(256, 2) void cgemm_f32_kernel(GemmArgs g) {
 
     // ---- epilogues ----
     float *C = reinterpret_cast<float *>(g.C + z * g.sC);
-    const int64_t ldc2 = 2 * g.ldc;
+    const int64_t ldc2 = 2 * (int64_t)g.ldc;
     if (MODE == GM_STORE) {
 #pragma unroll
         for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
             for (int bn = 0; bn < 4; ++bn) {
-                const int col = n0 + wn * 64 + bn * 16 + (j32 >> 1);
                 const int64_t fcol = 2 * (int64_t)(n0 + wn * 64 + bn * 16) + j32;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int row = m0 + wm * 64 + bm * 32 + acc_row(r, lane);
-                    if (row < M && col < N) C[row * ldc2 + fcol] = acc[bm][bn][r];
+                    C[row * ldc2 + fcol] = acc[bm][bn][r];
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
         return;
     }
 
     const float *E = reinterpret_cast<const float *>(g.E + z * g.sE);
-    const int64_t lde2 = 2 * g.lde;
+    const int64_t lde2 = 2 * (int64_t)g.lde;
     double sums[NSUM_MAX] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (MODE == GM_RESID) {
 #pragma unroll
@@ -211,15 +226,19 @@ __global__ __launch_bounds__(256, 2) void cgemm_f32_kernel(GemmArgs g) {
             for (int bn = 0; bn < 4; ++bn) {
                 const int col = n0 + wn * 64 + bn * 16 + (j32 >> 1);
                 const int64_t fcol = 2 * (int64_t)(n0 + wn * 64 + bn * 16) + j32;
+                float blk = 0.f;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int row = m0 + wm * 64 + bm * 32 + acc_row(r, lane);
-                    if (row < M && col < N) {
-                        const float v = acc[bm][bn][r] - E[row * lde2 + fcol];
-                        C[row * ldc2 + fcol] = v;
-                        sums[0] += (double)v * (double)v;
-                    }
+                    const bool in = row < g.Me && col < g.Ne;   // U has the true (unpadded) shape
+                    const float v = acc[bm][bn][r] - (in ? E[row * lde2 + fcol] : 0.f);
+                    C[row * ldc2 + fcol] = v;
+                    blk = fmaf(v, v, blk);
                 }
+                sums[0] += (double)blk;
+                // one accumulator block at a time: keeps the epilogue's loads from being
+                // hoisted together (register pressure)
+                __builtin_amdgcn_sched_barrier(0);
             }
     } else {  // GM_LINE
         float *C2 = reinterpret_cast<float *>(g.C2 + z * g.sC);
@@ -227,25 +246,26 @@ __global__ __launch_bounds__(256, 2) void cgemm_f32_kernel(GemmArgs g) {
         for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
             for (int bn = 0; bn < 2; ++bn) {
-                const int col = n0 + wn * 32 + bn * 16 + (j32 >> 1);
                 const int64_t fcol = 2 * (int64_t)(n0 + wn * 32 + bn * 16) + j32;
+                // 16 products per sum in FP32 registers, then folded into the FP64 sums
+                float blk[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int row = m0 + wm * 64 + bm * 32 + acc_row(r, lane);
-                    if (row < M && col < N) {
-                        const float av = acc[bm][bn][r];
-                        const float bv = acc[bm][bn + 2][r];
-                        const float rv = E[row * lde2 + fcol];
-                        C[row * ldc2 + fcol] = av;
-                        C2[row * ldc2 + fcol] = bv;
-                        const double ad = av, bd = bv, rd = rv;
-                        sums[0] += rd * ad;
-                        sums[1] += ad * ad;
-                        sums[2] += rd * bd;
-                        sums[3] += ad * bd;
-                        sums[4] += bd * bd;
-                    }
+                    const float av = acc[bm][bn][r];
+                    const float bv = acc[bm][bn + 2][r];
+                    const float rv = E[row * lde2 + fcol];
+                    C[row * ldc2 + fcol] = av;
+                    C2[row * ldc2 + fcol] = bv;
+                    blk[0] = fmaf(rv, av, blk[0]);
+                    blk[1] = fmaf(av, av, blk[1]);
+                    blk[2] = fmaf(rv, bv, blk[2]);
+                    blk[3] = fmaf(av, bv, blk[3]);
+                    blk[4] = fmaf(bv, bv, blk[4]);
                 }
+#pragma unroll
+                for (int q = 0; q < 5; ++q) sums[q] += (double)blk[q];
+                __builtin_amdgcn_sched_barrier(0);
             }
     }
     constexpr int NS = (MODE == GM_RESID) ? 1 : 5;
@@ -275,6 +295,19 @@ hipError_t launch_cgemm(int mode, const GemmArgs &a0, int batch, hipStream_t s) 
     a.tiles_m = (a.M + BM - 1) / BM;
     a.tiles_n = (mode == GM_LINE) ? (a.N + BN / 2 - 1) / (BN / 2) : (a.N + BN - 1) / BN;
     if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
+    if (a.M % BM || a.N % BN || a.K % BK || a.K <= 0) return hipErrorInvalidValue;   // padded operands only
+    // byte extents of the buffer resources (32-bit): A is M x lda, B is K x ldb (GM_LINE: B2 follows B)
+    const int64_t bytesA = (int64_t)a.M * a.lda * 8;
+    int64_t bytesB = (int64_t)a.K * a.ldb * 8;
+    a.b2_off = 0;
+    if (mode == GM_LINE) {
+        a.b2_off = a.B2 - a.B;
+        if (a.b2_off < 0) return hipErrorInvalidValue;
+        bytesB += a.b2_off * 8;
+    }
+    if (bytesA >= (int64_t)1 << 32 || bytesB >= (int64_t)1 << 32) return hipErrorInvalidValue;
+    a.bytesA = (uint32_t)bytesA;
+    a.bytesB = (uint32_t)bytesB;
     dim3 grid(a.tiles_m * a.tiles_n, batch);
     switch (mode) {
         case GM_STORE: hipLaunchKernelGGL(cgemm_f32_kernel<GM_STORE>, grid, dim3(256), 0, s, a); break;

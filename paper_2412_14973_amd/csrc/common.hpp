@@ -65,7 +65,10 @@ struct GemmArgs {
     float2 *C2;                      // GM_LINE: second output (same ldc)
     const float2 *E;  int64_t lde;   // GM_RESID: U (C = AB - U); GM_LINE: residual r
     double *partials;                // per-workgroup FP64 sums (GM_RESID: 1, GM_LINE: 5)
-    int32_t M, N, K;
+    int32_t M, N, K;                 // padded sizes: M, N multiples of 128, K of 16 (zero padding)
+    int32_t Me, Ne;                  // GM_RESID: true shape of E (reads outside are zero)
+    int64_t b2_off;                  // GM_LINE: B2 - B in complex elements (set by the launcher)
+    uint32_t bytesA, bytesB;         // buffer extents (set by the launcher)
     int32_t tiles_m, tiles_n;
     // uniform batch (grid.y): element strides between problems
     int64_t sA, sB, sC, sE;
@@ -74,6 +77,7 @@ struct GemmArgs {
 constexpr int GEMM_BM = 128;
 constexpr int GEMM_BN = 128;   // complex columns per workgroup (64 of a + 64 of b in GM_LINE)
 constexpr int GEMM_BK = 16;    // complex k per stage
+constexpr int GEMM_PAD = 128;  // internal matrices are padded to multiples of this
 
 // ---- vector / scalar kernels ----
 constexpr int RED_THREADS = 256;

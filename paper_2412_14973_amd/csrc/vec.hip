@@ -15,23 +15,22 @@ namespace {
 __global__ __launch_bounds__(256) void stage_d_kernel(const float2 *__restrict__ D, int64_t ns, int64_t nr,
                                                       float2 *__restrict__ Ds, int64_t ldk,
                                                       float2 *__restrict__ DHs, int64_t lds) {
+    // grid covers the padded lds x ldk block; padding is written as zeros
     __shared__ float2 tile[32][33];
     const int64_t s0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
     for (int r = ty; r < 32; r += 8) {
         const int64_t s = s0 + r, c = c0 + tx;
         float2 v = make_float2(0.f, 0.f);
-        if (s < ns && c < nr) {
-            v = D[s * nr + c];
-            if (Ds) Ds[s * ldk + c] = v;
-        }
+        if (s < ns && c < nr) v = D[s * nr + c];
+        if (Ds && s < lds && c < ldk) Ds[s * ldk + c] = v;
         tile[r][tx] = v;
     }
     if (!DHs) return;
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int64_t c = c0 + r, s = s0 + tx;
-        if (s < ns && c < nr) {
+        if (s < lds && c < ldk) {
             const float2 v = tile[tx][r];
             DHs[c * lds + s] = make_float2(v.x, -v.y);
         }
@@ -407,7 +406,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs fa) {
 // ---------------------------------------------------------------------------
 hipError_t launch_stage_d(const float2 *D, int64_t ns, int64_t nr, float2 *Ds, int64_t ldk,
                           float2 *DHs, int64_t lds, hipStream_t s) {
-    dim3 grid((unsigned)((nr + 31) / 32), (unsigned)((ns + 31) / 32));
+    dim3 grid((unsigned)((ldk + 31) / 32), (unsigned)((lds + 31) / 32));
     hipLaunchKernelGGL(stage_d_kernel, grid, dim3(256), 0, s, D, ns, nr, Ds, ldk, DHs, lds);
     return hipGetLastError();
 }

@@ -50,6 +50,23 @@ def build_inputs(wl, torch, tl, nfreq):
     return geom, Ds, Us, ths, plans
 
 
+def measured_traffic(nfreq, workload):
+    """HBM bytes per launch of the line-search GEMM from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (copy-calibrated), or None when the kernel
+    source changed since the counters were taken or the workload differs."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "cgemm_line_traffic.json")
+    src = os.path.join(ROOT, "paper_2412_14973_amd", "csrc", "cgemm.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != sha or workload != "batched" or nfreq != 64:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(wl, budget_s):
     """Time the FP64 oracle (as it stands) on one frequency of the workload."""
     import numpy as np
@@ -93,6 +110,8 @@ def main():
     ap.add_argument("--nfreq", type=int, default=None)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: frequencies are independent solves; "
@@ -105,6 +124,14 @@ def main():
     import synth
     tl._lib.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
     wl = synth.batched() if args.workload == "batched" else synth.large()
     nfreq = args.nfreq or (len(wl.freqs) if args.workload == "batched" else 4)
     iters = args.iters or wl.iters
@@ -180,7 +207,8 @@ def main():
                    "precision": "fp32-mfma"},
         "roofline": {"bound": "mfma", "kernel": "cgemm_f32_kernel<GM_LINE> ([a|b] = D [X1|X2])",
                      "achieved": achieved / 1e12, "peak": PEAK["f32"] / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["f32"], "traffic": None},
+                     "frac": achieved / PEAK["f32"], "traffic": measured_traffic(nfreq, args.workload),
+                     "algorithmic_bytes": 6 * 8.0 * ns * nr * nfreq},
         "mfma_frac_all_gemms": gemm_flops / gemm_s / PEAK["f32"],
         "kernels": kernels,
         "objective": {"f0_mean": sum(f_first) / nfreq, "fT_mean": sum(f_final) / nfreq},

@@ -277,6 +277,83 @@ def gradient(T: Tiling, D, U, theta) -> Tuple[float, np.ndarray]:
     return f, tile_gradient(T, theta, W)
 
 
+def factor_of_entry(T: Tiling, q: int):
+    """Locate packed entry q: (kind, tile index, row, col) with kind in
+    {'Q', 'Z', 'L', 'R'} and (row, col) inside that factor."""
+    for i in range(T.n):
+        cols = T.d[i] if T.kdiag[i] < 0 else T.kdiag[i]
+        o = T.off_diag[i]
+        if o <= q < o + T.d[i] * cols:
+            return ("Z" if T.kdiag[i] < 0 else "Q", i, (q - o) // cols, (q - o) % cols)
+    for t, (i, j, k) in enumerate(T.pairs):
+        o = T.off_L[t]
+        if o <= q < o + T.d[i] * k:
+            return ("L", t, (q - o) // k, (q - o) % k)
+        o = T.off_R[t]
+        if o <= q < o + k * T.d[j]:
+            return ("R", t, (q - o) // T.d[j], (q - o) % T.d[j])
+    raise IndexError(q)
+
+
+def gradient_entries(T: Tiling, D: np.ndarray, r: np.ndarray, theta: np.ndarray, idx) -> np.ndarray:
+    """Selected entries of the tile gradient, each from its definition
+    (gradient equations DXLR) with only the entries of W = D^H r it needs:
+    W'[p, q] = W[p, q] + W[q, p] and W[p, q] = conj(D[:, p]) . r[:, q]."""
+    def Wblock(rows, cols):
+        return D[:, rows].conj().T @ r[:, cols]
+
+    out = np.zeros(len(idx), dtype=np.complex128)
+    for n, q in enumerate(idx):
+        kind, tix, a, b = factor_of_entry(T, int(q))
+        if kind in ("Q", "Z"):
+            rows = np.arange(T.start[tix], T.start[tix] + T.d[tix])
+            p = T.start[tix] + a
+            wrow = Wblock([p], rows)[0] + Wblock(rows, [p])[:, 0]     # W'[p, tile cols]
+            if kind == "Z":
+                c = T.start[tix] + b
+                out[n] = 0.5 * (Wblock([p], [c])[0, 0] + Wblock([c], [p])[0, 0])
+            else:
+                Q = diag_block(T, theta, tix)
+                out[n] = np.sum(wrow * np.conj(Q[:, b]))              # (W' conj(Q))[a, b]
+        else:
+            i, j, k = T.pairs[tix]
+            ri = np.arange(T.start[i], T.start[i] + T.d[i])
+            cj = np.arange(T.start[j], T.start[j] + T.d[j])
+            if kind == "L":
+                p = T.start[i] + a
+                wrow = Wblock([p], cj)[0] + Wblock(cj, [p])[:, 0]      # W'_ij[a, :]
+                out[n] = np.sum(wrow * np.conj(R_block(T, theta, tix)[b, :]))   # (W' R^H)[a, b]
+            else:
+                c = T.start[j] + b
+                wcol = Wblock(ri, [c])[:, 0] + Wblock([c], ri)[0]      # W'_ij[:, b]
+                out[n] = np.sum(np.conj(L_block(T, theta, tix)[:, a]) * wcol)   # (L^H W')[a, b]
+    return out
+
+
+def fd_entries_large(T: Tiling, D, U, theta, idx, h: float = 1e-6) -> np.ndarray:
+    """Central differences of f along Re and Im of theta[idx] without forming
+    D X for every shifted theta: r(theta') = r + D (C(theta') - C(theta)), where
+    the difference is nonzero only in the rows/columns of the perturbed tiles
+    (D times the rows of the difference that are nonzero)."""
+    X = assemble(T, theta)
+    r = D @ X - U
+
+    def f_shift(e):
+        dX = assemble(T, theta + e) - X
+        nz = np.flatnonzero(np.any(dX != 0, axis=1))
+        rr = r + D[:, nz] @ dX[nz, :]
+        return 0.5 * float(np.vdot(rr, rr).real)
+
+    out = np.zeros(len(idx), dtype=np.complex128)
+    for n, q in enumerate(idx):
+        e = np.zeros_like(theta)
+        e[q] = h
+        fr = (f_shift(e) - f_shift(-e)) / (2 * h)
+        fi = (f_shift(1j * e) - f_shift(-1j * e)) / (2 * h)
+        out[n] = fr + 1j * fi
+    return out
+
+
 def fd_gradient_entries(T: Tiling, D, U, theta, idx, h: float = 1e-6) -> np.ndarray:
     """Central differences of f along Re and Im of theta[idx] (complex128)."""
     out = np.zeros(len(idx), dtype=np.complex128)

@@ -1,0 +1,111 @@
+"""Full-size GPU parity: the shapes the benchmark and the adjoint workload use.
+
+* nr = 4096 (64 x 64 receivers), ns = 2048, tile 256, rank 32: the objective
+  and its hand-written backward behind torch.autograd.Function, checked on 20
+  random factor entries against the oracle's entry-wise gradient and against
+  central finite differences of the complex128 objective (step 1e-6); plus a
+  2-iteration solve against the oracle.
+* nr = ns = 1024, 64 frequencies in one batched launch per phase (the bench
+  configuration), 3 iterations: four sampled frequencies against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_cases import U32, from_workload, gradient_bound, to_device
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def tl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2412_14973_amd as m
+    m._lib.load()
+    return m
+
+
+@pytest.mark.parametrize("f_idx", [5])
+def test_large_autograd_backward_vs_fd(tl, f_idx):
+    wl = synth.large()
+    case = from_workload(wl, f_idx)
+    print(f"case {case.name}: nr {case.T.nr} ns {case.D.shape[0]} theta {case.T.size}", flush=True)
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    thg = th.clone().requires_grad_(True)
+    loss = tl.objective(thg, D, U, plan)
+    loss.backward()
+    torch.cuda.synchronize()
+    g = thg.grad.cpu().numpy().astype(np.complex128)
+
+    X = O.assemble(case.T, case.theta)
+    r = case.D @ X - case.U
+    fo = 0.5 * np.vdot(r, r).real
+    assert abs(loss.item() - fo) <= 1e-5 * fo
+
+    rng = np.random.default_rng(20 + f_idx)
+    idx = np.sort(rng.choice(case.T.size, 20, replace=False))
+    go = O.gradient_entries(case.T, case.D, r, case.theta, idx)
+    bound = 8 * gradient_bound(case, X, r)[idx] + 1e-30
+    err = np.abs(g[idx] - go)
+    print("max |g_gpu - g_oracle| / bound", np.max(err / bound), flush=True)
+    assert np.all(err <= bound)
+
+    fd = O.fd_entries_large(case.T, case.D, case.U, case.theta, idx, h=1e-6)
+    # the finite differences pin the oracle's gradient at this size ...
+    fd_err = np.abs(fd - go)
+    assert np.all(fd_err <= 1e-6 * np.abs(go).max() + 1e-9 * fo)
+    # ... and the FP32 backward agrees with them within its derived bound
+    assert np.all(np.abs(g[idx] - fd) <= bound + fd_err + 1e-9 * fo)
+
+
+def test_large_two_iterations(tl):
+    wl = synth.large()
+    case = from_workload(wl, 20)
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    thg, fh = tl.solve(plan, D, U, th, iters=2)
+    torch.cuda.synchronize()
+    ref = O.solve(case.T, case.D, case.U, case.theta, iters=2)
+    fh = fh.cpu().numpy()
+    rel_hist = np.abs(fh - ref.f_hist) / ref.f_hist
+    th_g = thg.cpu().numpy().astype(np.complex128)
+    rel_t = np.linalg.norm(th_g - ref.theta) / np.linalg.norm(ref.theta)
+    print(f"large 2-iter: rel f_hist {rel_hist.max():.2e} rel_theta {rel_t:.2e}", flush=True)
+    assert rel_hist.max() <= 1e-5 and rel_t <= 1e-5
+
+
+def test_batched_bench_configuration_sampled(tl):
+    wl = synth.batched()
+    nf = len(wl.freqs)
+    iters = 3
+    dev = torch.device("cuda")
+    geom = wl.geometry()
+    perm = torch.from_numpy(tl.hilbert_order(geom.rec_ix, geom.rec_iy)).to(dev)
+    sample = {0: None, 21: None, 42: None, 63: None}
+    Ds, Us, ths, plans = [], [], [], []
+    for i in range(nf):
+        case = from_workload(wl, i) if i in sample else None
+        if case is not None:
+            sample[i] = case
+            Dn, Un, th = case.D_nat, case.U_nat, case.theta
+        else:
+            prob = wl.problem(i, geom)
+            Dn, Un, th = prob.D, prob.U, wl.theta0(i)
+        Ds.append(tl.permute_columns(torch.from_numpy(Dn.astype(np.complex64)).to(dev), perm))
+        Us.append(tl.permute_columns(torch.from_numpy(Un.astype(np.complex64)).to(dev), perm))
+        ths.append(torch.from_numpy(np.asarray(th).astype(np.complex64)).to(dev))
+        plans.append(tl.Plan.from_layout(wl.layout(i), geom.ns))
+    thT, fh = tl.solve_batched(plans, Ds, Us, ths, iters)
+    torch.cuda.synchronize()
+    for i, case in sample.items():
+        ref = O.solve(case.T, case.D, case.U, case.theta, iters=iters)
+        th_g = thT[i].cpu().numpy().astype(np.complex128)
+        f_g = O.objective(case.T, case.D, case.U, th_g)[0]
+        rel_f = abs(f_g - ref.f_hist[-1]) / ref.f_hist[-1]
+        rel_t = np.linalg.norm(th_g - ref.theta) / np.linalg.norm(ref.theta)
+        rel_h = np.max(np.abs(fh[i].cpu().numpy() - ref.f_hist) / ref.f_hist)
+        print(f"freq {i} (k={synth.batched_rank(float(wl.freqs[i]))}): rel_f {rel_f:.2e} "
+              f"rel_theta {rel_t:.2e} rel f_hist {rel_h:.2e}", flush=True)
+        assert rel_f <= 1e-5 and rel_t <= 1e-5 and rel_h <= 1e-5

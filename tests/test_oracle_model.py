@@ -217,3 +217,22 @@ def test_hilbert_equivalence_and_source_permutation():
     f_s, _ = O.objective(T, D[sp], U[sp], th)
     f_0, _ = O.objective(T, D, U, th)
     assert abs(f_s - f_0) <= 1e-12 * f_0
+
+
+def test_gradient_entries_match_full_gradient():
+    """The entry-wise gradient (used for sampled checks at large sizes) equals
+    the full tile gradient on every entry of a mixed layout."""
+    T, D, U, th = _small_problem(seed=21)
+    f, r = O.objective(T, D, U, th)
+    g = O.tile_gradient(T, th, D.conj().T @ r)
+    idx = np.arange(T.size)
+    ge = O.gradient_entries(T, D, r, th, idx)
+    assert np.allclose(ge, g, rtol=0, atol=1e-12 * np.abs(g).max())
+
+
+def test_fd_entries_large_matches_plain_fd():
+    T, D, U, th = _small_problem(seed=22)
+    idx = np.arange(0, T.size, 3)
+    a = O.fd_entries_large(T, D, U, th, idx)
+    b = O.fd_gradient_entries(T, D, U, th, idx)
+    assert np.allclose(a, b, rtol=1e-7, atol=1e-9)

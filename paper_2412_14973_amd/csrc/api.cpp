@@ -320,6 +320,7 @@ int partial_stride(const Tables &T, int64_t nrp, int64_t nsp) {
 // ---------------------------------------------------------------------------
 struct Ws {
     float2 *Ds = nullptr, *DHs = nullptr, *Us = nullptr, *XW = nullptr, *r = nullptr, *a = nullptr, *b = nullptr;
+    uint32_t *rT = nullptr;   // BF16 split planes of r^T (hi, lo), ldk x lds each
     float *th = nullptr, *g0 = nullptr, *g1 = nullptr, *q = nullptr, *p = nullptr, *S = nullptr, *Y = nullptr;
     double *partials = nullptr;
     SolveScalars *sc = nullptr;
@@ -345,6 +346,7 @@ Ws carve(char *base, int op, int nprob, int64_t ldk, int64_t lds, int64_t theta_
     if (op >= 1) w.DHs = (float2 *)take((size_t)nprob * ldk * lds * c8);
     w.XW = (float2 *)take(op == 2 ? 2 * xsz : xsz);
     w.r = (float2 *)take(rsz);
+    if (op >= 1) w.rT = (uint32_t *)take(rsz);
     if (op == 2) {
         w.Us = (float2 *)take(rsz);
         w.a = (float2 *)take(rsz);
@@ -372,17 +374,15 @@ int check_opts(const tlrmdd_opts *o) {
         return fail(TLRMDD_INVALID_ARGUMENT, "unknown optimizer");
     if (o->optimizer == TLRMDD_LBFGS && (o->lbfgs_m < 1 || o->lbfgs_m > MAX_LBFGS_M))
         return fail(TLRMDD_INVALID_ARGUMENT, "lbfgs_m must be in [1, 32]");
-    if (o->precision != TLRMDD_FP32)
-        return fail(o->precision == TLRMDD_BF16X3 ? TLRMDD_UNSUPPORTED : TLRMDD_INVALID_ARGUMENT,
-                    "precision not supported");
+    if (o->precision != TLRMDD_FP32 && o->precision != TLRMDD_BF16X3)
+        return fail(TLRMDD_INVALID_ARGUMENT, "unknown precision");
     if (!(o->lambda >= 0.0)) return fail(TLRMDD_INVALID_ARGUMENT, "lambda must be >= 0");
     if (o->resid_refresh < 0) return fail(TLRMDD_INVALID_ARGUMENT, "resid_refresh must be >= 0");
     return TLRMDD_OK;
 }
 
 int check_precision(int precision) {
-    if (precision == TLRMDD_FP32) return TLRMDD_OK;
-    if (precision == TLRMDD_BF16X3) return fail(TLRMDD_UNSUPPORTED, "BF16x3 precision not available");
+    if (precision == TLRMDD_FP32 || precision == TLRMDD_BF16X3) return TLRMDD_OK;
     return fail(TLRMDD_INVALID_ARGUMENT, "unknown precision");
 }
 
@@ -508,6 +508,15 @@ struct Ctx {
     Ws w;
     DevTables D;
     hipStream_t s;
+    bool bf16 = false;          // BF16 hi+lo split products
+    int64_t xspace = 0;         // complex64 elements of X space per problem (1 or 2 ldk x ldk)
+
+    // split planes (uint32 words, one per complex): per problem [hi | lo]
+    uint32_t *dsw() const { return reinterpret_cast<uint32_t *>(w.Ds); }
+    uint32_t *dhw() const { return reinterpret_cast<uint32_t *>(w.DHs); }
+    uint32_t *xw() const { return reinterpret_cast<uint32_t *>(w.XW); }
+    // X space in split form: X1 hi at 0, X2 hi at ldk^2, lo planes at + xspace words
+    int64_t lo_words() const { return xspace; }
 };
 
 int fin(const Ctx &c, FinArgs f, const int32_t *counts, int ucount, int nsum) {
@@ -521,6 +530,25 @@ int fin(const Ctx &c, FinArgs f, const int32_t *counts, int ucount, int nsum) {
 }
 
 int gemm_resid(const Ctx &c, const float2 *X, int64_t sX, const float2 *U, int64_t ldu, int64_t sU, float2 *r) {
+    if (c.bf16) {
+        // X given as the split planes that start at the same place (word 2 * offset of X)
+        const uint32_t *xh = reinterpret_cast<const uint32_t *>(X);
+        GemmArgsB g;
+        std::memset(&g, 0, sizeof(g));
+        g.Ahi = reinterpret_cast<const uint16_t *>(c.dsw());
+        g.Alo = reinterpret_cast<const uint16_t *>(c.dsw() + c.lds * c.ldk);
+        g.lda = c.ldk; g.sA = 2 * c.lds * c.ldk;
+        g.Bhi = reinterpret_cast<const uint16_t *>(xh);
+        g.Blo = reinterpret_cast<const uint16_t *>(xh + c.lo_words());
+        g.ldb = c.ldk; g.sB = 2 * sX;
+        g.C = r; g.ldc = c.ldk; g.sC = c.lds * c.ldk;
+        g.E = U; g.lde = ldu; g.sE = sU;
+        g.partials = c.w.partials; g.sP = (int64_t)c.pstride;
+        g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
+        g.Me = (int)c.ns; g.Ne = (int)c.nr;
+        HIP_TRY(timed(TLRMDD_K_GEMM_RESID, c.s, [&] { return launch_cgemm_bf16(GM_RESID, g, c.nprob, c.s); }));
+        return TLRMDD_OK;
+    }
     GemmArgs g = gemm_args();
     g.A = c.w.Ds; g.lda = c.ldk; g.sA = c.lds * c.ldk;
     g.B = X; g.ldb = c.ldk; g.sB = sX;
@@ -534,6 +562,21 @@ int gemm_resid(const Ctx &c, const float2 *X, int64_t sX, const float2 *U, int64
 }
 
 int gemm_adjoint(const Ctx &c, const float2 *r, float2 *W, int64_t sW) {
+    if (c.bf16) {
+        // r^T split planes (written by split_r_transpose) are the transposed B operand
+        GemmArgsB g;
+        std::memset(&g, 0, sizeof(g));
+        g.Ahi = reinterpret_cast<const uint16_t *>(c.dhw());
+        g.Alo = reinterpret_cast<const uint16_t *>(c.dhw() + c.ldk * c.lds);
+        g.lda = c.lds; g.sA = 2 * c.ldk * c.lds;
+        g.Bhi = reinterpret_cast<const uint16_t *>(c.w.rT);
+        g.Blo = reinterpret_cast<const uint16_t *>(c.w.rT + c.ldk * c.lds);
+        g.ldb = c.lds; g.sB = 2 * c.ldk * c.lds;
+        g.C = W; g.ldc = c.ldk; g.sC = sW;
+        g.M = (int)c.ldk; g.N = (int)c.ldk; g.K = (int)c.lds;
+        HIP_TRY(timed(TLRMDD_K_GEMM_ADJOINT, c.s, [&] { return launch_cgemm_bf16(GM_STORE, g, c.nprob, c.s); }));
+        return TLRMDD_OK;
+    }
     GemmArgs g = gemm_args();
     g.A = c.w.DHs; g.lda = c.lds; g.sA = c.ldk * c.lds;
     g.B = r; g.ldb = c.ldk; g.sB = c.lds * c.ldk;
@@ -544,6 +587,23 @@ int gemm_adjoint(const Ctx &c, const float2 *r, float2 *W, int64_t sW) {
 }
 
 int gemm_line(const Ctx &c, const float2 *X1, const float2 *X2, int64_t sX) {
+    if (c.bf16) {
+        const uint32_t *xh = reinterpret_cast<const uint32_t *>(X1);
+        GemmArgsB g;
+        std::memset(&g, 0, sizeof(g));
+        g.Ahi = reinterpret_cast<const uint16_t *>(c.dsw());
+        g.Alo = reinterpret_cast<const uint16_t *>(c.dsw() + c.lds * c.ldk);
+        g.lda = c.ldk; g.sA = 2 * c.lds * c.ldk;
+        g.Bhi = reinterpret_cast<const uint16_t *>(xh);
+        g.Blo = reinterpret_cast<const uint16_t *>(xh + c.lo_words());
+        g.ldb = c.ldk; g.sB = 2 * sX; g.b2_rows = c.ldk;   // X2 planes follow X1's ldk rows
+        g.C = c.w.a; g.C2 = c.w.b; g.ldc = c.ldk; g.sC = c.lds * c.ldk;
+        g.E = c.w.r; g.lde = c.ldk; g.sE = c.lds * c.ldk;
+        g.partials = c.w.partials; g.sP = (int64_t)c.pstride * 5;
+        g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
+        HIP_TRY(timed(TLRMDD_K_GEMM_LINE, c.s, [&] { return launch_cgemm_bf16(GM_LINE, g, c.nprob, c.s); }));
+        return TLRMDD_OK;
+    }
     GemmArgs g = gemm_args();
     g.A = c.w.Ds; g.lda = c.ldk; g.sA = c.lds * c.ldk;
     g.B = X1; g.B2 = X2; g.ldb = c.ldk; g.sB = sX;
@@ -552,6 +612,28 @@ int gemm_line(const Ctx &c, const float2 *X1, const float2 *X2, int64_t sX) {
     g.partials = c.w.partials; g.sP = (int64_t)c.pstride * 5;
     g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
     HIP_TRY(timed(TLRMDD_K_GEMM_LINE, c.s, [&] { return launch_cgemm(GM_LINE, g, c.nprob, c.s); }));
+    return TLRMDD_OK;
+}
+
+// r^T split planes for the BF16 adjoint product
+int split_r_transpose(const Ctx &c) {
+    if (!c.bf16) return TLRMDD_OK;
+    HIP_TRY(launch_split_transpose(c.w.r, c.ldk, c.lds, c.ldk, c.w.rT, c.w.rT + c.ldk * c.lds, c.lds, c.nprob,
+                                   c.lds * c.ldk, 2 * c.ldk * c.lds, c.s));
+    return TLRMDD_OK;
+}
+
+// staging of D for problem p (padded; split planes in BF16 mode)
+int stage(const Ctx &c, int p, const float2 *D, bool with_dh) {
+    if (c.bf16) {
+        uint32_t *dh = c.dsw() + (int64_t)p * 2 * c.lds * c.ldk;
+        uint32_t *hh = with_dh ? c.dhw() + (int64_t)p * 2 * c.ldk * c.lds : nullptr;
+        HIP_TRY(launch_stage_d_split(D, c.ns, c.nr, dh, dh + c.lds * c.ldk, c.ldk, hh,
+                                     hh ? hh + c.ldk * c.lds : nullptr, c.lds, c.s));
+    } else {
+        HIP_TRY(launch_stage_d(D, c.ns, c.nr, c.w.Ds + (int64_t)p * c.lds * c.ldk, c.ldk,
+                               with_dh ? c.w.DHs + (int64_t)p * c.ldk * c.lds : nullptr, c.lds, c.s));
+    }
     return TLRMDD_OK;
 }
 
@@ -607,7 +689,10 @@ int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const 
 
     const int64_t xstride = 2 * c.ldk * c.ldk;   // per-problem X-space stride
     const int64_t rstride = c.lds * c.ldk;
+    c.bf16 = opts->precision == TLRMDD_BF16X3;
+    c.xspace = xstride;
     float2 *X1 = c.w.XW, *X2 = c.w.XW + c.ldk * c.ldk;
+    const int64_t x2w = c.ldk * c.ldk;           // split form: X2 planes start ldk rows after X1's
     const int64_t stride2 = 2 * T.theta_total;   // floats between ring slots
     const int nt = c.D.n_tseg, nrs = c.D.n_rseg;
 
@@ -615,8 +700,7 @@ int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const 
     // padding of the X space must read as zero (the assembly writes only the true nr x nr block)
     if (c.ldk != nr) HIP_TRY(hipMemsetAsync(c.w.XW, 0, (size_t)nprob * xstride * sizeof(float2), s));
     for (int p = 0; p < nprob; ++p) {
-        HIP_TRY(launch_stage_d((const float2 *)D[p], ns, nr, c.w.Ds + p * rstride, c.ldk,
-                               c.w.DHs + (int64_t)p * c.ldk * c.lds, c.lds, s));
+        if ((st = stage(c, p, (const float2 *)D[p], true))) return st;
         HIP_TRY(launch_copy2d((const float2 *)U[p], nr, c.w.Us + p * rstride, c.ldk, ns, nr, s));
         HIP_TRY(hipMemcpyAsync(c.w.th + 2 * T.probs[p].theta, theta[p],
                                plans[p]->H.theta_size * sizeof(float2), hipMemcpyDeviceToDevice, s));
@@ -624,11 +708,20 @@ int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const 
     FinArgs f0 = fin_args(FIN_INIT, c.w.sc);
     if ((st = fin(c, f0, nullptr, 0, 1))) return st;
 
+    // Split planes of the X space: W (complex64, written by the adjoint product) overlays them
+    // with a different element layout, so their padding must be re-zeroed before each assembly.
+    auto clear_plane_padding = [&]() -> int {
+        if (!c.bf16 || c.ldk == nr) return TLRMDD_OK;
+        HIP_TRY(launch_zero_pad(c.xw(), c.ldk, nr, 4, c.ldk * c.ldk, nprob, 2 * xstride, s));
+        return TLRMDD_OK;
+    };
     auto objective_fresh = [&](int t) -> int {
+        if (int e0 = clear_plane_padding()) return e0;
         HIP_TRY(timed(TLRMDD_K_ASSEMBLE, s, [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)c.w.th,
-                                nullptr, X1, nullptr, s); }));
+                                nullptr, X1, nullptr, s, c.bf16, x2w, c.lo_words()); }));
         int e = gemm_resid(c, X1, xstride, c.w.Us, c.ldk, rstride, c.w.r);
         if (e) return e;
+        if ((e = split_r_transpose(c))) return e;
         FinArgs f = fin_args(FIN_F, c.w.sc);
         f.fhist = single ? nullptr : c.D.fhist;
         f.fhist0 = fhist0;
@@ -686,8 +779,9 @@ int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const 
             HIP_TRY(launch_restart(c.D.tsegs, nt, 0, c.w.p, gcur, c.w.sc, s));
         }
         // exact line search: a = D C1(theta;p), b = D C2(p)
+        if ((st = clear_plane_padding())) return st;
         HIP_TRY(timed(TLRMDD_K_ASSEMBLE_DIR, s, [&] { return launch_assemble(true, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)c.w.th,
-                                (const float2 *)c.w.p, X1, X2, s); }));
+                                (const float2 *)c.w.p, X1, X2, s, c.bf16, x2w, c.lo_words()); }));
         if (lam != 0.0) {
             HIP_TRY(launch_dot2(c.D.tsegs, nt, c.w.th, c.w.p, c.w.p, c.w.p, c.w.partials, s));
             if ((st = fin(c, fin_args(FIN_LAMTERMS, c.w.sc), c.D.tcount, 0, 2))) return st;
@@ -705,6 +799,7 @@ int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const 
             if ((st = fin(c, fin_args(FIN_THNORM, c.w.sc), c.D.tcount, 0, 1))) return st;
         HIP_TRY(launch_resid_update(c.D.rsegs, nrs, (float *)c.w.r, (const float *)c.w.a, (const float *)c.w.b,
                                     c.w.sc, c.w.partials, s));
+        if ((st = split_r_transpose(c))) return st;
         {
             FinArgs f = fin_args(FIN_F, c.w.sc);
             f.fhist = single ? nullptr : c.D.fhist;
@@ -745,16 +840,23 @@ int tlrmdd_forward(tlrmdd_plan plan, const void *D, const void *U, const void *t
     c.w = carve((char *)workspace, 0, 1, c.ldk, c.lds, plan->H.theta_size, 1, c.pstride, 0);
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     c.D = plan->D;
+    c.bf16 = precision == TLRMDD_BF16X3;
+    c.xspace = c.ldk * c.ldk;
     if (c.ldk != c.nr) HIP_TRY(hipMemsetAsync(c.w.XW, 0, (size_t)c.ldk * c.ldk * sizeof(float2), stream));
-    HIP_TRY(launch_stage_d((const float2 *)D, c.ns, c.nr, c.w.Ds, c.ldk, nullptr, c.lds, stream));
+    if ((st = stage(c, 0, (const float2 *)D, false))) return st;
     HIP_TRY(timed(TLRMDD_K_ASSEMBLE, stream, [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
-                            c.w.XW, nullptr, stream); }));
+                            c.w.XW, nullptr, stream, c.bf16, 0, c.lo_words()); }));
     if ((st = gemm_resid(c, c.w.XW, 0, (const float2 *)U, c.nr, 0, c.w.r))) return st;
     FinArgs f = fin_args(FIN_F_OUT, c.w.sc);
     f.fout = f_dev;
     if ((st = fin(c, f, nullptr, resid_tiles(c), 1))) return st;
     if (r_out) HIP_TRY(launch_copy2d(c.w.r, c.ldk, (float2 *)r_out, c.nr, c.ns, c.nr, stream));
-    if (X_out) HIP_TRY(launch_copy2d(c.w.XW, c.ldk, (float2 *)X_out, c.nr, c.nr, c.nr, stream));
+    if (X_out) {
+        if (c.bf16)   // the X space holds split planes: re-assemble X in complex64 for the caller
+            HIP_TRY(launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta,
+                                    nullptr, c.w.XW, nullptr, stream));
+        HIP_TRY(launch_copy2d(c.w.XW, c.ldk, (float2 *)X_out, c.nr, c.nr, c.nr, stream));
+    }
     return TLRMDD_OK;
 }
 
@@ -776,11 +878,14 @@ int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *thet
     c.w = carve((char *)workspace, 1, 1, c.ldk, c.lds, plan->H.theta_size, 1, c.pstride, 0);
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     c.D = plan->D;
+    c.bf16 = precision == TLRMDD_BF16X3;
+    c.xspace = c.ldk * c.ldk;
     if (c.ldk != c.nr) HIP_TRY(hipMemsetAsync(c.w.XW, 0, (size_t)c.ldk * c.ldk * sizeof(float2), stream));
-    HIP_TRY(launch_stage_d((const float2 *)D, c.ns, c.nr, c.w.Ds, c.ldk, c.w.DHs, c.lds, stream));
+    if ((st = stage(c, 0, (const float2 *)D, true))) return st;
     HIP_TRY(timed(TLRMDD_K_ASSEMBLE, stream, [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
-                            c.w.XW, nullptr, stream); }));
+                            c.w.XW, nullptr, stream, c.bf16, 0, c.lo_words()); }));
     if ((st = gemm_resid(c, c.w.XW, 0, (const float2 *)U, c.nr, 0, c.w.r))) return st;
+    if ((st = split_r_transpose(c))) return st;
     if (f_dev) {
         FinArgs f = fin_args(FIN_F_OUT, c.w.sc);
         f.fout = f_dev;

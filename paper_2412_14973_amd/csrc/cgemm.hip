@@ -21,11 +21,10 @@
 // of |C|^2) and GM_LINE (a = D X1, b = D X2 for the same columns in one
 // workgroup, plus FP64 partial sums of Re<r,a>, |a|^2, Re<r,b>, Re<a,b>,
 // |b|^2 for the exact line search).
-#include "common.hpp"
+#include "gemm_common.hpp"
 
 namespace tlr {
 
-typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
@@ -35,25 +34,11 @@ constexpr int A_PITCH = BM + 1;             // floats per real-k row (k-major A 
 constexpr int A_STAGE = 2 * BK * A_PITCH;   // floats per A stage
 constexpr int B_PITCH = 2 * BN;             // floats per k row of the B tile
 constexpr int B_STAGE = BK * B_PITCH;
-constexpr int NSUM_MAX = 5;
-
-// Output layout of the 32x32 MFMA accumulator: lane l holds column l % 32,
-// register r holds row (r % 4) + 8 (r / 4) + 4 (l / 32).
-__device__ __forceinline__ int acc_row(int r, int lane) {
-    return (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 template <int MODE>
 __global__ __launch_bounds__(256, 2) void cgemm_f32_kernel(GemmArgs g) {
     __shared__ float As[2][A_STAGE];
     __shared__ float Bs[2][B_STAGE];
-    __shared__ double red[4][NSUM_MAX];
 
     const int z = blockIdx.y;
     const float2 *A = g.A + z * g.sA;
@@ -197,88 +182,16 @@ __global__ __launch_bounds__(256, 2) void cgemm_f32_kernel(GemmArgs g) {
         __syncthreads();
     }
 
-    // ---- epilogues ----
-    float *C = reinterpret_cast<float *>(g.C + z * g.sC);
-    const int64_t ldc2 = 2 * (int64_t)g.ldc;
-    if (MODE == GM_STORE) {
-#pragma unroll
-        for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-            for (int bn = 0; bn < 4; ++bn) {
-                const int64_t fcol = 2 * (int64_t)(n0 + wn * 64 + bn * 16) + j32;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int row = m0 + wm * 64 + bm * 32 + acc_row(r, lane);
-                    C[row * ldc2 + fcol] = acc[bm][bn][r];
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        return;
-    }
-
-    const float *E = reinterpret_cast<const float *>(g.E + z * g.sE);
-    const int64_t lde2 = 2 * (int64_t)g.lde;
-    double sums[NSUM_MAX] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (MODE == GM_RESID) {
-#pragma unroll
-        for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-            for (int bn = 0; bn < 4; ++bn) {
-                const int col = n0 + wn * 64 + bn * 16 + (j32 >> 1);
-                const int64_t fcol = 2 * (int64_t)(n0 + wn * 64 + bn * 16) + j32;
-                float blk = 0.f;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int row = m0 + wm * 64 + bm * 32 + acc_row(r, lane);
-                    const bool in = row < g.Me && col < g.Ne;   // U has the true (unpadded) shape
-                    const float v = acc[bm][bn][r] - (in ? E[row * lde2 + fcol] : 0.f);
-                    C[row * ldc2 + fcol] = v;
-                    blk = fmaf(v, v, blk);
-                }
-                sums[0] += (double)blk;
-                // one accumulator block at a time: keeps the epilogue's loads from being
-                // hoisted together (register pressure)
-                __builtin_amdgcn_sched_barrier(0);
-            }
-    } else {  // GM_LINE
-        float *C2 = reinterpret_cast<float *>(g.C2 + z * g.sC);
-#pragma unroll
-        for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-            for (int bn = 0; bn < 2; ++bn) {
-                const int64_t fcol = 2 * (int64_t)(n0 + wn * 32 + bn * 16) + j32;
-                // 16 products per sum in FP32 registers, then folded into the FP64 sums
-                float blk[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int row = m0 + wm * 64 + bm * 32 + acc_row(r, lane);
-                    const float av = acc[bm][bn][r];
-                    const float bv = acc[bm][bn + 2][r];
-                    const float rv = E[row * lde2 + fcol];
-                    C[row * ldc2 + fcol] = av;
-                    C2[row * ldc2 + fcol] = bv;
-                    blk[0] = fmaf(rv, av, blk[0]);
-                    blk[1] = fmaf(av, av, blk[1]);
-                    blk[2] = fmaf(rv, bv, blk[2]);
-                    blk[3] = fmaf(av, bv, blk[3]);
-                    blk[4] = fmaf(bv, bv, blk[4]);
-                }
-#pragma unroll
-                for (int q = 0; q < 5; ++q) sums[q] += (double)blk[q];
-                __builtin_amdgcn_sched_barrier(0);
-            }
-    }
-    constexpr int NS = (MODE == GM_RESID) ? 1 : 5;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const double v = wave_sum(sums[s]);
-        if (lane == 0) red[wave][s] = v;
-    }
-    __syncthreads();
-    if (t < NS) {
-        const double v = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
-        g.partials[z * g.sP + (int64_t)pid * NS + t] = v;
-    }
+    EpiArgs ea;
+    ea.C = g.C + z * g.sC;
+    ea.C2 = (MODE == GM_LINE) ? g.C2 + z * g.sC : nullptr;
+    ea.ldc = g.ldc;
+    ea.E = (MODE == GM_STORE) ? nullptr : g.E + z * g.sE;
+    ea.lde = g.lde;
+    ea.Me = g.Me;
+    ea.Ne = g.Ne;
+    ea.partials = g.partials ? g.partials + z * g.sP : nullptr;
+    gemm_epilogue<MODE>(acc, ea, m0, n0, pid);
 }
 
 }  // namespace

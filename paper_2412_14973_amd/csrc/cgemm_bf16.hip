@@ -1,0 +1,190 @@
+// Complex64 GEMM on CDNA4 BF16 matrix cores with a hi+lo split.
+//
+// Every FP32 operand x is carried as two BF16 numbers, hi = bf16(x) and
+// lo = bf16(x - hi); a product is evaluated as hi*hi + hi*lo + lo*hi with FP32
+// accumulation (the lo*lo term, about 2^-16 of the product, is dropped).
+// The complex product is the same realified real GEMM as in the FP32 kernel
+// (M x 2N x 2K, B expanded to [[Re b, Im b], [-Im b, Re b]] blocks), here on
+// v_mfma_f32_32x32x16_bf16: one instruction consumes 8 complex k.
+//
+// Both operands are K-contiguous in memory ("NT" form): A is M x K complex
+// (row-major), B is given TRANSPOSED, N x K complex. For the products of the
+// method this is free: X, X1 and X2 are symmetric, and the adjoint operand
+// r^T is written by the kernel that updates r. Operands are pre-split into
+// separate hi and lo planes of interleaved complex BF16 (4 bytes per complex).
+//
+// Tiling: 256 threads = 4 waves (2 x 2), workgroup tile 128 rows x 128
+// complex columns, 8 complex k per stage, double-buffered LDS (four planes:
+// A hi/lo, B hi/lo, rows padded to 48 bytes so 16-byte operand reads are
+// bank-conflict free). Per stage each wave issues 2 x 4 x 3 MFMAs. Each
+// lane's B fragment (4 complex b of one column) is turned into the realified
+// row pair by one XOR (column parity 0: [Re, -Im]) or a 16-bit rotate
+// (parity 1: [Im, Re]) per 32-bit word.
+#include "gemm_common.hpp"
+
+namespace tlr {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int BM = GEMM_BM, BN = GEMM_BN;
+constexpr int BKC = 8;                    // complex k per stage
+constexpr int PITCH = 48;                 // bytes per LDS row (32 used)
+constexpr int PLANE = 128 * PITCH;        // bytes per plane (128 rows)
+constexpr int STAGE = 4 * PLANE;          // A hi, A lo, B hi, B lo
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+template <int MODE>
+__global__ __launch_bounds__(256, 2) void cgemm_bf16x3_kernel(GemmArgsB g) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[2 * STAGE];
+
+    const int z = blockIdx.y;
+    const int nb = gridDim.x;
+    int pid = blockIdx.x;
+    if ((nb & 7) == 0) pid = (pid & 7) * (nb >> 3) + (pid >> 3);
+    const int group_rows = 8;
+    const int per_group = group_rows * g.tiles_n;
+    const int grp = pid / per_group;
+    const int first_m = grp * group_rows;
+    const int gsz = min(g.tiles_m - first_m, group_rows);
+    const int tm = first_m + (pid % per_group) % gsz;
+    const int tn = (pid % per_group) / gsz;
+    const int m0 = tm * BM;
+    const int n0 = (MODE == GM_LINE) ? tn * (BN / 2) : tn * BN;
+
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    // buffer resources over each plane (bytes); lda/ldb are in complex elements (4 bytes each)
+    const __amdgpu_buffer_rsrc_t rAh = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(g.Ahi + z * g.sA * 2), (short)0, (int)g.bytesA, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rAl = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(g.Alo + z * g.sA * 2), (short)0, (int)g.bytesA, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rBh = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(g.Bhi + z * g.sB * 2), (short)0, (int)g.bytesB, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rBl = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(g.Blo + z * g.sB * 2), (short)0, (int)g.bytesB, 0x00020000);
+
+    // loader: thread t moves 16 bytes (4 complex k) of row t/2 of every plane per stage
+    const int lrow = t >> 1, lchunk = t & 1;
+    const uint32_t offA = (uint32_t)(((int64_t)(m0 + lrow) * g.lda) * 4 + lchunk * 16);
+    uint32_t offB;
+    {
+        int64_t row = n0 + lrow;
+        if (MODE == GM_LINE) {
+            const int grp2 = lrow >> 5;
+            row = n0 + (grp2 >> 1) * 32 + (lrow & 31) + ((grp2 & 1) ? g.b2_rows : 0);
+        }
+        offB = (uint32_t)(row * g.ldb * 4 + lchunk * 16);
+    }
+    const int lds_w = lrow * PITCH + lchunk * 16;
+    u32x4 pre[4];
+    auto load = [&](int k0) {
+        const uint32_t so = (uint32_t)k0 * 4u;
+        pre[0] = __builtin_amdgcn_raw_buffer_load_b128(rAh, (int)offA, (int)so, 0);
+        pre[1] = __builtin_amdgcn_raw_buffer_load_b128(rAl, (int)offA, (int)so, 0);
+        pre[2] = __builtin_amdgcn_raw_buffer_load_b128(rBh, (int)offB, (int)so, 0);
+        pre[3] = __builtin_amdgcn_raw_buffer_load_b128(rBl, (int)offB, (int)so, 0);
+    };
+    auto store = [&](int buf) {
+        unsigned char *st = smem + buf * STAGE + lds_w;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *reinterpret_cast<u32x4 *>(st + q * PLANE) = pre[q];
+    };
+
+    floatx16 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int j32 = lane & 31;
+    const int half = lane >> 5;
+    const bool odd = (j32 & 1) != 0;
+    // fragment read offsets inside a stage
+    const int a_off = (wm * 64 + j32) * PITCH + half * 16;            // + bm * 32 rows
+    const int b_off = (wn * 64 + (j32 >> 1)) * PITCH + half * 16;     // + bn * 16 rows
+
+    auto xform = [&](u32x4 v) {
+        u32x4 o;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const unsigned x = v[w];
+            o[w] = odd ? ((x >> 16) | (x << 16)) : (x ^ 0x80000000u);
+        }
+        return o;
+    };
+
+    const int nk = g.K / BKC;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load((kt + 1) * BKC);
+        const unsigned char *st = smem + buf * STAGE;
+        bf16x8 ah[2], al[2];
+#pragma unroll
+        for (int bm = 0; bm < 2; ++bm) {
+            ah[bm] = as_bf16x8(*reinterpret_cast<const u32x4 *>(st + a_off + bm * 32 * PITCH));
+            al[bm] = as_bf16x8(*reinterpret_cast<const u32x4 *>(st + PLANE + a_off + bm * 32 * PITCH));
+        }
+#pragma unroll
+        for (int bn = 0; bn < 4; ++bn) {
+            const bf16x8 bh = as_bf16x8(xform(*reinterpret_cast<const u32x4 *>(st + 2 * PLANE + b_off + bn * 16 * PITCH)));
+            const bf16x8 bl = as_bf16x8(xform(*reinterpret_cast<const u32x4 *>(st + 3 * PLANE + b_off + bn * 16 * PITCH)));
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm) {
+                acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bm], bh, acc[bm][bn], 0, 0, 0);
+                acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bm], bl, acc[bm][bn], 0, 0, 0);
+                acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bm], bh, acc[bm][bn], 0, 0, 0);
+            }
+        }
+        if (kt + 1 < nk) store(buf ^ 1);
+        __syncthreads();
+    }
+
+    EpiArgs ea;
+    ea.C = g.C + z * g.sC;
+    ea.C2 = (MODE == GM_LINE) ? g.C2 + z * g.sC : nullptr;
+    ea.ldc = g.ldc;
+    ea.E = (MODE == GM_STORE) ? nullptr : g.E + z * g.sE;
+    ea.lde = g.lde;
+    ea.Me = g.Me;
+    ea.Ne = g.Ne;
+    ea.partials = g.partials ? g.partials + z * g.sP : nullptr;
+    gemm_epilogue<MODE>(acc, ea, m0, n0, pid);
+}
+
+}  // namespace
+
+hipError_t launch_cgemm_bf16(int mode, const GemmArgsB &a0, int batch, hipStream_t s) {
+    GemmArgsB a = a0;
+    a.tiles_m = a.M / BM;
+    a.tiles_n = (mode == GM_LINE) ? a.N / (BN / 2) : a.N / BN;
+    if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
+    if (a.M % BM || a.N % BN || a.K % BKC || a.K <= 0) return hipErrorInvalidValue;
+    const int64_t bytesA = (int64_t)a.M * a.lda * 4;
+    const int64_t rowsB = (mode == GM_LINE) ? a.b2_rows + a.N : a.N;
+    const int64_t bytesB = rowsB * a.ldb * 4;
+    if (bytesA >= (int64_t)1 << 32 || bytesB >= (int64_t)1 << 32) return hipErrorInvalidValue;
+    a.bytesA = (uint32_t)bytesA;
+    a.bytesB = (uint32_t)bytesB;
+    dim3 grid(a.tiles_m * a.tiles_n, batch);
+    switch (mode) {
+        case GM_STORE: hipLaunchKernelGGL(cgemm_bf16x3_kernel<GM_STORE>, grid, dim3(256), 0, s, a); break;
+        case GM_RESID: hipLaunchKernelGGL(cgemm_bf16x3_kernel<GM_RESID>, grid, dim3(256), 0, s, a); break;
+        case GM_LINE:  hipLaunchKernelGGL(cgemm_bf16x3_kernel<GM_LINE>, grid, dim3(256), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tlr

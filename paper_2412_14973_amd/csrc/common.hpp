@@ -79,6 +79,36 @@ constexpr int GEMM_BN = 128;   // complex columns per workgroup (64 of a + 64 of
 constexpr int GEMM_BK = 16;    // complex k per stage
 constexpr int GEMM_PAD = 128;  // internal matrices are padded to multiples of this
 
+// BF16 hi+lo split: hi = bf16(x) (round to nearest even), lo = bf16(x - hi)
+__device__ __forceinline__ uint32_t bf16_rne(float x) {
+    const uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;   // NaN stays NaN
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ void split_c(float2 v, uint32_t &hi, uint32_t &lo) {
+    const uint32_t hr = bf16_rne(v.x), hi_ = bf16_rne(v.y);
+    const uint32_t lr = bf16_rne(v.x - __uint_as_float(hr << 16));
+    const uint32_t li = bf16_rne(v.y - __uint_as_float(hi_ << 16));
+    hi = hr | (hi_ << 16);
+    lo = lr | (li << 16);
+}
+
+// BF16 hi+lo split operands: planes of interleaved complex BF16 (one uint32 per complex).
+struct GemmArgsB {
+    const uint16_t *Ahi, *Alo;  int64_t lda;   // M x K complex (row-major planes)
+    const uint16_t *Bhi, *Blo;  int64_t ldb;   // B TRANSPOSED: N x K complex planes
+    int64_t b2_rows;                           // GM_LINE: B2's rows start this many rows after B's
+    float2 *C;        int64_t ldc;
+    float2 *C2;
+    const float2 *E;  int64_t lde;
+    double *partials;
+    int32_t M, N, K, Me, Ne;
+    int32_t tiles_m, tiles_n;
+    int64_t sA, sB, sC, sE, sP;                // batch strides (complex elements / doubles)
+    uint32_t bytesA, bytesB;                   // set by the launcher
+};
+hipError_t launch_cgemm_bf16(int mode, const GemmArgsB &a, int batch, hipStream_t s);
+
 // ---- vector / scalar kernels ----
 constexpr int RED_THREADS = 256;
 constexpr int MAX_LBFGS_M = 32;
@@ -101,15 +131,28 @@ struct SolveScalars {
 hipError_t launch_cgemm(int mode, const GemmArgs &a, int batch, hipStream_t s);
 int gemm_partials_per_problem(int mode, int M, int N);
 
+// out_bf16 == false: X / X2 are complex64 matrices (ProbOff.x offsets, ld ProbOff.ldx).
+// out_bf16 == true: the same region holds split planes of uint32 words; a problem's
+// X hi plane starts at word 2 * ProbOff.x, X2 hi at + x2_words, each lo plane at + lo_words.
 hipError_t launch_assemble(bool dir, const TileDesc *tiles, const AsmItem *items, int nitems,
                            const ProbOff *probs, const float2 *theta, const float2 *p,
-                           float2 *X, float2 *X2, hipStream_t s);
+                           float2 *X, float2 *X2, hipStream_t s, bool out_bf16 = false,
+                           int64_t x2_words = 0, int64_t lo_words = 0);
 hipError_t launch_grad(const TileDesc *tiles, const GradItem *items, int nitems,
                        const ProbOff *probs, const float2 *W, const float2 *theta, float2 *g,
                        hipStream_t s);
 
 hipError_t launch_stage_d(const float2 *D, int64_t ns, int64_t nr, float2 *Ds, int64_t ldk,
                           float2 *DHs, int64_t lds, hipStream_t s);
+// split staging: Dhi/Dlo (lds x ldk planes) and DHhi/DHlo (ldk x lds planes, conjugate transpose)
+hipError_t launch_stage_d_split(const float2 *D, int64_t ns, int64_t nr, uint32_t *Dh, uint32_t *Dl, int64_t ldk,
+                                uint32_t *DHh, uint32_t *DHl, int64_t lds, hipStream_t s);
+// rT = r^T split into planes: r is rows x cols (ld ldr), rT planes are cols x rows (ld ldt)
+hipError_t launch_split_transpose(const float2 *r, int64_t ldr, int64_t rows, int64_t cols, uint32_t *th,
+                                  uint32_t *tl, int64_t ldt, int batch, int64_t s_r, int64_t s_t, hipStream_t s);
+// zero the padding of nplanes ld x ld uint32 planes (true size n x n), per problem of a batch
+hipError_t launch_zero_pad(uint32_t *base, int64_t ld, int64_t n, int nplanes, int64_t plane_stride, int batch,
+                           int64_t batch_stride, hipStream_t s);
 hipError_t launch_copy2d(const float2 *src, int64_t lds, float2 *dst, int64_t ldd,
                          int64_t rows, int64_t cols, hipStream_t s);
 hipError_t launch_permute_cols(const float2 *in, const int64_t *perm, float2 *out,

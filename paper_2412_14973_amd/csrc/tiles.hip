@@ -33,14 +33,29 @@ constexpr int SL_P = ASM_KC + 1;   // pitch of the row-factor stage
 constexpr int SR_P = ASM_BC + 1;   // pitch of the column-factor stage
 constexpr int ST_P = ASM_BR + 1;   // pitch of the transpose stage
 
-template <bool DIR>
+// Output: complex64 (OUTB = false) or split BF16 planes (OUTB = true, see launch_assemble).
+template <bool OUTB>
+__device__ __forceinline__ void put(float2 *X, int64_t o, int64_t low, float2 v) {
+    if (OUTB) {
+        uint32_t h, l;
+        split_c(v, h, l);
+        uint32_t *w = reinterpret_cast<uint32_t *>(X);
+        w[o] = h;
+        w[o + low] = l;
+    } else {
+        X[o] = v;
+    }
+}
+
+template <bool DIR, bool OUTB>
 __global__ __launch_bounds__(256) void assemble_kernel(const TileDesc *__restrict__ tiles,
                                                        const AsmItem *__restrict__ items,
                                                        const ProbOff *__restrict__ probs,
                                                        const float2 *__restrict__ theta_base,
                                                        const float2 *__restrict__ p_base,
                                                        float2 *__restrict__ X_base,
-                                                       float2 *__restrict__ X2_base) {
+                                                       float2 *__restrict__ X2_base,
+                                                       int64_t x2w, int64_t low) {
     // stage buffers: [row factor][col factor] (x2 for the directional form), reused for the transpose
     constexpr int NSTAGE = DIR ? 2 : 1;
     __shared__ float2 sL[NSTAGE][ASM_BR * SL_P];
@@ -52,8 +67,11 @@ __global__ __launch_bounds__(256) void assemble_kernel(const TileDesc *__restric
     const ProbOff po = probs[it.prob];
     const float2 *theta = theta_base + po.theta;
     const float2 *pv = DIR ? p_base + po.theta : nullptr;
-    float2 *X = X_base + po.x;
-    float2 *X2 = DIR ? X2_base + po.x : nullptr;
+    // complex64: X at element po.x; split planes: X hi plane at word 2 po.x, X2 at + x2w words
+    float2 *X = OUTB ? reinterpret_cast<float2 *>(reinterpret_cast<uint32_t *>(X_base) + 2 * po.x) : X_base + po.x;
+    float2 *X2 = !DIR ? nullptr
+                      : (OUTB ? reinterpret_cast<float2 *>(reinterpret_cast<uint32_t *>(X_base) + 2 * po.x + x2w)
+                              : X2_base + po.x);
     const int64_t ldx = po.ldx;
 
     const int t = threadIdx.x;
@@ -158,8 +176,8 @@ __global__ __launch_bounds__(256) void assemble_kernel(const TileDesc *__restric
         const int rr = rg * 8 + i;
         if (rr < nrow && col < ncol) {
             const int64_t o = (td.row0 + r0 + rr) * ldx + td.col0 + c0 + col;
-            X[o] = acc[i];
-            if (DIR) X2[o] = acc2[i];
+            put<OUTB>(X, o, low, acc[i]);
+            if (DIR) put<OUTB>(X2, o, low, acc2[i]);
         }
     }
     if (td.kind != TILE_LR) return;
@@ -173,7 +191,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(const TileDesc *__restric
         for (int e = t; e < ASM_BC * ASM_BR; e += 256) {
             const int cc = e >> 5, rr = e & 31;
             if (cc < ncol && rr < nrow)
-                dst[(td.col0 + c0 + cc) * ldx + td.row0 + r0 + rr] = sT[cc * ST_P + rr];
+                put<OUTB>(dst, (td.col0 + c0 + cc) * ldx + td.row0 + r0 + rr, low, sT[cc * ST_P + rr]);
         }
     }
 }
@@ -333,14 +351,18 @@ __global__ __launch_bounds__(256) void grad_kernel(const TileDesc *__restrict__ 
 
 hipError_t launch_assemble(bool dir, const TileDesc *tiles, const AsmItem *items, int nitems,
                            const ProbOff *probs, const float2 *theta, const float2 *p,
-                           float2 *X, float2 *X2, hipStream_t s) {
+                           float2 *X, float2 *X2, hipStream_t s, bool out_bf16, int64_t x2_words,
+                           int64_t lo_words) {
     if (nitems <= 0) return hipSuccess;
-    if (dir)
-        hipLaunchKernelGGL(assemble_kernel<true>, dim3(nitems), dim3(256), 0, s, tiles, items, probs,
-                           theta, p, X, X2);
+    const dim3 g(nitems), b(256);
+    if (dir && out_bf16)
+        hipLaunchKernelGGL((assemble_kernel<true, true>), g, b, 0, s, tiles, items, probs, theta, p, X, X2, x2_words, lo_words);
+    else if (dir)
+        hipLaunchKernelGGL((assemble_kernel<true, false>), g, b, 0, s, tiles, items, probs, theta, p, X, X2, x2_words, lo_words);
+    else if (out_bf16)
+        hipLaunchKernelGGL((assemble_kernel<false, true>), g, b, 0, s, tiles, items, probs, theta, p, X, X2, x2_words, lo_words);
     else
-        hipLaunchKernelGGL(assemble_kernel<false>, dim3(nitems), dim3(256), 0, s, tiles, items, probs,
-                           theta, p, X, X2);
+        hipLaunchKernelGGL((assemble_kernel<false, false>), g, b, 0, s, tiles, items, probs, theta, p, X, X2, x2_words, lo_words);
     return hipGetLastError();
 }
 

@@ -37,6 +37,75 @@ __global__ __launch_bounds__(256) void stage_d_kernel(const float2 *__restrict__
     }
 }
 
+__global__ __launch_bounds__(256) void stage_d_split_kernel(const float2 *__restrict__ D, int64_t ns, int64_t nr,
+                                                            uint32_t *__restrict__ Dh, uint32_t *__restrict__ Dl,
+                                                            int64_t ldk, uint32_t *__restrict__ DHh,
+                                                            uint32_t *__restrict__ DHl, int64_t lds) {
+    __shared__ float2 tile[32][33];
+    const int64_t s0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t s = s0 + r, c = c0 + tx;
+        float2 v = make_float2(0.f, 0.f);
+        if (s < ns && c < nr) v = D[s * nr + c];
+        if (s < lds && c < ldk) {
+            uint32_t h, l;
+            split_c(v, h, l);
+            Dh[s * ldk + c] = h;
+            Dl[s * ldk + c] = l;
+        }
+        tile[r][tx] = v;
+    }
+    if (!DHh) return;
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t c = c0 + r, s = s0 + tx;
+        if (s < lds && c < ldk) {
+            const float2 v = tile[tx][r];
+            uint32_t h, l;
+            split_c(make_float2(v.x, -v.y), h, l);
+            DHh[c * lds + s] = h;
+            DHl[c * lds + s] = l;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void split_transpose_kernel(const float2 *__restrict__ r, int64_t ldr, int64_t rows,
+                                                              int64_t cols, uint32_t *__restrict__ th,
+                                                              uint32_t *__restrict__ tl, int64_t ldt, int64_t s_r,
+                                                              int64_t s_t) {
+    __shared__ float2 tile[32][33];
+    const int z = blockIdx.z;
+    r += z * s_r;
+    th += z * s_t;
+    tl += z * s_t;
+    const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int q = ty; q < 32; q += 8) {
+        const int64_t i = r0 + q, j = c0 + tx;
+        tile[q][tx] = (i < rows && j < cols) ? r[i * ldr + j] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    for (int q = ty; q < 32; q += 8) {
+        const int64_t j = c0 + q, i = r0 + tx;
+        if (i < rows && j < cols) {
+            uint32_t h, l;
+            split_c(tile[tx][q], h, l);
+            th[j * ldt + i] = h;
+            tl[j * ldt + i] = l;
+        }
+    }
+}
+
+// zero the padding (rows >= n, and columns >= n of rows < n) of ld x ld word planes
+__global__ void zero_pad_kernel(uint32_t *__restrict__ base, int64_t ld, int64_t n, int64_t plane_stride,
+                                int64_t batch_stride) {
+    const int64_t row = blockIdx.x;
+    uint32_t *p = base + (int64_t)blockIdx.z * batch_stride + (int64_t)blockIdx.y * plane_stride + row * ld;
+    const int64_t c0 = row < n ? n : 0;
+    for (int64_t c = c0 + threadIdx.x; c < ld; c += blockDim.x) p[c] = 0u;
+}
+
 __global__ void copy2d_kernel(const float2 *__restrict__ src, int64_t lds, float2 *__restrict__ dst,
                               int64_t ldd, int64_t rows, int64_t cols) {
     const int64_t r = blockIdx.y;
@@ -408,6 +477,29 @@ hipError_t launch_stage_d(const float2 *D, int64_t ns, int64_t nr, float2 *Ds, i
                           float2 *DHs, int64_t lds, hipStream_t s) {
     dim3 grid((unsigned)((ldk + 31) / 32), (unsigned)((lds + 31) / 32));
     hipLaunchKernelGGL(stage_d_kernel, grid, dim3(256), 0, s, D, ns, nr, Ds, ldk, DHs, lds);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_d_split(const float2 *D, int64_t ns, int64_t nr, uint32_t *Dh, uint32_t *Dl, int64_t ldk,
+                                uint32_t *DHh, uint32_t *DHl, int64_t lds, hipStream_t s) {
+    dim3 grid((unsigned)((ldk + 31) / 32), (unsigned)((lds + 31) / 32));
+    hipLaunchKernelGGL(stage_d_split_kernel, grid, dim3(256), 0, s, D, ns, nr, Dh, Dl, ldk, DHh, DHl, lds);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_transpose(const float2 *r, int64_t ldr, int64_t rows, int64_t cols, uint32_t *th,
+                                  uint32_t *tl, int64_t ldt, int batch, int64_t s_r, int64_t s_t, hipStream_t s) {
+    if (rows <= 0 || cols <= 0 || batch <= 0) return hipSuccess;
+    dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32), (unsigned)batch);
+    hipLaunchKernelGGL(split_transpose_kernel, grid, dim3(256), 0, s, r, ldr, rows, cols, th, tl, ldt, s_r, s_t);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_pad(uint32_t *base, int64_t ld, int64_t n, int nplanes, int64_t plane_stride, int batch,
+                           int64_t batch_stride, hipStream_t s) {
+    if (ld <= n || nplanes <= 0 || batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_pad_kernel, dim3((unsigned)ld, (unsigned)nplanes, (unsigned)batch), dim3(128), 0, s, base, ld,
+                       n, plane_stride, batch_stride);
     return hipGetLastError();
 }
 

@@ -88,3 +88,25 @@ def gradient_bound(case, X, r):
     W = case.D.conj().T @ r
     return (O.tile_gradient(case.T, at, EW.astype(np.complex128)).real
             + np.sqrt(dmax) * U32 * O.tile_gradient(case.T, at, np.abs(W).astype(np.complex128)).real)
+
+
+BF16_SPLIT = 2.0 ** -15   # relative error per product of the hi+lo split (dropped lo*lo + lo rounding)
+
+
+def residual_bound_bf16(case, X):
+    """Element-wise error scale of r = D X - U with BF16 hi+lo split products."""
+    aDX = np.abs(case.D) @ np.abs(X)
+    K = X.shape[0]
+    return BF16_SPLIT * aDX + np.sqrt(K) * U32 * (aDX + np.abs(case.U))
+
+
+def gradient_bound_bf16(case, X, r):
+    Er = residual_bound_bf16(case, X)
+    ns = case.D.shape[0]
+    aDH = np.abs(case.D).T
+    EW = aDH @ Er + (BF16_SPLIT + np.sqrt(ns) * U32) * (aDH @ np.abs(r))
+    at = np.abs(case.theta).astype(np.complex128)
+    dmax = max(case.T.d)
+    W = case.D.conj().T @ r
+    return (O.tile_gradient(case.T, at, EW.astype(np.complex128)).real
+            + np.sqrt(dmax) * U32 * O.tile_gradient(case.T, at, np.abs(W).astype(np.complex128)).real)

@@ -124,3 +124,26 @@ def test_invalid_arguments_raise(tl):
     with pytest.raises(tl.TLRMDDError) as e:
         tl.forward(plan, D, U, th, precision=7)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+def test_bf16x3_forward_and_gradient_parity(tl, name, mk):
+    from gpu_cases import gradient_bound_bf16, residual_bound_bf16
+    case = mk()
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    f, r, X = tl.forward(plan, D, U, th, precision=tl.BF16X3, want_r=True, want_X=True)
+    fg, g = tl.grad(plan, D, U, th, precision=tl.BF16X3)
+    torch.cuda.synchronize()
+    Xo = O.assemble(case.T, case.theta)
+    fo, ro = O.objective(case.T, case.D, case.U, case.theta)
+    _, go = O.gradient(case.T, case.D, case.U, case.theta)
+    assert np.array_equal(X.cpu().numpy(), X.cpu().numpy().T)
+    err = np.abs(r.cpu().numpy().astype(np.complex128) - ro)
+    bound = 8 * residual_bound_bf16(case, Xo)
+    print(f"{name} bf16x3: max r err/bound {np.max(err / bound):.3f}, rel f {abs(f.item() - fo) / fo:.2e}")
+    assert np.all(err <= bound)
+    gerr = np.abs(g.cpu().numpy().astype(np.complex128) - go)
+    gb = 8 * gradient_bound_bf16(case, Xo, ro) + 1e-30
+    print(f"{name} bf16x3: max g err/bound {np.max(gerr / gb):.3f}")
+    assert np.all(gerr <= gb)
+    assert abs(f.item() - fo) <= 5e-3 * fo and abs(fg.item() - fo) <= 5e-3 * fo

@@ -100,16 +100,142 @@ def cpu_baseline(wl, budget_s):
                       f"{n} L-BFGS iterations, complex128 NumPy, {dt:.1f} s"}
 
 
+def serving(tl, torch, args):
+    """Poisson stream of per-frequency solves of uneven size: continuous batching
+    (FIFO admission by HBM budget, up to --max-active overlapping solves) against
+    the same stream solved one at a time. Inputs are generated on the device before
+    the clock starts; each request's work (Hilbert column gather + 100-iteration
+    solve) runs on its own stream. Results of the two runs must agree bit for bit."""
+    import synth
+    from paper_2412_14973_amd import serve
+    prec = tl.FP32 if args.precision == "fp32" else tl.BF16X3
+    reqs = synth.request_stream(args.requests, iters=args.iters or 100)
+    dev = torch.device("cuda")
+    prepared = []
+    t0 = time.time()
+    for r in reqs:
+        D, U, th, lay, geom = synth.device_problem(r, dev)
+        perm = torch.from_numpy(tl.hilbert_order(geom.rec_ix, geom.rec_iy)).to(dev)
+        plan = tl.Plan.from_layout(lay, geom.ns)
+        prepared.append((r, D, U, th, perm, plan))
+        log(f"request {r.rid}: nr {geom.nr} ns {geom.ns} d {r.d} k {r.k} ({time.time() - t0:.1f}s)")
+    torch.cuda.synchronize()
+
+    class Backend(serve.GpuBackend):
+        def start(self, req):
+            r, D, U, th, perm, plan = req
+            sidx = self.free_streams.pop(0)
+            stream = self.streams[sidx]
+            stream.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(stream):
+                Dh = tl.permute_columns(D, perm)
+                Uh = tl.permute_columns(U, perm)
+                theta, fh = tl.solve(plan, Dh, Uh, th, r.iters, precision=prec)
+                ev = torch.cuda.Event()
+                ev.record(stream)
+            return {"event": ev, "stream": sidx, "theta": theta, "fhist": fh, "keep": (Dh, Uh)}
+
+        def footprint(self, req):
+            r, D, U, th, perm, plan = req
+            return super().footprint(serve.SolveRequest(plan, D, U, th, r.iters, prec)) + 2 * D.numel() * 8
+
+    out = {"metric": "TLR-MDD served solves/s, p50/p99 latency", "requests": len(reqs),
+           "arrival_rate_per_s": 200.0, "iters": reqs[0].iters, "precision": args.precision,
+           "hbm_budget_gib": args.hbm_budget_gib, "sizes": [[r.n_side ** 2, (r.n_side ** 2) // (2 if r.ns_mode == "half" else 1), r.d, r.k] for r in reqs]}
+    results = {}
+    for mode, active in (("one_at_a_time", 1), ("continuous", args.max_active)):
+        be = Backend(n_streams=max(active, 1))
+        jobs = [serve.Job(rid=p[0].rid, arrival=p[0].arrival, payload=p) for p in prepared]
+        torch.cuda.synchronize()
+        be.clock = serve.WallClock()
+        srv = serve.Server(be, hbm_budget=int(args.hbm_budget_gib * 2 ** 30), max_active=active)
+        srv.run(jobs)
+        torch.cuda.synchronize()
+        out[mode] = serve.summarize(jobs)
+        out[mode]["max_active"] = active
+        out[mode]["peak_hbm_gib"] = srv.peak_in_use / 2 ** 30
+        results[mode] = {j.rid: j.result for j in jobs}
+        log(f"{mode}: {out[mode]}")
+    same = all(torch.equal(results["one_at_a_time"][k]["theta"], results["continuous"][k]["theta"])
+               and torch.equal(results["one_at_a_time"][k]["fhist"], results["continuous"][k]["fhist"])
+               for k in results["continuous"])
+    out["bitwise_same_alone_and_in_mix"] = bool(same)
+    out["speedup_solves_per_s"] = out["continuous"]["solves_per_s"] / out["one_at_a_time"]["solves_per_s"]
+    return out
+
+
+def error_table(tl, torch, args):
+    """Mixed-precision error table on the 64 x 64-receiver problem (nr 4096, ns 2048,
+    tile 256, rank 32) at 10 and 30 dB: FP32 and BF16x3 solves against the FP64 oracle."""
+    import numpy as np
+
+    import oracle as O
+    import synth
+    iters = args.iters or 100
+    rows = []
+    for snr in (10.0, 30.0):
+        wl = synth.large(snr_db=snr, config_id=4)
+        f_idx = 10
+        geom = wl.geometry()
+        prob = wl.problem(f_idx, geom)
+        lay = wl.layout(f_idx)
+        T = O.tiling(lay.tile_size, lay.rank_off, lay.rank_diag)
+        D64 = prob.D.astype(np.complex64)
+        U64 = prob.U.astype(np.complex64)
+        th64 = wl.theta0(f_idx, lay).astype(np.complex64)
+        perm = tl.hilbert_order(geom.rec_ix, geom.rec_iy)
+        dev = torch.device("cuda")
+        pd = torch.from_numpy(perm).to(dev)
+        D = tl.permute_columns(torch.from_numpy(D64).to(dev), pd)
+        U = tl.permute_columns(torch.from_numpy(U64).to(dev), pd)
+        th = torch.from_numpy(th64).to(dev)
+        plan = tl.Plan.from_layout(lay, geom.ns)
+        res = {}
+        for name, prec in (("fp32", tl.FP32), ("bf16x3", tl.BF16X3)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            thT, fh = tl.solve(plan, D, U, th, iters, precision=prec)
+            torch.cuda.synchronize()
+            res[name] = (thT.cpu().numpy().astype(np.complex128), time.perf_counter() - t0)
+            log(f"snr {snr}: {name} solve {res[name][1]:.2f} s")
+        Do = D64.astype(np.complex128)[:, perm]
+        Uo = U64.astype(np.complex128)[:, perm]
+        t0 = time.perf_counter()
+
+        def progress(t, state):
+            if t % 10 == 0:
+                log(f"snr {snr}: oracle iteration {t}/{iters} ({time.perf_counter() - t0:.0f} s)")
+        ref = O.solve(T, Do, Uo, th64.astype(np.complex128), iters=iters, record=progress)
+        t_or = time.perf_counter() - t0
+        log(f"snr {snr}: oracle {t_or:.1f} s")
+        fo = O.objective(T, Do, Uo, ref.theta)[0]
+        Xo = O.assemble(T, ref.theta)
+        for name, (thg, tg) in res.items():
+            fg = O.objective(T, Do, Uo, thg)[0]
+            rows.append({"snr_db": snr, "freq_hz": float(wl.freqs[f_idx]), "precision": name, "iters": iters,
+                         "rel_f": abs(fg - fo) / fo,
+                         "rel_X": float(np.linalg.norm(O.assemble(T, thg) - Xo) / np.linalg.norm(Xo)),
+                         "rel_theta": float(np.linalg.norm(thg - ref.theta) / np.linalg.norm(ref.theta)),
+                         "f_oracle": fo, "f_gpu": fg, "gpu_s": tg, "oracle_s": t_or})
+    return {"error_table": rows, "workload": "nr4096_ns2048_d256_k32 (frequency index 10 of 32, 5-35 Hz)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["batched", "large"], default="batched")
+    ap.add_argument("--workload", choices=["batched", "large", "serving"], default="batched")
+    ap.add_argument("--requests", type=int, default=16, help="serving: requests in the Poisson stream")
+    ap.add_argument("--max-active", type=int, default=4, help="serving: concurrent solves")
+    ap.add_argument("--hbm-budget-gib", type=float, default=96.0, help="serving: admission budget")
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--nfreq", type=int, default=None)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--error-table", action="store_true",
+                    help="per-frequency error of FP32 and BF16x3 solves against the FP64 oracle (large workload)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -132,6 +258,13 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
         del src, dst
+    if args.error_table:
+        print(json.dumps(error_table(tl, torch, args)), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps(serving(tl, torch, args)), flush=True)
+        return
+    prec = tl.FP32 if args.precision == "fp32" else tl.BF16X3
     wl = synth.batched() if args.workload == "batched" else synth.large()
     nfreq = args.nfreq or (len(wl.freqs) if args.workload == "batched" else 4)
     iters = args.iters or wl.iters
@@ -139,7 +272,7 @@ def main():
     dev = torch.device("cuda")
     perm = torch.from_numpy(tl.hilbert_order(geom.rec_ix, geom.rec_iy)).to(dev)
     ns, nr = geom.ns, geom.nr
-    opts = tl.make_opts(iters)
+    opts = tl.make_opts(iters, precision=prec)
     ws = torch.empty(tl.batched_workspace_bytes(plans, opts), dtype=torch.uint8, device=dev)
     out_th = [t.clone() for t in ths]
     out_fh = [torch.empty(iters + 1, dtype=torch.float64, device=dev) for _ in range(nfreq)]
@@ -148,7 +281,8 @@ def main():
     def step():
         Dh = [tl.permute_columns(D, perm) for D in Ds]
         Uh = [tl.permute_columns(U, perm) for U in Us]
-        tl.solve_batched(plans, Dh, Uh, ths, iters, workspace=ws, out_thetas=out_th, out_fhist=out_fh)
+        tl.solve_batched(plans, Dh, Uh, ths, iters, precision=prec, workspace=ws, out_thetas=out_th,
+                         out_fhist=out_fh)
 
     for w in range(args.warmup):
         step()
@@ -184,9 +318,12 @@ def main():
             fl = per_prob[k] * nfreq
             entry["tflops"] = fl / avg / 1e12
             entry["frac_f32_peak"] = fl / avg / PEAK["f32"]
+            if prec != tl.FP32:   # three BF16 products per real product
+                entry["frac_bf16_peak_executed"] = 3 * fl / avg / PEAK["bf16"]
         kernels[k] = entry
     dom = kernels["gemm_line"]
     achieved = dom["tflops"] * 1e12
+    peak = PEAK["f32"] if prec == tl.FP32 else PEAK["bf16"]
     gemm_flops = sum(per_prob[k] * nfreq * kt.launches[k] for k in per_prob)
     gemm_s = sum(kt.ms[k] for k in per_prob) * 1e-3
     line = {
@@ -200,20 +337,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if prec == tl.FP32 else "bf16x3",
         "data": "synthetic",
         "config": {"workload": wl.name if nfreq == len(wl.freqs) else f"{wl.name}[first {nfreq}]",
                    "nr": nr, "ns": ns, "frequencies": nfreq, "iters": iters, "optimizer": "lbfgs(m=5)",
-                   "precision": "fp32-mfma"},
-        "roofline": {"bound": "mfma", "kernel": "cgemm_f32_kernel<GM_LINE> ([a|b] = D [X1|X2])",
-                     "achieved": achieved / 1e12, "peak": PEAK["f32"] / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["f32"], "traffic": measured_traffic(nfreq, args.workload),
+                   "precision": "fp32-mfma" if prec == tl.FP32 else "bf16x3-mfma"},
+        "roofline": {"bound": "mfma",
+                     "kernel": ("cgemm_f32_kernel<GM_LINE>" if prec == tl.FP32 else "cgemm_bf16x3_kernel<GM_LINE>")
+                     + " ([a|b] = D [X1|X2])",
+                     "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(nfreq, args.workload) if prec == tl.FP32 else None,
                      "algorithmic_bytes": 6 * 8.0 * ns * nr * nfreq},
         "mfma_frac_all_gemms": gemm_flops / gemm_s / PEAK["f32"],
         "kernels": kernels,
         "objective": {"f0_mean": sum(f_first) / nfreq, "fT_mean": sum(f_final) / nfreq},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and prec == tl.FP32:
         log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     print(json.dumps(line), flush=True)

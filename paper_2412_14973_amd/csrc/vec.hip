@@ -279,14 +279,18 @@ __global__ __launch_bounds__(256) void theta_update_kernel(const VecSeg *__restr
     const VecSeg sg = segs[blockIdx.x];
     const SolveScalars &s = sc[sg.prob];
     const float a = (float)s.step;
-    float *S = Sb ? Sb + s.head * stride2 : nullptr;
+    const bool frozen = s.frozen != 0;   // a non-finite step froze this problem: theta stays as is
+    float *S = (Sb && !frozen) ? Sb + s.head * stride2 : nullptr;
     double acc = 0.0;
     for (int e = threadIdx.x; e < sg.n; e += 256) {
         const int64_t o = sg.off + e;
-        const float sp = a * p[o];
-        const float v = th[o] + sp;
-        th[o] = v;
-        if (S) S[o] = sp;
+        float v = th[o];
+        if (!frozen) {
+            const float sp = a * p[o];
+            v += sp;
+            th[o] = v;
+            if (S) S[o] = sp;
+        }
         acc += (double)v * v;
     }
     acc = block_sum(acc, red);
@@ -303,11 +307,15 @@ __global__ __launch_bounds__(256) void resid_update_kernel(const VecSeg *__restr
     const SolveScalars &s = sc[sg.prob];
     const float al = (float)s.step;
     const float al2 = (float)(s.step * s.step);
+    const bool frozen = s.frozen != 0;
     double acc = 0.0;
     for (int e = threadIdx.x; e < sg.n; e += 256) {
         const int64_t o = sg.off + e;
-        const float v = r[o] + al * a[o] + al2 * b[o];
-        r[o] = v;
+        float v = r[o];
+        if (!frozen) {
+            v += al * a[o] + al2 * b[o];
+            r[o] = v;
+        }
         acc += (double)v * v;
     }
     acc = block_sum(acc, red);

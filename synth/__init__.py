@@ -345,3 +345,50 @@ def request_problem(req: Request, config_id: int = 5) -> Tuple[Problem, Layout, 
     lay = request_layout(req)
     th = init_theta(theta_length(lay), config_id, 1000 + req.rid)
     return prob, lay, th
+
+
+# ----------------------------------------------------------------------------
+# device-side generation (same recipe, torch on the GPU) for large request sizes
+# ----------------------------------------------------------------------------
+def device_problem(req: Request, device, config_id: int = 5):
+    """(D, U, theta0, layout, geometry) of a request, generated on `device`.
+
+    Same recipe as make_problem (homogeneous Green's functions, exact-SNR noise
+    on U, 5 % noise on D, normalisation by 1/min distance), computed in
+    complex128 with torch's device generator seeded from (config, request),
+    returned as complex64 in natural receiver order.
+    """
+    import torch
+    geom = make_geometry(req.n_side, req.n_side, req.ns_mode)
+    lay = request_layout(req)
+    seed = int(np.random.SeedSequence(BASE_SEED, spawn_key=(config_id, 1000 + req.rid, P_REQUEST))
+               .generate_state(1)[0])
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    rec = torch.as_tensor(geom.rec_xyz, device=device)
+    src = torch.as_tensor(geom.src_xyz, device=device)
+    w = 2.0 * math.pi * req.freq
+    dsr = torch.cdist(src, rec)
+    D_clean = torch.exp(-1j * w * dsr / VELOCITY) / dsr
+    drr = torch.cdist(rec, rec)
+    X_true = torch.exp(-1j * w * drr / VELOCITY) / (drr + X_TRUE_OFFSET)
+    X_true = 0.5 * (X_true + X_true.T)
+    U_clean = D_clean @ X_true
+    del X_true, drr
+
+    def cg(shape):
+        return torch.complex(torch.randn(shape, generator=gen, device=device, dtype=torch.float64),
+                             torch.randn(shape, generator=gen, device=device, dtype=torch.float64))
+    n_u = cg(U_clean.shape)
+    U = U_clean + n_u * (torch.linalg.norm(U_clean) / (torch.linalg.norm(n_u) * 10.0 ** (20.0 / 20.0)))
+    del n_u, U_clean
+    n_d = cg(D_clean.shape)
+    D = D_clean + n_d * (0.05 * torch.linalg.norm(D_clean) / torch.linalg.norm(n_d))
+    del n_d, D_clean
+    alpha = 1.0 / float(dsr.min())
+    n = theta_length(lay)
+    s = math.sqrt(1e-2 / 2.0)
+    th = torch.complex(s * torch.randn(n, generator=gen, device=device, dtype=torch.float32),
+                       s * torch.randn(n, generator=gen, device=device, dtype=torch.float32))
+    return ((D / alpha).to(torch.complex64).contiguous(), (U / alpha).to(torch.complex64).contiguous(),
+            th, lay, geom)

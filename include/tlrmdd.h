@@ -168,6 +168,13 @@ int tlrmdd_solve_batched(int count, const tlrmdd_plan *plans, const void *const 
                          const tlrmdd_opts *opts, double *const *f_hist_dev,
                          void *workspace, size_t ws_bytes, hipStream_t stream);
 
+/* Adjoint (cross-correlation) solution X_adj = D^H U (MDD Solver Evaluation section: the
+ * adjoint solution that needs no inversion). D, U: device ns x nr complex64; X_out: device
+ * nr x nr complex64. Uses the plan's sizes only (its tiles are ignored). Workspace: as for
+ * TLRMDD_OP_GRAD. */
+int tlrmdd_adjoint(tlrmdd_plan plan, const void *D, const void *U, void *X_out, int precision,
+                   void *workspace, size_t ws_bytes, hipStream_t stream);
+
 /* Hilbert ordering of receivers (Receivers re-ordering section, eq. hilbert).
  * ix, iy: host, n non-negative 0-based grid coordinates (x = station along a
  * line, y = line). perm_out: host, n entries: perm_out[k] is the natural

@@ -14,7 +14,8 @@ import torch
 from . import _lib
 from ._lib import BF16X3, FP32, GD, LBFGS, TLRMDDError  # noqa: F401
 
-__all__ = ["Plan", "hilbert_order", "permute_columns", "forward", "grad", "solve", "solve_batched",
+__all__ = ["Plan", "hilbert_order", "permute_columns", "forward", "grad", "solve", "solve_batched", "adjoint",
+           "benchmark_solve",
            "TLRMDDError", "FP32", "BF16X3", "LBFGS", "GD"]
 
 
@@ -143,6 +144,29 @@ def grad(plan, D, U, theta, precision=FP32, workspace=None):
     _lib.check(_lib.load().tlrmdd_grad(plan.handle, _ptr(D), _ptr(U), _ptr(theta), _ptr(f), _ptr(g), precision,
                                        _ptr(ws), ws.numel(), _stream()), "tlrmdd_grad")
     return f, g
+
+
+def adjoint(plan, D, U, precision=FP32, workspace=None):
+    """X_adj = D^H U (nr x nr complex64 on the device)."""
+    _dev_tensor(D, "D")
+    _dev_tensor(U, "U")
+    X = torch.empty((plan.nr, plan.nr), dtype=torch.complex64, device=D.device)
+    ws = workspace if workspace is not None else plan.workspace(_lib.OP_GRAD, device=D.device)
+    _lib.check(_lib.load().tlrmdd_adjoint(plan.handle, _ptr(D), _ptr(U), _ptr(X), precision, _ptr(ws), ws.numel(),
+                                          _stream()), "tlrmdd_adjoint")
+    return X
+
+
+def benchmark_solve(D, U, lam, iters, precision=FP32, lbfgs_m=5, Z0=None):
+    """Benchmark (preconditioned Tikhonov) solver: min 1/2 ||D P Z - U||^2 + lam ||Z||^2 with
+    P Z = (Z + Z^T)/2, then X = P Z. It is the tile solve with one dense diagonal tile of size
+    nr; returns (X, f_hist)."""
+    ns, nr = D.shape
+    plan = Plan(np.array([nr]), np.zeros(0, dtype=np.int32), np.array([-1]), ns)
+    Z = Z0 if Z0 is not None else torch.zeros(nr * nr, dtype=torch.complex64, device=D.device)
+    Z, fh = solve(plan, D, U, Z, iters, lbfgs_m=lbfgs_m, precision=precision, lam=lam)
+    _, _, X = forward(plan, D, U, Z, precision, want_X=True)
+    return X, fh
 
 
 def make_opts(iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0, resid_refresh=0):

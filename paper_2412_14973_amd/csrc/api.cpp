@@ -898,6 +898,34 @@ int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *thet
     return TLRMDD_OK;
 }
 
+int tlrmdd_adjoint(tlrmdd_plan plan, const void *D, const void *U, void *X_out, int precision, void *workspace,
+                   size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (!plan || !D || !U || !X_out || !workspace) return fail(TLRMDD_INVALID_ARGUMENT, "NULL argument");
+    int st = check_precision(precision);
+    if (st) return st;
+    Ctx c;
+    c.nprob = 1;
+    c.nr = plan->H.nr;
+    c.ns = plan->H.ns;
+    c.ldk = plan->ldk;
+    c.lds = plan->lds;
+    c.s = stream;
+    c.pstride = partial_stride(plan->T, c.ldk, c.lds);
+    c.w = carve((char *)workspace, 1, 1, c.ldk, c.lds, plan->H.theta_size, 1, c.pstride, 0);
+    if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
+    c.D = plan->D;
+    c.bf16 = precision == TLRMDD_BF16X3;
+    c.xspace = c.ldk * c.ldk;
+    if ((st = stage(c, 0, (const float2 *)D, true))) return st;
+    // U takes the place of the residual: padded copy with zero padding, then W = D^H U
+    HIP_TRY(launch_stage_d((const float2 *)U, c.ns, c.nr, c.w.r, c.ldk, nullptr, c.lds, stream));
+    if ((st = split_r_transpose(c))) return st;
+    if ((st = gemm_adjoint(c, c.w.r, c.w.XW, 0))) return st;
+    HIP_TRY(launch_copy2d(c.w.XW, c.ldk, (float2 *)X_out, c.nr, c.nr, c.nr, stream));
+    return TLRMDD_OK;
+}
+
 int tlrmdd_solve(tlrmdd_plan plan, const void *D, const void *U, void *theta_inout, const tlrmdd_opts *opts,
                  double *f_hist_dev, void *workspace, size_t ws_bytes, hipStream_t stream) {
     g_last_error.clear();

@@ -14,9 +14,11 @@
 // separate hi and lo planes of interleaved complex BF16 (4 bytes per complex).
 //
 // Tiling: 256 threads = 4 waves (2 x 2), workgroup tile 128 rows x 128
-// complex columns, 8 complex k per stage, double-buffered LDS (four planes:
-// A hi/lo, B hi/lo, rows padded to 48 bytes so 16-byte operand reads are
-// bank-conflict free). Per stage each wave issues 2 x 4 x 3 MFMAs. Each
+// complex columns, 8 complex k per stage. Operands go straight from global
+// memory to LDS (buffer_load ... lds, no staging registers) into a 4-stage
+// ring (four planes per stage: A hi/lo, B hi/lo, 16-byte chunks XOR-swizzled
+// so operand reads are bank-conflict free); loads run three stages ahead of
+// the matrix cores. Per stage each wave issues 2 x 4 x 3 MFMAs. Each
 // lane's B fragment (4 complex b of one column) is turned into the realified
 // row pair by one XOR (column parity 0: [Re, -Im]) or a 16-bit rotate
 // (parity 1: [Im, Re]) per 32-bit word.
@@ -30,16 +32,30 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int BM = GEMM_BM, BN = GEMM_BN;
-constexpr int BKC = 8;                    // complex k per stage
-constexpr int PITCH = 48;                 // bytes per LDS row (32 used)
-constexpr int PLANE = 128 * PITCH;        // bytes per plane (128 rows)
+constexpr int BKC = 8;                    // complex k per stage (= 16 real k = one MFMA)
+constexpr int ROWB = 32;                  // bytes per LDS row of a plane (8 complex BF16)
+constexpr int PLANE = 128 * ROWB;         // 4 KiB per plane
 constexpr int STAGE = 4 * PLANE;          // A hi, A lo, B hi, B lo
+constexpr int NSTAGE = 4;                 // LDS ring depth (64 KiB per workgroup)
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
+// s_waitcnt with only the vector-memory counter constrained (gfx9 encoding)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | (((N >> 4) & 3) << 14));
+}
+
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+
 template <int MODE>
 __global__ __launch_bounds__(256, 2) void cgemm_bf16x3_kernel(GemmArgsB g) {
-    __shared__ __attribute__((aligned(16))) unsigned char smem[2 * STAGE];
+    // four distinct LDS objects (one per ring stage): reads of one stage and DMA into another are
+    // then provably disjoint, so no conservative vmcnt wait is needed before the operand reads
+    __shared__ __attribute__((aligned(1024))) unsigned char sm0[STAGE];
+    __shared__ __attribute__((aligned(1024))) unsigned char sm1[STAGE];
+    __shared__ __attribute__((aligned(1024))) unsigned char sm2[STAGE];
+    __shared__ __attribute__((aligned(1024))) unsigned char sm3[STAGE];
 
     const int z = blockIdx.y;
     const int nb = gridDim.x;
@@ -57,10 +73,9 @@ __global__ __launch_bounds__(256, 2) void cgemm_bf16x3_kernel(GemmArgsB g) {
 
     const int t = threadIdx.x;
     const int lane = t & 63;
-    const int wave = t >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (LDS DMA base in M0)
     const int wm = wave >> 1, wn = wave & 1;
 
-    // buffer resources over each plane (bytes); lda/ldb are in complex elements (4 bytes each)
     const __amdgpu_buffer_rsrc_t rAh = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(g.Ahi + z * g.sA * 2), (short)0, (int)g.bytesA, 0x00020000);
     const __amdgpu_buffer_rsrc_t rAl = __builtin_amdgcn_make_buffer_rsrc(
@@ -70,8 +85,11 @@ __global__ __launch_bounds__(256, 2) void cgemm_bf16x3_kernel(GemmArgsB g) {
     const __amdgpu_buffer_rsrc_t rBl = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(g.Blo + z * g.sB * 2), (short)0, (int)g.bytesB, 0x00020000);
 
-    // loader: thread t moves 16 bytes (4 complex k) of row t/2 of every plane per stage
-    const int lrow = t >> 1, lchunk = t & 1;
+    // Direct global -> LDS loads: lane l of wave w fills the 16 bytes at (w * 64 + l) * 16 of
+    // each plane, i.e. row w*32 + l/2, stored chunk l&1. Chunks are XOR-swizzled by bit 3 of the
+    // row (stored = actual ^ ((row >> 3) & 1)) so the 16-byte operand reads hit distinct banks.
+    const int lrow = wave * 32 + (lane >> 1);
+    const int lchunk = (lane & 1) ^ ((lrow >> 3) & 1);
     const uint32_t offA = (uint32_t)(((int64_t)(m0 + lrow) * g.lda) * 4 + lchunk * 16);
     uint32_t offB;
     {
@@ -82,19 +100,13 @@ __global__ __launch_bounds__(256, 2) void cgemm_bf16x3_kernel(GemmArgsB g) {
         }
         offB = (uint32_t)(row * g.ldb * 4 + lchunk * 16);
     }
-    const int lds_w = lrow * PITCH + lchunk * 16;
-    u32x4 pre[4];
-    auto load = [&](int k0) {
-        const uint32_t so = (uint32_t)k0 * 4u;
-        pre[0] = __builtin_amdgcn_raw_buffer_load_b128(rAh, (int)offA, (int)so, 0);
-        pre[1] = __builtin_amdgcn_raw_buffer_load_b128(rAl, (int)offA, (int)so, 0);
-        pre[2] = __builtin_amdgcn_raw_buffer_load_b128(rBh, (int)offB, (int)so, 0);
-        pre[3] = __builtin_amdgcn_raw_buffer_load_b128(rBl, (int)offB, (int)so, 0);
-    };
-    auto store = [&](int buf) {
-        unsigned char *st = smem + buf * STAGE + lds_w;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) *reinterpret_cast<u32x4 *>(st + q * PLANE) = pre[q];
+    auto issue = [&](unsigned char *buf, int kt) {
+        unsigned char *st = buf + wave * 1024;
+        const int so = kt * BKC * 4;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rAh, (lds_ptr_t)(st + 0 * PLANE), 16, (int)offA, so, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rAl, (lds_ptr_t)(st + 1 * PLANE), 16, (int)offA, so, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rBh, (lds_ptr_t)(st + 2 * PLANE), 16, (int)offB, so, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rBl, (lds_ptr_t)(st + 3 * PLANE), 16, (int)offB, so, 0, 0);
     };
 
     floatx16 acc[2][4];
@@ -108,38 +120,32 @@ __global__ __launch_bounds__(256, 2) void cgemm_bf16x3_kernel(GemmArgsB g) {
     const int j32 = lane & 31;
     const int half = lane >> 5;
     const bool odd = (j32 & 1) != 0;
-    // fragment read offsets inside a stage
-    const int a_off = (wm * 64 + j32) * PITCH + half * 16;            // + bm * 32 rows
-    const int b_off = (wn * 64 + (j32 >> 1)) * PITCH + half * 16;     // + bn * 16 rows
+    // fragment reads (swizzled chunk): A rows wm*64 + bm*32 + j32, B rows wn*64 + bn*16 + j32/2
+    const int a_off = (wm * 64 + j32) * ROWB + ((half ^ ((j32 >> 3) & 1)) * 16);
+    const int b_off = (wn * 64 + (j32 >> 1)) * ROWB + ((half ^ ((j32 >> 4) & 1)) * 16);
 
+    // realified B row pair from 4 complex b: even column -> [Re, -Im] (flip the sign bit of the
+    // high half), odd column -> [Im, Re] (rotate by 16); branch-free: rotr(x, sh) ^ msk
+    const unsigned sh = odd ? 16u : 0u;
+    const unsigned msk = odd ? 0u : 0x80000000u;
     auto xform = [&](u32x4 v) {
         u32x4 o;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const unsigned x = v[w];
-            o[w] = odd ? ((x >> 16) | (x << 16)) : (x ^ 0x80000000u);
-        }
+        for (int w = 0; w < 4; ++w) o[w] = __builtin_amdgcn_alignbit(v[w], v[w], sh) ^ msk;
         return o;
     };
 
-    const int nk = g.K / BKC;
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < nk) load((kt + 1) * BKC);
-        const unsigned char *st = smem + buf * STAGE;
+    auto compute = [&](const unsigned char *st) {
         bf16x8 ah[2], al[2];
 #pragma unroll
         for (int bm = 0; bm < 2; ++bm) {
-            ah[bm] = as_bf16x8(*reinterpret_cast<const u32x4 *>(st + a_off + bm * 32 * PITCH));
-            al[bm] = as_bf16x8(*reinterpret_cast<const u32x4 *>(st + PLANE + a_off + bm * 32 * PITCH));
+            ah[bm] = as_bf16x8(*reinterpret_cast<const u32x4 *>(st + a_off + bm * 32 * ROWB));
+            al[bm] = as_bf16x8(*reinterpret_cast<const u32x4 *>(st + PLANE + a_off + bm * 32 * ROWB));
         }
 #pragma unroll
         for (int bn = 0; bn < 4; ++bn) {
-            const bf16x8 bh = as_bf16x8(xform(*reinterpret_cast<const u32x4 *>(st + 2 * PLANE + b_off + bn * 16 * PITCH)));
-            const bf16x8 bl = as_bf16x8(xform(*reinterpret_cast<const u32x4 *>(st + 3 * PLANE + b_off + bn * 16 * PITCH)));
+            const bf16x8 bh = as_bf16x8(xform(*reinterpret_cast<const u32x4 *>(st + 2 * PLANE + b_off + bn * 16 * ROWB)));
+            const bf16x8 bl = as_bf16x8(xform(*reinterpret_cast<const u32x4 *>(st + 3 * PLANE + b_off + bn * 16 * ROWB)));
 #pragma unroll
             for (int bm = 0; bm < 2; ++bm) {
                 acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bm], bh, acc[bm][bn], 0, 0, 0);
@@ -147,9 +153,33 @@ __global__ __launch_bounds__(256, 2) void cgemm_bf16x3_kernel(GemmArgsB g) {
                 acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bm], bh, acc[bm][bn], 0, 0, 0);
             }
         }
-        if (kt + 1 < nk) store(buf ^ 1);
-        __syncthreads();
+    };
+    // one ring step: stage kt (in `cur`) has landed once at most the loads of the two stages
+    // issued after it are outstanding; then the buffer of stage kt-1 (`nxt`) takes stage kt+3
+    auto step = [&](int kt, int nk, const unsigned char *cur, unsigned char *nxt) {
+        const int ahead = min(NSTAGE - 2, nk - 1 - kt);
+        if (ahead >= 2) wait_vm<8>();
+        else if (ahead == 1) wait_vm<4>();
+        else wait_vm<0>();
+        // Bare barrier: each wave has waited for its own DMA of stage kt above, so after the
+        // barrier the whole stage is in LDS, and every wave has finished reading stage kt-1.
+        // (A fenced barrier would drain all outstanding DMA and serialise the ring.)
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        if (kt + NSTAGE - 1 < nk) issue(nxt, kt + NSTAGE - 1);
+        compute(cur);
+    };
+
+    const int nk = g.K / BKC;   // a multiple of 16: K is padded to whole 128-tiles
+    issue(sm0, 0);
+    issue(sm1, 1);
+    issue(sm2, 2);
+    for (int kt = 0; kt < nk; kt += NSTAGE) {
+        step(kt + 0, nk, sm0, sm3);
+        step(kt + 1, nk, sm1, sm0);
+        step(kt + 2, nk, sm2, sm1);
+        step(kt + 3, nk, sm3, sm2);
     }
+    __syncthreads();   // the LDS ring is reused by the epilogue's reduction scratch only after all reads
 
     EpiArgs ea;
     ea.C = g.C + z * g.sC;
@@ -170,7 +200,7 @@ hipError_t launch_cgemm_bf16(int mode, const GemmArgsB &a0, int batch, hipStream
     a.tiles_m = a.M / BM;
     a.tiles_n = (mode == GM_LINE) ? a.N / (BN / 2) : a.N / BN;
     if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
-    if (a.M % BM || a.N % BN || a.K % BKC || a.K <= 0) return hipErrorInvalidValue;
+    if (a.M % BM || a.N % BN || a.K % (BKC * NSTAGE) || a.K <= 0) return hipErrorInvalidValue;
     const int64_t bytesA = (int64_t)a.M * a.lda * 4;
     const int64_t rowsB = (mode == GM_LINE) ? a.b2_rows + a.N : a.N;
     const int64_t bytesB = rowsB * a.ldb * 4;

@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 import synth
-from gpu_cases import U32, c64, from_geometry, from_workload, gradient_bound, residual_bound, to_device
+from gpu_cases import U32, c64, from_geometry, from_workload, gradient_bound, residual_bound, to_device  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -147,3 +147,43 @@ def test_bf16x3_forward_and_gradient_parity(tl, name, mk):
     print(f"{name} bf16x3: max g err/bound {np.max(gerr / gb):.3f}")
     assert np.all(gerr <= gb)
     assert abs(f.item() - fo) <= 5e-3 * fo and abs(fg.item() - fo) <= 5e-3 * fo
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_adjoint_solution(tl, prec):
+    case = from_geometry(12, 11, "half", 14.0, synth.uniform_layout(132, 40, 6, 7), 4, "adjoint")
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    X = tl.adjoint(plan, D, U, precision=tl.FP32 if prec == "fp32" else tl.BF16X3)
+    torch.cuda.synchronize()
+    ref = case.D.conj().T @ case.U
+    err = np.abs(X.cpu().numpy().astype(np.complex128) - ref)
+    aref = np.abs(case.D).T @ np.abs(case.U)
+    unit = U32 * np.sqrt(case.D.shape[0]) if prec == "fp32" else 2.0 ** -15 + U32 * np.sqrt(case.D.shape[0])
+    assert np.all(err <= 8 * unit * aref + 1e-30)
+
+
+def test_benchmark_solver_closed_form(tl):
+    """Preconditioned Tikhonov benchmark solver against its closed-form least-squares solution."""
+    rng = np.random.default_rng(31)
+    n, ns, lam = 12, 20, 0.05
+    D = c64((rng.standard_normal((ns, n)) + 1j * rng.standard_normal((ns, n))) / 4)
+    U = c64((rng.standard_normal((ns, n)) + 1j * rng.standard_normal((ns, n))) / 4)
+    cols = []
+    for q in range(n * n):
+        E = np.zeros(n * n, complex)
+        E[q] = 1
+        E = E.reshape(n, n)
+        cols.append((D @ (0.5 * (E + E.T))).ravel())
+    A = np.stack(cols, axis=1)
+    Aa = np.vstack([A, np.sqrt(2 * lam) * np.eye(n * n)])
+    z, *_ = np.linalg.lstsq(Aa, np.concatenate([U.ravel(), np.zeros(n * n)]), rcond=None)
+    Zs = z.reshape(n, n)
+    Xs = 0.5 * (Zs + Zs.T)
+    fstar = 0.5 * np.linalg.norm(A @ z - U.ravel()) ** 2 + lam * np.vdot(z, z).real
+    dev = torch.device("cuda")
+    Dg = torch.from_numpy(D.astype(np.complex64)).to(dev)
+    Ug = torch.from_numpy(U.astype(np.complex64)).to(dev)
+    X, fh = tl.benchmark_solve(Dg, Ug, lam, iters=150, lbfgs_m=10)
+    torch.cuda.synchronize()
+    assert fh[-1].item() == pytest.approx(fstar, rel=1e-5)
+    assert np.allclose(X.cpu().numpy(), Xs, atol=1e-4 * np.abs(Xs).max())

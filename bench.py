@@ -50,16 +50,28 @@ def build_inputs(wl, torch, tl, nfreq):
     return geom, Ds, Us, ths, plans
 
 
-def measured_traffic(nfreq, workload):
+TRAFFIC_RECORDS = {   # precision -> (committed counter summary, kernel sources it was measured on)
+    "fp32": ("cgemm_line_traffic.json", ("cgemm.hip", "gemm_common.hpp")),
+    "bf16x3": ("cgemm_bf16_line_traffic.json", ("cgemm_bf16.hip", "gemm_common.hpp")),
+}
+
+
+def source_sha(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_2412_14973_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(nfreq, workload, precision):
     """HBM bytes per launch of the line-search GEMM from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs (copy-calibrated), or None when the kernel
     source changed since the counters were taken or the workload differs."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "cgemm_line_traffic.json")
-    src = os.path.join(ROOT, "paper_2412_14973_amd", "csrc", "cgemm.hip")
+    name, files = TRAFFIC_RECORDS[precision]
     try:
-        rec = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        rec = json.load(open(os.path.join(ROOT, "profiles", name)))
+        sha = source_sha(files)
     except OSError:
         return None
     if rec.get("source_sha256") != sha or workload != "batched" or nfreq != 64:
@@ -347,7 +359,7 @@ def main():
                      + " ([a|b] = D [X1|X2])",
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic(nfreq, args.workload) if prec == tl.FP32 else None,
+                     "traffic": measured_traffic(nfreq, args.workload, args.precision),
                      "algorithmic_bytes": 6 * 8.0 * ns * nr * nfreq},
         "mfma_frac_all_gemms": gemm_flops / gemm_s / PEAK["f32"],
         "kernels": kernels,

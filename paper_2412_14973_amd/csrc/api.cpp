@@ -177,8 +177,10 @@ void append_problem(Tables &T, const HostLayout &H, int prob, int64_t x_off, int
     for (const TileDesc &td : H.tiles) T.tiles.push_back(td);
     for (int q = 0; q < (int)H.tiles.size(); ++q) {
         const TileDesc &td = H.tiles[q];
-        for (int r0 = 0; r0 < td.di; r0 += ASM_BR)
-            for (int c0 = 0; c0 < td.dj; c0 += ASM_BC) T.asm_items.push_back(AsmItem{tile_base + q, r0, c0, prob});
+        // Q Q^T tiles: blocks on and below the diagonal only (the kernel mirrors them)
+        for (int r0 = 0; r0 < td.di; r0 += ASM_B)
+            for (int c0 = 0; c0 < (td.kind == TILE_QQ ? r0 + 1 : td.dj); c0 += ASM_B)
+                T.asm_items.push_back(AsmItem{tile_base + q, r0, c0, prob});
         auto gi = [&](int kind, int a0, int b0) { T.grad_items.push_back(GradItem{tile_base + q, kind, a0, b0, prob, 0}); };
         if (td.kind == TILE_DENSE) {
             for (int a0 = 0; a0 < td.di; a0 += GZ_BR)

@@ -28,16 +28,15 @@ struct ProbOff {
     int64_t pad;
 };
 
-// Assembly work item: one 32 x 64 block of a tile (rows r0.., cols c0.. inside the tile).
+// Assembly work item: one 64 x 64 block of a tile (rows r0.., cols c0.. inside the tile).
 struct AsmItem {
     int32_t tile;   // index into the tile table
     int32_t r0;
     int32_t c0;
     int32_t prob;   // index into the ProbOff table
 };
-constexpr int ASM_BR = 32;
-constexpr int ASM_BC = 64;
-constexpr int ASM_KC = 32;
+constexpr int ASM_B = 64;    // assembly block edge (rows and columns of a tile block)
+constexpr int ASM_KC = 32;   // rank entries staged per step
 
 // Gradient work item.
 enum GradKind : int32_t { G_L = 0, G_Q = 1, G_R = 2, G_Z = 3 };

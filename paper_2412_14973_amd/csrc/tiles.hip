@@ -29,10 +29,6 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
 }
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 
-constexpr int SL_P = ASM_KC + 1;   // pitch of the row-factor stage
-constexpr int SR_P = ASM_BC + 1;   // pitch of the column-factor stage
-constexpr int ST_P = ASM_BR + 1;   // pitch of the transpose stage
-
 // Output: complex64 (OUTB = false) or split BF16 planes (OUTB = true, see launch_assemble).
 template <bool OUTB>
 __device__ __forceinline__ void put(float2 *X, int64_t o, int64_t low, float2 v) {
@@ -47,6 +43,15 @@ __device__ __forceinline__ void put(float2 *X, int64_t o, int64_t low, float2 v)
     }
 }
 
+constexpr int AB = ASM_B;            // block edge (rows and columns)
+constexpr int SL_P = ASM_KC + 1;     // row-factor stage [AB][SL_P]
+constexpr int SR_P = AB + 1;         // column-factor stage [ASM_KC][SR_P]
+constexpr int ST_P = AB + 1;         // transpose stage [AB][ST_P]
+constexpr int STAGE_F2 = AB * SL_P + ASM_KC * SR_P;
+
+// Each workgroup builds one 64 x 64 block of a tile; thread (ty, tx) = (t / 16, t % 16) owns
+// rows ty + 16 i and columns tx + 16 j (i, j < 4): a 4 x 4 register block, so every complex
+// value read from LDS feeds 4 (12 in the directional form) complex multiply-adds.
 template <bool DIR, bool OUTB>
 __global__ __launch_bounds__(256) void assemble_kernel(const TileDesc *__restrict__ tiles,
                                                        const AsmItem *__restrict__ items,
@@ -56,11 +61,12 @@ __global__ __launch_bounds__(256) void assemble_kernel(const TileDesc *__restric
                                                        float2 *__restrict__ X_base,
                                                        float2 *__restrict__ X2_base,
                                                        int64_t x2w, int64_t low) {
-    // stage buffers: [row factor][col factor] (x2 for the directional form), reused for the transpose
     constexpr int NSTAGE = DIR ? 2 : 1;
-    __shared__ float2 sL[NSTAGE][ASM_BR * SL_P];
-    __shared__ float2 sR[NSTAGE][ASM_KC * SR_P];
-    __shared__ float2 sT[ASM_BC * ST_P];
+    constexpr int SM_F2 = (NSTAGE * STAGE_F2 > AB * ST_P) ? NSTAGE * STAGE_F2 : AB * ST_P;
+    __shared__ float2 smem[SM_F2];
+    float2 *sL = smem;                               // [NSTAGE][AB][SL_P]
+    float2 *sR = smem + NSTAGE * AB * SL_P;          // [NSTAGE][ASM_KC][SR_P]
+    float2 *sT = smem;                               // transpose stage, reused after the k loop
 
     const AsmItem it = items[blockIdx.x];
     const TileDesc td = tiles[it.tile];
@@ -75,37 +81,40 @@ __global__ __launch_bounds__(256) void assemble_kernel(const TileDesc *__restric
     const int64_t ldx = po.ldx;
 
     const int t = threadIdx.x;
-    const int col = t & 63;
-    const int rg = t >> 6;
+    const int tx = t & 15, ty = t >> 4;
     const int r0 = it.r0, c0 = it.c0;
-    const int nrow = min(ASM_BR, td.di - r0);
-    const int ncol = min(ASM_BC, td.dj - c0);
+    const int nrow = min(AB, td.di - r0);
+    const int ncol = min(AB, td.dj - c0);
 
-    float2 acc[8], acc2[8];
+    float2 acc[4][4], acc2[4][4];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) { acc[i] = make_float2(0.f, 0.f); acc2[i] = acc[i]; }
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { acc[i][j] = make_float2(0.f, 0.f); acc2[i][j] = acc[i][j]; }
 
     if (td.kind == TILE_DENSE) {
         // X = (Z + Z^T)/2 ; X1 = (P + P^T)/2 ; X2 = 0
         const float2 *Z = DIR ? pv + td.offA : theta + td.offA;
         const int d = td.di;
-        // transposed block Z[c0+cc][r0+rr] through LDS
-        for (int e = t; e < ASM_BC * ASM_BR; e += 256) {
-            const int cc = e >> 5, rr = e & 31;
+        for (int e = t; e < AB * AB; e += 256) {   // transposed block Z[c0+cc][r0+rr]
+            const int cc = e >> 6, rr = e & 63;
             float2 v = make_float2(0.f, 0.f);
             if (cc < ncol && rr < nrow) v = Z[(int64_t)(c0 + cc) * d + r0 + rr];
             sT[cc * ST_P + rr] = v;
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int rr = rg * 8 + i;
-            if (rr < nrow && col < ncol) {
-                const float2 zd = Z[(int64_t)(r0 + rr) * d + c0 + col];
-                const float2 zt = sT[col * ST_P + rr];
-                acc[i] = make_float2(0.5f * (zd.x + zt.x), 0.5f * (zd.y + zt.y));
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int rr = ty + 16 * i, cc = tx + 16 * j;
+                if (rr < nrow && cc < ncol) {
+                    const float2 zd = Z[(int64_t)(r0 + rr) * d + c0 + cc];
+                    const float2 zt = sT[cc * ST_P + rr];
+                    acc[i][j] = make_float2(0.5f * (zd.x + zt.x), 0.5f * (zd.y + zt.y));
+                }
             }
-        }
+        __syncthreads();
     } else {
         const bool qq = (td.kind == TILE_QQ);
         const int k = td.k;
@@ -115,82 +124,79 @@ __global__ __launch_bounds__(256) void assemble_kernel(const TileDesc *__restric
         const float2 *PRf = DIR ? (qq ? PLf : pv + td.offB) : nullptr;
         for (int kc0 = 0; kc0 < k; kc0 += ASM_KC) {
             const int kn = min(ASM_KC, k - kc0);
-            // row factor rows r0.. : [rr][kk]
-            for (int e = t; e < ASM_BR * ASM_KC; e += 256) {
+            for (int e = t; e < AB * ASM_KC; e += 256) {    // row factor rows r0.. : [rr][kk]
                 const int rr = e >> 5, kk = e & 31;
                 const bool ok = rr < nrow && kk < kn;
                 const int64_t o = (int64_t)(r0 + rr) * k + kc0 + kk;
-                sL[0][rr * SL_P + kk] = ok ? Lf[o] : make_float2(0.f, 0.f);
-                if (DIR) sL[NSTAGE - 1][rr * SL_P + kk] = ok ? PLf[o] : make_float2(0.f, 0.f);
+                sL[rr * SL_P + kk] = ok ? Lf[o] : make_float2(0.f, 0.f);
+                if (DIR) sL[AB * SL_P + rr * SL_P + kk] = ok ? PLf[o] : make_float2(0.f, 0.f);
             }
-            // column factor: R[kc0+kk][c0+cc]  or  Q[c0+cc][kc0+kk]
-            for (int e = t; e < ASM_KC * ASM_BC; e += 256) {
+            for (int e = t; e < ASM_KC * AB; e += 256) {    // column factor R[kc0+kk][c0+cc] or Q[c0+cc][kc0+kk]
                 int kk, cc;
                 int64_t o;
                 if (qq) { cc = e >> 5; kk = e & 31; o = (int64_t)(c0 + cc) * k + kc0 + kk; }
                 else { kk = e >> 6; cc = e & 63; o = (int64_t)(kc0 + kk) * td.dj + c0 + cc; }
                 const bool ok = cc < ncol && kk < kn;
-                sR[0][kk * SR_P + cc] = ok ? Rf[o] : make_float2(0.f, 0.f);
-                if (DIR) sR[NSTAGE - 1][kk * SR_P + cc] = ok ? PRf[o] : make_float2(0.f, 0.f);
+                sR[kk * SR_P + cc] = ok ? Rf[o] : make_float2(0.f, 0.f);
+                if (DIR) sR[ASM_KC * SR_P + kk * SR_P + cc] = ok ? PRf[o] : make_float2(0.f, 0.f);
             }
             __syncthreads();
+#pragma unroll 2
             for (int kk = 0; kk < kn; ++kk) {
-                const float2 rv = sR[0][kk * SR_P + col];
-                const float2 prv = DIR ? sR[NSTAGE - 1][kk * SR_P + col] : rv;
+                float2 lv[4], rv[4], plv[4], prv[4];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int rr = rg * 8 + i;
-                    const float2 lv = sL[0][rr * SL_P + kk];
-                    if (!qq) {
-                        if (!DIR) {
-                            acc[i] = cadd(acc[i], cmul(lv, rv));
-                        } else {
-                            const float2 plv = sL[NSTAGE - 1][rr * SL_P + kk];
-                            acc[i] = cadd(acc[i], cadd(cmul(plv, rv), cmul(lv, prv)));
-                            acc2[i] = cadd(acc2[i], cmul(plv, prv));
-                        }
-                    } else {
-                        // operands ordered by (max(a,b), min(a,b)) for bitwise symmetry
-                        const bool lo_first = (r0 + rr) >= (c0 + col);
-                        const float2 qh = lo_first ? lv : rv;
-                        const float2 ql = lo_first ? rv : lv;
-                        if (!DIR) {
-                            acc[i] = cadd(acc[i], cmul(qh, ql));
-                        } else {
-                            const float2 plv = sL[NSTAGE - 1][rr * SL_P + kk];
-                            const float2 ph = lo_first ? plv : prv;
-                            const float2 pl = lo_first ? prv : plv;
-                            acc[i] = cadd(acc[i], cadd(cmul(ph, ql), cmul(qh, pl)));
-                            acc2[i] = cadd(acc2[i], cmul(ph, pl));
-                        }
+                for (int i = 0; i < 4; ++i) {
+                    lv[i] = sL[(ty + 16 * i) * SL_P + kk];
+                    rv[i] = sR[kk * SR_P + tx + 16 * i];
+                    if (DIR) {
+                        plv[i] = sL[AB * SL_P + (ty + 16 * i) * SL_P + kk];
+                        prv[i] = sR[ASM_KC * SR_P + kk * SR_P + tx + 16 * i];
                     }
                 }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if (!DIR) {
+                            acc[i][j] = cadd(acc[i][j], cmul(lv[i], rv[j]));
+                        } else {
+                            acc[i][j] = cadd(acc[i][j], cadd(cmul(plv[i], rv[j]), cmul(lv[i], prv[j])));
+                            acc2[i][j] = cadd(acc2[i][j], cmul(plv[i], prv[j]));
+                        }
+                    }
             }
             __syncthreads();
         }
     }
 
-    // direct block
+    // Q Q^T tiles are built on and below the block diagonal only and mirrored, so the tile is
+    // symmetric bit for bit: direct write where row >= column, transposed write where row > column
+    const bool qq = td.kind == TILE_QQ;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int rr = rg * 8 + i;
-        if (rr < nrow && col < ncol) {
-            const int64_t o = (td.row0 + r0 + rr) * ldx + td.col0 + c0 + col;
-            put<OUTB>(X, o, low, acc[i]);
-            if (DIR) put<OUTB>(X2, o, low, acc2[i]);
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int rr = ty + 16 * i, cc = tx + 16 * j;
+            if (rr < nrow && cc < ncol && (!qq || r0 + rr >= c0 + cc)) {
+                const int64_t o = (td.row0 + r0 + rr) * ldx + td.col0 + c0 + cc;
+                put<OUTB>(X, o, low, acc[i][j]);
+                if (DIR) put<OUTB>(X2, o, low, acc2[i][j]);
+            }
         }
-    }
-    if (td.kind != TILE_LR) return;
+    if (td.kind == TILE_DENSE) return;
     // transposed block X_ji = X_ij^T, staged through LDS for coalesced rows
     for (int pass = 0; pass < (DIR ? 2 : 1); ++pass) {
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 8; ++i) sT[col * ST_P + rg * 8 + i] = (pass == 0) ? acc[i] : acc2[i];
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                sT[(tx + 16 * j) * ST_P + ty + 16 * i] = (pass == 0) ? acc[i][j] : acc2[i][j];
         __syncthreads();
         float2 *dst = (pass == 0) ? X : X2;
-        for (int e = t; e < ASM_BC * ASM_BR; e += 256) {
-            const int cc = e >> 5, rr = e & 31;
-            if (cc < ncol && rr < nrow)
+        for (int e = t; e < AB * AB; e += 256) {
+            const int cc = e >> 6, rr = e & 63;
+            if (cc < ncol && rr < nrow && (!qq || r0 + rr > c0 + cc))
                 put<OUTB>(dst, (td.col0 + c0 + cc) * ldx + td.row0 + r0 + rr, low, sT[cc * ST_P + rr]);
         }
     }

@@ -181,7 +181,10 @@ void append_problem(Tables &T, const HostLayout &H, int prob, int64_t x_off, int
         for (int r0 = 0; r0 < td.di; r0 += ASM_B)
             for (int c0 = 0; c0 < (td.kind == TILE_QQ ? r0 + 1 : td.dj); c0 += ASM_B)
                 T.asm_items.push_back(AsmItem{tile_base + q, r0, c0, prob});
-        auto gi = [&](int kind, int a0, int b0) { T.grad_items.push_back(GradItem{tile_base + q, kind, a0, b0, prob, 0}); };
+        auto gi = [&](int kind, int a0, int b0) {
+            const int kq = kind == G_Z ? 0 : (std::min(GR_KK, td.k - b0) + 15) / 16;
+            T.grad_items.push_back(GradItem{tile_base + q, kind, a0, b0, prob, kq});
+        };
         if (td.kind == TILE_DENSE) {
             for (int a0 = 0; a0 < td.di; a0 += GZ_BR)
                 for (int b0 = 0; b0 < td.dj; b0 += GZ_BC) gi(G_Z, a0, b0);

@@ -46,11 +46,11 @@ struct GradItem {
     int32_t a0;     // G_L/G_Q: first row; G_R: first col; G_Z: first row
     int32_t b0;     // G_L/G_Q/G_R: first rank index; G_Z: first col
     int32_t prob;
-    int32_t pad;
+    int32_t kq;     // G_L/G_Q/G_R: rank entries in the item, in units of 16 (1..4)
 };
-constexpr int GR_ROWS = 32;   // rows (G_L/G_Q) or cols (G_R) per item
-constexpr int GR_KK = 32;     // rank entries per item
-constexpr int GR_CH = 64;     // contraction chunk
+constexpr int GR_ROWS = 64;   // rows (G_L/G_Q) or cols (G_R) per item
+constexpr int GR_KK = 64;     // rank entries per item (at most)
+constexpr int GR_CH = 32;     // contraction chunk
 constexpr int GZ_BR = 32, GZ_BC = 64;
 
 // ---- complex GEMM on MFMA ----

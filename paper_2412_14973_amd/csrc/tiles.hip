@@ -202,8 +202,109 @@ __global__ __launch_bounds__(256) void assemble_kernel(const TileDesc *__restric
     }
 }
 
-constexpr int GW_P = GR_CH + 1;
-constexpr int GF_P = GR_CH + 1;
+constexpr int GW_P = GR_CH + 1;        // sW [GR_ROWS][GW_P]: W' with the contraction index fastest
+constexpr int GF_P = GR_KK + 1;        // sF [GR_CH][GF_P]: conjugated factor, rank index fastest
+
+// One gradient item: a 64 x (16 KQ) block of G = W' conj(F) where
+//   G_L: rows of the tile, F[c][kk] = R[kk][c]    (G_L = W' R^H, contraction over tile columns)
+//   G_Q: rows of the tile, F[c][kk] = Q[c][kk]    (G_Q = (W + W^T) conj(Q))
+//   G_R: cols of the tile, F[r][kk] = L[r][kk]    (G_R^T = W'^T conj(L), contraction over tile rows)
+// with W' = W_ij + W_ji^T built in LDS chunk by chunk. Thread (ty, tx) owns out-rows ty + 16 i
+// (i < 4) and rank entries tx + 16 j (j < KQ).
+template <int KQ>
+__device__ __forceinline__ void grad_block(const GradItem &it, const TileDesc &td, const float2 *__restrict__ W,
+                                           int64_t ldw, const float2 *__restrict__ theta, float2 *__restrict__ g,
+                                           float2 *sW, float2 *sF) {
+    const int t = threadIdx.x;
+    const int tx = t & 15, ty = t >> 4;
+    const int k = td.k;
+    const int a0 = it.a0, b0 = it.b0;
+    const int kn = min(16 * KQ, k - b0);
+    const bool colside = it.kind == G_R;
+    const int nout = min(GR_ROWS, (colside ? td.dj : td.di) - a0);   // out-rows in this item
+    const int ncon = colside ? td.di : td.dj;                        // contraction length
+    const float2 *F = it.kind == G_L ? theta + td.offB : theta + td.offA;
+
+    float2 acc[4][KQ];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < KQ; ++j) acc[i][j] = make_float2(0.f, 0.f);
+
+    for (int c0 = 0; c0 < ncon; c0 += GR_CH) {
+        const int cn = min(GR_CH, ncon - c0);
+        if (!colside) {
+            // sW[rr][cc] = W_ij[a0+rr][c0+cc] + W_ji[c0+cc][a0+rr]
+            for (int e = t; e < GR_ROWS * GR_CH; e += 256) {
+                const int rr = e >> 5, cc = e & 31;
+                float2 v = make_float2(0.f, 0.f);
+                if (rr < nout && cc < cn) v = W[(td.row0 + a0 + rr) * ldw + td.col0 + c0 + cc];
+                sW[rr * GW_P + cc] = v;
+            }
+        } else {
+            // sW[cc][rr] = W_ij[c0+rr][a0+cc] + W_ji[a0+cc][c0+rr]   (out-row cc is a tile column)
+            for (int e = t; e < GR_CH * GR_ROWS; e += 256) {
+                const int rr = e >> 6, cc = e & 63;
+                float2 v = make_float2(0.f, 0.f);
+                if (cc < nout && rr < cn) v = W[(td.row0 + c0 + rr) * ldw + td.col0 + a0 + cc];
+                sW[cc * GW_P + rr] = v;
+            }
+        }
+        for (int e = t; e < GR_CH * 16 * KQ; e += 256) {
+            const int cc = e / (16 * KQ), kk = e % (16 * KQ);
+            float2 v = make_float2(0.f, 0.f);
+            if (cc < cn && kk < kn) {
+                const int64_t o = it.kind == G_L ? (int64_t)(b0 + kk) * td.dj + c0 + cc
+                                                 : (int64_t)(c0 + cc) * k + b0 + kk;
+                v = F[o];
+            }
+            sF[cc * GF_P + kk] = v;
+        }
+        __syncthreads();
+        if (!colside) {
+            for (int e = t; e < GR_CH * GR_ROWS; e += 256) {
+                const int cc = e >> 6, rr = e & 63;
+                if (rr < nout && cc < cn) {
+                    const float2 wt = W[(td.col0 + c0 + cc) * ldw + td.row0 + a0 + rr];
+                    sW[rr * GW_P + cc] = cadd(sW[rr * GW_P + cc], wt);
+                }
+            }
+        } else {
+            for (int e = t; e < GR_ROWS * GR_CH; e += 256) {
+                const int cc = e >> 5, rr = e & 31;
+                if (cc < nout && rr < cn) {
+                    const float2 wt = W[(td.col0 + a0 + cc) * ldw + td.row0 + c0 + rr];
+                    sW[cc * GW_P + rr] = cadd(sW[cc * GW_P + rr], wt);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int cc = 0; cc < cn; ++cc) {
+            float2 w[4], f[KQ];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) w[i] = sW[(ty + 16 * i) * GW_P + cc];
+#pragma unroll
+            for (int j = 0; j < KQ; ++j) f[j] = sF[cc * GF_P + tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < KQ; ++j) acc[i][j] = cadd(acc[i][j], cmulc(w[i], f[j]));
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < KQ; ++j) {
+            const int rr = ty + 16 * i, kk = tx + 16 * j;
+            if (rr < nout && kk < kn) {
+                // grad L / grad Q at the factor's own offset; grad R = L^H W' has the entries of acc
+                if (!colside) g[td.offA + (int64_t)(a0 + rr) * k + b0 + kk] = acc[i][j];
+                else g[td.offB + (int64_t)(b0 + kk) * td.dj + a0 + rr] = acc[i][j];
+            }
+        }
+}
 
 __global__ __launch_bounds__(256) void grad_kernel(const TileDesc *__restrict__ tiles,
                                                    const GradItem *__restrict__ items,
@@ -211,8 +312,8 @@ __global__ __launch_bounds__(256) void grad_kernel(const TileDesc *__restrict__ 
                                                    const float2 *__restrict__ W_base,
                                                    const float2 *__restrict__ theta_base,
                                                    float2 *__restrict__ g_base) {
-    __shared__ float2 sW[GR_CH * GW_P];   // 32 x 65 (G_L/G_Q) or 64 x 33 (G_R) or 32 x 65 (G_Z)
-    __shared__ float2 sF[GR_CH * (GR_KK + 1)];   // factor chunk: 32 x 65 (G_L/G_Q) or 64 x 33 (G_R)
+    __shared__ float2 sW[GR_ROWS * GW_P];
+    __shared__ float2 sF[GR_CH * GF_P];
     const GradItem it = items[blockIdx.x];
     const TileDesc td = tiles[it.tile];
     const ProbOff po = probs[it.prob];
@@ -245,111 +346,11 @@ __global__ __launch_bounds__(256) void grad_kernel(const TileDesc *__restrict__ 
         }
         return;
     }
-
-    const int k = td.k;
-    const int b0 = it.b0;
-    const int kn = min(GR_KK, k - b0);
-    float2 acc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = make_float2(0.f, 0.f);
-
-    if (it.kind == G_L || it.kind == G_Q) {
-        // grad[r][kk] = sum_c W'[r][c] conj(F[kk][c]);  F = R (k x dj) or Q^T
-        const int a0 = it.a0;
-        const int nrow = min(GR_ROWS, td.di - a0);
-        const int ncols = td.dj;
-        const float2 *F = (it.kind == G_L) ? theta + td.offB : theta + td.offA;
-        const int r = t >> 3, kq = (t & 7) * 4;
-        for (int c0 = 0; c0 < ncols; c0 += GR_CH) {
-            const int cn = min(GR_CH, ncols - c0);
-            for (int e = t; e < GR_ROWS * GR_CH; e += 256) {
-                const int rr = e >> 6, cc = e & 63;
-                float2 v = make_float2(0.f, 0.f);
-                if (rr < nrow && cc < cn) v = W[(td.row0 + a0 + rr) * ldw + td.col0 + c0 + cc];
-                sW[rr * GW_P + cc] = v;
-            }
-            for (int e = t; e < GR_KK * GR_CH; e += 256) {
-                int kk, cc;
-                int64_t o;
-                if (it.kind == G_L) { kk = e >> 6; cc = e & 63; o = (int64_t)(b0 + kk) * ncols + c0 + cc; }
-                else { cc = e >> 5; kk = e & 31; o = (int64_t)(c0 + cc) * k + b0 + kk; }
-                sF[kk * GF_P + cc] = (kk < kn && cc < cn) ? F[o] : make_float2(0.f, 0.f);
-            }
-            __syncthreads();
-            for (int e = t; e < GR_CH * GR_ROWS; e += 256) {
-                const int cc = e >> 5, rr = e & 31;
-                if (rr < nrow && cc < cn) {
-                    const float2 wt = W[(td.col0 + c0 + cc) * ldw + td.row0 + a0 + rr];
-                    sW[rr * GW_P + cc] = cadd(sW[rr * GW_P + cc], wt);
-                }
-            }
-            __syncthreads();
-            for (int cc = 0; cc < cn; ++cc) {
-                const float2 w = sW[r * GW_P + cc];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = cadd(acc[q], cmulc(w, sF[(kq + q) * GF_P + cc]));
-            }
-            __syncthreads();
-        }
-        if (r < nrow) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int kk = kq + q;
-                if (kk < kn) {
-                    // grad L (di x k) sits at the offset of L, grad Q (d x k) at that of Q
-                    g[td.offA + (int64_t)(a0 + r) * k + b0 + kk] = acc[q];
-                }
-            }
-        }
-        return;
-    }
-
-    // G_R: grad R[kk][c] = sum_r conj(L[r][kk]) W'[r][c], columns a0.. of tile j
-    {
-        const int a0 = it.a0;
-        const int ncol = min(GR_ROWS, td.dj - a0);
-        const int nrows = td.di;
-        const float2 *L = theta + td.offA;
-        const int c = t >> 3, kq = (t & 7) * 4;
-        constexpr int WP = GR_ROWS + 1;  // sW as [r][c] 64 x 33
-        constexpr int LP = GR_KK + 1;    // sF as [r][kk] 64 x 33
-        for (int q0 = 0; q0 < nrows; q0 += GR_CH) {
-            const int rn = min(GR_CH, nrows - q0);
-            for (int e = t; e < GR_CH * GR_ROWS; e += 256) {
-                const int rr = e >> 5, cc = e & 31;
-                float2 v = make_float2(0.f, 0.f);
-                if (rr < rn && cc < ncol) v = W[(td.row0 + q0 + rr) * ldw + td.col0 + a0 + cc];
-                sW[rr * WP + cc] = v;
-            }
-            for (int e = t; e < GR_CH * GR_KK; e += 256) {
-                const int rr = e >> 5, kk = e & 31;
-                sF[rr * LP + kk] = (rr < rn && kk < kn) ? L[(int64_t)(q0 + rr) * k + b0 + kk]
-                                                        : make_float2(0.f, 0.f);
-            }
-            __syncthreads();
-            for (int e = t; e < GR_ROWS * GR_CH; e += 256) {
-                const int cc = e >> 6, rr = e & 63;
-                if (rr < rn && cc < ncol) {
-                    const float2 wt = W[(td.col0 + a0 + cc) * ldw + td.row0 + q0 + rr];
-                    sW[rr * WP + cc] = cadd(sW[rr * WP + cc], wt);
-                }
-            }
-            __syncthreads();
-            for (int rr = 0; rr < rn; ++rr) {
-                const float2 w = sW[rr * WP + c];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = cadd(acc[q], cmulc(w, sF[rr * LP + kq + q]));
-            }
-            __syncthreads();
-        }
-        // acc = sum W' conj(L) -> grad R = L^H W' has exactly these entries
-        if (c < ncol) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int kk = kq + q;
-                if (kk < kn) g[td.offB + (int64_t)(b0 + kk) * td.dj + a0 + c] = acc[q];
-            }
-        }
+    switch (it.kq) {
+    case 1: grad_block<1>(it, td, W, ldw, theta, g, sW, sF); break;
+    case 2: grad_block<2>(it, td, W, ldw, theta, g, sW, sF); break;
+    case 3: grad_block<3>(it, td, W, ldw, theta, g, sW, sF); break;
+    default: grad_block<4>(it, td, W, ldw, theta, g, sW, sF); break;
     }
 }
 

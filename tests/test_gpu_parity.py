@@ -36,6 +36,9 @@ def _cases():
                                              2, "multi_tile", scale_theta=2.0)),
         ("dense_diag", lambda: from_geometry(12, 11, "full", 9.0, synth.uniform_layout(132, 40, 6, -1),
                                              3, "dense_diag", scale_theta=2.0)),
+        # ranks above one 64-entry gradient item and one 32-entry assembly stage; ragged 32-wide last tile
+        ("high_rank", lambda: from_geometry(18, 16, "half", 27.0, synth.uniform_layout(288, 128, 70, 50),
+                                            4, "high_rank")),
     ]
 
 

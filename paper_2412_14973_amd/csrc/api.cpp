@@ -172,6 +172,9 @@ struct Tables {
     int64_t theta_total = 0;        // complex elements over all problems
 };
 
+// each problem's theta starts on a 16-byte boundary (vector kernels move 4 floats at a time)
+int64_t theta_span(int64_t theta_size) { return (theta_size + 1) & ~int64_t(1); }
+
 void append_problem(Tables &T, const HostLayout &H, int prob, int64_t x_off, int64_t ldk) {
     const int tile_base = (int)T.tiles.size();
     for (const TileDesc &td : H.tiles) T.tiles.push_back(td);
@@ -203,7 +206,7 @@ void append_problem(Tables &T, const HostLayout &H, int prob, int64_t x_off, int
     po.x = x_off;
     po.ldx = ldk;
     T.probs.push_back(po);
-    T.theta_total += H.theta_size;
+    T.theta_total += theta_span(H.theta_size);
 }
 
 // segments: called after all problems are appended; residual space is nsp x ldk per problem
@@ -326,12 +329,16 @@ int partial_stride(const Tables &T, int64_t nrp, int64_t nsp) {
 struct Ws {
     float2 *Ds = nullptr, *DHs = nullptr, *Us = nullptr, *XW = nullptr, *r = nullptr, *a = nullptr, *b = nullptr;
     uint32_t *rT = nullptr;   // BF16 split planes of r^T (hi, lo), ldk x lds each
-    float *th = nullptr, *g0 = nullptr, *g1 = nullptr, *q = nullptr, *p = nullptr, *S = nullptr, *Y = nullptr;
+    float *th = nullptr, *g0 = nullptr, *g1 = nullptr, *p = nullptr, *S = nullptr, *Y = nullptr;
+    double *gram = nullptr;   // per problem: Gram matrix of the L-BFGS basis and direction coefficients
     double *partials = nullptr;
     SolveScalars *sc = nullptr;
     char *tables = nullptr;
     size_t bytes = 0;
 };
+
+// doubles per problem for the L-BFGS Gram matrix over (s_j, y_j, g) and the direction coefficients
+int64_t gram_stride(int m1) { return (int64_t)(2 * m1 + 1) * (2 * m1 + 1) + 2 * m1 + 1; }
 
 // op: 0 forward, 1 grad, 2 solve. Sizes for `nprob` problems of the same shape; every matrix is
 // padded to whole GEMM tiles: ns x nr operands are lds x ldk (rows x cols), nr x nr ones ldk x ldk.
@@ -360,12 +367,12 @@ Ws carve(char *base, int op, int nprob, int64_t ldk, int64_t lds, int64_t theta_
         w.th = (float *)take(tz);
         w.g0 = (float *)take(tz);
         w.g1 = (float *)take(tz);
-        w.q = (float *)take(tz);
         w.p = (float *)take(tz);
         w.S = (float *)take(tz * m1);
         w.Y = (float *)take(tz * m1);
+        w.gram = (double *)take((size_t)nprob * gram_stride(m1) * sizeof(double));
     }
-    w.partials = (double *)take((size_t)nprob * pstride * 5 * sizeof(double));
+    w.partials = (double *)take((size_t)nprob * pstride * std::max(5, 6 * m1) * sizeof(double));
     w.sc = (SolveScalars *)take((size_t)nprob * sizeof(SolveScalars));
     w.tables = take(tbytes);
     w.bytes = o;
@@ -472,7 +479,7 @@ int tlrmdd_plan_destroy(tlrmdd_plan plan) {
 static size_t ws_bytes_single(const tlrmdd_plan P, int op, int m1) {
     const Tables &T = P->T;
     const int ps = partial_stride(T, P->ldk, P->lds);
-    return carve(nullptr, op, 1, P->ldk, P->lds, P->H.theta_size, m1, ps, 0).bytes;
+    return carve(nullptr, op, 1, P->ldk, P->lds, theta_span(P->H.theta_size), m1, ps, 0).bytes;
 }
 
 int tlrmdd_workspace_bytes(tlrmdd_plan plan, int op, const tlrmdd_opts *opts, size_t *bytes) {
@@ -747,41 +754,19 @@ int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const 
         HIP_TRY(timed(TLRMDD_K_GRAD, s, [&] { return launch_grad(c.D.tiles, c.D.grad_items, c.D.n_grad, c.D.probs, X1, (const float2 *)c.w.th,
                             (float2 *)gcur, s); }));
         if (lam != 0.0) HIP_TRY(launch_reg_grad(c.D.tsegs, nt, gcur, c.w.th, (float)(2.0 * lam), s));
-        // direction
-        if (!lbfgs) {
-            HIP_TRY(launch_restart(c.D.tsegs, nt, 1, c.w.p, gcur, c.w.sc, s));
+        // direction: steepest descent first, then L-BFGS in vector-free form (Gram pass, two-loop
+        // recursion on the (2 m + 1)-term coefficient vectors on the device, one combination pass)
+        if (!lbfgs || t == 0) {
+            HIP_TRY(launch_negate(c.D.tsegs, nt, c.w.p, gcur, s));
         } else {
-            if (t > 0) {
-                HIP_TRY(launch_pair(c.D.tsegs, nt, gcur, gprev, c.w.Y, c.w.S, stride2, c.w.sc, c.w.partials, s));
-                FinArgs f = fin_args(FIN_PAIR, c.w.sc);
-                f.m1 = m1;
-                if ((st = fin(c, f, c.D.tcount, 0, 2))) return st;
-            }
-            const int L = std::min(t, m);
-            for (int i = 0; i <= L; ++i) {
-                HIP_TRY(launch_twoloop1(c.D.tsegs, nt, i, m1, c.w.q, gcur, c.w.S, c.w.Y, stride2, c.w.sc,
-                                        c.w.partials, s));
-                if (i < L) {
-                    FinArgs f = fin_args(FIN_ALPHA, c.w.sc);
-                    f.m1 = m1;
-                    f.i = i;
-                    if ((st = fin(c, f, c.D.tcount, 0, 1))) return st;
-                }
-            }
-            HIP_TRY(launch_twoloop2(c.D.tsegs, nt, 1, L == 0 ? 1 : 0, -1, L - 1, m1, c.w.q, c.w.q, c.w.p, gcur,
-                                    c.w.S, c.w.Y, stride2, c.w.sc, c.w.partials, s));
-            for (int i = L - 1; i >= 0; --i) {
-                FinArgs f = fin_args(FIN_BETA, c.w.sc);
-                f.m1 = m1;
-                f.i = i;
-                if ((st = fin(c, f, c.D.tcount, 0, 1))) return st;
-                HIP_TRY(launch_twoloop2(c.D.tsegs, nt, 0, i == 0 ? 1 : 0, i, i - 1, m1, c.w.q, c.w.q, c.w.p,
-                                        gcur, c.w.S, c.w.Y, stride2, c.w.sc, c.w.partials, s));
-            }
-            FinArgs f = fin_args(FIN_GP, c.w.sc);
+            HIP_TRY(launch_gram(c.D.tsegs, nt, m1, gcur, gprev, c.w.Y, c.w.S, stride2, c.w.sc, c.w.partials, s));
+            FinArgs f = fin_args(FIN_GRAM, c.w.sc);
             f.m1 = m1;
-            if ((st = fin(c, f, c.D.tcount, 0, 1))) return st;
-            HIP_TRY(launch_restart(c.D.tsegs, nt, 0, c.w.p, gcur, c.w.sc, s));
+            f.gram = c.w.gram;
+            f.gstride = gram_stride(m1);
+            if ((st = fin(c, f, c.D.tcount, 0, 6 * m1))) return st;
+            HIP_TRY(launch_combine(c.D.tsegs, nt, m1, c.w.p, gcur, c.w.S, c.w.Y, stride2, c.w.sc,
+                                   c.w.gram + (2 * m1 + 1) * (2 * m1 + 1), gram_stride(m1), s));
         }
         // exact line search: a = D C1(theta;p), b = D C2(p)
         if ((st = clear_plane_padding())) return st;
@@ -842,7 +827,7 @@ int tlrmdd_forward(tlrmdd_plan plan, const void *D, const void *U, const void *t
     c.lds = plan->lds;
     c.s = stream;
     c.pstride = partial_stride(plan->T, c.ldk, c.lds);
-    c.w = carve((char *)workspace, 0, 1, c.ldk, c.lds, plan->H.theta_size, 1, c.pstride, 0);
+    c.w = carve((char *)workspace, 0, 1, c.ldk, c.lds, theta_span(plan->H.theta_size), 1, c.pstride, 0);
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     c.D = plan->D;
     c.bf16 = precision == TLRMDD_BF16X3;
@@ -880,7 +865,7 @@ int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *thet
     c.lds = plan->lds;
     c.s = stream;
     c.pstride = partial_stride(plan->T, c.ldk, c.lds);
-    c.w = carve((char *)workspace, 1, 1, c.ldk, c.lds, plan->H.theta_size, 1, c.pstride, 0);
+    c.w = carve((char *)workspace, 1, 1, c.ldk, c.lds, theta_span(plan->H.theta_size), 1, c.pstride, 0);
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     c.D = plan->D;
     c.bf16 = precision == TLRMDD_BF16X3;
@@ -917,7 +902,7 @@ int tlrmdd_adjoint(tlrmdd_plan plan, const void *D, const void *U, void *X_out, 
     c.lds = plan->lds;
     c.s = stream;
     c.pstride = partial_stride(plan->T, c.ldk, c.lds);
-    c.w = carve((char *)workspace, 1, 1, c.ldk, c.lds, plan->H.theta_size, 1, c.pstride, 0);
+    c.w = carve((char *)workspace, 1, 1, c.ldk, c.lds, theta_span(plan->H.theta_size), 1, c.pstride, 0);
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     c.D = plan->D;
     c.bf16 = precision == TLRMDD_BF16X3;

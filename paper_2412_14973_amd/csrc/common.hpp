@@ -122,7 +122,6 @@ struct SolveScalars {
     double thnorm2;              // ||theta||^2 after update (lambda term of f)
     double rho[MAX_LBFGS_M + 1];
     double alpha[MAX_LBFGS_M];
-    double beta_coef;
     int32_t head, count, restart, frozen;
 };
 

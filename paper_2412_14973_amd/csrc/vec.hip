@@ -142,132 +142,176 @@ __device__ __forceinline__ int ring_slot(const SolveScalars &sc, int i, int m1) 
     return s;
 }
 
-// y = g_new - g_prev (into Y[head]); partials: Re<s, y>, Re<y, y>
-__global__ __launch_bounds__(256) void pair_kernel(const VecSeg *__restrict__ segs, const float *__restrict__ gnew,
-                                                   const float *__restrict__ gprev, float *__restrict__ Yb,
-                                                   const float *__restrict__ Sb, int64_t stride2,
-                                                   const SolveScalars *__restrict__ sc, double *__restrict__ part) {
-    __shared__ double red[4];
-    const VecSeg sg = segs[blockIdx.x];
-    const int slot = sc[sg.prob].head;
-    float *Y = Yb + slot * stride2;
-    const float *S = Sb + slot * stride2;
-    double a = 0.0, b = 0.0;
-    for (int e = threadIdx.x; e < sg.n; e += 256) {
-        const int64_t o = sg.off + e;
-        const float y = gnew[o] - gprev[o];
-        Y[o] = y;
-        a += (double)S[o] * y;
-        b += (double)y * y;
-    }
-    a = block_sum(a, red);
-    b = block_sum(b, red);
-    if (threadIdx.x == 0) { part[2 * sg.part] = a; part[2 * sg.part + 1] = b; }
-}
+// A thread's share of a segment: float4 chunks t, t + 256, t + 512, t + 768 (VEC_CH = 4096 floats;
+// segment offsets are multiples of 4 floats, a ragged tail is read and written element-wise).
+constexpr int VQ = VEC_CH / 1024;
+struct V16 { float v[4 * VQ]; };
 
-// first loop of the two-loop recursion, step i (newest pair first):
-//   q = (i == 0 ? g : q - alpha_{i-1} y_{i-1});  partial Re<s_i, q>
-__global__ __launch_bounds__(256) void twoloop1_kernel(const VecSeg *__restrict__ segs, int i, int m1,
-                                                       float *__restrict__ q, const float *__restrict__ g,
-                                                       const float *__restrict__ Sb, const float *__restrict__ Yb,
-                                                       int64_t stride2, const SolveScalars *__restrict__ sc,
-                                                       double *__restrict__ part) {
-    __shared__ double red[4];
-    const VecSeg sg = segs[blockIdx.x];
-    const SolveScalars &s = sc[sg.prob];
-    const int count = s.count;
-    const bool upd = (i > 0) && (i - 1 < count);
-    const bool dot = i < count;
-    const float al = upd ? (float)s.alpha[i - 1] : 0.f;
-    const float *Y = upd ? Yb + ring_slot(s, i - 1, m1) * stride2 : nullptr;
-    const float *S = dot ? Sb + ring_slot(s, i, m1) * stride2 : nullptr;
-    double acc = 0.0;
-    for (int e = threadIdx.x; e < sg.n; e += 256) {
-        const int64_t o = sg.off + e;
-        float v = (i == 0) ? g[o] : q[o];
-        if (upd) v -= al * Y[o];
-        q[o] = v;
-        if (dot) acc += (double)S[o] * v;
-    }
-    acc = block_sum(acc, red);
-    if (threadIdx.x == 0) part[sg.part] = acc;
-}
-
-// second loop of the two-loop recursion (oldest pair first):
-//   start: z = gamma q (else z from the previous step), then z += cb s_iu when iu is a valid pair;
-//   last:  p = -z with partial Re<g, p>;   otherwise store z with partial Re<y_inext, z>
-__global__ __launch_bounds__(256) void twoloop2_kernel(const VecSeg *__restrict__ segs, int start, int last, int iu,
-                                                       int inext, int m1, const float *__restrict__ q,
-                                                       float *__restrict__ zv, float *__restrict__ p,
-                                                       const float *__restrict__ g, const float *__restrict__ Sb,
-                                                       const float *__restrict__ Yb, int64_t stride2,
-                                                       const SolveScalars *__restrict__ sc,
-                                                       double *__restrict__ part) {
-    __shared__ double red[4];
-    const VecSeg sg = segs[blockIdx.x];
-    const SolveScalars &s = sc[sg.prob];
-    const int count = s.count;
-    const bool upd = (iu >= 0) && (iu < count);
-    const bool dot = !last && (inext >= 0) && (inext < count);
-    const float cb = upd ? (float)s.beta_coef : 0.f;
-    const float gam = (float)s.gamma;
-    const float *S = upd ? Sb + ring_slot(s, iu, m1) * stride2 : nullptr;
-    const float *Y = dot ? Yb + ring_slot(s, inext, m1) * stride2 : nullptr;
-    double acc = 0.0;
-    for (int e = threadIdx.x; e < sg.n; e += 256) {
-        const int64_t o = sg.off + e;
-        float v = start ? gam * q[o] : zv[o];
-        if (upd) v += cb * S[o];
-        if (last) {
-            const float pv = -v;
-            p[o] = pv;
-            acc += (double)g[o] * pv;
+__device__ __forceinline__ V16 ld16(const float *__restrict__ base, const VecSeg &sg) {
+    V16 r;
+#pragma unroll
+    for (int q = 0; q < VQ; ++q) {
+        const int e = (threadIdx.x + 256 * q) * 4;
+        if (e + 4 <= sg.n) {
+            const float4 x = *reinterpret_cast<const float4 *>(base + sg.off + e);
+            r.v[4 * q] = x.x; r.v[4 * q + 1] = x.y; r.v[4 * q + 2] = x.z; r.v[4 * q + 3] = x.w;
         } else {
-            zv[o] = v;
-            if (dot) acc += (double)Y[o] * v;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) r.v[4 * q + u] = (e + u < sg.n) ? base[sg.off + e + u] : 0.f;
         }
     }
-    acc = block_sum(acc, red);
-    if (threadIdx.x == 0) part[sg.part] = acc;
+    return r;
 }
 
-// p = -g where the problem restarts (or always when force != 0); partial Re<g,p> not needed
-__global__ __launch_bounds__(256) void restart_kernel(const VecSeg *__restrict__ segs, int force,
-                                                      float *__restrict__ p, const float *__restrict__ g,
-                                                      const SolveScalars *__restrict__ sc) {
-    const VecSeg sg = segs[blockIdx.x];
-    if (!force && !sc[sg.prob].restart) return;
-    for (int e = threadIdx.x; e < sg.n; e += 256) {
-        const int64_t o = sg.off + e;
-        p[o] = -g[o];
+__device__ __forceinline__ void st16(float *__restrict__ base, const VecSeg &sg, const V16 &r) {
+#pragma unroll
+    for (int q = 0; q < VQ; ++q) {
+        const int e = (threadIdx.x + 256 * q) * 4;
+        if (e + 4 <= sg.n) {
+            *reinterpret_cast<float4 *>(base + sg.off + e) =
+                make_float4(r.v[4 * q], r.v[4 * q + 1], r.v[4 * q + 2], r.v[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (e + u < sg.n) base[sg.off + e + u] = r.v[4 * q + u];
+        }
     }
+}
+
+__device__ __forceinline__ double dot16(const V16 &x, const V16 &y) {
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4 * VQ; ++u) a = fma((double)x.v[u], (double)y.v[u], a);
+    return a;
+}
+
+// N block sums at once (thread 0 gets the totals); same fixed order as block_sum
+template <int N>
+__device__ __forceinline__ void block_sums(double (&v)[N], double *red) {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) red[4 * k + w] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = ((red[4 * k] + red[4 * k + 1]) + red[4 * k + 2]) + red[4 * k + 3];
+    __syncthreads();
+}
+
+// Gram pass of the vector-free L-BFGS direction. With h = head (the slot of the newest step s_h,
+// written by the previous update): y_h = g - g_prev into Y[h]; then the real inner products of the
+// new vectors (s_h, y_h, g) with every stored one. Partials per segment, 6 per ring slot j:
+//   j == h : <s_h,s_h> <s_h,y_h> <y_h,y_h> <g,s_h> <g,y_h> <g,g>
+//   j valid: <s_j,s_h> <s_j,y_h> <s_j,g>   <y_j,s_h> <y_j,y_h> <y_j,g>
+//   else   : zeros
+__global__ __launch_bounds__(256) void gram_kernel(const VecSeg *__restrict__ segs, int m1,
+                                                   const float *__restrict__ g, const float *__restrict__ gprev,
+                                                   float *__restrict__ Yb, const float *__restrict__ Sb,
+                                                   int64_t stride2, const SolveScalars *__restrict__ sc,
+                                                   double *__restrict__ part) {
+    __shared__ double red[4 * 6];
+    const VecSeg sg = segs[blockIdx.x];
+    const SolveScalars &s = sc[sg.prob];
+    const int h = s.head, count = s.count;
+    double *pp = part + (int64_t)sg.part * 6 * m1;
+    const V16 vg = ld16(g, sg);
+    const V16 vs = ld16(Sb + h * stride2, sg);
+    V16 vy = ld16(gprev, sg);
+#pragma unroll
+    for (int u = 0; u < 4 * VQ; ++u) vy.v[u] = vg.v[u] - vy.v[u];
+    st16(Yb + h * stride2, sg, vy);
+    {
+        double a[6] = {dot16(vs, vs), dot16(vs, vy), dot16(vy, vy), dot16(vg, vs), dot16(vg, vy), dot16(vg, vg)};
+        block_sums<6>(a, red);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) pp[6 * h + k] = a[k];
+    }
+    for (int i = 0; i < count; ++i) {
+        const int j = ring_slot(s, i, m1);
+        const V16 sj = ld16(Sb + j * stride2, sg);
+        const V16 yj = ld16(Yb + j * stride2, sg);
+        double a[6] = {dot16(sj, vs), dot16(sj, vy), dot16(sj, vg), dot16(yj, vs), dot16(yj, vy), dot16(yj, vg)};
+        block_sums<6>(a, red);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) pp[6 * j + k] = a[k];
+    }
+    if (threadIdx.x < 6 * m1) {   // slots that are neither h nor valid
+        const int j = threadIdx.x / 6;
+        bool used = (j == h);
+        for (int i = 0; i < count; ++i) used = used || (ring_slot(s, i, m1) == j);
+        if (!used) pp[threadIdx.x] = 0.0;
+    }
+}
+
+// p = sum_b c_b v_b over the active basis {g, s_j, y_j : valid j} with the coefficients that the
+// finalisation of the Gram pass left in coef[] (index 2 m1 for g, j for s_j, m1 + j for y_j).
+__global__ __launch_bounds__(256) void combine_kernel(const VecSeg *__restrict__ segs, int m1,
+                                                      float *__restrict__ p, const float *__restrict__ g,
+                                                      const float *__restrict__ Sb, const float *__restrict__ Yb,
+                                                      int64_t stride2, const SolveScalars *__restrict__ sc,
+                                                      const double *__restrict__ coef, int64_t cstride) {
+    const VecSeg sg = segs[blockIdx.x];
+    const SolveScalars &s = sc[sg.prob];
+    const double *c = coef + (int64_t)sg.prob * cstride;
+    const int count = s.count;
+    double acc[4 * VQ];
+    {
+        const V16 vg = ld16(g, sg);
+        const double cg = c[2 * m1];
+#pragma unroll
+        for (int u = 0; u < 4 * VQ; ++u) acc[u] = cg * (double)vg.v[u];
+    }
+    for (int i = 0; i < count; ++i) {
+        const int j = ring_slot(s, i, m1);
+        const double cs = c[j], cy = c[m1 + j];
+        const V16 sj = ld16(Sb + j * stride2, sg);
+        const V16 yj = ld16(Yb + j * stride2, sg);
+#pragma unroll
+        for (int u = 0; u < 4 * VQ; ++u) acc[u] = fma(cy, (double)yj.v[u], fma(cs, (double)sj.v[u], acc[u]));
+    }
+    V16 r;
+#pragma unroll
+    for (int u = 0; u < 4 * VQ; ++u) r.v[u] = (float)acc[u];
+    st16(p, sg, r);
+}
+
+// p = -g (steepest descent: first iteration, restarts of plain gradient descent)
+__global__ __launch_bounds__(256) void negate_kernel(const VecSeg *__restrict__ segs, float *__restrict__ p,
+                                                     const float *__restrict__ g) {
+    const VecSeg sg = segs[blockIdx.x];
+    V16 v = ld16(g, sg);
+#pragma unroll
+    for (int u = 0; u < 4 * VQ; ++u) v.v[u] = -v.v[u];
+    st16(p, sg, v);
 }
 
 // g += 2 lambda theta
 __global__ __launch_bounds__(256) void reg_grad_kernel(const VecSeg *__restrict__ segs, float *__restrict__ g,
                                                        const float *__restrict__ th, float lam2) {
     const VecSeg sg = segs[blockIdx.x];
-    for (int e = threadIdx.x; e < sg.n; e += 256) {
-        const int64_t o = sg.off + e;
-        g[o] += lam2 * th[o];
-    }
+    V16 v = ld16(g, sg);
+    const V16 t = ld16(th, sg);
+#pragma unroll
+    for (int u = 0; u < 4 * VQ; ++u) v.v[u] += lam2 * t.v[u];
+    st16(g, sg, v);
 }
 
 // partials Re<x0,y0>, Re<x1,y1>
 __global__ __launch_bounds__(256) void dot2_kernel(const VecSeg *__restrict__ segs, const float *__restrict__ x0,
                                                    const float *__restrict__ y0, const float *__restrict__ x1,
                                                    const float *__restrict__ y1, double *__restrict__ part) {
-    __shared__ double red[4];
+    __shared__ double red[4 * 2];
     const VecSeg sg = segs[blockIdx.x];
-    double a = 0.0, b = 0.0;
-    for (int e = threadIdx.x; e < sg.n; e += 256) {
-        const int64_t o = sg.off + e;
-        a += (double)x0[o] * y0[o];
-        b += (double)x1[o] * y1[o];
-    }
-    a = block_sum(a, red);
-    b = block_sum(b, red);
-    if (threadIdx.x == 0) { part[2 * sg.part] = a; part[2 * sg.part + 1] = b; }
+    double a[2] = {dot16(ld16(x0, sg), ld16(y0, sg)), dot16(ld16(x1, sg), ld16(y1, sg))};
+    block_sums<2>(a, red);
+    if (threadIdx.x == 0) { part[2 * sg.part] = a[0]; part[2 * sg.part + 1] = a[1]; }
 }
 
 // theta += step p ; S[head] = step p ; partial ||theta||^2
@@ -280,21 +324,20 @@ __global__ __launch_bounds__(256) void theta_update_kernel(const VecSeg *__restr
     const SolveScalars &s = sc[sg.prob];
     const float a = (float)s.step;
     const bool frozen = s.frozen != 0;   // a non-finite step froze this problem: theta stays as is
-    float *S = (Sb && !frozen) ? Sb + s.head * stride2 : nullptr;
-    double acc = 0.0;
-    for (int e = threadIdx.x; e < sg.n; e += 256) {
-        const int64_t o = sg.off + e;
-        float v = th[o];
-        if (!frozen) {
-            const float sp = a * p[o];
-            v += sp;
-            th[o] = v;
-            if (S) S[o] = sp;
+    V16 v = ld16(th, sg);
+    if (!frozen) {
+        V16 sp = ld16(p, sg);
+#pragma unroll
+        for (int u = 0; u < 4 * VQ; ++u) {
+            sp.v[u] = a * sp.v[u];
+            v.v[u] += sp.v[u];
         }
-        acc += (double)v * v;
+        st16(th, sg, v);
+        if (Sb) st16(Sb + s.head * stride2, sg, sp);
     }
-    acc = block_sum(acc, red);
-    if (threadIdx.x == 0) part[sg.part] = acc;
+    double acc[1] = {dot16(v, v)};
+    block_sums<1>(acc, red);
+    if (threadIdx.x == 0) part[sg.part] = acc[0];
 }
 
 // r += step a + step^2 b ; partial ||r||^2
@@ -308,18 +351,16 @@ __global__ __launch_bounds__(256) void resid_update_kernel(const VecSeg *__restr
     const float al = (float)s.step;
     const float al2 = (float)(s.step * s.step);
     const bool frozen = s.frozen != 0;
-    double acc = 0.0;
-    for (int e = threadIdx.x; e < sg.n; e += 256) {
-        const int64_t o = sg.off + e;
-        float v = r[o];
-        if (!frozen) {
-            v += al * a[o] + al2 * b[o];
-            r[o] = v;
-        }
-        acc += (double)v * v;
+    V16 v = ld16(r, sg);
+    if (!frozen) {
+        const V16 va = ld16(a, sg), vb = ld16(b, sg);
+#pragma unroll
+        for (int u = 0; u < 4 * VQ; ++u) v.v[u] += al * va.v[u] + al2 * vb.v[u];
+        st16(r, sg, v);
     }
-    acc = block_sum(acc, red);
-    if (threadIdx.x == 0) part[sg.part] = acc;
+    double acc[1] = {dot16(v, v)};
+    block_sums<1>(acc, red);
+    if (threadIdx.x == 0) part[sg.part] = acc[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -394,7 +435,7 @@ __device__ double exact_step_dev(const double *c) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs fa) {
     __shared__ double red[4];
-    __shared__ double tot[8];
+    __shared__ double tot[6 * (MAX_LBFGS_M + 1)];
     const int prob = blockIdx.x;
     const int count = fa.counts ? fa.counts[prob] : fa.ucount;
     const double *base = fa.partials + (int64_t)prob * fa.pstride * fa.nsum;
@@ -426,31 +467,76 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs fa) {
         case FIN_THNORM:
             s.thnorm2 = tot[0];
             break;
-        case FIN_PAIR: {  // tot = (Re<s,y>, Re<y,y>)
-            const double sy = tot[0], yy = tot[1];
+        case FIN_GRAM: {  // Gram entries of the newest pair and of g; direction coefficients
+            const int nb = 2 * m1 + 1, ig = 2 * m1;
+            double *G = fa.gram + (int64_t)prob * fa.gstride;   // nb x nb, then nb coefficients
+            double *cf = G + nb * nb;
+            const int h = s.head;
+            const double *th = tot + 6 * h;
+            const double sy = th[1], yy = th[2];
+            // g against the pairs already held (before the newest one is taken in)
+            for (int i = 0; i < s.count; ++i) {
+                const int j = ring_slot(s, i, m1);
+                G[ig * nb + j] = G[j * nb + ig] = tot[6 * j + 2];
+                G[ig * nb + m1 + j] = G[(m1 + j) * nb + ig] = tot[6 * j + 5];
+            }
+            G[ig * nb + ig] = th[5];
             s.sy = sy; s.yy = yy;
             if (sy > 0.0 && yy > 0.0 && isfinite(sy) && isfinite(yy) && !s.frozen) {
-                s.rho[s.head] = 1.0 / sy;
+                for (int i = 0; i < s.count; ++i) {
+                    const int j = ring_slot(s, i, m1);
+                    const double *tj = tot + 6 * j;
+                    G[j * nb + h] = G[h * nb + j] = tj[0];
+                    G[j * nb + m1 + h] = G[(m1 + h) * nb + j] = tj[1];
+                    G[(m1 + j) * nb + h] = G[h * nb + m1 + j] = tj[3];
+                    G[(m1 + j) * nb + m1 + h] = G[(m1 + h) * nb + m1 + j] = tj[4];
+                }
+                G[h * nb + h] = th[0];
+                G[h * nb + m1 + h] = G[(m1 + h) * nb + h] = sy;
+                G[(m1 + h) * nb + m1 + h] = yy;
+                G[ig * nb + h] = G[h * nb + ig] = th[3];
+                G[ig * nb + m1 + h] = G[(m1 + h) * nb + ig] = th[4];
+                s.rho[h] = 1.0 / sy;
                 s.gamma = sy / yy;
-                s.head = (s.head + 1) % m1;
+                s.head = (h + 1) % m1;
                 s.count = min(s.count + 1, m1 - 1);
             }
-            break;
-        }
-        case FIN_ALPHA: {  // alpha_i = rho_i Re<s_i, q>
-            const int i = fa.i;
-            if (i < s.count) s.alpha[i] = s.rho[ring_slot(s, i, m1)] * tot[0];
-            break;
-        }
-        case FIN_BETA: {  // coefficient alpha_i - rho_i Re<y_i, z>
-            const int i = fa.i;
-            if (i >= 0 && i < s.count) s.beta_coef = s.alpha[i] - s.rho[ring_slot(s, i, m1)] * tot[0];
-            break;
-        }
-        case FIN_GP: {  // Re<g, p>: restart when not a descent direction
-            s.gp = tot[0];
-            s.restart = (tot[0] >= 0.0 || !isfinite(tot[0])) ? 1 : 0;
-            if (s.restart) { s.count = 0; s.gamma = 1.0; }
+            // two-loop recursion on coefficient vectors over the basis (s_j, y_j, g):
+            // q = sum_b d_b v_b, so <v_a, q> = sum_b G_ab d_b
+            for (int b2 = 0; b2 < nb; ++b2) cf[b2] = 0.0;
+            cf[ig] = 1.0;
+            const int cnt = s.count;
+            auto dotG = [&](int a_) {
+                double v = G[a_ * nb + ig] * cf[ig];
+                for (int i = 0; i < cnt; ++i) {
+                    const int j = ring_slot(s, i, m1);
+                    v += G[a_ * nb + j] * cf[j] + G[a_ * nb + m1 + j] * cf[m1 + j];
+                }
+                return v;
+            };
+            for (int i = 0; i < cnt; ++i) {   // newest first
+                const int j = ring_slot(s, i, m1);
+                s.alpha[i] = s.rho[j] * dotG(j);
+                cf[m1 + j] -= s.alpha[i];
+            }
+            if (cnt > 0)
+                for (int b2 = 0; b2 < nb; ++b2) cf[b2] *= s.gamma;
+            for (int i = cnt - 1; i >= 0; --i) {   // oldest first
+                const int j = ring_slot(s, i, m1);
+                const double beta = s.rho[j] * dotG(m1 + j);
+                cf[j] += s.alpha[i] - beta;
+            }
+            for (int b2 = 0; b2 < nb; ++b2) cf[b2] = -cf[b2];
+            const double gp = dotG(ig);
+            s.gp = gp;
+            s.restart = (gp >= 0.0 || !isfinite(gp)) ? 1 : 0;
+            if (s.restart) {   // not a descent direction: p = -g and the history is dropped
+                s.count = 0;
+                s.gamma = 1.0;
+                for (int b2 = 0; b2 < nb; ++b2) cf[b2] = 0.0;
+                cf[ig] = -1.0;
+                s.gp = -G[ig * nb + ig];
+            }
             break;
         }
         case FIN_LAMTERMS:  // (Re<theta,p>, ||p||^2)
@@ -534,24 +620,17 @@ hipError_t launch_permute_cols(const float2 *in, const int64_t *perm, float2 *ou
         return hipGetLastError();                                                    \
     } while (0)
 
-hipError_t launch_pair(const VecSeg *segs, int nseg, const float *gnew, const float *gprev, float *Yb,
+hipError_t launch_gram(const VecSeg *segs, int nseg, int m1, const float *g, const float *gprev, float *Yb,
                        const float *Sb, int64_t stride2, const SolveScalars *sc, double *part, hipStream_t s) {
-    SEGS_LAUNCH(pair_kernel, nseg, s, segs, gnew, gprev, Yb, Sb, stride2, sc, part);
+    SEGS_LAUNCH(gram_kernel, nseg, s, segs, m1, g, gprev, Yb, Sb, stride2, sc, part);
 }
-hipError_t launch_twoloop1(const VecSeg *segs, int nseg, int i, int m1, float *q, const float *g,
-                           const float *Sb, const float *Yb, int64_t stride2, const SolveScalars *sc,
-                           double *part, hipStream_t s) {
-    SEGS_LAUNCH(twoloop1_kernel, nseg, s, segs, i, m1, q, g, Sb, Yb, stride2, sc, part);
+hipError_t launch_combine(const VecSeg *segs, int nseg, int m1, float *p, const float *g, const float *Sb,
+                          const float *Yb, int64_t stride2, const SolveScalars *sc, const double *coef,
+                          int64_t cstride, hipStream_t s) {
+    SEGS_LAUNCH(combine_kernel, nseg, s, segs, m1, p, g, Sb, Yb, stride2, sc, coef, cstride);
 }
-hipError_t launch_twoloop2(const VecSeg *segs, int nseg, int start, int last, int iu, int inext, int m1,
-                           const float *q, float *z, float *p, const float *g, const float *Sb,
-                           const float *Yb, int64_t stride2, const SolveScalars *sc, double *part,
-                           hipStream_t s) {
-    SEGS_LAUNCH(twoloop2_kernel, nseg, s, segs, start, last, iu, inext, m1, q, z, p, g, Sb, Yb, stride2, sc, part);
-}
-hipError_t launch_restart(const VecSeg *segs, int nseg, int force, float *p, const float *g,
-                          const SolveScalars *sc, hipStream_t s) {
-    SEGS_LAUNCH(restart_kernel, nseg, s, segs, force, p, g, sc);
+hipError_t launch_negate(const VecSeg *segs, int nseg, float *p, const float *g, hipStream_t s) {
+    SEGS_LAUNCH(negate_kernel, nseg, s, segs, p, g);
 }
 hipError_t launch_reg_grad(const VecSeg *segs, int nseg, float *g, const float *th, float lam2, hipStream_t s) {
     SEGS_LAUNCH(reg_grad_kernel, nseg, s, segs, g, th, lam2);

@@ -12,10 +12,10 @@ struct VecSeg {
     int32_t part;   // partial-sum slot (prob * pstride + local index)
     int32_t pad;
 };
-constexpr int VEC_CH = 8192;
+constexpr int VEC_CH = 4096;   // floats per segment (a multiple of 1024; offsets multiples of 4)
 
 enum FinOp : int32_t {
-    FIN_INIT = 0, FIN_F, FIN_F_OUT, FIN_THNORM, FIN_PAIR, FIN_ALPHA, FIN_BETA, FIN_GP, FIN_LAMTERMS, FIN_LINE
+    FIN_INIT = 0, FIN_F, FIN_F_OUT, FIN_THNORM, FIN_GRAM, FIN_LAMTERMS, FIN_LINE
 };
 
 struct FinArgs {
@@ -25,7 +25,6 @@ struct FinArgs {
     int64_t pstride;       // entries per problem
     const int32_t *counts; // entries used per problem (NULL -> ucount)
     int32_t ucount;
-    int32_t i;             // loop index (FIN_ALPHA / FIN_BETA)
     int32_t m1;            // ring slots (lbfgs_m + 1)
     int32_t t;             // f-history index (FIN_F)
     SolveScalars *sc;
@@ -33,19 +32,16 @@ struct FinArgs {
     double *fhist0;        // f-history of a single problem (FIN_F)
     double *fout;          // FIN_F_OUT: per-problem objective
     double lam;
+    double *gram;          // FIN_GRAM: per-problem Gram matrix and direction coefficients
+    int64_t gstride;       // doubles per problem in gram: (2 m1 + 1)^2 + 2 m1 + 1
 };
 
-hipError_t launch_pair(const VecSeg *segs, int nseg, const float *gnew, const float *gprev, float *Yb,
+hipError_t launch_gram(const VecSeg *segs, int nseg, int m1, const float *g, const float *gprev, float *Yb,
                        const float *Sb, int64_t stride2, const SolveScalars *sc, double *part, hipStream_t s);
-hipError_t launch_twoloop1(const VecSeg *segs, int nseg, int i, int m1, float *q, const float *g,
-                           const float *Sb, const float *Yb, int64_t stride2, const SolveScalars *sc,
-                           double *part, hipStream_t s);
-hipError_t launch_twoloop2(const VecSeg *segs, int nseg, int start, int last, int iu, int inext, int m1,
-                           const float *q, float *z, float *p, const float *g, const float *Sb,
-                           const float *Yb, int64_t stride2, const SolveScalars *sc, double *part,
-                           hipStream_t s);
-hipError_t launch_restart(const VecSeg *segs, int nseg, int force, float *p, const float *g,
-                          const SolveScalars *sc, hipStream_t s);
+hipError_t launch_combine(const VecSeg *segs, int nseg, int m1, float *p, const float *g, const float *Sb,
+                          const float *Yb, int64_t stride2, const SolveScalars *sc, const double *coef,
+                          int64_t cstride, hipStream_t s);
+hipError_t launch_negate(const VecSeg *segs, int nseg, float *p, const float *g, hipStream_t s);
 hipError_t launch_reg_grad(const VecSeg *segs, int nseg, float *g, const float *th, float lam2, hipStream_t s);
 hipError_t launch_dot2(const VecSeg *segs, int nseg, const float *x0, const float *y0, const float *x1,
                        const float *y1, double *part, hipStream_t s);

@@ -21,7 +21,9 @@ Section / equation map (names as in the paper):
   * ADMM solver, X-update: limited-memory BFGS (Liu & Nocedal 1989); here with
     an exact line search along the quartic f(theta + alpha p).
   * Hyper-parameter selection: Frobenius regulariser lambda ||.||_F^2 whose
-    gradient is 2 lambda theta.
+    gradient is 2 lambda theta; lambda continuation 10 -> 1 -> 0.1.
+  * ADMM solver, X-update / Z-update (eq. proxofFro2) / dual update: scaled
+    ADMM on min f(theta) + lambda ||theta||^2 with the split theta = z.
 
 Readings where the paper is silent (the same readings the GPU path follows):
   * gradient convention: 2 df/d(conj theta) = df/dRe + i df/dIm (the paper
@@ -374,15 +376,17 @@ def re_dot(a: np.ndarray, b: np.ndarray) -> float:
 # ============================================================================
 # Exact line search along the quartic  phi(alpha) = f(theta + alpha p)
 # ============================================================================
-def line_coefficients(r, a, b, theta=None, p=None, lam: float = 0.0):
+def line_coefficients(r, a, b, theta=None, p=None, lam: float = 0.0, center=None):
     """phi'(alpha) = c0 + c1 alpha + c2 alpha^2 + c3 alpha^3 where
-    phi(alpha) = 1/2 ||r + alpha a + alpha^2 b||^2 + lam ||theta + alpha p||^2."""
+    phi(alpha) = 1/2 ||r + alpha a + alpha^2 b||^2 + lam ||theta + alpha p - center||^2
+    (center = 0 unless given)."""
     c0 = re_dot(r, a)
     c1 = re_dot(a, a) + 2.0 * re_dot(r, b)
     c2 = 3.0 * re_dot(a, b)
     c3 = 2.0 * re_dot(b, b)
     if lam != 0.0:
-        c0 += 2.0 * lam * re_dot(theta, p)
+        d = theta if center is None else theta - center
+        c0 += 2.0 * lam * re_dot(d, p)
         c1 += 2.0 * lam * re_dot(p, p)
     return np.array([c0, c1, c2, c3], dtype=np.float64)
 
@@ -464,21 +468,24 @@ class SolveResult:
 
 
 def solve(T: Tiling, D, U, theta0, iters: int, m: int = 5, optimizer: str = "lbfgs",
-          lam: float = 0.0, record=None) -> SolveResult:
-    """Fixed-count L-BFGS (or steepest descent) on f (+ lam ||theta||^2).
+          lam: float = 0.0, record=None, center=None) -> SolveResult:
+    """Fixed-count L-BFGS (or steepest descent) on f (+ lam ||theta - center||^2).
 
     Per iteration: gradient from the tracked residual r; direction; exact
     line search with a = D X1, b = D X2; theta += alpha p; r += alpha a +
     alpha^2 b. ``record(t, state)`` (optional) sees every iteration's state.
+    ``center`` (default 0) is the point the Frobenius penalty pulls towards:
+    0 for the plain regulariser, z - u in the ADMM X-update.
     """
     theta = np.array(theta0, dtype=np.complex128, copy=True)
     r = residual(D, assemble(T, theta), U)
     DH = D.conj().T
+    cen = np.zeros_like(theta) if center is None else np.asarray(center, dtype=np.complex128)
 
     def fval(rr, th):
         v = 0.5 * re_dot(rr, rr)
         if lam != 0.0:
-            v += lam * re_dot(th, th)
+            v += lam * re_dot(th - cen, th - cen)
         return v
 
     f_hist = [fval(r, theta)]
@@ -491,7 +498,7 @@ def solve(T: Tiling, D, U, theta0, iters: int, m: int = 5, optimizer: str = "lbf
     for t in range(iters):
         g = tile_gradient(T, theta, DH @ r)
         if lam != 0.0:
-            g = g + 2.0 * lam * theta
+            g = g + 2.0 * lam * (theta - cen)
         if g_prev is not None and s_prev is not None:
             y = g - g_prev
             if re_dot(s_prev, y) > 0.0:
@@ -512,7 +519,7 @@ def solve(T: Tiling, D, U, theta0, iters: int, m: int = 5, optimizer: str = "lbf
         X1, X2 = assemble_directional(T, theta, p)
         a = D @ X1
         b = D @ X2
-        c = line_coefficients(r, a, b, theta, p, lam)
+        c = line_coefficients(r, a, b, theta, p, lam, cen)
         alpha = exact_step(c)
         if record is not None:
             record(t, dict(theta=theta.copy(), r=r.copy(), g=g.copy(), p=p.copy(),
@@ -524,6 +531,49 @@ def solve(T: Tiling, D, U, theta0, iters: int, m: int = 5, optimizer: str = "lbf
         alphas.append(alpha)
         f_hist.append(fval(r, theta))
     return SolveResult(theta, np.array(f_hist), np.array(alphas), restarts)
+
+
+# ============================================================================
+# ADMM with lambda continuation (ADMM solver section; hyper-parameter selection)
+# ============================================================================
+@dataclasses.dataclass
+class AdmmResult:
+    theta: np.ndarray       # the X-variable (the returned solution)
+    z: np.ndarray           # the split variable after the last Z-update
+    u: np.ndarray           # scaled dual after the last update
+    f_hist: np.ndarray      # data misfit 1/2||D C(theta) - U||^2: start, then after every X-update
+    stage_end: List[int]    # index into f_hist of the last X-update of each lambda stage
+
+
+def admm(T: Tiling, D, U, theta0, lams=(10.0, 1.0, 0.1), outer: int = 5, inner: int = 10,
+         rho: float = 1.0, m: int = 5, record=None) -> AdmmResult:
+    """Scaled ADMM on min_theta f(theta) + lam ||theta||_F^2 with the split theta = z.
+
+    For every lam of the continuation (each stage warm-started from the last)
+    and `outer` times:
+      X-update  theta <- argmin f(theta) + rho/2 ||theta - z + u||^2, by `inner`
+                L-BFGS iterations from the current theta (fresh pair memory);
+      Z-update  z <- (theta + u) / (1 + 2 lam / rho), the proximal point of
+                lam ||.||^2 (closed form of the Frobenius prox);
+      dual      u <- u + theta - z.
+    Starts from z = theta0, u = 0.
+    """
+    theta = np.array(theta0, dtype=np.complex128, copy=True)
+    z = theta.copy()
+    u = np.zeros_like(theta)
+    f_hist = [0.5 * float(np.linalg.norm(residual(D, assemble(T, theta), U)) ** 2)]
+    stage_end = []
+    for lam in lams:
+        for k in range(outer):
+            res = solve(T, D, U, theta, inner, m=m, lam=rho / 2.0, center=z - u)
+            theta = res.theta
+            z = (theta + u) / (1.0 + 2.0 * lam / rho)
+            u = u + theta - z
+            f_hist.append(0.5 * float(np.linalg.norm(residual(D, assemble(T, theta), U)) ** 2))
+            if record is not None:
+                record(lam, k, dict(theta=theta.copy(), z=z.copy(), u=u.copy()))
+        stage_end.append(len(f_hist) - 1)
+    return AdmmResult(theta, z, u, np.array(f_hist), stage_end)
 
 
 # ============================================================================

@@ -18,7 +18,11 @@
 // memory to LDS (buffer_load ... lds, no staging registers) into a 4-stage
 // ring (four planes per stage: A hi/lo, B hi/lo, 16-byte chunks XOR-swizzled
 // so operand reads are bank-conflict free); loads run three stages ahead of
-// the matrix cores. Per stage each wave issues 2 x 4 x 3 MFMAs. Each
+// the matrix cores. A stage's twelve fragment reads are one inline-asm group
+// with its own LDS wait: as plain loads the compiler, unable to tell the ring
+// buffers apart from the one the DMA just targeted, would wait for that DMA
+// too and undo the prefetch. Per stage each wave issues 2 x 4 x 3 MFMAs,
+// ordered so consecutive MFMAs accumulate into different tiles. Each
 // lane's B fragment (4 complex b of one column) is turned into the realified
 // row pair by one XOR (column parity 0: [Re, -Im]) or a 16-bit rotate
 // (parity 1: [Im, Re]) per 32-bit word.
@@ -135,24 +139,49 @@ __global__ __launch_bounds__(256, 2) void cgemm_bf16x3_kernel(GemmArgsB g) {
         return o;
     };
 
+    // LDS addresses (32-bit) of this lane's fragments in each ring buffer
+    auto lds_addr = [](const unsigned char *p) { return (uint32_t)(uintptr_t)(lds_ptr_t)p; };
     auto compute = [&](const unsigned char *st) {
-        bf16x8 ah[2], al[2];
+        const uint32_t va = lds_addr(st) + a_off, vb = lds_addr(st) + b_off;
+        u32x4 ah0, ah1, al0, al1, bh0, bh1, bh2, bh3, bl0, bl1, bl2, bl3;
+        // all twelve fragment reads of the stage in flight together, waited in the same block
+        asm volatile(
+            "ds_read_b128 %0, %12\n\t"
+            "ds_read_b128 %1, %12 offset:1024\n\t"
+            "ds_read_b128 %2, %12 offset:4096\n\t"
+            "ds_read_b128 %3, %12 offset:5120\n\t"
+            "ds_read_b128 %4, %13 offset:8192\n\t"
+            "ds_read_b128 %5, %13 offset:8704\n\t"
+            "ds_read_b128 %6, %13 offset:9216\n\t"
+            "ds_read_b128 %7, %13 offset:9728\n\t"
+            "ds_read_b128 %8, %13 offset:12288\n\t"
+            "ds_read_b128 %9, %13 offset:12800\n\t"
+            "ds_read_b128 %10, %13 offset:13312\n\t"
+            "ds_read_b128 %11, %13 offset:13824\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(ah0), "=&v"(ah1), "=&v"(al0), "=&v"(al1), "=&v"(bh0), "=&v"(bh1), "=&v"(bh2), "=&v"(bh3),
+              "=&v"(bl0), "=&v"(bl1), "=&v"(bl2), "=&v"(bl3)
+            : "v"(va), "v"(vb));
+        const bf16x8 ah[2] = {as_bf16x8(ah0), as_bf16x8(ah1)};
+        const bf16x8 al[2] = {as_bf16x8(al0), as_bf16x8(al1)};
+        const bf16x8 bh[4] = {as_bf16x8(xform(bh0)), as_bf16x8(xform(bh1)), as_bf16x8(xform(bh2)), as_bf16x8(xform(bh3))};
+        const bf16x8 bl[4] = {as_bf16x8(xform(bl0)), as_bf16x8(xform(bl1)), as_bf16x8(xform(bl2)), as_bf16x8(xform(bl3))};
+        // consecutive MFMAs accumulate into different tiles
 #pragma unroll
-        for (int bm = 0; bm < 2; ++bm) {
-            ah[bm] = as_bf16x8(*reinterpret_cast<const u32x4 *>(st + a_off + bm * 32 * ROWB));
-            al[bm] = as_bf16x8(*reinterpret_cast<const u32x4 *>(st + PLANE + a_off + bm * 32 * ROWB));
-        }
+        for (int bn = 0; bn < 4; ++bn)
 #pragma unroll
-        for (int bn = 0; bn < 4; ++bn) {
-            const bf16x8 bh = as_bf16x8(xform(*reinterpret_cast<const u32x4 *>(st + 2 * PLANE + b_off + bn * 16 * ROWB)));
-            const bf16x8 bl = as_bf16x8(xform(*reinterpret_cast<const u32x4 *>(st + 3 * PLANE + b_off + bn * 16 * ROWB)));
+            for (int bm = 0; bm < 2; ++bm)
+                acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bm], bh[bn], acc[bm][bn], 0, 0, 0);
 #pragma unroll
-            for (int bm = 0; bm < 2; ++bm) {
-                acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bm], bh, acc[bm][bn], 0, 0, 0);
-                acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bm], bl, acc[bm][bn], 0, 0, 0);
-                acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bm], bh, acc[bm][bn], 0, 0, 0);
-            }
-        }
+        for (int bn = 0; bn < 4; ++bn)
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+                acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bm], bl[bn], acc[bm][bn], 0, 0, 0);
+#pragma unroll
+        for (int bn = 0; bn < 4; ++bn)
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+                acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bm], bh[bn], acc[bm][bn], 0, 0, 0);
     };
     // one ring step: stage kt (in `cur`) has landed once at most the loads of the two stages
     // issued after it are outstanding; then the buffer of stage kt-1 (`nxt`) takes stage kt+3

@@ -168,6 +168,40 @@ int tlrmdd_solve_batched(int count, const tlrmdd_plan *plans, const void *const 
                          const tlrmdd_opts *opts, double *const *f_hist_dev,
                          void *workspace, size_t ws_bytes, hipStream_t stream);
 
+/* ADMM with lambda continuation (ADMM solver section: X-update, Z-update
+ * eq. proxofFro2, dual update; hyper-parameter selection: lambda stages
+ * 10 -> 1 -> 0.1). The problem is min f(theta) + lambda ||theta||^2 on the
+ * factors, split as theta = z with the scaled dual u (u <- u + theta - z; the
+ * paper prints the unscaled dual step, the scaled form keeps its X-update
+ * consistent). Starting from z = theta_in, u = 0, for every stage and every
+ * outer step:
+ *   X-update: inner.iters iterations of the solver above on
+ *             f(theta) + rho/2 ||theta - z + u||^2 from the current theta
+ *             (fresh L-BFGS memory, tracked residual carried over);
+ *   Z-update: z = (theta + u) / (1 + 2 lambda / rho);
+ *   dual:     u = u + theta - z.
+ * theta_inout receives the X-variable. f_hist_dev: device, 1 + nstages *
+ * outer doubles per problem: the data misfit 1/2||D C(theta) - U||^2 of the
+ * tracked residual at the start and after every X-update. inner.lambda and
+ * inner.resid_refresh are ignored / used as in tlrmdd_solve. */
+typedef struct {
+    tlrmdd_opts inner;       /* X-update: iters per update, optimizer, lbfgs_m, precision */
+    int32_t nstages;         /* number of lambda stages, >= 1                               */
+    int32_t outer;           /* ADMM steps per stage, >= 0                                  */
+    const double *lambdas;   /* host, nstages values >= 0                                   */
+    double rho;              /* ADMM penalty, > 0                                           */
+} tlrmdd_admm_opts;
+
+int tlrmdd_workspace_bytes_admm(int count, const tlrmdd_plan *plans, const tlrmdd_admm_opts *opts,
+                                size_t *bytes);
+int tlrmdd_admm(tlrmdd_plan plan, const void *D, const void *U, void *theta_inout,
+                const tlrmdd_admm_opts *opts, double *f_hist_dev,
+                void *workspace, size_t ws_bytes, hipStream_t stream);
+int tlrmdd_admm_batched(int count, const tlrmdd_plan *plans, const void *const *D,
+                        const void *const *U, void *const *theta_inout,
+                        const tlrmdd_admm_opts *opts, double *const *f_hist_dev,
+                        void *workspace, size_t ws_bytes, hipStream_t stream);
+
 /* Adjoint (cross-correlation) solution X_adj = D^H U (MDD Solver Evaluation section: the
  * adjoint solution that needs no inversion). D, U: device ns x nr complex64; X_out: device
  * nr x nr complex64. Uses the plan's sizes only (its tiles are ignored). Workspace: as for

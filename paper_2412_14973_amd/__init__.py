@@ -217,6 +217,60 @@ def solve_batched(plans, Ds, Us, thetas0, iters, optimizer=LBFGS, lbfgs_m=5, pre
     return thetas, fh
 
 
+def make_admm_opts(lams=(10.0, 1.0, 0.1), outer=5, inner=10, rho=1.0, optimizer=LBFGS, lbfgs_m=5,
+                   precision=FP32):
+    """ADMM options; the returned struct keeps its lambda array alive."""
+    lam_arr = (ctypes.c_double * len(lams))(*[float(v) for v in lams])
+    o = _lib.c_admm_opts(make_opts(inner, optimizer, lbfgs_m, precision), len(lams), int(outer),
+                         ctypes.cast(lam_arr, ctypes.POINTER(ctypes.c_double)), float(rho))
+    o._keep = lam_arr
+    return o
+
+
+def admm_workspace_bytes(plans, aopts):
+    arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    n = ctypes.c_size_t()
+    _lib.check(_lib.load().tlrmdd_workspace_bytes_admm(len(plans), arr, ctypes.byref(aopts), ctypes.byref(n)),
+               "tlrmdd_workspace_bytes_admm")
+    return int(n.value)
+
+
+def admm_batched(plans, Ds, Us, thetas0, lams=(10.0, 1.0, 0.1), outer=5, inner=10, rho=1.0, optimizer=LBFGS,
+                 lbfgs_m=5, precision=FP32, workspace=None):
+    """Scaled ADMM with lambda continuation over independent frequencies of equal nr, ns.
+
+    Returns (thetas, f_hists); f_hist[k] is the data misfit at the start (k = 0) and after
+    the k-th X-update (1 + len(lams) * outer entries, FP64, device)."""
+    n = len(plans)
+    for p, D, U, th in zip(plans, Ds, Us, thetas0):
+        _check_problem(p, D, U, th)
+    aopts = make_admm_opts(lams, outer, inner, rho, optimizer, lbfgs_m, precision)
+    thetas = [t.clone() for t in thetas0]
+    fh = [torch.empty(1 + len(lams) * outer, dtype=torch.float64, device=Ds[0].device) for _ in range(n)]
+    ws = workspace if workspace is not None else torch.empty(admm_workspace_bytes(plans, aopts),
+                                                             dtype=torch.uint8, device=Ds[0].device)
+    V = ctypes.c_void_p * n
+    _lib.check(_lib.load().tlrmdd_admm_batched(
+        n, V(*[p.handle.value for p in plans]), V(*[d.data_ptr() for d in Ds]), V(*[u.data_ptr() for u in Us]),
+        V(*[t.data_ptr() for t in thetas]), ctypes.byref(aopts), V(*[f.data_ptr() for f in fh]),
+        _ptr(ws), ws.numel(), _stream()), "tlrmdd_admm_batched")
+    return thetas, fh
+
+
+def admm(plan, D, U, theta0, lams=(10.0, 1.0, 0.1), outer=5, inner=10, rho=1.0, optimizer=LBFGS, lbfgs_m=5,
+         precision=FP32, workspace=None):
+    """Scaled ADMM with lambda continuation on one frequency; returns (theta, f_hist)."""
+    _check_problem(plan, D, U, theta0)
+    aopts = make_admm_opts(lams, outer, inner, rho, optimizer, lbfgs_m, precision)
+    theta = theta0.clone()
+    fh = torch.empty(1 + len(lams) * outer, dtype=torch.float64, device=D.device)
+    ws = workspace if workspace is not None else torch.empty(admm_workspace_bytes([plan], aopts),
+                                                             dtype=torch.uint8, device=D.device)
+    _lib.check(_lib.load().tlrmdd_admm(plan.handle, _ptr(D), _ptr(U), _ptr(theta), ctypes.byref(aopts), _ptr(fh),
+                                       _ptr(ws), ws.numel(), _stream()), "tlrmdd_admm")
+    return theta, fh
+
+
 class KernelTimer:
     """Context manager: per-kind summed kernel milliseconds and launch counts (HIP events)."""
 

@@ -38,6 +38,11 @@ class c_opts(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class c_admm_opts(ctypes.Structure):
+    _fields_ = [("inner", c_opts), ("nstages", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("lambdas", ctypes.POINTER(ctypes.c_double)), ("rho", ctypes.c_double)]
+
+
 _lib = None
 
 _SIGS = {
@@ -66,6 +71,15 @@ _SIGS = {
                                               ctypes.c_int64, ctypes.c_void_p]),
     "tlrmdd_adjoint": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                                                                 ctypes.c_void_p]),
+    "tlrmdd_workspace_bytes_admm": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                                   ctypes.POINTER(c_admm_opts), ctypes.POINTER(ctypes.c_size_t)]),
+    "tlrmdd_admm": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.POINTER(c_admm_opts), ctypes.c_void_p,
+                                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "tlrmdd_admm_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(c_admm_opts),
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_size_t,
+                                           ctypes.c_void_p]),
     "tlrmdd_timing_begin": (ctypes.c_int, []),
     "tlrmdd_timing_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
 }

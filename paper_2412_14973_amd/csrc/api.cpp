@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -331,6 +332,7 @@ struct Ws {
     uint32_t *rT = nullptr;   // BF16 split planes of r^T (hi, lo), ldk x lds each
     float *th = nullptr, *g0 = nullptr, *g1 = nullptr, *p = nullptr, *S = nullptr, *Y = nullptr;
     double *gram = nullptr;   // per problem: Gram matrix of the L-BFGS basis and direction coefficients
+    float *z = nullptr, *u = nullptr, *cen = nullptr;   // ADMM
     double *partials = nullptr;
     SolveScalars *sc = nullptr;
     char *tables = nullptr;
@@ -340,7 +342,7 @@ struct Ws {
 // doubles per problem for the L-BFGS Gram matrix over (s_j, y_j, g) and the direction coefficients
 int64_t gram_stride(int m1) { return (int64_t)(2 * m1 + 1) * (2 * m1 + 1) + 2 * m1 + 1; }
 
-// op: 0 forward, 1 grad, 2 solve. Sizes for `nprob` problems of the same shape; every matrix is
+// op: 0 forward, 1 grad, 2 solve, 3 ADMM. Sizes for `nprob` problems of the same shape; every matrix is
 // padded to whole GEMM tiles: ns x nr operands are lds x ldk (rows x cols), nr x nr ones ldk x ldk.
 Ws carve(char *base, int op, int nprob, int64_t ldk, int64_t lds, int64_t theta_total, int m1, int pstride,
          size_t tbytes) {
@@ -356,10 +358,10 @@ Ws carve(char *base, int op, int nprob, int64_t ldk, int64_t lds, int64_t theta_
     const size_t rsz = (size_t)nprob * lds * ldk * c8;
     w.Ds = (float2 *)take(rsz);
     if (op >= 1) w.DHs = (float2 *)take((size_t)nprob * ldk * lds * c8);
-    w.XW = (float2 *)take(op == 2 ? 2 * xsz : xsz);
+    w.XW = (float2 *)take(op >= 2 ? 2 * xsz : xsz);
     w.r = (float2 *)take(rsz);
     if (op >= 1) w.rT = (uint32_t *)take(rsz);
-    if (op == 2) {
+    if (op >= 2) {
         w.Us = (float2 *)take(rsz);
         w.a = (float2 *)take(rsz);
         w.b = (float2 *)take(rsz);
@@ -371,6 +373,12 @@ Ws carve(char *base, int op, int nprob, int64_t ldk, int64_t lds, int64_t theta_
         w.S = (float *)take(tz * m1);
         w.Y = (float *)take(tz * m1);
         w.gram = (double *)take((size_t)nprob * gram_stride(m1) * sizeof(double));
+    }
+    if (op == 3) {   // ADMM: split variable, scaled dual, penalty center
+        const size_t tz = (size_t)theta_total * c8;
+        w.z = (float *)take(tz);
+        w.u = (float *)take(tz);
+        w.cen = (float *)take(tz);
     }
     w.partials = (double *)take((size_t)nprob * pstride * std::max(5, 6 * m1) * sizeof(double));
     w.sc = (SolveScalars *)take((size_t)nprob * sizeof(SolveScalars));
@@ -653,9 +661,61 @@ int resid_tiles(const Ctx &c) { return gemm_partials_per_problem(GM_RESID, (int)
 int line_tiles(const Ctx &c) { return gemm_partials_per_problem(GM_LINE, (int)c.lds, (int)c.ldk) / 5; }
 
 // The whole solve, for one problem or a batch of equal-shape problems.
-int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const void *const *U,
-               void *const *theta, const tlrmdd_opts *opts, double *const *fhist, void *workspace,
-               size_t ws_bytes, hipStream_t s) {
+// One run of the solver over `nprob` problems of one shape: tables, workspace views, staged operands
+// and the tracked residual. Setup stages D and U, copies theta in and forms r = D C(theta) - U; then
+// any number of iterate() calls continue from the current theta and residual.
+struct Run {
+    Ctx c;
+    Tables T;
+    bool single = true, lbfgs = true;
+    int m = 0, m1 = 1;
+    int64_t xstride = 0, rstride = 0, x2w = 0, stride2 = 0;
+    float2 *X1 = nullptr, *X2 = nullptr;
+    int nt = 0, nrs = 0;
+    float *gcur = nullptr, *gprev = nullptr;
+    double *fhist0 = nullptr;
+    const tlrmdd_opts *opts = nullptr;
+    // ADMM state (op 3): split variable, scaled dual, penalty center
+    float *z = nullptr, *u = nullptr, *cen = nullptr;
+};
+
+// Split planes of the X space: W (complex64, written by the adjoint product) overlays them with a
+// different element layout, so their padding must be re-zeroed before each assembly.
+int clear_plane_padding(Run &R) {
+    Ctx &c = R.c;
+    if (!c.bf16 || c.ldk == c.nr) return TLRMDD_OK;
+    HIP_TRY(launch_zero_pad(c.xw(), c.ldk, c.nr, 4, c.ldk * c.ldk, c.nprob, 2 * R.xstride, c.s));
+    return TLRMDD_OK;
+}
+
+// record < 0: no f-history entry
+int fin_f(Run &R, int record, double lam, int nsum_parts) {
+    FinArgs f = fin_args(FIN_F, R.c.w.sc);
+    if (record >= 0) {
+        f.fhist = R.single ? nullptr : R.c.D.fhist;
+        f.fhist0 = R.fhist0;
+        f.t = record;
+    }
+    f.lam = lam;
+    return fin(R.c, f, nullptr, nsum_parts, 1);
+}
+
+int objective_fresh(Run &R, int record, double lam) {
+    Ctx &c = R.c;
+    if (int e0 = clear_plane_padding(R)) return e0;
+    HIP_TRY(timed(TLRMDD_K_ASSEMBLE, c.s, [&] {
+        return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)c.w.th,
+                               nullptr, R.X1, nullptr, c.s, c.bf16, R.x2w, c.lo_words());
+    }));
+    int e = gemm_resid(c, R.X1, R.xstride, c.w.Us, c.ldk, R.rstride, c.w.r);
+    if (e) return e;
+    if ((e = split_r_transpose(c))) return e;
+    return fin_f(R, record, lam, resid_tiles(c));
+}
+
+int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *const *D, const void *const *U,
+              void *const *theta, const tlrmdd_opts *opts, double *const *fhist, void *workspace, size_t ws_bytes,
+              hipStream_t s) {
     int st = check_opts(opts);
     if (st != TLRMDD_OK) return st;
     const int64_t nr = plans[0]->H.nr, ns = plans[0]->H.ns;
@@ -666,146 +726,199 @@ int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const 
         if (!D[p] || !U[p] || !theta[p] || !fhist[p]) return fail(TLRMDD_INVALID_ARGUMENT, "NULL data pointer");
     }
     if (!workspace) return fail(TLRMDD_INVALID_ARGUMENT, "workspace is NULL");
-    const bool lbfgs = opts->optimizer == TLRMDD_LBFGS;
-    const int m = lbfgs ? opts->lbfgs_m : 0;
-    const int m1 = lbfgs ? m + 1 : 1;
-    const double lam = opts->lambda;
+    R.opts = opts;
+    R.lbfgs = opts->optimizer == TLRMDD_LBFGS;
+    R.m = R.lbfgs ? opts->lbfgs_m : 0;
+    R.m1 = R.lbfgs ? R.m + 1 : 1;
 
-    Ctx c;
+    Ctx &c = R.c;
     c.nprob = nprob;
     c.nr = nr;
     c.ns = ns;
     c.ldk = round_up(nr, GEMM_PAD);
     c.lds = round_up(ns, GEMM_PAD);
     c.s = s;
-    Tables T;
     std::vector<const HostLayout *> Hs;
     for (int p = 0; p < nprob; ++p) {
-        append_problem(T, plans[p]->H, p, (int64_t)p * 2 * c.ldk * c.ldk, c.ldk);
+        append_problem(R.T, plans[p]->H, p, (int64_t)p * 2 * c.ldk * c.ldk, c.ldk);
         Hs.push_back(&plans[p]->H);
     }
-    build_segments(T, Hs, c.lds, c.ldk);
-    c.pstride = partial_stride(T, c.ldk, c.lds);
-    assign_parts(T, c.pstride);
-    const bool single = (nprob == 1);
-    c.w = carve((char *)workspace, 2, nprob, c.ldk, c.lds, T.theta_total, m1, c.pstride,
-                single ? 0 : tables_bytes(T, nprob));
+    build_segments(R.T, Hs, c.lds, c.ldk);
+    c.pstride = partial_stride(R.T, c.ldk, c.lds);
+    assign_parts(R.T, c.pstride);
+    R.single = (nprob == 1);
+    c.w = carve((char *)workspace, op, nprob, c.ldk, c.lds, R.T.theta_total, R.m1, c.pstride,
+                R.single ? 0 : tables_bytes(R.T, nprob));
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
-    if (single) {
+    if (R.single) {
         c.D = plans[0]->D;
     } else {
-        st = upload_tables(T, nprob, c.w, c.D, fhist, s);
+        st = upload_tables(R.T, nprob, c.w, c.D, fhist, s);
         if (st != TLRMDD_OK) return st;
     }
-    double *fhist0 = single ? fhist[0] : nullptr;
-
-    const int64_t xstride = 2 * c.ldk * c.ldk;   // per-problem X-space stride
-    const int64_t rstride = c.lds * c.ldk;
+    R.fhist0 = R.single ? fhist[0] : nullptr;
+    R.xstride = 2 * c.ldk * c.ldk;   // per-problem X-space stride
+    R.rstride = c.lds * c.ldk;
     c.bf16 = opts->precision == TLRMDD_BF16X3;
-    c.xspace = xstride;
-    float2 *X1 = c.w.XW, *X2 = c.w.XW + c.ldk * c.ldk;
-    const int64_t x2w = c.ldk * c.ldk;           // split form: X2 planes start ldk rows after X1's
-    const int64_t stride2 = 2 * T.theta_total;   // floats between ring slots
-    const int nt = c.D.n_tseg, nrs = c.D.n_rseg;
+    c.xspace = R.xstride;
+    R.X1 = c.w.XW;
+    R.X2 = c.w.XW + c.ldk * c.ldk;
+    R.x2w = c.ldk * c.ldk;               // split form: X2 planes start ldk rows after X1's
+    R.stride2 = 2 * R.T.theta_total;     // floats between ring slots
+    R.nt = c.D.n_tseg;
+    R.nrs = c.D.n_rseg;
+    R.gcur = c.w.g0;
+    R.gprev = c.w.g1;
+    R.z = c.w.z;
+    R.u = c.w.u;
+    R.cen = c.w.cen;
 
-    // ---- setup: stage D, U, theta; zero the residual-space buffers (their padding stays 0) ----
     // padding of the X space must read as zero (the assembly writes only the true nr x nr block)
-    if (c.ldk != nr) HIP_TRY(hipMemsetAsync(c.w.XW, 0, (size_t)nprob * xstride * sizeof(float2), s));
+    if (c.ldk != nr) HIP_TRY(hipMemsetAsync(c.w.XW, 0, (size_t)nprob * R.xstride * sizeof(float2), s));
     for (int p = 0; p < nprob; ++p) {
         if ((st = stage(c, p, (const float2 *)D[p], true))) return st;
-        HIP_TRY(launch_copy2d((const float2 *)U[p], nr, c.w.Us + p * rstride, c.ldk, ns, nr, s));
-        HIP_TRY(hipMemcpyAsync(c.w.th + 2 * T.probs[p].theta, theta[p],
+        HIP_TRY(launch_copy2d((const float2 *)U[p], nr, c.w.Us + p * R.rstride, c.ldk, ns, nr, s));
+        HIP_TRY(hipMemcpyAsync(c.w.th + 2 * R.T.probs[p].theta, theta[p],
                                plans[p]->H.theta_size * sizeof(float2), hipMemcpyDeviceToDevice, s));
     }
     FinArgs f0 = fin_args(FIN_INIT, c.w.sc);
-    if ((st = fin(c, f0, nullptr, 0, 1))) return st;
+    return fin(c, f0, nullptr, 0, 1);
+}
 
-    // Split planes of the X space: W (complex64, written by the adjoint product) overlays them
-    // with a different element layout, so their padding must be re-zeroed before each assembly.
-    auto clear_plane_padding = [&]() -> int {
-        if (!c.bf16 || c.ldk == nr) return TLRMDD_OK;
-        HIP_TRY(launch_zero_pad(c.xw(), c.ldk, nr, 4, c.ldk * c.ldk, nprob, 2 * xstride, s));
-        return TLRMDD_OK;
-    };
-    auto objective_fresh = [&](int t) -> int {
-        if (int e0 = clear_plane_padding()) return e0;
-        HIP_TRY(timed(TLRMDD_K_ASSEMBLE, s, [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)c.w.th,
-                                nullptr, X1, nullptr, s, c.bf16, x2w, c.lo_words()); }));
-        int e = gemm_resid(c, X1, xstride, c.w.Us, c.ldk, rstride, c.w.r);
-        if (e) return e;
-        if ((e = split_r_transpose(c))) return e;
-        FinArgs f = fin_args(FIN_F, c.w.sc);
-        f.fhist = single ? nullptr : c.D.fhist;
-        f.fhist0 = fhist0;
-        f.t = t;
-        f.lam = lam;
-        return fin(c, f, nullptr, resid_tiles(c), 1);
-    };
+// `iters` iterations of L-BFGS (or steepest descent) with exact line search on
+//   f(theta) + lam ||theta - cen||^2     (cen == NULL: the plain Frobenius term; lam == 0: f alone)
+// from the current theta and tracked residual, with fresh pair memory. f-history entries go to
+// index record_base + t (none when record_base < 0).
+int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base) {
+    Ctx &c = R.c;
+    hipStream_t s = c.s;
+    const int m1 = R.m1, nt = R.nt;
+    int st;
+    if ((st = fin(c, fin_args(FIN_RESET, c.w.sc), nullptr, 0, 1))) return st;
     if (lam != 0.0) {
-        HIP_TRY(launch_dot2(c.D.tsegs, nt, c.w.th, c.w.th, c.w.th, c.w.th, c.w.partials, s));
-        if ((st = fin(c, fin_args(FIN_THNORM, c.w.sc), c.D.tcount, 0, 2))) return st;
+        HIP_TRY(launch_pen(c.D.tsegs, nt, c.w.th, cen, nullptr, c.w.partials, s));
+        if ((st = fin(c, fin_args(FIN_THNORM, c.w.sc), c.D.tcount, 0, 1))) return st;
     }
-    if ((st = objective_fresh(0))) return st;
-
-    float *gcur = c.w.g0, *gprev = c.w.g1;
-    for (int t = 0; t < opts->iters; ++t) {
+    for (int t = 0; t < iters; ++t) {
         // gradient from the tracked residual (eqs. DXLR)
-        if ((st = gemm_adjoint(c, c.w.r, X1, xstride))) return st;
-        HIP_TRY(timed(TLRMDD_K_GRAD, s, [&] { return launch_grad(c.D.tiles, c.D.grad_items, c.D.n_grad, c.D.probs, X1, (const float2 *)c.w.th,
-                            (float2 *)gcur, s); }));
-        if (lam != 0.0) HIP_TRY(launch_reg_grad(c.D.tsegs, nt, gcur, c.w.th, (float)(2.0 * lam), s));
+        if ((st = gemm_adjoint(c, c.w.r, R.X1, R.xstride))) return st;
+        HIP_TRY(timed(TLRMDD_K_GRAD, s, [&] {
+            return launch_grad(c.D.tiles, c.D.grad_items, c.D.n_grad, c.D.probs, R.X1, (const float2 *)c.w.th,
+                               (float2 *)R.gcur, s);
+        }));
+        if (lam != 0.0) HIP_TRY(launch_reg_grad(c.D.tsegs, nt, R.gcur, c.w.th, cen, (float)(2.0 * lam), s));
         // direction: steepest descent first, then L-BFGS in vector-free form (Gram pass, two-loop
         // recursion on the (2 m + 1)-term coefficient vectors on the device, one combination pass)
-        if (!lbfgs || t == 0) {
-            HIP_TRY(launch_negate(c.D.tsegs, nt, c.w.p, gcur, s));
+        if (!R.lbfgs || t == 0) {
+            HIP_TRY(launch_negate(c.D.tsegs, nt, c.w.p, R.gcur, s));
         } else {
-            HIP_TRY(launch_gram(c.D.tsegs, nt, m1, gcur, gprev, c.w.Y, c.w.S, stride2, c.w.sc, c.w.partials, s));
+            HIP_TRY(launch_gram(c.D.tsegs, nt, m1, R.gcur, R.gprev, c.w.Y, c.w.S, R.stride2, c.w.sc, c.w.partials, s));
             FinArgs f = fin_args(FIN_GRAM, c.w.sc);
             f.m1 = m1;
             f.gram = c.w.gram;
             f.gstride = gram_stride(m1);
             if ((st = fin(c, f, c.D.tcount, 0, 6 * m1))) return st;
-            HIP_TRY(launch_combine(c.D.tsegs, nt, m1, c.w.p, gcur, c.w.S, c.w.Y, stride2, c.w.sc,
+            HIP_TRY(launch_combine(c.D.tsegs, nt, m1, c.w.p, R.gcur, c.w.S, c.w.Y, R.stride2, c.w.sc,
                                    c.w.gram + (2 * m1 + 1) * (2 * m1 + 1), gram_stride(m1), s));
         }
         // exact line search: a = D C1(theta;p), b = D C2(p)
-        if ((st = clear_plane_padding())) return st;
-        HIP_TRY(timed(TLRMDD_K_ASSEMBLE_DIR, s, [&] { return launch_assemble(true, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)c.w.th,
-                                (const float2 *)c.w.p, X1, X2, s, c.bf16, x2w, c.lo_words()); }));
+        if ((st = clear_plane_padding(R))) return st;
+        HIP_TRY(timed(TLRMDD_K_ASSEMBLE_DIR, s, [&] {
+            return launch_assemble(true, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)c.w.th,
+                                   (const float2 *)c.w.p, R.X1, R.X2, s, c.bf16, R.x2w, c.lo_words());
+        }));
         if (lam != 0.0) {
-            HIP_TRY(launch_dot2(c.D.tsegs, nt, c.w.th, c.w.p, c.w.p, c.w.p, c.w.partials, s));
+            HIP_TRY(launch_pen(c.D.tsegs, nt, c.w.th, cen, c.w.p, c.w.partials, s));
             if ((st = fin(c, fin_args(FIN_LAMTERMS, c.w.sc), c.D.tcount, 0, 2))) return st;
         }
-        if ((st = gemm_line(c, X1, X2, xstride))) return st;
+        if ((st = gemm_line(c, R.X1, R.X2, R.xstride))) return st;
         {
             FinArgs f = fin_args(FIN_LINE, c.w.sc);
             f.lam = lam;
             if ((st = fin(c, f, nullptr, line_tiles(c), 5))) return st;
         }
         // updates
-        HIP_TRY(launch_theta_update(c.D.tsegs, nt, c.w.th, c.w.p, lbfgs ? c.w.S : nullptr, stride2, c.w.sc,
-                                    c.w.partials, s));
+        HIP_TRY(launch_theta_update(c.D.tsegs, nt, c.w.th, c.w.p, R.lbfgs ? c.w.S : nullptr, R.stride2, cen,
+                                    c.w.sc, c.w.partials, s));
         if (lam != 0.0)
             if ((st = fin(c, fin_args(FIN_THNORM, c.w.sc), c.D.tcount, 0, 1))) return st;
-        HIP_TRY(launch_resid_update(c.D.rsegs, nrs, (float *)c.w.r, (const float *)c.w.a, (const float *)c.w.b,
+        HIP_TRY(launch_resid_update(c.D.rsegs, R.nrs, (float *)c.w.r, (const float *)c.w.a, (const float *)c.w.b,
                                     c.w.sc, c.w.partials, s));
         if ((st = split_r_transpose(c))) return st;
-        {
-            FinArgs f = fin_args(FIN_F, c.w.sc);
-            f.fhist = single ? nullptr : c.D.fhist;
-            f.fhist0 = fhist0;
-            f.t = t + 1;
-            f.lam = lam;
-            if ((st = fin(c, f, nullptr, T.rseg_per_prob, 1))) return st;
-        }
-        if (opts->resid_refresh > 0 && (t + 1) % opts->resid_refresh == 0)
-            if ((st = objective_fresh(t + 1))) return st;
-        std::swap(gcur, gprev);
+        if ((st = fin_f(R, record_base >= 0 ? record_base + t + 1 : -1, lam, R.T.rseg_per_prob))) return st;
+        if (R.opts->resid_refresh > 0 && (t + 1) % R.opts->resid_refresh == 0)
+            if ((st = objective_fresh(R, record_base >= 0 ? record_base + t + 1 : -1, lam))) return st;
+        std::swap(R.gcur, R.gprev);
     }
-    for (int p = 0; p < nprob; ++p)
-        HIP_TRY(hipMemcpyAsync(theta[p], c.w.th + 2 * T.probs[p].theta, plans[p]->H.theta_size * sizeof(float2),
-                               hipMemcpyDeviceToDevice, s));
     return TLRMDD_OK;
+}
+
+int run_finish(Run &R, const tlrmdd_plan *plans, void *const *theta) {
+    for (int p = 0; p < R.c.nprob; ++p)
+        HIP_TRY(hipMemcpyAsync(theta[p], R.c.w.th + 2 * R.T.probs[p].theta, plans[p]->H.theta_size * sizeof(float2),
+                               hipMemcpyDeviceToDevice, R.c.s));
+    return TLRMDD_OK;
+}
+
+int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const void *const *U,
+               void *const *theta, const tlrmdd_opts *opts, double *const *fhist, void *workspace,
+               size_t ws_bytes, hipStream_t s) {
+    Run R;
+    int st = run_setup(R, 2, nprob, plans, D, U, theta, opts, fhist, workspace, ws_bytes, s);
+    if (st) return st;
+    const double lam = opts->lambda;
+    if (lam != 0.0) {
+        HIP_TRY(launch_pen(R.c.D.tsegs, R.nt, R.c.w.th, nullptr, nullptr, R.c.w.partials, s));
+        if ((st = fin(R.c, fin_args(FIN_THNORM, R.c.w.sc), R.c.D.tcount, 0, 1))) return st;
+    }
+    if ((st = objective_fresh(R, 0, lam))) return st;
+    if ((st = run_iterate(R, opts->iters, lam, nullptr, 0))) return st;
+    return run_finish(R, plans, theta);
+}
+
+int check_admm(const tlrmdd_admm_opts *a) {
+    if (!a) return fail(TLRMDD_INVALID_ARGUMENT, "admm opts is NULL");
+    if (a->nstages < 1 || !a->lambdas) return fail(TLRMDD_INVALID_ARGUMENT, "need at least one lambda");
+    if (a->outer < 0) return fail(TLRMDD_INVALID_ARGUMENT, "outer must be >= 0");
+    if (!(a->rho > 0.0) || !std::isfinite(a->rho)) return fail(TLRMDD_INVALID_ARGUMENT, "rho must be > 0");
+    for (int k = 0; k < a->nstages; ++k)
+        if (!(a->lambdas[k] >= 0.0) || !std::isfinite(a->lambdas[k]))
+            return fail(TLRMDD_INVALID_ARGUMENT, "lambdas must be finite and >= 0");
+    return check_opts(&a->inner);
+}
+
+// Scaled ADMM with lambda continuation: per stage and outer step, inner.iters L-BFGS iterations of
+// the X-update on f + rho/2 ||theta - (z - u)||^2, then the Z-update and the dual update on the
+// device. f-history: data misfit at the start and after every X-update.
+int admm_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const void *const *U,
+              void *const *theta, const tlrmdd_admm_opts *aopts, double *const *fhist, void *workspace,
+              size_t ws_bytes, hipStream_t s) {
+    int st = check_admm(aopts);
+    if (st) return st;
+    Run R;
+    if ((st = run_setup(R, 3, nprob, plans, D, U, theta, &aopts->inner, fhist, workspace, ws_bytes, s))) return st;
+    Ctx &c = R.c;
+    if ((st = objective_fresh(R, -1, 0.0))) return st;
+    auto record = [&](int k) -> int {
+        FinArgs f = fin_args(FIN_RECORD, c.w.sc);
+        f.fhist = R.single ? nullptr : c.D.fhist;
+        f.fhist0 = R.fhist0;
+        f.t = k;
+        return fin(c, f, nullptr, 0, 1);
+    };
+    if ((st = record(0))) return st;
+    HIP_TRY(launch_admm_update(c.D.tsegs, R.nt, 1, c.w.th, R.z, R.u, R.cen, 1.0f, s));
+    const double rho = aopts->rho;
+    int k = 0;
+    for (int stg = 0; stg < aopts->nstages; ++stg) {
+        const float scale = (float)(1.0 / (1.0 + 2.0 * aopts->lambdas[stg] / rho));
+        for (int o = 0; o < aopts->outer; ++o) {
+            if ((st = run_iterate(R, aopts->inner.iters, 0.5 * rho, R.cen, -1))) return st;
+            if ((st = record(++k))) return st;
+            HIP_TRY(launch_admm_update(c.D.tsegs, R.nt, 0, c.w.th, R.z, R.u, R.cen, scale, s));
+        }
+    }
+    return run_finish(R, plans, theta);
 }
 
 }  // namespace
@@ -927,8 +1040,10 @@ int tlrmdd_solve(tlrmdd_plan plan, const void *D, const void *U, void *theta_ino
     return solve_impl(1, &plan, Dp, Up, Tp, opts, Fp, workspace, ws_bytes, stream);
 }
 
-int tlrmdd_workspace_bytes_batched(int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, size_t *bytes) {
-    g_last_error.clear();
+}  // extern "C"
+
+namespace {
+int ws_bytes_group(int op, int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, size_t *bytes) {
     if (count <= 0 || !plans || !bytes) return fail(TLRMDD_INVALID_ARGUMENT, "bad arguments");
     int st = check_opts(opts);
     if (st) return st;
@@ -946,9 +1061,44 @@ int tlrmdd_workspace_bytes_batched(int count, const tlrmdd_plan *plans, const tl
     }
     build_segments(T, Hs, lds, ldk);
     const int m1 = opts->optimizer == TLRMDD_LBFGS ? opts->lbfgs_m + 1 : 1;
-    *bytes = carve(nullptr, 2, count, ldk, lds, T.theta_total, m1, partial_stride(T, ldk, lds),
+    *bytes = carve(nullptr, op, count, ldk, lds, T.theta_total, m1, partial_stride(T, ldk, lds),
                    count == 1 ? 0 : tables_bytes(T, count)).bytes;
     return TLRMDD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int tlrmdd_workspace_bytes_batched(int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, size_t *bytes) {
+    g_last_error.clear();
+    return ws_bytes_group(2, count, plans, opts, bytes);
+}
+
+int tlrmdd_workspace_bytes_admm(int count, const tlrmdd_plan *plans, const tlrmdd_admm_opts *opts, size_t *bytes) {
+    g_last_error.clear();
+    int st = check_admm(opts);
+    if (st) return st;
+    return ws_bytes_group(3, count, plans, &opts->inner, bytes);
+}
+
+int tlrmdd_admm(tlrmdd_plan plan, const void *D, const void *U, void *theta_inout, const tlrmdd_admm_opts *opts,
+                double *f_hist_dev, void *workspace, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (!plan) return fail(TLRMDD_INVALID_ARGUMENT, "plan is NULL");
+    const void *Dp[1] = {D};
+    const void *Up[1] = {U};
+    void *Tp[1] = {theta_inout};
+    double *Fp[1] = {f_hist_dev};
+    return admm_impl(1, &plan, Dp, Up, Tp, opts, Fp, workspace, ws_bytes, stream);
+}
+
+int tlrmdd_admm_batched(int count, const tlrmdd_plan *plans, const void *const *D, const void *const *U,
+                        void *const *theta_inout, const tlrmdd_admm_opts *opts, double *const *f_hist_dev,
+                        void *workspace, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (count <= 0 || !plans || !D || !U || !theta_inout || !f_hist_dev)
+        return fail(TLRMDD_INVALID_ARGUMENT, "bad arguments");
+    return admm_impl(count, plans, D, U, theta_inout, opts, f_hist_dev, workspace, ws_bytes, stream);
 }
 
 int tlrmdd_solve_batched(int count, const tlrmdd_plan *plans, const void *const *D, const void *const *U,

@@ -114,6 +114,7 @@ constexpr int MAX_LBFGS_M = 32;
 
 struct SolveScalars {
     double f;
+    double fdata;                // 1/2 ||r||^2 of the tracked residual (no penalty)
     double sy, yy, gamma;
     double gp;
     double coef[4];

@@ -292,32 +292,81 @@ __global__ __launch_bounds__(256) void negate_kernel(const VecSeg *__restrict__ 
     st16(p, sg, v);
 }
 
-// g += 2 lambda theta
+// g += 2 lambda (theta - c)   (c = 0 when cen is NULL)
 __global__ __launch_bounds__(256) void reg_grad_kernel(const VecSeg *__restrict__ segs, float *__restrict__ g,
-                                                       const float *__restrict__ th, float lam2) {
+                                                       const float *__restrict__ th, const float *__restrict__ cen,
+                                                       float lam2) {
     const VecSeg sg = segs[blockIdx.x];
     V16 v = ld16(g, sg);
-    const V16 t = ld16(th, sg);
+    V16 t = ld16(th, sg);
+    if (cen) {
+        const V16 c = ld16(cen, sg);
+#pragma unroll
+        for (int u = 0; u < 4 * VQ; ++u) t.v[u] -= c.v[u];
+    }
 #pragma unroll
     for (int u = 0; u < 4 * VQ; ++u) v.v[u] += lam2 * t.v[u];
     st16(g, sg, v);
 }
 
-// partials Re<x0,y0>, Re<x1,y1>
-__global__ __launch_bounds__(256) void dot2_kernel(const VecSeg *__restrict__ segs, const float *__restrict__ x0,
-                                                   const float *__restrict__ y0, const float *__restrict__ x1,
-                                                   const float *__restrict__ y1, double *__restrict__ part) {
+// penalty sums with d = theta - c (c = 0 when cen is NULL):
+//   p == NULL: partial ||d||^2 ;   else partials Re<d, p>, ||p||^2
+__global__ __launch_bounds__(256) void pen_kernel(const VecSeg *__restrict__ segs, const float *__restrict__ th,
+                                                  const float *__restrict__ cen, const float *__restrict__ p,
+                                                  double *__restrict__ part) {
     __shared__ double red[4 * 2];
     const VecSeg sg = segs[blockIdx.x];
-    double a[2] = {dot16(ld16(x0, sg), ld16(y0, sg)), dot16(ld16(x1, sg), ld16(y1, sg))};
+    V16 d = ld16(th, sg);
+    if (cen) {
+        const V16 c = ld16(cen, sg);
+#pragma unroll
+        for (int u = 0; u < 4 * VQ; ++u) d.v[u] -= c.v[u];
+    }
+    if (!p) {
+        double a[1] = {dot16(d, d)};
+        block_sums<1>(a, red);
+        if (threadIdx.x == 0) part[sg.part] = a[0];
+        return;
+    }
+    const V16 vp = ld16(p, sg);
+    double a[2] = {dot16(d, vp), dot16(vp, vp)};
     block_sums<2>(a, red);
     if (threadIdx.x == 0) { part[2 * sg.part] = a[0]; part[2 * sg.part + 1] = a[1]; }
 }
 
-// theta += step p ; S[head] = step p ; partial ||theta||^2
+// ADMM split and scaled dual (init: z = theta, u = 0), then the next X-update's center c = z - u:
+//   z = (theta + u) * scale with scale = 1 / (1 + 2 lambda / rho);  u = u + theta - z
+__global__ __launch_bounds__(256) void admm_update_kernel(const VecSeg *__restrict__ segs, int init,
+                                                          const float *__restrict__ th, float *__restrict__ z,
+                                                          float *__restrict__ uu, float *__restrict__ cen,
+                                                          float scale) {
+    const VecSeg sg = segs[blockIdx.x];
+    const V16 t = ld16(th, sg);
+    V16 vz, vu;
+    if (init) {
+        vz = t;
+#pragma unroll
+        for (int q = 0; q < 4 * VQ; ++q) vu.v[q] = 0.f;
+    } else {
+        vu = ld16(uu, sg);
+#pragma unroll
+        for (int q = 0; q < 4 * VQ; ++q) {
+            vz.v[q] = (t.v[q] + vu.v[q]) * scale;
+            vu.v[q] = vu.v[q] + t.v[q] - vz.v[q];
+        }
+    }
+    st16(z, sg, vz);
+    st16(uu, sg, vu);
+#pragma unroll
+    for (int q = 0; q < 4 * VQ; ++q) vz.v[q] -= vu.v[q];
+    st16(cen, sg, vz);
+}
+
+// theta += step p ; S[head] = step p ; partial ||theta - c||^2 (c = 0 when cen is NULL)
 __global__ __launch_bounds__(256) void theta_update_kernel(const VecSeg *__restrict__ segs, float *__restrict__ th,
                                                            const float *__restrict__ p, float *__restrict__ Sb,
-                                                           int64_t stride2, const SolveScalars *__restrict__ sc,
+                                                           int64_t stride2, const float *__restrict__ cen,
+                                                           const SolveScalars *__restrict__ sc,
                                                            double *__restrict__ part) {
     __shared__ double red[4];
     const VecSeg sg = segs[blockIdx.x];
@@ -334,6 +383,11 @@ __global__ __launch_bounds__(256) void theta_update_kernel(const VecSeg *__restr
         }
         st16(th, sg, v);
         if (Sb) st16(Sb + s.head * stride2, sg, sp);
+    }
+    if (cen) {
+        const V16 c = ld16(cen, sg);
+#pragma unroll
+        for (int u = 0; u < 4 * VQ; ++u) v.v[u] -= c.v[u];
     }
     double acc[1] = {dot16(v, v)};
     block_sums<1>(acc, red);
@@ -451,11 +505,12 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs fa) {
     switch (fa.op) {
         case FIN_INIT:
             s.head = 0; s.count = 0; s.restart = 0; s.frozen = 0; s.gamma = 1.0; s.step = 0.0;
-            s.f = 0.0; s.thnorm2 = 0.0; s.tp = 0.0; s.pnorm2 = 0.0;
+            s.f = 0.0; s.fdata = 0.0; s.thnorm2 = 0.0; s.tp = 0.0; s.pnorm2 = 0.0;
             break;
         case FIN_F: {  // tot[0] = ||r||^2
             const double f = 0.5 * tot[0] + fa.lam * s.thnorm2;
             s.f = f;
+            s.fdata = 0.5 * tot[0];
             if (fa.fhist) fa.fhist[prob][fa.t] = f;
             else if (fa.fhist0) fa.fhist0[fa.t] = f;
             break;
@@ -466,6 +521,13 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs fa) {
         }
         case FIN_THNORM:
             s.thnorm2 = tot[0];
+            break;
+        case FIN_RECORD:  // data misfit of the tracked residual into the history at index t
+            if (fa.fhist) fa.fhist[prob][fa.t] = s.fdata;
+            else if (fa.fhist0) fa.fhist0[fa.t] = s.fdata;
+            break;
+        case FIN_RESET:  // fresh pair memory (a new sub-problem starts from the current theta)
+            s.head = 0; s.count = 0; s.restart = 0; s.gamma = 1.0;
             break;
         case FIN_GRAM: {  // Gram entries of the newest pair and of g; direction coefficients
             const int nb = 2 * m1 + 1, ig = 2 * m1;
@@ -539,7 +601,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs fa) {
             }
             break;
         }
-        case FIN_LAMTERMS:  // (Re<theta,p>, ||p||^2)
+        case FIN_LAMTERMS:  // (Re<theta - c, p>, ||p||^2)
             s.tp = tot[0];
             s.pnorm2 = tot[1];
             break;
@@ -632,16 +694,22 @@ hipError_t launch_combine(const VecSeg *segs, int nseg, int m1, float *p, const 
 hipError_t launch_negate(const VecSeg *segs, int nseg, float *p, const float *g, hipStream_t s) {
     SEGS_LAUNCH(negate_kernel, nseg, s, segs, p, g);
 }
-hipError_t launch_reg_grad(const VecSeg *segs, int nseg, float *g, const float *th, float lam2, hipStream_t s) {
-    SEGS_LAUNCH(reg_grad_kernel, nseg, s, segs, g, th, lam2);
+hipError_t launch_reg_grad(const VecSeg *segs, int nseg, float *g, const float *th, const float *cen, float lam2,
+                           hipStream_t s) {
+    SEGS_LAUNCH(reg_grad_kernel, nseg, s, segs, g, th, cen, lam2);
 }
-hipError_t launch_dot2(const VecSeg *segs, int nseg, const float *x0, const float *y0, const float *x1,
-                       const float *y1, double *part, hipStream_t s) {
-    SEGS_LAUNCH(dot2_kernel, nseg, s, segs, x0, y0, x1, y1, part);
+hipError_t launch_pen(const VecSeg *segs, int nseg, const float *th, const float *cen, const float *p, double *part,
+                      hipStream_t s) {
+    SEGS_LAUNCH(pen_kernel, nseg, s, segs, th, cen, p, part);
+}
+hipError_t launch_admm_update(const VecSeg *segs, int nseg, int init, const float *th, float *z, float *u, float *cen,
+                              float scale, hipStream_t s) {
+    SEGS_LAUNCH(admm_update_kernel, nseg, s, segs, init, th, z, u, cen, scale);
 }
 hipError_t launch_theta_update(const VecSeg *segs, int nseg, float *th, const float *p, float *Sb,
-                               int64_t stride2, const SolveScalars *sc, double *part, hipStream_t s) {
-    SEGS_LAUNCH(theta_update_kernel, nseg, s, segs, th, p, Sb, stride2, sc, part);
+                               int64_t stride2, const float *cen, const SolveScalars *sc, double *part,
+                               hipStream_t s) {
+    SEGS_LAUNCH(theta_update_kernel, nseg, s, segs, th, p, Sb, stride2, cen, sc, part);
 }
 hipError_t launch_resid_update(const VecSeg *segs, int nseg, float *r, const float *a, const float *b,
                                const SolveScalars *sc, double *part, hipStream_t s) {

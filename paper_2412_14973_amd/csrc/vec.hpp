@@ -15,7 +15,7 @@ struct VecSeg {
 constexpr int VEC_CH = 4096;   // floats per segment (a multiple of 1024; offsets multiples of 4)
 
 enum FinOp : int32_t {
-    FIN_INIT = 0, FIN_F, FIN_F_OUT, FIN_THNORM, FIN_GRAM, FIN_LAMTERMS, FIN_LINE
+    FIN_INIT = 0, FIN_F, FIN_F_OUT, FIN_THNORM, FIN_GRAM, FIN_LAMTERMS, FIN_LINE, FIN_RECORD, FIN_RESET
 };
 
 struct FinArgs {
@@ -42,11 +42,15 @@ hipError_t launch_combine(const VecSeg *segs, int nseg, int m1, float *p, const 
                           const float *Yb, int64_t stride2, const SolveScalars *sc, const double *coef,
                           int64_t cstride, hipStream_t s);
 hipError_t launch_negate(const VecSeg *segs, int nseg, float *p, const float *g, hipStream_t s);
-hipError_t launch_reg_grad(const VecSeg *segs, int nseg, float *g, const float *th, float lam2, hipStream_t s);
-hipError_t launch_dot2(const VecSeg *segs, int nseg, const float *x0, const float *y0, const float *x1,
-                       const float *y1, double *part, hipStream_t s);
+hipError_t launch_reg_grad(const VecSeg *segs, int nseg, float *g, const float *th, const float *cen, float lam2,
+                           hipStream_t s);
+hipError_t launch_pen(const VecSeg *segs, int nseg, const float *th, const float *cen, const float *p, double *part,
+                      hipStream_t s);
+hipError_t launch_admm_update(const VecSeg *segs, int nseg, int init, const float *th, float *z, float *u, float *cen,
+                              float scale, hipStream_t s);
 hipError_t launch_theta_update(const VecSeg *segs, int nseg, float *th, const float *p, float *Sb,
-                               int64_t stride2, const SolveScalars *sc, double *part, hipStream_t s);
+                               int64_t stride2, const float *cen, const SolveScalars *sc, double *part,
+                               hipStream_t s);
 hipError_t launch_resid_update(const VecSeg *segs, int nseg, float *r, const float *a, const float *b,
                                const SolveScalars *sc, double *part, hipStream_t s);
 hipError_t launch_finalize(const FinArgs &fa, int nprob, hipStream_t s);

@@ -246,6 +246,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--solver", choices=["lbfgs", "admm"], default="lbfgs",
+                    help="admm: lambda stages 10, 1, 0.1 x --admm-outer X-updates of --admm-inner L-BFGS iterations")
+    ap.add_argument("--admm-outer", type=int, default=4)
+    ap.add_argument("--admm-inner", type=int, default=8)
     ap.add_argument("--error-table", action="store_true",
                     help="per-frequency error of FP32 and BF16x3 solves against the FP64 oracle (large workload)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -280,21 +284,35 @@ def main():
     wl = synth.batched() if args.workload == "batched" else synth.large()
     nfreq = args.nfreq or (len(wl.freqs) if args.workload == "batched" else 4)
     iters = args.iters or wl.iters
+    admm = args.solver == "admm"
+    lams = (10.0, 1.0, 0.1)
+    if admm:
+        iters = len(lams) * args.admm_outer * args.admm_inner
     geom, Ds, Us, ths, plans = build_inputs(wl, torch, tl, nfreq)
     dev = torch.device("cuda")
     perm = torch.from_numpy(tl.hilbert_order(geom.rec_ix, geom.rec_iy)).to(dev)
     ns, nr = geom.ns, geom.nr
     opts = tl.make_opts(iters, precision=prec)
-    ws = torch.empty(tl.batched_workspace_bytes(plans, opts), dtype=torch.uint8, device=dev)
+    if admm:
+        aopts = tl.make_admm_opts(lams, args.admm_outer, args.admm_inner, precision=prec)
+        ws = torch.empty(tl.admm_workspace_bytes(plans, aopts), dtype=torch.uint8, device=dev)
+    else:
+        ws = torch.empty(tl.batched_workspace_bytes(plans, opts), dtype=torch.uint8, device=dev)
     out_th = [t.clone() for t in ths]
     out_fh = [torch.empty(iters + 1, dtype=torch.float64, device=dev) for _ in range(nfreq)]
-    log(f"workspace {ws.numel() / 2**30:.2f} GiB, {nfreq} frequencies, {iters} iterations")
+    log(f"workspace {ws.numel() / 2**30:.2f} GiB, {nfreq} frequencies, {iters} iterations"
+        + (f" (ADMM {len(lams)} stages x {args.admm_outer} x {args.admm_inner})" if admm else ""))
 
     def step():
+        nonlocal out_fh
         Dh = [tl.permute_columns(D, perm) for D in Ds]
         Uh = [tl.permute_columns(U, perm) for U in Us]
-        tl.solve_batched(plans, Dh, Uh, ths, iters, precision=prec, workspace=ws, out_thetas=out_th,
-                         out_fhist=out_fh)
+        if admm:
+            _, out_fh = tl.admm_batched(plans, Dh, Uh, ths, lams=lams, outer=args.admm_outer, inner=args.admm_inner,
+                                        precision=prec, workspace=ws)
+        else:
+            tl.solve_batched(plans, Dh, Uh, ths, iters, precision=prec, workspace=ws, out_thetas=out_th,
+                             out_fhist=out_fh)
 
     for w in range(args.warmup):
         step()
@@ -352,7 +370,10 @@ def main():
         "dtype": "f32" if prec == tl.FP32 else "bf16x3",
         "data": "synthetic",
         "config": {"workload": wl.name if nfreq == len(wl.freqs) else f"{wl.name}[first {nfreq}]",
-                   "nr": nr, "ns": ns, "frequencies": nfreq, "iters": iters, "optimizer": "lbfgs(m=5)",
+                   "nr": nr, "ns": ns, "frequencies": nfreq, "iters": iters,
+                   "optimizer": ("admm(lambda 10,1,0.1; %d x %d L-BFGS(m=5) per stage)" % (args.admm_outer,
+                                                                                        args.admm_inner))
+                   if admm else "lbfgs(m=5)",
                    "precision": "fp32-mfma" if prec == tl.FP32 else "bf16x3-mfma"},
         "roofline": {"bound": "mfma",
                      "kernel": ("cgemm_f32_kernel<GM_LINE>" if prec == tl.FP32 else "cgemm_bf16x3_kernel<GM_LINE>")

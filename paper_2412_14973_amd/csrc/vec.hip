@@ -123,9 +123,15 @@ __global__ void permute_kernel(const float2 *__restrict__ in, const int64_t *__r
 // ---------------------------------------------------------------------------
 // segment helpers
 // ---------------------------------------------------------------------------
+}  // namespace
+// wave-wide FP64 sum of the ROCm device library (DPP row shifts and lane reads, fixed order, no LDS)
+extern "C" __device__ double __ockl_wfred_add_f64(double);
+namespace {
+
+__device__ __forceinline__ double wave_sum64(double v) { return __ockl_wfred_add_f64(v); }
+
 __device__ __forceinline__ double block_sum(double v, double *red) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    v = wave_sum64(v);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) red[w] = v;
     __syncthreads();
@@ -189,9 +195,7 @@ __device__ __forceinline__ double dot16(const V16 &x, const V16 &y) {
 template <int N>
 __device__ __forceinline__ void block_sums(double (&v)[N], double *red) {
 #pragma unroll
-    for (int k = 0; k < N; ++k)
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    for (int k = 0; k < N; ++k) v[k] = wave_sum64(v[k]);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0)
 #pragma unroll

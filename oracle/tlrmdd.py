@@ -24,6 +24,12 @@ Section / equation map (names as in the paper):
     gradient is 2 lambda theta; lambda continuation 10 -> 1 -> 0.1.
   * ADMM solver, X-update / Z-update (eq. proxofFro2) / dual update: scaled
     ADMM on min f(theta) + lambda ||theta||^2 with the split theta = z.
+  * Hyper-parameter selection and the examples' rank study: per-tile SVD of a
+    reference solution, numerical rank k = #{sigma >= eps v0} with v0 the
+    largest singular value over all tiles of that size (eps = 0.01), the tile
+    size with the fewest factor entries; warm start L = U_k S_k^(1/2),
+    R = S_k^(1/2) V_k^H, Q Q^T = X_ii by the Takagi factorisation (eq. qqinit),
+    Z_ii = X_ii for dense diagonal tiles.
 
 Readings where the paper is silent (the same readings the GPU path follows):
   * gradient convention: 2 df/d(conj theta) = df/dRe + i df/dIm (the paper
@@ -574,6 +580,104 @@ def admm(T: Tiling, D, U, theta0, lams=(10.0, 1.0, 0.1), outer: int = 5, inner: 
                 record(lam, k, dict(theta=theta.copy(), z=z.copy(), u=u.copy()))
         stage_end.append(len(f_hist) - 1)
     return AdmmResult(theta, z, u, np.array(f_hist), stage_end)
+
+
+# ============================================================================
+# Rank / tile-size estimate and warm start (Hyper-parameter selection and
+# initialization; the examples' entry-count study)
+# ============================================================================
+def split_sizes(nr: int, d: int) -> List[int]:
+    """Tiles of size d covering nr receivers, the last one ragged when d does not divide nr."""
+    sizes = [d] * (nr // d)
+    if nr % d:
+        sizes.append(nr % d)
+    return sizes
+
+
+def tile_ranks(X: np.ndarray, d: int, eps: float = 0.01):
+    """Numerical ranks of the tiles of a symmetric X at tile size d.
+
+    Every tile (i, j), i >= j, is decomposed by SVD; v0 is the largest singular
+    value over all of them and a tile's rank is the number of its singular
+    values >= eps v0 (0 possible; all of them = numerically full rank).
+    Returns (sizes, k_off in t order, k_diag, v0)."""
+    nr = X.shape[0]
+    sizes = split_sizes(nr, d)
+    start = np.concatenate([[0], np.cumsum(sizes)])
+    sv = {}
+    for i in range(len(sizes)):
+        for j in range(i + 1):
+            blk = X[start[i]:start[i + 1], start[j]:start[j + 1]]
+            sv[(i, j)] = np.linalg.svd(blk, compute_uv=False)
+    v0 = max(float(v[0]) for v in sv.values())
+    k_off = [int(np.count_nonzero(sv[(i, j)] >= eps * v0)) for i in range(len(sizes)) for j in range(i)]
+    k_diag = [int(np.count_nonzero(sv[(i, i)] >= eps * v0)) for i in range(len(sizes))]
+    return sizes, k_off, k_diag, v0
+
+
+def layout_from_ranks(sizes, k_off, k_diag):
+    """Layout of the estimate: ranks of at least 1; a diagonal tile is dense when its rank is at
+    least half its size (the symmetric part of a dense Z_ii then has no more degrees of freedom,
+    d(d+1)/2, than Q_ii's d k), else Q Q^T.
+    Returns (rank_off, rank_diag, entries), entries = complex unknowns of the layout."""
+    rank_off = [max(1, int(k)) for k in k_off]
+    rank_diag = [(-1 if k >= (sizes[i] + 1) // 2 else max(1, int(k))) for i, k in enumerate(k_diag)]
+    entries = 0
+    t = 0
+    for i in range(len(sizes)):
+        for j in range(i):
+            entries += rank_off[t] * (sizes[i] + sizes[j])
+            t += 1
+        entries += sizes[i] * (sizes[i] if rank_diag[i] < 0 else rank_diag[i])
+    return rank_off, rank_diag, entries
+
+
+def choose_layout(X: np.ndarray, candidates, eps: float = 0.01):
+    """The candidate tile size whose estimated layout has the fewest entries (first on ties).
+    Returns (d, sizes, rank_off, rank_diag, entries_per_candidate)."""
+    best = None
+    entries = []
+    for d in candidates:
+        sizes, k_off, k_diag, _ = tile_ranks(X, int(d), eps)
+        ro, rd, n = layout_from_ranks(sizes, k_off, k_diag)
+        entries.append(n)
+        if best is None or n < best[0]:
+            best = (n, int(d), sizes, ro, rd)
+    return best[1], best[2], best[3], best[4], entries
+
+
+def takagi(Xs: np.ndarray, k: int) -> np.ndarray:
+    """Q (n x k) with Q Q^T the rank-k Takagi truncation of a complex symmetric Xs.
+
+    From the SVD Xs = U S V^H and symmetry, conj(V) = U D with D diagonal unitary
+    (distinct singular values), so Xs = U S D U^T = W S W^T with W = U D^(1/2):
+    Q = U_k D_k^(1/2) S_k^(1/2)."""
+    U, S, Vh = np.linalg.svd(Xs)
+    V = Vh.conj().T
+    dph = np.einsum("ij,ij->j", U.conj(), V.conj())[:k]     # d_i = U_i^H conj(V_i)
+    dph = dph / np.abs(dph)
+    return U[:, :k] * (np.sqrt(dph) * np.sqrt(S[:k]))[None, :]
+
+
+def warm_start(T: Tiling, X: np.ndarray) -> np.ndarray:
+    """theta from a reference solution X tiled by T (Hyper-parameter selection and initialization):
+    off-diagonal L = U_k S_k^(1/2), R = S_k^(1/2) V_k^H from the SVD of X_ij; diagonal
+    Q_ii by the Takagi factorisation truncated to k_ii, or Z_ii = X_ii when dense."""
+    theta = np.zeros(T.size, dtype=np.complex128)
+    for i in range(T.n):
+        blk = X[_sl(T, i), _sl(T, i)]
+        if T.kdiag[i] < 0:
+            theta[T.off_diag[i]:T.off_diag[i] + blk.size] = blk.ravel()
+        else:
+            k = T.kdiag[i]
+            theta[T.off_diag[i]:T.off_diag[i] + T.d[i] * k] = takagi(blk, k).ravel()
+    for t, (i, j, k) in enumerate(T.pairs):
+        U, S, Vh = np.linalg.svd(X[_sl(T, i), _sl(T, j)])
+        L = U[:, :k] * np.sqrt(S[:k])[None, :]
+        R = np.sqrt(S[:k])[:, None] * Vh[:k, :]
+        theta[T.off_L[t]:T.off_L[t] + L.size] = L.ravel()
+        theta[T.off_R[t]:T.off_R[t] + R.size] = R.ravel()
+    return theta
 
 
 # ============================================================================

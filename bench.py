@@ -176,6 +176,72 @@ def serving(tl, torch, args):
     return out
 
 
+def estimate(tl, torch, args):
+    """Rank / tile-size estimate and warm start on the 32 x 32-receiver problem (nr = ns = 1024).
+
+    Per sampled frequency: reference solution X from the benchmark (Tikhonov, one dense tile) solve
+    and from the synthetic truth; GPU per-tile FP64 SVD over tile sizes 64, 128, 256 (eps = 0.01)
+    -> layout with the fewest entries; warm start of that layout; 100-iteration solves from the warm
+    start and from the random start, compared by objective and by distance to the truth."""
+    import numpy as np
+
+    import synth
+    wl = synth.batched()
+    geom = wl.geometry()
+    dev = torch.device("cuda")
+    perm_np = tl.hilbert_order(geom.rec_ix, geom.rec_iy)
+    perm = torch.from_numpy(perm_np).to(dev)
+    nf = len(wl.freqs)
+    idx = sorted(set(np.linspace(0, nf - 1, args.estimate_freqs).round().astype(int).tolist()))
+    cand = [64, 128, 256]
+    iters = args.iters or 100
+    recs = []
+    for i in idx:
+        prob = wl.problem(i, geom)
+        D = tl.permute_columns(torch.from_numpy(prob.D.astype(np.complex64)).to(dev), perm)
+        U = tl.permute_columns(torch.from_numpy(prob.U.astype(np.complex64)).to(dev), perm)
+        Xt = np.ascontiguousarray(prob.X_true[np.ix_(perm_np, perm_np)], dtype=np.complex64)
+        Xt_d = torch.from_numpy(Xt).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Xb, _ = tl.benchmark_solve(D, U, lam=args.bench_lambda, iters=iters)
+        torch.cuda.synchronize()
+        t_bench = time.perf_counter() - t0
+        rec = {"freq_index": i, "freq_hz": float(wl.freqs[i]), "benchmark_solve_s": t_bench,
+               "benchmark_rel_err_to_truth": float(torch.linalg.norm(Xb - Xt_d) / torch.linalg.norm(Xt_d))}
+        for src, Xr in (("benchmark", Xb), ("truth", Xt_d)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            d, sizes, ro, rd, ent = tl.choose_layout(Xr, cand, eps=0.01)
+            t_est = time.perf_counter() - t0
+            plan = tl.Plan(sizes, ro, rd, geom.ns)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            th_w = tl.warm_start(plan, Xr)
+            torch.cuda.synchronize()
+            t_warm = time.perf_counter() - t0
+            th_r = torch.from_numpy(synth.init_theta(plan.theta_size, wl.config_id, i).astype(np.complex64)).to(dev)
+            out = {"d": d, "entries": [int(e) for e in ent], "dense_entries": int(geom.nr) ** 2,
+                   "mean_rank_off": float(np.mean(ro)) if len(ro) else 0.0,
+                   "dense_diagonal_tiles": int(np.sum(rd < 0)), "estimate_s": t_est, "warm_start_s": t_warm}
+            for start, th0 in (("warm", th_w), ("random", th_r)):
+                th, fh = tl.solve(plan, D, U, th0, iters)
+                _, _, Xs = tl.forward(plan, D, U, th, want_X=True)
+                out[start] = {"f0": float(fh[0].item()), "fT": float(fh[-1].item()),
+                              "rel_err_to_truth": float(torch.linalg.norm(Xs - Xt_d) / torch.linalg.norm(Xt_d))}
+            rec[src] = out
+        recs.append(rec)
+        log(f"freq {i} ({rec['freq_hz']:.1f} Hz): benchmark d {rec['benchmark']['d']} "
+            f"est {rec['benchmark']['estimate_s'] * 1e3:.1f} ms warm {rec['benchmark']['warm_start_s'] * 1e3:.1f} ms; "
+            f"fT warm {rec['benchmark']['warm']['fT']:.4g} vs random {rec['benchmark']['random']['fT']:.4g}")
+    est = [r[s]["estimate_s"] for r in recs for s in ("benchmark", "truth")]
+    return {"metric": "rank estimate (3 tile sizes) ms per frequency", "value": 1e3 * float(np.mean(est)),
+            "unit": "ms", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": "nr1024_ns1024_64freq_adaptive (sampled frequencies)", "candidates": cand,
+                       "eps": 0.01, "iters": iters, "benchmark_lambda": args.bench_lambda},
+            "records": recs}
+
+
 def error_table(tl, torch, args):
     """Mixed-precision error table on the 64 x 64-receiver problem (nr 4096, ns 2048,
     tile 256, rank 32) at 10 and 30 dB: FP32 and BF16x3 solves against the FP64 oracle."""
@@ -237,7 +303,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["batched", "large", "serving"], default="batched")
+    ap.add_argument("--workload", choices=["batched", "large", "serving", "estimate"], default="batched")
+    ap.add_argument("--estimate-freqs", type=int, default=6, help="estimate: frequencies sampled over the band")
+    ap.add_argument("--bench-lambda", type=float, default=3.0, help="estimate: Tikhonov lambda of the benchmark solve")
     ap.add_argument("--requests", type=int, default=16, help="serving: requests in the Poisson stream")
     ap.add_argument("--max-active", type=int, default=4, help="serving: concurrent solves")
     ap.add_argument("--hbm-budget-gib", type=float, default=96.0, help="serving: admission budget")
@@ -279,6 +347,9 @@ def main():
         return
     if args.workload == "serving":
         print(json.dumps(serving(tl, torch, args)), flush=True)
+        return
+    if args.workload == "estimate":
+        print(json.dumps(estimate(tl, torch, args)), flush=True)
         return
     prec = tl.FP32 if args.precision == "fp32" else tl.BF16X3
     wl = synth.batched() if args.workload == "batched" else synth.large()

@@ -202,6 +202,49 @@ int tlrmdd_admm_batched(int count, const tlrmdd_plan *plans, const void *const *
                         const tlrmdd_admm_opts *opts, double *const *f_hist_dev,
                         void *workspace, size_t ws_bytes, hipStream_t stream);
 
+/* ---- rank / tile-size estimate and warm start --------------------------
+ * (Hyper-parameter selection and initialization; the examples' rank study.)
+ * X is a reference solution: device, nr x nr complex64, symmetric, in the
+ * receiver order of the solve (Hilbert). Tiles of size d cover nr with a
+ * ragged last tile. Every tile X_ij, i >= j, is decomposed in FP64 on the GPU
+ * by one-sided Jacobi (round-robin pairs, sweeps until no pair is rotated,
+ * at most 30). Tile sizes up to 1024.
+ *
+ * tlrmdd_tile_ranks: v0 = largest singular value over all tiles; the rank of a
+ * tile is the number of its singular values >= eps * v0 (0 possible; all of
+ * them = numerically full rank). k_off_out: host, N(N-1)/2 entries in t order
+ * (t = i(i-1)/2 + j); k_diag_out: host, N entries; v0_out: host (nullable).
+ * Synchronises `stream` (host outputs). Workspace: tlrmdd_workspace_bytes_ranks.
+ *
+ * tlrmdd_choose_layout: for every candidate tile size the estimated layout
+ * (ranks at least 1; a diagonal tile dense, rank_diag = -1, when its rank is
+ * at least half its size, else Q Q^T) and its entry count (complex unknowns:
+ * sum k_t (d_i + d_j) + sum of d_i^2 or d_i k_ii) into entries_out[c] (host,
+ * nullable); the candidate with the fewest entries (first on ties) is written
+ * to d_out, rank_off_out (capacity off_capacity) and rank_diag_out (capacity
+ * diag_capacity); status 1 when a chosen layout does not fit. Workspace: the
+ * largest candidate's tlrmdd_workspace_bytes_ranks. Synchronises `stream`.
+ *
+ * tlrmdd_warm_start: theta_out (device, theta_size complex64 of the plan's
+ * layout) from X: L = U_k S_k^(1/2), R = S_k^(1/2) V_k^H of every off-diagonal
+ * tile (truncated SVD, k = the layout's rank), Q = U_k D^(1/2) S_k^(1/2) of
+ * every Q Q^T tile (Takagi factorisation from the SVD of the symmetric tile,
+ * d_c = u_c^H conj(v_c); eq. qqinit), Z_ii = X_ii for dense tiles.
+ * Synchronises `stream` (the sweep count is decided on the host).
+ * Workspace: tlrmdd_workspace_bytes_warm. */
+int tlrmdd_workspace_bytes_ranks(int64_t nr, int32_t d, size_t *bytes);
+int tlrmdd_tile_ranks(const void *X, int64_t nr, int32_t d, double eps, int32_t *k_off_out,
+                      int32_t *k_diag_out, double *v0_out, void *workspace, size_t ws_bytes,
+                      hipStream_t stream);
+int tlrmdd_choose_layout(const void *X, int64_t nr, const int32_t *candidates, int32_t ncand,
+                         double eps, int32_t *d_out, int64_t *entries_out,
+                         int32_t *rank_off_out, int64_t off_capacity,
+                         int32_t *rank_diag_out, int64_t diag_capacity,
+                         void *workspace, size_t ws_bytes, hipStream_t stream);
+int tlrmdd_workspace_bytes_warm(tlrmdd_plan plan, size_t *bytes);
+int tlrmdd_warm_start(tlrmdd_plan plan, const void *X, void *theta_out, void *workspace,
+                      size_t ws_bytes, hipStream_t stream);
+
 /* Adjoint (cross-correlation) solution X_adj = D^H U (MDD Solver Evaluation section: the
  * adjoint solution that needs no inversion). D, U: device ns x nr complex64; X_out: device
  * nr x nr complex64. Uses the plan's sizes only (its tiles are ignored). Workspace: as for

@@ -271,6 +271,65 @@ def admm(plan, D, U, theta0, lams=(10.0, 1.0, 0.1), outer=5, inner=10, rho=1.0, 
     return theta, fh
 
 
+def tile_split(nr, d):
+    """Tile sizes of size d covering nr (ragged last tile), as the estimate uses them."""
+    return np.array([d] * (nr // d) + ([nr % d] if nr % d else []), dtype=np.int32)
+
+
+def _ranks_workspace(nr, d, device):
+    n = ctypes.c_size_t()
+    _lib.check(_lib.load().tlrmdd_workspace_bytes_ranks(int(nr), int(d), ctypes.byref(n)),
+               "tlrmdd_workspace_bytes_ranks")
+    return torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=device)
+
+
+def tile_ranks(X, d, eps=0.01):
+    """Numerical ranks of the tiles of a symmetric X (device, nr x nr complex64) at tile size d:
+    #{sigma >= eps v0} per tile, v0 the largest singular value of all tiles (FP64 Jacobi on the GPU).
+    Returns (k_off in t order, k_diag, v0); synchronises the stream."""
+    nr = int(X.shape[0])
+    ws = _ranks_workspace(nr, d, X.device)   # validates nr and d
+    N = len(tile_split(nr, d))
+    ko = np.zeros(max(N * (N - 1) // 2, 1), dtype=np.int32)
+    kd = np.zeros(N, dtype=np.int32)
+    v0 = ctypes.c_double()
+    _lib.check(_lib.load().tlrmdd_tile_ranks(_ptr(X), nr, int(d), float(eps), ko.ctypes.data, kd.ctypes.data,
+                                             ctypes.byref(v0), _ptr(ws), ws.numel(), _stream()), "tlrmdd_tile_ranks")
+    return ko[:N * (N - 1) // 2], kd, v0.value
+
+
+def choose_layout(X, candidates, eps=0.01):
+    """Tile size with the fewest factor entries among `candidates` and its layout (ranks >= 1, dense
+    diagonal tiles where k_ii >= d_i / 2). Returns (d, tile_size, rank_off, rank_diag, entries)."""
+    nr = int(X.shape[0])
+    cand = np.ascontiguousarray(candidates, dtype=np.int32)
+    nmax = max(len(tile_split(nr, int(d))) for d in cand)
+    ro = np.zeros(max(nmax * (nmax - 1) // 2, 1), dtype=np.int32)
+    rd = np.zeros(nmax, dtype=np.int32)
+    ent = np.zeros(len(cand), dtype=np.int64)
+    dsel = ctypes.c_int32()
+    ws = _ranks_workspace(nr, int(cand.max()), X.device)
+    _lib.check(_lib.load().tlrmdd_choose_layout(_ptr(X), nr, cand.ctypes.data, len(cand), float(eps),
+                                                ctypes.byref(dsel), ent.ctypes.data, ro.ctypes.data, ro.size,
+                                                rd.ctypes.data, rd.size, _ptr(ws), ws.numel(), _stream()),
+               "tlrmdd_choose_layout")
+    sizes = tile_split(nr, dsel.value)
+    N = len(sizes)
+    return dsel.value, sizes, ro[:N * (N - 1) // 2].copy(), rd[:N].copy(), ent
+
+
+def warm_start(plan, X):
+    """Factors of `plan`'s layout from a reference solution X (device, nr x nr complex64): truncated
+    SVD of every off-diagonal tile, Takagi factor of every Q Q^T tile, Z = X_ii for dense ones."""
+    n = ctypes.c_size_t()
+    _lib.check(_lib.load().tlrmdd_workspace_bytes_warm(plan.handle, ctypes.byref(n)), "tlrmdd_workspace_bytes_warm")
+    ws = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=X.device)
+    theta = torch.zeros(plan.theta_size, dtype=torch.complex64, device=X.device)
+    _lib.check(_lib.load().tlrmdd_warm_start(plan.handle, _ptr(X), _ptr(theta), _ptr(ws), ws.numel(), _stream()),
+               "tlrmdd_warm_start")
+    return theta
+
+
 class KernelTimer:
     """Context manager: per-kind summed kernel milliseconds and launch counts (HIP events)."""
 

@@ -80,6 +80,16 @@ _SIGS = {
                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(c_admm_opts),
                                            ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_size_t,
                                            ctypes.c_void_p]),
+    "tlrmdd_workspace_bytes_ranks": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "tlrmdd_tile_ranks": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "tlrmdd_choose_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_double, ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "tlrmdd_workspace_bytes_warm": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "tlrmdd_warm_start": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_size_t, ctypes.c_void_p]),
     "tlrmdd_timing_begin": (ctypes.c_int, []),
     "tlrmdd_timing_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
 }

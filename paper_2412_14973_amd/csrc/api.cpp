@@ -14,6 +14,7 @@
 
 #include "common.hpp"
 #include "tlrmdd.h"
+#include "svd.hpp"
 #include "vec.hpp"
 
 using namespace tlr;
@@ -1150,6 +1151,277 @@ int tlrmdd_timing_end(double *ms, int64_t *launches) {
         if (launches) launches[k] = cnt[k];
     }
     return status;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// per-tile SVD: rank / tile-size estimate and warm start
+// ---------------------------------------------------------------------------
+namespace {
+
+struct SvdHost {
+    std::vector<SvdTile> tiles;
+    std::vector<int32_t> pair_tile;
+    int64_t nW = 0, nV = 0, nS = 0;
+    int maxnp = 2;
+};
+
+// jacobi == false: the tile is only gathered (no rotations, no V), e.g. a dense diagonal tile of a warm start
+void svd_add_tile(SvdHost &S, int m, int n, int64_t row0, int64_t col0, bool with_v, bool jacobi = true) {
+    SvdTile t;
+    t.trans = m < n ? 1 : 0;   // decompose the transpose of a wide tile: A is never wider than tall
+    t.pad = 0;
+    if (t.trans) std::swap(m, n);
+    t.m = m;
+    t.n = n;
+    t.row0 = row0;
+    t.col0 = col0;
+    t.offW = S.nW;
+    t.offV = with_v ? S.nV : -1;
+    t.offS = S.nS;
+    t.npad = n + (n & 1);
+    t.pair0 = (int32_t)S.pair_tile.size();
+    S.nW += (int64_t)m * n;
+    if (with_v) S.nV += (int64_t)n * n;
+    S.nS += n;
+    if (jacobi) {
+        S.maxnp = std::max(S.maxnp, t.npad);
+        for (int k = 0; k < t.npad / 2; ++k) S.pair_tile.push_back((int32_t)S.tiles.size());
+    }
+    S.tiles.push_back(t);
+}
+
+std::vector<int> split_sizes(int64_t nr, int d) {
+    std::vector<int> sz((size_t)(nr / d), d);
+    if (nr % d) sz.push_back((int)(nr % d));
+    return sz;
+}
+
+// tiles (i, j), i >= j, in the order i(i+1)/2 + j
+SvdHost svd_grid(int64_t nr, int d, bool with_v) {
+    SvdHost S;
+    const std::vector<int> sz = split_sizes(nr, d);
+    std::vector<int64_t> st(sz.size() + 1, 0);
+    for (size_t i = 0; i < sz.size(); ++i) st[i + 1] = st[i] + sz[i];
+    for (size_t i = 0; i < sz.size(); ++i)
+        for (size_t j = 0; j <= i; ++j) svd_add_tile(S, sz[i], sz[j], st[i], st[j], with_v);
+    return S;
+}
+
+struct SvdWs {
+    double2 *W = nullptr, *V = nullptr;
+    double *sig = nullptr, *v0 = nullptr;
+    int32_t *order = nullptr, *kout = nullptr, *flags = nullptr, *pair_tile = nullptr;
+    SvdTile *tiles = nullptr;
+    WarmItem *items = nullptr;
+    size_t bytes = 0;
+};
+
+SvdWs svd_carve(char *base, const SvdHost &S, int nitems) {
+    SvdWs w;
+    size_t o = 0;
+    auto take = [&](size_t b) -> char * {
+        char *p = base ? base + o : nullptr;
+        o += align256(b);
+        return p;
+    };
+    w.W = (double2 *)take((size_t)S.nW * sizeof(double2));
+    if (S.nV) w.V = (double2 *)take((size_t)S.nV * sizeof(double2));
+    w.sig = (double *)take((size_t)S.nS * sizeof(double));
+    w.order = (int32_t *)take((size_t)S.nS * sizeof(int32_t));
+    w.kout = (int32_t *)take(S.tiles.size() * sizeof(int32_t));
+    w.v0 = (double *)take(sizeof(double));
+    w.flags = (int32_t *)take(2 * sizeof(int32_t));
+    w.tiles = (SvdTile *)take(S.tiles.size() * sizeof(SvdTile));
+    w.pair_tile = (int32_t *)take(S.pair_tile.size() * sizeof(int32_t));
+    w.items = (WarmItem *)take((size_t)std::max(nitems, 1) * sizeof(WarmItem));
+    w.bytes = o;
+    return w;
+}
+
+// Jacobi sweeps on the gathered tiles, then sigma per column. Tables must already be on the device.
+// Sweeps are enqueued two at a time; the host reads the convergence flag in between and stops
+// enqueueing once no pair was rotated (synchronises the stream).
+int svd_run(const SvdHost &S, const SvdWs &w, const float2 *X, int64_t ldx, hipStream_t s) {
+    const int nt = (int)S.tiles.size();
+    const int npairs = (int)S.pair_tile.size();
+    HIP_TRY(launch_svd_gather(w.tiles, nt, X, ldx, w.W, w.V, s));
+    HIP_TRY(hipMemsetAsync(w.flags, 0, 2 * sizeof(int32_t), s));
+    for (int sw = 0; sw < SVD_MAX_SWEEPS && npairs > 0; ++sw) {
+        for (int r = 0; r < S.maxnp - 1; ++r)
+            HIP_TRY(launch_svd_round(w.tiles, w.pair_tile, npairs, r, w.W, w.V, w.flags, w.flags + 1, SVD_TOL, s));
+        HIP_TRY(launch_svd_sweep_end(w.flags, w.flags + 1, s));
+        if (sw % 2 == 1) {
+            int32_t done = 0;
+            HIP_TRY(hipMemcpyAsync(&done, w.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (done) break;
+        }
+    }
+    HIP_TRY(launch_svd_sigma(w.tiles, nt, w.W, w.sig, s));
+    return TLRMDD_OK;
+}
+
+int svd_upload(const SvdHost &S, const SvdWs &w, const std::vector<WarmItem> *items, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(w.tiles, S.tiles.data(), S.tiles.size() * sizeof(SvdTile), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w.pair_tile, S.pair_tile.data(), S.pair_tile.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s));
+    if (items && !items->empty())
+        HIP_TRY(hipMemcpyAsync(w.items, items->data(), items->size() * sizeof(WarmItem), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));   // the host tables may be freed after this
+    return TLRMDD_OK;
+}
+
+int check_rank_args(const void *X, int64_t nr, int32_t d, double eps) {
+    if (!X) return fail(TLRMDD_INVALID_ARGUMENT, "X is NULL");
+    if (nr <= 0 || nr > ((int64_t)1 << 20)) return fail(TLRMDD_INVALID_ARGUMENT, "nr out of range");
+    if (d < 1 || d > SVD_MAX_N) return fail(TLRMDD_INVALID_ARGUMENT, "tile size must be in [1, 1024]");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(TLRMDD_INVALID_ARGUMENT, "eps must be finite and >= 0");
+    return TLRMDD_OK;
+}
+
+// ranks of all tiles at size d into host vectors (t order / diagonal order); synchronises the stream
+int tile_ranks_impl(const void *X, int64_t nr, int32_t d, double eps, std::vector<int32_t> &koff,
+                    std::vector<int32_t> &kdiag, double *v0, void *workspace, size_t ws_bytes, hipStream_t s) {
+    int st = check_rank_args(X, nr, d, eps);
+    if (st) return st;
+    if (!workspace) return fail(TLRMDD_INVALID_ARGUMENT, "workspace is NULL");
+    const SvdHost S = svd_grid(nr, d, false);
+    const SvdWs w = svd_carve((char *)workspace, S, 0);
+    if (w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
+    if ((st = svd_upload(S, w, nullptr, s))) return st;
+    if ((st = svd_run(S, w, (const float2 *)X, nr, s))) return st;
+    HIP_TRY(launch_svd_rank(w.tiles, (int)S.tiles.size(), w.sig, S.nS, eps, w.kout, w.v0, s));
+    std::vector<int32_t> k(S.tiles.size());
+    double v = 0.0;
+    HIP_TRY(hipMemcpyAsync(k.data(), w.kout, k.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&v, w.v0, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int N = (int)split_sizes(nr, d).size();
+    koff.clear();
+    kdiag.assign(N, 0);
+    for (int i = 0; i < N; ++i) {
+        for (int j = 0; j < i; ++j) koff.push_back(k[(size_t)i * (i + 1) / 2 + j]);
+        kdiag[i] = k[(size_t)i * (i + 1) / 2 + i];
+    }
+    if (v0) *v0 = v;
+    return TLRMDD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tlrmdd_workspace_bytes_ranks(int64_t nr, int32_t d, size_t *bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(TLRMDD_INVALID_ARGUMENT, "bytes is NULL");
+    if (nr <= 0 || nr > ((int64_t)1 << 20) || d < 1 || d > SVD_MAX_N)
+        return fail(TLRMDD_INVALID_ARGUMENT, "nr or tile size out of range");
+    *bytes = svd_carve(nullptr, svd_grid(nr, d, false), 0).bytes;
+    return TLRMDD_OK;
+}
+
+int tlrmdd_tile_ranks(const void *X, int64_t nr, int32_t d, double eps, int32_t *k_off_out, int32_t *k_diag_out,
+                      double *v0_out, void *workspace, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (!k_off_out || !k_diag_out) return fail(TLRMDD_INVALID_ARGUMENT, "output arrays are NULL");
+    std::vector<int32_t> ko, kd;
+    int st = tile_ranks_impl(X, nr, d, eps, ko, kd, v0_out, workspace, ws_bytes, stream);
+    if (st) return st;
+    std::copy(ko.begin(), ko.end(), k_off_out);
+    std::copy(kd.begin(), kd.end(), k_diag_out);
+    return TLRMDD_OK;
+}
+
+int tlrmdd_choose_layout(const void *X, int64_t nr, const int32_t *candidates, int32_t ncand, double eps,
+                         int32_t *d_out, int64_t *entries_out, int32_t *rank_off_out, int64_t off_capacity,
+                         int32_t *rank_diag_out, int64_t diag_capacity, void *workspace, size_t ws_bytes,
+                         hipStream_t stream) {
+    g_last_error.clear();
+    if (!candidates || ncand < 1 || !d_out || !rank_off_out || !rank_diag_out)
+        return fail(TLRMDD_INVALID_ARGUMENT, "bad arguments");
+    int64_t best = -1;
+    for (int c = 0; c < ncand; ++c) {
+        std::vector<int32_t> ko, kd;
+        int st = tile_ranks_impl(X, nr, candidates[c], eps, ko, kd, nullptr, workspace, ws_bytes, stream);
+        if (st) return st;
+        const std::vector<int> sz = split_sizes(nr, candidates[c]);
+        // layout of the estimate: ranks >= 1; dense diagonal when k_ii >= d_i / 2
+        int64_t n = 0;
+        size_t t = 0;
+        for (size_t i = 0; i < sz.size(); ++i) {
+            for (size_t j = 0; j < i; ++j, ++t) {
+                ko[t] = std::max(1, ko[t]);
+                n += (int64_t)ko[t] * (sz[i] + sz[j]);
+            }
+            kd[i] = (kd[i] >= (sz[i] + 1) / 2) ? -1 : std::max(1, kd[i]);
+            n += (int64_t)sz[i] * (kd[i] < 0 ? sz[i] : kd[i]);
+        }
+        if (entries_out) entries_out[c] = n;
+        if (best < 0 || n < best) {
+            if ((int64_t)ko.size() > off_capacity || (int64_t)kd.size() > diag_capacity)
+                return fail(TLRMDD_INVALID_ARGUMENT, "rank arrays too small for a candidate tile size");
+            best = n;
+            *d_out = candidates[c];
+            std::copy(ko.begin(), ko.end(), rank_off_out);
+            std::copy(kd.begin(), kd.end(), rank_diag_out);
+        }
+    }
+    return TLRMDD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+SvdHost warm_grid(const HostLayout &H, std::vector<WarmItem> &items) {
+    SvdHost S;
+    items.clear();
+    for (const TileDesc &td : H.tiles) {
+        WarmItem it{};
+        it.tile = (int32_t)S.tiles.size();
+        it.kind = td.kind == TILE_LR ? WARM_LR : (td.kind == TILE_QQ ? WARM_QQ : WARM_DENSE);
+        it.k = td.k;
+        it.offA = td.offA;
+        it.offB = td.offB;
+        items.push_back(it);
+        // a dense diagonal tile is copied as is (gathered, never rotated)
+        svd_add_tile(S, td.di, td.dj, td.row0, td.col0, td.kind != TILE_DENSE, td.kind != TILE_DENSE);
+    }
+    return S;
+}
+}  // namespace
+
+extern "C" {
+
+int tlrmdd_workspace_bytes_warm(tlrmdd_plan plan, size_t *bytes) {
+    g_last_error.clear();
+    if (!plan || !bytes) return fail(TLRMDD_INVALID_ARGUMENT, "plan / bytes is NULL");
+    for (int d : plan->H.d)
+        if (d > SVD_MAX_N) return fail(TLRMDD_INVALID_ARGUMENT, "tile sizes above 1024 are not supported");
+    std::vector<WarmItem> items;
+    const SvdHost S = warm_grid(plan->H, items);
+    *bytes = svd_carve(nullptr, S, (int)items.size()).bytes;
+    return TLRMDD_OK;
+}
+
+int tlrmdd_warm_start(tlrmdd_plan plan, const void *X, void *theta_out, void *workspace, size_t ws_bytes,
+                      hipStream_t stream) {
+    g_last_error.clear();
+    if (!plan || !X || !theta_out || !workspace) return fail(TLRMDD_INVALID_ARGUMENT, "NULL argument");
+    for (int d : plan->H.d)
+        if (d > SVD_MAX_N) return fail(TLRMDD_INVALID_ARGUMENT, "tile sizes above 1024 are not supported");
+    std::vector<WarmItem> items;
+    const SvdHost S = warm_grid(plan->H, items);
+    const SvdWs w = svd_carve((char *)workspace, S, (int)items.size());
+    if (w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
+    int st = svd_upload(S, w, &items, stream);
+    if (st) return st;
+    if ((st = svd_run(S, w, (const float2 *)X, plan->H.nr, stream))) return st;
+    HIP_TRY(launch_svd_order(w.tiles, (int)S.tiles.size(), w.sig, w.order, stream));
+    HIP_TRY(launch_svd_factors(w.tiles, w.items, (int)items.size(), w.W, w.V, w.sig, w.order, (const float2 *)X,
+                               plan->H.nr, (float2 *)theta_out, stream));
+    return TLRMDD_OK;
 }
 
 int hilbert_order(const int32_t *ix, const int32_t *iy, int64_t n, int64_t *perm_out) {

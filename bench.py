@@ -176,6 +176,59 @@ def serving(tl, torch, args):
     return out
 
 
+def tlr_product(tl, torch, args):
+    """Dense forward (assemble X, r = D X - U on MFMA) vs the tile low-rank product (no dense X)
+    on the 64 x 64-receiver problem (nr 4096, ns 2048, tile 256, rank 32): time per call, flops."""
+    import numpy as np
+
+    import synth
+    wl = synth.large()
+    nfreq = args.nfreq or 4
+    geom, Ds, Us, ths, plans = build_inputs(wl, torch, tl, nfreq)
+    dev = torch.device("cuda")
+    perm = torch.from_numpy(tl.hilbert_order(geom.rec_ix, geom.rec_iy)).to(dev)
+    ns, nr = geom.ns, geom.nr
+    recs = []
+    for i in range(nfreq):
+        D = tl.permute_columns(Ds[i], perm)
+        U = tl.permute_columns(Us[i], perm)
+        plan, th = plans[i], ths[i]
+        ws_d = plan.workspace(tl._lib.OP_FORWARD)
+        ws_t = torch.empty(tl.tlr_workspace_bytes(plan), dtype=torch.uint8, device=dev)
+        lay = wl.layout(i)
+        d = np.asarray(lay.tile_size)
+        k_pairs = sum(int(k) * (int(d[a]) + int(d[b])) for (a, b, k) in
+                      [(a, b, lay.rank_off[a * (a - 1) // 2 + b]) for a in range(len(d)) for b in range(a)])
+        k_diag = sum(int(d[a]) * (int(d[a]) if lay.rank_diag[a] < 0 else int(lay.rank_diag[a])) for a in range(len(d)))
+        flops_tlr = 2 * 8.0 * ns * (k_pairs + k_diag)
+        flops_dense = 8.0 * ns * nr * nr
+        out = {}
+        for name, fn in (("dense", lambda: tl.forward(plan, D, U, th, workspace=ws_d)[0]),
+                         ("tlr", lambda: tl.forward_tlr(plan, D, U, th, workspace=ws_t)[0])):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(args.steps + 2):
+                t0 = time.perf_counter()
+                fv = fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            out[name] = {"ms": 1e3 * float(np.median(ts)), "f": float(fv.item())}
+        out["dense"]["gemm_tflops_equiv"] = flops_dense / out["dense"]["ms"] / 1e9
+        out["tlr"]["tflops"] = flops_tlr / out["tlr"]["ms"] / 1e9
+        rec = {"freq_index": i, "flops_dense": flops_dense, "flops_tlr": flops_tlr,
+               "flop_ratio": flops_tlr / flops_dense, **out,
+               "speedup": out["dense"]["ms"] / out["tlr"]["ms"],
+               "rel_f_diff": abs(out["tlr"]["f"] - out["dense"]["f"]) / out["dense"]["f"]}
+        recs.append(rec)
+        log(f"freq {i}: dense {out['dense']['ms']:.2f} ms, tlr {out['tlr']['ms']:.2f} ms "
+            f"(flop ratio {rec['flop_ratio']:.3f}, speedup {rec['speedup']:.2f}, rel f diff {rec['rel_f_diff']:.1e})")
+    return {"metric": "forward f = 1/2||D C(theta) - U||^2, dense vs tile low-rank product", "unit": "ms",
+            "value": float(np.mean([r["tlr"]["ms"] for r in recs])), "higher_is_better": False, "n_gpus": 1,
+            "data": "synthetic", "config": {"workload": wl.name, "nr": nr, "ns": ns, "frequencies": nfreq},
+            "records": recs}
+
+
 def estimate(tl, torch, args):
     """Rank / tile-size estimate and warm start on the 32 x 32-receiver problem (nr = ns = 1024).
 
@@ -303,7 +356,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["batched", "large", "serving", "estimate"], default="batched")
+    ap.add_argument("--workload", choices=["batched", "large", "serving", "estimate", "tlr"], default="batched")
     ap.add_argument("--estimate-freqs", type=int, default=6, help="estimate: frequencies sampled over the band")
     ap.add_argument("--bench-lambda", type=float, default=3.0, help="estimate: Tikhonov lambda of the benchmark solve")
     ap.add_argument("--requests", type=int, default=16, help="serving: requests in the Poisson stream")
@@ -350,6 +403,9 @@ def main():
         return
     if args.workload == "estimate":
         print(json.dumps(estimate(tl, torch, args)), flush=True)
+        return
+    if args.workload == "tlr":
+        print(json.dumps(tlr_product(tl, torch, args)), flush=True)
         return
     prec = tl.FP32 if args.precision == "fp32" else tl.BF16X3
     wl = synth.batched() if args.workload == "batched" else synth.large()

@@ -271,6 +271,27 @@ def admm(plan, D, U, theta0, lams=(10.0, 1.0, 0.1), outer=5, inner=10, rho=1.0, 
     return theta, fh
 
 
+def forward_tlr(plan, D, U, theta, want_r=False, workspace=None):
+    """f = 1/2 ||D C(theta) - U||^2 by the tile low-rank product (no dense X); returns (f, r or None)."""
+    _check_problem(plan, D, U, theta)
+    f = torch.empty((), dtype=torch.float64, device=D.device)
+    r = torch.empty((plan.ns, plan.nr), dtype=torch.complex64, device=D.device) if want_r else None
+    if workspace is None:
+        n = ctypes.c_size_t()
+        _lib.check(_lib.load().tlrmdd_workspace_bytes_tlr(plan.handle, ctypes.byref(n)), "tlrmdd_workspace_bytes_tlr")
+        workspace = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=D.device)
+    _lib.check(_lib.load().tlrmdd_forward_tlr(plan.handle, _ptr(D), _ptr(U), _ptr(theta), _ptr(f),
+                                              _ptr(r), _ptr(workspace),
+                                              workspace.numel(), _stream()), "tlrmdd_forward_tlr")
+    return f, r
+
+
+def tlr_workspace_bytes(plan):
+    n = ctypes.c_size_t()
+    _lib.check(_lib.load().tlrmdd_workspace_bytes_tlr(plan.handle, ctypes.byref(n)), "tlrmdd_workspace_bytes_tlr")
+    return int(n.value)
+
+
 def tile_split(nr, d):
     """Tile sizes of size d covering nr (ragged last tile), as the estimate uses them."""
     return np.array([d] * (nr // d) + ([nr % d] if nr % d else []), dtype=np.int32)

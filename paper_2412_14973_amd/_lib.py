@@ -90,6 +90,8 @@ _SIGS = {
                                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "tlrmdd_workspace_bytes_warm": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
     "tlrmdd_warm_start": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "tlrmdd_workspace_bytes_tlr": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "tlrmdd_forward_tlr": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_size_t, ctypes.c_void_p]),
     "tlrmdd_timing_begin": (ctypes.c_int, []),
     "tlrmdd_timing_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
 }

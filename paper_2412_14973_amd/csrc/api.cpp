@@ -15,6 +15,7 @@
 #include "common.hpp"
 #include "tlrmdd.h"
 #include "svd.hpp"
+#include "tlr.hpp"
 #include "vec.hpp"
 
 using namespace tlr;
@@ -1421,6 +1422,198 @@ int tlrmdd_warm_start(tlrmdd_plan plan, const void *X, void *theta_out, void *wo
     HIP_TRY(launch_svd_order(w.tiles, (int)S.tiles.size(), w.sig, w.order, stream));
     HIP_TRY(launch_svd_factors(w.tiles, w.items, (int)items.size(), w.W, w.V, w.sig, w.order, (const float2 *)X,
                                plan->H.nr, (float2 *)theta_out, stream));
+    return TLRMDD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// tile low-rank product D C(theta) without the dense X
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TlrHost {
+    int N = 0;
+    int64_t Kpmax = 0, K1p = 0, K2p = 0, dp = 0;   // padded operand shapes (uniform per tile)
+    std::vector<PackItem> packA, packB;
+    std::vector<GatherItem> gather;
+    std::vector<std::pair<int, int>> runs;          // [first, last] tiles of equal size
+};
+
+struct TlrWs {
+    float2 *Ds, *A, *P, *B, *Pcol, *R;
+    double *partials;
+    SolveScalars *sc;
+    PackItem *pa, *pb;
+    GatherItem *gi;
+    size_t bytes;
+};
+
+TlrHost tlr_plan(const HostLayout &H, int64_t lds) {
+    TlrHost T;
+    const int N = H.N;
+    T.N = N;
+    // rank of tile (i, j) as a product of two factors, and the TileDesc of its factors
+    std::vector<int> tix(N * N, -1);   // index into H.tiles: diagonal tiles first, then t order
+    for (int i = 0; i < N; ++i) tix[i * N + i] = i;
+    {
+        int t = 0;
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < i; ++j, ++t) tix[i * N + j] = tix[j * N + i] = N + t;
+    }
+    auto kk = [&](int i, int j) -> int {
+        const TileDesc &td = H.tiles[tix[i * N + j]];
+        return (i == j && td.kind == TILE_DENSE) ? H.d[i] : td.k;
+    };
+    std::vector<int64_t> K1(N, 0);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) K1[i] += kk(i, j);
+    int64_t kmax = 0, dmax = 0;
+    for (int i = 0; i < N; ++i) {
+        kmax = std::max(kmax, K1[i]);
+        dmax = std::max<int64_t>(dmax, H.d[i]);
+    }
+    T.Kpmax = round_up(dmax, GEMM_BK);
+    T.K1p = round_up(kmax, GEMM_PAD);
+    T.K2p = round_up(kmax, GEMM_BK);   // sum over i of k(i, j) equals K1[j] (ranks are symmetric)
+    T.dp = round_up(dmax, GEMM_PAD);
+    const int64_t sA = T.Kpmax * T.K1p, sP = lds * T.K1p, sB = T.K2p * T.dp, sPc = lds * T.K2p;
+    std::vector<int64_t> roff(N, 0);   // running row offset inside B_j / column offset inside Pcol_j
+    for (int i = 0; i < N; ++i) {
+        int64_t coff = 0;
+        for (int j = 0; j < N; ++j) {
+            const TileDesc &td = H.tiles[tix[i * N + j]];
+            const int k = kk(i, j), di = H.d[i], dj = H.d[j];
+            PackItem a{}, b{};
+            a.rows = di; a.cols = k; a.dst = i * sA + coff; a.ldd = T.K1p;
+            b.rows = k; b.cols = dj; b.dst = j * sB + roff[j] * T.dp; b.ldd = T.dp;
+            if (i == j && td.kind == TILE_DENSE) {
+                a.op = PACK_IDENT;
+                b.op = PACK_SYM; b.src = td.offA; b.lds = di;
+            } else if (i == j) {   // Q Q^T
+                a.op = PACK_COPY; a.src = td.offA; a.lds = k;
+                b.op = PACK_TRANS; b.src = td.offA; b.lds = k;
+            } else if (i > j) {    // tile (i, j): L (d_i x k) R (k x d_j)
+                a.op = PACK_COPY; a.src = td.offA; a.lds = k;
+                b.op = PACK_COPY; b.src = td.offB; b.lds = dj;
+            } else {               // tile (j, i) holds L (d_j x k), R (k x d_i): X_ij = R^T L^T
+                a.op = PACK_TRANS; a.src = td.offB; a.lds = di;
+                b.op = PACK_TRANS; b.src = td.offA; b.lds = k;
+            }
+            T.packA.push_back(a);
+            T.packB.push_back(b);
+            GatherItem g{};
+            g.k = k;
+            g.src = i * sP + coff; g.lds = T.K1p;
+            g.dst = j * sPc + roff[j]; g.ldd = T.K2p;
+            T.gather.push_back(g);
+            coff += k;
+            roff[j] += k;
+        }
+    }
+    for (int i = 0; i < N;) {   // runs of equal tile size share one batched launch per stage
+        int e = i;
+        while (e + 1 < N && H.d[e + 1] == H.d[i]) ++e;
+        T.runs.push_back({i, e});
+        i = e + 1;
+    }
+    return T;
+}
+
+TlrWs tlr_carve(char *base, const TlrHost &T, int64_t lds, int64_t ldk) {
+    TlrWs w{};
+    size_t o = 0;
+    auto take = [&](size_t b) -> char * {
+        char *p = base ? base + o : nullptr;
+        o += align256(b);
+        return p;
+    };
+    const size_t c8 = sizeof(float2);
+    const int64_t N = T.N;
+    w.Ds = (float2 *)take((size_t)lds * ldk * c8);
+    w.A = (float2 *)take((size_t)N * T.Kpmax * T.K1p * c8);
+    w.P = (float2 *)take((size_t)N * lds * T.K1p * c8);
+    w.B = (float2 *)take((size_t)N * T.K2p * T.dp * c8);
+    w.Pcol = (float2 *)take((size_t)N * lds * T.K2p * c8);
+    w.R = (float2 *)take((size_t)N * lds * T.dp * c8);
+    w.partials = (double *)take((size_t)N * (lds / GEMM_BM) * (T.dp / GEMM_BN) * sizeof(double));
+    w.sc = (SolveScalars *)take(sizeof(SolveScalars));
+    w.pa = (PackItem *)take(T.packA.size() * sizeof(PackItem));
+    w.pb = (PackItem *)take(T.packB.size() * sizeof(PackItem));
+    w.gi = (GatherItem *)take(T.gather.size() * sizeof(GatherItem));
+    w.bytes = o;
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tlrmdd_workspace_bytes_tlr(tlrmdd_plan plan, size_t *bytes) {
+    g_last_error.clear();
+    if (!plan || !bytes) return fail(TLRMDD_INVALID_ARGUMENT, "plan / bytes is NULL");
+    const TlrHost T = tlr_plan(plan->H, plan->lds);
+    *bytes = tlr_carve(nullptr, T, plan->lds, plan->ldk).bytes;
+    return TLRMDD_OK;
+}
+
+int tlrmdd_forward_tlr(tlrmdd_plan plan, const void *D, const void *U, const void *theta, double *f_dev,
+                       void *r_out, void *workspace, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (!plan || !D || !U || !theta || !f_dev || !workspace) return fail(TLRMDD_INVALID_ARGUMENT, "NULL argument");
+    const HostLayout &H = plan->H;
+    const int64_t ns = H.ns, nr = H.nr, lds = plan->lds, ldk = plan->ldk;
+    const TlrHost T = tlr_plan(H, lds);
+    const TlrWs w = tlr_carve((char *)workspace, T, lds, ldk);
+    if (w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
+    hipStream_t s = stream;
+    // tables (blocking upload: the host vectors may go away afterwards)
+    HIP_TRY(hipMemcpyAsync(w.pa, T.packA.data(), T.packA.size() * sizeof(PackItem), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w.pb, T.packB.data(), T.packB.size() * sizeof(PackItem), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w.gi, T.gather.data(), T.gather.size() * sizeof(GatherItem), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int64_t N = T.N;
+    // padding of the packed operands must read as zero
+    HIP_TRY(hipMemsetAsync(w.A, 0, (size_t)N * T.Kpmax * T.K1p * sizeof(float2), s));
+    HIP_TRY(hipMemsetAsync(w.B, 0, (size_t)N * T.K2p * T.dp * sizeof(float2), s));
+    HIP_TRY(hipMemsetAsync(w.Pcol, 0, (size_t)N * lds * T.K2p * sizeof(float2), s));
+    HIP_TRY(launch_stage_d((const float2 *)D, ns, nr, w.Ds, ldk, nullptr, lds, s));
+    HIP_TRY(launch_tlr_pack(w.pa, (int)T.packA.size(), (const float2 *)theta, w.A, s));
+    HIP_TRY(launch_tlr_pack(w.pb, (int)T.packB.size(), (const float2 *)theta, w.B, s));
+    const int64_t tiles2 = (lds / GEMM_BM) * (T.dp / GEMM_BN);
+    for (const auto &run : T.runs) {   // stage 1: P_i = D_:,i A_i
+        const int i0 = run.first, cnt = run.second - run.first + 1, di = H.d[i0];
+        GemmArgs g = gemm_args();
+        g.A = w.Ds + H.start[i0]; g.lda = ldk; g.sA = di;
+        g.B = w.A + i0 * T.Kpmax * T.K1p; g.ldb = T.K1p; g.sB = T.Kpmax * T.K1p;
+        g.C = w.P + i0 * lds * T.K1p; g.ldc = T.K1p; g.sC = lds * T.K1p;
+        g.M = (int)lds; g.N = (int)T.K1p; g.K = (int)round_up(di, GEMM_BK);
+        HIP_TRY(launch_cgemm(GM_STORE, g, cnt, s));
+    }
+    HIP_TRY(launch_tlr_gather(w.gi, (int)T.gather.size(), w.P, w.Pcol, lds, s));
+    for (const auto &run : T.runs) {   // stage 2: r_:,j = Pcol_j B_j - U_:,j
+        const int j0 = run.first, cnt = run.second - run.first + 1, dj = H.d[j0];
+        GemmArgs g = gemm_args();
+        g.A = w.Pcol + j0 * lds * T.K2p; g.lda = T.K2p; g.sA = lds * T.K2p;
+        g.B = w.B + j0 * T.K2p * T.dp; g.ldb = T.dp; g.sB = T.K2p * T.dp;
+        g.C = w.R + j0 * lds * T.dp; g.ldc = T.dp; g.sC = lds * T.dp;
+        g.E = (const float2 *)U + H.start[j0]; g.lde = nr; g.sE = dj;
+        g.partials = w.partials + j0 * tiles2; g.sP = tiles2;
+        g.M = (int)lds; g.N = (int)T.dp; g.K = (int)T.K2p;
+        g.Me = (int)ns; g.Ne = dj;
+        HIP_TRY(launch_cgemm(GM_RESID, g, cnt, s));
+    }
+    FinArgs f = fin_args(FIN_F_OUT, w.sc);
+    f.partials = w.partials;
+    f.pstride = N * tiles2;
+    f.counts = nullptr;
+    f.ucount = (int32_t)(N * tiles2);
+    f.nsum = 1;
+    f.fout = f_dev;
+    HIP_TRY(launch_finalize(f, 1, s));
+    if (r_out)
+        for (int j = 0; j < N; ++j)
+            HIP_TRY(launch_copy2d(w.R + j * lds * T.dp, T.dp, (float2 *)r_out + H.start[j], nr, ns, H.d[j], s));
     return TLRMDD_OK;
 }
 

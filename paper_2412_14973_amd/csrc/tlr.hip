@@ -1,0 +1,71 @@
+// Tile low-rank matrix product D C(theta) without the dense X (the paper's
+// conclusions name it as the way to cut the cost of the dense products).
+//
+// Column block j of D X is sum_i D_:,i X_ij with every tile a product of two
+// factors, X_ij = A_ij B_ij:
+//   i > j: A = L_ij, B = R_ij;   i < j: A = R_ji^T, B = L_ji^T  (X_ij = X_ji^T);
+//   i = j: A = Q_ii, B = Q_ii^T, or (dense) A = I, B = (Z_ii + Z_ii^T)/2.
+// Stage 1 (one GEMM per tile row i): P_i = D_:,i [A_i0 | A_i1 | ...].
+// Stage 2 (one GEMM per tile column j): r_:,j = [P_0j | P_1j | ...] [B_0j; B_1j; ...] - U_:,j,
+// where P_ij is the column block of P_i that multiplies B_ij. The kernels below pack the
+// factor blocks into the GEMM operands and gather the P blocks; the products themselves run
+// on the FP32 MFMA GEMM.
+#include <algorithm>
+
+#include "common.hpp"
+#include "tlr.hpp"
+
+namespace tlr {
+namespace {
+
+// one packed block per work item: dst[r * ldd + c] = op(src) for r < rows, c < cols
+__global__ __launch_bounds__(256) void tlr_pack_kernel(const PackItem *__restrict__ items,
+                                                       const float2 *__restrict__ theta,
+                                                       float2 *__restrict__ dst_base) {
+    const PackItem it = items[blockIdx.x];
+    float2 *dst = dst_base + it.dst;
+    const float2 *src = theta + it.src;
+    const int64_t n = (int64_t)it.rows * it.cols;
+    for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.y * blockDim.x) {
+        const int r = (int)(e / it.cols), c = (int)(e % it.cols);
+        float2 v;
+        switch (it.op) {
+            case PACK_COPY: v = src[(int64_t)r * it.lds + c]; break;            // src rows x cols
+            case PACK_TRANS: v = src[(int64_t)c * it.lds + r]; break;           // src cols x rows
+            case PACK_IDENT: v = make_float2(r == c ? 1.f : 0.f, 0.f); break;
+            default: {                                                           // (Z + Z^T)/2
+                const float2 a = src[(int64_t)r * it.lds + c], b = src[(int64_t)c * it.lds + r];
+                v = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y + b.y));
+            }
+        }
+        dst[(int64_t)r * it.ldd + c] = v;
+    }
+}
+
+// Pcol_j[:, roff + c] = P_i[:, coff + c] for c < k, every source row (lds rows)
+__global__ __launch_bounds__(256) void tlr_gather_kernel(const GatherItem *__restrict__ items,
+                                                         const float2 *__restrict__ P, float2 *__restrict__ Pcol,
+                                                         int64_t rows) {
+    const GatherItem it = items[blockIdx.x];
+    for (int64_t s = blockIdx.y; s < rows; s += gridDim.y)
+        for (int c = threadIdx.x; c < it.k; c += blockDim.x)
+            Pcol[it.dst + s * it.ldd + c] = P[it.src + s * it.lds + c];
+}
+
+}  // namespace
+
+hipError_t launch_tlr_pack(const PackItem *items, int nitems, const float2 *theta, float2 *dst, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tlr_pack_kernel, dim3((unsigned)nitems, 16), dim3(256), 0, s, items, theta, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_tlr_gather(const GatherItem *items, int nitems, const float2 *P, float2 *Pcol, int64_t rows,
+                             hipStream_t s) {
+    if (nitems <= 0 || rows <= 0) return hipSuccess;
+    const unsigned gy = (unsigned)std::min<int64_t>(rows, 256);
+    hipLaunchKernelGGL(tlr_gather_kernel, dim3((unsigned)nitems, gy), dim3(256), 0, s, items, P, Pcol, rows);
+    return hipGetLastError();
+}
+
+}  // namespace tlr

@@ -304,7 +304,10 @@ def error_table(tl, torch, args):
     import synth
     iters = args.iters or 100
     rows = []
-    for snr in (10.0, 30.0):
+    variants = [("fp32", tl.FP32, 0), ("bf16x3", tl.BF16X3, 0)]
+    if args.resid_refresh > 0:
+        variants.append((f"fp32_refresh{args.resid_refresh}", tl.FP32, args.resid_refresh))
+    for snr in [float(v) for v in args.error_snrs.split(",")]:
         wl = synth.large(snr_db=snr, config_id=4)
         f_idx = 10
         geom = wl.geometry()
@@ -322,10 +325,10 @@ def error_table(tl, torch, args):
         th = torch.from_numpy(th64).to(dev)
         plan = tl.Plan.from_layout(lay, geom.ns)
         res = {}
-        for name, prec in (("fp32", tl.FP32), ("bf16x3", tl.BF16X3)):
+        for name, prec, refresh in variants:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            thT, fh = tl.solve(plan, D, U, th, iters, precision=prec)
+            thT, fh = tl.solve(plan, D, U, th, iters, precision=prec, resid_refresh=refresh)
             torch.cuda.synchronize()
             res[name] = (thT.cpu().numpy().astype(np.complex128), time.perf_counter() - t0)
             log(f"snr {snr}: {name} solve {res[name][1]:.2f} s")
@@ -373,6 +376,9 @@ def main():
     ap.add_argument("--admm-inner", type=int, default=8)
     ap.add_argument("--error-table", action="store_true",
                     help="per-frequency error of FP32 and BF16x3 solves against the FP64 oracle (large workload)")
+    ap.add_argument("--error-snrs", default="10,30", help="error table: SNRs in dB")
+    ap.add_argument("--resid-refresh", type=int, default=20,
+                    help="error table: also an FP32 solve that recomputes r = D C(theta) - U every this many iterations")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -498,6 +504,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name if nfreq == len(wl.freqs) else f"{wl.name}[first {nfreq}]",
                    "nr": nr, "ns": ns, "frequencies": nfreq, "iters": iters,
+                   "resid_refresh": tl.RESID_REFRESH,
                    "optimizer": ("admm(lambda 10,1,0.1; %d x %d L-BFGS(m=5) per stage)" % (args.admm_outer,
                                                                                         args.admm_inner))
                    if admm else "lbfgs(m=5)",

@@ -88,7 +88,8 @@ typedef struct {
     int32_t lbfgs_m;        /* L-BFGS memory, 1..32 (default 5)                     */
     int32_t precision;      /* TLRMDD_FP32 or TLRMDD_BF16X3                         */
     double  lambda;         /* Frobenius regulariser lambda ||theta||^2 (0 = none)  */
-    int32_t resid_refresh;  /* recompute r = D C(theta) - U every this many iters (0 = never) */
+    int32_t resid_refresh;  /* recompute r = D C(theta) - U every this many iters (0 = never); the
+                               tracked r accumulates FP32 rounding, 20 keeps long solves oracle-close */
     int32_t reserved;
 } tlrmdd_opts;
 

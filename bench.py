@@ -6,13 +6,18 @@ grid (nr = 1024, Hilbert ordered), ns = 1024 sources 40 m above, 64
 frequencies from 2 to 40 Hz, rank k(f) = round(4 + 44 (f - 2)/38) with tile
 256 / 128 / 64 for k <= 16 / <= 32 / larger, dense diagonal tiles when
 k >= d/2, SNR 20 dB, 5 % noise on D, complex64, 100 L-BFGS iterations with
-exact line search. One step = Hilbert column gather of every D and U plus the
-full 100-iteration solve of all 64 frequencies (fused launches per phase).
+exact line search (residual recomputed every 20). One step = Hilbert column
+gather of every D and U plus the full 100-iteration solve of all 64
+frequencies (fused launches per phase). Complex products by default in the
+three-real-product form on FP32 matrix cores (--precision fp32 for the
+four-product form, bf16x3 for the BF16 hi+lo split).
 
 value = grad iterations per second = 64 * 100 * steps / seconds (each grad
 iteration: objective gradient, L-BFGS direction, exact line search, update).
 The roofline object describes the dominant kernel (the line-search GEMM
-[a | b] = D [X1 | X2]), timed with HIP events on its launch stream.
+[a | b] = D [X1 | X2]), timed with HIP events on its launch stream; achieved
+counts the algorithmic 8mnk complex flops (the 3M form executes 6mnk:
+executed_tflops / executed_frac).
 cpu_baseline is the FP64 oracle on a bounded sample of the same workload.
 """
 import argparse
@@ -52,6 +57,7 @@ def build_inputs(wl, torch, tl, nfreq):
 
 TRAFFIC_RECORDS = {   # precision -> (committed counter summary, kernel sources it was measured on)
     "fp32": ("cgemm_line_traffic.json", ("cgemm.hip", "gemm_common.hpp")),
+    "fp32_3m": ("cgemm3m_line_traffic.json", ("cgemm3m.hip", "gemm_common.hpp")),
     "bf16x3": ("cgemm_bf16_line_traffic.json", ("cgemm_bf16.hip", "gemm_common.hpp")),
 }
 
@@ -64,10 +70,22 @@ def source_sha(files):
     return h.hexdigest()
 
 
+def precision_info(tl, name):
+    """(library constant, dtype label, config label, line-search kernel, peak key, executed MFMA flops
+    per algorithmic 8mnk flop)."""
+    return {
+        "fp32": (tl.FP32, "f32", "fp32-mfma", "cgemm_f32_kernel<GM_LINE>", "f32", 1.0),
+        "fp32_3m": (tl.FP32_3M, "f32", "fp32-3m-mfma", "cgemm3m_kernel<GM_LINE>", "f32", 0.75),
+        "bf16x3": (tl.BF16X3, "bf16x3", "bf16x3-mfma", "cgemm_bf16x3_kernel<GM_LINE>", "bf16", 3.0),
+    }[name]
+
+
 def measured_traffic(nfreq, workload, precision):
     """HBM bytes per launch of the line-search GEMM from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs (copy-calibrated), or None when the kernel
     source changed since the counters were taken or the workload differs."""
+    if precision not in TRAFFIC_RECORDS:
+        return None
     name, files = TRAFFIC_RECORDS[precision]
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", name)))
@@ -120,7 +138,7 @@ def serving(tl, torch, args):
     solve) runs on its own stream. Results of the two runs must agree bit for bit."""
     import synth
     from paper_2412_14973_amd import serve
-    prec = tl.FP32 if args.precision == "fp32" else tl.BF16X3
+    prec = precision_info(tl, args.precision)[0]
     reqs = synth.request_stream(args.requests, iters=args.iters or 100)
     dev = torch.device("cuda")
     prepared = []
@@ -304,9 +322,11 @@ def error_table(tl, torch, args):
     import synth
     iters = args.iters or 100
     rows = []
+    R = args.resid_refresh
     variants = [("fp32", tl.FP32, 0), ("bf16x3", tl.BF16X3, 0)]
-    if args.resid_refresh > 0:
-        variants.append((f"fp32_refresh{args.resid_refresh}", tl.FP32, args.resid_refresh))
+    if R > 0:
+        variants += [(f"fp32_refresh{R}", tl.FP32, R), (f"bf16x3_refresh{R}", tl.BF16X3, R),
+                     (f"fp32_3m_refresh{R}", tl.FP32_3M, R)]
     for snr in [float(v) for v in args.error_snrs.split(",")]:
         wl = synth.large(snr_db=snr, config_id=4)
         f_idx = 10
@@ -369,7 +389,9 @@ def main():
     ap.add_argument("--nfreq", type=int, default=None)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "bf16x3", "fp32_3m"], default="fp32_3m",
+                    help="complex64 products: fp32_3m (three real FP32 products, default), fp32 (four), "
+                         "bf16x3 (BF16 hi+lo split)")
     ap.add_argument("--solver", choices=["lbfgs", "admm"], default="lbfgs",
                     help="admm: lambda stages 10, 1, 0.1 x --admm-outer X-updates of --admm-inner L-BFGS iterations")
     ap.add_argument("--admm-outer", type=int, default=4)
@@ -413,7 +435,7 @@ def main():
     if args.workload == "tlr":
         print(json.dumps(tlr_product(tl, torch, args)), flush=True)
         return
-    prec = tl.FP32 if args.precision == "fp32" else tl.BF16X3
+    prec, dtype, prec_name, line_kernel, peak_name, exec_factor = precision_info(tl, args.precision)
     wl = synth.batched() if args.workload == "batched" else synth.large()
     nfreq = args.nfreq or (len(wl.freqs) if args.workload == "batched" else 4)
     iters = args.iters or wl.iters
@@ -479,14 +501,13 @@ def main():
         entry = {"launches": n, "avg_ms": avg * 1e3}
         if k in per_prob:
             fl = per_prob[k] * nfreq
-            entry["tflops"] = fl / avg / 1e12
+            entry["tflops"] = fl / avg / 1e12   # algorithmic (8mnk)
             entry["frac_f32_peak"] = fl / avg / PEAK["f32"]
-            if prec != tl.FP32:   # three BF16 products per real product
-                entry["frac_bf16_peak_executed"] = 3 * fl / avg / PEAK["bf16"]
+            entry["executed_frac_" + peak_name + "_peak"] = exec_factor * fl / avg / PEAK[peak_name]
         kernels[k] = entry
     dom = kernels["gemm_line"]
     achieved = dom["tflops"] * 1e12
-    peak = PEAK["f32"] if prec == tl.FP32 else PEAK["bf16"]
+    peak = PEAK[peak_name]
     gemm_flops = sum(per_prob[k] * nfreq * kt.launches[k] for k in per_prob)
     gemm_s = sum(kt.ms[k] for k in per_prob) * 1e-3
     line = {
@@ -500,7 +521,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == tl.FP32 else "bf16x3",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": wl.name if nfreq == len(wl.freqs) else f"{wl.name}[first {nfreq}]",
                    "nr": nr, "ns": ns, "frequencies": nfreq, "iters": iters,
@@ -508,19 +529,20 @@ def main():
                    "optimizer": ("admm(lambda 10,1,0.1; %d x %d L-BFGS(m=5) per stage)" % (args.admm_outer,
                                                                                         args.admm_inner))
                    if admm else "lbfgs(m=5)",
-                   "precision": "fp32-mfma" if prec == tl.FP32 else "bf16x3-mfma"},
+                   "precision": prec_name},
         "roofline": {"bound": "mfma",
-                     "kernel": ("cgemm_f32_kernel<GM_LINE>" if prec == tl.FP32 else "cgemm_bf16x3_kernel<GM_LINE>")
-                     + " ([a|b] = D [X1|X2])",
+                     "kernel": line_kernel + " ([a|b] = D [X1|X2])",
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak,
+                     "executed_tflops": exec_factor * achieved / 1e12,
+                     "executed_frac": exec_factor * achieved / peak,
                      "traffic": measured_traffic(nfreq, args.workload, args.precision),
                      "algorithmic_bytes": 6 * 8.0 * ns * nr * nfreq},
         "mfma_frac_all_gemms": gemm_flops / gemm_s / PEAK["f32"],
         "kernels": kernels,
         "objective": {"f0_mean": sum(f_first) / nfreq, "fT_mean": sum(f_final) / nfreq},
     }
-    if not args.no_cpu_baseline and prec == tl.FP32:
+    if not args.no_cpu_baseline and prec != tl.BF16X3:
         log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     print(json.dumps(line), flush=True)

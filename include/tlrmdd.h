@@ -58,6 +58,8 @@ extern "C" {
 /* ---- precisions of the bulk complex products ------------------------------ */
 #define TLRMDD_FP32      0  /* FP32 MFMA, complex as a real 2x2 block (4 real products) */
 #define TLRMDD_BF16X3    1  /* BF16 hi+lo split (hi*hi + hi*lo + lo*hi), FP32 accumulate */
+#define TLRMDD_FP32_3M   2  /* FP32 MFMA, three real products per complex product (3M form):
+                               Re = ArBr - AiBi, Im = (Ar+Ai)(Br+Bi) - ArBr - AiBi; 3/4 of the flops */
 
 /* ---- optimisers ------------------------------------------------------------ */
 #define TLRMDD_LBFGS 0
@@ -86,7 +88,7 @@ typedef struct {
     int32_t iters;          /* fixed iteration count T >= 0                        */
     int32_t optimizer;      /* TLRMDD_LBFGS or TLRMDD_GD                           */
     int32_t lbfgs_m;        /* L-BFGS memory, 1..32 (default 5)                     */
-    int32_t precision;      /* TLRMDD_FP32 or TLRMDD_BF16X3                         */
+    int32_t precision;      /* TLRMDD_FP32, TLRMDD_BF16X3 or TLRMDD_FP32_3M           */
     double  lambda;         /* Frobenius regulariser lambda ||theta||^2 (0 = none)  */
     int32_t resid_refresh;  /* recompute r = D C(theta) - U every this many iters (0 = never); the
                                tracked r accumulates FP32 rounding, 20 keeps long solves oracle-close */
@@ -129,7 +131,7 @@ int tlrmdd_workspace_bytes(tlrmdd_plan plan, int op, const tlrmdd_opts *opts, si
  * r_out:   device or NULL; receives r = D X - U (ns x nr complex64).
  * X_out:   device or NULL; receives X = C(theta) (nr x nr complex64, exactly
  *          symmetric bit for bit).
- * precision: TLRMDD_FP32 or TLRMDD_BF16X3. */
+ * precision: TLRMDD_FP32, TLRMDD_BF16X3 or TLRMDD_FP32_3M. */
 int tlrmdd_forward(tlrmdd_plan plan, const void *D, const void *U, const void *theta,
                    double *f_dev, void *r_out, void *X_out, int precision,
                    void *workspace, size_t ws_bytes, hipStream_t stream);

@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BF16X3, FP32, GD, LBFGS, TLRMDDError  # noqa: F401
+from ._lib import BF16X3, FP32, FP32_3M, GD, LBFGS, TLRMDDError  # noqa: F401
 
 __all__ = ["Plan", "hilbert_order", "permute_columns", "forward", "grad", "solve", "solve_batched", "adjoint",
            "benchmark_solve",

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libtlrmdd.so")
 
 OK, INVALID_ARGUMENT, WORKSPACE, HIP_ERROR, NONFINITE, UNSUPPORTED = 0, 1, 2, 3, 4, 5
-FP32, BF16X3 = 0, 1
+FP32, BF16X3, FP32_3M = 0, 1, 2
 LBFGS, GD = 0, 1
 OP_FORWARD, OP_GRAD, OP_SOLVE = 0, 1, 2
 

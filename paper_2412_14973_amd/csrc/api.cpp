@@ -396,7 +396,7 @@ int check_opts(const tlrmdd_opts *o) {
         return fail(TLRMDD_INVALID_ARGUMENT, "unknown optimizer");
     if (o->optimizer == TLRMDD_LBFGS && (o->lbfgs_m < 1 || o->lbfgs_m > MAX_LBFGS_M))
         return fail(TLRMDD_INVALID_ARGUMENT, "lbfgs_m must be in [1, 32]");
-    if (o->precision != TLRMDD_FP32 && o->precision != TLRMDD_BF16X3)
+    if (o->precision != TLRMDD_FP32 && o->precision != TLRMDD_BF16X3 && o->precision != TLRMDD_FP32_3M)
         return fail(TLRMDD_INVALID_ARGUMENT, "unknown precision");
     if (!(o->lambda >= 0.0)) return fail(TLRMDD_INVALID_ARGUMENT, "lambda must be >= 0");
     if (o->resid_refresh < 0) return fail(TLRMDD_INVALID_ARGUMENT, "resid_refresh must be >= 0");
@@ -404,7 +404,7 @@ int check_opts(const tlrmdd_opts *o) {
 }
 
 int check_precision(int precision) {
-    if (precision == TLRMDD_FP32 || precision == TLRMDD_BF16X3) return TLRMDD_OK;
+    if (precision == TLRMDD_FP32 || precision == TLRMDD_BF16X3 || precision == TLRMDD_FP32_3M) return TLRMDD_OK;
     return fail(TLRMDD_INVALID_ARGUMENT, "unknown precision");
 }
 
@@ -531,6 +531,7 @@ struct Ctx {
     DevTables D;
     hipStream_t s;
     bool bf16 = false;          // BF16 hi+lo split products
+    bool p3m = false;           // FP32 products in the three-real-product form
     int64_t xspace = 0;         // complex64 elements of X space per problem (1 or 2 ldk x ldk)
 
     // split planes (uint32 words, one per complex): per problem [hi | lo]
@@ -579,7 +580,9 @@ int gemm_resid(const Ctx &c, const float2 *X, int64_t sX, const float2 *U, int64
     g.partials = c.w.partials; g.sP = (int64_t)c.pstride;   // one sum per workgroup
     g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
     g.Me = (int)c.ns; g.Ne = (int)c.nr;
-    HIP_TRY(timed(TLRMDD_K_GEMM_RESID, c.s, [&] { return launch_cgemm(GM_RESID, g, c.nprob, c.s); }));
+    HIP_TRY(timed(TLRMDD_K_GEMM_RESID, c.s, [&] {
+        return c.p3m ? launch_cgemm3m(GM_RESID, g, c.nprob, c.s) : launch_cgemm(GM_RESID, g, c.nprob, c.s);
+    }));
     return TLRMDD_OK;
 }
 
@@ -604,7 +607,9 @@ int gemm_adjoint(const Ctx &c, const float2 *r, float2 *W, int64_t sW) {
     g.B = r; g.ldb = c.ldk; g.sB = c.lds * c.ldk;
     g.C = W; g.ldc = c.ldk; g.sC = sW;
     g.M = (int)c.ldk; g.N = (int)c.ldk; g.K = (int)c.lds;
-    HIP_TRY(timed(TLRMDD_K_GEMM_ADJOINT, c.s, [&] { return launch_cgemm(GM_STORE, g, c.nprob, c.s); }));
+    HIP_TRY(timed(TLRMDD_K_GEMM_ADJOINT, c.s, [&] {
+        return c.p3m ? launch_cgemm3m(GM_STORE, g, c.nprob, c.s) : launch_cgemm(GM_STORE, g, c.nprob, c.s);
+    }));
     return TLRMDD_OK;
 }
 
@@ -633,7 +638,9 @@ int gemm_line(const Ctx &c, const float2 *X1, const float2 *X2, int64_t sX) {
     g.E = c.w.r; g.lde = c.ldk; g.sE = c.lds * c.ldk;
     g.partials = c.w.partials; g.sP = (int64_t)c.pstride * 5;
     g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
-    HIP_TRY(timed(TLRMDD_K_GEMM_LINE, c.s, [&] { return launch_cgemm(GM_LINE, g, c.nprob, c.s); }));
+    HIP_TRY(timed(TLRMDD_K_GEMM_LINE, c.s, [&] {
+        return c.p3m ? launch_cgemm3m(GM_LINE, g, c.nprob, c.s) : launch_cgemm(GM_LINE, g, c.nprob, c.s);
+    }));
     return TLRMDD_OK;
 }
 
@@ -762,6 +769,7 @@ int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *c
     R.xstride = 2 * c.ldk * c.ldk;   // per-problem X-space stride
     R.rstride = c.lds * c.ldk;
     c.bf16 = opts->precision == TLRMDD_BF16X3;
+    c.p3m = opts->precision == TLRMDD_FP32_3M;
     c.xspace = R.xstride;
     R.X1 = c.w.XW;
     R.X2 = c.w.XW + c.ldk * c.ldk;
@@ -946,6 +954,7 @@ int tlrmdd_forward(tlrmdd_plan plan, const void *D, const void *U, const void *t
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     c.D = plan->D;
     c.bf16 = precision == TLRMDD_BF16X3;
+    c.p3m = precision == TLRMDD_FP32_3M;
     c.xspace = c.ldk * c.ldk;
     if (c.ldk != c.nr) HIP_TRY(hipMemsetAsync(c.w.XW, 0, (size_t)c.ldk * c.ldk * sizeof(float2), stream));
     if ((st = stage(c, 0, (const float2 *)D, false))) return st;
@@ -984,6 +993,7 @@ int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *thet
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     c.D = plan->D;
     c.bf16 = precision == TLRMDD_BF16X3;
+    c.p3m = precision == TLRMDD_FP32_3M;
     c.xspace = c.ldk * c.ldk;
     if (c.ldk != c.nr) HIP_TRY(hipMemsetAsync(c.w.XW, 0, (size_t)c.ldk * c.ldk * sizeof(float2), stream));
     if ((st = stage(c, 0, (const float2 *)D, true))) return st;
@@ -1021,6 +1031,7 @@ int tlrmdd_adjoint(tlrmdd_plan plan, const void *D, const void *U, void *X_out, 
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     c.D = plan->D;
     c.bf16 = precision == TLRMDD_BF16X3;
+    c.p3m = precision == TLRMDD_FP32_3M;
     c.xspace = c.ldk * c.ldk;
     if ((st = stage(c, 0, (const float2 *)D, true))) return st;
     // U takes the place of the residual: padded copy with zero padding, then W = D^H U

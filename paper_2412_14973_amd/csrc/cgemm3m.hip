@@ -1,0 +1,270 @@
+// Complex64 GEMM on FP32 matrix cores in the three-real-product ("3M") form.
+//
+// C = A B with A = Ar + i Ai, B = Br + i Bi is formed from three real products
+//   T1 = Ar Br,  T2 = Ai Bi,  T3 = (Ar + Ai)(Br + Bi),
+//   Re C = T1 - T2,  Im C = T3 - T1 - T2,
+// i.e. 6MNK real flops instead of the 8MNK of the four-product (realified) form,
+// at the price of one extra rounding level in Im C (the sums Ar + Ai, Br + Bi
+// and the final differences). Operands are the same interleaved complex64
+// matrices as for the four-product kernel: every loaded tile is split into
+// its real, imaginary and sum planes while it is stored to LDS.
+//
+// Tiling: 512 threads = 8 waves; workgroup tile 128 rows x 128 complex columns,
+// 16 complex k per stage, double-buffered LDS (three A planes k-major with an
+// odd pitch, three B planes row-major: conflict-free operand reads). One
+// v_mfma_f32_32x32x2_f32 consumes two complex k of one plane pair.
+//   GM_STORE / GM_RESID: waves 2 (rows) x 4 (columns), each 64 rows x 32 columns,
+//     accumulators T1, T2, T3 for two 32 x 32 blocks;
+//   GM_LINE: the B tile holds X1 and X2 at the same 64 columns; waves 4 x 2,
+//     each 32 rows x 32 columns of both, so a, b and r meet in one thread.
+// Epilogues as the four-product kernel: C; C = AB - U with FP64 partial sums of
+// |C|^2; a, b with the five line-search sums.
+#include "gemm_common.hpp"
+
+namespace tlr {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = GEMM_BK;
+constexpr int AP = BM + 1;            // A plane pitch (floats per complex-k row, k-major)
+constexpr int A_PLANE = BK * AP;
+constexpr int BP = BN;                // B plane pitch (floats per k row)
+constexpr int B_PLANE = BK * BP;
+constexpr int STAGE = 3 * A_PLANE + 3 * B_PLANE;   // floats
+
+template <int MODE>
+__global__ __launch_bounds__(512) void cgemm3m_kernel(GemmArgs g) {
+    __shared__ float sm[2][STAGE];
+
+    const int z = blockIdx.y;
+    const float2 *A = g.A + z * g.sA;
+    const float2 *B = g.B + z * g.sB;
+
+    // workgroup -> tile: contiguous tile ranges per XCD, grouped by 8 tile rows
+    const int nb = gridDim.x;
+    int pid = blockIdx.x;
+    if ((nb & 7) == 0) pid = (pid & 7) * (nb >> 3) + (pid >> 3);
+    const int group_rows = 8;
+    const int per_group = group_rows * g.tiles_n;
+    const int grp = pid / per_group;
+    const int first_m = grp * group_rows;
+    const int gsz = min(g.tiles_m - first_m, group_rows);
+    const int tm = first_m + (pid % per_group) % gsz;
+    const int tn = (pid % per_group) / gsz;
+    const int m0 = tm * BM;
+    const int n0 = (MODE == GM_LINE) ? tn * (BN / 2) : tn * BN;
+
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int j32 = lane & 31, half = lane >> 5;
+
+    // ---- global -> register loaders (operands padded to whole tiles: no bounds checks) ----
+    // A: row t/4, complex k 4 (t%4) .. +3 (two float4); B: k row t/32, complex columns 4 (t%32) .. +3
+    const int a_row = t >> 2, a_q = t & 3;
+    const int b_row = t >> 5, b_q = t & 31;
+    const __amdgpu_buffer_rsrc_t rsA =
+        __builtin_amdgcn_make_buffer_rsrc((void *)A, (short)0, (int)g.bytesA, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsB =
+        __builtin_amdgcn_make_buffer_rsrc((void *)B, (short)0, (int)g.bytesB, 0x00020000);
+    const uint32_t offA = (uint32_t)(((int64_t)(m0 + a_row) * g.lda + 4 * a_q) * 8);
+    uint32_t offB;
+    {
+        const int c = 4 * b_q;   // complex column inside the LDS tile
+        int64_t base = n0 + c;
+        if (MODE == GM_LINE) base = (c < 64) ? n0 + c : n0 + (c - 64) + g.b2_off;   // X1 | X2
+        offB = (uint32_t)((base + (int64_t)b_row * g.ldb) * 8);
+    }
+    auto ld16 = [](__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+        return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
+    };
+    float4 ra[2], rb[2];
+    auto load = [&](int k0) {
+        const uint32_t sa = (uint32_t)k0 * 8u;
+        const uint32_t sb = (uint32_t)((int64_t)k0 * g.ldb * 8);
+        ra[0] = ld16(rsA, offA, sa);
+        ra[1] = ld16(rsA, offA + 16, sa);
+        rb[0] = ld16(rsB, offB, sb);
+        rb[1] = ld16(rsB, offB + 16, sb);
+    };
+    // split into (re, im, re + im) planes
+    auto store_lds = [&](int buf) {
+        float *ar = sm[buf], *ai = ar + A_PLANE, *as = ai + A_PLANE;
+        float *br = as + A_PLANE, *bi = br + B_PLANE, *bs = bi + B_PLANE;
+        const float2 av[4] = {make_float2(ra[0].x, ra[0].y), make_float2(ra[0].z, ra[0].w),
+                              make_float2(ra[1].x, ra[1].y), make_float2(ra[1].z, ra[1].w)};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int o = (4 * a_q + q) * AP + a_row;
+            ar[o] = av[q].x;
+            ai[o] = av[q].y;
+            as[o] = av[q].x + av[q].y;
+        }
+        const int ob = b_row * BP + 4 * b_q;
+        *reinterpret_cast<float4 *>(br + ob) = make_float4(rb[0].x, rb[0].z, rb[1].x, rb[1].z);
+        *reinterpret_cast<float4 *>(bi + ob) = make_float4(rb[0].y, rb[0].w, rb[1].y, rb[1].w);
+        *reinterpret_cast<float4 *>(bs + ob) =
+            make_float4(rb[0].x + rb[0].y, rb[0].z + rb[0].w, rb[1].x + rb[1].y, rb[1].z + rb[1].w);
+    };
+
+    // wave tile: STORE/RESID rows wm*64 + 32 i (i < 2), columns wn*32; LINE rows wm*32, columns
+    // wn*32 of X1 (LDS column wn*32) and X2 (LDS column 64 + wn*32)
+    const int wm = (MODE == GM_LINE) ? wave >> 1 : wave >> 2;
+    const int wn = (MODE == GM_LINE) ? wave & 1 : wave & 3;
+    int aoff[2], boff[2];
+    if (MODE == GM_LINE) {
+        aoff[0] = aoff[1] = wm * 32 + j32;
+        boff[0] = wn * 32 + j32;
+        boff[1] = 64 + wn * 32 + j32;
+    } else {
+        aoff[0] = wm * 64 + j32;
+        aoff[1] = wm * 64 + 32 + j32;
+        boff[0] = boff[1] = wn * 32 + j32;
+    }
+    floatx16 acc[3][2];   // [T1, T2, T3][block]
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[p][i][r] = 0.f;
+
+    const int nk = g.K / BK;
+    load(0);
+    store_lds(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load((kt + 1) * BK);
+        const float *ar = sm[buf], *ai = ar + A_PLANE, *as = ai + A_PLANE;
+        const float *br = as + A_PLANE, *bi = br + B_PLANE, *bs = bi + B_PLANE;
+#pragma unroll
+        for (int kc = 0; kc < BK; kc += 2) {
+            const int ka = (kc + half) * AP, kb = (kc + half) * BP;
+            float a[3][2], b[3][2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                a[0][i] = ar[ka + aoff[i]];
+                a[1][i] = ai[ka + aoff[i]];
+                a[2][i] = as[ka + aoff[i]];
+                b[0][i] = br[kb + boff[i]];
+                b[1][i] = bi[kb + boff[i]];
+                b[2][i] = bs[kb + boff[i]];
+            }
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    acc[p][i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p][i], b[p][i], acc[p][i], 0, 0, 0);
+        }
+        if (kt + 1 < nk) store_lds(buf ^ 1);
+        __syncthreads();
+    }
+
+    // ---- epilogue: C = (T1 - T2) + i (T3 - T1 - T2) ----
+    __shared__ double red[8][5];
+    float2 *C = g.C + z * g.sC;
+    const int64_t ldc = g.ldc;
+    if (MODE == GM_STORE) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int col = n0 + wn * 32 + j32;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm * 64 + 32 * i + acc_row(r, lane);
+                const float t1 = acc[0][i][r], t2 = acc[1][i][r], t3 = acc[2][i][r];
+                C[(int64_t)row * ldc + col] = make_float2(t1 - t2, t3 - t1 - t2);
+            }
+        }
+        return;
+    }
+    const float2 *E = g.E + z * g.sE;
+    const int64_t lde = g.lde;
+    double sums[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (MODE == GM_RESID) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int col = n0 + wn * 32 + j32;
+            float blk = 0.f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm * 64 + 32 * i + acc_row(r, lane);
+                const bool in = row < g.Me && col < g.Ne;   // U has the true (unpadded) shape
+                const float2 e = in ? E[(int64_t)row * lde + col] : make_float2(0.f, 0.f);
+                const float t1 = acc[0][i][r], t2 = acc[1][i][r], t3 = acc[2][i][r];
+                const float2 v = make_float2(t1 - t2 - e.x, t3 - t1 - t2 - e.y);
+                C[(int64_t)row * ldc + col] = v;
+                blk = fmaf(v.x, v.x, fmaf(v.y, v.y, blk));
+            }
+            sums[0] += (double)blk;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {   // GM_LINE: block 0 = a = D X1, block 1 = b = D X2 at the same (row, column)
+        float2 *C2 = g.C2 + z * g.sC;
+        const int col = n0 + wn * 32 + j32;
+        float blk[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = m0 + wm * 32 + acc_row(r, lane);
+            const float2 av = make_float2(acc[0][0][r] - acc[1][0][r], acc[2][0][r] - acc[0][0][r] - acc[1][0][r]);
+            const float2 bv = make_float2(acc[0][1][r] - acc[1][1][r], acc[2][1][r] - acc[0][1][r] - acc[1][1][r]);
+            const float2 rv = E[(int64_t)row * lde + col];
+            C[(int64_t)row * ldc + col] = av;
+            C2[(int64_t)row * ldc + col] = bv;
+            blk[0] = fmaf(rv.x, av.x, fmaf(rv.y, av.y, blk[0]));
+            blk[1] = fmaf(av.x, av.x, fmaf(av.y, av.y, blk[1]));
+            blk[2] = fmaf(rv.x, bv.x, fmaf(rv.y, bv.y, blk[2]));
+            blk[3] = fmaf(av.x, bv.x, fmaf(av.y, bv.y, blk[3]));
+            blk[4] = fmaf(bv.x, bv.x, fmaf(bv.y, bv.y, blk[4]));
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) sums[q] = (double)blk[q];
+    }
+    constexpr int NS = (MODE == GM_RESID) ? 1 : 5;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const double v = wave_sum(sums[s]);
+        if (lane == 0) red[wave][s] = v;
+    }
+    __syncthreads();
+    if (t < NS) {
+        const double v = (((red[0][t] + red[1][t]) + (red[2][t] + red[3][t])) +
+                          ((red[4][t] + red[5][t]) + (red[6][t] + red[7][t])));
+        g.partials[z * g.sP + (int64_t)pid * NS + t] = v;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s) {
+    GemmArgs a = a0;
+    a.tiles_m = a.M / BM;
+    a.tiles_n = (mode == GM_LINE) ? a.N / (BN / 2) : a.N / BN;
+    if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
+    if (a.M % BM || a.N % BN || a.K % BK || a.K <= 0) return hipErrorInvalidValue;
+    // byte extents of the buffer resources (32-bit): A is M x lda, B is K x ldb (GM_LINE: B2 follows B)
+    const int64_t bytesA = (int64_t)a.M * a.lda * 8;
+    int64_t bytesB = (int64_t)a.K * a.ldb * 8;
+    a.b2_off = 0;
+    if (mode == GM_LINE) {
+        a.b2_off = a.B2 - a.B;
+        if (a.b2_off < 0) return hipErrorInvalidValue;
+        bytesB += a.b2_off * 8;
+    }
+    if (bytesA >= (int64_t)1 << 32 || bytesB >= (int64_t)1 << 32) return hipErrorInvalidValue;
+    a.bytesA = (uint32_t)bytesA;
+    a.bytesB = (uint32_t)bytesB;
+    dim3 grid(a.tiles_m * a.tiles_n, batch);
+    switch (mode) {
+        case GM_STORE: hipLaunchKernelGGL(cgemm3m_kernel<GM_STORE>, grid, dim3(512), 0, s, a); break;
+        case GM_RESID: hipLaunchKernelGGL(cgemm3m_kernel<GM_RESID>, grid, dim3(512), 0, s, a); break;
+        case GM_LINE:  hipLaunchKernelGGL(cgemm3m_kernel<GM_LINE>, grid, dim3(512), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tlr

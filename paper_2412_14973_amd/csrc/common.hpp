@@ -128,6 +128,8 @@ struct SolveScalars {
 
 // host launchers (stream ordered)
 hipError_t launch_cgemm(int mode, const GemmArgs &a, int batch, hipStream_t s);
+// the same products in the three-real-product form (FP32 MFMA, interleaved complex64 operands)
+hipError_t launch_cgemm3m(int mode, const GemmArgs &a, int batch, hipStream_t s);
 int gemm_partials_per_problem(int mode, int M, int N);
 
 // out_bf16 == false: X / X2 are complex64 matrices (ProbOff.x offsets, ld ProbOff.ldx).

@@ -152,6 +152,29 @@ def test_bf16x3_forward_and_gradient_parity(tl, name, mk):
     assert abs(f.item() - fo) <= 5e-3 * fo and abs(fg.item() - fo) <= 5e-3 * fo
 
 
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+def test_fp32_3m_forward_and_gradient_parity(tl, name, mk):
+    """Three-real-product form: Im C = (Ar+Ai)(Br+Bi) - ArBr - AiBi adds the rounding of two sums and
+    of products of magnitude up to 2|a||b|, so the FP32 bounds grow by a factor 4."""
+    case = mk()
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    f, r, _ = tl.forward(plan, D, U, th, precision=tl.FP32_3M, want_r=True)
+    fg, g = tl.grad(plan, D, U, th, precision=tl.FP32_3M)
+    torch.cuda.synchronize()
+    Xo = O.assemble(case.T, case.theta)
+    fo, ro = O.objective(case.T, case.D, case.U, case.theta)
+    _, go = O.gradient(case.T, case.D, case.U, case.theta)
+    err = np.abs(r.cpu().numpy().astype(np.complex128) - ro)
+    bound = 4 * 8 * residual_bound(case, Xo)
+    gerr = np.abs(g.cpu().numpy().astype(np.complex128) - go)
+    gb = 4 * 8 * gradient_bound(case, Xo, ro) + 1e-30
+    print(f"{name} fp32-3m: max r err/bound {np.max(err / bound):.3f}, max g err/bound {np.max(gerr / gb):.3f}, "
+          f"rel f {abs(f.item() - fo) / fo:.2e}")
+    assert np.all(err <= bound)
+    assert np.all(gerr <= gb)
+    assert abs(f.item() - fo) <= 1e-5 * fo and abs(fg.item() - fo) <= 1e-5 * fo
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_adjoint_solution(tl, prec):
     case = from_geometry(12, 11, "half", 14.0, synth.uniform_layout(132, 40, 6, 7), 4, "adjoint")

@@ -137,3 +137,27 @@ def test_bf16x3_batched_matches_single(tl):
     torch.cuda.synchronize()
     for (ts, fs), tb, fb in zip(singles, th_b, fh_b):
         assert torch.equal(ts, tb) and torch.equal(fs, fb)
+
+
+@pytest.mark.parametrize("f_idx", [2, 5])
+def test_fp32_3m_solve_small_workload(tl, f_idx):
+    wl = synth.small()
+    case = from_workload(wl, f_idx)
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    thg, fh = tl.solve(plan, D, U, th, iters=wl.iters, precision=tl.FP32_3M)
+    torch.cuda.synchronize()
+    ref = O.solve(case.T, case.D, case.U, case.theta, iters=wl.iters)
+    rf, rx, rt = _metrics(case, thg.cpu().numpy().astype(np.complex128), ref.theta)
+    print(f"fp32-3m f[{f_idx}]: rel_f {rf:.2e} rel_X {rx:.2e} rel_theta {rt:.2e}")
+    assert rf <= FP32_TOL and rx <= FP32_TOL and rt <= FP32_TOL
+
+
+def test_fp32_3m_batched_matches_single(tl):
+    wl = synth.small()
+    devs = [to_device(from_workload(wl, i), tl, torch) for i in range(3)]
+    th_b, fh_b = tl.solve_batched([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs],
+                                  [d[3] for d in devs], iters=10, precision=tl.FP32_3M)
+    singles = [tl.solve(d[0], d[1], d[2], d[3], iters=10, precision=tl.FP32_3M) for d in devs]
+    torch.cuda.synchronize()
+    for (ts, fs), tb, fb in zip(singles, th_b, fh_b):
+        assert torch.equal(ts, tb) and torch.equal(fs, fb)

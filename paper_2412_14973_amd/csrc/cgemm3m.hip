@@ -7,18 +7,20 @@
 // at the price of one extra rounding level in Im C (the sums Ar + Ai, Br + Bi
 // and the final differences). Operands are the same interleaved complex64
 // matrices as for the four-product kernel: every loaded tile is split into
-// its real, imaginary and sum planes while it is stored to LDS.
+// its real and imaginary planes while it is stored to LDS, and each lane forms
+// the sums Ar + Ai, Br + Bi of its operand fragments after reading them.
 //
 // Tiling: 512 threads = 8 waves; workgroup tile 128 rows x 128 complex columns,
-// 16 complex k per stage, double-buffered LDS (three A planes k-major with an
-// odd pitch, three B planes row-major: conflict-free operand reads). One
-// v_mfma_f32_32x32x2_f32 consumes two complex k of one plane pair.
+// 32 complex k per stage, double-buffered LDS (two A planes k-major with an
+// odd pitch, two B planes row-major: conflict-free operand reads and stores;
+// 2 x 64.3 KiB). One v_mfma_f32_32x32x2_f32 consumes two complex k of one
+// plane pair.
 //   GM_STORE / GM_RESID: waves 2 (rows) x 4 (columns), each 64 rows x 32 columns,
 //     accumulators T1, T2, T3 for two 32 x 32 blocks;
 //   GM_LINE: the B tile holds X1 and X2 at the same 64 columns; waves 4 x 2,
 //     each 32 rows x 32 columns of both, so a, b and r meet in one thread.
 // Epilogues as the four-product kernel: C; C = AB - U with FP64 partial sums of
-// |C|^2; a, b with the five line-search sums.
+// |C|^2; a, b with the five line-search sums. K must be a multiple of 32.
 #include "gemm_common.hpp"
 
 namespace tlr {
@@ -27,12 +29,13 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = GEMM_BK;
+constexpr int BM = GEMM_BM, BN = GEMM_BN;
+constexpr int BK = 2 * GEMM_BK;       // complex k per stage
 constexpr int AP = BM + 1;            // A plane pitch (floats per complex-k row, k-major)
 constexpr int A_PLANE = BK * AP;
 constexpr int BP = BN;                // B plane pitch (floats per k row)
 constexpr int B_PLANE = BK * BP;
-constexpr int STAGE = 3 * A_PLANE + 3 * B_PLANE;   // floats
+constexpr int STAGE = 2 * A_PLANE + 2 * B_PLANE;   // floats: re and im planes of A and B
 
 template <int MODE>
 __global__ __launch_bounds__(512) void cgemm3m_kernel(GemmArgs g) {
@@ -62,52 +65,55 @@ __global__ __launch_bounds__(512) void cgemm3m_kernel(GemmArgs g) {
     const int j32 = lane & 31, half = lane >> 5;
 
     // ---- global -> register loaders (operands padded to whole tiles: no bounds checks) ----
-    // A: row t/4, complex k 4 (t%4) .. +3 (two float4); B: k row t/32, complex columns 4 (t%32) .. +3
+    // A: row t/4, complex k 8 (t%4) .. +7 (four float4); B: k row t/16, complex columns
+    // 4 (t%16) .. +3 and 64 + 4 (t%16) .. +3 (two float4 each)
     const int a_row = t >> 2, a_q = t & 3;
-    const int b_row = t >> 5, b_q = t & 31;
+    const int b_row = t >> 4, b_q = t & 15;
     const __amdgpu_buffer_rsrc_t rsA =
         __builtin_amdgcn_make_buffer_rsrc((void *)A, (short)0, (int)g.bytesA, 0x00020000);
     const __amdgpu_buffer_rsrc_t rsB =
         __builtin_amdgcn_make_buffer_rsrc((void *)B, (short)0, (int)g.bytesB, 0x00020000);
-    const uint32_t offA = (uint32_t)(((int64_t)(m0 + a_row) * g.lda + 4 * a_q) * 8);
-    uint32_t offB;
-    {
-        const int c = 4 * b_q;   // complex column inside the LDS tile
+    const uint32_t offA = (uint32_t)(((int64_t)(m0 + a_row) * g.lda + 8 * a_q) * 8);
+    uint32_t offB[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = 64 * h + 4 * b_q;   // complex column inside the LDS tile
         int64_t base = n0 + c;
-        if (MODE == GM_LINE) base = (c < 64) ? n0 + c : n0 + (c - 64) + g.b2_off;   // X1 | X2
-        offB = (uint32_t)((base + (int64_t)b_row * g.ldb) * 8);
+        if (MODE == GM_LINE) base = h ? n0 + (c - 64) + g.b2_off : n0 + c;   // X1 | X2
+        offB[h] = (uint32_t)((base + (int64_t)b_row * g.ldb) * 8);
     }
     auto ld16 = [](__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
         const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
         return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
     };
-    float4 ra[2], rb[2];
+    float4 ra[4], rb[4];
     auto load = [&](int k0) {
         const uint32_t sa = (uint32_t)k0 * 8u;
         const uint32_t sb = (uint32_t)((int64_t)k0 * g.ldb * 8);
-        ra[0] = ld16(rsA, offA, sa);
-        ra[1] = ld16(rsA, offA + 16, sa);
-        rb[0] = ld16(rsB, offB, sb);
-        rb[1] = ld16(rsB, offB + 16, sb);
-    };
-    // split into (re, im, re + im) planes
-    auto store_lds = [&](int buf) {
-        float *ar = sm[buf], *ai = ar + A_PLANE, *as = ai + A_PLANE;
-        float *br = as + A_PLANE, *bi = br + B_PLANE, *bs = bi + B_PLANE;
-        const float2 av[4] = {make_float2(ra[0].x, ra[0].y), make_float2(ra[0].z, ra[0].w),
-                              make_float2(ra[1].x, ra[1].y), make_float2(ra[1].z, ra[1].w)};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int o = (4 * a_q + q) * AP + a_row;
-            ar[o] = av[q].x;
-            ai[o] = av[q].y;
-            as[o] = av[q].x + av[q].y;
+            ra[q] = ld16(rsA, offA + 16 * q, sa);
+            rb[q] = ld16(rsB, offB[q >> 1] + 16 * (q & 1), sb);
         }
-        const int ob = b_row * BP + 4 * b_q;
-        *reinterpret_cast<float4 *>(br + ob) = make_float4(rb[0].x, rb[0].z, rb[1].x, rb[1].z);
-        *reinterpret_cast<float4 *>(bi + ob) = make_float4(rb[0].y, rb[0].w, rb[1].y, rb[1].w);
-        *reinterpret_cast<float4 *>(bs + ob) =
-            make_float4(rb[0].x + rb[0].y, rb[0].z + rb[0].w, rb[1].x + rb[1].y, rb[1].z + rb[1].w);
+    };
+    // split into re and im planes (the sums re + im are formed after the operand reads)
+    auto store_lds = [&](int buf) {
+        float *ar = sm[buf], *ai = ar + A_PLANE;
+        float *br = ai + A_PLANE, *bi = br + B_PLANE;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int o = (8 * a_q + 2 * q) * AP + a_row;
+            ar[o] = ra[q].x;
+            ai[o] = ra[q].y;
+            ar[o + AP] = ra[q].z;
+            ai[o + AP] = ra[q].w;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ob = b_row * BP + 64 * h + 4 * b_q;
+            *reinterpret_cast<float4 *>(br + ob) = make_float4(rb[2 * h].x, rb[2 * h].z, rb[2 * h + 1].x, rb[2 * h + 1].z);
+            *reinterpret_cast<float4 *>(bi + ob) = make_float4(rb[2 * h].y, rb[2 * h].w, rb[2 * h + 1].y, rb[2 * h + 1].w);
+        }
     };
 
     // wave tile: STORE/RESID rows wm*64 + 32 i (i < 2), columns wn*32; LINE rows wm*32, columns
@@ -139,26 +145,46 @@ __global__ __launch_bounds__(512) void cgemm3m_kernel(GemmArgs g) {
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
         if (kt + 1 < nk) load((kt + 1) * BK);
-        const float *ar = sm[buf], *ai = ar + A_PLANE, *as = ai + A_PLANE;
-        const float *br = as + A_PLANE, *bi = br + B_PLANE, *bs = bi + B_PLANE;
-#pragma unroll
-        for (int kc = 0; kc < BK; kc += 2) {
+        const float *ar = sm[buf], *ai = ar + A_PLANE;
+        const float *br = ai + A_PLANE, *bi = br + B_PLANE;
+        // operand fragments [A|B][re, im, re + im][block], double-buffered in registers: the
+        // reads of step kc + 2 are issued between the six MFMAs of step kc
+        float cur[2][3][2], nxt[2][3][2];
+        auto frag = [&](int kc, float (&f)[2][3][2]) {
             const int ka = (kc + half) * AP, kb = (kc + half) * BP;
-            float a[3][2], b[3][2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                a[0][i] = ar[ka + aoff[i]];
-                a[1][i] = ai[ka + aoff[i]];
-                a[2][i] = as[ka + aoff[i]];
-                b[0][i] = br[kb + boff[i]];
-                b[1][i] = bi[kb + boff[i]];
-                b[2][i] = bs[kb + boff[i]];
+                f[0][0][i] = ar[ka + aoff[i]];
+                f[0][1][i] = ai[ka + aoff[i]];
+                f[1][0][i] = br[kb + boff[i]];
+                f[1][1][i] = bi[kb + boff[i]];
             }
+        };
+        auto sums = [&](float (&f)[2][3][2]) {
+#pragma unroll
+            for (int o = 0; o < 2; ++o)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) f[o][2][i] = f[o][0][i] + f[o][1][i];
+        };
+        frag(0, cur);
+        sums(cur);
+#pragma unroll
+        for (int kc = 0; kc < BK; kc += 2) {
+            if (kc + 2 < BK) frag(kc + 2, nxt);
 #pragma unroll
             for (int p = 0; p < 3; ++p)
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
-                    acc[p][i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p][i], b[p][i], acc[p][i], 0, 0, 0);
+                    acc[p][i] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[0][p][i], cur[1][p][i], acc[p][i], 0, 0, 0);
+            if (kc + 2 < BK) {
+                sums(nxt);
+#pragma unroll
+                for (int o = 0; o < 2; ++o)
+#pragma unroll
+                    for (int p = 0; p < 3; ++p)
+#pragma unroll
+                        for (int i = 0; i < 2; ++i) cur[o][p][i] = nxt[o][p][i];
+            }
         }
         if (kt + 1 < nk) store_lds(buf ^ 1);
         __syncthreads();

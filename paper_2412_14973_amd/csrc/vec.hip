@@ -148,39 +148,46 @@ __device__ __forceinline__ int ring_slot(const SolveScalars &sc, int i, int m1) 
     return s;
 }
 
-// A thread's share of a segment: float4 chunks t, t + 256, t + 512, t + 768 (VEC_CH = 4096 floats;
-// segment offsets are multiples of 4 floats, a ragged tail is read and written element-wise).
+// A thread's share of a segment: float4 chunks t, t + 256, t + 512, t + 768 (VEC_CH = 4096 floats).
+// Segment offsets are multiples of 4 floats and lengths are even (complex entries); a problem's
+// theta span is padded to an even number of complex entries, so the float4 that holds a segment's
+// ragged end lies inside the span. Loads and stores are buffer instructions over the segment
+// rounded up to whole float4s: chunks past the end read 0 and are not written (no branches, all
+// loads of a thread in flight together); the two floats past an odd end are read as 0 and written
+// back as the kernel's result for 0 inputs, inside the padding.
 constexpr int VQ = VEC_CH / 1024;
 struct V16 { float v[4 * VQ]; };
 
+typedef unsigned int vu32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t seg_rsrc(const float *base, const VecSeg &sg) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(base + sg.off), (short)0, ((sg.n + 3) & ~3) * 4, 0x00020000);
+}
+
 __device__ __forceinline__ V16 ld16(const float *__restrict__ base, const VecSeg &sg) {
+    const __amdgpu_buffer_rsrc_t rs = seg_rsrc(base, sg);
     V16 r;
 #pragma unroll
     for (int q = 0; q < VQ; ++q) {
         const int e = (threadIdx.x + 256 * q) * 4;
-        if (e + 4 <= sg.n) {
-            const float4 x = *reinterpret_cast<const float4 *>(base + sg.off + e);
-            r.v[4 * q] = x.x; r.v[4 * q + 1] = x.y; r.v[4 * q + 2] = x.z; r.v[4 * q + 3] = x.w;
-        } else {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) r.v[4 * q + u] = (e + u < sg.n) ? base[sg.off + e + u] : 0.f;
-        }
+        const vu32x4 x = __builtin_amdgcn_raw_buffer_load_b128(rs, e * 4, 0, 0);
+        const bool full = e + 4 <= sg.n;   // else at most the first two floats are in the segment
+        r.v[4 * q] = __uint_as_float(x.x);
+        r.v[4 * q + 1] = __uint_as_float(x.y);
+        r.v[4 * q + 2] = full ? __uint_as_float(x.z) : 0.f;
+        r.v[4 * q + 3] = full ? __uint_as_float(x.w) : 0.f;
     }
     return r;
 }
 
 __device__ __forceinline__ void st16(float *__restrict__ base, const VecSeg &sg, const V16 &r) {
+    const __amdgpu_buffer_rsrc_t rs = seg_rsrc(base, sg);
 #pragma unroll
     for (int q = 0; q < VQ; ++q) {
         const int e = (threadIdx.x + 256 * q) * 4;
-        if (e + 4 <= sg.n) {
-            *reinterpret_cast<float4 *>(base + sg.off + e) =
-                make_float4(r.v[4 * q], r.v[4 * q + 1], r.v[4 * q + 2], r.v[4 * q + 3]);
-        } else {
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (e + u < sg.n) base[sg.off + e + u] = r.v[4 * q + u];
-        }
+        const vu32x4 x = {__float_as_uint(r.v[4 * q]), __float_as_uint(r.v[4 * q + 1]),
+                          __float_as_uint(r.v[4 * q + 2]), __float_as_uint(r.v[4 * q + 3])};
+        __builtin_amdgcn_raw_buffer_store_b128(x, rs, e * 4, 0, 0);
     }
 }
 
@@ -226,6 +233,12 @@ __global__ __launch_bounds__(256) void gram_kernel(const VecSeg *__restrict__ se
     const V16 vg = ld16(g, sg);
     const V16 vs = ld16(Sb + h * stride2, sg);
     V16 vy = ld16(gprev, sg);
+    // the first held pair is loaded with the new vectors (an empty range when there is none)
+    VecSeg sg0 = sg;
+    if (count == 0) sg0.n = 0;
+    const int j0 = ring_slot(s, 0, m1);
+    V16 sj = ld16(Sb + j0 * stride2, sg0);
+    V16 yj = ld16(Yb + j0 * stride2, sg0);
 #pragma unroll
     for (int u = 0; u < 4 * VQ; ++u) vy.v[u] = vg.v[u] - vy.v[u];
     st16(Yb + h * stride2, sg, vy);
@@ -236,15 +249,21 @@ __global__ __launch_bounds__(256) void gram_kernel(const VecSeg *__restrict__ se
 #pragma unroll
             for (int k = 0; k < 6; ++k) pp[6 * h + k] = a[k];
     }
+    // the held pairs, each one's loads issued before the block reduction of the previous one
     for (int i = 0; i < count; ++i) {
         const int j = ring_slot(s, i, m1);
-        const V16 sj = ld16(Sb + j * stride2, sg);
-        const V16 yj = ld16(Yb + j * stride2, sg);
+        VecSeg sgn = sg;   // past the last pair: an empty range, the loads return 0 and move no data
+        if (i + 1 >= count) sgn.n = 0;
+        const int jn = ring_slot(s, i + 1, m1);
+        const V16 sn = ld16(Sb + jn * stride2, sgn);
+        const V16 yn = ld16(Yb + jn * stride2, sgn);
         double a[6] = {dot16(sj, vs), dot16(sj, vy), dot16(sj, vg), dot16(yj, vs), dot16(yj, vy), dot16(yj, vg)};
         block_sums<6>(a, red);
         if (threadIdx.x == 0)
 #pragma unroll
             for (int k = 0; k < 6; ++k) pp[6 * j + k] = a[k];
+        sj = sn;
+        yj = yn;
     }
     if (threadIdx.x < 6 * m1) {   // slots that are neither h nor valid
         const int j = threadIdx.x / 6;
@@ -406,16 +425,17 @@ __global__ __launch_bounds__(256) void resid_update_kernel(const VecSeg *__restr
     __shared__ double red[4];
     const VecSeg sg = segs[blockIdx.x];
     const SolveScalars &s = sc[sg.prob];
-    const float al = (float)s.step;
-    const float al2 = (float)(s.step * s.step);
+    // a non-finite step froze this problem: r stays as is (a and b read as 0, nothing written)
     const bool frozen = s.frozen != 0;
+    const float al = frozen ? 0.f : (float)s.step;
+    const float al2 = frozen ? 0.f : (float)(s.step * s.step);
+    VecSeg sgu = sg;
+    if (frozen) sgu.n = 0;
     V16 v = ld16(r, sg);
-    if (!frozen) {
-        const V16 va = ld16(a, sg), vb = ld16(b, sg);
+    const V16 va = ld16(a, sgu), vb = ld16(b, sgu);
 #pragma unroll
-        for (int u = 0; u < 4 * VQ; ++u) v.v[u] += al * va.v[u] + al2 * vb.v[u];
-        st16(r, sg, v);
-    }
+    for (int u = 0; u < 4 * VQ; ++u) v.v[u] += al * va.v[u] + al2 * vb.v[u];
+    st16(r, sgu, v);
     double acc[1] = {dot16(v, v)};
     block_sums<1>(acc, red);
     if (threadIdx.x == 0) part[sg.part] = acc[0];

@@ -36,7 +36,7 @@ struct AsmItem {
     int32_t prob;   // index into the ProbOff table
 };
 constexpr int ASM_B = 64;    // assembly block edge (rows and columns of a tile block)
-constexpr int ASM_KC = 32;   // rank entries staged per step
+constexpr int ASM_KC = 16;   // rank entries staged per step
 
 // Gradient work item.
 enum GradKind : int32_t { G_L = 0, G_Q = 1, G_R = 2, G_Z = 3 };

@@ -5,18 +5,18 @@
 // X_ji = X_ij^T; X_ii = Q_ii Q_ii^T or (Z_ii + Z_ii^T)/2. The directional
 // form used by the exact line search expands C(theta + a p) = C(theta) +
 // a X1 + a^2 X2, tile by tile: X1 = P_L R + L P_R, X2 = P_L P_R (and the
-// Q Q^T / dense analogues). Each workgroup builds one 32 x 64 block from
-// factors staged in LDS 32 rank entries at a time; sub-diagonal blocks are
-// written twice (directly and transposed through LDS, both coalesced), so
-// X = X^T holds bit for bit. Q Q^T entries are computed with the operands
-// ordered by (max(a,b), min(a,b)) so the (a,b) and (b,a) entries follow the
-// same rounding path.
+// Q Q^T / dense analogues). Each workgroup builds one 64 x 64 block on the
+// FP32 matrix cores from factors staged in LDS 16 rank entries at a time;
+// every product is staged through LDS once and written from there twice
+// (directly and transposed, both with whole rows per wave), so X = X^T holds
+// bit for bit; Q Q^T tiles are built on and below the block diagonal only
+// and mirrored.
 //
 // Gradient (ADMM solver section, eqs. DXLR): with W = D^H r and W' = W + W^T,
 // grad L = W' R^H, grad R = L^H W', grad Q = W' conj(Q), grad Z = W'/2.
 // W' is never formed: each block of W'_ij is built in LDS from a block of
 // W_ij plus the transposed block of W_ji, both read coalesced.
-#include "common.hpp"
+#include "gemm_common.hpp"
 
 namespace tlr {
 namespace {
@@ -44,16 +44,25 @@ __device__ __forceinline__ void put(float2 *X, int64_t o, int64_t low, float2 v)
 }
 
 constexpr int AB = ASM_B;            // block edge (rows and columns)
-constexpr int SL_P = ASM_KC + 1;     // row-factor stage [AB][SL_P]
-constexpr int SR_P = AB + 1;         // column-factor stage [ASM_KC][SR_P]
-constexpr int ST_P = AB + 1;         // transpose stage [AB][ST_P]
-constexpr int STAGE_F2 = AB * SL_P + ASM_KC * SR_P;
+constexpr int AKC = ASM_KC;          // rank entries staged per step
+constexpr int AAP = AB + 1;          // row-factor planes [AKC][AAP] floats (k-major: rows fastest)
+constexpr int ABP = AB + 1;          // column-factor stage [AKC][ABP] complex
+constexpr int ST_P = AB + 1;         // transpose stage [AB][ST_P] complex
+constexpr int A_PL = AKC * AAP;      // floats per row-factor plane
+constexpr int B_ST = AKC * ABP;      // complex per column-factor stage
 
-// Each workgroup builds one 64 x 64 block of a tile; thread (ty, tx) = (t / 16, t % 16) owns
-// rows ty + 16 i and columns tx + 16 j (i, j < 4): a 4 x 4 register block, so every complex
-// value read from LDS feeds 4 (12 in the directional form) complex multiply-adds.
+// Each workgroup builds one 64 x 64 block of a tile on the FP32 matrix cores. A factor product
+// F G (F: 64 x k rows of L, P_L or Q; G: k x 64 columns of R, P_R or Q^T) is a complex GEMM with
+// K = k, evaluated in realified form: one v_mfma_f32_32x32x2_f32 per complex k takes (Re, Im) of
+// F[m][k] as its two A entries and the real 2 x 2 block [[Re g, Im g], [-Im g, Re g]] of G[k][n] as
+// B, so the real output columns come out as interleaved (re, im) pairs. Wave w owns complex columns
+// 16 w .. 16 w + 15 of the block and both 32-row halves: X (or X1 and X2) in two (four) accumulators.
+// The row factors sit in LDS as separate real and imaginary planes, k-major, so a lane's A entry
+// is one conflict-free float read; the column factors stay interleaved complex. 33 KB of LDS and
+// at most 128 VGPRs (launch bound: 4 waves per SIMD) keep four workgroups on a CU, so the write
+// phases of some overlap the loads and products of others.
 template <bool DIR, bool OUTB>
-__global__ __launch_bounds__(256) void assemble_kernel(const TileDesc *__restrict__ tiles,
+__global__ __launch_bounds__(256, 4) void assemble_kernel(const TileDesc *__restrict__ tiles,
                                                        const AsmItem *__restrict__ items,
                                                        const ProbOff *__restrict__ probs,
                                                        const float2 *__restrict__ theta_base,
@@ -61,12 +70,15 @@ __global__ __launch_bounds__(256) void assemble_kernel(const TileDesc *__restric
                                                        float2 *__restrict__ X_base,
                                                        float2 *__restrict__ X2_base,
                                                        int64_t x2w, int64_t low) {
-    constexpr int NSTAGE = DIR ? 2 : 1;
-    constexpr int SM_F2 = (NSTAGE * STAGE_F2 > AB * ST_P) ? NSTAGE * STAGE_F2 : AB * ST_P;
-    __shared__ float2 smem[SM_F2];
-    float2 *sL = smem;                               // [NSTAGE][AB][SL_P]
-    float2 *sR = smem + NSTAGE * AB * SL_P;          // [NSTAGE][ASM_KC][SR_P]
-    float2 *sT = smem;                               // transpose stage, reused after the k loop
+    constexpr int NF = DIR ? 2 : 1;   // factor sets: (L, R) and, for the directional form, (P_L, P_R)
+    constexpr int SA_F = NF * 2 * A_PL;                 // floats
+    constexpr int SB_F = NF * 2 * B_ST;                 // floats
+    constexpr int ST_F = 2 * AB * ST_P;
+    constexpr int SM_F = (SA_F + SB_F > ST_F) ? SA_F + SB_F : ST_F;
+    __shared__ float smem[SM_F];
+    float *sA = smem;                                  // [NF][re, im][AKC][AAP]
+    float2 *sB = reinterpret_cast<float2 *>(smem + SA_F);   // [NF][AKC][ABP]
+    float2 *sT = reinterpret_cast<float2 *>(smem);     // transpose stage, reused after the k loop
 
     const AsmItem it = items[blockIdx.x];
     const TileDesc td = tiles[it.tile];
@@ -81,19 +93,12 @@ __global__ __launch_bounds__(256) void assemble_kernel(const TileDesc *__restric
     const int64_t ldx = po.ldx;
 
     const int t = threadIdx.x;
-    const int tx = t & 15, ty = t >> 4;
     const int r0 = it.r0, c0 = it.c0;
     const int nrow = min(AB, td.di - r0);
     const int ncol = min(AB, td.dj - c0);
 
-    float2 acc[4][4], acc2[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) { acc[i][j] = make_float2(0.f, 0.f); acc2[i][j] = acc[i][j]; }
-
     if (td.kind == TILE_DENSE) {
-        // X = (Z + Z^T)/2 ; X1 = (P + P^T)/2 ; X2 = 0
+        // X = (Z + Z^T)/2 ; X1 = (P + P^T)/2 ; X2 = 0 (element-wise, no products)
         const float2 *Z = DIR ? pv + td.offA : theta + td.offA;
         const int d = td.di;
         for (int e = t; e < AB * AB; e += 256) {   // transposed block Z[c0+cc][r0+rr]
@@ -103,101 +108,121 @@ __global__ __launch_bounds__(256) void assemble_kernel(const TileDesc *__restric
             sT[cc * ST_P + rr] = v;
         }
         __syncthreads();
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int rr = ty + 16 * i, cc = tx + 16 * j;
-                if (rr < nrow && cc < ncol) {
-                    const float2 zd = Z[(int64_t)(r0 + rr) * d + c0 + cc];
-                    const float2 zt = sT[cc * ST_P + rr];
-                    acc[i][j] = make_float2(0.5f * (zd.x + zt.x), 0.5f * (zd.y + zt.y));
-                }
+        for (int e = t; e < AB * AB; e += 256) {
+            const int rr = e >> 6, cc = e & 63;
+            if (rr < nrow && cc < ncol) {
+                const float2 zd = Z[(int64_t)(r0 + rr) * d + c0 + cc];
+                const float2 zt = sT[cc * ST_P + rr];
+                const int64_t o = (td.row0 + r0 + rr) * ldx + td.col0 + c0 + cc;
+                put<OUTB>(X, o, low, make_float2(0.5f * (zd.x + zt.x), 0.5f * (zd.y + zt.y)));
+                if (DIR) put<OUTB>(X2, o, low, make_float2(0.f, 0.f));
             }
-        __syncthreads();
-    } else {
-        const bool qq = (td.kind == TILE_QQ);
-        const int k = td.k;
-        const float2 *Lf = theta + td.offA;                 // L (di x k) or Q (d x k)
-        const float2 *Rf = qq ? Lf : theta + td.offB;       // R (k x dj) or Q again
-        const float2 *PLf = DIR ? pv + td.offA : nullptr;
-        const float2 *PRf = DIR ? (qq ? PLf : pv + td.offB) : nullptr;
-        for (int kc0 = 0; kc0 < k; kc0 += ASM_KC) {
-            const int kn = min(ASM_KC, k - kc0);
-            for (int e = t; e < AB * ASM_KC; e += 256) {    // row factor rows r0.. : [rr][kk]
-                const int rr = e >> 5, kk = e & 31;
-                const bool ok = rr < nrow && kk < kn;
-                const int64_t o = (int64_t)(r0 + rr) * k + kc0 + kk;
-                sL[rr * SL_P + kk] = ok ? Lf[o] : make_float2(0.f, 0.f);
-                if (DIR) sL[AB * SL_P + rr * SL_P + kk] = ok ? PLf[o] : make_float2(0.f, 0.f);
-            }
-            for (int e = t; e < ASM_KC * AB; e += 256) {    // column factor R[kc0+kk][c0+cc] or Q[c0+cc][kc0+kk]
-                int kk, cc;
-                int64_t o;
-                if (qq) { cc = e >> 5; kk = e & 31; o = (int64_t)(c0 + cc) * k + kc0 + kk; }
-                else { kk = e >> 6; cc = e & 63; o = (int64_t)(kc0 + kk) * td.dj + c0 + cc; }
-                const bool ok = cc < ncol && kk < kn;
-                sR[kk * SR_P + cc] = ok ? Rf[o] : make_float2(0.f, 0.f);
-                if (DIR) sR[ASM_KC * SR_P + kk * SR_P + cc] = ok ? PRf[o] : make_float2(0.f, 0.f);
-            }
-            __syncthreads();
-#pragma unroll 2
-            for (int kk = 0; kk < kn; ++kk) {
-                float2 lv[4], rv[4], plv[4], prv[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    lv[i] = sL[(ty + 16 * i) * SL_P + kk];
-                    rv[i] = sR[kk * SR_P + tx + 16 * i];
-                    if (DIR) {
-                        plv[i] = sL[AB * SL_P + (ty + 16 * i) * SL_P + kk];
-                        prv[i] = sR[ASM_KC * SR_P + kk * SR_P + tx + 16 * i];
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        if (!DIR) {
-                            acc[i][j] = cadd(acc[i][j], cmul(lv[i], rv[j]));
-                        } else {
-                            acc[i][j] = cadd(acc[i][j], cadd(cmul(plv[i], rv[j]), cmul(lv[i], prv[j])));
-                            acc2[i][j] = cadd(acc2[i][j], cmul(plv[i], prv[j]));
-                        }
-                    }
-            }
-            __syncthreads();
         }
+        return;
     }
 
-    // Q Q^T tiles are built on and below the block diagonal only and mirrored, so the tile is
-    // symmetric bit for bit: direct write where row >= column, transposed write where row > column
-    const bool qq = td.kind == TILE_QQ;
+    const int lane = t & 63, wave = t >> 6;
+    const int j32 = lane & 31, half = lane >> 5;
+    const int cb = 16 * wave;                                   // first complex column of the wave
+    const int bidx = 2 * cb + (j32 ^ half);                     // float of the realified B entry
+    const uint32_t bsign = (half && !(j32 & 1)) ? 0x80000000u : 0u;   // -Im g in the second k row
+
+    floatx16 acc[2][2];   // [X | X1, X2][row half]
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int f = 0; f < 2; ++f)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int rr = ty + 16 * i, cc = tx + 16 * j;
-            if (rr < nrow && cc < ncol && (!qq || r0 + rr >= c0 + cc)) {
-                const int64_t o = (td.row0 + r0 + rr) * ldx + td.col0 + c0 + cc;
-                put<OUTB>(X, o, low, acc[i][j]);
-                if (DIR) put<OUTB>(X2, o, low, acc2[i][j]);
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[f][i][r] = 0.f;
+
+    const bool qq = (td.kind == TILE_QQ);
+    const int k = td.k;
+    const float2 *Lf = theta + td.offA;                 // L (di x k) or Q (d x k)
+    const float2 *Rf = qq ? Lf : theta + td.offB;       // R (k x dj) or Q again
+    const float2 *PLf = DIR ? pv + td.offA : nullptr;
+    const float2 *PRf = DIR ? (qq ? PLf : pv + td.offB) : nullptr;
+    for (int kc0 = 0; kc0 < k; kc0 += AKC) {
+        const int kn = min(AKC, k - kc0);
+        for (int e = t; e < AB * AKC; e += 256) {    // row factors: rows r0.., k contiguous in theta
+            const int rr = e / AKC, kk = e % AKC;
+            const bool ok = rr < nrow && kk < kn;
+            const int64_t o = (int64_t)(r0 + rr) * k + kc0 + kk;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const float2 v = ok ? (f ? PLf : Lf)[o] : make_float2(0.f, 0.f);
+                float *pl = sA + f * 2 * A_PL + kk * AAP + rr;
+                pl[0] = v.x;
+                pl[A_PL] = v.y;
             }
         }
-    if (td.kind == TILE_DENSE) return;
-    // transposed block X_ji = X_ij^T, staged through LDS for coalesced rows
-    for (int pass = 0; pass < (DIR ? 2 : 1); ++pass) {
+        for (int e = t; e < AKC * AB; e += 256) {    // column factors G[kk][cc] = R[kc0+kk][c0+cc] or Q[c0+cc][kc0+kk]
+            int kk, cc;
+            int64_t o;
+            if (qq) { cc = e / AKC; kk = e % AKC; o = (int64_t)(c0 + cc) * k + kc0 + kk; }
+            else { kk = e >> 6; cc = e & 63; o = (int64_t)(kc0 + kk) * td.dj + c0 + cc; }
+            const bool ok = cc < ncol && kk < kn;
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                sB[f * B_ST + kk * ABP + cc] = ok ? (f ? PRf : Rf)[o] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        const float *bf = reinterpret_cast<const float *>(sB);
+#pragma unroll 2
+        for (int kk = 0; kk < kn; ++kk) {
+            float a[NF][2], b[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) a[f][i] = sA[f * 2 * A_PL + half * A_PL + kk * AAP + 32 * i + j32];
+                b[f] = __uint_as_float(__float_as_uint(bf[2 * (f * B_ST + kk * ABP) + bidx]) ^ bsign);
+            }
+            if (!DIR) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    acc[0][i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][i], b[0], acc[0][i], 0, 0, 0);
+            } else {
+                // X1 += P_L R + L P_R ; X2 += P_L P_R (the two X1 products of a row half three apart)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    acc[0][i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[NF - 1][i], b[0], acc[0][i], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    acc[1][i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[NF - 1][i], b[NF - 1], acc[1][i], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    acc[0][i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][i], b[NF - 1], acc[0][i], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+
+    // Lane (j32, half) holds component j32 & 1 of complex column cb + j32 / 2 for rows
+    // acc_row(r, lane) (+ 32 for the second half). Each product is staged through LDS once and
+    // written from there twice, both times with whole rows per wave: X_ij directly and X_ji = X_ij^T.
+    // Q Q^T tiles are built on and below the block diagonal only and mirrored, so the tile is
+    // symmetric bit for bit: direct write where row >= column, transposed write where row > column.
+    const int ccol = cb + (j32 >> 1);
+    const int comp = j32 & 1;
+    float *sTf = smem;   // [row][ST_P] complex
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                sT[(tx + 16 * j) * ST_P + ty + 16 * i] = (pass == 0) ? acc[i][j] : acc2[i][j];
+            for (int r = 0; r < 16; ++r)
+                sTf[2 * ((32 * i + acc_row(r, lane)) * ST_P + ccol) + comp] = acc[f][i][r];
         __syncthreads();
-        float2 *dst = (pass == 0) ? X : X2;
+        float2 *dst = f ? X2 : X;
+        for (int e = t; e < AB * AB; e += 256) {
+            const int rr = e >> 6, cc = e & 63;
+            if (rr < nrow && cc < ncol && (!qq || r0 + rr >= c0 + cc))
+                put<OUTB>(dst, (td.row0 + r0 + rr) * ldx + td.col0 + c0 + cc, low, sT[rr * ST_P + cc]);
+        }
         for (int e = t; e < AB * AB; e += 256) {
             const int cc = e >> 6, rr = e & 63;
             if (cc < ncol && rr < nrow && (!qq || r0 + rr > c0 + cc))
-                put<OUTB>(dst, (td.col0 + c0 + cc) * ldx + td.row0 + r0 + rr, low, sT[cc * ST_P + rr]);
+                put<OUTB>(dst, (td.col0 + c0 + cc) * ldx + td.row0 + r0 + rr, low, sT[rr * ST_P + cc]);
         }
     }
 }

@@ -227,108 +227,132 @@ __global__ __launch_bounds__(256, 4) void assemble_kernel(const TileDesc *__rest
     }
 }
 
-constexpr int GW_P = GR_CH + 1;        // sW [GR_ROWS][GW_P]: W' with the contraction index fastest
-constexpr int GF_P = GR_KK + 1;        // sF [GR_CH][GF_P]: conjugated factor, rank index fastest
+constexpr int GW_P = GR_ROWS + 1;      // W' planes [GR_CH][GW_P] floats (contraction index major)
+constexpr int GF_P = GR_KK + 1;        // factor stage [GR_CH][GF_P] complex
+constexpr int GW_PL = GR_CH * GW_P;    // floats per W' plane
+constexpr int GO_P = GR_ROWS + 1;      // output stage of G_R [GR_KK][GO_P] complex
 
-// One gradient item: a 64 x (16 KQ) block of G = W' conj(F) where
+// One gradient item: a 64 x kn block (kn <= 64 rank entries from b0) of G = W' conj(F), where
 //   G_L: rows of the tile, F[c][kk] = R[kk][c]    (G_L = W' R^H, contraction over tile columns)
 //   G_Q: rows of the tile, F[c][kk] = Q[c][kk]    (G_Q = (W + W^T) conj(Q))
 //   G_R: cols of the tile, F[r][kk] = L[r][kk]    (G_R^T = W'^T conj(L), contraction over tile rows)
-// with W' = W_ij + W_ji^T built in LDS chunk by chunk. Thread (ty, tx) owns out-rows ty + 16 i
-// (i < 4) and rank entries tx + 16 j (j < KQ).
-template <int KQ>
+// with W' = W_ij + W_ji^T built in LDS chunk by chunk (both parts' loads issued together, each read
+// along its own rows). The contraction runs on the FP32 matrix cores in realified form (one
+// v_mfma_f32_32x32x2_f32 per complex contraction step: (Re, Im) of W'[m][c] as the two A entries,
+// the real 2 x 2 block of conj(F[c][n]) as B). Wave w owns rank entries 16 w .. 16 w + 15 and both
+// 32-row halves; waves past the item's rank only stage data. W' sits in LDS as re / im planes with
+// the contraction index major (one conflict-free float per A entry); G_R is transposed through LDS
+// so its rows are written whole.
 __device__ __forceinline__ void grad_block(const GradItem &it, const TileDesc &td, const float2 *__restrict__ W,
                                            int64_t ldw, const float2 *__restrict__ theta, float2 *__restrict__ g,
-                                           float2 *sW, float2 *sF) {
+                                           float *smem) {
+    float *sW = smem;                                              // [re, im][GR_CH][GW_P]
+    float2 *sF = reinterpret_cast<float2 *>(smem + 2 * GW_PL);     // [GR_CH][GF_P]
     const int t = threadIdx.x;
-    const int tx = t & 15, ty = t >> 4;
+    const int lane = t & 63, wave = t >> 6;
+    const int j32 = lane & 31, half = lane >> 5;
     const int k = td.k;
     const int a0 = it.a0, b0 = it.b0;
-    const int kn = min(16 * KQ, k - b0);
+    const int kn = min(GR_KK, k - b0);
     const bool colside = it.kind == G_R;
     const int nout = min(GR_ROWS, (colside ? td.dj : td.di) - a0);   // out-rows in this item
     const int ncon = colside ? td.di : td.dj;                        // contraction length
     const float2 *F = it.kind == G_L ? theta + td.offB : theta + td.offA;
+    const bool active = 16 * wave < kn;
+    const int fidx = 2 * 16 * wave + (j32 ^ half);                   // float of the realified B entry
+    const uint32_t fsign = (!half && (j32 & 1)) ? 0x80000000u : 0u;  // conj: -Im f in the first k row
 
-    float2 acc[4][KQ];
+    floatx16 acc[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < KQ; ++j) acc[i][j] = make_float2(0.f, 0.f);
+        for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
 
     for (int c0 = 0; c0 < ncon; c0 += GR_CH) {
         const int cn = min(GR_CH, ncon - c0);
-        if (!colside) {
-            // sW[rr][cc] = W_ij[a0+rr][c0+cc] + W_ji[c0+cc][a0+rr]
-            for (int e = t; e < GR_ROWS * GR_CH; e += 256) {
-                const int rr = e >> 5, cc = e & 31;
-                float2 v = make_float2(0.f, 0.f);
-                if (rr < nout && cc < cn) v = W[(td.row0 + a0 + rr) * ldw + td.col0 + c0 + cc];
-                sW[rr * GW_P + cc] = v;
-            }
-        } else {
-            // sW[cc][rr] = W_ij[c0+rr][a0+cc] + W_ji[a0+cc][c0+rr]   (out-row cc is a tile column)
-            for (int e = t; e < GR_CH * GR_ROWS; e += 256) {
-                const int rr = e >> 6, cc = e & 63;
-                float2 v = make_float2(0.f, 0.f);
-                if (cc < nout && rr < cn) v = W[(td.row0 + c0 + rr) * ldw + td.col0 + a0 + cc];
-                sW[cc * GW_P + rr] = v;
-            }
+        // W' = W_ij part + W_ji part: both parts' loads are issued before either is stored
+        //   part 0: W'[m][c] = W_ij[a0+m][c0+c] (G_L, G_Q) or W_ij[c0+c][a0+m] (G_R)
+        //   part 1: + W_ji[c0+c][a0+m] (G_L, G_Q) or + W_ji[a0+m][c0+c] (G_R)
+        float2 v0[GR_ROWS * GR_CH / 256], v1[GR_ROWS * GR_CH / 256];
+#pragma unroll
+        for (int u = 0; u < GR_ROWS * GR_CH / 256; ++u) {
+            const int e = t + 256 * u;
+            int m, c;
+            int64_t o;
+            if (!colside) { m = e >> 5; c = e & 31; o = (td.row0 + a0 + m) * ldw + td.col0 + c0 + c; }
+            else { c = e >> 6; m = e & 63; o = (td.row0 + c0 + c) * ldw + td.col0 + a0 + m; }
+            v0[u] = (m < nout && c < cn) ? W[o] : make_float2(0.f, 0.f);
+            if (!colside) { c = e >> 6; m = e & 63; o = (td.col0 + c0 + c) * ldw + td.row0 + a0 + m; }
+            else { m = e >> 5; c = e & 31; o = (td.col0 + a0 + m) * ldw + td.row0 + c0 + c; }
+            v1[u] = (m < nout && c < cn) ? W[o] : make_float2(0.f, 0.f);
         }
-        for (int e = t; e < GR_CH * 16 * KQ; e += 256) {
-            const int cc = e / (16 * KQ), kk = e % (16 * KQ);
-            float2 v = make_float2(0.f, 0.f);
-            if (cc < cn && kk < kn) {
-                const int64_t o = it.kind == G_L ? (int64_t)(b0 + kk) * td.dj + c0 + cc
-                                                 : (int64_t)(c0 + cc) * k + b0 + kk;
-                v = F[o];
-            }
-            sF[cc * GF_P + kk] = v;
+#pragma unroll
+        for (int u = 0; u < GR_ROWS * GR_CH / 256; ++u) {
+            const int e = t + 256 * u;
+            int m, c;
+            if (!colside) { m = e >> 5; c = e & 31; } else { c = e >> 6; m = e & 63; }
+            sW[c * GW_P + m] = v0[u].x;
+            sW[GW_PL + c * GW_P + m] = v0[u].y;
         }
-        __syncthreads();
-        if (!colside) {
-            for (int e = t; e < GR_CH * GR_ROWS; e += 256) {
-                const int cc = e >> 6, rr = e & 63;
-                if (rr < nout && cc < cn) {
-                    const float2 wt = W[(td.col0 + c0 + cc) * ldw + td.row0 + a0 + rr];
-                    sW[rr * GW_P + cc] = cadd(sW[rr * GW_P + cc], wt);
-                }
-            }
-        } else {
-            for (int e = t; e < GR_ROWS * GR_CH; e += 256) {
-                const int cc = e >> 5, rr = e & 31;
-                if (cc < nout && rr < cn) {
-                    const float2 wt = W[(td.col0 + a0 + cc) * ldw + td.row0 + c0 + rr];
-                    sW[cc * GW_P + rr] = cadd(sW[cc * GW_P + rr], wt);
-                }
-            }
+        for (int e = t; e < GR_CH * GR_KK; e += 256) {
+            int c, kk;
+            int64_t o;
+            if (it.kind == G_L) { kk = e >> 5; c = e & 31; o = (int64_t)(b0 + kk) * td.dj + c0 + c; }
+            else { c = e >> 6; kk = e & 63; o = (int64_t)(c0 + c) * k + b0 + kk; }
+            sF[c * GF_P + kk] = (c < cn && kk < kn) ? F[o] : make_float2(0.f, 0.f);
         }
         __syncthreads();
+#pragma unroll
+        for (int u = 0; u < GR_ROWS * GR_CH / 256; ++u) {
+            const int e = t + 256 * u;
+            int m, c;
+            if (!colside) { c = e >> 6; m = e & 63; } else { m = e >> 5; c = e & 31; }
+            sW[c * GW_P + m] += v1[u].x;
+            sW[GW_PL + c * GW_P + m] += v1[u].y;
+        }
+        __syncthreads();
+        if (active) {
+            const float *fw = reinterpret_cast<const float *>(sF);
 #pragma unroll 4
-        for (int cc = 0; cc < cn; ++cc) {
-            float2 w[4], f[KQ];
+            for (int c = 0; c < cn; ++c) {
+                const float b = __uint_as_float(__float_as_uint(fw[2 * c * GF_P + fidx]) ^ fsign);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) w[i] = sW[(ty + 16 * i) * GW_P + cc];
-#pragma unroll
-            for (int j = 0; j < KQ; ++j) f[j] = sF[cc * GF_P + tx + 16 * j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < KQ; ++j) acc[i][j] = cadd(acc[i][j], cmulc(w[i], f[j]));
+                for (int i = 0; i < 2; ++i)
+                    acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(sW[half * GW_PL + c * GW_P + 32 * i + j32], b,
+                                                                   acc[i], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
+    // lane (j32, half) holds component j32 & 1 of rank entry 16 wave + j32 / 2 for out-rows
+    // 32 i + acc_row(r, lane)
+    const int kk = 16 * wave + (j32 >> 1), comp = j32 & 1;
+    if (!colside) {
+        // grad L / grad Q at the factor's own offset, rows of k entries
+        if (active)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < KQ; ++j) {
-            const int rr = ty + 16 * i, kk = tx + 16 * j;
-            if (rr < nout && kk < kn) {
-                // grad L / grad Q at the factor's own offset; grad R = L^H W' has the entries of acc
-                if (!colside) g[td.offA + (int64_t)(a0 + rr) * k + b0 + kk] = acc[i][j];
-                else g[td.offB + (int64_t)(b0 + kk) * td.dj + a0 + rr] = acc[i][j];
-            }
-        }
+                for (int r = 0; r < 16; ++r) {
+                    const int m = 32 * i + acc_row(r, lane);
+                    if (m < nout && kk < kn)
+                        reinterpret_cast<float *>(g)[2 * (td.offA + (int64_t)(a0 + m) * k + b0 + kk) + comp] = acc[i][r];
+                }
+        return;
+    }
+    // grad R = L^H W' has the entries of G_R^T: stage [kk][m] and write rows of R's gradient
+    float *sO = smem;   // [GR_KK][GO_P] complex
+    if (active)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) sO[2 * (kk * GO_P + 32 * i + acc_row(r, lane)) + comp] = acc[i][r];
+    __syncthreads();
+    const float2 *sO2 = reinterpret_cast<const float2 *>(sO);
+    for (int e = t; e < GR_KK * GR_ROWS; e += 256) {
+        const int q = e >> 6, m = e & 63;
+        if (q < kn && m < nout) g[td.offB + (int64_t)(b0 + q) * td.dj + a0 + m] = sO2[q * GO_P + m];
+    }
 }
 
 __global__ __launch_bounds__(256) void grad_kernel(const TileDesc *__restrict__ tiles,
@@ -337,8 +361,11 @@ __global__ __launch_bounds__(256) void grad_kernel(const TileDesc *__restrict__ 
                                                    const float2 *__restrict__ W_base,
                                                    const float2 *__restrict__ theta_base,
                                                    float2 *__restrict__ g_base) {
-    __shared__ float2 sW[GR_ROWS * GW_P];
-    __shared__ float2 sF[GR_CH * GF_P];
+    constexpr int SM_G = 2 * GW_PL + 2 * GR_CH * GF_P;
+    constexpr int SM_O = 2 * GR_KK * GO_P;
+    constexpr int SM_Z = 2 * GZ_BC * (GZ_BR + 1);
+    constexpr int SM_F = SM_G > SM_O ? (SM_G > SM_Z ? SM_G : SM_Z) : (SM_O > SM_Z ? SM_O : SM_Z);
+    __shared__ float smem[SM_F];
     const GradItem it = items[blockIdx.x];
     const TileDesc td = tiles[it.tile];
     const ProbOff po = probs[it.prob];
@@ -350,6 +377,7 @@ __global__ __launch_bounds__(256) void grad_kernel(const TileDesc *__restrict__ 
 
     if (it.kind == G_Z) {
         // grad Z = (W_ii + W_ii^T)/2 on the block rows a0.., cols b0..
+        float2 *sW = reinterpret_cast<float2 *>(smem);
         const int d = td.di;
         const int a0 = it.a0, b0 = it.b0;
         const int nrow = min(GZ_BR, d - a0), ncol = min(GZ_BC, d - b0);
@@ -371,12 +399,7 @@ __global__ __launch_bounds__(256) void grad_kernel(const TileDesc *__restrict__ 
         }
         return;
     }
-    switch (it.kq) {
-    case 1: grad_block<1>(it, td, W, ldw, theta, g, sW, sF); break;
-    case 2: grad_block<2>(it, td, W, ldw, theta, g, sW, sF); break;
-    case 3: grad_block<3>(it, td, W, ldw, theta, g, sW, sF); break;
-    default: grad_block<4>(it, td, W, ldw, theta, g, sW, sF); break;
-    }
+    grad_block(it, td, W, ldw, theta, g, smem);
 }
 
 }  // namespace

@@ -852,12 +852,16 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
                                     c.w.sc, c.w.partials, s));
         if (lam != 0.0)
             if ((st = fin(c, fin_args(FIN_THNORM, c.w.sc), c.D.tcount, 0, 1))) return st;
-        HIP_TRY(launch_resid_update(c.D.rsegs, R.nrs, (float *)c.w.r, (const float *)c.w.a, (const float *)c.w.b,
-                                    c.w.sc, c.w.partials, s));
-        if ((st = split_r_transpose(c))) return st;
-        if ((st = fin_f(R, record_base >= 0 ? record_base + t + 1 : -1, lam, R.T.rseg_per_prob))) return st;
-        if (R.opts->resid_refresh > 0 && (t + 1) % R.opts->resid_refresh == 0)
+        // residual: recomputed from theta every resid_refresh iterations, else updated in place
+        const bool refresh = R.opts->resid_refresh > 0 && (t + 1) % R.opts->resid_refresh == 0;
+        if (refresh) {
             if ((st = objective_fresh(R, record_base >= 0 ? record_base + t + 1 : -1, lam))) return st;
+        } else {
+            HIP_TRY(launch_resid_update(c.D.rsegs, R.nrs, (float *)c.w.r, (const float *)c.w.a,
+                                        (const float *)c.w.b, c.w.sc, c.w.partials, s));
+            if ((st = split_r_transpose(c))) return st;
+            if ((st = fin_f(R, record_base >= 0 ? record_base + t + 1 : -1, lam, R.T.rseg_per_prob))) return st;
+        }
         std::swap(R.gcur, R.gprev);
     }
     return TLRMDD_OK;

@@ -10,17 +10,20 @@
 // its real and imaginary planes while it is stored to LDS, and each lane forms
 // the sums Ar + Ai, Br + Bi of its operand fragments after reading them.
 //
-// Tiling: 512 threads = 8 waves; workgroup tile 128 rows x 128 complex columns,
-// 32 complex k per stage, double-buffered LDS (two A planes k-major with an
-// odd pitch, two B planes row-major: conflict-free operand reads and stores;
-// 2 x 64.3 KiB). One v_mfma_f32_32x32x2_f32 consumes two complex k of one
-// plane pair.
-//   GM_STORE / GM_RESID: waves 2 (rows) x 4 (columns), each 64 rows x 32 columns,
-//     accumulators T1, T2, T3 for two 32 x 32 blocks;
-//   GM_LINE: the B tile holds X1 and X2 at the same 64 columns; waves 4 x 2,
-//     each 32 rows x 32 columns of both, so a, b and r meet in one thread.
+// Tiling: 256 threads = 4 waves (2 x 2), two workgroups per CU (the barrier and
+// epilogue of one overlap the products of the other); workgroup tile 128 rows x
+// 128 complex columns, 16 complex k per stage, double-buffered LDS (two A planes
+// k-major with an odd pitch, two B planes row-major: conflict-free operand reads;
+// 2 x 32.1 KiB). Each wave owns 64 rows x 64 columns: accumulators T1, T2, T3 for
+// 2 x 2 blocks of 32 x 32 (192 of its 256 VGPRs), so each operand fragment read
+// from LDS feeds two MFMAs. One v_mfma_f32_32x32x2_f32 consumes two complex k of
+// one plane pair.
+//   GM_STORE / GM_RESID: wave columns wn*64 .. +63;
+//   GM_LINE: the B tile holds X1 and X2 at the same 64 columns; a wave's column
+//     block 0 is 32 columns of X1 and block 1 the same 32 columns of X2, so a, b
+//     and r meet in one thread.
 // Epilogues as the four-product kernel: C; C = AB - U with FP64 partial sums of
-// |C|^2; a, b with the five line-search sums. K must be a multiple of 32.
+// |C|^2; a, b with the five line-search sums. K must be a multiple of 16.
 #include "gemm_common.hpp"
 
 namespace tlr {
@@ -30,7 +33,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int BM = GEMM_BM, BN = GEMM_BN;
-constexpr int BK = 2 * GEMM_BK;       // complex k per stage
+constexpr int BK = GEMM_BK;           // complex k per stage
 constexpr int AP = BM + 1;            // A plane pitch (floats per complex-k row, k-major)
 constexpr int A_PLANE = BK * AP;
 constexpr int BP = BN;                // B plane pitch (floats per k row)
@@ -38,7 +41,7 @@ constexpr int B_PLANE = BK * BP;
 constexpr int STAGE = 2 * A_PLANE + 2 * B_PLANE;   // floats: re and im planes of A and B
 
 template <int MODE>
-__global__ __launch_bounds__(512) void cgemm3m_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
     __shared__ float sm[2][STAGE];
 
     const int z = blockIdx.y;
@@ -67,7 +70,10 @@ __global__ __launch_bounds__(512) void cgemm3m_kernel(GemmArgs g) {
     // ---- global -> register loaders (operands padded to whole tiles: no bounds checks) ----
     // A: row t/4, complex k 8 (t%4) .. +7 (four float4); B: k row t/16, complex columns
     // 4 (t%16) .. +3 and 64 + 4 (t%16) .. +3 (two float4 each)
-    const int a_row = t >> 2, a_q = t & 3;
+    constexpr int AQ = BK / 8;                     // threads per A row (8 complex k each)
+    constexpr int BR = 256 / 16;                   // B rows per pass (16 threads per row)
+    static_assert(BK % 8 == 0 && BK <= 16, "A loader");
+    const int a_row = t / AQ, a_q = t % AQ;
     const int b_row = t >> 4, b_q = t & 15;
     const __amdgpu_buffer_rsrc_t rsA =
         __builtin_amdgcn_make_buffer_rsrc((void *)A, (short)0, (int)g.bytesA, 0x00020000);
@@ -86,14 +92,17 @@ __global__ __launch_bounds__(512) void cgemm3m_kernel(GemmArgs g) {
         const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
         return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
     };
-    float4 ra[4], rb[4];
+    constexpr int NBQ = BK / BR;                   // B row passes per stage
+    float4 ra[4], rb[NBQ][4];
     auto load = [&](int k0) {
         const uint32_t sa = (uint32_t)k0 * 8u;
-        const uint32_t sb = (uint32_t)((int64_t)k0 * g.ldb * 8);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            ra[q] = ld16(rsA, offA + 16 * q, sa);
-            rb[q] = ld16(rsB, offB[q >> 1] + 16 * (q & 1), sb);
+        for (int q = 0; q < 4; ++q) ra[q] = ld16(rsA, offA + 16 * q, sa);
+#pragma unroll
+        for (int pb = 0; pb < NBQ; ++pb) {
+            const uint32_t sb = (uint32_t)((int64_t)(k0 + BR * pb) * g.ldb * 8);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) rb[pb][q] = ld16(rsB, offB[q >> 1] + 16 * (q & 1), sb);
         }
     };
     // split into re and im planes (the sums re + im are formed after the operand reads)
@@ -109,34 +118,38 @@ __global__ __launch_bounds__(512) void cgemm3m_kernel(GemmArgs g) {
             ai[o + AP] = ra[q].w;
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int ob = b_row * BP + 64 * h + 4 * b_q;
-            *reinterpret_cast<float4 *>(br + ob) = make_float4(rb[2 * h].x, rb[2 * h].z, rb[2 * h + 1].x, rb[2 * h + 1].z);
-            *reinterpret_cast<float4 *>(bi + ob) = make_float4(rb[2 * h].y, rb[2 * h].w, rb[2 * h + 1].y, rb[2 * h + 1].w);
-        }
+        for (int pb = 0; pb < NBQ; ++pb)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float4 *rr = rb[pb];
+                const int ob = (b_row + BR * pb) * BP + 64 * h + 4 * b_q;
+                *reinterpret_cast<float4 *>(br + ob) = make_float4(rr[2 * h].x, rr[2 * h].z, rr[2 * h + 1].x, rr[2 * h + 1].z);
+                *reinterpret_cast<float4 *>(bi + ob) = make_float4(rr[2 * h].y, rr[2 * h].w, rr[2 * h + 1].y, rr[2 * h + 1].w);
+            }
     };
 
-    // wave tile: STORE/RESID rows wm*64 + 32 i (i < 2), columns wn*32; LINE rows wm*32, columns
-    // wn*32 of X1 (LDS column wn*32) and X2 (LDS column 64 + wn*32)
-    const int wm = (MODE == GM_LINE) ? wave >> 1 : wave >> 2;
-    const int wn = (MODE == GM_LINE) ? wave & 1 : wave & 3;
+    // wave tile (2 x 2 waves): rows wm*64 + 32 i (i < 2); STORE/RESID columns wn*64 + 32 j (j < 2),
+    // LINE columns wn*32 of X1 (j = 0, LDS column wn*32) and X2 (j = 1, LDS column 64 + wn*32)
+    const int wm = wave >> 1, wn = wave & 1;
     int aoff[2], boff[2];
+    aoff[0] = wm * 64 + j32;
+    aoff[1] = wm * 64 + 32 + j32;
     if (MODE == GM_LINE) {
-        aoff[0] = aoff[1] = wm * 32 + j32;
         boff[0] = wn * 32 + j32;
         boff[1] = 64 + wn * 32 + j32;
     } else {
-        aoff[0] = wm * 64 + j32;
-        aoff[1] = wm * 64 + 32 + j32;
-        boff[0] = boff[1] = wn * 32 + j32;
+        boff[0] = wn * 64 + j32;
+        boff[1] = wn * 64 + 32 + j32;
     }
-    floatx16 acc[3][2];   // [T1, T2, T3][block]
+    floatx16 acc[3][2][2];   // [T1, T2, T3][row block][column block]
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[p][i][r] = 0.f;
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[p][i][j][r] = 0.f;
 
     const int nk = g.K / BK;
     load(0);
@@ -175,7 +188,9 @@ __global__ __launch_bounds__(512) void cgemm3m_kernel(GemmArgs g) {
             for (int p = 0; p < 3; ++p)
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
-                    acc[p][i] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[0][p][i], cur[1][p][i], acc[p][i], 0, 0, 0);
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[p][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[0][p][i], cur[1][p][j], acc[p][i][j], 0, 0, 0);
             if (kc + 2 < BK) {
                 sums(nxt);
 #pragma unroll
@@ -191,20 +206,25 @@ __global__ __launch_bounds__(512) void cgemm3m_kernel(GemmArgs g) {
     }
 
     // ---- epilogue: C = (T1 - T2) + i (T3 - T1 - T2) ----
-    __shared__ double red[8][5];
+    __shared__ double red[4][5];
     float2 *C = g.C + z * g.sC;
     const int64_t ldc = g.ldc;
+    auto cval = [&](int i, int j, int r) {
+        const float t1 = acc[0][i][j][r], t2 = acc[1][i][j][r], t3 = acc[2][i][j][r];
+        return make_float2(t1 - t2, t3 - t1 - t2);
+    };
     if (MODE == GM_STORE) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int col = n0 + wn * 32 + j32;
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = m0 + wm * 64 + 32 * i + acc_row(r, lane);
-                const float t1 = acc[0][i][r], t2 = acc[1][i][r], t3 = acc[2][i][r];
-                C[(int64_t)row * ldc + col] = make_float2(t1 - t2, t3 - t1 - t2);
+            for (int j = 0; j < 2; ++j) {
+                const int col = n0 + wn * 64 + 32 * j + j32;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = m0 + wm * 64 + 32 * i + acc_row(r, lane);
+                    C[(int64_t)row * ldc + col] = cval(i, j, r);
+                }
             }
-        }
         return;
     }
     const float2 *E = g.E + z * g.sE;
@@ -212,42 +232,46 @@ __global__ __launch_bounds__(512) void cgemm3m_kernel(GemmArgs g) {
     double sums[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (MODE == GM_RESID) {
 #pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = n0 + wn * 64 + 32 * j + j32;
+                float blk = 0.f;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = m0 + wm * 64 + 32 * i + acc_row(r, lane);
+                    const bool in = row < g.Me && col < g.Ne;   // U has the true (unpadded) shape
+                    const float2 e = in ? E[(int64_t)row * lde + col] : make_float2(0.f, 0.f);
+                    const float2 c = cval(i, j, r);
+                    const float2 v = make_float2(c.x - e.x, c.y - e.y);
+                    C[(int64_t)row * ldc + col] = v;
+                    blk = fmaf(v.x, v.x, fmaf(v.y, v.y, blk));
+                }
+                sums[0] += (double)blk;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+    } else {   // GM_LINE: column block 0 = a = D X1, block 1 = b = D X2 at the same (row, column)
+        float2 *C2 = g.C2 + z * g.sC;
+        const int col = n0 + wn * 32 + j32;
+#pragma unroll
         for (int i = 0; i < 2; ++i) {
-            const int col = n0 + wn * 32 + j32;
-            float blk = 0.f;
+            float blk[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = m0 + wm * 64 + 32 * i + acc_row(r, lane);
-                const bool in = row < g.Me && col < g.Ne;   // U has the true (unpadded) shape
-                const float2 e = in ? E[(int64_t)row * lde + col] : make_float2(0.f, 0.f);
-                const float t1 = acc[0][i][r], t2 = acc[1][i][r], t3 = acc[2][i][r];
-                const float2 v = make_float2(t1 - t2 - e.x, t3 - t1 - t2 - e.y);
-                C[(int64_t)row * ldc + col] = v;
-                blk = fmaf(v.x, v.x, fmaf(v.y, v.y, blk));
+                const float2 av = cval(i, 0, r), bv = cval(i, 1, r);
+                const float2 rv = E[(int64_t)row * lde + col];
+                C[(int64_t)row * ldc + col] = av;
+                C2[(int64_t)row * ldc + col] = bv;
+                blk[0] = fmaf(rv.x, av.x, fmaf(rv.y, av.y, blk[0]));
+                blk[1] = fmaf(av.x, av.x, fmaf(av.y, av.y, blk[1]));
+                blk[2] = fmaf(rv.x, bv.x, fmaf(rv.y, bv.y, blk[2]));
+                blk[3] = fmaf(av.x, bv.x, fmaf(av.y, bv.y, blk[3]));
+                blk[4] = fmaf(bv.x, bv.x, fmaf(bv.y, bv.y, blk[4]));
             }
-            sums[0] += (double)blk;
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    } else {   // GM_LINE: block 0 = a = D X1, block 1 = b = D X2 at the same (row, column)
-        float2 *C2 = g.C2 + z * g.sC;
-        const int col = n0 + wn * 32 + j32;
-        float blk[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = m0 + wm * 32 + acc_row(r, lane);
-            const float2 av = make_float2(acc[0][0][r] - acc[1][0][r], acc[2][0][r] - acc[0][0][r] - acc[1][0][r]);
-            const float2 bv = make_float2(acc[0][1][r] - acc[1][1][r], acc[2][1][r] - acc[0][1][r] - acc[1][1][r]);
-            const float2 rv = E[(int64_t)row * lde + col];
-            C[(int64_t)row * ldc + col] = av;
-            C2[(int64_t)row * ldc + col] = bv;
-            blk[0] = fmaf(rv.x, av.x, fmaf(rv.y, av.y, blk[0]));
-            blk[1] = fmaf(av.x, av.x, fmaf(av.y, av.y, blk[1]));
-            blk[2] = fmaf(rv.x, bv.x, fmaf(rv.y, bv.y, blk[2]));
-            blk[3] = fmaf(av.x, bv.x, fmaf(av.y, bv.y, blk[3]));
-            blk[4] = fmaf(bv.x, bv.x, fmaf(bv.y, bv.y, blk[4]));
+            for (int q = 0; q < 5; ++q) sums[q] += (double)blk[q];
         }
-#pragma unroll
-        for (int q = 0; q < 5; ++q) sums[q] = (double)blk[q];
     }
     constexpr int NS = (MODE == GM_RESID) ? 1 : 5;
 #pragma unroll
@@ -257,8 +281,7 @@ __global__ __launch_bounds__(512) void cgemm3m_kernel(GemmArgs g) {
     }
     __syncthreads();
     if (t < NS) {
-        const double v = (((red[0][t] + red[1][t]) + (red[2][t] + red[3][t])) +
-                          ((red[4][t] + red[5][t]) + (red[6][t] + red[7][t])));
+        const double v = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
         g.partials[z * g.sP + (int64_t)pid * NS + t] = v;
     }
 }
@@ -285,9 +308,9 @@ hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s
     a.bytesB = (uint32_t)bytesB;
     dim3 grid(a.tiles_m * a.tiles_n, batch);
     switch (mode) {
-        case GM_STORE: hipLaunchKernelGGL(cgemm3m_kernel<GM_STORE>, grid, dim3(512), 0, s, a); break;
-        case GM_RESID: hipLaunchKernelGGL(cgemm3m_kernel<GM_RESID>, grid, dim3(512), 0, s, a); break;
-        case GM_LINE:  hipLaunchKernelGGL(cgemm3m_kernel<GM_LINE>, grid, dim3(512), 0, s, a); break;
+        case GM_STORE: hipLaunchKernelGGL(cgemm3m_kernel<GM_STORE>, grid, dim3(256), 0, s, a); break;
+        case GM_RESID: hipLaunchKernelGGL(cgemm3m_kernel<GM_RESID>, grid, dim3(256), 0, s, a); break;
+        case GM_LINE:  hipLaunchKernelGGL(cgemm3m_kernel<GM_LINE>, grid, dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -399,6 +399,8 @@ def main():
     ap.add_argument("--error-table", action="store_true",
                     help="per-frequency error of FP32 and BF16x3 solves against the FP64 oracle (large workload)")
     ap.add_argument("--error-snrs", default="10,30", help="error table: SNRs in dB")
+    ap.add_argument("--streams", type=int, default=1,
+                    help="batched solve: sub-batches on their own streams (problem i in sub-batch i %% streams)")
     ap.add_argument("--resid-refresh", type=int, default=20,
                     help="error table: also an FP32 solve that recomputes r = D C(theta) - U every this many iterations")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -447,9 +449,9 @@ def main():
     dev = torch.device("cuda")
     perm = torch.from_numpy(tl.hilbert_order(geom.rec_ix, geom.rec_iy)).to(dev)
     ns, nr = geom.ns, geom.nr
-    opts = tl.make_opts(iters, precision=prec)
+    opts = tl.make_opts(iters, precision=prec, streams=args.streams)
     if admm:
-        aopts = tl.make_admm_opts(lams, args.admm_outer, args.admm_inner, precision=prec)
+        aopts = tl.make_admm_opts(lams, args.admm_outer, args.admm_inner, precision=prec, streams=args.streams)
         ws = torch.empty(tl.admm_workspace_bytes(plans, aopts), dtype=torch.uint8, device=dev)
     else:
         ws = torch.empty(tl.batched_workspace_bytes(plans, opts), dtype=torch.uint8, device=dev)
@@ -464,10 +466,10 @@ def main():
         Uh = [tl.permute_columns(U, perm) for U in Us]
         if admm:
             _, out_fh = tl.admm_batched(plans, Dh, Uh, ths, lams=lams, outer=args.admm_outer, inner=args.admm_inner,
-                                        precision=prec, workspace=ws)
+                                        precision=prec, workspace=ws, streams=args.streams)
         else:
             tl.solve_batched(plans, Dh, Uh, ths, iters, precision=prec, workspace=ws, out_thetas=out_th,
-                             out_fhist=out_fh)
+                             out_fhist=out_fh, streams=args.streams)
 
     for w in range(args.warmup):
         step()
@@ -492,6 +494,10 @@ def main():
         "gemm_adjoint": 8.0 * nr * ns * nr,
         "gemm_resid": 8.0 * ns * nr * nr,
     }
+    # with sub-batches on several streams a launch covers nfreq / streams problems (on average), and
+    # launches of different sub-batches overlap in time
+    nstreams = max(1, min(args.streams, nfreq))
+    probs_per_launch = nfreq / nstreams
     kernels = {}
     for k, ms in kt.ms.items():
         n = kt.launches[k]
@@ -500,7 +506,7 @@ def main():
         avg = ms / n * 1e-3
         entry = {"launches": n, "avg_ms": avg * 1e3}
         if k in per_prob:
-            fl = per_prob[k] * nfreq
+            fl = per_prob[k] * probs_per_launch
             entry["tflops"] = fl / avg / 1e12   # algorithmic (8mnk)
             entry["frac_f32_peak"] = fl / avg / PEAK["f32"]
             entry["executed_frac_" + peak_name + "_peak"] = exec_factor * fl / avg / PEAK[peak_name]
@@ -508,7 +514,7 @@ def main():
     dom = kernels["gemm_line"]
     achieved = dom["tflops"] * 1e12
     peak = PEAK[peak_name]
-    gemm_flops = sum(per_prob[k] * nfreq * kt.launches[k] for k in per_prob)
+    gemm_flops = sum(per_prob[k] * probs_per_launch * kt.launches[k] for k in per_prob)
     gemm_s = sum(kt.ms[k] for k in per_prob) * 1e-3
     line = {
         "metric": "TLR-MDD grad iters/s",
@@ -525,7 +531,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name if nfreq == len(wl.freqs) else f"{wl.name}[first {nfreq}]",
                    "nr": nr, "ns": ns, "frequencies": nfreq, "iters": iters,
-                   "resid_refresh": tl.RESID_REFRESH,
+                   "resid_refresh": tl.RESID_REFRESH, "streams": nstreams,
                    "optimizer": ("admm(lambda 10,1,0.1; %d x %d L-BFGS(m=5) per stage)" % (args.admm_outer,
                                                                                         args.admm_inner))
                    if admm else "lbfgs(m=5)",
@@ -536,8 +542,10 @@ def main():
                      "frac": achieved / peak,
                      "executed_tflops": exec_factor * achieved / 1e12,
                      "executed_frac": exec_factor * achieved / peak,
-                     "traffic": measured_traffic(nfreq, args.workload, args.precision),
-                     "algorithmic_bytes": 6 * 8.0 * ns * nr * nfreq},
+                     "traffic": measured_traffic(nfreq, args.workload, args.precision) if nstreams == 1 else None,
+                     "algorithmic_bytes": 6 * 8.0 * ns * nr * probs_per_launch,
+                     **({"note": "launches of the %d sub-batches overlap in time: a launch's duration includes "
+                                 "the sharing of the GPU" % nstreams} if nstreams > 1 else {})},
         "mfma_frac_all_gemms": gemm_flops / gemm_s / PEAK["f32"],
         "kernels": kernels,
         "objective": {"f0_mean": sum(f_first) / nfreq, "fT_mean": sum(f_final) / nfreq},

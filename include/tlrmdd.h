@@ -92,7 +92,13 @@ typedef struct {
     double  lambda;         /* Frobenius regulariser lambda ||theta||^2 (0 = none)  */
     int32_t resid_refresh;  /* recompute r = D C(theta) - U every this many iters (0 = never); the
                                tracked r accumulates FP32 rounding, 20 keeps long solves oracle-close */
-    int32_t reserved;
+    int32_t streams;        /* batched calls: 0 or 1 = all problems in one launch per phase on
+                               `stream`; 2..8 = problem i in sub-batch i % streams, each sub-batch
+                               on its own stream (the first on `stream`, the others on streams the
+                               library creates once per device at default priority, joined to
+                               `stream` with events), so the matrix-core products of one
+                               sub-batch overlap the HBM-bound passes of another. Results are
+                               bit-identical for every value; single-problem calls ignore it. */
 } tlrmdd_opts;
 
 /* Opaque plan: validated layout plus device-side tile tables. */
@@ -161,9 +167,9 @@ int tlrmdd_solve(tlrmdd_plan plan, const void *D, const void *U, void *theta_ino
 
 /* Batched solve of independent frequencies (the paper solves each frequency
  * independently, Theory section, eq. standard_solver). Arrays have `count`
- * entries; every problem uses the same opts. Work of all problems is fused
- * into shared launches per phase. workspace: sized by
- * tlrmdd_workspace_bytes_batched. */
+ * entries; every problem uses the same opts. Work of all problems (of each
+ * sub-batch when opts->streams > 1) is fused into shared launches per phase.
+ * workspace: sized by tlrmdd_workspace_bytes_batched with the same opts. */
 int tlrmdd_workspace_bytes_batched(int count, const tlrmdd_plan *plans,
                                    const tlrmdd_opts *opts, size_t *bytes);
 int tlrmdd_solve_batched(int count, const tlrmdd_plan *plans, const void *const *D,

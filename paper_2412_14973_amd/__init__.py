@@ -175,8 +175,9 @@ def benchmark_solve(D, U, lam, iters, precision=FP32, lbfgs_m=5, Z0=None):
 RESID_REFRESH = 20
 
 
-def make_opts(iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0, resid_refresh=RESID_REFRESH):
-    return _lib.c_opts(int(iters), int(optimizer), int(lbfgs_m), int(precision), float(lam), int(resid_refresh), 0)
+def make_opts(iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0, resid_refresh=RESID_REFRESH, streams=1):
+    return _lib.c_opts(int(iters), int(optimizer), int(lbfgs_m), int(precision), float(lam), int(resid_refresh),
+                       int(streams))
 
 
 def solve(plan, D, U, theta0, iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0, resid_refresh=RESID_REFRESH,
@@ -201,12 +202,13 @@ def batched_workspace_bytes(plans, opts):
 
 
 def solve_batched(plans, Ds, Us, thetas0, iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0,
-                  resid_refresh=RESID_REFRESH, workspace=None, out_thetas=None, out_fhist=None):
-    """Solve independent frequencies of equal nr, ns with fused launches per phase."""
+                  resid_refresh=RESID_REFRESH, workspace=None, out_thetas=None, out_fhist=None, streams=1):
+    """Solve independent frequencies of equal nr, ns with fused launches per phase (per sub-batch:
+    streams > 1 runs problem i in sub-batch i % streams on its own stream; same results)."""
     n = len(plans)
     for p, D, U, th in zip(plans, Ds, Us, thetas0):
         _check_problem(p, D, U, th)
-    opts = make_opts(iters, optimizer, lbfgs_m, precision, lam, resid_refresh)
+    opts = make_opts(iters, optimizer, lbfgs_m, precision, lam, resid_refresh, streams)
     thetas = out_thetas if out_thetas is not None else [t.clone() for t in thetas0]
     if out_thetas is not None:
         for dst, src in zip(thetas, thetas0):
@@ -224,10 +226,10 @@ def solve_batched(plans, Ds, Us, thetas0, iters, optimizer=LBFGS, lbfgs_m=5, pre
 
 
 def make_admm_opts(lams=(10.0, 1.0, 0.1), outer=5, inner=10, rho=1.0, optimizer=LBFGS, lbfgs_m=5,
-                   precision=FP32):
+                   precision=FP32, streams=1):
     """ADMM options; the returned struct keeps its lambda array alive."""
     lam_arr = (ctypes.c_double * len(lams))(*[float(v) for v in lams])
-    o = _lib.c_admm_opts(make_opts(inner, optimizer, lbfgs_m, precision), len(lams), int(outer),
+    o = _lib.c_admm_opts(make_opts(inner, optimizer, lbfgs_m, precision, streams=streams), len(lams), int(outer),
                          ctypes.cast(lam_arr, ctypes.POINTER(ctypes.c_double)), float(rho))
     o._keep = lam_arr
     return o
@@ -242,7 +244,7 @@ def admm_workspace_bytes(plans, aopts):
 
 
 def admm_batched(plans, Ds, Us, thetas0, lams=(10.0, 1.0, 0.1), outer=5, inner=10, rho=1.0, optimizer=LBFGS,
-                 lbfgs_m=5, precision=FP32, workspace=None):
+                 lbfgs_m=5, precision=FP32, workspace=None, streams=1):
     """Scaled ADMM with lambda continuation over independent frequencies of equal nr, ns.
 
     Returns (thetas, f_hists); f_hist[k] is the data misfit at the start (k = 0) and after
@@ -250,7 +252,7 @@ def admm_batched(plans, Ds, Us, thetas0, lams=(10.0, 1.0, 0.1), outer=5, inner=1
     n = len(plans)
     for p, D, U, th in zip(plans, Ds, Us, thetas0):
         _check_problem(p, D, U, th)
-    aopts = make_admm_opts(lams, outer, inner, rho, optimizer, lbfgs_m, precision)
+    aopts = make_admm_opts(lams, outer, inner, rho, optimizer, lbfgs_m, precision, streams)
     thetas = [t.clone() for t in thetas0]
     fh = [torch.empty(1 + len(lams) * outer, dtype=torch.float64, device=Ds[0].device) for _ in range(n)]
     ws = workspace if workspace is not None else torch.empty(admm_workspace_bytes(plans, aopts),

@@ -35,7 +35,7 @@ class c_layout(ctypes.Structure):
 class c_opts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("optimizer", ctypes.c_int32), ("lbfgs_m", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("lam", ctypes.c_double), ("resid_refresh", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("streams", ctypes.c_int32)]
 
 
 class c_admm_opts(ctypes.Structure):

@@ -389,6 +389,8 @@ Ws carve(char *base, int op, int nprob, int64_t ldk, int64_t lds, int64_t theta_
     return w;
 }
 
+constexpr int MAX_STREAMS = 8;   // sub-batches of a batched call (tlrmdd_opts.streams)
+
 int check_opts(const tlrmdd_opts *o) {
     if (!o) return fail(TLRMDD_INVALID_ARGUMENT, "opts is NULL");
     if (o->iters < 0) return fail(TLRMDD_INVALID_ARGUMENT, "iters must be >= 0");
@@ -400,7 +402,102 @@ int check_opts(const tlrmdd_opts *o) {
         return fail(TLRMDD_INVALID_ARGUMENT, "unknown precision");
     if (!(o->lambda >= 0.0)) return fail(TLRMDD_INVALID_ARGUMENT, "lambda must be >= 0");
     if (o->resid_refresh < 0) return fail(TLRMDD_INVALID_ARGUMENT, "resid_refresh must be >= 0");
+    if (o->streams < 0 || o->streams > MAX_STREAMS) return fail(TLRMDD_INVALID_ARGUMENT, "streams must be in [0, 8]");
     return TLRMDD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sub-batches on their own streams
+// ---------------------------------------------------------------------------
+
+// Extra streams (default priority, non-blocking) and join events, created once per device and kept
+// for the life of the process.
+struct StreamPool {
+    std::mutex mu;
+    std::vector<std::vector<hipStream_t>> streams;   // [device][k]
+    std::vector<std::vector<hipEvent_t>> events;     // [device][k]
+};
+StreamPool g_pool;
+
+int pool_get(int n, std::vector<hipStream_t> &st, std::vector<hipEvent_t> &ev) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_pool.mu);
+    if ((int)g_pool.streams.size() <= dev) {
+        g_pool.streams.resize(dev + 1);
+        g_pool.events.resize(dev + 1);
+    }
+    auto &S = g_pool.streams[dev];
+    auto &E = g_pool.events[dev];
+    while ((int)S.size() < n) {
+        hipStream_t x;
+        HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        S.push_back(x);
+    }
+    while ((int)E.size() < n + 1) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        E.push_back(e);
+    }
+    st.assign(S.begin(), S.begin() + n);
+    ev.assign(E.begin(), E.begin() + n + 1);
+    return TLRMDD_OK;
+}
+
+int stream_groups(const tlrmdd_opts *o, int count) { return std::max(1, std::min(o ? o->streams : 1, count)); }
+
+// problem indices of sub-batch g of G: g, g + G, g + 2G, ... (every sub-batch gets the same mix)
+std::vector<int> group_members(int g, int G, int count) {
+    std::vector<int> m;
+    for (int i = g; i < count; i += G) m.push_back(i);
+    return m;
+}
+
+template <typename T> std::vector<T> pick(const T *a, const std::vector<int> &idx) {
+    std::vector<T> r;
+    for (int i : idx) r.push_back(a[i]);
+    return r;
+}
+
+// Workspace of G sub-batches: their own workspaces back to back (256-byte aligned).
+int ws_bytes_grouped(int op, int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, size_t *bytes,
+                     std::vector<size_t> *parts = nullptr);
+
+// Runs impl(sub-batch arrays, workspace slice, bytes, stream) for every sub-batch: the first on
+// `stream`, the others on pool streams that wait for `stream` first and are waited for at the end.
+template <typename Impl>
+int run_grouped(int op, int count, const tlrmdd_plan *plans, const void *const *D, const void *const *U,
+                void *const *theta, const tlrmdd_opts *opts, double *const *fhist, void *workspace,
+                size_t ws_bytes, hipStream_t stream, Impl impl) {
+    const int G = stream_groups(opts, count);
+    std::vector<size_t> parts;
+    size_t need = 0;
+    int st = ws_bytes_grouped(op, count, plans, opts, &need, &parts);
+    if (st) return st;
+    if (!workspace || ws_bytes < need) return fail(TLRMDD_WORKSPACE, "workspace too small");
+    std::vector<hipStream_t> ps;
+    std::vector<hipEvent_t> ev;
+    if ((st = pool_get(G - 1, ps, ev))) return st;
+    HIP_TRY(hipEventRecord(ev[G - 1], stream));
+    for (int k = 0; k < G - 1; ++k) HIP_TRY(hipStreamWaitEvent(ps[k], ev[G - 1], 0));
+    char *base = static_cast<char *>(workspace);
+    int first_err = TLRMDD_OK;
+    for (int g = 0; g < G; ++g) {
+        const std::vector<int> m = group_members(g, G, count);
+        const std::vector<tlrmdd_plan> gp = pick(plans, m);
+        const std::vector<const void *> gd = pick(D, m), gu = pick(U, m);
+        const std::vector<void *> gt = pick(theta, m);
+        const std::vector<double *> gf = pick(fhist, m);
+        const int e = impl((int)m.size(), gp.data(), gd.data(), gu.data(), gt.data(), gf.data(), base, parts[g],
+                           g == 0 ? stream : ps[g - 1]);
+        if (e && !first_err) first_err = e;
+        base += align256(parts[g]);
+    }
+    for (int k = 0; k < G - 1; ++k) {
+        HIP_TRY(hipEventRecord(ev[k], ps[k]));
+        HIP_TRY(hipStreamWaitEvent(stream, ev[k], 0));
+    }
+    return first_err;
 }
 
 int check_precision(int precision) {
@@ -1082,20 +1179,39 @@ int ws_bytes_group(int op, int count, const tlrmdd_plan *plans, const tlrmdd_opt
                    count == 1 ? 0 : tables_bytes(T, count)).bytes;
     return TLRMDD_OK;
 }
+
+int ws_bytes_grouped(int op, int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, size_t *bytes,
+                     std::vector<size_t> *parts) {
+    if (count <= 0 || !plans || !bytes) return fail(TLRMDD_INVALID_ARGUMENT, "bad arguments");
+    int st = check_opts(opts);
+    if (st) return st;
+    const int G = stream_groups(opts, count);
+    size_t total = 0;
+    for (int g = 0; g < G; ++g) {
+        const std::vector<tlrmdd_plan> gp = pick(plans, group_members(g, G, count));
+        size_t b = 0;
+        if ((st = ws_bytes_group(op, (int)gp.size(), gp.data(), opts, &b))) return st;
+        if (parts) parts->push_back(b);
+        total += align256(b);
+    }
+    *bytes = total;
+    return TLRMDD_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 int tlrmdd_workspace_bytes_batched(int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, size_t *bytes) {
     g_last_error.clear();
-    return ws_bytes_group(2, count, plans, opts, bytes);
+    return ws_bytes_grouped(2, count, plans, opts, bytes);
 }
 
 int tlrmdd_workspace_bytes_admm(int count, const tlrmdd_plan *plans, const tlrmdd_admm_opts *opts, size_t *bytes) {
     g_last_error.clear();
     int st = check_admm(opts);
     if (st) return st;
-    return ws_bytes_group(3, count, plans, &opts->inner, bytes);
+    return ws_bytes_grouped(3, count, plans, &opts->inner, bytes);
 }
 
 int tlrmdd_admm(tlrmdd_plan plan, const void *D, const void *U, void *theta_inout, const tlrmdd_admm_opts *opts,
@@ -1115,7 +1231,15 @@ int tlrmdd_admm_batched(int count, const tlrmdd_plan *plans, const void *const *
     g_last_error.clear();
     if (count <= 0 || !plans || !D || !U || !theta_inout || !f_hist_dev)
         return fail(TLRMDD_INVALID_ARGUMENT, "bad arguments");
-    return admm_impl(count, plans, D, U, theta_inout, opts, f_hist_dev, workspace, ws_bytes, stream);
+    int st = check_admm(opts);
+    if (st) return st;
+    if (stream_groups(&opts->inner, count) == 1)
+        return admm_impl(count, plans, D, U, theta_inout, opts, f_hist_dev, workspace, ws_bytes, stream);
+    return run_grouped(3, count, plans, D, U, theta_inout, &opts->inner, f_hist_dev, workspace, ws_bytes, stream,
+                       [&](int n, const tlrmdd_plan *p, const void *const *d, const void *const *u, void *const *t,
+                           double *const *f, void *w, size_t b, hipStream_t s) {
+                           return admm_impl(n, p, d, u, t, opts, f, w, b, s);
+                       });
 }
 
 int tlrmdd_solve_batched(int count, const tlrmdd_plan *plans, const void *const *D, const void *const *U,
@@ -1124,7 +1248,15 @@ int tlrmdd_solve_batched(int count, const tlrmdd_plan *plans, const void *const 
     g_last_error.clear();
     if (count <= 0 || !plans || !D || !U || !theta_inout || !f_hist_dev)
         return fail(TLRMDD_INVALID_ARGUMENT, "bad arguments");
-    return solve_impl(count, plans, D, U, theta_inout, opts, f_hist_dev, workspace, ws_bytes, stream);
+    int st = check_opts(opts);
+    if (st) return st;
+    if (stream_groups(opts, count) == 1)
+        return solve_impl(count, plans, D, U, theta_inout, opts, f_hist_dev, workspace, ws_bytes, stream);
+    return run_grouped(2, count, plans, D, U, theta_inout, opts, f_hist_dev, workspace, ws_bytes, stream,
+                       [&](int n, const tlrmdd_plan *p, const void *const *d, const void *const *u, void *const *t,
+                           double *const *f, void *w, size_t b, hipStream_t s) {
+                           return solve_impl(n, p, d, u, t, opts, f, w, b, s);
+                       });
 }
 
 int tlrmdd_timing_begin(void) {

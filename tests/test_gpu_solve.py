@@ -161,3 +161,40 @@ def test_fp32_3m_batched_matches_single(tl):
     torch.cuda.synchronize()
     for (ts, fs), tb, fb in zip(singles, th_b, fh_b):
         assert torch.equal(ts, tb) and torch.equal(fs, fb)
+
+
+@pytest.mark.parametrize("precision_name,streams", [("FP32_3M", 2), ("FP32_3M", 4), ("FP32", 3), ("BF16X3", 2)])
+def test_batched_streams_match_one_stream(tl, precision_name, streams):
+    """Sub-batches on their own streams give the one-stream results bit for bit (problem i in
+    sub-batch i % streams; 5 problems so the sub-batches are uneven)."""
+    prec = getattr(tl, precision_name)
+    wl = synth.small()
+    devs = [to_device(from_workload(wl, i), tl, torch) for i in range(5)]
+    args = ([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs], [d[3] for d in devs])
+    th1, fh1 = tl.solve_batched(*args, iters=12, precision=prec)
+    thk, fhk = tl.solve_batched(*args, iters=12, precision=prec, streams=streams)
+    torch.cuda.synchronize()
+    for a, b, fa, fb in zip(th1, thk, fh1, fhk):
+        assert torch.equal(a, b) and torch.equal(fa, fb)
+
+
+def test_admm_batched_streams_match_one_stream(tl):
+    wl = synth.small()
+    devs = [to_device(from_workload(wl, i), tl, torch) for i in range(3)]
+    args = ([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs], [d[3] for d in devs])
+    kw = dict(lams=(1.0, 0.1), outer=2, inner=4, precision=tl.FP32_3M)
+    th1, fh1 = tl.admm_batched(*args, **kw)
+    th3, fh3 = tl.admm_batched(*args, streams=3, **kw)
+    torch.cuda.synchronize()
+    for a, b, fa, fb in zip(th1, th3, fh1, fh3):
+        assert torch.equal(a, b) and torch.equal(fa, fb)
+
+
+def test_batched_streams_invalid(tl):
+    wl = synth.small()
+    devs = [to_device(from_workload(wl, i), tl, torch) for i in range(2)]
+    for bad in (-1, 9):
+        with pytest.raises(tl.TLRMDDError) as e:
+            tl.solve_batched([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs],
+                             [d[3] for d in devs], iters=2, streams=bad)
+        assert e.value.status == 1

@@ -192,7 +192,9 @@ int tlrmdd_solve_batched(int count, const tlrmdd_plan *plans, const void *const 
  * theta_inout receives the X-variable. f_hist_dev: device, 1 + nstages *
  * outer doubles per problem: the data misfit 1/2||D C(theta) - U||^2 of the
  * tracked residual at the start and after every X-update. inner.lambda and
- * inner.resid_refresh are ignored / used as in tlrmdd_solve. */
+ * inner.resid_refresh are ignored / used as in tlrmdd_solve; inner.streams
+ * splits batched calls into sub-batches on their own streams as in
+ * tlrmdd_solve_batched (same results). */
 typedef struct {
     tlrmdd_opts inner;       /* X-update: iters per update, optimizer, lbfgs_m, precision */
     int32_t nstages;         /* number of lambda stages, >= 1                               */

@@ -98,7 +98,9 @@ def measured_traffic(nfreq, workload, precision):
 
 
 def cpu_baseline(wl, budget_s):
-    """Time the FP64 oracle (as it stands) on one frequency of the workload."""
+    """Time the FP64 oracle (as it stands) on a bounded sample of the workload: frequencies from the
+    low, middle and high part of the band (their layouts differ: tile 256 / 128 / 64), each for up to
+    the workload's iteration count, within about budget_s seconds in total."""
     import numpy as np
 
     import oracle as O
@@ -109,25 +111,31 @@ def cpu_baseline(wl, budget_s):
                       if i.get("user_api") == "blas") or None
     except Exception:
         threads = None
-    f_idx = len(wl.freqs) // 2
+    nf = len(wl.freqs)
     geom = wl.geometry()
-    prob = wl.problem(f_idx, geom)
-    lay = wl.layout(f_idx)
-    T = O.tiling(lay.tile_size, lay.rank_off, lay.rank_diag)
     perm = O.hilbert_order(geom.rec_ix, geom.rec_iy)
-    D = O.permute_columns(prob.D, perm)
-    U = O.permute_columns(prob.U, perm)
-    th = wl.theta0(f_idx, lay)
-    t0 = time.perf_counter()
-    O.solve(T, D, U, th, iters=2)
-    per = (time.perf_counter() - t0) / 2
-    n = int(max(2, min(wl.iters, budget_s / max(per, 1e-6))))
-    t0 = time.perf_counter()
-    O.solve(T, D, U, th, iters=n)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "grad-iters/s", "cores": threads or os.cpu_count(), "kind": "oracle",
-            "sample": f"1 of {len(wl.freqs)} frequencies (index {f_idx}, {wl.freqs[f_idx]:.2f} Hz), "
-                      f"{n} L-BFGS iterations, complex128 NumPy, {dt:.1f} s"}
+    its, secs, used = 0, 0.0, []
+    picks = (nf // 6, nf // 2, (5 * nf) // 6)
+    for f_idx in picks:
+        left = budget_s / len(picks)   # an equal share of the budget per frequency
+        prob = wl.problem(f_idx, geom)
+        lay = wl.layout(f_idx)
+        T = O.tiling(lay.tile_size, lay.rank_off, lay.rank_diag)
+        D = O.permute_columns(prob.D, perm)
+        U = O.permute_columns(prob.U, perm)
+        th = wl.theta0(f_idx, lay)
+        t0 = time.perf_counter()
+        O.solve(T, D, U, th, iters=2)
+        per = (time.perf_counter() - t0) / 2
+        n = int(max(2, min(wl.iters, left / max(per, 1e-6))))
+        t0 = time.perf_counter()
+        O.solve(T, D, U, th, iters=n)
+        secs += time.perf_counter() - t0
+        its += n
+        used.append(f"index {f_idx} ({wl.freqs[f_idx]:.2f} Hz, tile {int(np.max(lay.tile_size))}) x {n} iterations")
+    return {"value": its / secs, "unit": "grad-iters/s", "cores": threads or os.cpu_count(), "kind": "oracle",
+            "sample": f"{len(used)} of {nf} frequencies: " + "; ".join(used) +
+                      f"; L-BFGS, complex128 NumPy, {secs:.1f} s"}
 
 
 def serving(tl, torch, args):
@@ -387,7 +395,7 @@ def main():
     ap.add_argument("--hbm-budget-gib", type=float, default=96.0, help="serving: admission budget")
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--nfreq", type=int, default=None)
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp32", "bf16x3", "fp32_3m"], default="fp32_3m",
                     help="complex64 products: fp32_3m (three real FP32 products, default), fp32 (four), "

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
     const int j32 = lane & 31, half = lane >> 5;
 
     // ---- global -> register loaders (operands padded to whole tiles: no bounds checks) ----
-    // A: row t/4, complex k 8 (t%4) .. +7 (four float4); B: k row t/16, complex columns
+    // A: row t/2, complex k 8 (t%2) .. +7 (four float4); B: k row t/16, complex columns
     // 4 (t%16) .. +3 and 64 + 4 (t%16) .. +3 (two float4 each)
     constexpr int AQ = BK / 8;                     // threads per A row (8 complex k each)
     constexpr int BR = 256 / 16;                   // B rows per pass (16 threads per row)
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
         const float *ar = sm[buf], *ai = ar + A_PLANE;
         const float *br = ai + A_PLANE, *bi = br + B_PLANE;
         // operand fragments [A|B][re, im, re + im][block], double-buffered in registers: the
-        // reads of step kc + 2 are issued between the six MFMAs of step kc
+        // reads of step kc + 2 are issued between the twelve MFMAs of step kc
         float cur[2][3][2], nxt[2][3][2];
         auto frag = [&](int kc, float (&f)[2][3][2]) {
             const int ka = (kc + half) * AP, kb = (kc + half) * BP;

@@ -6,7 +6,8 @@
   central finite differences of the complex128 objective (step 1e-6); plus a
   2-iteration solve against the oracle.
 * nr = ns = 1024, 64 frequencies in one batched launch per phase (the bench
-  configuration), 3 iterations: four sampled frequencies against the oracle.
+  configuration), 3 iterations in the three-product form (the bench's default)
+  and the four-product form: four sampled frequencies against the oracle.
 """
 import numpy as np
 import pytest
@@ -76,10 +77,11 @@ def test_large_two_iterations(tl):
     assert rel_hist.max() <= 1e-5 and rel_t <= 1e-5
 
 
-def test_batched_bench_configuration_sampled(tl):
+@pytest.fixture(scope="module")
+def bench_inputs(tl):
+    """The bench configuration's 64 frequencies on the device; four of them also as oracle cases."""
     wl = synth.batched()
     nf = len(wl.freqs)
-    iters = 3
     dev = torch.device("cuda")
     geom = wl.geometry()
     perm = torch.from_numpy(tl.hilbert_order(geom.rec_ix, geom.rec_iy)).to(dev)
@@ -97,7 +99,15 @@ def test_batched_bench_configuration_sampled(tl):
         Us.append(tl.permute_columns(torch.from_numpy(Un.astype(np.complex64)).to(dev), perm))
         ths.append(torch.from_numpy(np.asarray(th).astype(np.complex64)).to(dev))
         plans.append(tl.Plan.from_layout(wl.layout(i), geom.ns))
-    thT, fh = tl.solve_batched(plans, Ds, Us, ths, iters)
+    return wl, plans, Ds, Us, ths, sample
+
+
+# the bench's default line runs the three-product form on one stream
+@pytest.mark.parametrize("precision_name", ["FP32_3M", "FP32"])
+def test_batched_bench_configuration_sampled(tl, bench_inputs, precision_name):
+    wl, plans, Ds, Us, ths, sample = bench_inputs
+    iters = 3
+    thT, fh = tl.solve_batched(plans, Ds, Us, ths, iters, precision=getattr(tl, precision_name))
     torch.cuda.synchronize()
     for i, case in sample.items():
         ref = O.solve(case.T, case.D, case.U, case.theta, iters=iters)
@@ -106,6 +116,6 @@ def test_batched_bench_configuration_sampled(tl):
         rel_f = abs(f_g - ref.f_hist[-1]) / ref.f_hist[-1]
         rel_t = np.linalg.norm(th_g - ref.theta) / np.linalg.norm(ref.theta)
         rel_h = np.max(np.abs(fh[i].cpu().numpy() - ref.f_hist) / ref.f_hist)
-        print(f"freq {i} (k={synth.batched_rank(float(wl.freqs[i]))}): rel_f {rel_f:.2e} "
+        print(f"{precision_name} freq {i} (k={synth.batched_rank(float(wl.freqs[i]))}): rel_f {rel_f:.2e} "
               f"rel_theta {rel_t:.2e} rel f_hist {rel_h:.2e}", flush=True)
         assert rel_f <= 1e-5 and rel_t <= 1e-5 and rel_h <= 1e-5

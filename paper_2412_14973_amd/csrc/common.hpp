@@ -50,7 +50,7 @@ struct GradItem {
 };
 constexpr int GR_ROWS = 64;   // rows (G_L/G_Q) or cols (G_R) per item
 constexpr int GR_KK = 64;     // rank entries per item (at most)
-constexpr int GR_CH = 32;     // contraction chunk
+constexpr int GR_CH = 4;      // contraction chunk (small: many workgroups per CU hide the W loads)
 constexpr int GZ_BR = 32, GZ_BC = 64;
 
 // ---- complex GEMM on MFMA ----

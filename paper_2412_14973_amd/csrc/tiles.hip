@@ -237,7 +237,9 @@ constexpr int GO_P = GR_ROWS + 1;      // output stage of G_R [GR_KK][GO_P] comp
 //   G_Q: rows of the tile, F[c][kk] = Q[c][kk]    (G_Q = (W + W^T) conj(Q))
 //   G_R: cols of the tile, F[r][kk] = L[r][kk]    (G_R^T = W'^T conj(L), contraction over tile rows)
 // with W' = W_ij + W_ji^T built in LDS chunk by chunk (both parts' loads issued together, each read
-// along its own rows). The contraction runs on the FP32 matrix cores in realified form (one
+// along its own rows). Chunks are only 4 contraction steps wide: that keeps a workgroup at 72 VGPRs
+// and 17 KB of LDS, and the seven workgroups per CU that this allows hide the W loads far better
+// than fewer, wider ones (32-wide chunks: 3 workgroups per CU, 1.3x the time). The contraction runs on the FP32 matrix cores in realified form (one
 // v_mfma_f32_32x32x2_f32 per complex contraction step: (Re, Im) of W'[m][c] as the two A entries,
 // the real 2 x 2 block of conj(F[c][n]) as B). Wave w owns rank entries 16 w .. 16 w + 15 and both
 // 32-row halves; waves past the item's rank only stage data. W' sits in LDS as re / im planes with
@@ -279,26 +281,26 @@ __device__ __forceinline__ void grad_block(const GradItem &it, const TileDesc &t
             const int e = t + 256 * u;
             int m, c;
             int64_t o;
-            if (!colside) { m = e >> 5; c = e & 31; o = (td.row0 + a0 + m) * ldw + td.col0 + c0 + c; }
-            else { c = e >> 6; m = e & 63; o = (td.row0 + c0 + c) * ldw + td.col0 + a0 + m; }
+            if (!colside) { m = e / GR_CH; c = e % GR_CH; o = (td.row0 + a0 + m) * ldw + td.col0 + c0 + c; }
+            else { c = e / GR_ROWS; m = e % GR_ROWS; o = (td.row0 + c0 + c) * ldw + td.col0 + a0 + m; }
             v0[u] = (m < nout && c < cn) ? W[o] : make_float2(0.f, 0.f);
-            if (!colside) { c = e >> 6; m = e & 63; o = (td.col0 + c0 + c) * ldw + td.row0 + a0 + m; }
-            else { m = e >> 5; c = e & 31; o = (td.col0 + a0 + m) * ldw + td.row0 + c0 + c; }
+            if (!colside) { c = e / GR_ROWS; m = e % GR_ROWS; o = (td.col0 + c0 + c) * ldw + td.row0 + a0 + m; }
+            else { m = e / GR_CH; c = e % GR_CH; o = (td.col0 + a0 + m) * ldw + td.row0 + c0 + c; }
             v1[u] = (m < nout && c < cn) ? W[o] : make_float2(0.f, 0.f);
         }
 #pragma unroll
         for (int u = 0; u < GR_ROWS * GR_CH / 256; ++u) {
             const int e = t + 256 * u;
             int m, c;
-            if (!colside) { m = e >> 5; c = e & 31; } else { c = e >> 6; m = e & 63; }
+            if (!colside) { m = e / GR_CH; c = e % GR_CH; } else { c = e / GR_ROWS; m = e % GR_ROWS; }
             sW[c * GW_P + m] = v0[u].x;
             sW[GW_PL + c * GW_P + m] = v0[u].y;
         }
         for (int e = t; e < GR_CH * GR_KK; e += 256) {
             int c, kk;
             int64_t o;
-            if (it.kind == G_L) { kk = e >> 5; c = e & 31; o = (int64_t)(b0 + kk) * td.dj + c0 + c; }
-            else { c = e >> 6; kk = e & 63; o = (int64_t)(c0 + c) * k + b0 + kk; }
+            if (it.kind == G_L) { kk = e / GR_CH; c = e % GR_CH; o = (int64_t)(b0 + kk) * td.dj + c0 + c; }
+            else { c = e / GR_KK; kk = e % GR_KK; o = (int64_t)(c0 + c) * k + b0 + kk; }
             sF[c * GF_P + kk] = (c < cn && kk < kn) ? F[o] : make_float2(0.f, 0.f);
         }
         __syncthreads();
@@ -306,7 +308,7 @@ __device__ __forceinline__ void grad_block(const GradItem &it, const TileDesc &t
         for (int u = 0; u < GR_ROWS * GR_CH / 256; ++u) {
             const int e = t + 256 * u;
             int m, c;
-            if (!colside) { c = e >> 6; m = e & 63; } else { m = e >> 5; c = e & 31; }
+            if (!colside) { c = e / GR_ROWS; m = e % GR_ROWS; } else { m = e / GR_CH; c = e % GR_CH; }
             sW[c * GW_P + m] += v1[u].x;
             sW[GW_PL + c * GW_P + m] += v1[u].y;
         }
@@ -340,18 +342,25 @@ __device__ __forceinline__ void grad_block(const GradItem &it, const TileDesc &t
                 }
         return;
     }
-    // grad R = L^H W' has the entries of G_R^T: stage [kk][m] and write rows of R's gradient
-    float *sO = smem;   // [GR_KK][GO_P] complex
-    if (active)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) sO[2 * (kk * GO_P + 32 * i + acc_row(r, lane)) + comp] = acc[i][r];
-    __syncthreads();
+    // grad R = L^H W' has the entries of G_R^T: stage [kk][m] (32 rank entries at a time: the
+    // waves that own them) and write rows of R's gradient
+    float *sO = smem;   // [GR_KK / 2][GO_P] complex
     const float2 *sO2 = reinterpret_cast<const float2 *>(sO);
-    for (int e = t; e < GR_KK * GR_ROWS; e += 256) {
-        const int q = e >> 6, m = e & 63;
-        if (q < kn && m < nout) g[td.offB + (int64_t)(b0 + q) * td.dj + a0 + m] = sO2[q * GO_P + m];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        if (active && (wave >> 1) == hh)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    sO[2 * ((kk - 32 * hh) * GO_P + 32 * i + acc_row(r, lane)) + comp] = acc[i][r];
+        __syncthreads();
+        for (int e = t; e < (GR_KK / 2) * GR_ROWS; e += 256) {
+            const int q = e >> 6, m = e & 63;
+            const int qq = 32 * hh + q;
+            if (qq < kn && m < nout) g[td.offB + (int64_t)(b0 + qq) * td.dj + a0 + m] = sO2[q * GO_P + m];
+        }
+        __syncthreads();
     }
 }
 
@@ -362,7 +371,7 @@ __global__ __launch_bounds__(256) void grad_kernel(const TileDesc *__restrict__ 
                                                    const float2 *__restrict__ theta_base,
                                                    float2 *__restrict__ g_base) {
     constexpr int SM_G = 2 * GW_PL + 2 * GR_CH * GF_P;
-    constexpr int SM_O = 2 * GR_KK * GO_P;
+    constexpr int SM_O = 2 * (GR_KK / 2) * GO_P;
     constexpr int SM_Z = 2 * GZ_BC * (GZ_BR + 1);
     constexpr int SM_F = SM_G > SM_O ? (SM_G > SM_Z ? SM_G : SM_Z) : (SM_O > SM_Z ? SM_O : SM_Z);
     __shared__ float smem[SM_F];

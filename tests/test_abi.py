@@ -2,6 +2,7 @@
 
   * the built library loads and exports every function include/tlrmdd.h declares;
   * hilbert_order (host C++) equals the oracle bit for bit on many grids;
+  * the ctypes mirrors of the header structs have its sizes and field offsets;
   * layout validation: tlrmdd_theta_size rejects every malformed layout and
     otherwise equals the oracle's packed size.
 """
@@ -114,3 +115,32 @@ def test_null_layout(lib):
     assert lib.tlrmdd_theta_size(None) < 0
     h = ctypes.c_void_p()
     assert lib.tlrmdd_plan_create(None, ctypes.byref(h)) == 1
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field offsets (a C++ program
+    compiled against include/tlrmdd.h prints them)."""
+    import shutil
+    import subprocess
+    if shutil.which("g++") is None or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("g++ or the HIP headers are missing")
+    structs = {"tlrmdd_layout": lib_mod.c_layout, "tlrmdd_opts": lib_mod.c_opts,
+               "tlrmdd_admm_opts": lib_mod.c_admm_opts}
+    cfield = {"lam": "lambda"}   # Python spelling -> C member
+    lines = ['#include <cstdio>', '#include <cstddef>', '#include "tlrmdd.h"', 'int main() {']
+    for cname, ct in structs.items():
+        lines.append(f'  std::printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in ct._fields_:
+            lines.append(f'  std::printf("{cname} {fname} %zu\\n", offsetof({cname}, {cfield.get(fname, fname)}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.cpp"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["g++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, ct in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(ct), cname
+        for fname, _ in ct._fields_:
+            assert got[(cname, fname)] == getattr(ct, fname).offset, (cname, fname)

@@ -55,13 +55,6 @@ def build_inputs(wl, torch, tl, nfreq):
     return geom, Ds, Us, ths, plans
 
 
-TRAFFIC_RECORDS = {   # precision -> (committed counter summary, kernel sources it was measured on)
-    "fp32": ("cgemm_line_traffic.json", ("cgemm.hip", "gemm_common.hpp")),
-    "fp32_3m": ("cgemm3m_line_traffic.json", ("cgemm3m.hip", "gemm_common.hpp")),
-    "bf16x3": ("cgemm_bf16_line_traffic.json", ("cgemm_bf16.hip", "gemm_common.hpp")),
-}
-
-
 def source_sha(files):
     import hashlib
     h = hashlib.sha256()
@@ -70,23 +63,36 @@ def source_sha(files):
     return h.hexdigest()
 
 
+ADJOINT_KERNEL = {"fp32": "cgemm_f32_kernel<GM_STORE>", "fp32_3m": "cgemm3m_kernel<GM_STORE, 0>",
+                  "bf16x3": "cgemm_bf16x3_kernel<GM_STORE>"}
+
+
 def precision_info(tl, name):
     """(library constant, dtype label, config label, line-search kernel, peak key, executed MFMA flops
     per algorithmic 8mnk flop)."""
     return {
         "fp32": (tl.FP32, "f32", "fp32-mfma", "cgemm_f32_kernel<GM_LINE>", "f32", 1.0),
-        "fp32_3m": (tl.FP32_3M, "f32", "fp32-3m-mfma", "cgemm3m_kernel<GM_LINE>", "f32", 0.75),
+        "fp32_3m": (tl.FP32_3M, "f32", "fp32-3m-mfma", "cgemm3m_kernel<GM_LINE, 0>", "f32", 0.75),
         "bf16x3": (tl.BF16X3, "bf16x3", "bf16x3-mfma", "cgemm_bf16x3_kernel<GM_LINE>", "bf16", 3.0),
     }[name]
 
 
-def measured_traffic(nfreq, workload, precision):
-    """HBM bytes per launch of the line-search GEMM from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE runs (copy-calibrated), or None when the kernel
-    source changed since the counters were taken or the workload differs."""
-    if precision not in TRAFFIC_RECORDS:
+TRAFFIC_RECORDS = {   # (precision, line-search form, product kind) -> (counter summary, kernel sources)
+    ("fp32", "dense", "gemm_line"): ("cgemm_line_traffic.json", ("cgemm.hip", "gemm_common.hpp")),
+    ("fp32_3m", "dense", "gemm_line"): ("cgemm3m_line_traffic.json", ("cgemm3m.hip", "gemm_common.hpp")),
+    ("fp32_3m", "tile", "gemm_adjoint"): ("cgemm3m_adjoint_traffic_tile.json", ("cgemm3m.hip", "gemm_common.hpp")),
+    ("bf16x3", "dense", "gemm_line"): ("cgemm_bf16_line_traffic.json", ("cgemm_bf16.hip", "gemm_common.hpp")),
+}
+
+
+def measured_traffic(nfreq, workload, precision, mode, kind):
+    """HBM bytes per launch (average over the launches of that product kind) from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs (copy-calibrated), or None when the kernel source changed
+    since the counters were taken or the configuration differs."""
+    key = (precision, mode, kind)
+    if key not in TRAFFIC_RECORDS:
         return None
-    name, files = TRAFFIC_RECORDS[precision]
+    name, files = TRAFFIC_RECORDS[key]
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", name)))
         sha = source_sha(files)
@@ -407,6 +413,8 @@ def main():
     ap.add_argument("--error-table", action="store_true",
                     help="per-frequency error of FP32 and BF16x3 solves against the FP64 oracle (large workload)")
     ap.add_argument("--error-snrs", default="10,30", help="error table: SNRs in dB")
+    ap.add_argument("--line-products", choices=["dense", "tile"], default="dense",
+                    help="line search products from the assembled X1, X2, or in tile form where cheaper")
     ap.add_argument("--streams", type=int, default=1,
                     help="batched solve: sub-batches on their own streams (problem i in sub-batch i %% streams)")
     ap.add_argument("--resid-refresh", type=int, default=20,
@@ -446,6 +454,7 @@ def main():
         print(json.dumps(tlr_product(tl, torch, args)), flush=True)
         return
     prec, dtype, prec_name, line_kernel, peak_name, exec_factor = precision_info(tl, args.precision)
+    adjoint_kernel = ADJOINT_KERNEL[args.precision]
     wl = synth.batched() if args.workload == "batched" else synth.large()
     nfreq = args.nfreq or (len(wl.freqs) if args.workload == "batched" else 4)
     iters = args.iters or wl.iters
@@ -457,9 +466,11 @@ def main():
     dev = torch.device("cuda")
     perm = torch.from_numpy(tl.hilbert_order(geom.rec_ix, geom.rec_iy)).to(dev)
     ns, nr = geom.ns, geom.nr
-    opts = tl.make_opts(iters, precision=prec, streams=args.streams)
+    line_products = tl.LINE_TILE if args.line_products == "tile" else tl.LINE_DENSE
+    opts = tl.make_opts(iters, precision=prec, streams=args.streams, line_products=line_products)
     if admm:
-        aopts = tl.make_admm_opts(lams, args.admm_outer, args.admm_inner, precision=prec, streams=args.streams)
+        aopts = tl.make_admm_opts(lams, args.admm_outer, args.admm_inner, precision=prec, streams=args.streams,
+                                  line_products=line_products)
         ws = torch.empty(tl.admm_workspace_bytes(plans, aopts), dtype=torch.uint8, device=dev)
     else:
         ws = torch.empty(tl.batched_workspace_bytes(plans, opts), dtype=torch.uint8, device=dev)
@@ -474,10 +485,10 @@ def main():
         Uh = [tl.permute_columns(U, perm) for U in Us]
         if admm:
             _, out_fh = tl.admm_batched(plans, Dh, Uh, ths, lams=lams, outer=args.admm_outer, inner=args.admm_inner,
-                                        precision=prec, workspace=ws, streams=args.streams)
+                                        precision=prec, workspace=ws, streams=args.streams, line_products=line_products)
         else:
             tl.solve_batched(plans, Dh, Uh, ths, iters, precision=prec, workspace=ws, out_thetas=out_th,
-                             out_fhist=out_fh, streams=args.streams)
+                             out_fhist=out_fh, streams=args.streams, line_products=line_products)
 
     for w in range(args.warmup):
         step()
@@ -496,34 +507,54 @@ def main():
     f_first = [float(f[0].item()) for f in out_fh]
     value = nfreq * iters * args.steps / elapsed
 
-    # algorithmic flops per launch (complex products counted as 8 m n k)
-    per_prob = {
-        "gemm_line": 2 * 8.0 * ns * nr * nr,
-        "gemm_adjoint": 8.0 * nr * ns * nr,
-        "gemm_resid": 8.0 * ns * nr * nr,
-    }
-    # with sub-batches on several streams a launch covers nfreq / streams problems (on average), and
-    # launches of different sub-batches overlap in time
+    # Algorithmic flops (complex products counted as 8 m n k) of each product kind over the timed
+    # region, from the problems each kind covers: the adjoint every problem and iteration, the
+    # dense line-search product the problems whose line search is dense, the tile-form stages the
+    # others (their padded flops: 3 x 8 ns nr (nt 2 kpad) per problem), the residual product
+    # every problem at each recompute (every sub-batch recomputes at the same iterations).
+    forms = [tl.line_form(p, prec, line_products) for p in plans]
+    n_tile = sum(1 for f in forms if f[0])
+    n_dense = nfreq - n_tile
     nstreams = max(1, min(args.streams, nfreq))
-    probs_per_launch = nfreq / nstreams
+    if line_products == tl.LINE_TILE and prec == tl.FP32_3M:
+        classes = {(int(p.tile_size[0]), k) for p, (t, k) in zip(plans, forms) if t}
+        n_groups = (1 if n_dense else 0) + len(classes)
+    else:
+        n_groups = nstreams
+    steps_iters = args.steps * iters
+    tile_flops = sum(24.0 * ns * nr * (nr // int(p.tile_size[0])) * 2 * k for p, (t, k) in zip(plans, forms) if t)
+    total_flops = {
+        "gemm_adjoint": 8.0 * nr * ns * nr * nfreq * steps_iters,
+        "gemm_line": 16.0 * ns * nr * nr * n_dense * steps_iters,
+        "line_tile": tile_flops * steps_iters,
+        "gemm_resid": 8.0 * ns * nr * nr * nfreq * kt.launches["gemm_resid"] / max(1, n_groups),
+    }
+    # algorithmic bytes per problem: operands read once, outputs written once
+    bytes_per_prob = {"gemm_adjoint": 8.0 * (2 * nr * ns + nr * nr), "gemm_line": 6 * 8.0 * ns * nr}
     kernels = {}
     for k, ms in kt.ms.items():
         n = kt.launches[k]
         if n == 0:
             continue
-        avg = ms / n * 1e-3
-        entry = {"launches": n, "avg_ms": avg * 1e3}
-        if k in per_prob:
-            fl = per_prob[k] * probs_per_launch
-            entry["tflops"] = fl / avg / 1e12   # algorithmic (8mnk)
-            entry["frac_f32_peak"] = fl / avg / PEAK["f32"]
-            entry["executed_frac_" + peak_name + "_peak"] = exec_factor * fl / avg / PEAK[peak_name]
+        entry = {"launches": n, "avg_ms": ms / n}
+        if k in total_flops and total_flops[k] > 0:
+            rate = total_flops[k] / (ms * 1e-3)   # = per-launch flops / average launch duration
+            entry["tflops"] = rate / 1e12
+            entry["frac_f32_peak"] = rate / PEAK["f32"]
+            entry["executed_frac_" + peak_name + "_peak"] = exec_factor * rate / PEAK[peak_name]
         kernels[k] = entry
-    dom = kernels["gemm_line"]
+    # the roofline kernel: the product kind with the most time
+    gemm_kinds = [k for k in ("gemm_line", "gemm_adjoint") if kt.launches[k] > 0]
+    dom_kind = max(gemm_kinds, key=lambda k: kt.ms[k])
+    dom = kernels[dom_kind]
     achieved = dom["tflops"] * 1e12
     peak = PEAK[peak_name]
-    gemm_flops = sum(per_prob[k] * probs_per_launch * kt.launches[k] for k in per_prob)
-    gemm_s = sum(kt.ms[k] for k in per_prob) * 1e-3
+    dom_probs = (n_dense if dom_kind == "gemm_line" else nfreq) * steps_iters / kt.launches[dom_kind]
+    dom_name = (line_kernel + " ([a|b] = D [X1|X2])" if dom_kind == "gemm_line"
+                else adjoint_kernel + " (W = D^H r)")
+    gemm_flops = sum(total_flops[k] for k in total_flops)
+    gemm_s = sum(kt.ms[k] for k in total_flops) * 1e-3
+    mode = "tile" if n_tile else "dense"
     line = {
         "metric": "TLR-MDD grad iters/s",
         "value": value,
@@ -540,18 +571,21 @@ def main():
         "config": {"workload": wl.name if nfreq == len(wl.freqs) else f"{wl.name}[first {nfreq}]",
                    "nr": nr, "ns": ns, "frequencies": nfreq, "iters": iters,
                    "resid_refresh": tl.RESID_REFRESH, "streams": nstreams,
+                   "line_products": f"{args.line_products} ({n_tile} of {nfreq} frequencies in tile form)",
                    "optimizer": ("admm(lambda 10,1,0.1; %d x %d L-BFGS(m=5) per stage)" % (args.admm_outer,
                                                                                         args.admm_inner))
                    if admm else "lbfgs(m=5)",
                    "precision": prec_name},
         "roofline": {"bound": "mfma",
-                     "kernel": line_kernel + " ([a|b] = D [X1|X2])",
+                     "kernel": dom_name,
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "executed_tflops": exec_factor * achieved / 1e12,
                      "executed_frac": exec_factor * achieved / peak,
-                     "traffic": measured_traffic(nfreq, args.workload, args.precision) if nstreams == 1 else None,
-                     "algorithmic_bytes": 6 * 8.0 * ns * nr * probs_per_launch,
+                     "traffic": (measured_traffic(nfreq, args.workload, args.precision, mode, dom_kind)
+                                 if nstreams == 1 else None),
+                     "algorithmic_bytes": bytes_per_prob[dom_kind] * dom_probs,
+                     "problems_per_launch": dom_probs,
                      **({"note": "launches of the %d sub-batches overlap in time: a launch's duration includes "
                                  "the sharing of the GPU" % nstreams} if nstreams > 1 else {})},
         "mfma_frac_all_gemms": gemm_flops / gemm_s / PEAK["f32"],

@@ -99,7 +99,15 @@ typedef struct {
                                `stream` with events), so the matrix-core products of one
                                sub-batch overlap the HBM-bound passes of another. Results are
                                bit-identical for every value; single-problem calls ignore it. */
+    int32_t line_products;  /* TLRMDD_LINE_DENSE (0): the line search's [a | b] = D [X1 | X2] from
+                               the assembled X1, X2; TLRMDD_LINE_TILE (1): in tile form wherever that
+                               needs fewer flops (see tlrmdd_line_form); batched calls then run the
+                               problems in sub-batches of equal form */
+    int32_t reserved;       /* 0 */
 } tlrmdd_opts;
+
+#define TLRMDD_LINE_DENSE 0
+#define TLRMDD_LINE_TILE  1
 
 /* Opaque plan: validated layout plus device-side tile tables. */
 typedef struct tlrmdd_plan_s *tlrmdd_plan;
@@ -164,6 +172,18 @@ int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *thet
 int tlrmdd_solve(tlrmdd_plan plan, const void *D, const void *U, void *theta_inout,
                  const tlrmdd_opts *opts, double *f_hist_dev,
                  void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Form of the exact line search's products for this plan under opts
+ * (tlrmdd_solve and the batched / ADMM calls): *tile_form = 1 when
+ * opts->line_products is TLRMDD_LINE_TILE, the precision is TLRMDD_FP32_3M
+ * and the layout qualifies - all tiles of one size d (a multiple of 128),
+ * nr a multiple of 128, Q Q^T diagonal tiles - with 3 kpad / d <= 0.6, where
+ * kpad is the largest rank rounded up so that a stage-1 row of nt blocks of
+ * 2 kpad columns is a whole number of 128-column tiles (the tile form's share
+ * of the dense products' flops; conclusions of the paper: the TLR product as
+ * the way to cut the cost of the dense products). *kpad (may be NULL) gets
+ * the padded rank, 0 for the dense form. */
+int tlrmdd_line_form(tlrmdd_plan plan, const tlrmdd_opts *opts, int *tile_form, int *kpad);
 
 /* Batched solve of independent frequencies (the paper solves each frequency
  * independently, Theory section, eq. standard_solver). Arrays have `count`
@@ -305,7 +325,9 @@ int tlrmdd_permute_columns(const void *in, const int64_t *perm, void *out,
 #define TLRMDD_K_ASSEMBLE      3  /* X = C(theta)                              */
 #define TLRMDD_K_ASSEMBLE_DIR  4  /* X1, X2 of the line search                 */
 #define TLRMDD_K_GRAD          5  /* per-tile gradient contractions            */
-#define TLRMDD_K_NKINDS        6
+#define TLRMDD_K_LINE_PACK     6  /* tile-form line search: factor packing, gather */
+#define TLRMDD_K_LINE_TILE     7  /* tile-form line search: both product stages */
+#define TLRMDD_K_NKINDS        8
 int tlrmdd_timing_begin(void);
 int tlrmdd_timing_end(double *ms, int64_t *launches);
 

@@ -175,16 +175,29 @@ def benchmark_solve(D, U, lam, iters, precision=FP32, lbfgs_m=5, Z0=None):
 RESID_REFRESH = 20
 
 
-def make_opts(iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0, resid_refresh=RESID_REFRESH, streams=1):
+LINE_DENSE, LINE_TILE = 0, 1   # line-search products from the assembled X1, X2 / in tile form where cheaper
+
+
+def make_opts(iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0, resid_refresh=RESID_REFRESH, streams=1,
+              line_products=LINE_DENSE):
     return _lib.c_opts(int(iters), int(optimizer), int(lbfgs_m), int(precision), float(lam), int(resid_refresh),
-                       int(streams))
+                       int(streams), int(line_products), 0)
+
+
+def line_form(plan, precision=FP32_3M, line_products=LINE_TILE):
+    """(tile_form, kpad): whether the line search of this plan runs in tile form under these options."""
+    tf, kp = ctypes.c_int(), ctypes.c_int()
+    opts = make_opts(1, precision=precision, line_products=line_products)
+    _lib.check(_lib.load().tlrmdd_line_form(plan.handle, ctypes.byref(opts), ctypes.byref(tf), ctypes.byref(kp)),
+               "tlrmdd_line_form")
+    return bool(tf.value), int(kp.value)
 
 
 def solve(plan, D, U, theta0, iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0, resid_refresh=RESID_REFRESH,
-          workspace=None):
+          workspace=None, line_products=LINE_DENSE):
     """Fixed-count solve from theta0; returns (theta_T, f_hist) with f_hist[t] (FP64, device)."""
     _check_problem(plan, D, U, theta0)
-    opts = make_opts(iters, optimizer, lbfgs_m, precision, lam, resid_refresh)
+    opts = make_opts(iters, optimizer, lbfgs_m, precision, lam, resid_refresh, line_products=line_products)
     theta = theta0.clone()
     fh = torch.empty(iters + 1, dtype=torch.float64, device=D.device)
     ws = workspace if workspace is not None else plan.workspace(_lib.OP_SOLVE, opts, device=D.device)
@@ -202,13 +215,15 @@ def batched_workspace_bytes(plans, opts):
 
 
 def solve_batched(plans, Ds, Us, thetas0, iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0,
-                  resid_refresh=RESID_REFRESH, workspace=None, out_thetas=None, out_fhist=None, streams=1):
+                  resid_refresh=RESID_REFRESH, workspace=None, out_thetas=None, out_fhist=None, streams=1,
+                  line_products=LINE_DENSE):
     """Solve independent frequencies of equal nr, ns with fused launches per phase (per sub-batch:
-    streams > 1 runs problem i in sub-batch i % streams on its own stream; same results)."""
+    streams > 1 runs problem i in sub-batch i % streams on its own stream; same results;
+    line_products=LINE_TILE groups the problems by line-search form)."""
     n = len(plans)
     for p, D, U, th in zip(plans, Ds, Us, thetas0):
         _check_problem(p, D, U, th)
-    opts = make_opts(iters, optimizer, lbfgs_m, precision, lam, resid_refresh, streams)
+    opts = make_opts(iters, optimizer, lbfgs_m, precision, lam, resid_refresh, streams, line_products)
     thetas = out_thetas if out_thetas is not None else [t.clone() for t in thetas0]
     if out_thetas is not None:
         for dst, src in zip(thetas, thetas0):
@@ -226,10 +241,11 @@ def solve_batched(plans, Ds, Us, thetas0, iters, optimizer=LBFGS, lbfgs_m=5, pre
 
 
 def make_admm_opts(lams=(10.0, 1.0, 0.1), outer=5, inner=10, rho=1.0, optimizer=LBFGS, lbfgs_m=5,
-                   precision=FP32, streams=1):
+                   precision=FP32, streams=1, line_products=LINE_DENSE):
     """ADMM options; the returned struct keeps its lambda array alive."""
     lam_arr = (ctypes.c_double * len(lams))(*[float(v) for v in lams])
-    o = _lib.c_admm_opts(make_opts(inner, optimizer, lbfgs_m, precision, streams=streams), len(lams), int(outer),
+    o = _lib.c_admm_opts(make_opts(inner, optimizer, lbfgs_m, precision, streams=streams, line_products=line_products),
+                         len(lams), int(outer),
                          ctypes.cast(lam_arr, ctypes.POINTER(ctypes.c_double)), float(rho))
     o._keep = lam_arr
     return o
@@ -244,7 +260,7 @@ def admm_workspace_bytes(plans, aopts):
 
 
 def admm_batched(plans, Ds, Us, thetas0, lams=(10.0, 1.0, 0.1), outer=5, inner=10, rho=1.0, optimizer=LBFGS,
-                 lbfgs_m=5, precision=FP32, workspace=None, streams=1):
+                 lbfgs_m=5, precision=FP32, workspace=None, streams=1, line_products=LINE_DENSE):
     """Scaled ADMM with lambda continuation over independent frequencies of equal nr, ns.
 
     Returns (thetas, f_hists); f_hist[k] is the data misfit at the start (k = 0) and after
@@ -252,7 +268,7 @@ def admm_batched(plans, Ds, Us, thetas0, lams=(10.0, 1.0, 0.1), outer=5, inner=1
     n = len(plans)
     for p, D, U, th in zip(plans, Ds, Us, thetas0):
         _check_problem(p, D, U, th)
-    aopts = make_admm_opts(lams, outer, inner, rho, optimizer, lbfgs_m, precision, streams)
+    aopts = make_admm_opts(lams, outer, inner, rho, optimizer, lbfgs_m, precision, streams, line_products)
     thetas = [t.clone() for t in thetas0]
     fh = [torch.empty(1 + len(lams) * outer, dtype=torch.float64, device=Ds[0].device) for _ in range(n)]
     ws = workspace if workspace is not None else torch.empty(admm_workspace_bytes(plans, aopts),
@@ -266,10 +282,10 @@ def admm_batched(plans, Ds, Us, thetas0, lams=(10.0, 1.0, 0.1), outer=5, inner=1
 
 
 def admm(plan, D, U, theta0, lams=(10.0, 1.0, 0.1), outer=5, inner=10, rho=1.0, optimizer=LBFGS, lbfgs_m=5,
-         precision=FP32, workspace=None):
+         precision=FP32, workspace=None, line_products=LINE_DENSE):
     """Scaled ADMM with lambda continuation on one frequency; returns (theta, f_hist)."""
     _check_problem(plan, D, U, theta0)
-    aopts = make_admm_opts(lams, outer, inner, rho, optimizer, lbfgs_m, precision)
+    aopts = make_admm_opts(lams, outer, inner, rho, optimizer, lbfgs_m, precision, line_products=line_products)
     theta = theta0.clone()
     fh = torch.empty(1 + len(lams) * outer, dtype=torch.float64, device=D.device)
     ws = workspace if workspace is not None else torch.empty(admm_workspace_bytes([plan], aopts),

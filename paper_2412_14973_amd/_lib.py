@@ -35,7 +35,7 @@ class c_layout(ctypes.Structure):
 class c_opts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("optimizer", ctypes.c_int32), ("lbfgs_m", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("lam", ctypes.c_double), ("resid_refresh", ctypes.c_int32),
-                ("streams", ctypes.c_int32)]
+                ("streams", ctypes.c_int32), ("line_products", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class c_admm_opts(ctypes.Structure):
@@ -59,6 +59,8 @@ _SIGS = {
                                                              ctypes.c_void_p]),
     "tlrmdd_solve": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.POINTER(c_opts), ctypes.c_void_p,
                                                               ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "tlrmdd_line_form": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_opts), ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int)]),
     "tlrmdd_workspace_bytes_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
                                                       ctypes.POINTER(c_opts), ctypes.POINTER(ctypes.c_size_t)]),
     "tlrmdd_solve_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
@@ -95,8 +97,9 @@ _SIGS = {
     "tlrmdd_timing_begin": (ctypes.c_int, []),
     "tlrmdd_timing_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
 }
-K_GEMM_RESID, K_GEMM_ADJOINT, K_GEMM_LINE, K_ASSEMBLE, K_ASSEMBLE_DIR, K_GRAD, K_NKINDS = range(7)
-KIND_NAMES = ("gemm_resid", "gemm_adjoint", "gemm_line", "assemble", "assemble_dir", "grad")
+(K_GEMM_RESID, K_GEMM_ADJOINT, K_GEMM_LINE, K_ASSEMBLE, K_ASSEMBLE_DIR, K_GRAD, K_LINE_PACK, K_LINE_TILE,
+ K_NKINDS) = range(9)
+KIND_NAMES = ("gemm_resid", "gemm_adjoint", "gemm_line", "assemble", "assemble_dir", "grad", "line_pack", "line_tile")
 
 EXPORTS = tuple(_SIGS)
 

@@ -389,6 +389,167 @@ Ws carve(char *base, int op, int nprob, int64_t ldk, int64_t lds, int64_t theta_
     return w;
 }
 
+// ---------------------------------------------------------------------------
+// tile-form line search: [a | b] = D [X1 | X2] from the factors of theta and p, without X1, X2
+// ---------------------------------------------------------------------------
+// Every tile pair of X1 = C1(theta; p) and X2 = C2(p) is a product of packed factor blocks
+//   X1_ij = A_p B_th + A_th B_p,  X2_ij = A_p B_p
+// (i > j: A = L, B = R; i < j: A = R_ji^T, B = L_ji^T; i = j: A = Q, B = Q^T; the p-blocks are the
+// same factors of the direction p). Stage 1 forms P_i = D_:,i [A_p(i0) A_th(i0) | A_p(i1) A_th(i1) | ...]
+// for every tile row, a gather regroups the blocks by tile column, and stage 2 forms
+//   a_:,j = sum_i P_ij [B_th; B_p],   b_:,j = sum_i P_ij [B_p; 0]
+// in one line-search product with the five line sums. Ranks are padded to kpad with zero columns.
+// Flops: 3 kpad / d of the dense pair (stage 1 and the two halves of stage 2, each kpad / d).
+constexpr double LINE_TILE_MAX_COST = 0.6;   // tile form where its flops are at most this share
+
+struct LineClass {
+    int d = 0, nt = 0, kpad = 0;
+    bool operator==(const LineClass &o) const { return d == o.d && nt == o.nt && kpad == o.kpad; }
+};
+
+// Tile form is available when all tiles have one size d (a multiple of 128), nr needs no padding,
+// the diagonal tiles are Q Q^T and the padded rank keeps the flops under LINE_TILE_MAX_COST.
+bool line_class(const HostLayout &H, LineClass &lc) {
+    if (H.nr % GEMM_PAD) return false;
+    const int d = H.d[0];
+    for (int i = 0; i < H.N; ++i)
+        if (H.d[i] != d) return false;
+    if (d % GEMM_BN) return false;
+    int kmax = 1;
+    for (const TileDesc &td : H.tiles) {
+        if (td.kind == TILE_DENSE) return false;
+        kmax = std::max(kmax, td.k);
+    }
+    const int nt = H.N;
+    // stage-1 rows hold nt blocks of 2 kpad columns, a whole number of 128-column GEMM tiles:
+    // nt * 2 * kpad divisible by 128 <=> kpad divisible by 64 / gcd(nt, 64)
+    int gcd = nt, b = 64;
+    while (b) {
+        const int r = gcd % b;
+        gcd = b;
+        b = r;
+    }
+    const int q = 64 / gcd;
+    const int kpad = (int)round_up(kmax, q);
+    if (3.0 * kpad > LINE_TILE_MAX_COST * d) return false;
+    lc = LineClass{d, nt, kpad};
+    return true;
+}
+
+bool run_line_class(int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, LineClass &lc);
+
+// Device state of the tile-form line search of one run (all problems of one class).
+struct LineTile {
+    bool on = false;
+    LineClass lc;
+    int64_t NA = 0;                  // columns of a stage-1 row block: nt * 2 kpad (= rows of a stage-2 B)
+    float2 *PA = nullptr, *PB = nullptr, *PB2 = nullptr, *P = nullptr, *Pcol = nullptr;
+    PackItem *pack = nullptr;
+    GatherItem *gather = nullptr;
+    int npack = 0, ngather = 0;
+    size_t bytes = 0, zero_bytes = 0;   // zero_bytes: PA .. PB2 (their padding must read as zero)
+};
+
+// Workspace region of the tile-form line search for `nprob` problems of class lc (laid out at base).
+LineTile line_tile_carve(char *base, int nprob, const LineClass &lc, int64_t lds, int npack, int ngather) {
+    LineTile L;
+    L.on = true;
+    L.lc = lc;
+    L.NA = (int64_t)lc.nt * 2 * lc.kpad;
+    size_t o = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *q = base ? base + o : nullptr;
+        o += align256(bytes);
+        return q;
+    };
+    const size_t c8 = sizeof(float2);
+    const int64_t nrr = (int64_t)lc.nt * lc.d;
+    // one block: PA (per (p, i): d x NA), PB and PB2 (per (p, j): NA x d); the packing items address
+    // all three from PA (line_tile_tables)
+    const int64_t blk = (int64_t)nprob * nrr * L.NA;
+    L.PA = (float2 *)take((size_t)3 * blk * c8);
+    L.PB = L.PA ? L.PA + blk : nullptr;
+    L.PB2 = L.PA ? L.PA + 2 * blk : nullptr;
+    L.zero_bytes = o;
+    L.P = (float2 *)take((size_t)nprob * lc.nt * lds * L.NA * c8);    // per (p, i): lds x NA
+    L.Pcol = (float2 *)take((size_t)nprob * lc.nt * lds * L.NA * c8); // per (p, j): lds x NA
+    L.pack = (PackItem *)take((size_t)npack * sizeof(PackItem));
+    L.gather = (GatherItem *)take((size_t)ngather * sizeof(GatherItem));
+    L.npack = npack;
+    L.ngather = ngather;
+    L.bytes = o;
+    return L;
+}
+
+// Packing and gather items of the run; theta_off[p]: the problem's offset in the theta-space vectors.
+void line_tile_tables(const std::vector<const HostLayout *> &Hs, const std::vector<int64_t> &theta_off,
+                      const LineClass &lc, int64_t lds, std::vector<PackItem> &pack,
+                      std::vector<GatherItem> &gather) {
+    const int nt = lc.nt, d = lc.d, kp = lc.kpad;
+    const int64_t NA = (int64_t)nt * 2 * kp, nrr = (int64_t)nt * d;
+    const int64_t nprob = (int64_t)Hs.size();
+    const int64_t pb = nprob * nrr * NA, pb2 = 2 * pb;   // PB - PA, PB2 - PA (line_tile_carve)
+    for (int64_t p = 0; p < nprob; ++p) {
+        const HostLayout &H = *Hs[p];
+        // tile index of (i, j): diagonal tiles first, then the sub-diagonal ones in t order
+        std::vector<int> tix(nt * nt, -1);
+        for (int i = 0; i < nt; ++i) tix[i * nt + i] = i;
+        for (int i = 0, t = 0; i < nt; ++i)
+            for (int j = 0; j < i; ++j, ++t) tix[i * nt + j] = tix[j * nt + i] = nt + t;
+        const int64_t th = theta_off[p];
+        for (int i = 0; i < nt; ++i)
+            for (int j = 0; j < nt; ++j) {
+                const TileDesc &td = H.tiles[tix[i * nt + j]];
+                const int k = td.k;
+                for (int from = 0; from < 2; ++from) {   // 0: theta block, 1: p block
+                    // A block of row i, column block j: [A_p | A_th] at columns j * 2kp
+                    PackItem a{};
+                    a.from = from;
+                    a.rows = d; a.cols = k;
+                    a.dst = (p * nt + i) * d * NA + j * 2 * kp + (from ? 0 : kp);
+                    a.ldd = NA;
+                    // B block of column j, row block i: [B_th; B_p] at rows i * 2kp (PB), [B_p; 0] (PB2)
+                    PackItem b{};
+                    b.from = from;
+                    b.rows = k; b.cols = d;
+                    b.dst = pb + (p * nt + j) * NA * d + (int64_t)(i * 2 * kp + (from ? kp : 0)) * d;
+                    b.ldd = d;
+                    if (i > j) {          // L (d x k), R (k x d) of tile (i, j)
+                        a.op = PACK_COPY; a.src = th + td.offA; a.lds = k;
+                        b.op = PACK_COPY; b.src = th + td.offB; b.lds = d;
+                    } else if (i < j) {   // tile (j, i): X_ij = R^T L^T
+                        a.op = PACK_TRANS; a.src = th + td.offB; a.lds = d;
+                        b.op = PACK_TRANS; b.src = th + td.offA; b.lds = k;
+                    } else {              // Q Q^T
+                        a.op = PACK_COPY; a.src = th + td.offA; a.lds = k;
+                        b.op = PACK_TRANS; b.src = th + td.offA; b.lds = k;
+                    }
+                    pack.push_back(a);
+                    pack.push_back(b);
+                    if (from) {           // X2 = A_p B_p: B_p also in the first half of the PB2 block
+                        PackItem b2 = b;
+                        b2.dst = pb2 + (p * nt + j) * NA * d + (int64_t)(i * 2 * kp) * d;
+                        pack.push_back(b2);
+                    }
+                }
+                // stage-1 block (row i, column block j) -> stage-2 A of column j at columns i * 2kp
+                GatherItem gi{};
+                gi.k = 2 * kp;
+                gi.src = (p * nt + i) * lds * NA + j * 2 * kp;
+                gi.lds = NA;
+                gi.dst = (p * nt + j) * lds * NA + i * 2 * kp;
+                gi.ldd = NA;
+                gather.push_back(gi);
+            }
+    }
+}
+
+int line_tile_counts(int nprob, const LineClass &lc, int &npack, int &ngather) {
+    npack = nprob * lc.nt * lc.nt * 5;
+    ngather = nprob * lc.nt * lc.nt;
+    return 0;
+}
+
 constexpr int MAX_STREAMS = 8;   // sub-batches of a batched call (tlrmdd_opts.streams)
 
 int check_opts(const tlrmdd_opts *o) {
@@ -403,6 +564,8 @@ int check_opts(const tlrmdd_opts *o) {
     if (!(o->lambda >= 0.0)) return fail(TLRMDD_INVALID_ARGUMENT, "lambda must be >= 0");
     if (o->resid_refresh < 0) return fail(TLRMDD_INVALID_ARGUMENT, "resid_refresh must be >= 0");
     if (o->streams < 0 || o->streams > MAX_STREAMS) return fail(TLRMDD_INVALID_ARGUMENT, "streams must be in [0, 8]");
+    if (o->line_products != TLRMDD_LINE_DENSE && o->line_products != TLRMDD_LINE_TILE)
+        return fail(TLRMDD_INVALID_ARGUMENT, "unknown line_products");
     return TLRMDD_OK;
 }
 
@@ -453,6 +616,49 @@ std::vector<int> group_members(int g, int G, int count) {
     return m;
 }
 
+// Sub-batches of a batched call and the number of streams they run on. With the tile-form line
+// search requested, problems are grouped by form (one sub-batch of dense-form problems, one per
+// tile class, in order of first appearance) and the sub-batches take turns on min(streams, groups)
+// streams; otherwise `streams` interleaved sub-batches, one per stream.
+std::vector<std::vector<int>> make_groups(int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts,
+                                          int *nstreams) {
+    std::vector<std::vector<int>> groups;
+    const bool tile = opts && opts->line_products == TLRMDD_LINE_TILE && opts->precision == TLRMDD_FP32_3M;
+    if (tile) {
+        std::vector<int> dense;
+        std::vector<LineClass> keys;
+        std::vector<std::vector<int>> cls;
+        for (int i = 0; i < count; ++i) {
+            LineClass lc;
+            if (!line_class(plans[i]->H, lc)) {
+                dense.push_back(i);
+                continue;
+            }
+            size_t k = 0;
+            while (k < keys.size() && !(keys[k] == lc)) ++k;
+            if (k == keys.size()) {
+                keys.push_back(lc);
+                cls.emplace_back();
+            }
+            cls[k].push_back(i);
+        }
+        if (!dense.empty()) groups.push_back(dense);
+        for (auto &g : cls) groups.push_back(g);
+        *nstreams = std::max(1, std::min(opts->streams, (int)groups.size()));
+        return groups;
+    }
+    const int G = stream_groups(opts, count);
+    for (int g = 0; g < G; ++g) groups.push_back(group_members(g, G, count));
+    *nstreams = G;
+    return groups;
+}
+
+// a batched call splits into sub-batches (streams or tile-form line search)
+bool grouped_call(int count, const tlrmdd_opts *opts) {
+    return count > 1 && (stream_groups(opts, count) > 1 ||
+                         (opts->line_products == TLRMDD_LINE_TILE && opts->precision == TLRMDD_FP32_3M));
+}
+
 template <typename T> std::vector<T> pick(const T *a, const std::vector<int> &idx) {
     std::vector<T> r;
     for (int i : idx) r.push_back(a[i]);
@@ -469,7 +675,8 @@ template <typename Impl>
 int run_grouped(int op, int count, const tlrmdd_plan *plans, const void *const *D, const void *const *U,
                 void *const *theta, const tlrmdd_opts *opts, double *const *fhist, void *workspace,
                 size_t ws_bytes, hipStream_t stream, Impl impl) {
-    const int G = stream_groups(opts, count);
+    int S = 1;
+    const std::vector<std::vector<int>> groups = make_groups(count, plans, opts, &S);
     std::vector<size_t> parts;
     size_t need = 0;
     int st = ws_bytes_grouped(op, count, plans, opts, &need, &parts);
@@ -477,23 +684,24 @@ int run_grouped(int op, int count, const tlrmdd_plan *plans, const void *const *
     if (!workspace || ws_bytes < need) return fail(TLRMDD_WORKSPACE, "workspace too small");
     std::vector<hipStream_t> ps;
     std::vector<hipEvent_t> ev;
-    if ((st = pool_get(G - 1, ps, ev))) return st;
-    HIP_TRY(hipEventRecord(ev[G - 1], stream));
-    for (int k = 0; k < G - 1; ++k) HIP_TRY(hipStreamWaitEvent(ps[k], ev[G - 1], 0));
+    if ((st = pool_get(S - 1, ps, ev))) return st;
+    HIP_TRY(hipEventRecord(ev[S - 1], stream));
+    for (int k = 0; k < S - 1; ++k) HIP_TRY(hipStreamWaitEvent(ps[k], ev[S - 1], 0));
     char *base = static_cast<char *>(workspace);
     int first_err = TLRMDD_OK;
-    for (int g = 0; g < G; ++g) {
-        const std::vector<int> m = group_members(g, G, count);
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const std::vector<int> &m = groups[g];
         const std::vector<tlrmdd_plan> gp = pick(plans, m);
         const std::vector<const void *> gd = pick(D, m), gu = pick(U, m);
         const std::vector<void *> gt = pick(theta, m);
         const std::vector<double *> gf = pick(fhist, m);
+        const int k = (int)(g % S);
         const int e = impl((int)m.size(), gp.data(), gd.data(), gu.data(), gt.data(), gf.data(), base, parts[g],
-                           g == 0 ? stream : ps[g - 1]);
+                           k == 0 ? stream : ps[k - 1]);
         if (e && !first_err) first_err = e;
         base += align256(parts[g]);
     }
-    for (int k = 0; k < G - 1; ++k) {
+    for (int k = 0; k < S - 1; ++k) {
         HIP_TRY(hipEventRecord(ev[k], ps[k]));
         HIP_TRY(hipStreamWaitEvent(stream, ev[k], 0));
     }
@@ -600,6 +808,12 @@ int tlrmdd_workspace_bytes(tlrmdd_plan plan, int op, const tlrmdd_opts *opts, si
         m1 = (opts->optimizer == TLRMDD_LBFGS) ? opts->lbfgs_m + 1 : 1;
     }
     *bytes = ws_bytes_single(plan, op, m1);
+    LineClass lc;
+    if (op == TLRMDD_OP_SOLVE && run_line_class(1, &plan, opts, lc)) {
+        int npack = 0, ngather = 0;
+        line_tile_counts(1, lc, npack, ngather);
+        *bytes += line_tile_carve(nullptr, 1, lc, plan->lds, npack, ngather).bytes;
+    }
     return TLRMDD_OK;
 }
 
@@ -783,7 +997,40 @@ struct Run {
     const tlrmdd_opts *opts = nullptr;
     // ADMM state (op 3): split variable, scaled dual, penalty center
     float *z = nullptr, *u = nullptr, *cen = nullptr;
+    LineTile lt;                     // tile-form line search (off: dense X1, X2)
 };
+
+// [a | b] = D [X1 | X2] with the five line-search sums, in tile form (see LineTile)
+int line_products_tile(Run &R) {
+    Ctx &c = R.c;
+    const LineTile &L = R.lt;
+    const LineClass &lc = L.lc;
+    const int64_t NA = L.NA, d = lc.d, nt = lc.nt;
+    HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
+        return launch_tlr_pack(L.pack, L.npack, (const float2 *)c.w.th, L.PA, c.s, (const float2 *)c.w.p);
+    }));
+    GemmArgs g1 = gemm_args();   // stage 1: P_(p,i) = D_p[:, i d ...] PA_(p,i)
+    g1.A = c.w.Ds; g1.lda = c.ldk; g1.sA = c.lds * c.ldk; g1.sA2 = d;
+    g1.B = L.PA; g1.ldb = NA; g1.sB = nt * d * NA; g1.sB2 = d * NA;
+    g1.C = L.P; g1.ldc = NA; g1.sC = nt * c.lds * NA; g1.sC2 = c.lds * NA;
+    g1.M = (int)c.lds; g1.N = (int)NA; g1.K = (int)d;
+    g1.nz2 = (int)nt;
+    HIP_TRY(timed(TLRMDD_K_LINE_TILE, c.s, [&] { return launch_cgemm3m(GM_STORE, g1, (int)(c.nprob * nt), c.s, true); }));
+    HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
+        return launch_tlr_gather2(L.gather, L.ngather, L.P, L.Pcol, c.lds, c.s);
+    }));
+    GemmArgs g2 = gemm_args();   // stage 2: [a | b]_(p, columns of tile j) = Pcol_(p,j) [PB | PB2]_(p,j)
+    g2.A = L.Pcol; g2.lda = NA; g2.sA = nt * c.lds * NA; g2.sA2 = c.lds * NA;
+    g2.B = L.PB; g2.B2 = L.PB2; g2.ldb = d; g2.sB = nt * NA * d; g2.sB2 = NA * d;
+    g2.C = c.w.a; g2.C2 = c.w.b; g2.ldc = c.ldk; g2.sC = c.lds * c.ldk; g2.sC2 = d;
+    g2.E = c.w.r; g2.lde = c.ldk; g2.sE = c.lds * c.ldk; g2.sE2 = d;
+    g2.partials = c.w.partials; g2.sP = (int64_t)c.pstride * 5;
+    g2.sP2 = (c.lds / GEMM_BM) * (d / (GEMM_BN / 2)) * 5;   // the line tiles of one tile column
+    g2.M = (int)c.lds; g2.N = (int)d; g2.K = (int)NA;
+    g2.nz2 = (int)nt;
+    HIP_TRY(timed(TLRMDD_K_LINE_TILE, c.s, [&] { return launch_cgemm3m(GM_LINE, g2, (int)(c.nprob * nt), c.s, true); }));
+    return TLRMDD_OK;
+}
 
 // Split planes of the X space: W (complex64, written by the adjoint product) overlays them with a
 // different element layout, so their padding must be re-zeroed before each assembly.
@@ -856,6 +1103,25 @@ int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *c
     c.w = carve((char *)workspace, op, nprob, c.ldk, c.lds, R.T.theta_total, R.m1, c.pstride,
                 R.single ? 0 : tables_bytes(R.T, nprob));
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
+    LineClass lc;
+    if (op >= 2 && run_line_class(nprob, plans, opts, lc)) {
+        int npack = 0, ngather = 0;
+        line_tile_counts(nprob, lc, npack, ngather);
+        R.lt = line_tile_carve((char *)workspace + c.w.bytes, nprob, lc, c.lds, npack, ngather);
+        if (c.w.bytes + R.lt.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
+        std::vector<PackItem> pack;
+        std::vector<GatherItem> gather;
+        std::vector<int64_t> toff;
+        for (int p = 0; p < nprob; ++p) toff.push_back(R.T.probs[p].theta);
+        line_tile_tables(Hs, toff, lc, c.lds, pack, gather);
+        if ((int)pack.size() != npack || (int)gather.size() != ngather)
+            return fail(TLRMDD_UNSUPPORTED, "tile-form line search tables");
+        HIP_TRY(hipMemcpyAsync(R.lt.pack, pack.data(), pack.size() * sizeof(PackItem), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(R.lt.gather, gather.data(), gather.size() * sizeof(GatherItem),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemsetAsync(R.lt.PA, 0, R.lt.zero_bytes, s));   // rank padding reads as zero
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     if (R.single) {
         c.D = plans[0]->D;
     } else {
@@ -929,16 +1195,23 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
                                    c.w.gram + (2 * m1 + 1) * (2 * m1 + 1), gram_stride(m1), s));
         }
         // exact line search: a = D C1(theta;p), b = D C2(p)
-        if ((st = clear_plane_padding(R))) return st;
-        HIP_TRY(timed(TLRMDD_K_ASSEMBLE_DIR, s, [&] {
-            return launch_assemble(true, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)c.w.th,
-                                   (const float2 *)c.w.p, R.X1, R.X2, s, c.bf16, R.x2w, c.lo_words());
-        }));
+        if (!R.lt.on) {
+            if ((st = clear_plane_padding(R))) return st;
+            HIP_TRY(timed(TLRMDD_K_ASSEMBLE_DIR, s, [&] {
+                return launch_assemble(true, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs,
+                                       (const float2 *)c.w.th, (const float2 *)c.w.p, R.X1, R.X2, s, c.bf16, R.x2w,
+                                       c.lo_words());
+            }));
+        }
         if (lam != 0.0) {
             HIP_TRY(launch_pen(c.D.tsegs, nt, c.w.th, cen, c.w.p, c.w.partials, s));
             if ((st = fin(c, fin_args(FIN_LAMTERMS, c.w.sc), c.D.tcount, 0, 2))) return st;
         }
-        if ((st = gemm_line(c, R.X1, R.X2, R.xstride))) return st;
+        if (R.lt.on) {
+            if ((st = line_products_tile(R))) return st;
+        } else if ((st = gemm_line(c, R.X1, R.X2, R.xstride))) {
+            return st;
+        }
         {
             FinArgs f = fin_args(FIN_LINE, c.w.sc);
             f.lam = lam;
@@ -1177,7 +1450,24 @@ int ws_bytes_group(int op, int count, const tlrmdd_plan *plans, const tlrmdd_opt
     const int m1 = opts->optimizer == TLRMDD_LBFGS ? opts->lbfgs_m + 1 : 1;
     *bytes = carve(nullptr, op, count, ldk, lds, T.theta_total, m1, partial_stride(T, ldk, lds),
                    count == 1 ? 0 : tables_bytes(T, count)).bytes;
+    LineClass lc;
+    if (op >= 2 && run_line_class(count, plans, opts, lc)) {
+        int npack = 0, ngather = 0;
+        line_tile_counts(count, lc, npack, ngather);
+        *bytes += line_tile_carve(nullptr, count, lc, lds, npack, ngather).bytes;
+    }
     return TLRMDD_OK;
+}
+
+bool run_line_class(int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, LineClass &lc) {
+    if (!opts || opts->line_products != TLRMDD_LINE_TILE || opts->precision != TLRMDD_FP32_3M) return false;
+    for (int p = 0; p < count; ++p) {
+        LineClass q;
+        if (!line_class(plans[p]->H, q)) return false;
+        if (p == 0) lc = q;
+        else if (!(q == lc)) return false;
+    }
+    return count > 0;
 }
 
 int ws_bytes_grouped(int op, int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, size_t *bytes,
@@ -1185,10 +1475,12 @@ int ws_bytes_grouped(int op, int count, const tlrmdd_plan *plans, const tlrmdd_o
     if (count <= 0 || !plans || !bytes) return fail(TLRMDD_INVALID_ARGUMENT, "bad arguments");
     int st = check_opts(opts);
     if (st) return st;
-    const int G = stream_groups(opts, count);
+    for (int p = 0; p < count; ++p)
+        if (!plans[p]) return fail(TLRMDD_INVALID_ARGUMENT, "plan is NULL");
+    int S = 1;
     size_t total = 0;
-    for (int g = 0; g < G; ++g) {
-        const std::vector<tlrmdd_plan> gp = pick(plans, group_members(g, G, count));
+    for (const std::vector<int> &m : make_groups(count, plans, opts, &S)) {
+        const std::vector<tlrmdd_plan> gp = pick(plans, m);
         size_t b = 0;
         if ((st = ws_bytes_group(op, (int)gp.size(), gp.data(), opts, &b))) return st;
         if (parts) parts->push_back(b);
@@ -1201,6 +1493,18 @@ int ws_bytes_grouped(int op, int count, const tlrmdd_plan *plans, const tlrmdd_o
 }  // namespace
 
 extern "C" {
+
+int tlrmdd_line_form(tlrmdd_plan plan, const tlrmdd_opts *opts, int *tile_form, int *kpad) {
+    g_last_error.clear();
+    if (!plan || !tile_form) return fail(TLRMDD_INVALID_ARGUMENT, "plan / tile_form is NULL");
+    int st = check_opts(opts);
+    if (st) return st;
+    LineClass lc;
+    const bool on = run_line_class(1, &plan, opts, lc);
+    *tile_form = on ? 1 : 0;
+    if (kpad) *kpad = on ? lc.kpad : 0;
+    return TLRMDD_OK;
+}
 
 int tlrmdd_workspace_bytes_batched(int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, size_t *bytes) {
     g_last_error.clear();
@@ -1233,7 +1537,7 @@ int tlrmdd_admm_batched(int count, const tlrmdd_plan *plans, const void *const *
         return fail(TLRMDD_INVALID_ARGUMENT, "bad arguments");
     int st = check_admm(opts);
     if (st) return st;
-    if (stream_groups(&opts->inner, count) == 1)
+    if (!grouped_call(count, &opts->inner))
         return admm_impl(count, plans, D, U, theta_inout, opts, f_hist_dev, workspace, ws_bytes, stream);
     return run_grouped(3, count, plans, D, U, theta_inout, &opts->inner, f_hist_dev, workspace, ws_bytes, stream,
                        [&](int n, const tlrmdd_plan *p, const void *const *d, const void *const *u, void *const *t,
@@ -1250,7 +1554,7 @@ int tlrmdd_solve_batched(int count, const tlrmdd_plan *plans, const void *const 
         return fail(TLRMDD_INVALID_ARGUMENT, "bad arguments");
     int st = check_opts(opts);
     if (st) return st;
-    if (stream_groups(opts, count) == 1)
+    if (!grouped_call(count, opts))
         return solve_impl(count, plans, D, U, theta_inout, opts, f_hist_dev, workspace, ws_bytes, stream);
     return run_grouped(2, count, plans, D, U, theta_inout, opts, f_hist_dev, workspace, ws_bytes, stream,
                        [&](int n, const tlrmdd_plan *p, const void *const *d, const void *const *u, void *const *t,

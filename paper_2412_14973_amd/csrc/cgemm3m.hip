@@ -40,13 +40,18 @@ constexpr int BP = BN;                // B plane pitch (floats per k row)
 constexpr int B_PLANE = BK * BP;
 constexpr int STAGE = 2 * A_PLANE + 2 * B_PLANE;   // floats: re and im planes of A and B
 
-template <int MODE>
+// ROLE: 0 = the solver's dense products, 1 = the stages of the tile-form line search (the same code;
+// separate instantiations so that profiles tell the two apart)
+template <int MODE, int ROLE>
 __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
     __shared__ float sm[2][STAGE];
 
-    const int z = blockIdx.y;
-    const float2 *A = g.A + z * g.sA;
-    const float2 *B = g.B + z * g.sB;
+    // batch entry: z1 * s + z2 * s2 (two-level batch) or z * s
+    const int zz = blockIdx.y;
+    const int z = g.nz2 > 1 ? zz / g.nz2 : zz;
+    const int z2 = g.nz2 > 1 ? zz % g.nz2 : 0;
+    const float2 *A = g.A + z * g.sA + z2 * g.sA2;
+    const float2 *B = g.B + z * g.sB + z2 * g.sB2;
 
     // workgroup -> tile: contiguous tile ranges per XCD, grouped by 8 tile rows
     const int nb = gridDim.x;
@@ -207,7 +212,7 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
 
     // ---- epilogue: C = (T1 - T2) + i (T3 - T1 - T2) ----
     __shared__ double red[4][5];
-    float2 *C = g.C + z * g.sC;
+    float2 *C = g.C + z * g.sC + z2 * g.sC2;
     const int64_t ldc = g.ldc;
     auto cval = [&](int i, int j, int r) {
         const float t1 = acc[0][i][j][r], t2 = acc[1][i][j][r], t3 = acc[2][i][j][r];
@@ -227,7 +232,7 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
             }
         return;
     }
-    const float2 *E = g.E + z * g.sE;
+    const float2 *E = g.E + z * g.sE + z2 * g.sE2;
     const int64_t lde = g.lde;
     double sums[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (MODE == GM_RESID) {
@@ -251,7 +256,7 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
                 __builtin_amdgcn_sched_barrier(0);
             }
     } else {   // GM_LINE: column block 0 = a = D X1, block 1 = b = D X2 at the same (row, column)
-        float2 *C2 = g.C2 + z * g.sC;
+        float2 *C2 = g.C2 + z * g.sC + z2 * g.sC2;
         const int col = n0 + wn * 32 + j32;
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -282,13 +287,13 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
     __syncthreads();
     if (t < NS) {
         const double v = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
-        g.partials[z * g.sP + (int64_t)pid * NS + t] = v;
+        g.partials[z * g.sP + z2 * g.sP2 + (int64_t)pid * NS + t] = v;
     }
 }
 
 }  // namespace
 
-hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s) {
+hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s, bool tile_stage) {
     GemmArgs a = a0;
     a.tiles_m = a.M / BM;
     a.tiles_n = (mode == GM_LINE) ? a.N / (BN / 2) : a.N / BN;
@@ -308,9 +313,15 @@ hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s
     a.bytesB = (uint32_t)bytesB;
     dim3 grid(a.tiles_m * a.tiles_n, batch);
     switch (mode) {
-        case GM_STORE: hipLaunchKernelGGL(cgemm3m_kernel<GM_STORE>, grid, dim3(256), 0, s, a); break;
-        case GM_RESID: hipLaunchKernelGGL(cgemm3m_kernel<GM_RESID>, grid, dim3(256), 0, s, a); break;
-        case GM_LINE:  hipLaunchKernelGGL(cgemm3m_kernel<GM_LINE>, grid, dim3(256), 0, s, a); break;
+        case GM_STORE:
+            if (tile_stage) hipLaunchKernelGGL((cgemm3m_kernel<GM_STORE, 1>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((cgemm3m_kernel<GM_STORE, 0>), grid, dim3(256), 0, s, a);
+            break;
+        case GM_RESID: hipLaunchKernelGGL((cgemm3m_kernel<GM_RESID, 0>), grid, dim3(256), 0, s, a); break;
+        case GM_LINE:
+            if (tile_stage) hipLaunchKernelGGL((cgemm3m_kernel<GM_LINE, 1>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((cgemm3m_kernel<GM_LINE, 0>), grid, dim3(256), 0, s, a);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

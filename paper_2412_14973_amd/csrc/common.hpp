@@ -72,6 +72,10 @@ struct GemmArgs {
     // uniform batch (grid.y): element strides between problems
     int64_t sA, sB, sC, sE;
     int64_t sP;                      // partial stride (doubles) between problems
+    // two-level batch (three-product kernel): grid.y = nz * nz2, entry z = z1 * nz2 + z2 is at
+    // z1 * s + z2 * s2 for every operand (nz2 <= 1: one level, the s2 are unused)
+    int32_t nz2;
+    int64_t sA2, sB2, sC2, sE2, sP2;
 };
 constexpr int GEMM_BM = 128;
 constexpr int GEMM_BN = 128;   // complex columns per workgroup (64 of a + 64 of b in GM_LINE)
@@ -129,7 +133,7 @@ struct SolveScalars {
 // host launchers (stream ordered)
 hipError_t launch_cgemm(int mode, const GemmArgs &a, int batch, hipStream_t s);
 // the same products in the three-real-product form (FP32 MFMA, interleaved complex64 operands)
-hipError_t launch_cgemm3m(int mode, const GemmArgs &a, int batch, hipStream_t s);
+hipError_t launch_cgemm3m(int mode, const GemmArgs &a, int batch, hipStream_t s, bool tile_stage = false);
 int gemm_partials_per_problem(int mode, int M, int N);
 
 // out_bf16 == false: X / X2 are complex64 matrices (ProbOff.x offsets, ld ProbOff.ldx).

@@ -102,12 +102,17 @@ def bench_inputs(tl):
     return wl, plans, Ds, Us, ths, sample
 
 
-# the bench's default line runs the three-product form on one stream
-@pytest.mark.parametrize("precision_name", ["FP32_3M", "FP32"])
-def test_batched_bench_configuration_sampled(tl, bench_inputs, precision_name):
+# the bench's default line runs the three-product form on one stream; with the tile-form line
+# search the batch splits into sub-batches by form (frequencies 0 and 21 take the tile form)
+@pytest.mark.parametrize("precision_name,line", [("FP32_3M", "LINE_DENSE"), ("FP32", "LINE_DENSE"),
+                                                 ("FP32_3M", "LINE_TILE")])
+def test_batched_bench_configuration_sampled(tl, bench_inputs, precision_name, line):
     wl, plans, Ds, Us, ths, sample = bench_inputs
     iters = 3
-    thT, fh = tl.solve_batched(plans, Ds, Us, ths, iters, precision=getattr(tl, precision_name))
+    if line == "LINE_TILE":
+        assert [tl.line_form(plans[i])[0] for i in sample] == [True, True, False, False]
+    thT, fh = tl.solve_batched(plans, Ds, Us, ths, iters, precision=getattr(tl, precision_name),
+                               line_products=getattr(tl, line))
     torch.cuda.synchronize()
     for i, case in sample.items():
         ref = O.solve(case.T, case.D, case.U, case.theta, iters=iters)
@@ -116,6 +121,6 @@ def test_batched_bench_configuration_sampled(tl, bench_inputs, precision_name):
         rel_f = abs(f_g - ref.f_hist[-1]) / ref.f_hist[-1]
         rel_t = np.linalg.norm(th_g - ref.theta) / np.linalg.norm(ref.theta)
         rel_h = np.max(np.abs(fh[i].cpu().numpy() - ref.f_hist) / ref.f_hist)
-        print(f"{precision_name} freq {i} (k={synth.batched_rank(float(wl.freqs[i]))}): rel_f {rel_f:.2e} "
+        print(f"{precision_name} {line} freq {i} (k={synth.batched_rank(float(wl.freqs[i]))}): rel_f {rel_f:.2e} "
               f"rel_theta {rel_t:.2e} rel f_hist {rel_h:.2e}", flush=True)
         assert rel_f <= 1e-5 and rel_t <= 1e-5 and rel_h <= 1e-5

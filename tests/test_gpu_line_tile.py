@@ -1,0 +1,92 @@
+"""GPU exact line search in tile form (tlrmdd_opts.line_products = TLRMDD_LINE_TILE) vs the oracle.
+
+The line search's [a | b] = D [X1 | X2] is formed from packed factor blocks of theta and p in two
+product stages instead of from the assembled X1, X2; the result is the same up to rounding, so
+the solve is held to the FP32 bar against the FP64 oracle (rel_f, rel_X, rel_theta and the
+f-history entry by entry). Batched calls group the problems by form; every problem's result
+equals its single-problem solve bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_cases import from_geometry, from_workload, to_device
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def tl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2412_14973_amd as m
+    m._lib.load()
+    return m
+
+
+def _case(seed, k_off, k_diag, name):
+    """32 x 16 receivers (nr = 512), sources on every other line (ns = 256), two tiles of 256."""
+    lay = synth.Layout(np.array([256, 256]), np.array([k_off]), np.array(k_diag))
+    return from_geometry(32, 16, "half", 12.0, lay, seed, name)
+
+
+def _metrics(case, th_gpu, th_or):
+    f_g = O.objective(case.T, case.D, case.U, th_gpu)[0]
+    f_o = O.objective(case.T, case.D, case.U, th_or)[0]
+    Xg, Xo = O.assemble(case.T, th_gpu), O.assemble(case.T, th_or)
+    return (abs(f_g - f_o) / f_o, np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo),
+            np.linalg.norm(th_gpu - th_or) / np.linalg.norm(th_or))
+
+
+def test_line_form_query(tl):
+    cases = {"eligible": _case(1, 10, [12, 20], "a"), "dense_diag": _case(1, 10, [-1, 20], "b")}
+    plan = to_device(cases["eligible"], tl, torch)[0]
+    assert tl.line_form(plan) == (True, 32)                       # kpad: a multiple of 32 for two tiles
+    assert tl.line_form(plan, precision=tl.FP32) == (False, 0)    # tile form runs on the 3M products
+    assert tl.line_form(plan, line_products=tl.LINE_DENSE) == (False, 0)
+    assert tl.line_form(to_device(cases["dense_diag"], tl, torch)[0]) == (False, 0)
+
+
+@pytest.mark.parametrize("seed,k_off,k_diag", [(3, 10, [12, 20]), (4, 32, [32, 7])])
+def test_tile_line_search_solve_vs_oracle(tl, seed, k_off, k_diag):
+    case = _case(seed, k_off, k_diag, "tile512")
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    assert tl.line_form(plan)[0]
+    iters = 20
+    thg, fh = tl.solve(plan, D, U, th, iters=iters, precision=tl.FP32_3M, line_products=tl.LINE_TILE)
+    torch.cuda.synchronize()
+    ref = O.solve(case.T, case.D, case.U, case.theta, iters=iters)
+    rf, rx, rt = _metrics(case, thg.cpu().numpy().astype(np.complex128), ref.theta)
+    rel_h = np.max(np.abs(fh.cpu().numpy() - ref.f_hist) / ref.f_hist)
+    print(f"tile line search k_off {k_off}: rel_f {rf:.2e} rel_X {rx:.2e} rel_theta {rt:.2e} "
+          f"f_hist {rel_h:.2e}", flush=True)
+    assert rf <= FP32_TOL and rx <= FP32_TOL and rt <= FP32_TOL and rel_h <= FP32_TOL
+
+
+def test_tile_batched_groups_match_single(tl):
+    cases = [_case(5, 10, [12, 20], "a"), _case(6, 3, [-1, 4], "dense"), _case(7, 20, [30, 9], "b"),
+             _case(8, 5, [6, 7], "c")]
+    devs = [to_device(c, tl, torch) for c in cases]
+    kw = dict(iters=8, precision=tl.FP32_3M, line_products=tl.LINE_TILE)
+    th_b, fh_b = tl.solve_batched([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs],
+                                  [d[3] for d in devs], **kw)
+    singles = [tl.solve(d[0], d[1], d[2], d[3], **kw) for d in devs]
+    torch.cuda.synchronize()
+    for (ts, fs), tb, fb in zip(singles, th_b, fh_b):
+        assert torch.equal(ts, tb) and torch.equal(fs, fb)
+
+
+def test_tile_admm_vs_oracle(tl):
+    case = _case(9, 12, [10, 14], "admm")
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    kw = dict(lams=(1.0, 0.1), outer=2, inner=6, rho=1.0)
+    thg, fh = tl.admm(plan, D, U, th, precision=tl.FP32_3M, line_products=tl.LINE_TILE, **kw)
+    torch.cuda.synchronize()
+    ref = O.admm(case.T, case.D, case.U, case.theta, **kw)
+    rf, rx, rt = _metrics(case, thg.cpu().numpy().astype(np.complex128), ref.theta)
+    rel_h = np.max(np.abs(fh.cpu().numpy() - ref.f_hist) / ref.f_hist)
+    print(f"tile admm: rel_f {rf:.2e} rel_X {rx:.2e} rel_theta {rt:.2e} f_hist {rel_h:.2e}", flush=True)
+    assert rf <= FP32_TOL and rx <= FP32_TOL and rt <= FP32_TOL and rel_h <= FP32_TOL

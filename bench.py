@@ -10,12 +10,18 @@ exact line search (residual recomputed every 20). One step = Hilbert column
 gather of every D and U plus the full 100-iteration solve of all 64
 frequencies (fused launches per phase). Complex products by default in the
 three-real-product form on FP32 matrix cores (--precision fp32 for the
-four-product form, bf16x3 for the BF16 hi+lo split).
+four-product form, bf16x3 for the BF16 hi+lo split). The line search runs
+in tile form for the frequencies where that is cheaper (uniform tiles, Q Q^T
+diagonals, padded rank kpad with 2.5 kpad <= 0.6 d; --line-products dense for
+the assembled X1, X2 everywhere); the batched call then runs one sub-batch
+per (tile size, padded rank) class plus one for the rest.
 
 value = grad iterations per second = 64 * 100 * steps / seconds (each grad
 iteration: objective gradient, L-BFGS direction, exact line search, update).
-The roofline object describes the dominant kernel (the line-search GEMM
-[a | b] = D [X1 | X2]), timed with HIP events on its launch stream; achieved
+The roofline object describes the dominant kernel (the product kind with
+the most time: the adjoint product W = D^H r in the default configuration,
+the line-search product [a | b] = D [X1 | X2] with --line-products dense),
+timed with HIP events on its launch stream; achieved
 counts the algorithmic 8mnk complex flops (the 3M form executes 6mnk:
 executed_tflops / executed_frac).
 cpu_baseline is the FP64 oracle on a bounded sample of the same workload.
@@ -413,7 +419,7 @@ def main():
     ap.add_argument("--error-table", action="store_true",
                     help="per-frequency error of FP32 and BF16x3 solves against the FP64 oracle (large workload)")
     ap.add_argument("--error-snrs", default="10,30", help="error table: SNRs in dB")
-    ap.add_argument("--line-products", choices=["dense", "tile"], default="dense",
+    ap.add_argument("--line-products", choices=["dense", "tile"], default="tile",
                     help="line search products from the assembled X1, X2, or in tile form where cheaper")
     ap.add_argument("--streams", type=int, default=1,
                     help="batched solve: sub-batches on their own streams (problem i in sub-batch i %% streams)")
@@ -510,7 +516,7 @@ def main():
     # Algorithmic flops (complex products counted as 8 m n k) of each product kind over the timed
     # region, from the problems each kind covers: the adjoint every problem and iteration, the
     # dense line-search product the problems whose line search is dense, the tile-form stages the
-    # others (their padded flops: 3 x 8 ns nr (nt 2 kpad) per problem), the residual product
+    # others (their padded flops: 40 ns nr nt kpad per problem), the residual product
     # every problem at each recompute (every sub-batch recomputes at the same iterations).
     forms = [tl.line_form(p, prec, line_products) for p in plans]
     n_tile = sum(1 for f in forms if f[0])
@@ -522,7 +528,7 @@ def main():
     else:
         n_groups = nstreams
     steps_iters = args.steps * iters
-    tile_flops = sum(24.0 * ns * nr * (nr // int(p.tile_size[0])) * 2 * k for p, (t, k) in zip(plans, forms) if t)
+    tile_flops = sum(40.0 * ns * nr * (nr // int(p.tile_size[0])) * k for p, (t, k) in zip(plans, forms) if t)
     total_flops = {
         "gemm_adjoint": 8.0 * nr * ns * nr * nfreq * steps_iters,
         "gemm_line": 16.0 * ns * nr * nr * n_dense * steps_iters,

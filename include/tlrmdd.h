@@ -177,12 +177,13 @@ int tlrmdd_solve(tlrmdd_plan plan, const void *D, const void *U, void *theta_ino
  * (tlrmdd_solve and the batched / ADMM calls): *tile_form = 1 when
  * opts->line_products is TLRMDD_LINE_TILE, the precision is TLRMDD_FP32_3M
  * and the layout qualifies - all tiles of one size d (a multiple of 128),
- * nr a multiple of 128, Q Q^T diagonal tiles - with 3 kpad / d <= 0.6, where
- * kpad is the largest rank rounded up so that a stage-1 row of nt blocks of
- * 2 kpad columns is a whole number of 128-column tiles (the tile form's share
- * of the dense products' flops; conclusions of the paper: the TLR product as
- * the way to cut the cost of the dense products). *kpad (may be NULL) gets
- * the padded rank, 0 for the dense form. */
+ * nr a multiple of 128, Q Q^T diagonal tiles - with 2.5 kpad / d <= 0.6,
+ * where kpad is the largest rank rounded up (to an even number) so that a
+ * stage-1 row of 2 nt blocks of kpad columns is a whole number of 128-column
+ * tiles (2.5 kpad / d: the tile form's share of the dense products' flops;
+ * conclusions of the paper: the TLR product as the way to cut the cost of
+ * the dense products). *kpad (may be NULL) gets the padded rank, 0 for the
+ * dense form. */
 int tlrmdd_line_form(tlrmdd_plan plan, const tlrmdd_opts *opts, int *tile_form, int *kpad);
 
 /* Batched solve of independent frequencies (the paper solves each frequency

@@ -395,11 +395,14 @@ Ws carve(char *base, int op, int nprob, int64_t ldk, int64_t lds, int64_t theta_
 // Every tile pair of X1 = C1(theta; p) and X2 = C2(p) is a product of packed factor blocks
 //   X1_ij = A_p B_th + A_th B_p,  X2_ij = A_p B_p
 // (i > j: A = L, B = R; i < j: A = R_ji^T, B = L_ji^T; i = j: A = Q, B = Q^T; the p-blocks are the
-// same factors of the direction p). Stage 1 forms P_i = D_:,i [A_p(i0) A_th(i0) | A_p(i1) A_th(i1) | ...]
-// for every tile row, a gather regroups the blocks by tile column, and stage 2 forms
-//   a_:,j = sum_i P_ij [B_th; B_p],   b_:,j = sum_i P_ij [B_p; 0]
-// in one line-search product with the five line sums. Ranks are padded to kpad with zero columns.
-// Flops: 3 kpad / d of the dense pair (stage 1 and the two halves of stage 2, each kpad / d).
+// same factors of the direction p). Stage 1 forms P_i = D_:,i [A_p(i0) | A_p(i1) | ... | A_th(i0) | ...]
+// for every tile row (the nt direction blocks first, then the nt theta blocks), a gather regroups the
+// blocks by tile column into Pcol_j = [P_p(0j) | ... | P_th(0j) | ...], and stage 2 forms
+//   a_:,j = Pcol_j [B_th(0j); ...; B_p(0j); ...],   b_:,j = Pcol_j[:, first half] [B_p(0j); ...]
+// in one line-search product with the five line sums (b contracts over the first nt kpad columns only).
+// Ranks are padded to kpad with zero columns. Flops relative to the dense pair D [X1 | X2]:
+// stage 1 kpad / d, stage 2 kpad / d for a and kpad / 2d for b.
+constexpr double LINE_TILE_FLOPS = 2.5;      // flops of the tile form per kpad / d of the dense pair
 constexpr double LINE_TILE_MAX_COST = 0.6;   // tile form where its flops are at most this share
 
 struct LineClass {
@@ -421,17 +424,18 @@ bool line_class(const HostLayout &H, LineClass &lc) {
         kmax = std::max(kmax, td.k);
     }
     const int nt = H.N;
-    // stage-1 rows hold nt blocks of 2 kpad columns, a whole number of 128-column GEMM tiles:
-    // nt * 2 * kpad divisible by 128 <=> kpad divisible by 64 / gcd(nt, 64)
+    // stage-1 rows hold 2 nt blocks of kpad columns, a whole number of 128-column GEMM tiles:
+    // nt * 2 * kpad divisible by 128 <=> kpad divisible by 64 / gcd(nt, 64); then nt kpad (the
+    // k of b) is a multiple of 64, and kpad is kept even for the 16-byte gather copies
     int gcd = nt, b = 64;
     while (b) {
         const int r = gcd % b;
         gcd = b;
         b = r;
     }
-    const int q = 64 / gcd;
+    const int q = std::max(2, 64 / gcd);
     const int kpad = (int)round_up(kmax, q);
-    if (3.0 * kpad > LINE_TILE_MAX_COST * d) return false;
+    if (LINE_TILE_FLOPS * kpad > LINE_TILE_MAX_COST * d) return false;
     lc = LineClass{d, nt, kpad};
     return true;
 }
@@ -502,17 +506,19 @@ void line_tile_tables(const std::vector<const HostLayout *> &Hs, const std::vect
                 const TileDesc &td = H.tiles[tix[i * nt + j]];
                 const int k = td.k;
                 for (int from = 0; from < 2; ++from) {   // 0: theta block, 1: p block
-                    // A block of row i, column block j: [A_p | A_th] at columns j * 2kp
+                    // A block of row i, column block j: A_p at columns j kp, A_th at nt kp + j kp
                     PackItem a{};
                     a.from = from;
                     a.rows = d; a.cols = k;
-                    a.dst = (p * nt + i) * d * NA + j * 2 * kp + (from ? 0 : kp);
+                    a.dst = (p * nt + i) * d * NA + (from ? 0 : nt * kp) + j * kp;
                     a.ldd = NA;
-                    // B block of column j, row block i: [B_th; B_p] at rows i * 2kp (PB), [B_p; 0] (PB2)
+                    // B block of column j, row block i, facing the stage-2 A columns: in PB, B_th at
+                    // rows i kp (facing P_p) and B_p at rows nt kp + i kp (facing P_th); in PB2, B_p at
+                    // rows i kp
                     PackItem b{};
                     b.from = from;
                     b.rows = k; b.cols = d;
-                    b.dst = pb + (p * nt + j) * NA * d + (int64_t)(i * 2 * kp + (from ? kp : 0)) * d;
+                    b.dst = pb + (p * nt + j) * NA * d + (int64_t)((from ? nt * kp : 0) + i * kp) * d;
                     b.ldd = d;
                     if (i > j) {          // L (d x k), R (k x d) of tile (i, j)
                         a.op = PACK_COPY; a.src = th + td.offA; a.lds = k;
@@ -528,25 +534,28 @@ void line_tile_tables(const std::vector<const HostLayout *> &Hs, const std::vect
                     pack.push_back(b);
                     if (from) {           // X2 = A_p B_p: B_p also in the first half of the PB2 block
                         PackItem b2 = b;
-                        b2.dst = pb2 + (p * nt + j) * NA * d + (int64_t)(i * 2 * kp) * d;
+                        b2.dst = pb2 + (p * nt + j) * NA * d + (int64_t)(i * kp) * d;
                         pack.push_back(b2);
                     }
                 }
-                // stage-1 block (row i, column block j) -> stage-2 A of column j at columns i * 2kp
-                GatherItem gi{};
-                gi.k = 2 * kp;
-                gi.src = (p * nt + i) * lds * NA + j * 2 * kp;
-                gi.lds = NA;
-                gi.dst = (p * nt + j) * lds * NA + i * 2 * kp;
-                gi.ldd = NA;
-                gather.push_back(gi);
+                // stage-1 blocks (row i, column block j) -> stage-2 A of column j at columns i kp
+                // (direction half) and nt kp + i kp (theta half)
+                for (int half = 0; half < 2; ++half) {
+                    GatherItem gi{};
+                    gi.k = kp;
+                    gi.src = (p * nt + i) * lds * NA + half * nt * kp + j * kp;
+                    gi.lds = NA;
+                    gi.dst = (p * nt + j) * lds * NA + half * nt * kp + i * kp;
+                    gi.ldd = NA;
+                    gather.push_back(gi);
+                }
             }
     }
 }
 
 int line_tile_counts(int nprob, const LineClass &lc, int &npack, int &ngather) {
     npack = nprob * lc.nt * lc.nt * 5;
-    ngather = nprob * lc.nt * lc.nt;
+    ngather = nprob * lc.nt * lc.nt * 2;
     return 0;
 }
 
@@ -1027,6 +1036,7 @@ int line_products_tile(Run &R) {
     g2.partials = c.w.partials; g2.sP = (int64_t)c.pstride * 5;
     g2.sP2 = (c.lds / GEMM_BM) * (d / (GEMM_BN / 2)) * 5;   // the line tiles of one tile column
     g2.M = (int)c.lds; g2.N = (int)d; g2.K = (int)NA;
+    g2.K2 = (int)(nt * lc.kpad);   // b: the direction half of Pcol only
     g2.nz2 = (int)nt;
     HIP_TRY(timed(TLRMDD_K_LINE_TILE, c.s, [&] { return launch_cgemm3m(GM_LINE, g2, (int)(c.nprob * nt), c.s, true); }));
     return TLRMDD_OK;

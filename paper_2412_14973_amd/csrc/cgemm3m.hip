@@ -24,6 +24,8 @@
 //     and r meet in one thread.
 // Epilogues as the four-product kernel: C; C = AB - U with FP64 partial sums of
 // |C|^2; a, b with the five line-search sums. K must be a multiple of 16.
+#include <type_traits>
+
 #include "gemm_common.hpp"
 
 namespace tlr {
@@ -99,7 +101,8 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
     };
     constexpr int NBQ = BK / BR;                   // B row passes per stage
     float4 ra[4], rb[NBQ][4];
-    auto load = [&](int k0) {
+    // b2: this stage also needs the B2 half of the tile (GM_LINE past K2 reads B only)
+    auto load = [&](int k0, bool b2) {
         const uint32_t sa = (uint32_t)k0 * 8u;
 #pragma unroll
         for (int q = 0; q < 4; ++q) ra[q] = ld16(rsA, offA + 16 * q, sa);
@@ -107,11 +110,15 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
         for (int pb = 0; pb < NBQ; ++pb) {
             const uint32_t sb = (uint32_t)((int64_t)(k0 + BR * pb) * g.ldb * 8);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) rb[pb][q] = ld16(rsB, offB[q >> 1] + 16 * (q & 1), sb);
+            for (int q = 0; q < 2; ++q) rb[pb][q] = ld16(rsB, offB[0] + 16 * q, sb);
+            if (b2) {
+#pragma unroll
+                for (int q = 2; q < 4; ++q) rb[pb][q] = ld16(rsB, offB[1] + 16 * (q & 1), sb);
+            }
         }
     };
     // split into re and im planes (the sums re + im are formed after the operand reads)
-    auto store_lds = [&](int buf) {
+    auto store_lds = [&](int buf, bool b2) {
         float *ar = sm[buf], *ai = ar + A_PLANE;
         float *br = ai + A_PLANE, *bi = br + B_PLANE;
 #pragma unroll
@@ -126,6 +133,7 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
         for (int pb = 0; pb < NBQ; ++pb)
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
+                if (h == 1 && !b2) continue;
                 const float4 *rr = rb[pb];
                 const int ob = (b_row + BR * pb) * BP + 64 * h + 4 * b_q;
                 *reinterpret_cast<float4 *>(br + ob) = make_float4(rr[2 * h].x, rr[2 * h].z, rr[2 * h + 1].x, rr[2 * h + 1].z);
@@ -156,13 +164,19 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[p][i][j][r] = 0.f;
 
+    // GM_LINE stages of the tile-form line search: b = A B2 only over the first K2 k (B2 is zero
+    // beyond), so later stages skip the B2 loads and the column-block-1 products
+    constexpr bool SPLIT_K2 = MODE == GM_LINE && ROLE == 1;
     const int nk = g.K / BK;
-    load(0);
-    store_lds(0);
+    const int nk2 = (SPLIT_K2 && g.K2 > 0) ? g.K2 / BK : nk;
+    load(0, 0 < nk2);
+    store_lds(0, 0 < nk2);
     __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
+    auto stage = [&](int kt, auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        constexpr int NJ = FULL ? 2 : 1;   // column blocks with products in this stage
         const int buf = kt & 1;
-        if (kt + 1 < nk) load((kt + 1) * BK);
+        if (kt + 1 < nk) load((kt + 1) * BK, kt + 1 < nk2);
         const float *ar = sm[buf], *ai = ar + A_PLANE;
         const float *br = ai + A_PLANE, *bi = br + B_PLANE;
         // operand fragments [A|B][re, im, re + im][block], double-buffered in registers: the
@@ -194,7 +208,7 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j)
+                    for (int j = 0; j < NJ; ++j)
                         acc[p][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[0][p][i], cur[1][p][j], acc[p][i][j], 0, 0, 0);
             if (kc + 2 < BK) {
                 sums(nxt);
@@ -206,9 +220,13 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
                         for (int i = 0; i < 2; ++i) cur[o][p][i] = nxt[o][p][i];
             }
         }
-        if (kt + 1 < nk) store_lds(buf ^ 1);
+        if (kt + 1 < nk) store_lds(buf ^ 1, kt + 1 < nk2);
         __syncthreads();
-    }
+    };
+    int kt = 0;
+    for (; kt < nk2; ++kt) stage(kt, std::true_type{});
+    if constexpr (SPLIT_K2)
+        for (; kt < nk; ++kt) stage(kt, std::false_type{});
 
     // ---- epilogue: C = (T1 - T2) + i (T3 - T1 - T2) ----
     __shared__ double red[4][5];
@@ -299,6 +317,8 @@ hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s
     a.tiles_n = (mode == GM_LINE) ? a.N / (BN / 2) : a.N / BN;
     if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
     if (a.M % BM || a.N % BN || a.K % BK || a.K <= 0) return hipErrorInvalidValue;
+    if (a.K2 < 0 || a.K2 > a.K || a.K2 % BK || (a.K2 && !(mode == GM_LINE && tile_stage)))
+        return hipErrorInvalidValue;
     // byte extents of the buffer resources (32-bit): A is M x lda, B is K x ldb (GM_LINE: B2 follows B)
     const int64_t bytesA = (int64_t)a.M * a.lda * 8;
     int64_t bytesB = (int64_t)a.K * a.ldb * 8;

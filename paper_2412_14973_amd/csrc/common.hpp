@@ -75,6 +75,7 @@ struct GemmArgs {
     // two-level batch (three-product kernel): grid.y = nz * nz2, entry z = z1 * nz2 + z2 is at
     // z1 * s + z2 * s2 for every operand (nz2 <= 1: one level, the s2 are unused)
     int32_t nz2;
+    int32_t K2;                      // GM_LINE: b = A B2 sums over k < K2 only (0: all K; a multiple of 16)
     int64_t sA2, sB2, sC2, sE2, sP2;
 };
 constexpr int GEMM_BM = 128;

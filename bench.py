@@ -19,8 +19,8 @@ per (tile size, padded rank) class plus one for the rest.
 value = grad iterations per second = 64 * 100 * steps / seconds (each grad
 iteration: objective gradient, L-BFGS direction, exact line search, update).
 The roofline object describes the dominant kernel (the product kind with
-the most time: the adjoint product W = D^H r in the default configuration,
-the line-search product [a | b] = D [X1 | X2] with --line-products dense),
+the most algorithmic flops: the line-search product [a | b] = D [X1 | X2]
+of the frequencies whose line search stays dense),
 timed with HIP events on its launch stream; achieved
 counts the algorithmic 8mnk complex flops (the 3M form executes 6mnk:
 executed_tflops / executed_frac).
@@ -86,6 +86,7 @@ def precision_info(tl, name):
 TRAFFIC_RECORDS = {   # (precision, line-search form, product kind) -> (counter summary, kernel sources)
     ("fp32", "dense", "gemm_line"): ("cgemm_line_traffic.json", ("cgemm.hip", "gemm_common.hpp")),
     ("fp32_3m", "dense", "gemm_line"): ("cgemm3m_line_traffic.json", ("cgemm3m.hip", "gemm_common.hpp")),
+    ("fp32_3m", "tile", "gemm_line"): ("cgemm3m_line_traffic_tile.json", ("cgemm3m.hip", "gemm_common.hpp")),
     ("fp32_3m", "tile", "gemm_adjoint"): ("cgemm3m_adjoint_traffic_tile.json", ("cgemm3m.hip", "gemm_common.hpp")),
     ("bf16x3", "dense", "gemm_line"): ("cgemm_bf16_line_traffic.json", ("cgemm_bf16.hip", "gemm_common.hpp")),
 }
@@ -549,9 +550,10 @@ def main():
             entry["frac_f32_peak"] = rate / PEAK["f32"]
             entry["executed_frac_" + peak_name + "_peak"] = exec_factor * rate / PEAK[peak_name]
         kernels[k] = entry
-    # the roofline kernel: the product kind with the most time
+    # the roofline kernel: the product kind with the most algorithmic flops (with the tile-form line
+    # search the dense line product of the remaining frequencies and the adjoint take about equal time)
     gemm_kinds = [k for k in ("gemm_line", "gemm_adjoint") if kt.launches[k] > 0]
-    dom_kind = max(gemm_kinds, key=lambda k: kt.ms[k])
+    dom_kind = max(gemm_kinds, key=lambda k: total_flops[k])
     dom = kernels[dom_kind]
     achieved = dom["tflops"] * 1e12
     peak = PEAK[peak_name]

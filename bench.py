@@ -13,8 +13,10 @@ three-real-product form on FP32 matrix cores (--precision fp32 for the
 four-product form, bf16x3 for the BF16 hi+lo split). The line search runs
 in tile form for the frequencies where that is cheaper (uniform tiles, Q Q^T
 diagonals, padded rank kpad with 2.5 kpad <= 0.6 d; --line-products dense for
-the assembled X1, X2 everywhere); the batched call then runs one sub-batch
-per (tile size, padded rank) class plus one for the rest.
+the assembled X1, X2 everywhere); every phase is then one launch for all 64
+frequencies except the line-search products: one dense launch for the
+frequencies that keep the dense form, the tile-form stages per (tile size,
+padded rank) class.
 
 value = grad iterations per second = 64 * 100 * steps / seconds (each grad
 iteration: objective gradient, L-BFGS direction, exact line search, update).
@@ -523,7 +525,8 @@ def main():
     n_tile = sum(1 for f in forms if f[0])
     n_dense = nfreq - n_tile
     nstreams = max(1, min(args.streams, nfreq))
-    if line_products == tl.LINE_TILE and prec == tl.FP32_3M:
+    if line_products == tl.LINE_TILE and prec == tl.FP32_3M and nstreams > 1:
+        # one sub-batch per form (the dense-line problems, each tile class), taking turns on the streams
         classes = {(int(p.tile_size[0]), k) for p, (t, k) in zip(plans, forms) if t}
         n_groups = (1 if n_dense else 0) + len(classes)
     else:

@@ -165,6 +165,7 @@ int build_layout(const tlrmdd_layout *L, HostLayout &H) {
 struct Tables {
     std::vector<TileDesc> tiles;
     std::vector<AsmItem> asm_items;
+    std::vector<int> asm_first;     // first assembly item of every problem (items are in problem order)
     std::vector<GradItem> grad_items;
     std::vector<ProbOff> probs;
     std::vector<VecSeg> tsegs;      // theta-space segments
@@ -180,6 +181,7 @@ int64_t theta_span(int64_t theta_size) { return (theta_size + 1) & ~int64_t(1); 
 
 void append_problem(Tables &T, const HostLayout &H, int prob, int64_t x_off, int64_t ldk) {
     const int tile_base = (int)T.tiles.size();
+    T.asm_first.push_back((int)T.asm_items.size());
     for (const TileDesc &td : H.tiles) T.tiles.push_back(td);
     for (int q = 0; q < (int)H.tiles.size(); ++q) {
         const TileDesc &td = H.tiles[q];
@@ -559,6 +561,48 @@ int line_tile_counts(int nprob, const LineClass &lc, int &npack, int &ngather) {
     return 0;
 }
 
+// A run's problems in maximal ranges of one line-search form: dense (X1, X2 assembled, one product
+// D [X1 | X2]) or one tile class. Batched calls order their problems so that every form is one range.
+struct LineSeg {
+    int p0 = 0, np = 0;
+    bool tile = false;
+    LineTile lt;                     // tile ranges: device state of the stages
+};
+
+bool tile_line_requested(int op, const tlrmdd_opts *opts) {
+    return op >= 2 && opts && opts->line_products == TLRMDD_LINE_TILE && opts->precision == TLRMDD_FP32_3M;
+}
+
+// Ranges of the run and the bytes of their tile regions (carved back to back from `base`, or sized
+// only when base is NULL).
+std::vector<LineSeg> line_segments(int op, int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts,
+                                   int64_t lds, char *base, size_t *bytes) {
+    std::vector<LineSeg> segs;
+    std::vector<LineClass> cls(count);
+    std::vector<bool> tile(count, false);
+    if (tile_line_requested(op, opts))
+        for (int p = 0; p < count; ++p) tile[p] = line_class(plans[p]->H, cls[p]);
+    size_t o = 0;
+    for (int p = 0; p < count;) {
+        int q = p + 1;
+        while (q < count && tile[q] == tile[p] && (!tile[p] || cls[q] == cls[p])) ++q;
+        LineSeg sg;
+        sg.p0 = p;
+        sg.np = q - p;
+        sg.tile = tile[p];
+        if (sg.tile) {
+            int npack = 0, ngather = 0;
+            line_tile_counts(sg.np, cls[p], npack, ngather);
+            sg.lt = line_tile_carve(base ? base + o : nullptr, sg.np, cls[p], lds, npack, ngather);
+            o += align256(sg.lt.bytes);
+        }
+        segs.push_back(sg);
+        p = q;
+    }
+    if (bytes) *bytes = o;
+    return segs;
+}
+
 constexpr int MAX_STREAMS = 8;   // sub-batches of a batched call (tlrmdd_opts.streams)
 
 int check_opts(const tlrmdd_opts *o) {
@@ -626,9 +670,10 @@ std::vector<int> group_members(int g, int G, int count) {
 }
 
 // Sub-batches of a batched call and the number of streams they run on. With the tile-form line
-// search requested, problems are grouped by form (one sub-batch of dense-form problems, one per
-// tile class, in order of first appearance) and the sub-batches take turns on min(streams, groups)
-// streams; otherwise `streams` interleaved sub-batches, one per stream.
+// search requested, problems are ordered by form (the dense-form problems, then every tile class in
+// order of first appearance): on one stream as one sub-batch (one launch per phase for all problems,
+// a range of launches for the line search), on several streams as one sub-batch per form taking
+// turns on min(streams, forms) streams. Otherwise `streams` interleaved sub-batches, one per stream.
 std::vector<std::vector<int>> make_groups(int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts,
                                           int *nstreams) {
     std::vector<std::vector<int>> groups;
@@ -654,6 +699,11 @@ std::vector<std::vector<int>> make_groups(int count, const tlrmdd_plan *plans, c
         if (!dense.empty()) groups.push_back(dense);
         for (auto &g : cls) groups.push_back(g);
         *nstreams = std::max(1, std::min(opts->streams, (int)groups.size()));
+        if (*nstreams == 1 && groups.size() > 1) {
+            std::vector<int> all;
+            for (auto &g : groups) all.insert(all.end(), g.begin(), g.end());
+            groups.assign(1, all);
+        }
         return groups;
     }
     const int G = stream_groups(opts, count);
@@ -817,11 +867,10 @@ int tlrmdd_workspace_bytes(tlrmdd_plan plan, int op, const tlrmdd_opts *opts, si
         m1 = (opts->optimizer == TLRMDD_LBFGS) ? opts->lbfgs_m + 1 : 1;
     }
     *bytes = ws_bytes_single(plan, op, m1);
-    LineClass lc;
-    if (op == TLRMDD_OP_SOLVE && run_line_class(1, &plan, opts, lc)) {
-        int npack = 0, ngather = 0;
-        line_tile_counts(1, lc, npack, ngather);
-        *bytes += line_tile_carve(nullptr, 1, lc, plan->lds, npack, ngather).bytes;
+    if (op == TLRMDD_OP_SOLVE) {
+        size_t tb = 0;
+        line_segments(op, 1, &plan, opts, plan->lds, nullptr, &tb);
+        *bytes += tb;
     }
     return TLRMDD_OK;
 }
@@ -1006,13 +1055,28 @@ struct Run {
     const tlrmdd_opts *opts = nullptr;
     // ADMM state (op 3): split variable, scaled dual, penalty center
     float *z = nullptr, *u = nullptr, *cen = nullptr;
-    LineTile lt;                     // tile-form line search (off: dense X1, X2)
+    std::vector<LineSeg> segs;       // line-search form of every problem range
+    std::vector<int> asm_first;      // first assembly item of every problem, and the total
 };
 
-// [a | b] = D [X1 | X2] with the five line-search sums, in tile form (see LineTile)
-int line_products_tile(Run &R) {
-    Ctx &c = R.c;
-    const LineTile &L = R.lt;
+// The context of problems p0 .. p0 + np - 1 of a run for the line-search products (complex64 operands
+// and the line-search partial slots offset to the first problem).
+Ctx line_ctx(const Ctx &c, int p0, int np) {
+    Ctx s = c;
+    const int64_t rs = c.lds * c.ldk;
+    s.nprob = np;
+    s.w.Ds += p0 * rs;
+    s.w.r += p0 * rs;
+    s.w.a += p0 * rs;
+    s.w.b += p0 * rs;
+    s.w.partials += (int64_t)p0 * c.pstride * 5;
+    return s;
+}
+
+// [a | b] = D [X1 | X2] with the five line-search sums for the problems of a tile range (see LineTile)
+int line_products_tile(Run &R, const LineSeg &sg) {
+    const Ctx c = line_ctx(R.c, sg.p0, sg.np);
+    const LineTile &L = sg.lt;
     const LineClass &lc = L.lc;
     const int64_t NA = L.NA, d = lc.d, nt = lc.nt;
     HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
@@ -1113,25 +1177,32 @@ int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *c
     c.w = carve((char *)workspace, op, nprob, c.ldk, c.lds, R.T.theta_total, R.m1, c.pstride,
                 R.single ? 0 : tables_bytes(R.T, nprob));
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
-    LineClass lc;
-    if (op >= 2 && run_line_class(nprob, plans, opts, lc)) {
-        int npack = 0, ngather = 0;
-        line_tile_counts(nprob, lc, npack, ngather);
-        R.lt = line_tile_carve((char *)workspace + c.w.bytes, nprob, lc, c.lds, npack, ngather);
-        if (c.w.bytes + R.lt.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
+    size_t tbytes = 0;
+    R.segs = line_segments(op, nprob, plans, opts, c.lds, (char *)workspace + c.w.bytes, &tbytes);
+    if (c.w.bytes + tbytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
+    R.asm_first = R.T.asm_first;
+    R.asm_first.push_back((int)R.T.asm_items.size());
+    bool any_tile = false;
+    for (LineSeg &sg : R.segs) {
+        if (!sg.tile) continue;
+        any_tile = true;
         std::vector<PackItem> pack;
         std::vector<GatherItem> gather;
         std::vector<int64_t> toff;
-        for (int p = 0; p < nprob; ++p) toff.push_back(R.T.probs[p].theta);
-        line_tile_tables(Hs, toff, lc, c.lds, pack, gather);
-        if ((int)pack.size() != npack || (int)gather.size() != ngather)
+        std::vector<const HostLayout *> Hseg;
+        for (int p = sg.p0; p < sg.p0 + sg.np; ++p) {
+            toff.push_back(R.T.probs[p].theta);
+            Hseg.push_back(Hs[p]);
+        }
+        line_tile_tables(Hseg, toff, sg.lt.lc, c.lds, pack, gather);
+        if ((int)pack.size() != sg.lt.npack || (int)gather.size() != sg.lt.ngather)
             return fail(TLRMDD_UNSUPPORTED, "tile-form line search tables");
-        HIP_TRY(hipMemcpyAsync(R.lt.pack, pack.data(), pack.size() * sizeof(PackItem), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(R.lt.gather, gather.data(), gather.size() * sizeof(GatherItem),
+        HIP_TRY(hipMemcpyAsync(sg.lt.pack, pack.data(), pack.size() * sizeof(PackItem), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(sg.lt.gather, gather.data(), gather.size() * sizeof(GatherItem),
                                hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemsetAsync(R.lt.PA, 0, R.lt.zero_bytes, s));   // rank padding reads as zero
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipMemsetAsync(sg.lt.PA, 0, sg.lt.zero_bytes, s));   // rank padding reads as zero
     }
+    if (any_tile) HIP_TRY(hipStreamSynchronize(s));
     if (R.single) {
         c.D = plans[0]->D;
     } else {
@@ -1205,10 +1276,13 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
                                    c.w.gram + (2 * m1 + 1) * (2 * m1 + 1), gram_stride(m1), s));
         }
         // exact line search: a = D C1(theta;p), b = D C2(p)
-        if (!R.lt.on) {
+        for (const LineSeg &sg : R.segs) {
+            if (sg.tile) continue;
             if ((st = clear_plane_padding(R))) return st;
+            const int a0 = R.single ? 0 : R.asm_first[sg.p0];
+            const int na = R.single ? c.D.n_asm : R.asm_first[sg.p0 + sg.np] - a0;
             HIP_TRY(timed(TLRMDD_K_ASSEMBLE_DIR, s, [&] {
-                return launch_assemble(true, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs,
+                return launch_assemble(true, c.D.tiles, c.D.asm_items + a0, na, c.D.probs,
                                        (const float2 *)c.w.th, (const float2 *)c.w.p, R.X1, R.X2, s, c.bf16, R.x2w,
                                        c.lo_words());
             }));
@@ -1217,10 +1291,12 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
             HIP_TRY(launch_pen(c.D.tsegs, nt, c.w.th, cen, c.w.p, c.w.partials, s));
             if ((st = fin(c, fin_args(FIN_LAMTERMS, c.w.sc), c.D.tcount, 0, 2))) return st;
         }
-        if (R.lt.on) {
-            if ((st = line_products_tile(R))) return st;
-        } else if ((st = gemm_line(c, R.X1, R.X2, R.xstride))) {
-            return st;
+        for (const LineSeg &sg : R.segs) {
+            if (sg.tile) st = line_products_tile(R, sg);
+            else if (sg.np == c.nprob) st = gemm_line(c, R.X1, R.X2, R.xstride);
+            else st = gemm_line(line_ctx(c, sg.p0, sg.np), R.X1 + sg.p0 * R.xstride, R.X2 + sg.p0 * R.xstride,
+                                R.xstride);
+            if (st) return st;
         }
         {
             FinArgs f = fin_args(FIN_LINE, c.w.sc);
@@ -1460,12 +1536,9 @@ int ws_bytes_group(int op, int count, const tlrmdd_plan *plans, const tlrmdd_opt
     const int m1 = opts->optimizer == TLRMDD_LBFGS ? opts->lbfgs_m + 1 : 1;
     *bytes = carve(nullptr, op, count, ldk, lds, T.theta_total, m1, partial_stride(T, ldk, lds),
                    count == 1 ? 0 : tables_bytes(T, count)).bytes;
-    LineClass lc;
-    if (op >= 2 && run_line_class(count, plans, opts, lc)) {
-        int npack = 0, ngather = 0;
-        line_tile_counts(count, lc, npack, ngather);
-        *bytes += line_tile_carve(nullptr, count, lc, lds, npack, ngather).bytes;
-    }
+    size_t tb = 0;
+    line_segments(op, count, plans, opts, lds, nullptr, &tb);
+    *bytes += tb;
     return TLRMDD_OK;
 }
 

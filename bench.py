@@ -525,12 +525,7 @@ def main():
     n_tile = sum(1 for f in forms if f[0])
     n_dense = nfreq - n_tile
     nstreams = max(1, min(args.streams, nfreq))
-    if line_products == tl.LINE_TILE and prec == tl.FP32_3M and nstreams > 1:
-        # one sub-batch per form (the dense-line problems, each tile class), taking turns on the streams
-        classes = {(int(p.tile_size[0]), k) for p, (t, k) in zip(plans, forms) if t}
-        n_groups = (1 if n_dense else 0) + len(classes)
-    else:
-        n_groups = nstreams
+    n_groups = nstreams
     steps_iters = args.steps * iters
     tile_flops = sum(40.0 * ns * nr * (nr // int(p.tile_size[0])) * k for p, (t, k) in zip(plans, forms) if t)
     total_flops = {

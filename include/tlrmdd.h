@@ -101,8 +101,10 @@ typedef struct {
                                bit-identical for every value; single-problem calls ignore it. */
     int32_t line_products;  /* TLRMDD_LINE_DENSE (0): the line search's [a | b] = D [X1 | X2] from
                                the assembled X1, X2; TLRMDD_LINE_TILE (1): in tile form wherever that
-                               needs fewer flops (see tlrmdd_line_form); batched calls then run the
-                               problems in sub-batches of equal form */
+                               needs fewer flops (see tlrmdd_line_form); batched calls still run
+                               every phase as one launch per sub-batch, except the line-search
+                               products: one launch for the dense-form problems and the tile-form
+                               stages once per (tile size, padded rank) class */
     int32_t reserved;       /* 0 */
 } tlrmdd_opts;
 

@@ -669,11 +669,12 @@ std::vector<int> group_members(int g, int G, int count) {
     return m;
 }
 
-// Sub-batches of a batched call and the number of streams they run on. With the tile-form line
-// search requested, problems are ordered by form (the dense-form problems, then every tile class in
-// order of first appearance): on one stream as one sub-batch (one launch per phase for all problems,
-// a range of launches for the line search), on several streams as one sub-batch per form taking
-// turns on min(streams, forms) streams. Otherwise `streams` interleaved sub-batches, one per stream.
+// Sub-batches of a batched call and the number of streams they run on: `streams` interleaved
+// sub-batches, one per stream (problem i in sub-batch i mod streams, so every sub-batch gets the same
+// mix). With the tile-form line search requested, every sub-batch lists its problems by form (the
+// dense-form problems, then every tile class in order of first appearance), so each form is one
+// range of its run (one launch per phase for the whole sub-batch, a launch per range for the line
+// search products).
 std::vector<std::vector<int>> make_groups(int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts,
                                           int *nstreams) {
     std::vector<std::vector<int>> groups;
@@ -696,14 +697,18 @@ std::vector<std::vector<int>> make_groups(int count, const tlrmdd_plan *plans, c
             }
             cls[k].push_back(i);
         }
-        if (!dense.empty()) groups.push_back(dense);
-        for (auto &g : cls) groups.push_back(g);
-        *nstreams = std::max(1, std::min(opts->streams, (int)groups.size()));
-        if (*nstreams == 1 && groups.size() > 1) {
-            std::vector<int> all;
-            for (auto &g : groups) all.insert(all.end(), g.begin(), g.end());
-            groups.assign(1, all);
+        std::vector<int> rank(count);   // position of every problem in form order
+        int r = 0;
+        for (int i : dense) rank[i] = r++;
+        for (auto &g : cls)
+            for (int i : g) rank[i] = r++;
+        const int G = stream_groups(opts, count);
+        for (int g = 0; g < G; ++g) {
+            std::vector<int> m = group_members(g, G, count);
+            std::sort(m.begin(), m.end(), [&](int a, int b) { return rank[a] < rank[b]; });
+            groups.push_back(m);
         }
+        *nstreams = G;
         return groups;
     }
     const int G = stream_groups(opts, count);

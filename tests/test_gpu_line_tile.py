@@ -27,9 +27,11 @@ def tl():
     return m
 
 
-def _case(seed, k_off, k_diag, name):
-    """32 x 16 receivers (nr = 512), sources on every other line (ns = 256), two tiles of 256."""
-    lay = synth.Layout(np.array([256, 256]), np.array([k_off]), np.array(k_diag))
+def _case(seed, k_off, k_diag, name, tiles=(256, 256)):
+    """32 x 16 receivers (nr = 512), sources on every other line (ns = 256), two tiles of 256 (or
+    the given tile sizes, every off-diagonal tile of rank k_off)."""
+    nt = len(tiles)
+    lay = synth.Layout(np.array(tiles), np.full(nt * (nt - 1) // 2, k_off), np.array(k_diag))
     return from_geometry(32, 16, "half", 12.0, lay, seed, name)
 
 
@@ -73,6 +75,26 @@ def test_tile_batched_groups_match_single(tl):
     kw = dict(iters=8, precision=tl.FP32_3M, line_products=tl.LINE_TILE)
     th_b, fh_b = tl.solve_batched([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs],
                                   [d[3] for d in devs], **kw)
+    singles = [tl.solve(d[0], d[1], d[2], d[3], **kw) for d in devs]
+    torch.cuda.synchronize()
+    for (ts, fs), tb, fb in zip(singles, th_b, fh_b):
+        assert torch.equal(ts, tb) and torch.equal(fs, fb)
+
+
+@pytest.mark.parametrize("streams", [1, 2, 3])
+def test_tile_batched_two_classes_match_single(tl, streams):
+    """Two tile classes (tile 256, kpad 32; tile 128, kpad 16) and a dense-form problem in one call,
+    in an order that interleaves them: the call lists every sub-batch's problems by form; each
+    problem's factors and f-history equal its single-problem solve bit for bit."""
+    cases = [_case(11, 10, [12, 20], "a"), _case(12, 12, [9, 14, 5, 16], "q4a", tiles=(128,) * 4),
+             _case(13, 3, [-1, 4], "dense"), _case(14, 20, [30, 9], "b"),
+             _case(15, 6, [5, 6, 7, 8], "q4b", tiles=(128,) * 4)]
+    devs = [to_device(c, tl, torch) for c in cases]
+    forms = [tl.line_form(d[0]) for d in devs]
+    assert forms == [(True, 32), (True, 16), (False, 0), (True, 32), (True, 16)]
+    kw = dict(iters=6, precision=tl.FP32_3M, line_products=tl.LINE_TILE)
+    th_b, fh_b = tl.solve_batched([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs],
+                                  [d[3] for d in devs], streams=streams, **kw)
     singles = [tl.solve(d[0], d[1], d[2], d[3], **kw) for d in devs]
     torch.cuda.synchronize()
     for (ts, fs), tb, fb in zip(singles, th_b, fh_b):

@@ -180,9 +180,8 @@ int tlrmdd_solve(tlrmdd_plan plan, const void *D, const void *U, void *theta_ino
  * opts->line_products is TLRMDD_LINE_TILE, the precision is TLRMDD_FP32_3M
  * and the layout qualifies - all tiles of one size d (a multiple of 128),
  * nr a multiple of 128, Q Q^T diagonal tiles - with 2.5 kpad / d <= 0.6,
- * where kpad is the largest rank rounded up (to an even number) so that a
- * stage-1 row of 2 nt blocks of kpad columns is a whole number of 128-column
- * tiles (2.5 kpad / d: the tile form's share of the dense products' flops;
+ * where kpad is the largest rank rounded up so that a stage-1 row of 2 nt
+ * blocks of kpad columns is a whole number of 128-column tiles (2.5 kpad / d: the tile form's share of the dense products' flops;
  * conclusions of the paper: the TLR product as the way to cut the cost of
  * the dense products). *kpad (may be NULL) gets the padded rank, 0 for the
  * dense form. */
@@ -328,7 +327,7 @@ int tlrmdd_permute_columns(const void *in, const int64_t *perm, void *out,
 #define TLRMDD_K_ASSEMBLE      3  /* X = C(theta)                              */
 #define TLRMDD_K_ASSEMBLE_DIR  4  /* X1, X2 of the line search                 */
 #define TLRMDD_K_GRAD          5  /* per-tile gradient contractions            */
-#define TLRMDD_K_LINE_PACK     6  /* tile-form line search: factor packing, gather */
+#define TLRMDD_K_LINE_PACK     6  /* tile-form line search: factor packing */
 #define TLRMDD_K_LINE_TILE     7  /* tile-form line search: both product stages */
 #define TLRMDD_K_NKINDS        8
 int tlrmdd_timing_begin(void);

@@ -398,8 +398,8 @@ Ws carve(char *base, int op, int nprob, int64_t ldk, int64_t lds, int64_t theta_
 //   X1_ij = A_p B_th + A_th B_p,  X2_ij = A_p B_p
 // (i > j: A = L, B = R; i < j: A = R_ji^T, B = L_ji^T; i = j: A = Q, B = Q^T; the p-blocks are the
 // same factors of the direction p). Stage 1 forms P_i = D_:,i [A_p(i0) | A_p(i1) | ... | A_th(i0) | ...]
-// for every tile row (the nt direction blocks first, then the nt theta blocks), a gather regroups the
-// blocks by tile column into Pcol_j = [P_p(0j) | ... | P_th(0j) | ...], and stage 2 forms
+// for every tile row (the nt direction blocks first, then the nt theta blocks) and stores its blocks
+// regrouped by tile column, Pcol_j = [P_p(0j) | ... | P_th(0j) | ...], and stage 2 forms
 //   a_:,j = Pcol_j [B_th(0j); ...; B_p(0j); ...],   b_:,j = Pcol_j[:, first half] [B_p(0j); ...]
 // in one line-search product with the five line sums (b contracts over the first nt kpad columns only).
 // Ranks are padded to kpad with zero columns. Flops relative to the dense pair D [X1 | X2]:
@@ -428,14 +428,14 @@ bool line_class(const HostLayout &H, LineClass &lc) {
     const int nt = H.N;
     // stage-1 rows hold 2 nt blocks of kpad columns, a whole number of 128-column GEMM tiles:
     // nt * 2 * kpad divisible by 128 <=> kpad divisible by 64 / gcd(nt, 64); then nt kpad (the
-    // k of b) is a multiple of 64, and kpad is kept even for the 16-byte gather copies
+    // k of b) is a multiple of 64
     int gcd = nt, b = 64;
     while (b) {
         const int r = gcd % b;
         gcd = b;
         b = r;
     }
-    const int q = std::max(2, 64 / gcd);
+    const int q = 64 / gcd;
     const int kpad = (int)round_up(kmax, q);
     if (LINE_TILE_FLOPS * kpad > LINE_TILE_MAX_COST * d) return false;
     lc = LineClass{d, nt, kpad};
@@ -449,15 +449,14 @@ struct LineTile {
     bool on = false;
     LineClass lc;
     int64_t NA = 0;                  // columns of a stage-1 row block: nt * 2 kpad (= rows of a stage-2 B)
-    float2 *PA = nullptr, *PB = nullptr, *PB2 = nullptr, *P = nullptr, *Pcol = nullptr;
+    float2 *PA = nullptr, *PB = nullptr, *PB2 = nullptr, *Pcol = nullptr;
     PackItem *pack = nullptr;
-    GatherItem *gather = nullptr;
-    int npack = 0, ngather = 0;
+    int npack = 0;
     size_t bytes = 0, zero_bytes = 0;   // zero_bytes: PA .. PB2 (their padding must read as zero)
 };
 
 // Workspace region of the tile-form line search for `nprob` problems of class lc (laid out at base).
-LineTile line_tile_carve(char *base, int nprob, const LineClass &lc, int64_t lds, int npack, int ngather) {
+LineTile line_tile_carve(char *base, int nprob, const LineClass &lc, int64_t lds, int npack) {
     LineTile L;
     L.on = true;
     L.lc = lc;
@@ -477,20 +476,16 @@ LineTile line_tile_carve(char *base, int nprob, const LineClass &lc, int64_t lds
     L.PB = L.PA ? L.PA + blk : nullptr;
     L.PB2 = L.PA ? L.PA + 2 * blk : nullptr;
     L.zero_bytes = o;
-    L.P = (float2 *)take((size_t)nprob * lc.nt * lds * L.NA * c8);    // per (p, i): lds x NA
     L.Pcol = (float2 *)take((size_t)nprob * lc.nt * lds * L.NA * c8); // per (p, j): lds x NA
     L.pack = (PackItem *)take((size_t)npack * sizeof(PackItem));
-    L.gather = (GatherItem *)take((size_t)ngather * sizeof(GatherItem));
     L.npack = npack;
-    L.ngather = ngather;
     L.bytes = o;
     return L;
 }
 
-// Packing and gather items of the run; theta_off[p]: the problem's offset in the theta-space vectors.
+// Packing items of the run; theta_off[p]: the problem's offset in the theta-space vectors.
 void line_tile_tables(const std::vector<const HostLayout *> &Hs, const std::vector<int64_t> &theta_off,
-                      const LineClass &lc, int64_t lds, std::vector<PackItem> &pack,
-                      std::vector<GatherItem> &gather) {
+                      const LineClass &lc, int64_t lds, std::vector<PackItem> &pack) {
     const int nt = lc.nt, d = lc.d, kp = lc.kpad;
     const int64_t NA = (int64_t)nt * 2 * kp, nrr = (int64_t)nt * d;
     const int64_t nprob = (int64_t)Hs.size();
@@ -540,24 +535,12 @@ void line_tile_tables(const std::vector<const HostLayout *> &Hs, const std::vect
                         pack.push_back(b2);
                     }
                 }
-                // stage-1 blocks (row i, column block j) -> stage-2 A of column j at columns i kp
-                // (direction half) and nt kp + i kp (theta half)
-                for (int half = 0; half < 2; ++half) {
-                    GatherItem gi{};
-                    gi.k = kp;
-                    gi.src = (p * nt + i) * lds * NA + half * nt * kp + j * kp;
-                    gi.lds = NA;
-                    gi.dst = (p * nt + j) * lds * NA + half * nt * kp + i * kp;
-                    gi.ldd = NA;
-                    gather.push_back(gi);
-                }
             }
     }
 }
 
-int line_tile_counts(int nprob, const LineClass &lc, int &npack, int &ngather) {
+int line_tile_counts(int nprob, const LineClass &lc, int &npack) {
     npack = nprob * lc.nt * lc.nt * 5;
-    ngather = nprob * lc.nt * lc.nt * 2;
     return 0;
 }
 
@@ -591,9 +574,9 @@ std::vector<LineSeg> line_segments(int op, int count, const tlrmdd_plan *plans, 
         sg.np = q - p;
         sg.tile = tile[p];
         if (sg.tile) {
-            int npack = 0, ngather = 0;
-            line_tile_counts(sg.np, cls[p], npack, ngather);
-            sg.lt = line_tile_carve(base ? base + o : nullptr, sg.np, cls[p], lds, npack, ngather);
+            int npack = 0;
+            line_tile_counts(sg.np, cls[p], npack);
+            sg.lt = line_tile_carve(base ? base + o : nullptr, sg.np, cls[p], lds, npack);
             o += align256(sg.lt.bytes);
         }
         segs.push_back(sg);
@@ -1090,13 +1073,12 @@ int line_products_tile(Run &R, const LineSeg &sg) {
     GemmArgs g1 = gemm_args();   // stage 1: P_(p,i) = D_p[:, i d ...] PA_(p,i)
     g1.A = c.w.Ds; g1.lda = c.ldk; g1.sA = c.lds * c.ldk; g1.sA2 = d;
     g1.B = L.PA; g1.ldb = NA; g1.sB = nt * d * NA; g1.sB2 = d * NA;
-    g1.C = L.P; g1.ldc = NA; g1.sC = nt * c.lds * NA; g1.sC2 = c.lds * NA;
+    // stored regrouped by tile column: block j of row i -> Pcol_(p,j) at columns i kpad (each half)
+    g1.C = L.Pcol; g1.ldc = NA; g1.sC = nt * c.lds * NA; g1.sC2 = lc.kpad;
+    g1.scat_kp = lc.kpad; g1.scat_w = (int)(nt * lc.kpad); g1.scat_js = c.lds * NA - lc.kpad;
     g1.M = (int)c.lds; g1.N = (int)NA; g1.K = (int)d;
     g1.nz2 = (int)nt;
     HIP_TRY(timed(TLRMDD_K_LINE_TILE, c.s, [&] { return launch_cgemm3m(GM_STORE, g1, (int)(c.nprob * nt), c.s, true); }));
-    HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
-        return launch_tlr_gather2(L.gather, L.ngather, L.P, L.Pcol, c.lds, c.s);
-    }));
     GemmArgs g2 = gemm_args();   // stage 2: [a | b]_(p, columns of tile j) = Pcol_(p,j) [PB | PB2]_(p,j)
     g2.A = L.Pcol; g2.lda = NA; g2.sA = nt * c.lds * NA; g2.sA2 = c.lds * NA;
     g2.B = L.PB; g2.B2 = L.PB2; g2.ldb = d; g2.sB = nt * NA * d; g2.sB2 = NA * d;
@@ -1192,19 +1174,16 @@ int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *c
         if (!sg.tile) continue;
         any_tile = true;
         std::vector<PackItem> pack;
-        std::vector<GatherItem> gather;
         std::vector<int64_t> toff;
         std::vector<const HostLayout *> Hseg;
         for (int p = sg.p0; p < sg.p0 + sg.np; ++p) {
             toff.push_back(R.T.probs[p].theta);
             Hseg.push_back(Hs[p]);
         }
-        line_tile_tables(Hseg, toff, sg.lt.lc, c.lds, pack, gather);
-        if ((int)pack.size() != sg.lt.npack || (int)gather.size() != sg.lt.ngather)
+        line_tile_tables(Hseg, toff, sg.lt.lc, c.lds, pack);
+        if ((int)pack.size() != sg.lt.npack)
             return fail(TLRMDD_UNSUPPORTED, "tile-form line search tables");
         HIP_TRY(hipMemcpyAsync(sg.lt.pack, pack.data(), pack.size() * sizeof(PackItem), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(sg.lt.gather, gather.data(), gather.size() * sizeof(GatherItem),
-                               hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemsetAsync(sg.lt.PA, 0, sg.lt.zero_bytes, s));   // rank padding reads as zero
     }
     if (any_tile) HIP_TRY(hipStreamSynchronize(s));

@@ -242,10 +242,12 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const int col = n0 + wn * 64 + 32 * j + j32;
+                int64_t ccol = col;
+                if (ROLE == 1 && g.scat_kp > 0) ccol += (int64_t)((col % g.scat_w) / g.scat_kp) * g.scat_js;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int row = m0 + wm * 64 + 32 * i + acc_row(r, lane);
-                    C[(int64_t)row * ldc + col] = cval(i, j, r);
+                    C[(int64_t)row * ldc + ccol] = cval(i, j, r);
                 }
             }
         return;
@@ -318,6 +320,8 @@ hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s
     if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
     if (a.M % BM || a.N % BN || a.K % BK || a.K <= 0) return hipErrorInvalidValue;
     if (a.K2 < 0 || a.K2 > a.K || a.K2 % BK || (a.K2 && !(mode == GM_LINE && tile_stage)))
+        return hipErrorInvalidValue;
+    if (a.scat_kp < 0 || (a.scat_kp && (!(mode == GM_STORE && tile_stage) || a.scat_w < a.scat_kp)))
         return hipErrorInvalidValue;
     // byte extents of the buffer resources (32-bit): A is M x lda, B is K x ldb (GM_LINE: B2 follows B)
     const int64_t bytesA = (int64_t)a.M * a.lda * 8;

@@ -77,6 +77,10 @@ struct GemmArgs {
     int32_t nz2;
     int32_t K2;                      // GM_LINE: b = A B2 sums over k < K2 only (0: all K; a multiple of 16)
     int64_t sA2, sB2, sC2, sE2, sP2;
+    // GM_STORE tile stage: output column n is stored at column n + ((n mod scat_w) / scat_kp) * scat_js
+    // (scat_kp = 0: plain), which regroups blocks of scat_kp columns across batch entries
+    int32_t scat_kp, scat_w;
+    int64_t scat_js;
 };
 constexpr int GEMM_BM = 128;
 constexpr int GEMM_BN = 128;   // complex columns per workgroup (64 of a + 64 of b in GM_LINE)

@@ -53,30 +53,7 @@ __global__ __launch_bounds__(256) void tlr_gather_kernel(const GatherItem *__res
             Pcol[it.dst + s * it.ldd + c] = P[it.src + s * it.lds + c];
 }
 
-// The same copy for even k with even offsets and pitches (whole float4 = two complex per thread,
-// consecutive threads along a row, then along rows): the tile-form line search's blocks of 2 kpad.
-__global__ __launch_bounds__(256) void tlr_gather2_kernel(const GatherItem *__restrict__ items,
-                                                          const float2 *__restrict__ P, float2 *__restrict__ Pcol,
-                                                          int64_t rows) {
-    const GatherItem it = items[blockIdx.x];
-    const int h = it.k >> 1;   // float4 per row
-    const int64_t n = rows * h;
-    for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.y * blockDim.x) {
-        const int64_t s = e / h;
-        const int c = (int)(e - s * h);
-        *reinterpret_cast<float4 *>(Pcol + it.dst + s * it.ldd + 2 * c) =
-            *reinterpret_cast<const float4 *>(P + it.src + s * it.lds + 2 * c);
-    }
-}
-
 }  // namespace
-
-hipError_t launch_tlr_gather2(const GatherItem *items, int nitems, const float2 *P, float2 *Pcol, int64_t rows,
-                              hipStream_t s) {
-    if (nitems <= 0 || rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(tlr_gather2_kernel, dim3((unsigned)nitems, 16), dim3(256), 0, s, items, P, Pcol, rows);
-    return hipGetLastError();
-}
 
 hipError_t launch_tlr_pack(const PackItem *items, int nitems, const float2 *theta, float2 *dst, hipStream_t s,
                            const float2 *theta2) {

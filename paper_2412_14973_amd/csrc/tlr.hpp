@@ -31,8 +31,5 @@ hipError_t launch_tlr_pack(const PackItem *items, int nitems, const float2 *thet
                            const float2 *theta2 = nullptr);
 hipError_t launch_tlr_gather(const GatherItem *items, int nitems, const float2 *P, float2 *Pcol, int64_t rows,
                              hipStream_t s);
-// the same for items with even k, src, lds, dst and ldd (16-byte aligned float4 copies)
-hipError_t launch_tlr_gather2(const GatherItem *items, int nitems, const float2 *P, float2 *Pcol, int64_t rows,
-                              hipStream_t s);
 
 }  // namespace tlr

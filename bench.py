@@ -12,11 +12,12 @@ frequencies (fused launches per phase). Complex products by default in the
 three-real-product form on FP32 matrix cores (--precision fp32 for the
 four-product form, bf16x3 for the BF16 hi+lo split). The line search runs
 in tile form for the frequencies where that is cheaper (uniform tiles, Q Q^T
-diagonals, padded rank kpad with 2.5 kpad <= 0.6 d; --line-products dense for
-the assembled X1, X2 everywhere); every phase is then one launch for all 64
-frequencies except the line-search products: one dense launch for the
-frequencies that keep the dense form, the tile-form stages per (tile size,
-padded rank) class.
+diagonals, padded rank kpad with 2.5 kpad <= 0.6 d), and so does the gradient
+(its three products at most 0.6 of the adjoint product: tile 256 here);
+--line-products tile keeps the dense gradient, dense the assembled X1, X2
+everywhere. Every phase is one launch for all 64 frequencies except the
+tile-form products: one dense launch for the frequencies that keep the dense
+form, the tile-form stages per (tile size, padded rank) class.
 
 value = grad iterations per second = 64 * 100 * steps / seconds (each grad
 iteration: objective gradient, L-BFGS direction, exact line search, update).
@@ -422,8 +423,9 @@ def main():
     ap.add_argument("--error-table", action="store_true",
                     help="per-frequency error of FP32 and BF16x3 solves against the FP64 oracle (large workload)")
     ap.add_argument("--error-snrs", default="10,30", help="error table: SNRs in dB")
-    ap.add_argument("--line-products", choices=["dense", "tile"], default="tile",
-                    help="line search products from the assembled X1, X2, or in tile form where cheaper")
+    ap.add_argument("--line-products", choices=["dense", "tile", "tile-grad"], default="tile-grad",
+                    help="line search products from the assembled X1, X2, or in tile form where cheaper "
+                         "(tile-grad: the gradient's products too)")
     ap.add_argument("--streams", type=int, default=1,
                     help="batched solve: sub-batches on their own streams (problem i in sub-batch i %% streams)")
     ap.add_argument("--resid-refresh", type=int, default=20,
@@ -475,7 +477,7 @@ def main():
     dev = torch.device("cuda")
     perm = torch.from_numpy(tl.hilbert_order(geom.rec_ix, geom.rec_iy)).to(dev)
     ns, nr = geom.ns, geom.nr
-    line_products = tl.LINE_TILE if args.line_products == "tile" else tl.LINE_DENSE
+    line_products = {"dense": tl.LINE_DENSE, "tile": tl.LINE_TILE, "tile-grad": tl.LINE_TILE_GRAD}[args.line_products]
     opts = tl.make_opts(iters, precision=prec, streams=args.streams, line_products=line_products)
     if admm:
         aopts = tl.make_admm_opts(lams, args.admm_outer, args.admm_inner, precision=prec, streams=args.streams,
@@ -523,13 +525,19 @@ def main():
     # every problem at each recompute (every sub-batch recomputes at the same iterations).
     forms = [tl.line_form(p, prec, line_products) for p in plans]
     n_tile = sum(1 for f in forms if f[0])
+    n_tgrad = sum(1 for f in forms if f[0] == 2)
     n_dense = nfreq - n_tile
     nstreams = max(1, min(args.streams, nfreq))
     n_groups = nstreams
     steps_iters = args.steps * iters
     tile_flops = sum(40.0 * ns * nr * (nr // int(p.tile_size[0])) * k for p, (t, k) in zip(plans, forms) if t)
+
+    def grad_width(p, k):   # nt kpad rounded up to 128
+        return -(-(nr // int(p.tile_size[0])) * k // 128) * 128
+    grad_flops = sum(24.0 * ns * nr * grad_width(p, k) for p, (t, k) in zip(plans, forms) if t == 2)
     total_flops = {
-        "gemm_adjoint": 8.0 * nr * ns * nr * nfreq * steps_iters,
+        "gemm_adjoint": 8.0 * nr * ns * nr * (nfreq - n_tgrad) * steps_iters,
+        "grad_tile": grad_flops * steps_iters,
         "gemm_line": 16.0 * ns * nr * nr * n_dense * steps_iters,
         "line_tile": tile_flops * steps_iters,
         "gemm_resid": 8.0 * ns * nr * nr * nfreq * kt.launches["gemm_resid"] / max(1, n_groups),
@@ -555,12 +563,12 @@ def main():
     dom = kernels[dom_kind]
     achieved = dom["tflops"] * 1e12
     peak = PEAK[peak_name]
-    dom_probs = (n_dense if dom_kind == "gemm_line" else nfreq) * steps_iters / kt.launches[dom_kind]
+    dom_probs = (n_dense if dom_kind == "gemm_line" else nfreq - n_tgrad) * steps_iters / kt.launches[dom_kind]
     dom_name = (line_kernel + " ([a|b] = D [X1|X2])" if dom_kind == "gemm_line"
                 else adjoint_kernel + " (W = D^H r)")
     gemm_flops = sum(total_flops[k] for k in total_flops)
     gemm_s = sum(kt.ms[k] for k in total_flops) * 1e-3
-    mode = "tile" if n_tile else "dense"
+    mode = ("tile_grad" if n_tgrad else "tile") if n_tile else "dense"
     line = {
         "metric": "TLR-MDD grad iters/s",
         "value": value,
@@ -577,7 +585,8 @@ def main():
         "config": {"workload": wl.name if nfreq == len(wl.freqs) else f"{wl.name}[first {nfreq}]",
                    "nr": nr, "ns": ns, "frequencies": nfreq, "iters": iters,
                    "resid_refresh": tl.RESID_REFRESH, "streams": nstreams,
-                   "line_products": f"{args.line_products} ({n_tile} of {nfreq} frequencies in tile form)",
+                   "line_products": f"{args.line_products} ({n_tile} of {nfreq} frequencies in tile form"
+                                    + (f", {n_tgrad} with the gradient in tile form)" if n_tgrad else ")"),
                    "optimizer": ("admm(lambda 10,1,0.1; %d x %d L-BFGS(m=5) per stage)" % (args.admm_outer,
                                                                                         args.admm_inner))
                    if admm else "lbfgs(m=5)",

@@ -104,12 +104,19 @@ typedef struct {
                                needs fewer flops (see tlrmdd_line_form); batched calls still run
                                every phase as one launch per sub-batch, except the line-search
                                products: one launch for the dense-form problems and the tile-form
-                               stages once per (tile size, padded rank) class */
+                               stages once per (tile size, padded rank) class;
+                               TLRMDD_LINE_TILE_GRAD (2): as 1, and the gradient in tile form too
+                               where its three products (3 Wg / nr of the adjoint product D^H r,
+                               Wg = nt kpad rounded up to 128) cost at most 0.6 of the adjoint:
+                               W_ij B_ij^H = D_:,i^H (r_:,j B_ij^H), A_ij^H W_ij = (D_:,i A_ij)^H r_:,j
+                               with X_ij = A_ij B_ij (gradient equations); the adjoint product then
+                               runs on the other problems only */
     int32_t reserved;       /* 0 */
 } tlrmdd_opts;
 
 #define TLRMDD_LINE_DENSE 0
 #define TLRMDD_LINE_TILE  1
+#define TLRMDD_LINE_TILE_GRAD 2
 
 /* Opaque plan: validated layout plus device-side tile tables. */
 typedef struct tlrmdd_plan_s *tlrmdd_plan;
@@ -175,16 +182,21 @@ int tlrmdd_solve(tlrmdd_plan plan, const void *D, const void *U, void *theta_ino
                  const tlrmdd_opts *opts, double *f_hist_dev,
                  void *workspace, size_t ws_bytes, hipStream_t stream);
 
-/* Form of the exact line search's products for this plan under opts
- * (tlrmdd_solve and the batched / ADMM calls): *tile_form = 1 when
- * opts->line_products is TLRMDD_LINE_TILE, the precision is TLRMDD_FP32_3M
- * and the layout qualifies - all tiles of one size d (a multiple of 128),
- * nr a multiple of 128, Q Q^T diagonal tiles - with 2.5 kpad / d <= 0.6,
- * where kpad is the largest rank rounded up so that a stage-1 row of 2 nt
- * blocks of kpad columns is a whole number of 128-column tiles (2.5 kpad / d: the tile form's share of the dense products' flops;
- * conclusions of the paper: the TLR product as the way to cut the cost of
- * the dense products). *kpad (may be NULL) gets the padded rank, 0 for the
- * dense form. */
+/* Form of the exact line search's (and gradient's) products for this plan
+ * under opts (tlrmdd_solve and the batched / ADMM calls): *tile_form = 1
+ * when opts->line_products is TLRMDD_LINE_TILE or TLRMDD_LINE_TILE_GRAD, the
+ * precision is TLRMDD_FP32_3M and the layout qualifies - all tiles of one
+ * size d (a multiple of 128), nr a multiple of 128, Q Q^T diagonal tiles -
+ * with 2.5 kpad / d <= 0.6, where kpad is the largest rank rounded up so
+ * that a stage-1 row of 2 nt blocks of kpad columns is a whole number of
+ * 128-column tiles (2.5 kpad / d: the tile form's share of the dense
+ * products' flops; conclusions of the paper: the TLR product as the way to
+ * cut the cost of the dense products); 2 when the gradient is in tile form
+ * as well (TLRMDD_LINE_TILE_GRAD and 3 Wg / nr <= 0.6). In a batched call a
+ * problem whose gradient would be in tile form keeps the dense gradient when
+ * a problem of another form follows it in the call's order (the library
+ * orders problems by form itself). *kpad (may be NULL) gets the padded rank,
+ * 0 for the dense form. */
 int tlrmdd_line_form(tlrmdd_plan plan, const tlrmdd_opts *opts, int *tile_form, int *kpad);
 
 /* Batched solve of independent frequencies (the paper solves each frequency
@@ -329,7 +341,8 @@ int tlrmdd_permute_columns(const void *in, const int64_t *perm, void *out,
 #define TLRMDD_K_GRAD          5  /* per-tile gradient contractions            */
 #define TLRMDD_K_LINE_PACK     6  /* tile-form line search: factor packing */
 #define TLRMDD_K_LINE_TILE     7  /* tile-form line search: both product stages */
-#define TLRMDD_K_NKINDS        8
+#define TLRMDD_K_GRAD_TILE     8  /* tile-form gradient: its three products */
+#define TLRMDD_K_NKINDS        9
 int tlrmdd_timing_begin(void);
 int tlrmdd_timing_end(double *ms, int64_t *launches);
 

@@ -175,7 +175,9 @@ def benchmark_solve(D, U, lam, iters, precision=FP32, lbfgs_m=5, Z0=None):
 RESID_REFRESH = 20
 
 
-LINE_DENSE, LINE_TILE = 0, 1   # line-search products from the assembled X1, X2 / in tile form where cheaper
+# line-search products from the assembled X1, X2 / in tile form where cheaper / and the gradient in tile form
+# where cheaper too
+LINE_DENSE, LINE_TILE, LINE_TILE_GRAD = 0, 1, 2
 
 
 def make_opts(iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0, resid_refresh=RESID_REFRESH, streams=1,
@@ -185,12 +187,13 @@ def make_opts(iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0, resid_
 
 
 def line_form(plan, precision=FP32_3M, line_products=LINE_TILE):
-    """(tile_form, kpad): whether the line search of this plan runs in tile form under these options."""
+    """(tile_form, kpad): 0 when the line search of this plan runs on the dense products under these
+    options, 1 in tile form, 2 with the gradient in tile form as well."""
     tf, kp = ctypes.c_int(), ctypes.c_int()
     opts = make_opts(1, precision=precision, line_products=line_products)
     _lib.check(_lib.load().tlrmdd_line_form(plan.handle, ctypes.byref(opts), ctypes.byref(tf), ctypes.byref(kp)),
                "tlrmdd_line_form")
-    return bool(tf.value), int(kp.value)
+    return int(tf.value), int(kp.value)
 
 
 def solve(plan, D, U, theta0, iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0, resid_refresh=RESID_REFRESH,

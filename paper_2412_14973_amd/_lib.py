@@ -98,8 +98,9 @@ _SIGS = {
     "tlrmdd_timing_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
 }
 (K_GEMM_RESID, K_GEMM_ADJOINT, K_GEMM_LINE, K_ASSEMBLE, K_ASSEMBLE_DIR, K_GRAD, K_LINE_PACK, K_LINE_TILE,
- K_NKINDS) = range(9)
-KIND_NAMES = ("gemm_resid", "gemm_adjoint", "gemm_line", "assemble", "assemble_dir", "grad", "line_pack", "line_tile")
+ K_GRAD_TILE, K_NKINDS) = range(10)
+KIND_NAMES = ("gemm_resid", "gemm_adjoint", "gemm_line", "assemble", "assemble_dir", "grad", "line_pack", "line_tile",
+              "grad_tile")
 
 EXPORTS = tuple(_SIGS)
 

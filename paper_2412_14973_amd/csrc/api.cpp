@@ -166,6 +166,7 @@ struct Tables {
     std::vector<TileDesc> tiles;
     std::vector<AsmItem> asm_items;
     std::vector<int> asm_first;     // first assembly item of every problem (items are in problem order)
+    std::vector<int> grad_first;    // first gradient item of every problem
     std::vector<GradItem> grad_items;
     std::vector<ProbOff> probs;
     std::vector<VecSeg> tsegs;      // theta-space segments
@@ -182,6 +183,7 @@ int64_t theta_span(int64_t theta_size) { return (theta_size + 1) & ~int64_t(1); 
 void append_problem(Tables &T, const HostLayout &H, int prob, int64_t x_off, int64_t ldk) {
     const int tile_base = (int)T.tiles.size();
     T.asm_first.push_back((int)T.asm_items.size());
+    T.grad_first.push_back((int)T.grad_items.size());
     for (const TileDesc &td : H.tiles) T.tiles.push_back(td);
     for (int q = 0; q < (int)H.tiles.size(); ++q) {
         const TileDesc &td = H.tiles[q];
@@ -409,8 +411,26 @@ constexpr double LINE_TILE_MAX_COST = 0.6;   // tile form where its flops are at
 
 struct LineClass {
     int d = 0, nt = 0, kpad = 0;
-    bool operator==(const LineClass &o) const { return d == o.d && nt == o.nt && kpad == o.kpad; }
+    bool grad = false;               // the gradient in tile form too
+    bool operator==(const LineClass &o) const {
+        return d == o.d && nt == o.nt && kpad == o.kpad && grad == o.grad;
+    }
 };
+
+// Gradient in tile form (TLRMDD_LINE_TILE_GRAD). With W = D^H r and every tile pair a factor product
+// X_ij = A_ij B_ij, the gradient blocks are W_ij B_ij^H = D_:,i^H (r_:,j B_ij^H) and
+// A_ij^H W_ij = (D_:,i A_ij)^H r_:,j (gradient equations; the sum over both orders of a tile pair
+// forms W' = W + W^T). Three batched products of width Wg = nt kpad rounded up to 128:
+//   G1: S_j = r_:,j [B_0j^H | B_1j^H | ...], stored regrouped by tile row (Scol_i = [S_i0 | S_i1 | ...]);
+//   G2: GA_i = D_:,i^H Scol_i;   G3: GBT_j = r_:,j^T conj(P_th(:,j)), with P_th(ij) = D_:,i A_ij the theta
+//   half of the line search's stage 1 (carried to the updated theta by P_th += step P_p);
+// G2 and G3 split their ns-long contraction in GRAD_TILE_KS parts, and
+//   grad A_ij = GA_i[:, j kpad ..] + GBT_i[:, j kpad ..],  grad B_ij = (GA_j[:, i kpad ..] + GBT_j[:, i kpad ..])^T
+// summed over the parts (Q: A = Q, B = Q^T; L, R: the pair (i > j) and its transpose (j, i)).
+// Flops: 3 Wg / nr of the adjoint product D^H r.
+constexpr double GRAD_TILE_MAX_COST = 0.6;
+constexpr int GRAD_TILE_KS = 4;
+int64_t grad_tile_width(const LineClass &lc) { return round_up((int64_t)lc.nt * lc.kpad, GEMM_BN); }
 
 // Tile form is available when all tiles have one size d (a multiple of 128), nr needs no padding,
 // the diagonal tiles are Q Q^T and the padded rank keeps the flops under LINE_TILE_MAX_COST.
@@ -442,7 +462,16 @@ bool line_class(const HostLayout &H, LineClass &lc) {
     return true;
 }
 
-bool run_line_class(int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, LineClass &lc);
+
+// Line-search (and gradient) form of one problem under opts: false = dense; lc.grad = gradient too.
+bool tile_line_requested(int op, const tlrmdd_opts *opts);
+bool problem_form(int op, const HostLayout &H, const tlrmdd_opts *opts, LineClass &lc) {
+    if (!tile_line_requested(op, opts) || !line_class(H, lc)) return false;
+    lc.grad = opts->line_products == TLRMDD_LINE_TILE_GRAD &&
+              3.0 * (double)grad_tile_width(lc) <= GRAD_TILE_MAX_COST * (double)H.nr &&
+              (int64_t)GRAD_TILE_KS * 16 <= round_up(H.ns, GEMM_PAD) && round_up(H.ns, GEMM_PAD) % (GRAD_TILE_KS * 16) == 0;
+    return true;
+}
 
 // Device state of the tile-form line search of one run (all problems of one class).
 struct LineTile {
@@ -452,11 +481,20 @@ struct LineTile {
     float2 *PA = nullptr, *PB = nullptr, *PB2 = nullptr, *Pcol = nullptr;
     PackItem *pack = nullptr;
     int npack = 0;
+    // gradient in tile form (lc.grad): B^H blocks (per (p, j): d x Wg), S regrouped by tile row
+    // (per (p, i): lds x Wg), the partial planes of G2 and G3 (per (p, x): KS planes of d x Wg)
+    int64_t Wg = 0;
+    float2 *PBH = nullptr, *Scol = nullptr, *GA = nullptr, *GBT = nullptr;
+    PackItem *gpack = nullptr;
+    TGradItem *gitems = nullptr;
+    int ngpack = 0, ngitems = 0;
+    size_t gzero_off = 0, gzero_bytes = 0;   // PBH .. Scol, from the region's start
     size_t bytes = 0, zero_bytes = 0;   // zero_bytes: PA .. PB2 (their padding must read as zero)
 };
 
 // Workspace region of the tile-form line search for `nprob` problems of class lc (laid out at base).
 LineTile line_tile_carve(char *base, int nprob, const LineClass &lc, int64_t lds, int npack) {
+    const bool grad = lc.grad;
     LineTile L;
     L.on = true;
     L.lc = lc;
@@ -476,7 +514,23 @@ LineTile line_tile_carve(char *base, int nprob, const LineClass &lc, int64_t lds
     L.PB = L.PA ? L.PA + blk : nullptr;
     L.PB2 = L.PA ? L.PA + 2 * blk : nullptr;
     L.zero_bytes = o;
-    L.Pcol = (float2 *)take((size_t)nprob * lc.nt * lds * L.NA * c8); // per (p, j): lds x NA
+    // the tile gradient's G3 reads Wg columns from the theta half of every row: Wg past the end
+    L.Wg = grad ? grad_tile_width(lc) : 0;
+    const int64_t npc = (int64_t)nprob * lc.nt * lds * L.NA + L.Wg;
+    L.Pcol = (float2 *)take((size_t)npc * c8);                          // per (p, j): lds x NA
+    if (grad) {
+        const int64_t zb = o;   // PBH and Scol: their padding must read as zero
+        L.PBH = (float2 *)take((size_t)nprob * lc.nt * lc.d * L.Wg * c8);
+        L.Scol = (float2 *)take((size_t)nprob * lc.nt * lds * L.Wg * c8);
+        L.gzero_off = zb;
+        L.gzero_bytes = o - zb;
+        L.GA = (float2 *)take((size_t)nprob * lc.nt * GRAD_TILE_KS * lc.d * L.Wg * c8);
+        L.GBT = (float2 *)take((size_t)nprob * lc.nt * GRAD_TILE_KS * lc.d * L.Wg * c8);
+        L.ngpack = nprob * lc.nt * lc.nt;
+        L.ngitems = nprob * lc.nt * lc.nt;
+        L.gpack = (PackItem *)take((size_t)L.ngpack * sizeof(PackItem));
+        L.gitems = (TGradItem *)take((size_t)L.ngitems * sizeof(TGradItem));
+    }
     L.pack = (PackItem *)take((size_t)npack * sizeof(PackItem));
     L.npack = npack;
     L.bytes = o;
@@ -539,6 +593,52 @@ void line_tile_tables(const std::vector<const HostLayout *> &Hs, const std::vect
     }
 }
 
+// Gradient items of a tile range: B^H packing into PBH and the gradient blocks from the G2 / G3 planes.
+void grad_tile_tables(const std::vector<const HostLayout *> &Hs, const std::vector<int64_t> &theta_off,
+                      const LineTile &L, std::vector<PackItem> &pack, std::vector<TGradItem> &items) {
+    const LineClass &lc = L.lc;
+    const int nt = lc.nt, d = lc.d, kp = lc.kpad;
+    const int64_t Wg = L.Wg, plane = (int64_t)d * Wg, blk = GRAD_TILE_KS * plane;
+    for (int64_t p = 0; p < (int64_t)Hs.size(); ++p) {
+        const HostLayout &H = *Hs[p];
+        std::vector<int> tix(nt * nt, -1);
+        for (int i = 0; i < nt; ++i) tix[i * nt + i] = i;
+        for (int i = 0, t = 0; i < nt; ++i)
+            for (int j = 0; j < i; ++j, ++t) tix[i * nt + j] = tix[j * nt + i] = nt + t;
+        const int64_t th = theta_off[p];
+        for (int i = 0; i < nt; ++i)
+            for (int j = 0; j < nt; ++j) {
+                const TileDesc &td = H.tiles[tix[i * nt + j]];
+                const int k = td.k;
+                PackItem b{};   // B_ij^H (d x k) into column block i of PBH_(p, j)
+                b.rows = d; b.cols = k;
+                b.dst = (p * nt + j) * d * Wg + (int64_t)i * kp;
+                b.ldd = Wg;
+                if (i > j) {            // B = R (k x d)
+                    b.op = PACK_CTRANS; b.src = th + td.offB; b.lds = d;
+                } else {                // B = L_ji^T or Q^T: B^H = conj(L_ji), conj(Q) (d x k)
+                    b.op = PACK_CONJ; b.src = th + td.offA; b.lds = k;
+                }
+                pack.push_back(b);
+                if (i < j) continue;
+                // grad A_ij (Q or L: d x k) = H_(p,i)[:, j kp ..]; grad R_ij (k x d) = H_(p,j)[:, i kp ..]^T
+                TGradItem a{};
+                a.rows = d; a.cols = k; a.trans = 0;
+                a.src = (p * nt + i) * blk + (int64_t)j * kp;
+                a.dst = th + td.offA;
+                a.ldd = k;
+                items.push_back(a);
+                if (i == j) continue;
+                TGradItem r{};
+                r.rows = d; r.cols = k; r.trans = 1;
+                r.src = (p * nt + j) * blk + (int64_t)i * kp;
+                r.dst = th + td.offB;
+                r.ldd = d;
+                items.push_back(r);
+            }
+    }
+}
+
 int line_tile_counts(int nprob, const LineClass &lc, int &npack) {
     npack = nprob * lc.nt * lc.nt * 5;
     return 0;
@@ -553,7 +653,7 @@ struct LineSeg {
 };
 
 bool tile_line_requested(int op, const tlrmdd_opts *opts) {
-    return op >= 2 && opts && opts->line_products == TLRMDD_LINE_TILE && opts->precision == TLRMDD_FP32_3M;
+    return op >= 2 && opts && opts->line_products != TLRMDD_LINE_DENSE && opts->precision == TLRMDD_FP32_3M;
 }
 
 // Ranges of the run and the bytes of their tile regions (carved back to back from `base`, or sized
@@ -563,8 +663,11 @@ std::vector<LineSeg> line_segments(int op, int count, const tlrmdd_plan *plans, 
     std::vector<LineSeg> segs;
     std::vector<LineClass> cls(count);
     std::vector<bool> tile(count, false);
-    if (tile_line_requested(op, opts))
-        for (int p = 0; p < count; ++p) tile[p] = line_class(plans[p]->H, cls[p]);
+    for (int p = 0; p < count; ++p) tile[p] = problem_form(op, plans[p]->H, opts, cls[p]);
+    // the adjoint product runs on the problems before the tile-form gradient: those form a suffix
+    int suffix = count;
+    while (suffix > 0 && tile[suffix - 1] && cls[suffix - 1].grad) --suffix;
+    for (int p = 0; p < suffix; ++p) cls[p].grad = false;
     size_t o = 0;
     for (int p = 0; p < count;) {
         int q = p + 1;
@@ -600,7 +703,8 @@ int check_opts(const tlrmdd_opts *o) {
     if (!(o->lambda >= 0.0)) return fail(TLRMDD_INVALID_ARGUMENT, "lambda must be >= 0");
     if (o->resid_refresh < 0) return fail(TLRMDD_INVALID_ARGUMENT, "resid_refresh must be >= 0");
     if (o->streams < 0 || o->streams > MAX_STREAMS) return fail(TLRMDD_INVALID_ARGUMENT, "streams must be in [0, 8]");
-    if (o->line_products != TLRMDD_LINE_DENSE && o->line_products != TLRMDD_LINE_TILE)
+    if (o->line_products != TLRMDD_LINE_DENSE && o->line_products != TLRMDD_LINE_TILE &&
+        o->line_products != TLRMDD_LINE_TILE_GRAD)
         return fail(TLRMDD_INVALID_ARGUMENT, "unknown line_products");
     return TLRMDD_OK;
 }
@@ -655,20 +759,20 @@ std::vector<int> group_members(int g, int G, int count) {
 // Sub-batches of a batched call and the number of streams they run on: `streams` interleaved
 // sub-batches, one per stream (problem i in sub-batch i mod streams, so every sub-batch gets the same
 // mix). With the tile-form line search requested, every sub-batch lists its problems by form (the
-// dense-form problems, then every tile class in order of first appearance), so each form is one
-// range of its run (one launch per phase for the whole sub-batch, a launch per range for the line
-// search products).
+// dense-form problems, then every tile class in order of first appearance, those with the gradient in
+// tile form last), so each form is one range of its run (one launch per phase for the whole
+// sub-batch, a launch per range for the line-search products, the adjoint product on the problems
+// before the tile-form gradient ranges).
 std::vector<std::vector<int>> make_groups(int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts,
                                           int *nstreams) {
     std::vector<std::vector<int>> groups;
-    const bool tile = opts && opts->line_products == TLRMDD_LINE_TILE && opts->precision == TLRMDD_FP32_3M;
-    if (tile) {
+    if (tile_line_requested(2, opts)) {
         std::vector<int> dense;
         std::vector<LineClass> keys;
         std::vector<std::vector<int>> cls;
         for (int i = 0; i < count; ++i) {
             LineClass lc;
-            if (!line_class(plans[i]->H, lc)) {
+            if (!problem_form(2, plans[i]->H, opts, lc)) {
                 dense.push_back(i);
                 continue;
             }
@@ -683,8 +787,10 @@ std::vector<std::vector<int>> make_groups(int count, const tlrmdd_plan *plans, c
         std::vector<int> rank(count);   // position of every problem in form order
         int r = 0;
         for (int i : dense) rank[i] = r++;
-        for (auto &g : cls)
-            for (int i : g) rank[i] = r++;
+        for (int pass = 0; pass < 2; ++pass)   // classes with the dense gradient, then the tile-form gradient
+            for (size_t k = 0; k < cls.size(); ++k)
+                if (keys[k].grad == (pass == 1))
+                    for (int i : cls[k]) rank[i] = r++;
         const int G = stream_groups(opts, count);
         for (int g = 0; g < G; ++g) {
             std::vector<int> m = group_members(g, G, count);
@@ -703,7 +809,7 @@ std::vector<std::vector<int>> make_groups(int count, const tlrmdd_plan *plans, c
 // a batched call splits into sub-batches (streams or tile-form line search)
 bool grouped_call(int count, const tlrmdd_opts *opts) {
     return count > 1 && (stream_groups(opts, count) > 1 ||
-                         (opts->line_products == TLRMDD_LINE_TILE && opts->precision == TLRMDD_FP32_3M));
+                         tile_line_requested(2, opts));
 }
 
 template <typename T> std::vector<T> pick(const T *a, const std::vector<int> &idx) {
@@ -1045,6 +1151,8 @@ struct Run {
     float *z = nullptr, *u = nullptr, *cen = nullptr;
     std::vector<LineSeg> segs;       // line-search form of every problem range
     std::vector<int> asm_first;      // first assembly item of every problem, and the total
+    std::vector<int> grad_first;     // first gradient item of every problem, and the total
+    int n_adj = 0;                   // problems before the tile-form gradient ranges (adjoint product)
 };
 
 // The context of problems p0 .. p0 + np - 1 of a run for the line-search products (complex64 operands
@@ -1054,6 +1162,7 @@ Ctx line_ctx(const Ctx &c, int p0, int np) {
     const int64_t rs = c.lds * c.ldk;
     s.nprob = np;
     s.w.Ds += p0 * rs;
+    if (s.w.DHs) s.w.DHs += p0 * rs;
     s.w.r += p0 * rs;
     s.w.a += p0 * rs;
     s.w.b += p0 * rs;
@@ -1061,24 +1170,36 @@ Ctx line_ctx(const Ctx &c, int p0, int np) {
     return s;
 }
 
-// [a | b] = D [X1 | X2] with the five line-search sums for the problems of a tile range (see LineTile)
-int line_products_tile(Run &R, const LineSeg &sg) {
+// Stage 1 of a tile range: pack the factor blocks of theta and of the direction `dir`, then
+// Pcol_(p,j) = [D_:,i A_dir(ij) ... | D_:,i A_th(ij) ...] (see LineTile)
+int tile_stage1(Run &R, const LineSeg &sg, const float *dir) {
     const Ctx c = line_ctx(R.c, sg.p0, sg.np);
     const LineTile &L = sg.lt;
     const LineClass &lc = L.lc;
     const int64_t NA = L.NA, d = lc.d, nt = lc.nt;
     HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
-        return launch_tlr_pack(L.pack, L.npack, (const float2 *)c.w.th, L.PA, c.s, (const float2 *)c.w.p);
+        return launch_tlr_pack(L.pack, L.npack, (const float2 *)c.w.th, L.PA, c.s, (const float2 *)dir);
     }));
     GemmArgs g1 = gemm_args();   // stage 1: P_(p,i) = D_p[:, i d ...] PA_(p,i)
     g1.A = c.w.Ds; g1.lda = c.ldk; g1.sA = c.lds * c.ldk; g1.sA2 = d;
     g1.B = L.PA; g1.ldb = NA; g1.sB = nt * d * NA; g1.sB2 = d * NA;
     // stored regrouped by tile column: block j of row i -> Pcol_(p,j) at columns i kpad (each half)
     g1.C = L.Pcol; g1.ldc = NA; g1.sC = nt * c.lds * NA; g1.sC2 = lc.kpad;
-    g1.scat_kp = lc.kpad; g1.scat_w = (int)(nt * lc.kpad); g1.scat_js = c.lds * NA - lc.kpad;
+    g1.scat_kp = lc.kpad; g1.scat_w = (int)(nt * lc.kpad); g1.scat_lim = (int)NA; g1.scat_js = c.lds * NA - lc.kpad;
     g1.M = (int)c.lds; g1.N = (int)NA; g1.K = (int)d;
     g1.nz2 = (int)nt;
-    HIP_TRY(timed(TLRMDD_K_LINE_TILE, c.s, [&] { return launch_cgemm3m(GM_STORE, g1, (int)(c.nprob * nt), c.s, true); }));
+    HIP_TRY(timed(TLRMDD_K_LINE_TILE, c.s, [&] { return launch_cgemm3m(GM_STORE, g1, (int)(c.nprob * nt), c.s, GR_TILE); }));
+    return TLRMDD_OK;
+}
+
+// [a | b] = D [X1 | X2] with the five line-search sums for the problems of a tile range (see LineTile)
+int line_products_tile(Run &R, const LineSeg &sg) {
+    int st = tile_stage1(R, sg, R.c.w.p);
+    if (st) return st;
+    const Ctx c = line_ctx(R.c, sg.p0, sg.np);
+    const LineTile &L = sg.lt;
+    const LineClass &lc = L.lc;
+    const int64_t NA = L.NA, d = lc.d, nt = lc.nt;
     GemmArgs g2 = gemm_args();   // stage 2: [a | b]_(p, columns of tile j) = Pcol_(p,j) [PB | PB2]_(p,j)
     g2.A = L.Pcol; g2.lda = NA; g2.sA = nt * c.lds * NA; g2.sA2 = c.lds * NA;
     g2.B = L.PB; g2.B2 = L.PB2; g2.ldb = d; g2.sB = nt * NA * d; g2.sB2 = NA * d;
@@ -1089,7 +1210,63 @@ int line_products_tile(Run &R, const LineSeg &sg) {
     g2.M = (int)c.lds; g2.N = (int)d; g2.K = (int)NA;
     g2.K2 = (int)(nt * lc.kpad);   // b: the direction half of Pcol only
     g2.nz2 = (int)nt;
-    HIP_TRY(timed(TLRMDD_K_LINE_TILE, c.s, [&] { return launch_cgemm3m(GM_LINE, g2, (int)(c.nprob * nt), c.s, true); }));
+    HIP_TRY(timed(TLRMDD_K_LINE_TILE, c.s, [&] { return launch_cgemm3m(GM_LINE, g2, (int)(c.nprob * nt), c.s, GR_TILE); }));
+    return TLRMDD_OK;
+}
+
+// Gradient of the problems of a tile range in tile form (see GRAD_TILE_MAX_COST), into g. Needs the
+// theta half of Pcol for the current theta.
+int tile_gradient(Run &R, const LineSeg &sg, float *g) {
+    const Ctx c = line_ctx(R.c, sg.p0, sg.np);
+    const LineTile &L = sg.lt;
+    const LineClass &lc = L.lc;
+    const int64_t NA = L.NA, d = lc.d, nt = lc.nt, kp = lc.kpad, Wg = L.Wg;
+    const int KS = GRAD_TILE_KS;
+    const int64_t Kc = c.lds / KS;
+    HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
+        return launch_tlr_pack(L.gpack, L.ngpack, (const float2 *)c.w.th, L.PBH, c.s);
+    }));
+    GemmArgs g1 = gemm_args();   // G1: S_(p,j) = r_p[:, j d ...] PBH_(p,j), stored as Scol_(p,i)[:, j kp ...]
+    g1.A = c.w.r; g1.lda = c.ldk; g1.sA = c.lds * c.ldk; g1.sA2 = d;
+    g1.B = L.PBH; g1.ldb = Wg; g1.sB = nt * d * Wg; g1.sB2 = d * Wg;
+    g1.C = L.Scol; g1.ldc = Wg; g1.sC = nt * c.lds * Wg; g1.sC2 = kp;
+    g1.scat_kp = (int)kp; g1.scat_w = (int)(nt * kp); g1.scat_lim = (int)(nt * kp); g1.scat_js = c.lds * Wg - kp;
+    g1.M = (int)c.lds; g1.N = (int)Wg; g1.K = (int)d;
+    g1.nz2 = (int)nt;
+    HIP_TRY(timed(TLRMDD_K_GRAD_TILE, c.s, [&] { return launch_cgemm3m(GM_STORE, g1, (int)(c.nprob * nt), c.s, GR_TILE); }));
+    GemmArgs g2 = gemm_args();   // G2: GA_(p,i,q) = D_p^H[i d ..., q Kc ...] Scol_(p,i)[q Kc ...]
+    g2.A = c.w.DHs; g2.lda = c.lds; g2.sA = c.ldk * c.lds; g2.sA2 = d * c.lds; g2.sA3 = Kc;
+    g2.B = L.Scol; g2.ldb = Wg; g2.sB = nt * c.lds * Wg; g2.sB2 = c.lds * Wg; g2.sB3 = Kc * Wg;
+    g2.C = L.GA; g2.ldc = Wg; g2.sC = nt * KS * d * Wg; g2.sC2 = KS * d * Wg; g2.sC3 = d * Wg;
+    g2.M = (int)d; g2.N = (int)Wg; g2.K = (int)Kc;
+    g2.nz2 = (int)(nt * KS); g2.nz3 = KS;
+    HIP_TRY(timed(TLRMDD_K_GRAD_TILE, c.s, [&] {
+        return launch_cgemm3m(GM_STORE, g2, (int)(c.nprob * nt * KS), c.s, GR_TILE);
+    }));
+    GemmArgs g3 = gemm_args();   // G3: GBT_(p,j,q) = r_p[q Kc ..., j d ...]^T conj(Pcol_th(p,j)[q Kc ...])
+    g3.A = c.w.r; g3.lda = c.ldk; g3.sA = c.lds * c.ldk; g3.sA2 = d; g3.sA3 = Kc * c.ldk;
+    g3.B = L.Pcol + nt * kp; g3.ldb = NA; g3.sB = nt * c.lds * NA; g3.sB2 = c.lds * NA; g3.sB3 = Kc * NA;
+    g3.C = L.GBT; g3.ldc = Wg; g3.sC = nt * KS * d * Wg; g3.sC2 = KS * d * Wg; g3.sC3 = d * Wg;
+    g3.M = (int)d; g3.N = (int)Wg; g3.K = (int)Kc;
+    g3.nz2 = (int)(nt * KS); g3.nz3 = KS;
+    HIP_TRY(timed(TLRMDD_K_GRAD_TILE, c.s, [&] {
+        return launch_cgemm3m(GM_STORE, g3, (int)(c.nprob * nt * KS), c.s, GR_TILE_TA_CB);
+    }));
+    HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
+        return launch_tlr_grad(L.gitems, L.ngitems, L.GA, L.GBT, KS, d * Wg, Wg, (float2 *)g, c.s);
+    }));
+    return TLRMDD_OK;
+}
+
+// After the update theta += step p: the theta half of Pcol follows (P_th += step P_p).
+int tile_pcol_update(Run &R, const LineSeg &sg) {
+    const Ctx c = line_ctx(R.c, sg.p0, sg.np);
+    const LineTile &L = sg.lt;
+    const int64_t nt = L.lc.nt;
+    HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
+        return launch_tlr_paxpy(L.Pcol, (int)(c.nprob * nt), (int)nt, c.lds * L.NA, c.lds, L.NA, nt * L.lc.kpad,
+                                c.w.sc + sg.p0, c.s);
+    }));
     return TLRMDD_OK;
 }
 
@@ -1169,6 +1346,11 @@ int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *c
     if (c.w.bytes + tbytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     R.asm_first = R.T.asm_first;
     R.asm_first.push_back((int)R.T.asm_items.size());
+    R.grad_first = R.T.grad_first;
+    R.grad_first.push_back((int)R.T.grad_items.size());
+    R.n_adj = nprob;
+    for (const LineSeg &sg : R.segs)
+        if (sg.tile && sg.lt.lc.grad) R.n_adj = std::min(R.n_adj, sg.p0);
     bool any_tile = false;
     for (LineSeg &sg : R.segs) {
         if (!sg.tile) continue;
@@ -1185,6 +1367,20 @@ int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *c
             return fail(TLRMDD_UNSUPPORTED, "tile-form line search tables");
         HIP_TRY(hipMemcpyAsync(sg.lt.pack, pack.data(), pack.size() * sizeof(PackItem), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemsetAsync(sg.lt.PA, 0, sg.lt.zero_bytes, s));   // rank padding reads as zero
+        if (sg.lt.lc.grad) {
+            std::vector<PackItem> gpack;
+            std::vector<TGradItem> gitems;
+            grad_tile_tables(Hseg, toff, sg.lt, gpack, gitems);
+            if ((int)gpack.size() != sg.lt.ngpack || (int)gitems.size() > sg.lt.ngitems)
+                return fail(TLRMDD_UNSUPPORTED, "tile-form gradient tables");
+            sg.lt.ngitems = (int)gitems.size();
+            HIP_TRY(hipMemcpyAsync(sg.lt.gpack, gpack.data(), gpack.size() * sizeof(PackItem), hipMemcpyHostToDevice,
+                                   s));
+            HIP_TRY(hipMemcpyAsync(sg.lt.gitems, gitems.data(), gitems.size() * sizeof(TGradItem),
+                                   hipMemcpyHostToDevice, s));
+            // B^H padding and the unused columns of S read as zero
+            HIP_TRY(hipMemsetAsync((char *)sg.lt.PA + sg.lt.gzero_off, 0, sg.lt.gzero_bytes, s));
+        }
     }
     if (any_tile) HIP_TRY(hipStreamSynchronize(s));
     if (R.single) {
@@ -1237,13 +1433,26 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
         HIP_TRY(launch_pen(c.D.tsegs, nt, c.w.th, cen, nullptr, c.w.partials, s));
         if ((st = fin(c, fin_args(FIN_THNORM, c.w.sc), c.D.tcount, 0, 1))) return st;
     }
+    // tile-form gradient ranges: the theta half of Pcol for the current theta (the direction half is
+    // theta too here, and unused)
+    for (const LineSeg &sg : R.segs)
+        if (sg.tile && sg.lt.lc.grad && iters > 0)
+            if ((st = tile_stage1(R, sg, c.w.th))) return st;
     for (int t = 0; t < iters; ++t) {
-        // gradient from the tracked residual (eqs. DXLR)
-        if ((st = gemm_adjoint(c, c.w.r, R.X1, R.xstride))) return st;
-        HIP_TRY(timed(TLRMDD_K_GRAD, s, [&] {
-            return launch_grad(c.D.tiles, c.D.grad_items, c.D.n_grad, c.D.probs, R.X1, (const float2 *)c.w.th,
-                               (float2 *)R.gcur, s);
-        }));
+        // gradient from the tracked residual (eqs. DXLR): W = D^H r and the tile blocks of W' for the
+        // problems before the tile-form gradient ranges, the tile form for those
+        if (R.n_adj > 0) {
+            const Ctx ca = R.n_adj == c.nprob ? c : line_ctx(c, 0, R.n_adj);
+            if ((st = gemm_adjoint(ca, c.w.r, R.X1, R.xstride))) return st;
+            const int ng = (R.single || R.n_adj == c.nprob) ? c.D.n_grad : R.grad_first[R.n_adj];
+            HIP_TRY(timed(TLRMDD_K_GRAD, s, [&] {
+                return launch_grad(c.D.tiles, c.D.grad_items, ng, c.D.probs, R.X1, (const float2 *)c.w.th,
+                                   (float2 *)R.gcur, s);
+            }));
+        }
+        for (const LineSeg &sg : R.segs)
+            if (sg.tile && sg.lt.lc.grad)
+                if ((st = tile_gradient(R, sg, R.gcur))) return st;
         if (lam != 0.0) HIP_TRY(launch_reg_grad(c.D.tsegs, nt, R.gcur, c.w.th, cen, (float)(2.0 * lam), s));
         // direction: steepest descent first, then L-BFGS in vector-free form (Gram pass, two-loop
         // recursion on the (2 m + 1)-term coefficient vectors on the device, one combination pass)
@@ -1290,6 +1499,9 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
         // updates
         HIP_TRY(launch_theta_update(c.D.tsegs, nt, c.w.th, c.w.p, R.lbfgs ? c.w.S : nullptr, R.stride2, cen,
                                     c.w.sc, c.w.partials, s));
+        for (const LineSeg &sg : R.segs)
+            if (sg.tile && sg.lt.lc.grad)
+                if ((st = tile_pcol_update(R, sg))) return st;
         if (lam != 0.0)
             if ((st = fin(c, fin_args(FIN_THNORM, c.w.sc), c.D.tcount, 0, 1))) return st;
         // residual: recomputed from theta every resid_refresh iterations, else updated in place
@@ -1526,17 +1738,6 @@ int ws_bytes_group(int op, int count, const tlrmdd_plan *plans, const tlrmdd_opt
     return TLRMDD_OK;
 }
 
-bool run_line_class(int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, LineClass &lc) {
-    if (!opts || opts->line_products != TLRMDD_LINE_TILE || opts->precision != TLRMDD_FP32_3M) return false;
-    for (int p = 0; p < count; ++p) {
-        LineClass q;
-        if (!line_class(plans[p]->H, q)) return false;
-        if (p == 0) lc = q;
-        else if (!(q == lc)) return false;
-    }
-    return count > 0;
-}
-
 int ws_bytes_grouped(int op, int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, size_t *bytes,
                      std::vector<size_t> *parts) {
     if (count <= 0 || !plans || !bytes) return fail(TLRMDD_INVALID_ARGUMENT, "bad arguments");
@@ -1567,8 +1768,8 @@ int tlrmdd_line_form(tlrmdd_plan plan, const tlrmdd_opts *opts, int *tile_form, 
     int st = check_opts(opts);
     if (st) return st;
     LineClass lc;
-    const bool on = run_line_class(1, &plan, opts, lc);
-    *tile_form = on ? 1 : 0;
+    const bool on = problem_form(2, plan->H, opts, lc);
+    *tile_form = on ? (lc.grad ? 2 : 1) : 0;
     if (kpad) *kpad = on ? lc.kpad : 0;
     return TLRMDD_OK;
 }

@@ -42,18 +42,26 @@ constexpr int BP = BN;                // B plane pitch (floats per k row)
 constexpr int B_PLANE = BK * BP;
 constexpr int STAGE = 2 * A_PLANE + 2 * B_PLANE;   // floats: re and im planes of A and B
 
-// ROLE: 0 = the solver's dense products, 1 = the stages of the tile-form line search (the same code;
-// separate instantiations so that profiles tell the two apart)
+// ROLE (GemmRole): 0 = the solver's dense products, 1 = the stages of the tile-form line search and
+// gradient (the same code; separate instantiations so that profiles tell them apart), 2 = a tile-form
+// gradient stage whose A is given transposed (a K x M source with row pitch lda, read along M like a
+// B tile) and whose B enters conjugated
 template <int MODE, int ROLE>
 __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
     __shared__ float sm[2][STAGE];
 
-    // batch entry: z1 * s + z2 * s2 (two-level batch) or z * s
+    // batch entry: z1 * s + z2 * s2 (two-level batch) or z * s; GM_STORE tile stages may split z2
+    // further into (z2 / nz3, z2 mod nz3) with strides s2, s3
     const int zz = blockIdx.y;
     const int z = g.nz2 > 1 ? zz / g.nz2 : zz;
-    const int z2 = g.nz2 > 1 ? zz % g.nz2 : 0;
-    const float2 *A = g.A + z * g.sA + z2 * g.sA2;
-    const float2 *B = g.B + z * g.sB + z2 * g.sB2;
+    int z2 = g.nz2 > 1 ? zz % g.nz2 : 0;
+    int z3 = 0;
+    if (MODE == GM_STORE && ROLE != 0 && g.nz3 > 1) {
+        z3 = z2 % g.nz3;
+        z2 = z2 / g.nz3;
+    }
+    const float2 *A = g.A + z * g.sA + z2 * g.sA2 + z3 * g.sA3;
+    const float2 *B = g.B + z * g.sB + z2 * g.sB2 + z3 * g.sB3;
 
     // workgroup -> tile: contiguous tile ranges per XCD, grouped by 8 tile rows
     const int nb = gridDim.x;
@@ -86,7 +94,9 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
         __builtin_amdgcn_make_buffer_rsrc((void *)A, (short)0, (int)g.bytesA, 0x00020000);
     const __amdgpu_buffer_rsrc_t rsB =
         __builtin_amdgcn_make_buffer_rsrc((void *)B, (short)0, (int)g.bytesB, 0x00020000);
-    const uint32_t offA = (uint32_t)(((int64_t)(m0 + a_row) * g.lda + 8 * a_q) * 8);
+    constexpr bool TA = ROLE == 2;                 // A source K x M: k row t/16, m 4 (t%16) .. +3, 64 + ..
+    const uint32_t offA = TA ? (uint32_t)(((int64_t)b_row * g.lda + m0 + 4 * b_q) * 8)
+                             : (uint32_t)(((int64_t)(m0 + a_row) * g.lda + 8 * a_q) * 8);
     uint32_t offB[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -103,9 +113,15 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
     float4 ra[4], rb[NBQ][4];
     // b2: this stage also needs the B2 half of the tile (GM_LINE past K2 reads B only)
     auto load = [&](int k0, bool b2) {
-        const uint32_t sa = (uint32_t)k0 * 8u;
+        if (TA) {
+            const uint32_t sa = (uint32_t)((int64_t)k0 * g.lda * 8);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ra[q] = ld16(rsA, offA + 16 * q, sa);
+            for (int q = 0; q < 4; ++q) ra[q] = ld16(rsA, offA + 512 * (q >> 1) + 16 * (q & 1), sa);
+        } else {
+            const uint32_t sa = (uint32_t)k0 * 8u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ra[q] = ld16(rsA, offA + 16 * q, sa);
+        }
 #pragma unroll
         for (int pb = 0; pb < NBQ; ++pb) {
             const uint32_t sb = (uint32_t)((int64_t)(k0 + BR * pb) * g.ldb * 8);
@@ -121,13 +137,24 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
     auto store_lds = [&](int buf, bool b2) {
         float *ar = sm[buf], *ai = ar + A_PLANE;
         float *br = ai + A_PLANE, *bi = br + B_PLANE;
+        if (TA) {   // k row b_row, m = 64 (q / 2) + 4 b_q + 2 (q % 2) + {0, 1}
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int o = (8 * a_q + 2 * q) * AP + a_row;
-            ar[o] = ra[q].x;
-            ai[o] = ra[q].y;
-            ar[o + AP] = ra[q].z;
-            ai[o + AP] = ra[q].w;
+            for (int q = 0; q < 4; ++q) {
+                const int o = b_row * AP + 64 * (q >> 1) + 4 * b_q + 2 * (q & 1);
+                ar[o] = ra[q].x;
+                ai[o] = ra[q].y;
+                ar[o + 1] = ra[q].z;
+                ai[o + 1] = ra[q].w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int o = (8 * a_q + 2 * q) * AP + a_row;
+                ar[o] = ra[q].x;
+                ai[o] = ra[q].y;
+                ar[o + AP] = ra[q].z;
+                ai[o + AP] = ra[q].w;
+            }
         }
 #pragma unroll
         for (int pb = 0; pb < NBQ; ++pb)
@@ -137,7 +164,9 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
                 const float4 *rr = rb[pb];
                 const int ob = (b_row + BR * pb) * BP + 64 * h + 4 * b_q;
                 *reinterpret_cast<float4 *>(br + ob) = make_float4(rr[2 * h].x, rr[2 * h].z, rr[2 * h + 1].x, rr[2 * h + 1].z);
-                *reinterpret_cast<float4 *>(bi + ob) = make_float4(rr[2 * h].y, rr[2 * h].w, rr[2 * h + 1].y, rr[2 * h + 1].w);
+                float4 vi = make_float4(rr[2 * h].y, rr[2 * h].w, rr[2 * h + 1].y, rr[2 * h + 1].w);
+                if (ROLE == 2) vi = make_float4(-vi.x, -vi.y, -vi.z, -vi.w);   // conj(B)
+                *reinterpret_cast<float4 *>(bi + ob) = vi;
             }
     };
 
@@ -230,7 +259,7 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
 
     // ---- epilogue: C = (T1 - T2) + i (T3 - T1 - T2) ----
     __shared__ double red[4][5];
-    float2 *C = g.C + z * g.sC + z2 * g.sC2;
+    float2 *C = g.C + z * g.sC + z2 * g.sC2 + z3 * g.sC3;
     const int64_t ldc = g.ldc;
     auto cval = [&](int i, int j, int r) {
         const float t1 = acc[0][i][j][r], t2 = acc[1][i][j][r], t3 = acc[2][i][j][r];
@@ -243,7 +272,10 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
             for (int j = 0; j < 2; ++j) {
                 const int col = n0 + wn * 64 + 32 * j + j32;
                 int64_t ccol = col;
-                if (ROLE == 1 && g.scat_kp > 0) ccol += (int64_t)((col % g.scat_w) / g.scat_kp) * g.scat_js;
+                if (ROLE != 0 && g.scat_kp > 0) {
+                    if (col >= g.scat_lim) continue;
+                    ccol += (int64_t)((col % g.scat_w) / g.scat_kp) * g.scat_js;
+                }
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int row = m0 + wm * 64 + 32 * i + acc_row(r, lane);
@@ -313,7 +345,10 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
 
 }  // namespace
 
-hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s, bool tile_stage) {
+hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s, int role) {
+    const bool tile_stage = role != GR_DENSE;
+    if (role < GR_DENSE || role > GR_TILE_TA_CB || (role == GR_TILE_TA_CB && mode != GM_STORE))
+        return hipErrorInvalidValue;
     GemmArgs a = a0;
     a.tiles_m = a.M / BM;
     a.tiles_n = (mode == GM_LINE) ? a.N / (BN / 2) : a.N / BN;
@@ -321,10 +356,15 @@ hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s
     if (a.M % BM || a.N % BN || a.K % BK || a.K <= 0) return hipErrorInvalidValue;
     if (a.K2 < 0 || a.K2 > a.K || a.K2 % BK || (a.K2 && !(mode == GM_LINE && tile_stage)))
         return hipErrorInvalidValue;
-    if (a.scat_kp < 0 || (a.scat_kp && (!(mode == GM_STORE && tile_stage) || a.scat_w < a.scat_kp)))
+    if (a.nz3 > 1 && !(mode == GM_STORE && tile_stage && a.nz2 > 1 && a.nz2 % a.nz3 == 0))
         return hipErrorInvalidValue;
-    // byte extents of the buffer resources (32-bit): A is M x lda, B is K x ldb (GM_LINE: B2 follows B)
-    const int64_t bytesA = (int64_t)a.M * a.lda * 8;
+    if (a.scat_kp < 0 || (a.scat_kp && (!(mode == GM_STORE && tile_stage) || a.scat_w < a.scat_kp ||
+                                        a.scat_lim <= 0 || a.scat_lim > a.N)))
+        return hipErrorInvalidValue;
+    // byte extents of the buffer resources (32-bit): A is M x lda (transposed source: K x lda), B is
+    // K x ldb (GM_LINE: B2 follows B)
+    const int64_t bytesA = (int64_t)(role == GR_TILE_TA_CB ? a.K : a.M) * a.lda * 8;
+    if (role == GR_TILE_TA_CB && a.lda < a.M) return hipErrorInvalidValue;
     int64_t bytesB = (int64_t)a.K * a.ldb * 8;
     a.b2_off = 0;
     if (mode == GM_LINE) {
@@ -338,7 +378,8 @@ hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s
     dim3 grid(a.tiles_m * a.tiles_n, batch);
     switch (mode) {
         case GM_STORE:
-            if (tile_stage) hipLaunchKernelGGL((cgemm3m_kernel<GM_STORE, 1>), grid, dim3(256), 0, s, a);
+            if (role == GR_TILE_TA_CB) hipLaunchKernelGGL((cgemm3m_kernel<GM_STORE, 2>), grid, dim3(256), 0, s, a);
+            else if (tile_stage) hipLaunchKernelGGL((cgemm3m_kernel<GM_STORE, 1>), grid, dim3(256), 0, s, a);
             else hipLaunchKernelGGL((cgemm3m_kernel<GM_STORE, 0>), grid, dim3(256), 0, s, a);
             break;
         case GM_RESID: hipLaunchKernelGGL((cgemm3m_kernel<GM_RESID, 0>), grid, dim3(256), 0, s, a); break;

@@ -77,11 +77,19 @@ struct GemmArgs {
     int32_t nz2;
     int32_t K2;                      // GM_LINE: b = A B2 sums over k < K2 only (0: all K; a multiple of 16)
     int64_t sA2, sB2, sC2, sE2, sP2;
-    // GM_STORE tile stage: output column n is stored at column n + ((n mod scat_w) / scat_kp) * scat_js
-    // (scat_kp = 0: plain), which regroups blocks of scat_kp columns across batch entries
-    int32_t scat_kp, scat_w;
+    // third level (GM_STORE): with nz3 > 1 the second-level index z2 splits into z2 / nz3 (strides s2)
+    // and z3 = z2 mod nz3 (strides s3); grid.y = nz * nz2 * nz3
+    int32_t nz3;
+    int64_t sA3, sB3, sC3;
+    // GM_STORE tile stages: output column n < scat_lim is stored at column
+    // n + ((n mod scat_w) / scat_kp) * scat_js, columns from scat_lim on are dropped (scat_kp = 0:
+    // plain), which regroups blocks of scat_kp columns across batch entries
+    int32_t scat_kp, scat_w, scat_lim;
     int64_t scat_js;
 };
+// roles of the three-product kernel: the solver's dense products; the tile-form stages; the same
+// with A given transposed (K x M source, row pitch lda) and B conjugated
+enum GemmRole : int32_t { GR_DENSE = 0, GR_TILE = 1, GR_TILE_TA_CB = 2 };
 constexpr int GEMM_BM = 128;
 constexpr int GEMM_BN = 128;   // complex columns per workgroup (64 of a + 64 of b in GM_LINE)
 constexpr int GEMM_BK = 16;    // complex k per stage
@@ -138,7 +146,7 @@ struct SolveScalars {
 // host launchers (stream ordered)
 hipError_t launch_cgemm(int mode, const GemmArgs &a, int batch, hipStream_t s);
 // the same products in the three-real-product form (FP32 MFMA, interleaved complex64 operands)
-hipError_t launch_cgemm3m(int mode, const GemmArgs &a, int batch, hipStream_t s, bool tile_stage = false);
+hipError_t launch_cgemm3m(int mode, const GemmArgs &a, int batch, hipStream_t s, int role = GR_DENSE);
 int gemm_partials_per_problem(int mode, int M, int N);
 
 // out_bf16 == false: X / X2 are complex64 matrices (ProbOff.x offsets, ld ProbOff.ldx).

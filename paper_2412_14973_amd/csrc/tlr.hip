@@ -33,6 +33,8 @@ __global__ __launch_bounds__(256) void tlr_pack_kernel(const PackItem *__restric
         switch (it.op) {
             case PACK_COPY: v = src[(int64_t)r * it.lds + c]; break;            // src rows x cols
             case PACK_TRANS: v = src[(int64_t)c * it.lds + r]; break;           // src cols x rows
+            case PACK_CONJ: v = src[(int64_t)r * it.lds + c]; v.y = -v.y; break;
+            case PACK_CTRANS: v = src[(int64_t)c * it.lds + r]; v.y = -v.y; break;
             case PACK_IDENT: v = make_float2(r == c ? 1.f : 0.f, 0.f); break;
             default: {                                                           // (Z + Z^T)/2
                 const float2 a = src[(int64_t)r * it.lds + c], b = src[(int64_t)c * it.lds + r];
@@ -53,7 +55,84 @@ __global__ __launch_bounds__(256) void tlr_gather_kernel(const GatherItem *__res
             Pcol[it.dst + s * it.ldd + c] = P[it.src + s * it.lds + c];
 }
 
+// Gradient blocks of the tile form from the partial planes of its two products (fixed summation
+// order: the H1 planes, then the H2 planes). Non-transposed blocks run along c (contiguous in H and
+// g), transposed ones along r (contiguous in g).
+__global__ __launch_bounds__(256) void tlr_grad_kernel(const TGradItem *__restrict__ items,
+                                                       const float2 *__restrict__ H1,
+                                                       const float2 *__restrict__ H2, int nparts,
+                                                       int64_t part_stride, int64_t ldh,
+                                                       float2 *__restrict__ g) {
+    const TGradItem it = items[blockIdx.x];
+    const int64_t n = (int64_t)it.rows * it.cols;
+    for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.y * blockDim.x) {
+        int r, c;
+        if (it.trans) {
+            c = (int)(e / it.rows);
+            r = (int)(e % it.rows);
+        } else {
+            r = (int)(e / it.cols);
+            c = (int)(e % it.cols);
+        }
+        const int64_t h = it.src + (int64_t)r * ldh + c;
+        float sx = 0.f, sy = 0.f;
+        for (int q = 0; q < nparts; ++q) {
+            const float2 v = H1[h + q * part_stride];
+            sx += v.x;
+            sy += v.y;
+        }
+        for (int q = 0; q < nparts; ++q) {
+            const float2 v = H2[h + q * part_stride];
+            sx += v.x;
+            sy += v.y;
+        }
+        const int64_t o = it.trans ? it.dst + (int64_t)c * it.ldd + r : it.dst + (int64_t)r * it.ldd + c;
+        g[o] = make_float2(sx, sy);
+    }
+}
+
+// Pcol theta half += step * direction half (float4 = two complex per thread; half_cols and ld even)
+__global__ __launch_bounds__(256) void tlr_paxpy_kernel(float2 *__restrict__ Pcol, int nt, int64_t entry_stride,
+                                                        int64_t rows, int64_t ld, int64_t half_cols,
+                                                        const SolveScalars *__restrict__ sc) {
+    const int e = blockIdx.x;
+    const SolveScalars &st = sc[e / nt];
+    if (st.frozen) return;   // theta was not updated
+    const float a = (float)st.step;
+    float2 *base = Pcol + e * entry_stride;
+    const int64_t h = half_cols >> 1;   // float4 per row and half
+    const int64_t n = rows * h;
+    for (int64_t i = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.y * blockDim.x) {
+        const int64_t row = i / h, c2 = i - row * h;
+        const float4 pv = *reinterpret_cast<const float4 *>(base + row * ld + 2 * c2);
+        float4 *tp = reinterpret_cast<float4 *>(base + row * ld + half_cols + 2 * c2);
+        float4 tv = *tp;
+        tv.x += a * pv.x;
+        tv.y += a * pv.y;
+        tv.z += a * pv.z;
+        tv.w += a * pv.w;
+        *tp = tv;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_tlr_grad(const TGradItem *items, int nitems, const float2 *H1, const float2 *H2, int nparts,
+                           int64_t part_stride, int64_t ldh, float2 *g, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tlr_grad_kernel, dim3((unsigned)nitems, 8), dim3(256), 0, s, items, H1, H2, nparts,
+                       part_stride, ldh, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_tlr_paxpy(float2 *Pcol, int nentries, int nt, int64_t entry_stride, int64_t rows, int64_t ld,
+                            int64_t half_cols, const SolveScalars *sc, hipStream_t s) {
+    if (nentries <= 0 || rows <= 0) return hipSuccess;
+    if ((half_cols & 1) || (ld & 1) || (entry_stride & 1)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(tlr_paxpy_kernel, dim3((unsigned)nentries, 16), dim3(256), 0, s, Pcol, nt, entry_stride,
+                       rows, ld, half_cols, sc);
+    return hipGetLastError();
+}
 
 hipError_t launch_tlr_pack(const PackItem *items, int nitems, const float2 *theta, float2 *dst, hipStream_t s,
                            const float2 *theta2) {

@@ -102,15 +102,18 @@ def bench_inputs(tl):
     return wl, plans, Ds, Us, ths, sample
 
 
-# the bench's default line runs the three-product form on one stream; with the tile-form line
-# search the batch splits into sub-batches by form (frequencies 0 and 21 take the tile form)
+# the bench's default line runs the three-product form on one stream with the line search in tile form
+# where cheaper (frequencies 0 and 21 of the sample) and the gradient in tile form where cheaper
+# (frequency 0: tile 256)
 @pytest.mark.parametrize("precision_name,line", [("FP32_3M", "LINE_DENSE"), ("FP32", "LINE_DENSE"),
-                                                 ("FP32_3M", "LINE_TILE")])
+                                                 ("FP32_3M", "LINE_TILE"), ("FP32_3M", "LINE_TILE_GRAD")])
 def test_batched_bench_configuration_sampled(tl, bench_inputs, precision_name, line):
     wl, plans, Ds, Us, ths, sample = bench_inputs
     iters = 3
     if line == "LINE_TILE":
-        assert [tl.line_form(plans[i])[0] for i in sample] == [True, True, False, False]
+        assert [tl.line_form(plans[i])[0] for i in sample] == [1, 1, 0, 0]
+    if line == "LINE_TILE_GRAD":
+        assert [tl.line_form(plans[i], line_products=tl.LINE_TILE_GRAD)[0] for i in sample] == [2, 1, 0, 0]
     thT, fh = tl.solve_batched(plans, Ds, Us, ths, iters, precision=getattr(tl, precision_name),
                                line_products=getattr(tl, line))
     torch.cuda.synchronize()

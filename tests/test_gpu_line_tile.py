@@ -112,3 +112,81 @@ def test_tile_admm_vs_oracle(tl):
     rel_h = np.max(np.abs(fh.cpu().numpy() - ref.f_hist) / ref.f_hist)
     print(f"tile admm: rel_f {rf:.2e} rel_X {rx:.2e} rel_theta {rt:.2e} f_hist {rel_h:.2e}", flush=True)
     assert rf <= FP32_TOL and rx <= FP32_TOL and rt <= FP32_TOL and rel_h <= FP32_TOL
+
+
+# ---- gradient in tile form (line_products = LINE_TILE_GRAD) -------------------------------------------
+# Its three products cost 3 Wg / nr of the adjoint product (Wg = nt kpad rounded up to 128), so it needs
+# nr = 1024 here: 32 x 32 receivers, sources on every other line (ns = 512), four tiles of 256.
+
+def _case_nr1024(seed, k_off, k_diag, name, tiles=(256,) * 4):
+    nt = len(tiles)
+    lay = synth.Layout(np.array(tiles), np.full(nt * (nt - 1) // 2, k_off), np.array(k_diag))
+    return from_geometry(32, 32, "half", 12.0, lay, seed, name)
+
+
+def test_tile_grad_form_query(tl):
+    plan = to_device(_case_nr1024(21, 12, [9, 14, 5, 16], "g"), tl, torch)[0]
+    assert tl.line_form(plan, line_products=tl.LINE_TILE_GRAD) == (2, 16)     # 3 * 128 / 1024 <= 0.6
+    assert tl.line_form(plan, line_products=tl.LINE_TILE) == (1, 16)
+    q8 = to_device(_case_nr1024(22, 20, [20] * 8, "q8", tiles=(128,) * 8), tl, torch)[0]
+    assert tl.line_form(q8, line_products=tl.LINE_TILE_GRAD) == (1, 24)       # Wg 256: 0.75 of the adjoint
+
+
+@pytest.mark.parametrize("k_off", [6, 16])
+def test_tile_grad_solve_vs_oracle(tl, k_off):
+    case = _case_nr1024(23 + k_off, k_off, [4, k_off, 9, 12], f"g{k_off}")
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    iters = 8
+    thg, fh = tl.solve(plan, D, U, th, iters=iters, precision=tl.FP32_3M, line_products=tl.LINE_TILE_GRAD)
+    torch.cuda.synchronize()
+    ref = O.solve(case.T, case.D, case.U, case.theta, iters=iters)
+    rf, rx, rt = _metrics(case, thg.cpu().numpy().astype(np.complex128), ref.theta)
+    rel_h = np.max(np.abs(fh.cpu().numpy() - ref.f_hist) / ref.f_hist)
+    print(f"tile gradient k_off {k_off}: rel_f {rf:.2e} rel_X {rx:.2e} rel_theta {rt:.2e} f_hist {rel_h:.2e}",
+          flush=True)
+    assert rf <= FP32_TOL and rx <= FP32_TOL and rt <= FP32_TOL and rel_h <= FP32_TOL
+
+
+def test_tile_grad_first_gradient_vs_oracle(tl):
+    """One iteration from theta0: the step is the exact line search along -g(theta0), so theta_1
+    pins the tile-form gradient itself (theta_1 - theta0 = -alpha g) against the oracle's."""
+    case = _case_nr1024(31, 10, [7, 10, 3, 16], "g1")
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    thg, _ = tl.solve(plan, D, U, th, iters=1, precision=tl.FP32_3M, line_products=tl.LINE_TILE_GRAD)
+    torch.cuda.synchronize()
+    ref = O.solve(case.T, case.D, case.U, case.theta, iters=1)
+    step_g = thg.cpu().numpy().astype(np.complex128) - case.theta
+    step_o = ref.theta - case.theta
+    rel = np.linalg.norm(step_g - step_o) / np.linalg.norm(step_o)
+    print(f"tile gradient first step: rel {rel:.2e}", flush=True)
+    assert rel <= FP32_TOL
+
+
+@pytest.mark.parametrize("streams", [1, 2])
+def test_tile_grad_batched_match_single(tl, streams):
+    """Problems with the tile-form gradient, a tile class whose gradient stays dense and a dense-form
+    problem, interleaved: every problem equals its single-problem solve bit for bit."""
+    cases = [_case_nr1024(41, 12, [9, 14, 5, 16], "g_a"), _case_nr1024(42, 3, [-1, 4, 5, 6], "dense"),
+             _case_nr1024(43, 20, [20] * 8, "q8", tiles=(128,) * 8), _case_nr1024(44, 5, [3, 4, 5, 6], "g_b")]
+    devs = [to_device(c, tl, torch) for c in cases]
+    kw = dict(iters=5, precision=tl.FP32_3M, line_products=tl.LINE_TILE_GRAD)
+    assert [tl.line_form(d[0], line_products=tl.LINE_TILE_GRAD)[0] for d in devs] == [2, 0, 1, 2]
+    th_b, fh_b = tl.solve_batched([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs],
+                                  [d[3] for d in devs], streams=streams, **kw)
+    singles = [tl.solve(d[0], d[1], d[2], d[3], **kw) for d in devs]
+    torch.cuda.synchronize()
+    for (ts, fs), tb, fb in zip(singles, th_b, fh_b):
+        assert torch.equal(ts, tb) and torch.equal(fs, fb)
+
+
+def test_tile_grad_admm_vs_oracle(tl):
+    case = _case_nr1024(51, 8, [6, 8, 10, 12], "gadmm")
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    kw = dict(lams=(1.0, 0.1), outer=2, inner=4, rho=1.0)
+    thg, fh = tl.admm(plan, D, U, th, precision=tl.FP32_3M, line_products=tl.LINE_TILE_GRAD, **kw)
+    torch.cuda.synchronize()
+    ref = O.admm(case.T, case.D, case.U, case.theta, **kw)
+    rf, rx, rt = _metrics(case, thg.cpu().numpy().astype(np.complex128), ref.theta)
+    rel_h = np.max(np.abs(fh.cpu().numpy() - ref.f_hist) / ref.f_hist)
+    print(f"tile gradient admm: rel_f {rf:.2e} rel_X {rx:.2e} rel_theta {rt:.2e} f_hist {rel_h:.2e}", flush=True)
+    assert rf <= FP32_TOL and rx <= FP32_TOL and rt <= FP32_TOL and rel_h <= FP32_TOL

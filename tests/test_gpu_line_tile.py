@@ -190,3 +190,35 @@ def test_tile_grad_admm_vs_oracle(tl):
     rel_h = np.max(np.abs(fh.cpu().numpy() - ref.f_hist) / ref.f_hist)
     print(f"tile gradient admm: rel_f {rf:.2e} rel_X {rx:.2e} rel_theta {rt:.2e} f_hist {rel_h:.2e}", flush=True)
     assert rf <= FP32_TOL and rx <= FP32_TOL and rt <= FP32_TOL and rel_h <= FP32_TOL
+
+
+def test_tile_grad_long_solve_with_lambda_vs_oracle(tl):
+    """25 iterations (the residual is recomputed from theta at iteration 20) with the Frobenius term
+    lam ||theta||^2: the tile-form gradient plus the regulariser's gradient, P_theta carried through 25
+    updates."""
+    case = _case_nr1024(61, 10, [8, 12, 6, 10], "glong")
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    iters, lam = 25, 0.05
+    thg, fh = tl.solve(plan, D, U, th, iters=iters, precision=tl.FP32_3M, lam=lam,
+                       line_products=tl.LINE_TILE_GRAD)
+    torch.cuda.synchronize()
+    ref = O.solve(case.T, case.D, case.U, case.theta, iters=iters, lam=lam)
+    rf, rx, rt = _metrics(case, thg.cpu().numpy().astype(np.complex128), ref.theta)
+    rel_h = np.max(np.abs(fh.cpu().numpy() - ref.f_hist) / ref.f_hist)
+    print(f"tile gradient 25 iterations, lam {lam}: rel_f {rf:.2e} rel_X {rx:.2e} rel_theta {rt:.2e} "
+          f"f_hist {rel_h:.2e}", flush=True)
+    assert rf <= FP32_TOL and rx <= FP32_TOL and rt <= FP32_TOL and rel_h <= FP32_TOL
+
+
+@pytest.mark.parametrize("streams", [1, 2])
+def test_tile_grad_admm_batched_match_single(tl, streams):
+    cases = [_case_nr1024(71, 12, [9, 14, 5, 16], "g_a"), _case_nr1024(72, 3, [-1, 4, 5, 6], "dense"),
+             _case_nr1024(73, 5, [3, 4, 5, 6], "g_b")]
+    devs = [to_device(c, tl, torch) for c in cases]
+    kw = dict(lams=(1.0, 0.1), outer=2, inner=3, rho=1.0, precision=tl.FP32_3M, line_products=tl.LINE_TILE_GRAD)
+    th_b, fh_b = tl.admm_batched([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs],
+                                 [d[3] for d in devs], streams=streams, **kw)
+    singles = [tl.admm(d[0], d[1], d[2], d[3], **kw) for d in devs]
+    torch.cuda.synchronize()
+    for (ts, fs), tb, fb in zip(singles, th_b, fh_b):
+        assert torch.equal(ts, tb) and torch.equal(fs, fb)

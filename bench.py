@@ -340,7 +340,8 @@ def estimate(tl, torch, args):
 
 def error_table(tl, torch, args):
     """Mixed-precision error table on the 64 x 64-receiver problem (nr 4096, ns 2048,
-    tile 256, rank 32) at 10 and 30 dB: FP32 and BF16x3 solves against the FP64 oracle."""
+    tile 256, rank 32) at 10 and 30 dB: FP32 and BF16x3 solves (and the three-product FP32 solve
+    with the tile-form line search and gradient) against the FP64 oracle."""
     import numpy as np
 
     import oracle as O
@@ -348,10 +349,12 @@ def error_table(tl, torch, args):
     iters = args.iters or 100
     rows = []
     R = args.resid_refresh
-    variants = [("fp32", tl.FP32, 0), ("bf16x3", tl.BF16X3, 0)]
+    dense = tl.LINE_DENSE
+    variants = [("fp32", tl.FP32, 0, dense), ("bf16x3", tl.BF16X3, 0, dense)]
     if R > 0:
-        variants += [(f"fp32_refresh{R}", tl.FP32, R), (f"bf16x3_refresh{R}", tl.BF16X3, R),
-                     (f"fp32_3m_refresh{R}", tl.FP32_3M, R)]
+        variants += [(f"fp32_refresh{R}", tl.FP32, R, dense), (f"bf16x3_refresh{R}", tl.BF16X3, R, dense),
+                     (f"fp32_3m_refresh{R}", tl.FP32_3M, R, dense),
+                     (f"fp32_3m_tile_forms_refresh{R}", tl.FP32_3M, R, tl.LINE_TILE_GRAD)]
     for snr in [float(v) for v in args.error_snrs.split(",")]:
         wl = synth.large(snr_db=snr, config_id=4)
         f_idx = 10
@@ -370,10 +373,10 @@ def error_table(tl, torch, args):
         th = torch.from_numpy(th64).to(dev)
         plan = tl.Plan.from_layout(lay, geom.ns)
         res = {}
-        for name, prec, refresh in variants:
+        for name, prec, refresh, line in variants:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            thT, fh = tl.solve(plan, D, U, th, iters, precision=prec, resid_refresh=refresh)
+            thT, fh = tl.solve(plan, D, U, th, iters, precision=prec, resid_refresh=refresh, line_products=line)
             torch.cuda.synchronize()
             res[name] = (thT.cpu().numpy().astype(np.complex128), time.perf_counter() - t0)
             log(f"snr {snr}: {name} solve {res[name][1]:.2f} s")
@@ -559,14 +562,18 @@ def main():
         kernels[k] = entry
     # the roofline kernel: the product kind with the most algorithmic flops (with the tile-form line
     # search the dense line product of the remaining frequencies and the adjoint take about equal time)
-    gemm_kinds = [k for k in ("gemm_line", "gemm_adjoint") if kt.launches[k] > 0]
+    # (all frequencies in tile form: the tile-form stages)
+    gemm_kinds = [k for k in ("gemm_line", "gemm_adjoint") if kt.launches[k] > 0] or \
+        [k for k in ("line_tile", "grad_tile") if kt.launches[k] > 0]
     dom_kind = max(gemm_kinds, key=lambda k: total_flops[k])
     dom = kernels[dom_kind]
     achieved = dom["tflops"] * 1e12
     peak = PEAK[peak_name]
-    dom_probs = (n_dense if dom_kind == "gemm_line" else nfreq - n_tgrad) * steps_iters / kt.launches[dom_kind]
-    dom_name = (line_kernel + " ([a|b] = D [X1|X2])" if dom_kind == "gemm_line"
-                else adjoint_kernel + " (W = D^H r)")
+    dom_probs = {"gemm_line": n_dense, "gemm_adjoint": nfreq - n_tgrad, "line_tile": n_tile,
+                 "grad_tile": n_tgrad}[dom_kind] * steps_iters / kt.launches[dom_kind]
+    dom_name = {"gemm_line": line_kernel + " ([a|b] = D [X1|X2])", "gemm_adjoint": adjoint_kernel + " (W = D^H r)",
+                "line_tile": "cgemm3m_kernel<GM_STORE|GM_LINE, 1> (tile-form line-search stages)",
+                "grad_tile": "cgemm3m_kernel<GM_STORE, 1|2> (tile-form gradient products)"}[dom_kind]
     gemm_flops = sum(total_flops[k] for k in total_flops)
     gemm_s = sum(kt.ms[k] for k in total_flops) * 1e-3
     mode = ("tile_grad" if n_tgrad else "tile") if n_tile else "dense"
@@ -600,7 +607,8 @@ def main():
                      "executed_frac": exec_factor * achieved / peak,
                      "traffic": (measured_traffic(nfreq, args.workload, args.precision, mode, dom_kind)
                                  if nstreams == 1 else None),
-                     "algorithmic_bytes": bytes_per_prob[dom_kind] * dom_probs,
+                     "algorithmic_bytes": (bytes_per_prob[dom_kind] * dom_probs if dom_kind in bytes_per_prob
+                                           else None),
                      "problems_per_launch": dom_probs,
                      **({"note": "launches of the %d sub-batches overlap in time: a launch's duration includes "
                                  "the sharing of the GPU" % nstreams} if nstreams > 1 else {})},

@@ -424,7 +424,8 @@ struct LineClass {
 //   G1: S_j = r_:,j [B_0j^H | B_1j^H | ...], stored regrouped by tile row (Scol_i = [S_i0 | S_i1 | ...]);
 //   G2: GA_i = D_:,i^H Scol_i;   G3: GBT_j = r_:,j^T conj(P_th(:,j)), with P_th(ij) = D_:,i A_ij the theta
 //   half of the line search's stage 1 (carried to the updated theta by P_th += step P_p);
-// G2 and G3 split their ns-long contraction in GRAD_TILE_KS parts, and
+// G2 and G3 split their ns-long contraction in GRAD_TILE_KS parts and run as one launch (G2 as its
+// conjugate, D^T conj(Scol), in the transposed-A / conjugated-B role of G3), and
 //   grad A_ij = GA_i[:, j kpad ..] + GBT_i[:, j kpad ..],  grad B_ij = (GA_j[:, i kpad ..] + GBT_j[:, i kpad ..])^T
 // summed over the parts (Q: A = Q, B = Q^T; L, R: the pair (i > j) and its transpose (j, i)).
 // Flops: 3 Wg / nr of the adjoint product D^H r.
@@ -482,7 +483,8 @@ struct LineTile {
     PackItem *pack = nullptr;
     int npack = 0;
     // gradient in tile form (lc.grad): B^H blocks (per (p, j): d x Wg), S regrouped by tile row
-    // (per (p, i): lds x Wg), the partial planes of G2 and G3 (per (p, x): KS planes of d x Wg)
+    // (per (p, i): lds x NA, Wg columns used), the partial planes of G2 and G3 (per (p, x): KS planes
+    // of d x Wg)
     int64_t Wg = 0;
     float2 *PBH = nullptr, *Scol = nullptr, *GA = nullptr, *GBT = nullptr;
     PackItem *gpack = nullptr;
@@ -521,7 +523,7 @@ LineTile line_tile_carve(char *base, int nprob, const LineClass &lc, int64_t lds
     if (grad) {
         const int64_t zb = o;   // PBH and Scol: their padding must read as zero
         L.PBH = (float2 *)take((size_t)nprob * lc.nt * lc.d * L.Wg * c8);
-        L.Scol = (float2 *)take((size_t)nprob * lc.nt * lds * L.Wg * c8);
+        L.Scol = (float2 *)take((size_t)nprob * lc.nt * lds * L.NA * c8);   // row pitch NA, like Pcol
         L.gzero_off = zb;
         L.gzero_bytes = o - zb;
         L.GA = (float2 *)take((size_t)nprob * lc.nt * GRAD_TILE_KS * lc.d * L.Wg * c8);
@@ -1178,7 +1180,7 @@ int tile_stage1(Run &R, const LineSeg &sg, const float *dir) {
     const LineClass &lc = L.lc;
     const int64_t NA = L.NA, d = lc.d, nt = lc.nt;
     HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
-        return launch_tlr_pack(L.pack, L.npack, (const float2 *)c.w.th, L.PA, c.s, (const float2 *)dir);
+        return launch_tlr_pack(L.pack, L.npack, (const float2 *)c.w.th, L.PA, c.s, (const float2 *)dir, 2);
     }));
     GemmArgs g1 = gemm_args();   // stage 1: P_(p,i) = D_p[:, i d ...] PA_(p,i)
     g1.A = c.w.Ds; g1.lda = c.ldk; g1.sA = c.lds * c.ldk; g1.sA2 = d;
@@ -1224,36 +1226,32 @@ int tile_gradient(Run &R, const LineSeg &sg, float *g) {
     const int KS = GRAD_TILE_KS;
     const int64_t Kc = c.lds / KS;
     HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
-        return launch_tlr_pack(L.gpack, L.ngpack, (const float2 *)c.w.th, L.PBH, c.s);
+        return launch_tlr_pack(L.gpack, L.ngpack, (const float2 *)c.w.th, L.PBH, c.s, nullptr, 2);
     }));
     GemmArgs g1 = gemm_args();   // G1: S_(p,j) = r_p[:, j d ...] PBH_(p,j), stored as Scol_(p,i)[:, j kp ...]
     g1.A = c.w.r; g1.lda = c.ldk; g1.sA = c.lds * c.ldk; g1.sA2 = d;
     g1.B = L.PBH; g1.ldb = Wg; g1.sB = nt * d * Wg; g1.sB2 = d * Wg;
-    g1.C = L.Scol; g1.ldc = Wg; g1.sC = nt * c.lds * Wg; g1.sC2 = kp;
-    g1.scat_kp = (int)kp; g1.scat_w = (int)(nt * kp); g1.scat_lim = (int)(nt * kp); g1.scat_js = c.lds * Wg - kp;
+    g1.C = L.Scol; g1.ldc = NA; g1.sC = nt * c.lds * NA; g1.sC2 = kp;
+    g1.scat_kp = (int)kp; g1.scat_w = (int)(nt * kp); g1.scat_lim = (int)(nt * kp); g1.scat_js = c.lds * NA - kp;
     g1.M = (int)c.lds; g1.N = (int)Wg; g1.K = (int)d;
     g1.nz2 = (int)nt;
     HIP_TRY(timed(TLRMDD_K_GRAD_TILE, c.s, [&] { return launch_cgemm3m(GM_STORE, g1, (int)(c.nprob * nt), c.s, GR_TILE); }));
-    GemmArgs g2 = gemm_args();   // G2: GA_(p,i,q) = D_p^H[i d ..., q Kc ...] Scol_(p,i)[q Kc ...]
-    g2.A = c.w.DHs; g2.lda = c.lds; g2.sA = c.ldk * c.lds; g2.sA2 = d * c.lds; g2.sA3 = Kc;
-    g2.B = L.Scol; g2.ldb = Wg; g2.sB = nt * c.lds * Wg; g2.sB2 = c.lds * Wg; g2.sB3 = Kc * Wg;
-    g2.C = L.GA; g2.ldc = Wg; g2.sC = nt * KS * d * Wg; g2.sC2 = KS * d * Wg; g2.sC3 = d * Wg;
-    g2.M = (int)d; g2.N = (int)Wg; g2.K = (int)Kc;
-    g2.nz2 = (int)(nt * KS); g2.nz3 = KS;
-    HIP_TRY(timed(TLRMDD_K_GRAD_TILE, c.s, [&] {
-        return launch_cgemm3m(GM_STORE, g2, (int)(c.nprob * nt * KS), c.s, GR_TILE);
-    }));
-    GemmArgs g3 = gemm_args();   // G3: GBT_(p,j,q) = r_p[q Kc ..., j d ...]^T conj(Pcol_th(p,j)[q Kc ...])
-    g3.A = c.w.r; g3.lda = c.ldk; g3.sA = c.lds * c.ldk; g3.sA2 = d; g3.sA3 = Kc * c.ldk;
+    // G2 and G3 in one launch of the transposed-A / conjugated-B role, per (p, tile x, part q):
+    //   set 0: GBT_(p,x,q) = r_p[q Kc ..., x d ...]^T conj(Pcol_th(p,x)[q Kc ...])
+    //   set 1: conj(GA_(p,x,q)) = D_p[q Kc ..., x d ...]^T conj(Scol_(p,x)[q Kc ...])
+    // (the same strides: D and r, Pcol and Scol share their layouts)
+    GemmArgs g3 = gemm_args();
+    g3.A = c.w.r; g3.lda = c.ldk; g3.sA = c.lds * c.ldk; g3.sA2 = d; g3.sA3 = Kc * c.ldk; g3.sA4 = c.w.Ds - c.w.r;
     g3.B = L.Pcol + nt * kp; g3.ldb = NA; g3.sB = nt * c.lds * NA; g3.sB2 = c.lds * NA; g3.sB3 = Kc * NA;
-    g3.C = L.GBT; g3.ldc = Wg; g3.sC = nt * KS * d * Wg; g3.sC2 = KS * d * Wg; g3.sC3 = d * Wg;
+    g3.sB4 = L.Scol - (L.Pcol + nt * kp);
+    g3.C = L.GBT; g3.ldc = Wg; g3.sC = nt * KS * d * Wg; g3.sC2 = KS * d * Wg; g3.sC3 = d * Wg; g3.sC4 = L.GA - L.GBT;
     g3.M = (int)d; g3.N = (int)Wg; g3.K = (int)Kc;
-    g3.nz2 = (int)(nt * KS); g3.nz3 = KS;
+    g3.nz2 = (int)(nt * KS * 2); g3.nz3 = KS; g3.nz4 = 2;
     HIP_TRY(timed(TLRMDD_K_GRAD_TILE, c.s, [&] {
-        return launch_cgemm3m(GM_STORE, g3, (int)(c.nprob * nt * KS), c.s, GR_TILE_TA_CB);
+        return launch_cgemm3m(GM_STORE, g3, (int)(c.nprob * nt * KS * 2), c.s, GR_TILE_TA_CB);
     }));
     HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
-        return launch_tlr_grad(L.gitems, L.ngitems, L.GA, L.GBT, KS, d * Wg, Wg, (float2 *)g, c.s);
+        return launch_tlr_grad(L.gitems, L.ngitems, L.GA, L.GBT, KS, d * Wg, Wg, true, (float2 *)g, c.s);
     }));
     return TLRMDD_OK;
 }

@@ -24,6 +24,7 @@
 //     and r meet in one thread.
 // Epilogues as the four-product kernel: C; C = AB - U with FP64 partial sums of
 // |C|^2; a, b with the five line-search sums. K must be a multiple of 16.
+#include <algorithm>
 #include <type_traits>
 
 #include "gemm_common.hpp"
@@ -51,17 +52,23 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
     __shared__ float sm[2][STAGE];
 
     // batch entry: z1 * s + z2 * s2 (two-level batch) or z * s; GM_STORE tile stages may split z2
-    // further into (z2 / nz3, z2 mod nz3) with strides s2, s3
+    // further into operand sets (z4, strides s4) and contraction parts (z3, strides s3)
     const int zz = blockIdx.y;
     const int z = g.nz2 > 1 ? zz / g.nz2 : zz;
     int z2 = g.nz2 > 1 ? zz % g.nz2 : 0;
-    int z3 = 0;
-    if (MODE == GM_STORE && ROLE != 0 && g.nz3 > 1) {
-        z3 = z2 % g.nz3;
-        z2 = z2 / g.nz3;
+    int z3 = 0, z4 = 0;
+    if (MODE == GM_STORE && ROLE != 0) {
+        if (g.nz4 > 1) {
+            z4 = z2 % g.nz4;
+            z2 = z2 / g.nz4;
+        }
+        if (g.nz3 > 1) {
+            z3 = z2 % g.nz3;
+            z2 = z2 / g.nz3;
+        }
     }
-    const float2 *A = g.A + z * g.sA + z2 * g.sA2 + z3 * g.sA3;
-    const float2 *B = g.B + z * g.sB + z2 * g.sB2 + z3 * g.sB3;
+    const float2 *A = g.A + z * g.sA + z2 * g.sA2 + z3 * g.sA3 + z4 * g.sA4;
+    const float2 *B = g.B + z * g.sB + z2 * g.sB2 + z3 * g.sB3 + z4 * g.sB4;
 
     // workgroup -> tile: contiguous tile ranges per XCD, grouped by 8 tile rows
     const int nb = gridDim.x;
@@ -259,7 +266,7 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
 
     // ---- epilogue: C = (T1 - T2) + i (T3 - T1 - T2) ----
     __shared__ double red[4][5];
-    float2 *C = g.C + z * g.sC + z2 * g.sC2 + z3 * g.sC3;
+    float2 *C = g.C + z * g.sC + z2 * g.sC2 + z3 * g.sC3 + z4 * g.sC4;
     const int64_t ldc = g.ldc;
     auto cval = [&](int i, int j, int r) {
         const float t1 = acc[0][i][j][r], t2 = acc[1][i][j][r], t3 = acc[2][i][j][r];
@@ -356,8 +363,10 @@ hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s
     if (a.M % BM || a.N % BN || a.K % BK || a.K <= 0) return hipErrorInvalidValue;
     if (a.K2 < 0 || a.K2 > a.K || a.K2 % BK || (a.K2 && !(mode == GM_LINE && tile_stage)))
         return hipErrorInvalidValue;
-    if (a.nz3 > 1 && !(mode == GM_STORE && tile_stage && a.nz2 > 1 && a.nz2 % a.nz3 == 0))
-        return hipErrorInvalidValue;
+    if (a.nz3 > 1 || a.nz4 > 1) {
+        const int64_t inner = (int64_t)std::max(1, a.nz3) * std::max(1, a.nz4);
+        if (!(mode == GM_STORE && tile_stage && a.nz2 > 1 && a.nz2 % inner == 0)) return hipErrorInvalidValue;
+    }
     if (a.scat_kp < 0 || (a.scat_kp && (!(mode == GM_STORE && tile_stage) || a.scat_w < a.scat_kp ||
                                         a.scat_lim <= 0 || a.scat_lim > a.N)))
         return hipErrorInvalidValue;

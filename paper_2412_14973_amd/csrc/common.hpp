@@ -77,10 +77,12 @@ struct GemmArgs {
     int32_t nz2;
     int32_t K2;                      // GM_LINE: b = A B2 sums over k < K2 only (0: all K; a multiple of 16)
     int64_t sA2, sB2, sC2, sE2, sP2;
-    // third level (GM_STORE): with nz3 > 1 the second-level index z2 splits into z2 / nz3 (strides s2)
-    // and z3 = z2 mod nz3 (strides s3); grid.y = nz * nz2 * nz3
-    int32_t nz3;
-    int64_t sA3, sB3, sC3;
+    // further levels (GM_STORE tile stages): the second-level index first splits into (z2 / nz4,
+    // z4 = z2 mod nz4) when nz4 > 1 (strides s4: operand sets of one launch, s4 may be the distance
+    // between two buffers), then into (z2 / nz3, z3 = z2 mod nz3) when nz3 > 1 (strides s3); nz2
+    // counts all of them (grid.y = nz * nz2)
+    int32_t nz3, nz4;
+    int64_t sA3, sB3, sC3, sA4, sB4, sC4;
     // GM_STORE tile stages: output column n < scat_lim is stored at column
     // n + ((n mod scat_w) / scat_kp) * scat_js, columns from scat_lim on are dropped (scat_kp = 0:
     // plain), which regroups blocks of scat_kp columns across batch entries

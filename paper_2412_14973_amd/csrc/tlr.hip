@@ -26,15 +26,39 @@ __global__ __launch_bounds__(256) void tlr_pack_kernel(const PackItem *__restric
     const PackItem it = items[blockIdx.x];
     float2 *dst = dst_base + it.dst;
     const float2 *src = (it.from ? theta2 : theta) + it.src;
+    if (it.op == PACK_TRANS || it.op == PACK_CTRANS) {
+        // transposes through LDS in 32 x 32 tiles: reads along the source rows, writes along dst rows
+        __shared__ float2 tile[32][33];
+        const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+        const int ntr = (it.rows + 31) / 32, ntc = (it.cols + 31) / 32;
+        const float sgn = it.op == PACK_CTRANS ? -1.f : 1.f;
+        for (int q = blockIdx.y; q < ntr * ntc; q += gridDim.y) {
+            const int r0 = (q / ntc) * 32, c0 = (q % ntc) * 32;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = c0 + ty + 8 * j, r = r0 + tx;
+                if (c < it.cols && r < it.rows) tile[ty + 8 * j][tx] = src[(int64_t)c * it.lds + r];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = r0 + ty + 8 * j, c = c0 + tx;
+                if (c < it.cols && r < it.rows) {
+                    const float2 v = tile[tx][ty + 8 * j];
+                    dst[(int64_t)r * it.ldd + c] = make_float2(v.x, sgn * v.y);
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
     const int64_t n = (int64_t)it.rows * it.cols;
     for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.y * blockDim.x) {
         const int r = (int)(e / it.cols), c = (int)(e % it.cols);
         float2 v;
         switch (it.op) {
             case PACK_COPY: v = src[(int64_t)r * it.lds + c]; break;            // src rows x cols
-            case PACK_TRANS: v = src[(int64_t)c * it.lds + r]; break;           // src cols x rows
             case PACK_CONJ: v = src[(int64_t)r * it.lds + c]; v.y = -v.y; break;
-            case PACK_CTRANS: v = src[(int64_t)c * it.lds + r]; v.y = -v.y; break;
             case PACK_IDENT: v = make_float2(r == c ? 1.f : 0.f, 0.f); break;
             default: {                                                           // (Z + Z^T)/2
                 const float2 a = src[(int64_t)r * it.lds + c], b = src[(int64_t)c * it.lds + r];
@@ -61,7 +85,7 @@ __global__ __launch_bounds__(256) void tlr_gather_kernel(const GatherItem *__res
 __global__ __launch_bounds__(256) void tlr_grad_kernel(const TGradItem *__restrict__ items,
                                                        const float2 *__restrict__ H1,
                                                        const float2 *__restrict__ H2, int nparts,
-                                                       int64_t part_stride, int64_t ldh,
+                                                       int64_t part_stride, int64_t ldh, int conj1,
                                                        float2 *__restrict__ g) {
     const TGradItem it = items[blockIdx.x];
     const int64_t n = (int64_t)it.rows * it.cols;
@@ -81,6 +105,7 @@ __global__ __launch_bounds__(256) void tlr_grad_kernel(const TGradItem *__restri
             sx += v.x;
             sy += v.y;
         }
+        if (conj1) sy = -sy;
         for (int q = 0; q < nparts; ++q) {
             const float2 v = H2[h + q * part_stride];
             sx += v.x;
@@ -118,10 +143,10 @@ __global__ __launch_bounds__(256) void tlr_paxpy_kernel(float2 *__restrict__ Pco
 }  // namespace
 
 hipError_t launch_tlr_grad(const TGradItem *items, int nitems, const float2 *H1, const float2 *H2, int nparts,
-                           int64_t part_stride, int64_t ldh, float2 *g, hipStream_t s) {
+                           int64_t part_stride, int64_t ldh, bool conj1, float2 *g, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     hipLaunchKernelGGL(tlr_grad_kernel, dim3((unsigned)nitems, 8), dim3(256), 0, s, items, H1, H2, nparts,
-                       part_stride, ldh, g);
+                       part_stride, ldh, conj1 ? 1 : 0, g);
     return hipGetLastError();
 }
 
@@ -135,10 +160,11 @@ hipError_t launch_tlr_paxpy(float2 *Pcol, int nentries, int nt, int64_t entry_st
 }
 
 hipError_t launch_tlr_pack(const PackItem *items, int nitems, const float2 *theta, float2 *dst, hipStream_t s,
-                           const float2 *theta2) {
+                           const float2 *theta2, int blocks_per_item) {
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(tlr_pack_kernel, dim3((unsigned)nitems, 16), dim3(256), 0, s, items, theta,
-                       theta2 ? theta2 : theta, dst);
+    if (blocks_per_item < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(tlr_pack_kernel, dim3((unsigned)nitems, (unsigned)blocks_per_item), dim3(256), 0, s, items,
+                       theta, theta2 ? theta2 : theta, dst);
     return hipGetLastError();
 }
 

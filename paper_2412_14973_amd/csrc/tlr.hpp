@@ -29,7 +29,8 @@ struct GatherItem {
 };
 
 // One block of the tile-form gradient: g[dst + r * ldd + c] (or g[dst + c * ldd + r] with trans) =
-// sum over the partial planes of H1 and H2 at src + r * ldh + c, for r < rows, c < cols.
+// sum over the partial planes of H1 (conjugated when conj1) and H2 at src + r * ldh + c, for r < rows,
+// c < cols.
 struct TGradItem {
     int32_t rows, cols;
     int32_t trans;
@@ -38,7 +39,7 @@ struct TGradItem {
 };
 
 hipError_t launch_tlr_grad(const TGradItem *items, int nitems, const float2 *H1, const float2 *H2, int nparts,
-                           int64_t part_stride, int64_t ldh, float2 *g, hipStream_t s);
+                           int64_t part_stride, int64_t ldh, bool conj1, float2 *g, hipStream_t s);
 
 // Pcol theta half += step * direction half for every (problem, tile column) of a tile range: rows x
 // (nt kpad) per entry at Pcol + e * entry_stride (direction half at column 0, theta half at column
@@ -47,8 +48,9 @@ struct SolveScalars;
 hipError_t launch_tlr_paxpy(float2 *Pcol, int nentries, int nt, int64_t entry_stride, int64_t rows, int64_t ld,
                             int64_t half_cols, const SolveScalars *sc, hipStream_t s);
 
+// blocks_per_item: workgroups that share one item (grid-stride over its elements or 32 x 32 tiles)
 hipError_t launch_tlr_pack(const PackItem *items, int nitems, const float2 *theta, float2 *dst, hipStream_t s,
-                           const float2 *theta2 = nullptr);
+                           const float2 *theta2 = nullptr, int blocks_per_item = 16);
 hipError_t launch_tlr_gather(const GatherItem *items, int nitems, const float2 *P, float2 *Pcol, int64_t rows,
                              hipStream_t s);
 

@@ -80,39 +80,57 @@ __global__ __launch_bounds__(256) void tlr_gather_kernel(const GatherItem *__res
 }
 
 // Gradient blocks of the tile form from the partial planes of its two products (fixed summation
-// order: the H1 planes, then the H2 planes). Non-transposed blocks run along c (contiguous in H and
-// g), transposed ones along r (contiguous in g).
+// order: the H1 planes, then the H2 planes) in 32 x 32 tiles: every thread reads along the rows of H
+// (c fastest); transposed blocks pass through LDS so that they are written along the rows of g too.
 __global__ __launch_bounds__(256) void tlr_grad_kernel(const TGradItem *__restrict__ items,
                                                        const float2 *__restrict__ H1,
                                                        const float2 *__restrict__ H2, int nparts,
                                                        int64_t part_stride, int64_t ldh, int conj1,
                                                        float2 *__restrict__ g) {
+    __shared__ float2 tile[32][33];
     const TGradItem it = items[blockIdx.x];
-    const int64_t n = (int64_t)it.rows * it.cols;
-    for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.y * blockDim.x) {
-        int r, c;
-        if (it.trans) {
-            c = (int)(e / it.rows);
-            r = (int)(e % it.rows);
-        } else {
-            r = (int)(e / it.cols);
-            c = (int)(e % it.cols);
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int ntr = (it.rows + 31) / 32, ntc = (it.cols + 31) / 32;
+    for (int q = blockIdx.y; q < ntr * ntc; q += gridDim.y) {
+        const int r0 = (q / ntc) * 32, c0 = (q % ntc) * 32;
+        float2 v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = r0 + ty + 8 * j, c = c0 + tx;
+            float sx = 0.f, sy = 0.f;
+            if (r < it.rows && c < it.cols) {
+                const int64_t h = it.src + (int64_t)r * ldh + c;
+                for (int p = 0; p < nparts; ++p) {
+                    const float2 a = H1[h + p * part_stride];
+                    sx += a.x;
+                    sy += a.y;
+                }
+                if (conj1) sy = -sy;
+                for (int p = 0; p < nparts; ++p) {
+                    const float2 a = H2[h + p * part_stride];
+                    sx += a.x;
+                    sy += a.y;
+                }
+            }
+            v[j] = make_float2(sx, sy);
         }
-        const int64_t h = it.src + (int64_t)r * ldh + c;
-        float sx = 0.f, sy = 0.f;
-        for (int q = 0; q < nparts; ++q) {
-            const float2 v = H1[h + q * part_stride];
-            sx += v.x;
-            sy += v.y;
+        if (!it.trans) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = r0 + ty + 8 * j, c = c0 + tx;
+                if (r < it.rows && c < it.cols) g[it.dst + (int64_t)r * it.ldd + c] = v[j];
+            }
+            continue;   // uniform per block: it.trans is the item's
         }
-        if (conj1) sy = -sy;
-        for (int q = 0; q < nparts; ++q) {
-            const float2 v = H2[h + q * part_stride];
-            sx += v.x;
-            sy += v.y;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) tile[ty + 8 * j][tx] = v[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {   // g[dst + c * ldd + r], r fastest
+            const int c = c0 + ty + 8 * j, r = r0 + tx;
+            if (r < it.rows && c < it.cols) g[it.dst + (int64_t)c * it.ldd + r] = tile[tx][ty + 8 * j];
         }
-        const int64_t o = it.trans ? it.dst + (int64_t)c * it.ldd + r : it.dst + (int64_t)r * it.ldd + c;
-        g[o] = make_float2(sx, sy);
+        __syncthreads();
     }
 }
 

@@ -164,6 +164,7 @@ def serving(tl, torch, args):
     import synth
     from paper_2412_14973_amd import serve
     prec = precision_info(tl, args.precision)[0]
+    line = {"dense": tl.LINE_DENSE, "tile": tl.LINE_TILE, "tile-grad": tl.LINE_TILE_GRAD}[args.line_products]
     reqs = synth.request_stream(args.requests, iters=args.iters or 100)
     dev = torch.device("cuda")
     prepared = []
@@ -173,7 +174,8 @@ def serving(tl, torch, args):
         perm = torch.from_numpy(tl.hilbert_order(geom.rec_ix, geom.rec_iy)).to(dev)
         plan = tl.Plan.from_layout(lay, geom.ns)
         prepared.append((r, D, U, th, perm, plan))
-        log(f"request {r.rid}: nr {geom.nr} ns {geom.ns} d {r.d} k {r.k} ({time.time() - t0:.1f}s)")
+        form = tl.line_form(plan, prec, line)[0]
+        log(f"request {r.rid}: nr {geom.nr} ns {geom.ns} d {r.d} k {r.k} form {form} ({time.time() - t0:.1f}s)")
     torch.cuda.synchronize()
 
     class Backend(serve.GpuBackend):
@@ -185,17 +187,20 @@ def serving(tl, torch, args):
             with torch.cuda.stream(stream):
                 Dh = tl.permute_columns(D, perm)
                 Uh = tl.permute_columns(U, perm)
-                theta, fh = tl.solve(plan, Dh, Uh, th, r.iters, precision=prec)
+                theta, fh = tl.solve(plan, Dh, Uh, th, r.iters, precision=prec, line_products=line)
                 ev = torch.cuda.Event()
                 ev.record(stream)
             return {"event": ev, "stream": sidx, "theta": theta, "fhist": fh, "keep": (Dh, Uh)}
 
         def footprint(self, req):
             r, D, U, th, perm, plan = req
-            return super().footprint(serve.SolveRequest(plan, D, U, th, r.iters, prec)) + 2 * D.numel() * 8
+            return super().footprint(serve.SolveRequest(plan, D, U, th, r.iters, prec, line_products=line)) + \
+                2 * D.numel() * 8
 
     out = {"metric": "TLR-MDD served solves/s, p50/p99 latency", "requests": len(reqs),
            "arrival_rate_per_s": 200.0, "iters": reqs[0].iters, "precision": args.precision,
+           "line_products": args.line_products,
+           "forms": [tl.line_form(p[5], prec, line)[0] for p in prepared],
            "hbm_budget_gib": args.hbm_budget_gib, "sizes": [[r.n_side ** 2, (r.n_side ** 2) // (2 if r.ns_mode == "half" else 1), r.d, r.k] for r in reqs]}
     results = {}
     for mode, active in (("one_at_a_time", 1), ("continuous", args.max_active)):

@@ -157,6 +157,7 @@ class SolveRequest:
     iters: int
     precision: int = 0
     lbfgs_m: int = 5
+    line_products: int = 0    # LINE_DENSE, LINE_TILE or LINE_TILE_GRAD
 
 
 class GpuBackend:
@@ -175,7 +176,8 @@ class GpuBackend:
     def footprint(self, req: SolveRequest) -> int:
         """Device bytes a solve keeps resident: workspace + theta + f-history (+ inputs)."""
         from . import _lib
-        opts = self.make_opts(req.iters, lbfgs_m=req.lbfgs_m, precision=req.precision)
+        opts = self.make_opts(req.iters, lbfgs_m=req.lbfgs_m, precision=req.precision,
+                              line_products=req.line_products)
         ws = req.plan.workspace_bytes(_lib.OP_SOLVE, opts)
         return ws + 8 * req.plan.theta_size + 8 * (req.iters + 1)
 
@@ -187,7 +189,7 @@ class GpuBackend:
         stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(stream):
             theta, fh = solve(req.plan, req.D, req.U, req.theta0, req.iters, lbfgs_m=req.lbfgs_m,
-                              precision=req.precision)
+                              precision=req.precision, line_products=req.line_products)
             ev = torch.cuda.Event()
             ev.record(stream)
         return {"event": ev, "stream": sidx, "theta": theta, "fhist": fh}

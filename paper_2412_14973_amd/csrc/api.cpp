@@ -431,6 +431,7 @@ struct LineClass {
 // Flops: 3 Wg / nr of the adjoint product D^H r.
 constexpr double GRAD_TILE_MAX_COST = 0.6;
 constexpr int GRAD_TILE_KS = 4;
+static_assert(GEMM_PAD % (GRAD_TILE_KS * GEMM_BK) == 0, "every part of the padded ns is a whole number of k stages");
 int64_t grad_tile_width(const LineClass &lc) { return round_up((int64_t)lc.nt * lc.kpad, GEMM_BN); }
 
 // Tile form is available when all tiles have one size d (a multiple of 128), nr needs no padding,
@@ -469,8 +470,7 @@ bool tile_line_requested(int op, const tlrmdd_opts *opts);
 bool problem_form(int op, const HostLayout &H, const tlrmdd_opts *opts, LineClass &lc) {
     if (!tile_line_requested(op, opts) || !line_class(H, lc)) return false;
     lc.grad = opts->line_products == TLRMDD_LINE_TILE_GRAD &&
-              3.0 * (double)grad_tile_width(lc) <= GRAD_TILE_MAX_COST * (double)H.nr &&
-              (int64_t)GRAD_TILE_KS * 16 <= round_up(H.ns, GEMM_PAD) && round_up(H.ns, GEMM_PAD) % (GRAD_TILE_KS * 16) == 0;
+              3.0 * (double)grad_tile_width(lc) <= GRAD_TILE_MAX_COST * (double)H.nr;
     return true;
 }
 

@@ -222,3 +222,22 @@ def test_tile_grad_admm_batched_match_single(tl, streams):
     torch.cuda.synchronize()
     for (ts, fs), tb, fb in zip(singles, th_b, fh_b):
         assert torch.equal(ts, tb) and torch.equal(fs, fb)
+
+
+def test_tile_forms_single_tile_and_ragged(tl):
+    """Edge layouts: one Q Q^T tile over all receivers (nt = 1: kpad a multiple of 64) takes both tile
+    forms and matches the oracle; a ragged layout (tiles 384 + 384 + 256) keeps the dense forms."""
+    lay = synth.Layout(np.array([1024]), np.array([], dtype=np.int64), np.array([30]))
+    case = from_geometry(32, 32, "half", 12.0, lay, 81, "one_tile")
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    assert tl.line_form(plan, line_products=tl.LINE_TILE_GRAD) == (2, 64)   # 2.5*64/1024, 3*128/1024
+    iters = 6
+    thg, fh = tl.solve(plan, D, U, th, iters=iters, precision=tl.FP32_3M, line_products=tl.LINE_TILE_GRAD)
+    torch.cuda.synchronize()
+    ref = O.solve(case.T, case.D, case.U, case.theta, iters=iters)
+    rf, rx, rt = _metrics(case, thg.cpu().numpy().astype(np.complex128), ref.theta)
+    print(f"one tile: rel_f {rf:.2e} rel_X {rx:.2e} rel_theta {rt:.2e}", flush=True)
+    assert rf <= FP32_TOL and rx <= FP32_TOL and rt <= FP32_TOL
+    rag = synth.Layout(np.array([384, 384, 256]), np.full(3, 8), np.array([6, 6, 6]))
+    plan_r = to_device(from_geometry(32, 32, "half", 12.0, rag, 82, "ragged"), tl, torch)[0]
+    assert tl.line_form(plan_r, line_products=tl.LINE_TILE_GRAD) == (0, 0)

@@ -185,7 +185,9 @@ int tlrmdd_solve(tlrmdd_plan plan, const void *D, const void *U, void *theta_ino
 /* Form of the exact line search's (and gradient's) products for this plan
  * under opts (tlrmdd_solve and the batched / ADMM calls): *tile_form = 1
  * when opts->line_products is TLRMDD_LINE_TILE or TLRMDD_LINE_TILE_GRAD, the
- * precision is TLRMDD_FP32_3M and the layout qualifies - all tiles of one
+ * precision is TLRMDD_FP32_3M or TLRMDD_BF16X3 (the tile-form products run on
+ * the three-product FP32 kernel in both; the dense ones keep the precision's
+ * kernels) and the layout qualifies - all tiles of one
  * size d (a multiple of 128), nr a multiple of 128, Q Q^T diagonal tiles -
  * with 2.5 kpad / d <= 0.6, where kpad is the largest rank rounded up so
  * that a stage-1 row of 2 nt blocks of kpad columns is a whole number of

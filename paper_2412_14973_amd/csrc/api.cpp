@@ -335,6 +335,7 @@ int partial_stride(const Tables &T, int64_t nrp, int64_t nsp) {
 // ---------------------------------------------------------------------------
 struct Ws {
     float2 *Ds = nullptr, *DHs = nullptr, *Us = nullptr, *XW = nullptr, *r = nullptr, *a = nullptr, *b = nullptr;
+    float2 *Dc = nullptr;     // complex64 D for the tile-form products (Ds itself, or a copy in BF16 mode)
     uint32_t *rT = nullptr;   // BF16 split planes of r^T (hi, lo), ldk x lds each
     float *th = nullptr, *g0 = nullptr, *g1 = nullptr, *p = nullptr, *S = nullptr, *Y = nullptr;
     double *gram = nullptr;   // per problem: Gram matrix of the L-BFGS basis and direction coefficients
@@ -434,8 +435,8 @@ constexpr int GRAD_TILE_KS = 4;
 static_assert(GEMM_PAD % (GRAD_TILE_KS * GEMM_BK) == 0, "every part of the padded ns is a whole number of k stages");
 int64_t grad_tile_width(const LineClass &lc) { return round_up((int64_t)lc.nt * lc.kpad, GEMM_BN); }
 
-// Tile form is available when all tiles have one size d (a multiple of 128), nr needs no padding,
-// the diagonal tiles are Q Q^T and the padded rank keeps the flops under LINE_TILE_MAX_COST.
+// Tile form is possible when all tiles have one size d (a multiple of 128), nr needs no padding and the
+// diagonal tiles are Q Q^T; problem_form decides whether the padded rank keeps the flops low enough.
 bool line_class(const HostLayout &H, LineClass &lc) {
     if (H.nr % GEMM_PAD) return false;
     const int d = H.d[0];
@@ -459,18 +460,23 @@ bool line_class(const HostLayout &H, LineClass &lc) {
     }
     const int q = 64 / gcd;
     const int kpad = (int)round_up(kmax, q);
-    if (LINE_TILE_FLOPS * kpad > LINE_TILE_MAX_COST * d) return false;
     lc = LineClass{d, nt, kpad};
     return true;
 }
 
 
 // Line-search (and gradient) form of one problem under opts: false = dense; lc.grad = gradient too.
+// The tile-form products run on the three-product FP32 kernel; in BF16 mode the dense products they
+// replace run at about twice its rate (measured: 340 against 171 TFLOP/s algorithmic on the bench
+// workload), so there the flop shares must be half as large.
+constexpr double BF16_DENSE_SPEED = 2.0;
 bool tile_line_requested(int op, const tlrmdd_opts *opts);
 bool problem_form(int op, const HostLayout &H, const tlrmdd_opts *opts, LineClass &lc) {
     if (!tile_line_requested(op, opts) || !line_class(H, lc)) return false;
+    const double speed = opts->precision == TLRMDD_BF16X3 ? BF16_DENSE_SPEED : 1.0;
+    if (LINE_TILE_FLOPS * lc.kpad * speed > LINE_TILE_MAX_COST * lc.d) return false;
     lc.grad = opts->line_products == TLRMDD_LINE_TILE_GRAD &&
-              3.0 * (double)grad_tile_width(lc) <= GRAD_TILE_MAX_COST * (double)H.nr;
+              3.0 * (double)grad_tile_width(lc) * speed <= GRAD_TILE_MAX_COST * (double)H.nr;
     return true;
 }
 
@@ -655,13 +661,14 @@ struct LineSeg {
 };
 
 bool tile_line_requested(int op, const tlrmdd_opts *opts) {
-    return op >= 2 && opts && opts->line_products != TLRMDD_LINE_DENSE && opts->precision == TLRMDD_FP32_3M;
+    return op >= 2 && opts && opts->line_products != TLRMDD_LINE_DENSE &&
+           (opts->precision == TLRMDD_FP32_3M || opts->precision == TLRMDD_BF16X3);
 }
 
 // Ranges of the run and the bytes of their tile regions (carved back to back from `base`, or sized
 // only when base is NULL).
 std::vector<LineSeg> line_segments(int op, int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts,
-                                   int64_t lds, char *base, size_t *bytes) {
+                                   int64_t lds, char *base, size_t *bytes, float2 **dcopy = nullptr) {
     std::vector<LineSeg> segs;
     std::vector<LineClass> cls(count);
     std::vector<bool> tile(count, false);
@@ -671,6 +678,16 @@ std::vector<LineSeg> line_segments(int op, int count, const tlrmdd_plan *plans, 
     while (suffix > 0 && tile[suffix - 1] && cls[suffix - 1].grad) --suffix;
     for (int p = 0; p < suffix; ++p) cls[p].grad = false;
     size_t o = 0;
+    // BF16 mode stages D as split planes; the tile-form products read a complex64 copy (every problem
+    // of the run, so that problem p's copy sits at p lds ldk), carved first
+    bool any_tile = false;
+    for (int p = 0; p < count; ++p) any_tile = any_tile || tile[p];
+    if (dcopy) *dcopy = nullptr;
+    if (any_tile && opts->precision == TLRMDD_BF16X3) {
+        const int64_t ldk = round_up(plans[0]->H.nr, GEMM_PAD);
+        if (dcopy) *dcopy = base ? (float2 *)base : nullptr;
+        o += align256((size_t)count * lds * ldk * sizeof(float2));
+    }
     for (int p = 0; p < count;) {
         int q = p + 1;
         while (q < count && tile[q] == tile[p] && (!tile[p] || cls[q] == cls[p])) ++q;
@@ -1164,6 +1181,7 @@ Ctx line_ctx(const Ctx &c, int p0, int np) {
     const int64_t rs = c.lds * c.ldk;
     s.nprob = np;
     s.w.Ds += p0 * rs;
+    if (s.w.Dc) s.w.Dc += p0 * rs;
     if (s.w.DHs) s.w.DHs += p0 * rs;
     s.w.r += p0 * rs;
     s.w.a += p0 * rs;
@@ -1183,7 +1201,7 @@ int tile_stage1(Run &R, const LineSeg &sg, const float *dir) {
         return launch_tlr_pack(L.pack, L.npack, (const float2 *)c.w.th, L.PA, c.s, (const float2 *)dir, 2);
     }));
     GemmArgs g1 = gemm_args();   // stage 1: P_(p,i) = D_p[:, i d ...] PA_(p,i)
-    g1.A = c.w.Ds; g1.lda = c.ldk; g1.sA = c.lds * c.ldk; g1.sA2 = d;
+    g1.A = c.w.Dc; g1.lda = c.ldk; g1.sA = c.lds * c.ldk; g1.sA2 = d;
     g1.B = L.PA; g1.ldb = NA; g1.sB = nt * d * NA; g1.sB2 = d * NA;
     // stored regrouped by tile column: block j of row i -> Pcol_(p,j) at columns i kpad (each half)
     g1.C = L.Pcol; g1.ldc = NA; g1.sC = nt * c.lds * NA; g1.sC2 = lc.kpad;
@@ -1241,7 +1259,7 @@ int tile_gradient(Run &R, const LineSeg &sg, float *g) {
     //   set 1: conj(GA_(p,x,q)) = D_p[q Kc ..., x d ...]^T conj(Scol_(p,x)[q Kc ...])
     // (the same strides: D and r, Pcol and Scol share their layouts)
     GemmArgs g3 = gemm_args();
-    g3.A = c.w.r; g3.lda = c.ldk; g3.sA = c.lds * c.ldk; g3.sA2 = d; g3.sA3 = Kc * c.ldk; g3.sA4 = c.w.Ds - c.w.r;
+    g3.A = c.w.r; g3.lda = c.ldk; g3.sA = c.lds * c.ldk; g3.sA2 = d; g3.sA3 = Kc * c.ldk; g3.sA4 = c.w.Dc - c.w.r;
     g3.B = L.Pcol + nt * kp; g3.ldb = NA; g3.sB = nt * c.lds * NA; g3.sB2 = c.lds * NA; g3.sB3 = Kc * NA;
     g3.sB4 = L.Scol - (L.Pcol + nt * kp);
     g3.C = L.GBT; g3.ldc = Wg; g3.sC = nt * KS * d * Wg; g3.sC2 = KS * d * Wg; g3.sC3 = d * Wg; g3.sC4 = L.GA - L.GBT;
@@ -1340,8 +1358,10 @@ int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *c
                 R.single ? 0 : tables_bytes(R.T, nprob));
     if (c.w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     size_t tbytes = 0;
-    R.segs = line_segments(op, nprob, plans, opts, c.lds, (char *)workspace + c.w.bytes, &tbytes);
+    float2 *dcopy = nullptr;
+    R.segs = line_segments(op, nprob, plans, opts, c.lds, (char *)workspace + c.w.bytes, &tbytes, &dcopy);
     if (c.w.bytes + tbytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
+    c.w.Dc = dcopy ? dcopy : c.w.Ds;
     R.asm_first = R.T.asm_first;
     R.asm_first.push_back((int)R.T.asm_items.size());
     R.grad_first = R.T.grad_first;
@@ -1409,6 +1429,9 @@ int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *c
     if (c.ldk != nr) HIP_TRY(hipMemsetAsync(c.w.XW, 0, (size_t)nprob * R.xstride * sizeof(float2), s));
     for (int p = 0; p < nprob; ++p) {
         if ((st = stage(c, p, (const float2 *)D[p], true))) return st;
+        if (c.w.Dc != c.w.Ds)   // BF16 mode with tile-form ranges: their complex64 D
+            HIP_TRY(launch_stage_d((const float2 *)D[p], c.ns, c.nr, c.w.Dc + p * c.lds * c.ldk, c.ldk, nullptr,
+                                   c.lds, s));
         HIP_TRY(launch_copy2d((const float2 *)U[p], nr, c.w.Us + p * R.rstride, c.ldk, ns, nr, s));
         HIP_TRY(hipMemcpyAsync(c.w.th + 2 * R.T.probs[p].theta, theta[p],
                                plans[p]->H.theta_size * sizeof(float2), hipMemcpyDeviceToDevice, s));

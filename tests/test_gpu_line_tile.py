@@ -241,3 +241,44 @@ def test_tile_forms_single_tile_and_ragged(tl):
     rag = synth.Layout(np.array([384, 384, 256]), np.full(3, 8), np.array([6, 6, 6]))
     plan_r = to_device(from_geometry(32, 32, "half", 12.0, rag, 82, "ragged"), tl, torch)[0]
     assert tl.line_form(plan_r, line_products=tl.LINE_TILE_GRAD) == (0, 0)
+
+
+# ---- BF16 hi+lo split mode: dense products in BF16, the tile-form products on the FP32 three-product kernel
+BF16_TOL = 5e-3
+
+
+# In BF16 mode the tile forms must beat dense products that run about twice as fast: half the flop
+# shares (the nr = 1024 tile-256 case keeps the dense gradient, nr = 2048 with rank 8 takes both forms).
+@pytest.mark.parametrize("shape", ["nr1024", "nr2048"])
+def test_tile_forms_bf16_solve_vs_oracle(tl, shape):
+    if shape == "nr1024":
+        case = _case_nr1024(91, 10, [8, 12, 6, 10], "bf16")
+        expect = (1, 16)
+    else:
+        lay = synth.Layout(np.array([256] * 8), np.full(28, 6), np.array([8, 5, 7, 8, 3, 6, 8, 4]))
+        case = from_geometry(64, 32, "half", 12.0, lay, 96, "bf16_nr2048")
+        expect = (2, 8)
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    assert tl.line_form(plan, precision=tl.BF16X3, line_products=tl.LINE_TILE_GRAD) == expect
+    iters = 8 if shape == "nr1024" else 4
+    thg, fh = tl.solve(plan, D, U, th, iters=iters, precision=tl.BF16X3, line_products=tl.LINE_TILE_GRAD)
+    torch.cuda.synchronize()
+    ref = O.solve(case.T, case.D, case.U, case.theta, iters=iters)
+    rf, rx, rt = _metrics(case, thg.cpu().numpy().astype(np.complex128), ref.theta)
+    rel_h = np.max(np.abs(fh.cpu().numpy() - ref.f_hist) / ref.f_hist)
+    print(f"bf16 tile forms {shape}: rel_f {rf:.2e} rel_X {rx:.2e} rel_theta {rt:.2e} f_hist {rel_h:.2e}",
+          flush=True)
+    assert rf <= BF16_TOL and rx <= BF16_TOL and rt <= BF16_TOL and rel_h <= BF16_TOL
+
+
+def test_tile_forms_bf16_batched_match_single(tl):
+    cases = [_case_nr1024(92, 12, [9, 14, 5, 16], "g_a"), _case_nr1024(93, 3, [-1, 4, 5, 6], "dense"),
+             _case_nr1024(94, 20, [20] * 8, "q8", tiles=(128,) * 8), _case_nr1024(95, 5, [3, 4, 5, 6], "g_b")]
+    devs = [to_device(c, tl, torch) for c in cases]
+    kw = dict(iters=5, precision=tl.BF16X3, line_products=tl.LINE_TILE_GRAD)
+    th_b, fh_b = tl.solve_batched([d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs],
+                                  [d[3] for d in devs], **kw)
+    singles = [tl.solve(d[0], d[1], d[2], d[3], **kw) for d in devs]
+    torch.cuda.synchronize()
+    for (ts, fs), tb, fb in zip(singles, th_b, fh_b):
+        assert torch.equal(ts, tb) and torch.equal(fs, fb)

@@ -194,7 +194,9 @@ int tlrmdd_solve(tlrmdd_plan plan, const void *D, const void *U, void *theta_ino
  * 128-column tiles (2.5 kpad / d: the tile form's share of the dense
  * products' flops; conclusions of the paper: the TLR product as the way to
  * cut the cost of the dense products); 2 when the gradient is in tile form
- * as well (TLRMDD_LINE_TILE_GRAD and 3 Wg / nr <= 0.6). In a batched call a
+ * as well (TLRMDD_LINE_TILE_GRAD and 3 Wg / nr <= 0.6). In TLRMDD_BF16X3 mode
+ * both bounds are 0.3: the BF16 dense products they replace run about twice
+ * as fast. In a batched call a
  * problem whose gradient would be in tile form keeps the dense gradient when
  * a problem of another form follows it in the call's order (the library
  * orders problems by form itself). *kpad (may be NULL) gets the padded rank,

@@ -101,13 +101,15 @@ typedef struct {
                                bit-identical for every value; single-problem calls ignore it. */
     int32_t line_products;  /* TLRMDD_LINE_DENSE (0): the line search's [a | b] = D [X1 | X2] from
                                the assembled X1, X2; TLRMDD_LINE_TILE (1): in tile form wherever that
-                               needs fewer flops (see tlrmdd_line_form); batched calls still run
+                               needs fewer flops (precisions TLRMDD_FP32_3M and TLRMDD_BF16X3; see
+                               tlrmdd_line_form for the bounds); batched calls still run
                                every phase as one launch per sub-batch, except the line-search
                                products: one launch for the dense-form problems and the tile-form
                                stages once per (tile size, padded rank) class;
                                TLRMDD_LINE_TILE_GRAD (2): as 1, and the gradient in tile form too
                                where its three products (3 Wg / nr of the adjoint product D^H r,
-                               Wg = nt kpad rounded up to 128) cost at most 0.6 of the adjoint:
+                               Wg = nt kpad rounded up to 128) cost at most 0.6 of the adjoint
+                               (0.3 in BF16X3 mode):
                                W_ij B_ij^H = D_:,i^H (r_:,j B_ij^H), A_ij^H W_ij = (D_:,i A_ij)^H r_:,j
                                with X_ij = A_ij B_ij (gradient equations); the adjoint product then
                                runs on the other problems only */

@@ -62,18 +62,25 @@ def test_large_autograd_backward_vs_fd(tl, f_idx):
     assert np.all(np.abs(g[idx] - fd) <= bound + fd_err + 1e-9 * fo)
 
 
-def test_large_two_iterations(tl):
+# the nr = 4096 configuration (bench --workload large): dense products (four-product FP32) and the tile
+# forms on the three-product kernel (line search 0.31, gradient 0.375 of the dense products)
+@pytest.mark.parametrize("form", ["dense", "tile"])
+def test_large_two_iterations(tl, form):
     wl = synth.large()
     case = from_workload(wl, 20)
     plan, D, U, th, _ = to_device(case, tl, torch)
-    thg, fh = tl.solve(plan, D, U, th, iters=2)
+    if form == "tile":
+        assert tl.line_form(plan, line_products=tl.LINE_TILE_GRAD) == (2, 32)
+        thg, fh = tl.solve(plan, D, U, th, iters=2, precision=tl.FP32_3M, line_products=tl.LINE_TILE_GRAD)
+    else:
+        thg, fh = tl.solve(plan, D, U, th, iters=2)
     torch.cuda.synchronize()
     ref = O.solve(case.T, case.D, case.U, case.theta, iters=2)
     fh = fh.cpu().numpy()
     rel_hist = np.abs(fh - ref.f_hist) / ref.f_hist
     th_g = thg.cpu().numpy().astype(np.complex128)
     rel_t = np.linalg.norm(th_g - ref.theta) / np.linalg.norm(ref.theta)
-    print(f"large 2-iter: rel f_hist {rel_hist.max():.2e} rel_theta {rel_t:.2e}", flush=True)
+    print(f"large 2-iter {form}: rel f_hist {rel_hist.max():.2e} rel_theta {rel_t:.2e}", flush=True)
     assert rel_hist.max() <= 1e-5 and rel_t <= 1e-5
 
 

@@ -1191,8 +1191,9 @@ Ctx line_ctx(const Ctx &c, int p0, int np) {
 }
 
 // Stage 1 of a tile range: pack the factor blocks of theta and of the direction `dir`, then
-// Pcol_(p,j) = [D_:,i A_dir(ij) ... | D_:,i A_th(ij) ...] (see LineTile)
-int tile_stage1(Run &R, const LineSeg &sg, const float *dir) {
+// Pcol_(p,j) = [D_:,i A_dir(ij) ... | D_:,i A_th(ij) ...] (see LineTile), or the direction half only
+// (dir_only: the theta half is carried by P_th += step P_p in ranges with the tile-form gradient)
+int tile_stage1(Run &R, const LineSeg &sg, const float *dir, bool dir_only = false) {
     const Ctx c = line_ctx(R.c, sg.p0, sg.np);
     const LineTile &L = sg.lt;
     const LineClass &lc = L.lc;
@@ -1205,16 +1206,18 @@ int tile_stage1(Run &R, const LineSeg &sg, const float *dir) {
     g1.B = L.PA; g1.ldb = NA; g1.sB = nt * d * NA; g1.sB2 = d * NA;
     // stored regrouped by tile column: block j of row i -> Pcol_(p,j) at columns i kpad (each half)
     g1.C = L.Pcol; g1.ldc = NA; g1.sC = nt * c.lds * NA; g1.sC2 = lc.kpad;
-    g1.scat_kp = lc.kpad; g1.scat_w = (int)(nt * lc.kpad); g1.scat_lim = (int)NA; g1.scat_js = c.lds * NA - lc.kpad;
-    g1.M = (int)c.lds; g1.N = (int)NA; g1.K = (int)d;
+    const int N = dir_only ? (int)(nt * lc.kpad) : (int)NA;
+    g1.scat_kp = lc.kpad; g1.scat_w = (int)(nt * lc.kpad); g1.scat_lim = N; g1.scat_js = c.lds * NA - lc.kpad;
+    g1.M = (int)c.lds; g1.N = N; g1.K = (int)d;
     g1.nz2 = (int)nt;
     HIP_TRY(timed(TLRMDD_K_LINE_TILE, c.s, [&] { return launch_cgemm3m(GM_STORE, g1, (int)(c.nprob * nt), c.s, GR_TILE); }));
     return TLRMDD_OK;
 }
 
-// [a | b] = D [X1 | X2] with the five line-search sums for the problems of a tile range (see LineTile)
-int line_products_tile(Run &R, const LineSeg &sg) {
-    int st = tile_stage1(R, sg, R.c.w.p);
+// [a | b] = D [X1 | X2] with the five line-search sums for the problems of a tile range (see LineTile).
+// dir_only: stage 1 forms the direction half only (the theta half is current, see tile_pcol_update).
+int line_products_tile(Run &R, const LineSeg &sg, bool dir_only = false) {
+    int st = tile_stage1(R, sg, R.c.w.p, dir_only);
     if (st) return st;
     const Ctx c = line_ctx(R.c, sg.p0, sg.np);
     const LineTile &L = sg.lt;
@@ -1459,6 +1462,7 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
     for (const LineSeg &sg : R.segs)
         if (sg.tile && sg.lt.lc.grad && iters > 0)
             if ((st = tile_stage1(R, sg, c.w.th))) return st;
+    bool pth_fresh = false;   // the next line search recomputes P_th too (after a residual recompute)
     for (int t = 0; t < iters; ++t) {
         // gradient from the tracked residual (eqs. DXLR): W = D^H r and the tile blocks of W' for the
         // problems before the tile-form gradient ranges, the tile form for those
@@ -1506,7 +1510,12 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
             if ((st = fin(c, fin_args(FIN_LAMTERMS, c.w.sc), c.D.tcount, 0, 2))) return st;
         }
         for (const LineSeg &sg : R.segs) {
-            if (sg.tile) st = line_products_tile(R, sg);
+            // ranges with the tile-form gradient carry P_th from step to step; stage 1 forms it afresh
+            // (both halves) in the first iteration after every residual recompute, so its rounding
+            // does not accumulate over more iterations than the tracked residual's
+            const bool dir_only = sg.tile && sg.lt.lc.grad && (sg.lt.lc.nt * sg.lt.lc.kpad) % GEMM_BN == 0 &&
+                                  !pth_fresh;
+            if (sg.tile) st = line_products_tile(R, sg, dir_only);
             else if (sg.np == c.nprob) st = gemm_line(c, R.X1, R.X2, R.xstride);
             else st = gemm_line(line_ctx(c, sg.p0, sg.np), R.X1 + sg.p0 * R.xstride, R.X2 + sg.p0 * R.xstride,
                                 R.xstride);
@@ -1527,6 +1536,7 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
             if ((st = fin(c, fin_args(FIN_THNORM, c.w.sc), c.D.tcount, 0, 1))) return st;
         // residual: recomputed from theta every resid_refresh iterations, else updated in place
         const bool refresh = R.opts->resid_refresh > 0 && (t + 1) % R.opts->resid_refresh == 0;
+        pth_fresh = refresh;
         if (refresh) {
             if ((st = objective_fresh(R, record_base >= 0 ? record_base + t + 1 : -1, lam))) return st;
         } else {

@@ -282,3 +282,21 @@ def test_tile_forms_bf16_batched_match_single(tl):
     torch.cuda.synchronize()
     for (ts, fs), tb, fb in zip(singles, th_b, fh_b):
         assert torch.equal(ts, tb) and torch.equal(fs, fb)
+
+
+def test_tile_grad_carried_theta_half_vs_oracle(tl):
+    """nt kpad a multiple of 128 (4 tiles of 256, kpad 32): stage 1 forms only the direction half and
+    the theta half is carried by P_th += step P_p, formed afresh after each residual recompute (every
+    20 iterations); 25 iterations against the oracle."""
+    case = _case_nr1024(101, 20, [18, 24, 30, 12], "carried")
+    plan, D, U, th, _ = to_device(case, tl, torch)
+    assert tl.line_form(plan, line_products=tl.LINE_TILE_GRAD) == (2, 32)
+    iters = 25
+    thg, fh = tl.solve(plan, D, U, th, iters=iters, precision=tl.FP32_3M, line_products=tl.LINE_TILE_GRAD)
+    torch.cuda.synchronize()
+    ref = O.solve(case.T, case.D, case.U, case.theta, iters=iters)
+    rf, rx, rt = _metrics(case, thg.cpu().numpy().astype(np.complex128), ref.theta)
+    rel_h = np.max(np.abs(fh.cpu().numpy() - ref.f_hist) / ref.f_hist)
+    print(f"carried theta half, 25 iterations: rel_f {rf:.2e} rel_X {rx:.2e} rel_theta {rt:.2e} f_hist {rel_h:.2e}",
+          flush=True)
+    assert rf <= FP32_TOL and rx <= FP32_TOL and rt <= FP32_TOL and rel_h <= FP32_TOL

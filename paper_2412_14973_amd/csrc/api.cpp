@@ -1193,7 +1193,7 @@ Ctx line_ctx(const Ctx &c, int p0, int np) {
 // Stage 1 of a tile range: pack the factor blocks of theta and of the direction `dir`, then
 // Pcol_(p,j) = [D_:,i A_dir(ij) ... | D_:,i A_th(ij) ...] (see LineTile), or the direction half only
 // (dir_only: the theta half is carried by P_th += step P_p in ranges with the tile-form gradient)
-int tile_stage1(Run &R, const LineSeg &sg, const float *dir, bool dir_only = false) {
+int tile_stage1(Run &R, const LineSeg &sg, const float *dir, bool dir_only = false, bool theta_only = false) {
     const Ctx c = line_ctx(R.c, sg.p0, sg.np);
     const LineTile &L = sg.lt;
     const LineClass &lc = L.lc;
@@ -1202,11 +1202,12 @@ int tile_stage1(Run &R, const LineSeg &sg, const float *dir, bool dir_only = fal
         return launch_tlr_pack(L.pack, L.npack, (const float2 *)c.w.th, L.PA, c.s, (const float2 *)dir, 2);
     }));
     GemmArgs g1 = gemm_args();   // stage 1: P_(p,i) = D_p[:, i d ...] PA_(p,i)
+    const int64_t half = theta_only ? nt * lc.kpad : 0;   // the theta half starts nt kpad columns in
     g1.A = c.w.Dc; g1.lda = c.ldk; g1.sA = c.lds * c.ldk; g1.sA2 = d;
-    g1.B = L.PA; g1.ldb = NA; g1.sB = nt * d * NA; g1.sB2 = d * NA;
+    g1.B = L.PA + half; g1.ldb = NA; g1.sB = nt * d * NA; g1.sB2 = d * NA;
     // stored regrouped by tile column: block j of row i -> Pcol_(p,j) at columns i kpad (each half)
-    g1.C = L.Pcol; g1.ldc = NA; g1.sC = nt * c.lds * NA; g1.sC2 = lc.kpad;
-    const int N = dir_only ? (int)(nt * lc.kpad) : (int)NA;
+    g1.C = L.Pcol + half; g1.ldc = NA; g1.sC = nt * c.lds * NA; g1.sC2 = lc.kpad;
+    const int N = (dir_only || theta_only) ? (int)(nt * lc.kpad) : (int)NA;
     g1.scat_kp = lc.kpad; g1.scat_w = (int)(nt * lc.kpad); g1.scat_lim = N; g1.scat_js = c.lds * NA - lc.kpad;
     g1.M = (int)c.lds; g1.N = N; g1.K = (int)d;
     g1.nz2 = (int)nt;
@@ -1277,6 +1278,34 @@ int tile_gradient(Run &R, const LineSeg &sg, float *g) {
     return TLRMDD_OK;
 }
 
+// r = D C(theta) - U for the problems of a range with the tile-form gradient, from the factors
+// (the tile low-rank product): P_th afresh by stage 1 on theta, then per tile column
+// r_:,j = sum_i P_th(ij) B_th(ij) - U_:,j with the FP64 partial sums of |r|^2 (K = nt kpad instead of nr).
+int tile_resid(Run &R, const LineSeg &sg) {
+    const LineTile &L = sg.lt;
+    const LineClass &lc = L.lc;
+    const int64_t NA = L.NA, d = lc.d, nt = lc.nt, kp = lc.kpad;
+    const bool halves = (nt * kp) % GEMM_BN == 0;
+    int st = tile_stage1(R, sg, R.c.w.th, false, halves);
+    if (st) return st;
+    const Ctx &c0 = R.c;
+    const int64_t rs = c0.lds * c0.ldk;
+    GemmArgs g = gemm_args();
+    g.A = L.Pcol + nt * kp; g.lda = NA; g.sA = nt * c0.lds * NA; g.sA2 = c0.lds * NA;
+    g.B = L.PB; g.ldb = d; g.sB = nt * NA * d; g.sB2 = NA * d;   // rows i kpad: B_th(ij)
+    g.C = c0.w.r + sg.p0 * rs; g.ldc = c0.ldk; g.sC = rs; g.sC2 = d;
+    g.E = c0.w.Us + sg.p0 * rs; g.lde = c0.ldk; g.sE = rs; g.sE2 = d;
+    g.partials = c0.w.partials + (int64_t)sg.p0 * c0.pstride; g.sP = c0.pstride;
+    g.sP2 = (c0.lds / GEMM_BM) * (d / GEMM_BN);   // the residual tiles of one tile column
+    g.M = (int)c0.lds; g.N = (int)d; g.K = (int)(nt * kp);
+    g.Me = (int)c0.ns; g.Ne = (int)d;             // E's columns are local to the tile column
+    g.nz2 = (int)nt;
+    HIP_TRY(timed(TLRMDD_K_GEMM_RESID, c0.s, [&] {
+        return launch_cgemm3m(GM_RESID, g, (int)(sg.np * nt), c0.s, GR_TILE);
+    }));
+    return TLRMDD_OK;
+}
+
 // After the update theta += step p: the theta half of Pcol follows (P_th += step P_p).
 int tile_pcol_update(Run &R, const LineSeg &sg) {
     const Ctx c = line_ctx(R.c, sg.p0, sg.np);
@@ -1310,15 +1339,25 @@ int fin_f(Run &R, int record, double lam, int nsum_parts) {
     return fin(R.c, f, nullptr, nsum_parts, 1);
 }
 
+// r = D C(theta) - U afresh: assembly and the dense product for the problems before the tile-form
+// gradient ranges, the tile low-rank product for those
 int objective_fresh(Run &R, int record, double lam) {
     Ctx &c = R.c;
-    if (int e0 = clear_plane_padding(R)) return e0;
-    HIP_TRY(timed(TLRMDD_K_ASSEMBLE, c.s, [&] {
-        return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)c.w.th,
-                               nullptr, R.X1, nullptr, c.s, c.bf16, R.x2w, c.lo_words());
-    }));
-    int e = gemm_resid(c, R.X1, R.xstride, c.w.Us, c.ldk, R.rstride, c.w.r);
-    if (e) return e;
+    int e = 0;
+    if (R.n_adj > 0) {
+        if ((e = clear_plane_padding(R))) return e;
+        const int na = (R.single || R.n_adj == c.nprob) ? c.D.n_asm : R.asm_first[R.n_adj];
+        HIP_TRY(timed(TLRMDD_K_ASSEMBLE, c.s, [&] {
+            return launch_assemble(false, c.D.tiles, c.D.asm_items, na, c.D.probs, (const float2 *)c.w.th,
+                                   nullptr, R.X1, nullptr, c.s, c.bf16, R.x2w, c.lo_words());
+        }));
+        Ctx ca = c;
+        ca.nprob = R.n_adj;
+        if ((e = gemm_resid(ca, R.X1, R.xstride, c.w.Us, c.ldk, R.rstride, c.w.r))) return e;
+    }
+    for (const LineSeg &sg : R.segs)
+        if (sg.tile && sg.lt.lc.grad)
+            if ((e = tile_resid(R, sg))) return e;
     if ((e = split_r_transpose(c))) return e;
     return fin_f(R, record, lam, resid_tiles(c));
 }
@@ -1462,7 +1501,6 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
     for (const LineSeg &sg : R.segs)
         if (sg.tile && sg.lt.lc.grad && iters > 0)
             if ((st = tile_stage1(R, sg, c.w.th))) return st;
-    bool pth_fresh = false;   // the next line search recomputes P_th too (after a residual recompute)
     for (int t = 0; t < iters; ++t) {
         // gradient from the tracked residual (eqs. DXLR): W = D^H r and the tile blocks of W' for the
         // problems before the tile-form gradient ranges, the tile form for those
@@ -1510,11 +1548,10 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
             if ((st = fin(c, fin_args(FIN_LAMTERMS, c.w.sc), c.D.tcount, 0, 2))) return st;
         }
         for (const LineSeg &sg : R.segs) {
-            // ranges with the tile-form gradient carry P_th from step to step; stage 1 forms it afresh
-            // (both halves) in the first iteration after every residual recompute, so its rounding
-            // does not accumulate over more iterations than the tracked residual's
-            const bool dir_only = sg.tile && sg.lt.lc.grad && (sg.lt.lc.nt * sg.lt.lc.kpad) % GEMM_BN == 0 &&
-                                  !pth_fresh;
+            // ranges with the tile-form gradient carry P_th from step to step (formed afresh with every
+            // residual recompute, so its rounding accumulates over no more iterations than the tracked
+            // residual's): stage 1 forms the direction half only where the halves fill whole tiles
+            const bool dir_only = sg.tile && sg.lt.lc.grad && (sg.lt.lc.nt * sg.lt.lc.kpad) % GEMM_BN == 0;
             if (sg.tile) st = line_products_tile(R, sg, dir_only);
             else if (sg.np == c.nprob) st = gemm_line(c, R.X1, R.X2, R.xstride);
             else st = gemm_line(line_ctx(c, sg.p0, sg.np), R.X1 + sg.p0 * R.xstride, R.X2 + sg.p0 * R.xstride,
@@ -1536,7 +1573,6 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
             if ((st = fin(c, fin_args(FIN_THNORM, c.w.sc), c.D.tcount, 0, 1))) return st;
         // residual: recomputed from theta every resid_refresh iterations, else updated in place
         const bool refresh = R.opts->resid_refresh > 0 && (t + 1) % R.opts->resid_refresh == 0;
-        pth_fresh = refresh;
         if (refresh) {
             if ((st = objective_fresh(R, record_base >= 0 ? record_base + t + 1 : -1, lam))) return st;
         } else {

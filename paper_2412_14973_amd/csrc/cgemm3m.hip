@@ -391,7 +391,10 @@ hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s
             else if (tile_stage) hipLaunchKernelGGL((cgemm3m_kernel<GM_STORE, 1>), grid, dim3(256), 0, s, a);
             else hipLaunchKernelGGL((cgemm3m_kernel<GM_STORE, 0>), grid, dim3(256), 0, s, a);
             break;
-        case GM_RESID: hipLaunchKernelGGL((cgemm3m_kernel<GM_RESID, 0>), grid, dim3(256), 0, s, a); break;
+        case GM_RESID:
+            if (tile_stage) hipLaunchKernelGGL((cgemm3m_kernel<GM_RESID, 1>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((cgemm3m_kernel<GM_RESID, 0>), grid, dim3(256), 0, s, a);
+            break;
         case GM_LINE:
             if (tile_stage) hipLaunchKernelGGL((cgemm3m_kernel<GM_LINE, 1>), grid, dim3(256), 0, s, a);
             else hipLaunchKernelGGL((cgemm3m_kernel<GM_LINE, 0>), grid, dim3(256), 0, s, a);

@@ -9,7 +9,10 @@
 // Stage 2 (one GEMM per tile column j): r_:,j = [P_0j | P_1j | ...] [B_0j; B_1j; ...] - U_:,j,
 // where P_ij is the column block of P_i that multiplies B_ij. The kernels below pack the
 // factor blocks into the GEMM operands and gather the P blocks; the products themselves run
-// on the FP32 MFMA GEMM.
+// on the FP32 MFMA GEMM. The solver's tile forms of the line search and the gradient use the
+// same factorisation (their stage 1 stores its blocks regrouped in its epilogue instead of a
+// gather); for them this file also holds the summation of the gradient's partial planes into
+// the factor gradients and the update of the carried theta half of stage 1.
 #include <algorithm>
 
 #include "common.hpp"

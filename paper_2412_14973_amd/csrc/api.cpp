@@ -841,7 +841,13 @@ template <typename T> std::vector<T> pick(const T *a, const std::vector<int> &id
 int ws_bytes_grouped(int op, int count, const tlrmdd_plan *plans, const tlrmdd_opts *opts, size_t *bytes,
                      std::vector<size_t> *parts = nullptr);
 
-// Runs impl(sub-batch arrays, workspace slice, bytes, stream) for every sub-batch: the first on
+// A second stream with its fork / join events for a run (see Run::side), or none.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+// Runs impl(sub-batch arrays, workspace slice, bytes, stream, side stream) for every sub-batch: the first on
 // `stream`, the others on pool streams that wait for `stream` first and are waited for at the end.
 template <typename Impl>
 int run_grouped(int op, int count, const tlrmdd_plan *plans, const void *const *D, const void *const *U,
@@ -856,7 +862,14 @@ int run_grouped(int op, int count, const tlrmdd_plan *plans, const void *const *
     if (!workspace || ws_bytes < need) return fail(TLRMDD_WORKSPACE, "workspace too small");
     std::vector<hipStream_t> ps;
     std::vector<hipEvent_t> ev;
-    if ((st = pool_get(S - 1, ps, ev))) return st;
+    // one sub-batch: pool stream 0 serves as the run's side stream (events 0 and 1 fork and join it)
+    if ((st = pool_get(S == 1 ? 1 : S - 1, ps, ev))) return st;
+    SideStream side;
+    if (S == 1) {
+        side.s = ps[0];
+        side.fork = ev[0];
+        side.join = ev[1];
+    }
     HIP_TRY(hipEventRecord(ev[S - 1], stream));
     for (int k = 0; k < S - 1; ++k) HIP_TRY(hipStreamWaitEvent(ps[k], ev[S - 1], 0));
     char *base = static_cast<char *>(workspace);
@@ -869,7 +882,7 @@ int run_grouped(int op, int count, const tlrmdd_plan *plans, const void *const *
         const std::vector<double *> gf = pick(fhist, m);
         const int k = (int)(g % S);
         const int e = impl((int)m.size(), gp.data(), gd.data(), gu.data(), gt.data(), gf.data(), base, parts[g],
-                           k == 0 ? stream : ps[k - 1]);
+                           k == 0 ? stream : ps[k - 1], S == 1 ? &side : nullptr);
         if (e && !first_err) first_err = e;
         base += align256(parts[g]);
     }
@@ -1172,6 +1185,10 @@ struct Run {
     std::vector<int> asm_first;      // first assembly item of every problem, and the total
     std::vector<int> grad_first;     // first gradient item of every problem, and the total
     int n_adj = 0;                   // problems before the tile-form gradient ranges (adjoint product)
+    // a second stream (default priority) on which the tile-form gradient runs beside the adjoint
+    // product of the other problems, and the events that fork it from and join it to c.s
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 // The context of problems p0 .. p0 + np - 1 of a run for the line-search products (complex64 operands
@@ -1240,8 +1257,9 @@ int line_products_tile(Run &R, const LineSeg &sg, bool dir_only = false) {
 
 // Gradient of the problems of a tile range in tile form (see GRAD_TILE_MAX_COST), into g. Needs the
 // theta half of Pcol for the current theta.
-int tile_gradient(Run &R, const LineSeg &sg, float *g) {
-    const Ctx c = line_ctx(R.c, sg.p0, sg.np);
+int tile_gradient(Run &R, const LineSeg &sg, float *g, hipStream_t stream) {
+    Ctx c = line_ctx(R.c, sg.p0, sg.np);
+    c.s = stream;
     const LineTile &L = sg.lt;
     const LineClass &lc = L.lc;
     const int64_t NA = L.NA, d = lc.d, nt = lc.nt, kp = lc.kpad, Wg = L.Wg;
@@ -1504,6 +1522,17 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
     for (int t = 0; t < iters; ++t) {
         // gradient from the tracked residual (eqs. DXLR): W = D^H r and the tile blocks of W' for the
         // problems before the tile-form gradient ranges, the tile form for those
+        // (the two parts write disjoint problems' gradients; with a side stream they run side by side)
+        const bool overlap = R.side && R.n_adj > 0 && R.n_adj < c.nprob;
+        hipStream_t gs = s;
+        if (overlap) {
+            HIP_TRY(hipEventRecord(R.fork, s));
+            HIP_TRY(hipStreamWaitEvent(R.side, R.fork, 0));
+            gs = R.side;
+        }
+        for (const LineSeg &sg : R.segs)
+            if (sg.tile && sg.lt.lc.grad)
+                if ((st = tile_gradient(R, sg, R.gcur, gs))) return st;
         if (R.n_adj > 0) {
             const Ctx ca = R.n_adj == c.nprob ? c : line_ctx(c, 0, R.n_adj);
             if ((st = gemm_adjoint(ca, c.w.r, R.X1, R.xstride))) return st;
@@ -1513,9 +1542,10 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
                                    (float2 *)R.gcur, s);
             }));
         }
-        for (const LineSeg &sg : R.segs)
-            if (sg.tile && sg.lt.lc.grad)
-                if ((st = tile_gradient(R, sg, R.gcur))) return st;
+        if (overlap) {
+            HIP_TRY(hipEventRecord(R.join, R.side));
+            HIP_TRY(hipStreamWaitEvent(s, R.join, 0));
+        }
         if (lam != 0.0) HIP_TRY(launch_reg_grad(c.D.tsegs, nt, R.gcur, c.w.th, cen, (float)(2.0 * lam), s));
         // direction: steepest descent first, then L-BFGS in vector-free form (Gram pass, two-loop
         // recursion on the (2 m + 1)-term coefficient vectors on the device, one combination pass)
@@ -1595,10 +1625,15 @@ int run_finish(Run &R, const tlrmdd_plan *plans, void *const *theta) {
 
 int solve_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const void *const *U,
                void *const *theta, const tlrmdd_opts *opts, double *const *fhist, void *workspace,
-               size_t ws_bytes, hipStream_t s) {
+               size_t ws_bytes, hipStream_t s, const SideStream *side = nullptr) {
     Run R;
     int st = run_setup(R, 2, nprob, plans, D, U, theta, opts, fhist, workspace, ws_bytes, s);
     if (st) return st;
+    if (side) {
+        R.side = side->s;
+        R.fork = side->fork;
+        R.join = side->join;
+    }
     const double lam = opts->lambda;
     if (lam != 0.0) {
         HIP_TRY(launch_pen(R.c.D.tsegs, R.nt, R.c.w.th, nullptr, nullptr, R.c.w.partials, s));
@@ -1625,11 +1660,16 @@ int check_admm(const tlrmdd_admm_opts *a) {
 // device. f-history: data misfit at the start and after every X-update.
 int admm_impl(int nprob, const tlrmdd_plan *plans, const void *const *D, const void *const *U,
               void *const *theta, const tlrmdd_admm_opts *aopts, double *const *fhist, void *workspace,
-              size_t ws_bytes, hipStream_t s) {
+              size_t ws_bytes, hipStream_t s, const SideStream *side = nullptr) {
     int st = check_admm(aopts);
     if (st) return st;
     Run R;
     if ((st = run_setup(R, 3, nprob, plans, D, U, theta, &aopts->inner, fhist, workspace, ws_bytes, s))) return st;
+    if (side) {
+        R.side = side->s;
+        R.fork = side->fork;
+        R.join = side->join;
+    }
     Ctx &c = R.c;
     if ((st = objective_fresh(R, -1, 0.0))) return st;
     auto record = [&](int k) -> int {
@@ -1876,8 +1916,8 @@ int tlrmdd_admm_batched(int count, const tlrmdd_plan *plans, const void *const *
         return admm_impl(count, plans, D, U, theta_inout, opts, f_hist_dev, workspace, ws_bytes, stream);
     return run_grouped(3, count, plans, D, U, theta_inout, &opts->inner, f_hist_dev, workspace, ws_bytes, stream,
                        [&](int n, const tlrmdd_plan *p, const void *const *d, const void *const *u, void *const *t,
-                           double *const *f, void *w, size_t b, hipStream_t s) {
-                           return admm_impl(n, p, d, u, t, opts, f, w, b, s);
+                           double *const *f, void *w, size_t b, hipStream_t s, const SideStream *side) {
+                           return admm_impl(n, p, d, u, t, opts, f, w, b, s, side);
                        });
 }
 
@@ -1893,8 +1933,8 @@ int tlrmdd_solve_batched(int count, const tlrmdd_plan *plans, const void *const 
         return solve_impl(count, plans, D, U, theta_inout, opts, f_hist_dev, workspace, ws_bytes, stream);
     return run_grouped(2, count, plans, D, U, theta_inout, opts, f_hist_dev, workspace, ws_bytes, stream,
                        [&](int n, const tlrmdd_plan *p, const void *const *d, const void *const *u, void *const *t,
-                           double *const *f, void *w, size_t b, hipStream_t s) {
-                           return solve_impl(n, p, d, u, t, opts, f, w, b, s);
+                           double *const *f, void *w, size_t b, hipStream_t s, const SideStream *side) {
+                           return solve_impl(n, p, d, u, t, opts, f, w, b, s, side);
                        });
 }
 

@@ -74,15 +74,18 @@ def source_sha(files):
 
 ADJOINT_KERNEL = {"fp32": "cgemm_f32_kernel<GM_STORE>", "fp32_3m": "cgemm3m_kernel<GM_STORE, 0>",
                   "bf16x3": "cgemm_bf16x3_kernel<GM_STORE>"}
+LINE_KERNEL = {"fp32": "cgemm_f32_kernel<GM_LINE>", "fp32_3m": "cgemm3m_kernel<GM_LINE, 0>",
+               "bf16x3": "cgemm_bf16x3_kernel<GM_LINE>"}
+FORM_FLOPS = {"fp32": "four-product FP32, 8 m n k", "fp32_3m": "three-product FP32, 6 m n k",
+              "bf16x3": "BF16 hi+lo split, 24 m n k in BF16"}
 
 
 def precision_info(tl, name):
-    """(library constant, dtype label, config label, line-search kernel, peak key, executed MFMA flops
-    per algorithmic 8mnk flop)."""
+    """(library constant, dtype label, config label)."""
     return {
-        "fp32": (tl.FP32, "f32", "fp32-mfma", "cgemm_f32_kernel<GM_LINE>", "f32", 1.0),
-        "fp32_3m": (tl.FP32_3M, "f32", "fp32-3m-mfma", "cgemm3m_kernel<GM_LINE, 0>", "f32", 0.75),
-        "bf16x3": (tl.BF16X3, "bf16x3", "bf16x3-mfma", "cgemm_bf16x3_kernel<GM_LINE>", "bf16", 3.0),
+        "fp32": (tl.FP32, "f32", "fp32-mfma"),
+        "fp32_3m": (tl.FP32_3M, "f32", "fp32-3m-mfma"),
+        "bf16x3": (tl.BF16X3, "bf16x3", "bf16x3-mfma"),
     }[name]
 
 
@@ -109,7 +112,7 @@ def measured_traffic(nfreq, workload, precision, mode, kind):
         sha = source_sha(files)
     except OSError:
         return None
-    if rec.get("source_sha256") != sha or workload != "batched" or nfreq != 64:
+    if rec.get("source_sha256") != sha or workload != rec.get("workload") or nfreq != rec.get("frequencies"):
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -439,6 +442,9 @@ def main():
                     help="batched solve: sub-batches on their own streams (problem i in sub-batch i %% streams)")
     ap.add_argument("--resid-refresh", type=int, default=20,
                     help="error table: also an FP32 solve that recomputes r = D C(theta) - U every this many iterations")
+    ap.add_argument("--no-extra", dest="extra", action="store_false",
+                    help="batched workload: skip the nr 64 latency and nr 4096 throughput objects")
+    ap.add_argument("--large-steps", type=int, default=2, help="timed steps of the nr 4096 object")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -473,20 +479,145 @@ def main():
     if args.workload == "tlr":
         print(json.dumps(tlr_product(tl, torch, args)), flush=True)
         return
-    prec, dtype, prec_name, line_kernel, peak_name, exec_factor = precision_info(tl, args.precision)
-    adjoint_kernel = ADJOINT_KERNEL[args.precision]
-    wl = synth.batched() if args.workload == "batched" else synth.large()
-    nfreq = args.nfreq or (len(wl.freqs) if args.workload == "batched" else 4)
-    iters = args.iters or wl.iters
+    prec, dtype, prec_name = precision_info(tl, args.precision)[:3]
+    line_products = {"dense": tl.LINE_DENSE, "tile": tl.LINE_TILE, "tile-grad": tl.LINE_TILE_GRAD}[args.line_products]
     admm = args.solver == "admm"
+    if args.workload == "batched":
+        wl = synth.batched()
+        nfreq = args.nfreq or len(wl.freqs)
+        inputs = build_inputs(wl, torch, tl, nfreq)
+    else:
+        wl = synth.large()
+        nfreq = args.nfreq or len(wl.freqs)
+        inputs = device_inputs(wl, torch, tl, nfreq)
+    run = measure_workload(tl, torch, args, wl, inputs, args.steps, args.warmup, prec, line_products, admm)
+    line = {
+        "metric": "TLR-MDD grad iters/s",
+        "value": run["value"],
+        "unit": "grad-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": dict(run["config"], precision=prec_name),
+        "roofline": run["roofline"],
+        "hbm_passes": run["hbm_passes"],
+        "mfma_frac_all_gemms": run["mfma_frac_all_gemms"],
+        "kernels": run["kernels"],
+        "objective": run["objective"],
+    }
+    if args.workload == "batched" and not admm and args.nfreq is None and args.extra:
+        log("nr 64 parity workload: microseconds per iteration")
+        line["small_workload"] = small_latency(tl, torch, prec, args)
+        log("nr 4096 workload (32 frequencies, inputs generated on the device)")
+        wl3 = synth.large()
+        inputs3 = device_inputs(wl3, torch, tl, len(wl3.freqs))
+        run3 = measure_workload(tl, torch, args, wl3, inputs3, args.large_steps, 1, prec, line_products, False)
+        del inputs3
+        line["large_workload"] = {k: run3[k] for k in ("value", "unit", "ms_per_step", "steps", "config", "roofline",
+                                                      "hbm_passes", "mfma_frac_all_gemms", "kernels", "objective")}
+    if not args.no_cpu_baseline and prec != tl.BF16X3 and args.workload == "batched":
+        log("timing the CPU oracle")
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+def device_inputs(wl, torch, tl, nfreq):
+    """Inputs of a workload generated on the device (same recipe, torch's device generator)."""
+    import synth
+    geom = wl.geometry()
+    dev = torch.device("cuda")
+    Ds, Us, ths, plans = [], [], [], []
+    t0 = time.time()
+    for i in range(nfreq):
+        D, U, th = synth.device_workload_problem(wl, i, dev)
+        Ds.append(D)
+        Us.append(U)
+        ths.append(th)
+        plans.append(tl.Plan.from_layout(wl.layout(i), geom.ns))
+        if (i + 1) % 8 == 0:
+            torch.cuda.synchronize()
+            log(f"device inputs {i + 1}/{nfreq} ({time.time() - t0:.1f}s)")
+    return geom, Ds, Us, ths, plans
+
+
+def small_latency(tl, torch, prec, args):
+    """The nr 64 parity workload (8 frequencies, 50 iterations) as one batched solve: wall time per
+    iteration (launch-latency bound: about 20 launches per iteration)."""
+    import synth
+    wl = synth.small()
+    geom, Ds, Us, ths, plans = build_inputs(wl, torch, tl, len(wl.freqs))
+    dev = torch.device("cuda")
+    perm = torch.from_numpy(tl.hilbert_order(geom.rec_ix, geom.rec_iy)).to(dev)
+    Dh = [tl.permute_columns(D, perm) for D in Ds]
+    Uh = [tl.permute_columns(U, perm) for U in Us]
+    out = {}
+    for label, fn in (
+            ("batched_8freq", lambda: tl.solve_batched(plans, Dh, Uh, ths, wl.iters, precision=prec)),
+            ("single_freq", lambda: tl.solve(plans[0], Dh[0], Uh[0], ths[0], wl.iters, precision=prec))):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(10):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        med = ts[len(ts) // 2]
+        out[label] = {"us_per_iteration": med / wl.iters * 1e6, "ms_per_solve": med * 1e3}
+    out["config"] = {"workload": wl.name, "iters": wl.iters, "frequencies": len(wl.freqs)}
+    return out
+
+
+def kernel_table(kt):
+    """Per kernel kind: launches, average duration, and (from the library's per-launch work counts) the
+    rate of the product form's real flops against its instruction type's peak, the complex-equivalent
+    rate (8 m n k), and the algorithmic HBM bytes per second against 8 TB/s."""
+    out = {}
+    for k, ms in kt.ms.items():
+        n = kt.launches[k]
+        if n == 0 or ms <= 0:
+            continue
+        e = {"launches": n, "avg_ms": ms / n}
+        sec = ms * 1e-3
+        if kt.flops[k] > 0:
+            dt = kt.dtype[k]
+            e["flop_dtype"] = dt
+            e["tflops"] = kt.flops[k] / sec / 1e12
+            if dt in PEAK:
+                e["frac_peak"] = kt.flops[k] / sec / PEAK[dt]
+            e["complex_equiv_tflops"] = kt.cflops[k] / sec / 1e12
+        if kt.bytes[k] > 0:
+            e["algorithmic_bytes_per_launch"] = kt.bytes[k] / n
+            e["gbps"] = kt.bytes[k] / sec / 1e9
+            e["frac_hbm"] = kt.bytes[k] / sec / HBM_PEAK
+        out[k] = e
+    return out
+
+
+HBM_ROWS = {   # hot-path steps bound by HBM: the kernel kinds that carry them
+    "a2_permute": ("permute",), "a2_stage": ("stage",), "a3_assemble_dir": ("assemble_dir",),
+    "a6_tile_gradients": ("grad",), "a8_gram": ("gram",), "a8_combine": ("combine",),
+    "a7_theta_update": ("theta_update",), "a7_resid_update": ("resid_update",),
+}
+
+
+def measure_workload(tl, torch, args, wl, inputs, steps, warmup, prec, line_products, admm):
+    geom, Ds, Us, ths, plans = inputs
+    nfreq = len(plans)
+    iters = args.iters or wl.iters
     lams = (10.0, 1.0, 0.1)
     if admm:
         iters = len(lams) * args.admm_outer * args.admm_inner
-    geom, Ds, Us, ths, plans = build_inputs(wl, torch, tl, nfreq)
     dev = torch.device("cuda")
     perm = torch.from_numpy(tl.hilbert_order(geom.rec_ix, geom.rec_iy)).to(dev)
     ns, nr = geom.ns, geom.nr
-    line_products = {"dense": tl.LINE_DENSE, "tile": tl.LINE_TILE, "tile-grad": tl.LINE_TILE_GRAD}[args.line_products]
     opts = tl.make_opts(iters, precision=prec, streams=args.streams, line_products=line_products)
     if admm:
         aopts = tl.make_admm_opts(lams, args.admm_outer, args.admm_inner, precision=prec, streams=args.streams,
@@ -496,7 +627,7 @@ def main():
         ws = torch.empty(tl.batched_workspace_bytes(plans, opts), dtype=torch.uint8, device=dev)
     out_th = [t.clone() for t in ths]
     out_fh = [torch.empty(iters + 1, dtype=torch.float64, device=dev) for _ in range(nfreq)]
-    log(f"workspace {ws.numel() / 2**30:.2f} GiB, {nfreq} frequencies, {iters} iterations"
+    log(f"{wl.name}: workspace {ws.numel() / 2**30:.2f} GiB, {nfreq} frequencies, {iters} iterations"
         + (f" (ADMM {len(lams)} stages x {args.admm_outer} x {args.admm_inner})" if admm else ""))
 
     def step():
@@ -510,121 +641,77 @@ def main():
             tl.solve_batched(plans, Dh, Uh, ths, iters, precision=prec, workspace=ws, out_thetas=out_th,
                              out_fhist=out_fh, streams=args.streams, line_products=line_products)
 
-    for w in range(args.warmup):
+    for w in range(warmup):
         step()
         torch.cuda.synchronize()
-        log(f"warmup {w + 1}/{args.warmup} done")
+        log(f"warmup {w + 1}/{warmup} done")
     torch.cuda.synchronize()
     with tl.KernelTimer() as kt:
         t0 = time.perf_counter()
-        for s in range(args.steps):
+        for s in range(steps):
             step()
             torch.cuda.synchronize()
-            log(f"step {s + 1}/{args.steps} done")
+            log(f"step {s + 1}/{steps} done")
         t1 = time.perf_counter()
     elapsed = t1 - t0
     f_final = [float(f[-1].item()) for f in out_fh]
     f_first = [float(f[0].item()) for f in out_fh]
-    value = nfreq * iters * args.steps / elapsed
-
-    # Algorithmic flops (complex products counted as 8 m n k) of each product kind over the timed
-    # region, from the problems each kind covers: the adjoint every problem and iteration, the
-    # dense line-search product the problems whose line search is dense, the tile-form stages the
-    # others (their padded flops: 40 ns nr nt kpad per problem), the residual product
-    # every problem at each recompute (every sub-batch recomputes at the same iterations).
+    value = nfreq * iters * steps / elapsed
     forms = [tl.line_form(p, prec, line_products) for p in plans]
     n_tile = sum(1 for f in forms if f[0])
     n_tgrad = sum(1 for f in forms if f[0] == 2)
-    n_dense = nfreq - n_tile
     nstreams = max(1, min(args.streams, nfreq))
-    n_groups = nstreams
-    steps_iters = args.steps * iters
-    tile_flops = sum(40.0 * ns * nr * (nr // int(p.tile_size[0])) * k for p, (t, k) in zip(plans, forms) if t)
-
-    def grad_width(p, k):   # nt kpad rounded up to 128
-        return -(-(nr // int(p.tile_size[0])) * k // 128) * 128
-    grad_flops = sum(24.0 * ns * nr * grad_width(p, k) for p, (t, k) in zip(plans, forms) if t == 2)
-    total_flops = {
-        "gemm_adjoint": 8.0 * nr * ns * nr * (nfreq - n_tgrad) * steps_iters,
-        "grad_tile": grad_flops * steps_iters,
-        "gemm_line": 16.0 * ns * nr * nr * n_dense * steps_iters,
-        "line_tile": tile_flops * steps_iters,
-        "gemm_resid": 8.0 * ns * nr * nr * nfreq * kt.launches["gemm_resid"] / max(1, n_groups),
-    }
-    # algorithmic bytes per problem: operands read once, outputs written once
-    bytes_per_prob = {"gemm_adjoint": 8.0 * (2 * nr * ns + nr * nr), "gemm_line": 6 * 8.0 * ns * nr}
-    kernels = {}
-    for k, ms in kt.ms.items():
-        n = kt.launches[k]
-        if n == 0:
-            continue
-        entry = {"launches": n, "avg_ms": ms / n}
-        if k in total_flops and total_flops[k] > 0:
-            rate = total_flops[k] / (ms * 1e-3)   # = per-launch flops / average launch duration
-            entry["tflops"] = rate / 1e12
-            entry["frac_f32_peak"] = rate / PEAK["f32"]
-            entry["executed_frac_" + peak_name + "_peak"] = exec_factor * rate / PEAK[peak_name]
-        kernels[k] = entry
-    # the roofline kernel: the product kind with the most algorithmic flops (with the tile-form line
-    # search the dense line product of the remaining frequencies and the adjoint take about equal time)
-    # (all frequencies in tile form: the tile-form stages)
-    gemm_kinds = [k for k in ("gemm_line", "gemm_adjoint") if kt.launches[k] > 0] or \
-        [k for k in ("line_tile", "grad_tile") if kt.launches[k] > 0]
-    dom_kind = max(gemm_kinds, key=lambda k: total_flops[k])
+    kernels = kernel_table(kt)
+    # the roofline kernel: the matrix-core product kind that takes the most time
+    gemm_kinds = [k for k in ("gemm_line", "gemm_adjoint", "line_tile", "grad_tile", "gemm_resid", "resid_tile")
+                  if k in kernels and "tflops" in kernels[k]]
+    dom_kind = max(gemm_kinds, key=lambda k: kt.ms[k])
     dom = kernels[dom_kind]
-    achieved = dom["tflops"] * 1e12
-    peak = PEAK[peak_name]
-    dom_probs = {"gemm_line": n_dense, "gemm_adjoint": nfreq - n_tgrad, "line_tile": n_tile,
-                 "grad_tile": n_tgrad}[dom_kind] * steps_iters / kt.launches[dom_kind]
-    dom_name = {"gemm_line": line_kernel + " ([a|b] = D [X1|X2])", "gemm_adjoint": adjoint_kernel + " (W = D^H r)",
+    dom_name = {"gemm_line": LINE_KERNEL[args.precision] + " ([a|b] = D [X1|X2], dense line search)",
+                "gemm_adjoint": ADJOINT_KERNEL[args.precision] + " (W = D^H r)",
                 "line_tile": "cgemm3m_kernel<GM_STORE|GM_LINE, 1> (tile-form line-search stages)",
-                "grad_tile": "cgemm3m_kernel<GM_STORE, 1|2> (tile-form gradient products)"}[dom_kind]
-    gemm_flops = sum(total_flops[k] for k in total_flops)
-    gemm_s = sum(kt.ms[k] for k in total_flops) * 1e-3
+                "grad_tile": "cgemm3m_kernel<GM_STORE, 1|2> (tile-form gradient products)",
+                "gemm_resid": "r = D X - U", "resid_tile": "tile-form residual product"}[dom_kind]
     mode = ("tile_grad" if n_tgrad else "tile") if n_tile else "dense"
-    line = {
-        "metric": "TLR-MDD grad iters/s",
-        "value": value,
-        "unit": "grad-iters/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": dtype,
-        "data": "synthetic",
-        "config": {"workload": wl.name if nfreq == len(wl.freqs) else f"{wl.name}[first {nfreq}]",
-                   "nr": nr, "ns": ns, "frequencies": nfreq, "iters": iters,
-                   "resid_refresh": tl.RESID_REFRESH, "streams": nstreams,
-                   "line_products": f"{args.line_products} ({n_tile} of {nfreq} frequencies in tile form"
-                                    + (f", {n_tgrad} with the gradient in tile form)" if n_tgrad else ")"),
-                   "optimizer": ("admm(lambda 10,1,0.1; %d x %d L-BFGS(m=5) per stage)" % (args.admm_outer,
-                                                                                        args.admm_inner))
-                   if admm else "lbfgs(m=5)",
-                   "precision": prec_name},
-        "roofline": {"bound": "mfma",
-                     "kernel": dom_name,
-                     "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak,
-                     "executed_tflops": exec_factor * achieved / 1e12,
-                     "executed_frac": exec_factor * achieved / peak,
-                     "traffic": (measured_traffic(nfreq, args.workload, args.precision, mode, dom_kind)
-                                 if nstreams == 1 else None),
-                     "algorithmic_bytes": (bytes_per_prob[dom_kind] * dom_probs if dom_kind in bytes_per_prob
-                                           else None),
-                     "problems_per_launch": dom_probs,
-                     **({"note": "launches of the %d sub-batches overlap in time: a launch's duration includes "
-                                 "the sharing of the GPU" % nstreams} if nstreams > 1 else {})},
-        "mfma_frac_all_gemms": gemm_flops / gemm_s / PEAK["f32"],
-        "kernels": kernels,
-        "objective": {"f0_mean": sum(f_first) / nfreq, "fT_mean": sum(f_final) / nfreq},
+    traffic = (measured_traffic(nfreq, wl.name, args.precision, mode, dom_kind) if nstreams == 1 else None)
+    roofline = {
+        "bound": "mfma",
+        "kernel": dom_name,
+        "achieved": dom["tflops"], "peak": PEAK[dom["flop_dtype"]] / 1e12, "unit": "TFLOP/s",
+        "frac": dom["frac_peak"],
+        "flops": "real flops of the product form that runs, true sizes: " + FORM_FLOPS[args.precision]
+                 if dom_kind in ("gemm_line", "gemm_adjoint", "gemm_resid") else
+                 "real flops of the three-product FP32 form (6 m n k), true ranks",
+        "complex_equiv_tflops": dom["complex_equiv_tflops"],
+        "traffic": traffic,
+        "algorithmic_bytes": dom["algorithmic_bytes_per_launch"],
+        "avg_launch_ms": dom["avg_ms"],
+        "launches": dom["launches"],
+        **({"note": "launches of the %d sub-batches overlap in time: a launch's duration includes "
+                    "the sharing of the GPU" % nstreams} if nstreams > 1 else {}),
     }
-    if not args.no_cpu_baseline and prec != tl.BF16X3:
-        log("timing the CPU oracle")
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
-    print(json.dumps(line), flush=True)
+    mm_flops = sum(kt.flops[k] for k in gemm_kinds if kt.dtype[k] == "f32")
+    mm_s = sum(kt.ms[k] for k in gemm_kinds if kt.dtype[k] == "f32") * 1e-3
+    hbm = {}
+    for row, kinds in HBM_ROWS.items():
+        ms = sum(kt.ms[k] for k in kinds)
+        b = sum(kt.bytes[k] for k in kinds)
+        if ms > 0 and b > 0:
+            hbm[row] = {"gbps": b / (ms * 1e-3) / 1e9, "frac_hbm": b / (ms * 1e-3) / HBM_PEAK,
+                        "ms_per_step": ms / steps}
+    config = {"workload": wl.name if nfreq == len(wl.freqs) else f"{wl.name}[first {nfreq}]",
+              "nr": nr, "ns": ns, "frequencies": nfreq, "iters": iters,
+              "resid_refresh": tl.RESID_REFRESH, "streams": nstreams,
+              "line_products": f"{args.line_products} ({n_tile} of {nfreq} frequencies in tile form"
+                               + (f", {n_tgrad} with the gradient in tile form)" if n_tgrad else ")"),
+              "optimizer": ("admm(lambda 10,1,0.1; %d x %d L-BFGS(m=5) per stage)" % (args.admm_outer,
+                                                                                   args.admm_inner))
+              if admm else "lbfgs(m=5)"}
+    return {"value": value, "unit": "grad-iters/s", "ms_per_step": elapsed / steps * 1e3, "steps": steps,
+            "config": config, "roofline": roofline, "hbm_passes": hbm,
+            "mfma_frac_all_gemms": (mm_flops / mm_s / PEAK["f32"]) if mm_s > 0 else None,
+            "kernels": kernels,
+            "objective": {"f0_mean": sum(f_first) / nfreq, "fT_mean": sum(f_final) / nfreq}}
 
 
 if __name__ == "__main__":

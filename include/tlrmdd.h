@@ -54,6 +54,8 @@ extern "C" {
 #define TLRMDD_HIP_ERROR        3  /* a HIP runtime call failed                  */
 #define TLRMDD_NONFINITE        4  /* non-finite value met (solve)               */
 #define TLRMDD_UNSUPPORTED      5  /* e.g. unknown precision                     */
+#define TLRMDD_NOT_CONVERGED    6  /* per-tile Jacobi SVD still rotating after its
+                                      sweep limit (outputs not written)          */
 
 /* ---- precisions of the bulk complex products ------------------------------ */
 #define TLRMDD_FP32      0  /* FP32 MFMA, complex as a real 2x2 block (4 real products) */
@@ -93,12 +95,16 @@ typedef struct {
     int32_t resid_refresh;  /* recompute r = D C(theta) - U every this many iters (0 = never); the
                                tracked r accumulates FP32 rounding, 20 keeps long solves oracle-close */
     int32_t streams;        /* batched calls: 0 or 1 = all problems in one launch per phase on
-                               `stream`; 2..8 = problem i in sub-batch i % streams, each sub-batch
-                               on its own stream (the first on `stream`, the others on streams the
-                               library creates once per device at default priority, joined to
-                               `stream` with events), so the matrix-core products of one
-                               sub-batch overlap the HBM-bound passes of another. Results are
-                               bit-identical for every value; single-problem calls ignore it. */
+                               `stream` (with one library-owned side stream on which the tile-form
+                               gradient runs beside the adjoint product of the other problems);
+                               2..8 = problem i in sub-batch i % streams, each sub-batch on its own
+                               stream (the first on `stream`, the others on streams the library
+                               creates at default priority for each (device, caller stream) pair
+                               and keeps until the process ends, forked from and joined to
+                               `stream` with events owned by the call), so the matrix-core
+                               products of one sub-batch overlap the HBM-bound passes of another.
+                               Results are bit-identical for every value; single-problem calls
+                               ignore it. */
     int32_t line_products;  /* TLRMDD_LINE_DENSE (0): the line search's [a | b] = D [X1 | X2] from
                                the assembled X1, X2; TLRMDD_LINE_TILE (1): in tile form wherever that
                                needs fewer flops (precisions TLRMDD_FP32_3M and TLRMDD_BF16X3; see
@@ -120,7 +126,9 @@ typedef struct {
 #define TLRMDD_LINE_TILE  1
 #define TLRMDD_LINE_TILE_GRAD 2
 
-/* Opaque plan: validated layout plus device-side tile tables. */
+/* Opaque plan: validated layout plus device-side tile tables. The calls take a
+ * plan instead of the layout itself so that the tile tables of a frequency are
+ * built and uploaded once (at plan creation) and not on every call. */
 typedef struct tlrmdd_plan_s *tlrmdd_plan;
 
 /* Message for a status code (static storage). */
@@ -194,8 +202,8 @@ int tlrmdd_solve(tlrmdd_plan plan, const void *D, const void *U, void *theta_ino
  * with 2.5 kpad / d <= 0.6, where kpad is the largest rank rounded up so
  * that a stage-1 row of 2 nt blocks of kpad columns is a whole number of
  * 128-column tiles (2.5 kpad / d: the tile form's share of the dense
- * products' flops; conclusions of the paper: the TLR product as the way to
- * cut the cost of the dense products); 2 when the gradient is in tile form
+ * products' flops; the paper's Discussion section names the TLR product as
+ * the way to cut the cost of the dense products); 2 when the gradient is in tile form
  * as well (TLRMDD_LINE_TILE_GRAD and 3 Wg / nr <= 0.6). In TLRMDD_BF16X3 mode
  * both bounds are 0.3: the BF16 dense products they replace run about twice
  * as fast. In a batched call a
@@ -253,14 +261,14 @@ int tlrmdd_admm_batched(int count, const tlrmdd_plan *plans, const void *const *
                         const tlrmdd_admm_opts *opts, double *const *f_hist_dev,
                         void *workspace, size_t ws_bytes, hipStream_t stream);
 
-/* Tile low-rank product (Conclusions: the TLR matrix-matrix product as the way to cut the
- * dense products' cost): f = 1/2 ||D C(theta) - U||^2 without forming X. With every tile
+/* Tile low-rank product (Discussion section: the TLR matrix-matrix product as the way to cut
+ * the dense products' cost): f = 1/2 ||D C(theta) - U||^2 without forming X. With every tile
  * X_ij = A_ij B_ij (i > j: L_ij R_ij; i < j: R_ji^T L_ji^T; Q Q^T; dense: I and (Z+Z^T)/2),
  * P_i = D_:,i [A_i0 | A_i1 | ...] per tile row, then r_:,j = sum_i P_ij B_ij - U_:,j per tile
  * column: 16 ns sum_ij d_i k_ij flops instead of 8 ns nr^2 (about 2k/d of the dense product).
  * FP32 MFMA. D, U: device ns x nr complex64; theta: device theta_size complex64; f_dev:
- * device double; r_out: device ns x nr complex64 or NULL. Stream ordered after a blocking
- * upload of the packing tables. Workspace: tlrmdd_workspace_bytes_tlr. */
+ * device double; r_out: device ns x nr complex64 or NULL. Stream ordered (the packing tables
+ * go through a library-owned pinned buffer). Workspace: tlrmdd_workspace_bytes_tlr. */
 int tlrmdd_workspace_bytes_tlr(tlrmdd_plan plan, size_t *bytes);
 int tlrmdd_forward_tlr(tlrmdd_plan plan, const void *D, const void *U, const void *theta,
                        double *f_dev, void *r_out, void *workspace, size_t ws_bytes,
@@ -327,30 +335,60 @@ int hilbert_order(const int32_t *ix, const int32_t *iy, int64_t n, int64_t *perm
 
 /* Column gather Dhat = D S (eq. axb_sd): out[s, k] = in[s, perm[k]].
  * in, out: device, rows x cols complex64 (must not overlap);
- * perm: device int64, cols entries, each in [0, cols). */
+ * perm: device int64, cols entries, each expected in [0, cols). The device
+ * entries are checked in the kernel: an entry outside [0, cols) writes a zero
+ * column k and sets *bad_dev to 1 (bad_dev: device int32 or NULL; the library
+ * only ever writes 1 into it, so the caller clears it before the call). The
+ * call is stream ordered: read *bad_dev after synchronising the stream. */
 int tlrmdd_permute_columns(const void *in, const int64_t *perm, void *out,
-                           int64_t rows, int64_t cols, hipStream_t stream);
+                           int64_t rows, int64_t cols, int32_t *bad_dev, hipStream_t stream);
 
 /* ---- kernel timing (instrumentation) -------------------------------------
  * Between tlrmdd_timing_begin() and tlrmdd_timing_end(), every launch of the
  * kernel kinds below made by this library (any thread, any stream) is
- * bracketed by two HIP events recorded on its own stream. timing_end waits
- * for the last event, then writes the summed elapsed milliseconds and the
- * launch count of each kind into ms[TLRMDD_K_NKINDS] and
- * launches[TLRMDD_K_NKINDS] (host arrays, either may be NULL). Calls that
- * run while timing is active are serialised with the recorder by a mutex. */
-#define TLRMDD_K_GEMM_RESID    0  /* r = D X - U with FP64 |r|^2 partials      */
-#define TLRMDD_K_GEMM_ADJOINT  1  /* W = D^H r                                 */
-#define TLRMDD_K_GEMM_LINE     2  /* [a | b] = D [X1 | X2] + line-search sums  */
-#define TLRMDD_K_ASSEMBLE      3  /* X = C(theta)                              */
-#define TLRMDD_K_ASSEMBLE_DIR  4  /* X1, X2 of the line search                 */
-#define TLRMDD_K_GRAD          5  /* per-tile gradient contractions            */
-#define TLRMDD_K_LINE_PACK     6  /* tile-form line search: factor packing */
-#define TLRMDD_K_LINE_TILE     7  /* tile-form line search: both product stages */
-#define TLRMDD_K_GRAD_TILE     8  /* tile-form gradient: its three products */
-#define TLRMDD_K_NKINDS        9
+ * bracketed by two HIP events recorded on its own stream, and its algorithmic
+ * work is counted on the true (unpadded) sizes and ranks. timing_end waits for
+ * the last event and writes one tlrmdd_kernel_stats per kind into
+ * stats[TLRMDD_K_NKINDS] (host array, may be NULL). Calls that run while
+ * timing is active are serialised with the recorder by a mutex. */
+#define TLRMDD_K_GEMM_RESID    0  /* r = D X - U with FP64 |r|^2 partials (dense)            */
+#define TLRMDD_K_GEMM_ADJOINT  1  /* W = D^H r                                              */
+#define TLRMDD_K_GEMM_LINE     2  /* [a | b] = D [X1 | X2] + line-search sums               */
+#define TLRMDD_K_ASSEMBLE      3  /* X = C(theta)                                           */
+#define TLRMDD_K_ASSEMBLE_DIR  4  /* X1, X2 of the line search                              */
+#define TLRMDD_K_GRAD          5  /* per-tile gradient contractions                         */
+#define TLRMDD_K_LINE_PACK     6  /* tile forms: factor packing, gradient summation, P update */
+#define TLRMDD_K_LINE_TILE     7  /* tile-form line search: both product stages             */
+#define TLRMDD_K_GRAD_TILE     8  /* tile-form gradient: its three products                 */
+#define TLRMDD_K_RESID_TILE    9  /* tile-form residual product r_:,j = sum_i P_ij B_ij - U  */
+#define TLRMDD_K_STAGE        10  /* staging of D (padded copy, D^H, split planes) and of U   */
+#define TLRMDD_K_PERMUTE      11  /* column gather D S (tlrmdd_permute_columns)               */
+#define TLRMDD_K_GRAM         12  /* L-BFGS Gram pass                                        */
+#define TLRMDD_K_COMBINE      13  /* L-BFGS direction p = sum_b c_b v_b                       */
+#define TLRMDD_K_THETA_UPDATE 14  /* theta += a* p (and the newest s pair)                  */
+#define TLRMDD_K_RESID_UPDATE 15  /* r += a* a + a*^2 b                                     */
+#define TLRMDD_K_NKINDS       16
+
+#define TLRMDD_DT_NONE  (-1)      /* no matrix-core flops counted (memory-bound kind)        */
+#define TLRMDD_DT_FP32  0
+#define TLRMDD_DT_BF16  1
+#define TLRMDD_DT_MIXED 2         /* launches of one kind ran in different instruction types */
+
+typedef struct {
+    double  ms;          /* summed launch durations (HIP events on the launch stream)          */
+    int64_t launches;
+    double  cflops;      /* complex products counted 8 m n k (true sizes and ranks)             */
+    double  flops;       /* real flops of the product form that ran, on the same sizes:
+                            four-product FP32 8 m n k, three-product FP32 6 m n k,
+                            BF16 hi+lo split 24 m n k (BF16 instructions)                     */
+    double  bytes;       /* algorithmic HBM bytes: each operand read once, each output written
+                            once (L-BFGS passes: the held pairs of a run without restarts)    */
+    int32_t flop_dtype;  /* TLRMDD_DT_* of `flops`                                            */
+    int32_t reserved;
+} tlrmdd_kernel_stats;
+
 int tlrmdd_timing_begin(void);
-int tlrmdd_timing_end(double *ms, int64_t *launches);
+int tlrmdd_timing_end(tlrmdd_kernel_stats *stats);
 
 #ifdef __cplusplus
 }

@@ -100,15 +100,19 @@ def hilbert_order(ix, iy):
     return out
 
 
-def permute_columns(A, perm):
-    """out[:, k] = A[:, perm[k]] on the device (Dhat = D S)."""
+def permute_columns(A, perm, bad=None):
+    """out[:, k] = A[:, perm[k]] on the device (Dhat = D S). bad: optional device int32 tensor (one
+    element, cleared by the caller) that the kernel sets to 1 when a perm entry is outside [0, cols);
+    such columns come out as zeros."""
     _dev_tensor(A, "A")
     _dev_tensor(perm, "perm", torch.int64)
+    if bad is not None:
+        _dev_tensor(bad, "bad", torch.int32)
     rows, cols = A.shape
     if perm.shape != (cols,):
         raise ValueError("perm must have one entry per column")
     out = torch.empty_like(A)
-    _lib.check(_lib.load().tlrmdd_permute_columns(_ptr(A), _ptr(perm), _ptr(out), rows, cols, _stream()),
+    _lib.check(_lib.load().tlrmdd_permute_columns(_ptr(A), _ptr(perm), _ptr(out), rows, cols, _ptr(bad), _stream()),
                "tlrmdd_permute_columns")
     return out
 
@@ -379,18 +383,24 @@ def warm_start(plan, X):
 
 
 class KernelTimer:
-    """Context manager: per-kind summed kernel milliseconds and launch counts (HIP events)."""
+    """Context manager: per kernel kind the summed launch milliseconds (HIP events on the launch
+    stream), launch count and the algorithmic work the library counted for those launches."""
 
     def __enter__(self):
         _lib.check(_lib.load().tlrmdd_timing_begin(), "tlrmdd_timing_begin")
         return self
 
     def __exit__(self, *exc):
-        ms = (ctypes.c_double * _lib.K_NKINDS)()
-        n = (ctypes.c_int64 * _lib.K_NKINDS)()
-        _lib.check(_lib.load().tlrmdd_timing_end(ms, n), "tlrmdd_timing_end")
-        self.ms = {k: ms[i] for i, k in enumerate(_lib.KIND_NAMES)}
-        self.launches = {k: n[i] for i, k in enumerate(_lib.KIND_NAMES)}
+        st = (_lib.c_kernel_stats * _lib.K_NKINDS)()
+        _lib.check(_lib.load().tlrmdd_timing_end(st), "tlrmdd_timing_end")
+        names = _lib.KIND_NAMES
+        self.ms = {k: st[i].ms for i, k in enumerate(names)}
+        self.launches = {k: st[i].launches for i, k in enumerate(names)}
+        self.cflops = {k: st[i].cflops for i, k in enumerate(names)}
+        self.flops = {k: st[i].flops for i, k in enumerate(names)}
+        self.bytes = {k: st[i].bytes for i, k in enumerate(names)}
+        self.dtype = {k: {_lib.DT_NONE: None, _lib.DT_FP32: "f32", _lib.DT_BF16: "bf16",
+                          _lib.DT_MIXED: "mixed"}[st[i].flop_dtype] for i, k in enumerate(names)}
         return False
 
 

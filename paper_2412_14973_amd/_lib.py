@@ -13,7 +13,7 @@ import torch  # noqa: F401  (loads the HIP runtime the library links)
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libtlrmdd.so")
 
-OK, INVALID_ARGUMENT, WORKSPACE, HIP_ERROR, NONFINITE, UNSUPPORTED = 0, 1, 2, 3, 4, 5
+OK, INVALID_ARGUMENT, WORKSPACE, HIP_ERROR, NONFINITE, UNSUPPORTED, NOT_CONVERGED = 0, 1, 2, 3, 4, 5, 6
 FP32, BF16X3, FP32_3M = 0, 1, 2
 LBFGS, GD = 0, 1
 OP_FORWARD, OP_GRAD, OP_SOLVE = 0, 1, 2
@@ -36,6 +36,12 @@ class c_opts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("optimizer", ctypes.c_int32), ("lbfgs_m", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("lam", ctypes.c_double), ("resid_refresh", ctypes.c_int32),
                 ("streams", ctypes.c_int32), ("line_products", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class c_kernel_stats(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_int64), ("cflops", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double), ("flop_dtype", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class c_admm_opts(ctypes.Structure):
@@ -70,7 +76,7 @@ _SIGS = {
                                             ctypes.c_void_p]),
     "hilbert_order": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "tlrmdd_permute_columns": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
-                                              ctypes.c_int64, ctypes.c_void_p]),
+                                              ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "tlrmdd_adjoint": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                                                                 ctypes.c_void_p]),
     "tlrmdd_workspace_bytes_admm": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
@@ -95,12 +101,14 @@ _SIGS = {
     "tlrmdd_workspace_bytes_tlr": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
     "tlrmdd_forward_tlr": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_size_t, ctypes.c_void_p]),
     "tlrmdd_timing_begin": (ctypes.c_int, []),
-    "tlrmdd_timing_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "tlrmdd_timing_end": (ctypes.c_int, [ctypes.c_void_p]),
 }
 (K_GEMM_RESID, K_GEMM_ADJOINT, K_GEMM_LINE, K_ASSEMBLE, K_ASSEMBLE_DIR, K_GRAD, K_LINE_PACK, K_LINE_TILE,
- K_GRAD_TILE, K_NKINDS) = range(10)
+ K_GRAD_TILE, K_RESID_TILE, K_STAGE, K_PERMUTE, K_GRAM, K_COMBINE, K_THETA_UPDATE, K_RESID_UPDATE,
+ K_NKINDS) = range(17)
 KIND_NAMES = ("gemm_resid", "gemm_adjoint", "gemm_line", "assemble", "assemble_dir", "grad", "line_pack", "line_tile",
-              "grad_tile")
+              "grad_tile", "resid_tile", "stage", "permute", "gram", "combine", "theta_update", "resid_update")
+DT_NONE, DT_FP32, DT_BF16, DT_MIXED = -1, 0, 1, 2
 
 EXPORTS = tuple(_SIGS)
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -29,6 +30,12 @@ int fail(int status, const std::string &msg) {
     return status;
 }
 
+}  // namespace
+
+int tlr::set_error(int status, const std::string &msg) { return fail(status, msg); }
+
+namespace {
+
 #define HIP_TRY(expr)                                                                     \
     do {                                                                                  \
         hipError_t e_ = (expr);                                                           \
@@ -40,11 +47,38 @@ inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // ---------------------------------------------------------------------------
-// kernel timing: HIP events around launches of selected kinds
+// kernel timing: HIP events around launches of selected kinds, with each launch's algorithmic work
 // ---------------------------------------------------------------------------
+// Product forms of the complex GEMMs: real flops per complex flop (8 m n k) and the instruction type
+enum Form : int32_t { F_4M = 0, F_3M = 1, F_BF16X3 = 2 };
+
+// Work of one launch on the true (unpadded) sizes and ranks: complex flops counted 8 m n k, the real
+// flops of the form that runs (four products 8 m n k, three products 6 m n k, BF16 hi+lo split 24 m n k
+// in BF16), and HBM bytes with every operand read once and every output written once.
+struct Work {
+    double cflops = 0.0, flops = 0.0, bytes = 0.0;
+    int dtype = TLRMDD_DT_NONE;
+};
+
+Work gemm_work(int form, double cflops, double bytes) {
+    Work w;
+    w.cflops = cflops;
+    w.flops = cflops * (form == F_4M ? 1.0 : form == F_3M ? 0.75 : 3.0);
+    w.bytes = bytes;
+    w.dtype = form == F_BF16X3 ? TLRMDD_DT_BF16 : TLRMDD_DT_FP32;
+    return w;
+}
+
+Work bytes_work(double bytes) {
+    Work w;
+    w.bytes = bytes;
+    return w;
+}
+
 struct TimedLaunch {
     int kind;
     hipEvent_t a, b;
+    Work work;
 };
 struct Recorder {
     std::mutex mu;
@@ -65,15 +99,98 @@ hipEvent_t rec_event() {
 }
 
 template <class F>
-hipError_t timed(int kind, hipStream_t s, F &&launch) {
+hipError_t timed(int kind, hipStream_t s, const Work &work, F &&launch) {
     if (!g_rec.on) return launch();
     std::lock_guard<std::mutex> lk(g_rec.mu);
     hipEvent_t a = rec_event(), b = rec_event();
     if (a) (void)hipEventRecord(a, s);
     hipError_t e = launch();
     if (b) (void)hipEventRecord(b, s);
-    if (a && b) g_rec.ev.push_back(TimedLaunch{kind, a, b});
+    if (a && b) g_rec.ev.push_back(TimedLaunch{kind, a, b, work});
     return e;
+}
+
+// ---------------------------------------------------------------------------
+// host -> device uploads of host-built tables without waiting for the device
+// ---------------------------------------------------------------------------
+// A call's tables are gathered into one image, copied into a library-owned pinned buffer and sent
+// to their device addresses on the caller's stream; an event recorded after the copies tells when
+// the buffer may take another image. A call takes a buffer whose event has completed (or a new
+// one), so no call blocks on the device and nothing the caller owns is read after it returns.
+struct PinnedBuf {
+    char *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    int device = -1;
+};
+struct PinnedPool {
+    std::mutex mu;
+    std::vector<PinnedBuf> bufs;
+} g_pinned;
+constexpr size_t PINNED_MIN = size_t(64) << 10;
+constexpr int PINNED_MAX_BUFS = 64;   // beyond this many buffers in flight a call waits for the oldest
+
+class Upload {
+  public:
+    // queue `bytes` of host memory `src` for device address `dst`
+    void add(void *dst, const void *src, size_t bytes) {
+        if (!bytes) return;
+        const size_t off = img_.size();
+        img_.resize(off + ((bytes + 15) & ~size_t(15)));
+        std::memcpy(img_.data() + off, src, bytes);
+        pieces_.push_back(Piece{dst, off, bytes});
+    }
+    int commit(hipStream_t s);
+
+  private:
+    struct Piece {
+        void *dst;
+        size_t off, bytes;
+    };
+    std::vector<char> img_;
+    std::vector<Piece> pieces_;
+};
+
+int Upload::commit(hipStream_t s) {
+    if (img_.empty()) return TLRMDD_OK;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_pinned.mu);
+    PinnedBuf *pick = nullptr;
+    int ndev = 0;
+    for (PinnedBuf &b : g_pinned.bufs) {
+        if (b.device != dev) continue;
+        ++ndev;
+        if (b.cap < img_.size() || hipEventQuery(b.done) != hipSuccess) continue;
+        if (!pick || b.cap < pick->cap) pick = &b;
+    }
+    if (!pick && ndev >= PINNED_MAX_BUFS) {   // bounded: wait for a large enough buffer of this device
+        for (PinnedBuf &b : g_pinned.bufs)
+            if (b.device == dev && b.cap >= img_.size()) {
+                HIP_TRY(hipEventSynchronize(b.done));
+                pick = &b;
+                break;
+            }
+    }
+    if (!pick) {
+        PinnedBuf b;
+        b.device = dev;
+        b.cap = PINNED_MIN;
+        while (b.cap < img_.size()) b.cap *= 2;
+        HIP_TRY(hipHostMalloc((void **)&b.host, b.cap, hipHostMallocDefault));
+        hipError_t e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipHostFree(b.host);
+            return fail(TLRMDD_HIP_ERROR, std::string("upload event: ") + hipGetErrorString(e));
+        }
+        g_pinned.bufs.push_back(b);
+        pick = &g_pinned.bufs.back();
+    }
+    std::memcpy(pick->host, img_.data(), img_.size());
+    for (const Piece &p : pieces_)
+        if (p.bytes) HIP_TRY(hipMemcpyAsync(p.dst, pick->host + p.off, p.bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(pick->done, s));
+    return TLRMDD_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -484,6 +601,7 @@ bool problem_form(int op, const HostLayout &H, const tlrmdd_opts *opts, LineClas
 struct LineTile {
     bool on = false;
     LineClass lc;
+    double ksum = 0.0;               // sum over the range's problems of the ranks of all ordered tile pairs
     int64_t NA = 0;                  // columns of a stage-1 row block: nt * 2 kpad (= rows of a stage-2 B)
     float2 *PA = nullptr, *PB = nullptr, *PB2 = nullptr, *Pcol = nullptr;
     PackItem *pack = nullptr;
@@ -700,6 +818,8 @@ std::vector<LineSeg> line_segments(int op, int count, const tlrmdd_plan *plans, 
             line_tile_counts(sg.np, cls[p], npack);
             sg.lt = line_tile_carve(base ? base + o : nullptr, sg.np, cls[p], lds, npack);
             o += align256(sg.lt.bytes);
+            for (int e = p; e < q; ++e)
+                for (const TileDesc &td : plans[e]->H.tiles) sg.lt.ksum += td.kind == TILE_LR ? 2.0 * td.k : td.k;
         }
         segs.push_back(sg);
         p = q;
@@ -732,37 +852,52 @@ int check_opts(const tlrmdd_opts *o) {
 // sub-batches on their own streams
 // ---------------------------------------------------------------------------
 
-// Extra streams (default priority, non-blocking) and join events, created once per device and kept
-// for the life of the process.
+// Extra streams (default priority, non-blocking), created on first use per (device, caller stream) and
+// kept for the life of the process, so calls on different caller streams never share them; fork /
+// join events come from a free list and belong to one call while it enqueues its work (a wait that
+// has been enqueued keeps referring to the record it was enqueued after, so an event may be recorded
+// again once its waits are enqueued).
 struct StreamPool {
     std::mutex mu;
-    std::vector<std::vector<hipStream_t>> streams;   // [device][k]
-    std::vector<std::vector<hipEvent_t>> events;     // [device][k]
+    std::map<std::pair<int, hipStream_t>, std::vector<hipStream_t>> streams;
+    std::map<int, std::vector<hipEvent_t>> free_events;   // by device
 };
 StreamPool g_pool;
 
-int pool_get(int n, std::vector<hipStream_t> &st, std::vector<hipEvent_t> &ev) {
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lk(g_pool.mu);
-    if ((int)g_pool.streams.size() <= dev) {
-        g_pool.streams.resize(dev + 1);
-        g_pool.events.resize(dev + 1);
+// The call's side streams and events; the events return to the free list when it ends.
+struct CallStreams {
+    int device = 0;
+    std::vector<hipStream_t> st;
+    std::vector<hipEvent_t> ev;
+    ~CallStreams() {
+        if (ev.empty()) return;
+        std::lock_guard<std::mutex> lk(g_pool.mu);
+        auto &F = g_pool.free_events[device];
+        F.insert(F.end(), ev.begin(), ev.end());
     }
-    auto &S = g_pool.streams[dev];
-    auto &E = g_pool.events[dev];
+};
+
+int pool_get(int n, int nev, hipStream_t caller, CallStreams &cs) {
+    HIP_TRY(hipGetDevice(&cs.device));
+    std::lock_guard<std::mutex> lk(g_pool.mu);
+    auto &S = g_pool.streams[{cs.device, caller}];
     while ((int)S.size() < n) {
         hipStream_t x;
         HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
         S.push_back(x);
     }
-    while ((int)E.size() < n + 1) {
+    cs.st.assign(S.begin(), S.begin() + n);
+    auto &F = g_pool.free_events[cs.device];
+    while ((int)cs.ev.size() < nev) {
         hipEvent_t e;
-        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        E.push_back(e);
+        if (!F.empty()) {
+            e = F.back();
+            F.pop_back();
+        } else {
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        }
+        cs.ev.push_back(e);
     }
-    st.assign(S.begin(), S.begin() + n);
-    ev.assign(E.begin(), E.begin() + n + 1);
     return TLRMDD_OK;
 }
 
@@ -860,15 +995,17 @@ int run_grouped(int op, int count, const tlrmdd_plan *plans, const void *const *
     int st = ws_bytes_grouped(op, count, plans, opts, &need, &parts);
     if (st) return st;
     if (!workspace || ws_bytes < need) return fail(TLRMDD_WORKSPACE, "workspace too small");
-    std::vector<hipStream_t> ps;
-    std::vector<hipEvent_t> ev;
-    // one sub-batch: pool stream 0 serves as the run's side stream (events 0 and 1 fork and join it)
-    if ((st = pool_get(S == 1 ? 1 : S - 1, ps, ev))) return st;
+    // S sub-batches: S - 1 pool streams forked with event S - 1 and joined with events 0 .. S - 2;
+    // one sub-batch: a pool stream serves as the run's side stream (events S and S + 1 fork and join it)
+    CallStreams cs;
+    if ((st = pool_get(S == 1 ? 1 : S - 1, S + 2, stream, cs))) return st;
+    const std::vector<hipStream_t> &ps = cs.st;
+    const std::vector<hipEvent_t> &ev = cs.ev;
     SideStream side;
     if (S == 1) {
         side.s = ps[0];
-        side.fork = ev[0];
-        side.join = ev[1];
+        side.fork = ev[S];
+        side.join = ev[S + 1];
     }
     HIP_TRY(hipEventRecord(ev[S - 1], stream));
     for (int k = 0; k < S - 1; ++k) HIP_TRY(hipStreamWaitEvent(ps[k], ev[S - 1], 0));
@@ -928,6 +1065,7 @@ const char *tlrmdd_status_string(int status) {
         case TLRMDD_HIP_ERROR: return "HIP runtime error";
         case TLRMDD_NONFINITE: return "non-finite value";
         case TLRMDD_UNSUPPORTED: return "unsupported";
+        case TLRMDD_NOT_CONVERGED: return "not converged";
         default: return "unknown status";
     }
 }
@@ -1008,14 +1146,11 @@ int tlrmdd_workspace_bytes(tlrmdd_plan plan, int op, const tlrmdd_opts *opts, si
 // ---------------------------------------------------------------------------
 namespace {
 
-// upload the tables into the workspace (blocking until the copy is done, so
-// the host image may be freed)
-int upload_tables(const Tables &T, int nprob, const Ws &w, DevTables &D, double *const *fhist, hipStream_t s) {
+// the tables of a batch into the workspace (queued on `up`)
+void upload_tables(const Tables &T, int nprob, const Ws &w, DevTables &D, double *const *fhist, Upload &up) {
     std::vector<char> img;
     pack_tables(T, nprob, w.tables, img, D, fhist);
-    HIP_TRY(hipMemcpyAsync(w.tables, img.data(), img.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    return TLRMDD_OK;
+    up.add(w.tables, img.data(), img.size());
 }
 
 struct Ctx {
@@ -1029,6 +1164,7 @@ struct Ctx {
     bool p3m = false;           // FP32 products in the three-real-product form
     int64_t xspace = 0;         // complex64 elements of X space per problem (1 or 2 ldk x ldk)
 
+    int form() const { return bf16 ? F_BF16X3 : p3m ? F_3M : F_4M; }
     // split planes (uint32 words, one per complex): per problem [hi | lo]
     uint32_t *dsw() const { return reinterpret_cast<uint32_t *>(w.Ds); }
     uint32_t *dhw() const { return reinterpret_cast<uint32_t *>(w.DHs); }
@@ -1048,6 +1184,8 @@ int fin(const Ctx &c, FinArgs f, const int32_t *counts, int ucount, int nsum) {
 }
 
 int gemm_resid(const Ctx &c, const float2 *X, int64_t sX, const float2 *U, int64_t ldu, int64_t sU, float2 *r) {
+    const double np = c.nprob, ns = (double)c.ns, nr = (double)c.nr;
+    const Work wk = gemm_work(c.form(), 8.0 * ns * nr * nr * np, 8.0 * np * (3.0 * ns * nr + nr * nr));
     if (c.bf16) {
         // X given as the split planes that start at the same place (word 2 * offset of X)
         const uint32_t *xh = reinterpret_cast<const uint32_t *>(X);
@@ -1064,7 +1202,7 @@ int gemm_resid(const Ctx &c, const float2 *X, int64_t sX, const float2 *U, int64
         g.partials = c.w.partials; g.sP = (int64_t)c.pstride;
         g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
         g.Me = (int)c.ns; g.Ne = (int)c.nr;
-        HIP_TRY(timed(TLRMDD_K_GEMM_RESID, c.s, [&] { return launch_cgemm_bf16(GM_RESID, g, c.nprob, c.s); }));
+        HIP_TRY(timed(TLRMDD_K_GEMM_RESID, c.s, wk, [&] { return launch_cgemm_bf16(GM_RESID, g, c.nprob, c.s); }));
         return TLRMDD_OK;
     }
     GemmArgs g = gemm_args();
@@ -1075,13 +1213,15 @@ int gemm_resid(const Ctx &c, const float2 *X, int64_t sX, const float2 *U, int64
     g.partials = c.w.partials; g.sP = (int64_t)c.pstride;   // one sum per workgroup
     g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
     g.Me = (int)c.ns; g.Ne = (int)c.nr;
-    HIP_TRY(timed(TLRMDD_K_GEMM_RESID, c.s, [&] {
+    HIP_TRY(timed(TLRMDD_K_GEMM_RESID, c.s, wk, [&] {
         return c.p3m ? launch_cgemm3m(GM_RESID, g, c.nprob, c.s) : launch_cgemm(GM_RESID, g, c.nprob, c.s);
     }));
     return TLRMDD_OK;
 }
 
 int gemm_adjoint(const Ctx &c, const float2 *r, float2 *W, int64_t sW) {
+    const double np = c.nprob, ns = (double)c.ns, nr = (double)c.nr;
+    const Work wk = gemm_work(c.form(), 8.0 * nr * ns * nr * np, 8.0 * np * (2.0 * ns * nr + nr * nr));
     if (c.bf16) {
         // r^T split planes (written by split_r_transpose) are the transposed B operand
         GemmArgsB g;
@@ -1094,7 +1234,7 @@ int gemm_adjoint(const Ctx &c, const float2 *r, float2 *W, int64_t sW) {
         g.ldb = c.lds; g.sB = 2 * c.ldk * c.lds;
         g.C = W; g.ldc = c.ldk; g.sC = sW;
         g.M = (int)c.ldk; g.N = (int)c.ldk; g.K = (int)c.lds;
-        HIP_TRY(timed(TLRMDD_K_GEMM_ADJOINT, c.s, [&] { return launch_cgemm_bf16(GM_STORE, g, c.nprob, c.s); }));
+        HIP_TRY(timed(TLRMDD_K_GEMM_ADJOINT, c.s, wk, [&] { return launch_cgemm_bf16(GM_STORE, g, c.nprob, c.s); }));
         return TLRMDD_OK;
     }
     GemmArgs g = gemm_args();
@@ -1102,13 +1242,15 @@ int gemm_adjoint(const Ctx &c, const float2 *r, float2 *W, int64_t sW) {
     g.B = r; g.ldb = c.ldk; g.sB = c.lds * c.ldk;
     g.C = W; g.ldc = c.ldk; g.sC = sW;
     g.M = (int)c.ldk; g.N = (int)c.ldk; g.K = (int)c.lds;
-    HIP_TRY(timed(TLRMDD_K_GEMM_ADJOINT, c.s, [&] {
+    HIP_TRY(timed(TLRMDD_K_GEMM_ADJOINT, c.s, wk, [&] {
         return c.p3m ? launch_cgemm3m(GM_STORE, g, c.nprob, c.s) : launch_cgemm(GM_STORE, g, c.nprob, c.s);
     }));
     return TLRMDD_OK;
 }
 
 int gemm_line(const Ctx &c, const float2 *X1, const float2 *X2, int64_t sX) {
+    const double np = c.nprob, ns = (double)c.ns, nr = (double)c.nr;
+    const Work wk = gemm_work(c.form(), 16.0 * ns * nr * nr * np, 8.0 * np * (4.0 * ns * nr + 2.0 * nr * nr));
     if (c.bf16) {
         const uint32_t *xh = reinterpret_cast<const uint32_t *>(X1);
         GemmArgsB g;
@@ -1123,7 +1265,7 @@ int gemm_line(const Ctx &c, const float2 *X1, const float2 *X2, int64_t sX) {
         g.E = c.w.r; g.lde = c.ldk; g.sE = c.lds * c.ldk;
         g.partials = c.w.partials; g.sP = (int64_t)c.pstride * 5;
         g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
-        HIP_TRY(timed(TLRMDD_K_GEMM_LINE, c.s, [&] { return launch_cgemm_bf16(GM_LINE, g, c.nprob, c.s); }));
+        HIP_TRY(timed(TLRMDD_K_GEMM_LINE, c.s, wk, [&] { return launch_cgemm_bf16(GM_LINE, g, c.nprob, c.s); }));
         return TLRMDD_OK;
     }
     GemmArgs g = gemm_args();
@@ -1133,7 +1275,7 @@ int gemm_line(const Ctx &c, const float2 *X1, const float2 *X2, int64_t sX) {
     g.E = c.w.r; g.lde = c.ldk; g.sE = c.lds * c.ldk;
     g.partials = c.w.partials; g.sP = (int64_t)c.pstride * 5;
     g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
-    HIP_TRY(timed(TLRMDD_K_GEMM_LINE, c.s, [&] {
+    HIP_TRY(timed(TLRMDD_K_GEMM_LINE, c.s, wk, [&] {
         return c.p3m ? launch_cgemm3m(GM_LINE, g, c.nprob, c.s) : launch_cgemm(GM_LINE, g, c.nprob, c.s);
     }));
     return TLRMDD_OK;
@@ -1147,16 +1289,21 @@ int split_r_transpose(const Ctx &c) {
     return TLRMDD_OK;
 }
 
-// staging of D for problem p (padded; split planes in BF16 mode)
+// staging of D for problem p (padded; split planes in BF16 mode): reads D, writes D and D^H
 int stage(const Ctx &c, int p, const float2 *D, bool with_dh) {
+    const Work wk = bytes_work((with_dh ? 24.0 : 16.0) * (double)c.ns * (double)c.nr);
     if (c.bf16) {
         uint32_t *dh = c.dsw() + (int64_t)p * 2 * c.lds * c.ldk;
         uint32_t *hh = with_dh ? c.dhw() + (int64_t)p * 2 * c.ldk * c.lds : nullptr;
-        HIP_TRY(launch_stage_d_split(D, c.ns, c.nr, dh, dh + c.lds * c.ldk, c.ldk, hh,
-                                     hh ? hh + c.ldk * c.lds : nullptr, c.lds, c.s));
+        HIP_TRY(timed(TLRMDD_K_STAGE, c.s, wk, [&] {
+            return launch_stage_d_split(D, c.ns, c.nr, dh, dh + c.lds * c.ldk, c.ldk, hh,
+                                        hh ? hh + c.ldk * c.lds : nullptr, c.lds, c.s);
+        }));
     } else {
-        HIP_TRY(launch_stage_d(D, c.ns, c.nr, c.w.Ds + (int64_t)p * c.lds * c.ldk, c.ldk,
-                               with_dh ? c.w.DHs + (int64_t)p * c.ldk * c.lds : nullptr, c.lds, c.s));
+        HIP_TRY(timed(TLRMDD_K_STAGE, c.s, wk, [&] {
+            return launch_stage_d(D, c.ns, c.nr, c.w.Ds + (int64_t)p * c.lds * c.ldk, c.ldk,
+                                  with_dh ? c.w.DHs + (int64_t)p * c.ldk * c.lds : nullptr, c.lds, c.s);
+        }));
     }
     return TLRMDD_OK;
 }
@@ -1185,6 +1332,7 @@ struct Run {
     std::vector<int> asm_first;      // first assembly item of every problem, and the total
     std::vector<int> grad_first;     // first gradient item of every problem, and the total
     int n_adj = 0;                   // problems before the tile-form gradient ranges (adjoint product)
+    std::vector<double> theta_pre;   // complex unknowns of problems 0 .. p - 1 (true sizes)
     // a second stream (default priority) on which the tile-form gradient runs beside the adjoint
     // product of the other problems, and the events that fork it from and join it to c.s
     hipStream_t side = nullptr;
@@ -1215,7 +1363,9 @@ int tile_stage1(Run &R, const LineSeg &sg, const float *dir, bool dir_only = fal
     const LineTile &L = sg.lt;
     const LineClass &lc = L.lc;
     const int64_t NA = L.NA, d = lc.d, nt = lc.nt;
-    HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
+    const double ks = L.ksum, dd = (double)d, ns = (double)c.ns, nr = (double)c.nr, np = c.nprob;
+    // the A and B blocks of theta and of the direction, and B_p once more: 5 d ksum entries
+    HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, bytes_work(16.0 * 5.0 * dd * ks), [&] {
         return launch_tlr_pack(L.pack, L.npack, (const float2 *)c.w.th, L.PA, c.s, (const float2 *)dir, 2);
     }));
     GemmArgs g1 = gemm_args();   // stage 1: P_(p,i) = D_p[:, i d ...] PA_(p,i)
@@ -1228,7 +1378,11 @@ int tile_stage1(Run &R, const LineSeg &sg, const float *dir, bool dir_only = fal
     g1.scat_kp = lc.kpad; g1.scat_w = (int)(nt * lc.kpad); g1.scat_lim = N; g1.scat_js = c.lds * NA - lc.kpad;
     g1.M = (int)c.lds; g1.N = N; g1.K = (int)d;
     g1.nz2 = (int)nt;
-    HIP_TRY(timed(TLRMDD_K_LINE_TILE, c.s, [&] { return launch_cgemm3m(GM_STORE, g1, (int)(c.nprob * nt), c.s, GR_TILE); }));
+    const double h = (dir_only || theta_only) ? 1.0 : 2.0;   // halves formed
+    const Work wk = gemm_work(F_3M, 8.0 * ns * dd * ks * h, 8.0 * (ns * nr * np + dd * ks * h + ns * ks * h));
+    HIP_TRY(timed(TLRMDD_K_LINE_TILE, c.s, wk, [&] {
+        return launch_cgemm3m(GM_STORE, g1, (int)(c.nprob * nt), c.s, GR_TILE);
+    }));
     return TLRMDD_OK;
 }
 
@@ -1251,7 +1405,14 @@ int line_products_tile(Run &R, const LineSeg &sg, bool dir_only = false) {
     g2.M = (int)c.lds; g2.N = (int)d; g2.K = (int)NA;
     g2.K2 = (int)(nt * lc.kpad);   // b: the direction half of Pcol only
     g2.nz2 = (int)nt;
-    HIP_TRY(timed(TLRMDD_K_LINE_TILE, c.s, [&] { return launch_cgemm3m(GM_LINE, g2, (int)(c.nprob * nt), c.s, GR_TILE); }));
+    {   // a: K = 2 ksum, b: K = ksum per tile column; reads Pcol, the B blocks of theta and p, r; writes a, b
+        const double ks = L.ksum, dd = (double)d, ns = (double)c.ns, nr = (double)c.nr, np = c.nprob;
+        const Work wk = gemm_work(F_3M, 24.0 * ns * dd * ks,
+                                  8.0 * (2.0 * ns * ks + 2.0 * ks * dd + 3.0 * ns * nr * np));
+        HIP_TRY(timed(TLRMDD_K_LINE_TILE, c.s, wk, [&] {
+            return launch_cgemm3m(GM_LINE, g2, (int)(c.nprob * nt), c.s, GR_TILE);
+        }));
+    }
     return TLRMDD_OK;
 }
 
@@ -1265,7 +1426,8 @@ int tile_gradient(Run &R, const LineSeg &sg, float *g, hipStream_t stream) {
     const int64_t NA = L.NA, d = lc.d, nt = lc.nt, kp = lc.kpad, Wg = L.Wg;
     const int KS = GRAD_TILE_KS;
     const int64_t Kc = c.lds / KS;
-    HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
+    const double ks = L.ksum, dd = (double)d, ns = (double)c.ns, nr = (double)c.nr, np = c.nprob;
+    HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, bytes_work(16.0 * dd * ks), [&] {
         return launch_tlr_pack(L.gpack, L.ngpack, (const float2 *)c.w.th, L.PBH, c.s, nullptr, 2);
     }));
     GemmArgs g1 = gemm_args();   // G1: S_(p,j) = r_p[:, j d ...] PBH_(p,j), stored as Scol_(p,i)[:, j kp ...]
@@ -1275,7 +1437,10 @@ int tile_gradient(Run &R, const LineSeg &sg, float *g, hipStream_t stream) {
     g1.scat_kp = (int)kp; g1.scat_w = (int)(nt * kp); g1.scat_lim = (int)(nt * kp); g1.scat_js = c.lds * NA - kp;
     g1.M = (int)c.lds; g1.N = (int)Wg; g1.K = (int)d;
     g1.nz2 = (int)nt;
-    HIP_TRY(timed(TLRMDD_K_GRAD_TILE, c.s, [&] { return launch_cgemm3m(GM_STORE, g1, (int)(c.nprob * nt), c.s, GR_TILE); }));
+    HIP_TRY(timed(TLRMDD_K_GRAD_TILE, c.s,
+                  gemm_work(F_3M, 8.0 * ns * dd * ks, 8.0 * (ns * nr * np + dd * ks + ns * ks)), [&] {
+                      return launch_cgemm3m(GM_STORE, g1, (int)(c.nprob * nt), c.s, GR_TILE);
+                  }));
     // G2 and G3 in one launch of the transposed-A / conjugated-B role, per (p, tile x, part q):
     //   set 0: GBT_(p,x,q) = r_p[q Kc ..., x d ...]^T conj(Pcol_th(p,x)[q Kc ...])
     //   set 1: conj(GA_(p,x,q)) = D_p[q Kc ..., x d ...]^T conj(Scol_(p,x)[q Kc ...])
@@ -1287,10 +1452,11 @@ int tile_gradient(Run &R, const LineSeg &sg, float *g, hipStream_t stream) {
     g3.C = L.GBT; g3.ldc = Wg; g3.sC = nt * KS * d * Wg; g3.sC2 = KS * d * Wg; g3.sC3 = d * Wg; g3.sC4 = L.GA - L.GBT;
     g3.M = (int)d; g3.N = (int)Wg; g3.K = (int)Kc;
     g3.nz2 = (int)(nt * KS * 2); g3.nz3 = KS; g3.nz4 = 2;
-    HIP_TRY(timed(TLRMDD_K_GRAD_TILE, c.s, [&] {
-        return launch_cgemm3m(GM_STORE, g3, (int)(c.nprob * nt * KS * 2), c.s, GR_TILE_TA_CB);
-    }));
-    HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
+    HIP_TRY(timed(TLRMDD_K_GRAD_TILE, c.s,
+                  gemm_work(F_3M, 16.0 * ns * dd * ks, 8.0 * (2.0 * ns * nr * np + 2.0 * ns * ks + 2.0 * dd * ks)),
+                  [&] { return launch_cgemm3m(GM_STORE, g3, (int)(c.nprob * nt * KS * 2), c.s, GR_TILE_TA_CB); }));
+    // every gradient entry (d ksum of them) from 2 KS partial planes
+    HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, bytes_work(8.0 * (2.0 * KS + 1.0) * dd * ks), [&] {
         return launch_tlr_grad(L.gitems, L.ngitems, L.GA, L.GBT, KS, d * Wg, Wg, true, (float2 *)g, c.s);
     }));
     return TLRMDD_OK;
@@ -1318,7 +1484,9 @@ int tile_resid(Run &R, const LineSeg &sg) {
     g.M = (int)c0.lds; g.N = (int)d; g.K = (int)(nt * kp);
     g.Me = (int)c0.ns; g.Ne = (int)d;             // E's columns are local to the tile column
     g.nz2 = (int)nt;
-    HIP_TRY(timed(TLRMDD_K_GEMM_RESID, c0.s, [&] {
+    const double ks = L.ksum, dd = (double)d, ns = (double)c0.ns, nr = (double)c0.nr, np = sg.np;
+    const Work wk = gemm_work(F_3M, 8.0 * ns * dd * ks, 8.0 * (ns * ks + dd * ks + 2.0 * ns * nr * np));
+    HIP_TRY(timed(TLRMDD_K_RESID_TILE, c0.s, wk, [&] {
         return launch_cgemm3m(GM_RESID, g, (int)(sg.np * nt), c0.s, GR_TILE);
     }));
     return TLRMDD_OK;
@@ -1329,7 +1497,7 @@ int tile_pcol_update(Run &R, const LineSeg &sg) {
     const Ctx c = line_ctx(R.c, sg.p0, sg.np);
     const LineTile &L = sg.lt;
     const int64_t nt = L.lc.nt;
-    HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, [&] {
+    HIP_TRY(timed(TLRMDD_K_LINE_PACK, c.s, bytes_work(24.0 * (double)c.ns * L.ksum), [&] {
         return launch_tlr_paxpy(L.Pcol, (int)(c.nprob * nt), (int)nt, c.lds * L.NA, c.lds, L.NA, nt * L.lc.kpad,
                                 c.w.sc + sg.p0, c.s);
     }));
@@ -1365,7 +1533,8 @@ int objective_fresh(Run &R, int record, double lam) {
     if (R.n_adj > 0) {
         if ((e = clear_plane_padding(R))) return e;
         const int na = (R.single || R.n_adj == c.nprob) ? c.D.n_asm : R.asm_first[R.n_adj];
-        HIP_TRY(timed(TLRMDD_K_ASSEMBLE, c.s, [&] {
+        const double nr = (double)c.nr;
+        HIP_TRY(timed(TLRMDD_K_ASSEMBLE, c.s, bytes_work(8.0 * (nr * nr * R.n_adj + R.theta_pre[R.n_adj])), [&] {
             return launch_assemble(false, c.D.tiles, c.D.asm_items, na, c.D.probs, (const float2 *)c.w.th,
                                    nullptr, R.X1, nullptr, c.s, c.bf16, R.x2w, c.lo_words());
         }));
@@ -1406,9 +1575,11 @@ int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *c
     c.lds = round_up(ns, GEMM_PAD);
     c.s = s;
     std::vector<const HostLayout *> Hs;
+    R.theta_pre.assign(1, 0.0);
     for (int p = 0; p < nprob; ++p) {
         append_problem(R.T, plans[p]->H, p, (int64_t)p * 2 * c.ldk * c.ldk, c.ldk);
         Hs.push_back(&plans[p]->H);
+        R.theta_pre.push_back(R.theta_pre.back() + (double)plans[p]->H.theta_size);
     }
     build_segments(R.T, Hs, c.lds, c.ldk);
     c.pstride = partial_stride(R.T, c.ldk, c.lds);
@@ -1429,10 +1600,9 @@ int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *c
     R.n_adj = nprob;
     for (const LineSeg &sg : R.segs)
         if (sg.tile && sg.lt.lc.grad) R.n_adj = std::min(R.n_adj, sg.p0);
-    bool any_tile = false;
+    Upload up;
     for (LineSeg &sg : R.segs) {
         if (!sg.tile) continue;
-        any_tile = true;
         std::vector<PackItem> pack;
         std::vector<int64_t> toff;
         std::vector<const HostLayout *> Hseg;
@@ -1443,8 +1613,8 @@ int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *c
         line_tile_tables(Hseg, toff, sg.lt.lc, c.lds, pack);
         if ((int)pack.size() != sg.lt.npack)
             return fail(TLRMDD_UNSUPPORTED, "tile-form line search tables");
-        HIP_TRY(hipMemcpyAsync(sg.lt.pack, pack.data(), pack.size() * sizeof(PackItem), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemsetAsync(sg.lt.PA, 0, sg.lt.zero_bytes, s));   // rank padding reads as zero
+        up.add(sg.lt.pack, pack.data(), pack.size() * sizeof(PackItem));
+        HIP_TRY(launch_fill_zero(sg.lt.PA, sg.lt.zero_bytes, s));   // rank padding reads as zero
         if (sg.lt.lc.grad) {
             std::vector<PackItem> gpack;
             std::vector<TGradItem> gitems;
@@ -1452,21 +1622,15 @@ int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *c
             if ((int)gpack.size() != sg.lt.ngpack || (int)gitems.size() > sg.lt.ngitems)
                 return fail(TLRMDD_UNSUPPORTED, "tile-form gradient tables");
             sg.lt.ngitems = (int)gitems.size();
-            HIP_TRY(hipMemcpyAsync(sg.lt.gpack, gpack.data(), gpack.size() * sizeof(PackItem), hipMemcpyHostToDevice,
-                                   s));
-            HIP_TRY(hipMemcpyAsync(sg.lt.gitems, gitems.data(), gitems.size() * sizeof(TGradItem),
-                                   hipMemcpyHostToDevice, s));
+            up.add(sg.lt.gpack, gpack.data(), gpack.size() * sizeof(PackItem));
+            up.add(sg.lt.gitems, gitems.data(), gitems.size() * sizeof(TGradItem));
             // B^H padding and the unused columns of S read as zero
-            HIP_TRY(hipMemsetAsync((char *)sg.lt.PA + sg.lt.gzero_off, 0, sg.lt.gzero_bytes, s));
+            HIP_TRY(launch_fill_zero((char *)sg.lt.PA + sg.lt.gzero_off, sg.lt.gzero_bytes, s));
         }
     }
-    if (any_tile) HIP_TRY(hipStreamSynchronize(s));
-    if (R.single) {
-        c.D = plans[0]->D;
-    } else {
-        st = upload_tables(R.T, nprob, c.w, c.D, fhist, s);
-        if (st != TLRMDD_OK) return st;
-    }
+    if (R.single) c.D = plans[0]->D;
+    else upload_tables(R.T, nprob, c.w, c.D, fhist, up);
+    if ((st = up.commit(s))) return st;
     R.fhist0 = R.single ? fhist[0] : nullptr;
     R.xstride = 2 * c.ldk * c.ldk;   // per-problem X-space stride
     R.rstride = c.lds * c.ldk;
@@ -1486,13 +1650,18 @@ int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *c
     R.cen = c.w.cen;
 
     // padding of the X space must read as zero (the assembly writes only the true nr x nr block)
-    if (c.ldk != nr) HIP_TRY(hipMemsetAsync(c.w.XW, 0, (size_t)nprob * R.xstride * sizeof(float2), s));
+    if (c.ldk != nr) HIP_TRY(launch_fill_zero(c.w.XW, (size_t)nprob * R.xstride * sizeof(float2), s));
+    const double snr = (double)ns * (double)nr;
     for (int p = 0; p < nprob; ++p) {
         if ((st = stage(c, p, (const float2 *)D[p], true))) return st;
         if (c.w.Dc != c.w.Ds)   // BF16 mode with tile-form ranges: their complex64 D
-            HIP_TRY(launch_stage_d((const float2 *)D[p], c.ns, c.nr, c.w.Dc + p * c.lds * c.ldk, c.ldk, nullptr,
-                                   c.lds, s));
-        HIP_TRY(launch_copy2d((const float2 *)U[p], nr, c.w.Us + p * R.rstride, c.ldk, ns, nr, s));
+            HIP_TRY(timed(TLRMDD_K_STAGE, s, bytes_work(16.0 * snr), [&] {
+                return launch_stage_d((const float2 *)D[p], c.ns, c.nr, c.w.Dc + p * c.lds * c.ldk, c.ldk, nullptr,
+                                      c.lds, s);
+            }));
+        HIP_TRY(timed(TLRMDD_K_STAGE, s, bytes_work(16.0 * snr), [&] {
+            return launch_copy2d((const float2 *)U[p], nr, c.w.Us + p * R.rstride, c.ldk, ns, nr, s);
+        }));
         HIP_TRY(hipMemcpyAsync(c.w.th + 2 * R.T.probs[p].theta, theta[p],
                                plans[p]->H.theta_size * sizeof(float2), hipMemcpyDeviceToDevice, s));
     }
@@ -1537,7 +1706,9 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
             const Ctx ca = R.n_adj == c.nprob ? c : line_ctx(c, 0, R.n_adj);
             if ((st = gemm_adjoint(ca, c.w.r, R.X1, R.xstride))) return st;
             const int ng = (R.single || R.n_adj == c.nprob) ? c.D.n_grad : R.grad_first[R.n_adj];
-            HIP_TRY(timed(TLRMDD_K_GRAD, s, [&] {
+            const double nr = (double)c.nr;
+            const Work wk = bytes_work(8.0 * (nr * nr * R.n_adj + 2.0 * R.theta_pre[R.n_adj]));
+            HIP_TRY(timed(TLRMDD_K_GRAD, s, wk, [&] {
                 return launch_grad(c.D.tiles, c.D.grad_items, ng, c.D.probs, R.X1, (const float2 *)c.w.th,
                                    (float2 *)R.gcur, s);
             }));
@@ -1552,14 +1723,23 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
         if (!R.lbfgs || t == 0) {
             HIP_TRY(launch_negate(c.D.tsegs, nt, c.w.p, R.gcur, s));
         } else {
-            HIP_TRY(launch_gram(c.D.tsegs, nt, m1, R.gcur, R.gprev, c.w.Y, c.w.S, R.stride2, c.w.sc, c.w.partials, s));
+            // held pairs besides the newest (a run without restarts): min(t - 1, m) in the Gram pass,
+            // min(t, m) in the combination
+            const double th_all = R.theta_pre.back();
+            const double held = std::min(t - 1, R.m);
+            HIP_TRY(timed(TLRMDD_K_GRAM, s, bytes_work(8.0 * th_all * (4.0 + 2.0 * held)), [&] {
+                return launch_gram(c.D.tsegs, nt, m1, R.gcur, R.gprev, c.w.Y, c.w.S, R.stride2, c.w.sc, c.w.partials,
+                                   s);
+            }));
             FinArgs f = fin_args(FIN_GRAM, c.w.sc);
             f.m1 = m1;
             f.gram = c.w.gram;
             f.gstride = gram_stride(m1);
             if ((st = fin(c, f, c.D.tcount, 0, 6 * m1))) return st;
-            HIP_TRY(launch_combine(c.D.tsegs, nt, m1, c.w.p, R.gcur, c.w.S, c.w.Y, R.stride2, c.w.sc,
-                                   c.w.gram + (2 * m1 + 1) * (2 * m1 + 1), gram_stride(m1), s));
+            HIP_TRY(timed(TLRMDD_K_COMBINE, s, bytes_work(8.0 * th_all * (2.0 + 2.0 * std::min(t, R.m))), [&] {
+                return launch_combine(c.D.tsegs, nt, m1, c.w.p, R.gcur, c.w.S, c.w.Y, R.stride2, c.w.sc,
+                                      c.w.gram + (2 * m1 + 1) * (2 * m1 + 1), gram_stride(m1), s);
+            }));
         }
         // exact line search: a = D C1(theta;p), b = D C2(p)
         for (const LineSeg &sg : R.segs) {
@@ -1567,7 +1747,9 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
             if ((st = clear_plane_padding(R))) return st;
             const int a0 = R.single ? 0 : R.asm_first[sg.p0];
             const int na = R.single ? c.D.n_asm : R.asm_first[sg.p0 + sg.np] - a0;
-            HIP_TRY(timed(TLRMDD_K_ASSEMBLE_DIR, s, [&] {
+            const double nr = (double)c.nr;
+            const Work wk = bytes_work(16.0 * (nr * nr * sg.np + R.theta_pre[sg.p0 + sg.np] - R.theta_pre[sg.p0]));
+            HIP_TRY(timed(TLRMDD_K_ASSEMBLE_DIR, s, wk, [&] {
                 return launch_assemble(true, c.D.tiles, c.D.asm_items + a0, na, c.D.probs,
                                        (const float2 *)c.w.th, (const float2 *)c.w.p, R.X1, R.X2, s, c.bf16, R.x2w,
                                        c.lo_words());
@@ -1594,8 +1776,11 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
             if ((st = fin(c, f, nullptr, line_tiles(c), 5))) return st;
         }
         // updates
-        HIP_TRY(launch_theta_update(c.D.tsegs, nt, c.w.th, c.w.p, R.lbfgs ? c.w.S : nullptr, R.stride2, cen,
-                                    c.w.sc, c.w.partials, s));
+        HIP_TRY(timed(TLRMDD_K_THETA_UPDATE, s,
+                      bytes_work(8.0 * R.theta_pre.back() * ((R.lbfgs ? 4.0 : 3.0) + (cen ? 1.0 : 0.0))), [&] {
+                          return launch_theta_update(c.D.tsegs, nt, c.w.th, c.w.p, R.lbfgs ? c.w.S : nullptr,
+                                                     R.stride2, cen, c.w.sc, c.w.partials, s);
+                      }));
         for (const LineSeg &sg : R.segs)
             if (sg.tile && sg.lt.lc.grad)
                 if ((st = tile_pcol_update(R, sg))) return st;
@@ -1606,8 +1791,10 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
         if (refresh) {
             if ((st = objective_fresh(R, record_base >= 0 ? record_base + t + 1 : -1, lam))) return st;
         } else {
-            HIP_TRY(launch_resid_update(c.D.rsegs, R.nrs, (float *)c.w.r, (const float *)c.w.a,
-                                        (const float *)c.w.b, c.w.sc, c.w.partials, s));
+            HIP_TRY(timed(TLRMDD_K_RESID_UPDATE, s, bytes_work(32.0 * (double)c.ns * (double)c.nr * c.nprob), [&] {
+                return launch_resid_update(c.D.rsegs, R.nrs, (float *)c.w.r, (const float *)c.w.a,
+                                           (const float *)c.w.b, c.w.sc, c.w.partials, s);
+            }));
             if ((st = split_r_transpose(c))) return st;
             if ((st = fin_f(R, record_base >= 0 ? record_base + t + 1 : -1, lam, R.T.rseg_per_prob))) return st;
         }
@@ -1719,9 +1906,10 @@ int tlrmdd_forward(tlrmdd_plan plan, const void *D, const void *U, const void *t
     c.bf16 = precision == TLRMDD_BF16X3;
     c.p3m = precision == TLRMDD_FP32_3M;
     c.xspace = c.ldk * c.ldk;
-    if (c.ldk != c.nr) HIP_TRY(hipMemsetAsync(c.w.XW, 0, (size_t)c.ldk * c.ldk * sizeof(float2), stream));
+    if (c.ldk != c.nr) HIP_TRY(launch_fill_zero(c.w.XW, (size_t)c.ldk * c.ldk * sizeof(float2), stream));
     if ((st = stage(c, 0, (const float2 *)D, false))) return st;
-    HIP_TRY(timed(TLRMDD_K_ASSEMBLE, stream, [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
+    const double nr2 = (double)c.nr * (double)c.nr, thn = (double)plan->H.theta_size;
+    HIP_TRY(timed(TLRMDD_K_ASSEMBLE, stream, bytes_work(8.0 * (nr2 + thn)), [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
                             c.w.XW, nullptr, stream, c.bf16, 0, c.lo_words()); }));
     if ((st = gemm_resid(c, c.w.XW, 0, (const float2 *)U, c.nr, 0, c.w.r))) return st;
     FinArgs f = fin_args(FIN_F_OUT, c.w.sc);
@@ -1758,9 +1946,10 @@ int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *thet
     c.bf16 = precision == TLRMDD_BF16X3;
     c.p3m = precision == TLRMDD_FP32_3M;
     c.xspace = c.ldk * c.ldk;
-    if (c.ldk != c.nr) HIP_TRY(hipMemsetAsync(c.w.XW, 0, (size_t)c.ldk * c.ldk * sizeof(float2), stream));
+    if (c.ldk != c.nr) HIP_TRY(launch_fill_zero(c.w.XW, (size_t)c.ldk * c.ldk * sizeof(float2), stream));
     if ((st = stage(c, 0, (const float2 *)D, true))) return st;
-    HIP_TRY(timed(TLRMDD_K_ASSEMBLE, stream, [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
+    const double nr2 = (double)c.nr * (double)c.nr, thn = (double)plan->H.theta_size;
+    HIP_TRY(timed(TLRMDD_K_ASSEMBLE, stream, bytes_work(8.0 * (nr2 + thn)), [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
                             c.w.XW, nullptr, stream, c.bf16, 0, c.lo_words()); }));
     if ((st = gemm_resid(c, c.w.XW, 0, (const float2 *)U, c.nr, 0, c.w.r))) return st;
     if ((st = split_r_transpose(c))) return st;
@@ -1771,7 +1960,7 @@ int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *thet
     }
     // the assembled X is dead once r exists: W = D^H r reuses its storage
     if ((st = gemm_adjoint(c, c.w.r, c.w.XW, 0))) return st;
-    HIP_TRY(timed(TLRMDD_K_GRAD, stream, [&] { return launch_grad(c.D.tiles, c.D.grad_items, c.D.n_grad, c.D.probs, c.w.XW, (const float2 *)theta,
+    HIP_TRY(timed(TLRMDD_K_GRAD, stream, bytes_work(8.0 * (nr2 + 2.0 * thn)), [&] { return launch_grad(c.D.tiles, c.D.grad_items, c.D.n_grad, c.D.probs, c.w.XW, (const float2 *)theta,
                         (float2 *)grad_out, stream); }));
     return TLRMDD_OK;
 }
@@ -1950,12 +2139,15 @@ int tlrmdd_timing_begin(void) {
     return TLRMDD_OK;
 }
 
-int tlrmdd_timing_end(double *ms, int64_t *launches) {
+int tlrmdd_timing_end(tlrmdd_kernel_stats *stats) {
     g_last_error.clear();
     std::lock_guard<std::mutex> lk(g_rec.mu);
     g_rec.on = false;
-    double acc[TLRMDD_K_NKINDS] = {0};
-    int64_t cnt[TLRMDD_K_NKINDS] = {0};
+    tlrmdd_kernel_stats acc[TLRMDD_K_NKINDS];
+    for (int k = 0; k < TLRMDD_K_NKINDS; ++k) {
+        std::memset(&acc[k], 0, sizeof(acc[k]));
+        acc[k].flop_dtype = TLRMDD_DT_NONE;
+    }
     int status = TLRMDD_OK;
     for (TimedLaunch &t : g_rec.ev) {
         float v = 0.f;
@@ -1966,17 +2158,23 @@ int tlrmdd_timing_end(double *ms, int64_t *launches) {
             continue;
         }
         if (t.kind >= 0 && t.kind < TLRMDD_K_NKINDS) {
-            acc[t.kind] += v;
-            cnt[t.kind] += 1;
+            tlrmdd_kernel_stats &a = acc[t.kind];
+            a.ms += v;
+            a.launches += 1;
+            a.cflops += t.work.cflops;
+            a.flops += t.work.flops;
+            a.bytes += t.work.bytes;
+            if (t.work.dtype != TLRMDD_DT_NONE) {
+                if (a.flop_dtype == TLRMDD_DT_NONE) a.flop_dtype = t.work.dtype;
+                else if (a.flop_dtype != t.work.dtype) a.flop_dtype = TLRMDD_DT_MIXED;
+            }
         }
         g_rec.pool.push_back(t.a);
         g_rec.pool.push_back(t.b);
     }
     g_rec.ev.clear();
-    for (int k = 0; k < TLRMDD_K_NKINDS; ++k) {
-        if (ms) ms[k] = acc[k];
-        if (launches) launches[k] = cnt[k];
-    }
+    if (stats)
+        for (int k = 0; k < TLRMDD_K_NKINDS; ++k) stats[k] = acc[k];
     return status;
 }
 
@@ -2074,30 +2272,31 @@ int svd_run(const SvdHost &S, const SvdWs &w, const float2 *X, int64_t ldx, hipS
     const int nt = (int)S.tiles.size();
     const int npairs = (int)S.pair_tile.size();
     HIP_TRY(launch_svd_gather(w.tiles, nt, X, ldx, w.W, w.V, s));
-    HIP_TRY(hipMemsetAsync(w.flags, 0, 2 * sizeof(int32_t), s));
-    for (int sw = 0; sw < SVD_MAX_SWEEPS && npairs > 0; ++sw) {
+    HIP_TRY(launch_fill_zero(w.flags, 2 * sizeof(int32_t), s));
+    bool converged = npairs == 0;
+    for (int sw = 0; sw < SVD_MAX_SWEEPS && !converged; ++sw) {
         for (int r = 0; r < S.maxnp - 1; ++r)
             HIP_TRY(launch_svd_round(w.tiles, w.pair_tile, npairs, r, w.W, w.V, w.flags, w.flags + 1, SVD_TOL, s));
         HIP_TRY(launch_svd_sweep_end(w.flags, w.flags + 1, s));
-        if (sw % 2 == 1) {
+        if (sw % 2 == 1 || sw + 1 == SVD_MAX_SWEEPS) {
             int32_t done = 0;
             HIP_TRY(hipMemcpyAsync(&done, w.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            if (done) break;
+            converged = done != 0;
         }
     }
+    if (!converged)
+        return fail(TLRMDD_NOT_CONVERGED, "per-tile Jacobi SVD: pairs still rotated after the sweep limit");
     HIP_TRY(launch_svd_sigma(w.tiles, nt, w.W, w.sig, s));
     return TLRMDD_OK;
 }
 
 int svd_upload(const SvdHost &S, const SvdWs &w, const std::vector<WarmItem> *items, hipStream_t s) {
-    HIP_TRY(hipMemcpyAsync(w.tiles, S.tiles.data(), S.tiles.size() * sizeof(SvdTile), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w.pair_tile, S.pair_tile.data(), S.pair_tile.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, s));
-    if (items && !items->empty())
-        HIP_TRY(hipMemcpyAsync(w.items, items->data(), items->size() * sizeof(WarmItem), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));   // the host tables may be freed after this
-    return TLRMDD_OK;
+    Upload up;
+    up.add(w.tiles, S.tiles.data(), S.tiles.size() * sizeof(SvdTile));
+    up.add(w.pair_tile, S.pair_tile.data(), S.pair_tile.size() * sizeof(int32_t));
+    if (items) up.add(w.items, items->data(), items->size() * sizeof(WarmItem));
+    return up.commit(s);
 }
 
 int check_rank_args(const void *X, int64_t nr, int32_t d, double eps) {
@@ -2393,16 +2592,17 @@ int tlrmdd_forward_tlr(tlrmdd_plan plan, const void *D, const void *U, const voi
     const TlrWs w = tlr_carve((char *)workspace, T, lds, ldk);
     if (w.bytes > ws_bytes) return fail(TLRMDD_WORKSPACE, "workspace too small");
     hipStream_t s = stream;
-    // tables (blocking upload: the host vectors may go away afterwards)
-    HIP_TRY(hipMemcpyAsync(w.pa, T.packA.data(), T.packA.size() * sizeof(PackItem), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w.pb, T.packB.data(), T.packB.size() * sizeof(PackItem), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w.gi, T.gather.data(), T.gather.size() * sizeof(GatherItem), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    Upload up;
+    up.add(w.pa, T.packA.data(), T.packA.size() * sizeof(PackItem));
+    up.add(w.pb, T.packB.data(), T.packB.size() * sizeof(PackItem));
+    up.add(w.gi, T.gather.data(), T.gather.size() * sizeof(GatherItem));
+    int st = up.commit(s);
+    if (st) return st;
     const int64_t N = T.N;
     // padding of the packed operands must read as zero
-    HIP_TRY(hipMemsetAsync(w.A, 0, (size_t)N * T.Kpmax * T.K1p * sizeof(float2), s));
-    HIP_TRY(hipMemsetAsync(w.B, 0, (size_t)N * T.K2p * T.dp * sizeof(float2), s));
-    HIP_TRY(hipMemsetAsync(w.Pcol, 0, (size_t)N * lds * T.K2p * sizeof(float2), s));
+    HIP_TRY(launch_fill_zero(w.A, (size_t)N * T.Kpmax * T.K1p * sizeof(float2), s));
+    HIP_TRY(launch_fill_zero(w.B, (size_t)N * T.K2p * T.dp * sizeof(float2), s));
+    HIP_TRY(launch_fill_zero(w.Pcol, (size_t)N * lds * T.K2p * sizeof(float2), s));
     HIP_TRY(launch_stage_d((const float2 *)D, ns, nr, w.Ds, ldk, nullptr, lds, s));
     HIP_TRY(launch_tlr_pack(w.pa, (int)T.packA.size(), (const float2 *)theta, w.A, s));
     HIP_TRY(launch_tlr_pack(w.pb, (int)T.packB.size(), (const float2 *)theta, w.B, s));
@@ -2481,13 +2681,17 @@ int hilbert_order(const int32_t *ix, const int32_t *iy, int64_t n, int64_t *perm
 }
 
 int tlrmdd_permute_columns(const void *in, const int64_t *perm, void *out, int64_t rows, int64_t cols,
-                           hipStream_t stream) {
+                           int32_t *bad_dev, hipStream_t stream) {
     g_last_error.clear();
     if (rows < 0 || cols < 0) return fail(TLRMDD_INVALID_ARGUMENT, "negative size");
     if (rows == 0 || cols == 0) return TLRMDD_OK;
     if (!in || !perm || !out) return fail(TLRMDD_INVALID_ARGUMENT, "NULL pointer");
-    if (in == out) return fail(TLRMDD_INVALID_ARGUMENT, "in and out must not overlap");
-    HIP_TRY(launch_permute_cols((const float2 *)in, perm, (float2 *)out, rows, cols, stream));
+    const char *a = (const char *)in, *b = (const char *)out;
+    const size_t bytes = (size_t)rows * (size_t)cols * sizeof(float2);
+    if (a < b + bytes && b < a + bytes) return fail(TLRMDD_INVALID_ARGUMENT, "in and out must not overlap");
+    HIP_TRY(timed(TLRMDD_K_PERMUTE, stream, bytes_work(16.0 * (double)rows * (double)cols + 8.0 * (double)cols), [&] {
+        return launch_permute_cols((const float2 *)in, perm, (float2 *)out, rows, cols, bad_dev, stream);
+    }));
     return TLRMDD_OK;
 }
 

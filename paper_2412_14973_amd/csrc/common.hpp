@@ -3,8 +3,12 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 namespace tlr {
+
+// records `msg` as the calling thread's last error (tlrmdd_last_error) and returns `status`
+int set_error(int status, const std::string &msg);
 
 // ---- tile tables (Tile Low-rank MDD section: diagonal Q Q^T / P Z, sub-diagonal L R) ----
 enum TileKind : int32_t { TILE_LR = 0, TILE_QQ = 1, TILE_DENSE = 2 };
@@ -175,7 +179,10 @@ hipError_t launch_zero_pad(uint32_t *base, int64_t ld, int64_t n, int nplanes, i
                            int64_t batch_stride, hipStream_t s);
 hipError_t launch_copy2d(const float2 *src, int64_t lds, float2 *dst, int64_t ldd,
                          int64_t rows, int64_t cols, hipStream_t s);
+// bad: device int32 or NULL, set to 1 when a perm entry lies outside [0, cols) (its column is zeroed)
 hipError_t launch_permute_cols(const float2 *in, const int64_t *perm, float2 *out,
-                               int64_t rows, int64_t cols, hipStream_t s);
+                               int64_t rows, int64_t cols, int32_t *bad, hipStream_t s);
+// zero `bytes` (a multiple of 4, 4-byte aligned) at p with a kernel (no memset node in captured graphs)
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 
 }  // namespace tlr

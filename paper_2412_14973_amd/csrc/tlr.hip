@@ -1,5 +1,5 @@
 // Tile low-rank matrix product D C(theta) without the dense X (the paper's
-// conclusions name it as the way to cut the cost of the dense products).
+// Discussion section names it as the way to cut the cost of the dense products).
 //
 // Column block j of D X is sum_i D_:,i X_ij with every tile a product of two
 // factors, X_ij = A_ij B_ij:

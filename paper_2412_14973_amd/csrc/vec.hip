@@ -4,6 +4,7 @@
 // per-segment partials, then one fixed-order tree per problem), with no
 // atomics. Scalars never leave the device.
 #include "common.hpp"
+#include "exact_step.hpp"
 #include "vec.hpp"
 
 namespace tlr {
@@ -108,16 +109,35 @@ __global__ void zero_pad_kernel(uint32_t *__restrict__ base, int64_t ld, int64_t
 
 __global__ void copy2d_kernel(const float2 *__restrict__ src, int64_t lds, float2 *__restrict__ dst,
                               int64_t ldd, int64_t rows, int64_t cols) {
-    const int64_t r = blockIdx.y;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cols; c += (int64_t)gridDim.x * blockDim.x)
-        if (r < rows) dst[r * ldd + c] = src[r * lds + c];
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y)
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cols; c += (int64_t)gridDim.x * blockDim.x)
+            dst[r * ldd + c] = src[r * lds + c];
 }
 
+// out[r, c] = in[r, perm[c]]; a perm entry outside [0, cols) gives a zero column and sets *bad
 __global__ void permute_kernel(const float2 *__restrict__ in, const int64_t *__restrict__ perm,
-                               float2 *__restrict__ out, int64_t rows, int64_t cols) {
-    const int64_t r = blockIdx.y;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cols; c += (int64_t)gridDim.x * blockDim.x)
-        out[r * cols + c] = in[r * cols + perm[c]];
+                               float2 *__restrict__ out, int64_t rows, int64_t cols, int32_t *__restrict__ bad) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cols; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = perm[c];
+        const bool ok = q >= 0 && q < cols;
+        if (!ok && bad && blockIdx.y == 0) *bad = 1;
+        for (int64_t r = blockIdx.y; r < rows; r += gridDim.y)
+            out[r * cols + c] = ok ? in[r * cols + q] : make_float2(0.f, 0.f);
+    }
+}
+
+// zero `words` 32-bit words at p (16-byte stores over the aligned body)
+__global__ void fill_zero_kernel(uint32_t *__restrict__ p, int64_t words) {
+    const int64_t mis = (int64_t)((16 - ((uintptr_t)p & 15)) & 15) / 4;   // words before a 16-byte boundary
+    const int64_t lead = mis < words ? mis : words;
+    const int64_t nvec = (words - lead) / 4;
+    uint4 *v = reinterpret_cast<uint4 *>(p + lead);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t; i < nvec; i += stride) v[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (t < lead) p[t] = 0u;
+    const int64_t tail = lead + 4 * nvec;
+    if (t < words - tail) p[tail + t] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -442,73 +462,6 @@ __global__ __launch_bounds__(256) void resid_update_kernel(const VecSeg *__restr
 }
 
 // ---------------------------------------------------------------------------
-// exact step: positive minimiser of phi with phi'(a) = c0 + c1 a + c2 a^2 + c3 a^3
-// ---------------------------------------------------------------------------
-__device__ double phi_inc(const double *c, double a) {
-    return a * (c[0] + a * (c[1] / 2 + a * (c[2] / 3 + a * c[3] / 4)));
-}
-
-__device__ double polish(const double *c, double x) {
-    for (int it = 0; it < 6; ++it) {
-        const double f = ((c[3] * x + c[2]) * x + c[1]) * x + c[0];
-        const double fp = (3 * c[3] * x + 2 * c[2]) * x + c[1];
-        if (fp == 0.0 || !isfinite(fp)) break;
-        const double nx = x - f / fp;
-        if (!isfinite(nx)) break;
-        x = nx;
-    }
-    return x;
-}
-
-__device__ double exact_step_dev(const double *c) {
-    double roots[3];
-    int nroot = 0;
-    const double scale = fabs(c[0]) + fabs(c[1]) + fabs(c[2]) + fabs(c[3]);
-    if (!(scale > 0.0) || !isfinite(scale)) return 0.0;
-    if (c[3] == 0.0 && c[2] == 0.0) {
-        if (c[1] != 0.0) roots[nroot++] = -c[0] / c[1];
-    } else if (c[3] == 0.0) {
-        const double disc = c[1] * c[1] - 4 * c[2] * c[0];
-        if (disc >= 0.0) {
-            const double sq = sqrt(disc);
-            const double qv = -0.5 * (c[1] + (c[1] >= 0 ? sq : -sq));
-            if (qv != 0.0) roots[nroot++] = c[0] / qv;
-            roots[nroot++] = qv / c[2];
-        }
-    } else {
-        // depressed cubic t^3 + P t + Q = 0 with a = t - A/3
-        const double A = c[2] / c[3], B = c[1] / c[3], C = c[0] / c[3];
-        const double P = B - A * A / 3.0;
-        const double Q = 2.0 * A * A * A / 27.0 - A * B / 3.0 + C;
-        const double disc = 0.25 * Q * Q + P * P * P / 27.0;
-        if (disc > 0.0) {
-            const double sq = sqrt(disc);
-            const double u = cbrt(-0.5 * Q + (Q <= 0 ? sq : -sq));
-            const double v = (u != 0.0) ? -P / (3.0 * u) : 0.0;
-            roots[nroot++] = u + v - A / 3.0;
-        } else if (P == 0.0) {
-            roots[nroot++] = -A / 3.0;
-        } else {
-            const double rr = 2.0 * sqrt(-P / 3.0);
-            double arg = (3.0 * Q / (2.0 * P)) * sqrt(-3.0 / P);
-            arg = fmin(1.0, fmax(-1.0, arg));
-            const double ph = acos(arg) / 3.0;
-            const double tp = 2.0943951023931954923;  // 2 pi / 3
-            for (int k = 0; k < 3; ++k) roots[nroot++] = rr * cos(ph - k * tp) - A / 3.0;
-        }
-    }
-    double best = 0.0, bestv = 0.0;
-    bool have = false;
-    for (int k = 0; k < nroot; ++k) {
-        const double x = polish(c, roots[k]);
-        if (!(x > 0.0) || !isfinite(x)) continue;
-        const double v = phi_inc(c, x);
-        if (!have || v < bestv || (v == bestv && x < best)) { best = x; bestv = v; have = true; }
-    }
-    return have ? best : 0.0;
-}
-
-// ---------------------------------------------------------------------------
 // per-problem finalisation (one block per problem)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs fa) {
@@ -687,15 +640,26 @@ hipError_t launch_copy2d(const float2 *src, int64_t lds, float2 *dst, int64_t ld
                          int64_t cols, hipStream_t s) {
     if (rows <= 0 || cols <= 0) return hipSuccess;
     const unsigned gx = (unsigned)std::min<int64_t>((cols + 255) / 256, 64);
-    hipLaunchKernelGGL(copy2d_kernel, dim3(gx, (unsigned)rows), dim3(256), 0, s, src, lds, dst, ldd, rows, cols);
+    const unsigned gy = (unsigned)std::min<int64_t>(rows, 65535);
+    hipLaunchKernelGGL(copy2d_kernel, dim3(gx, gy), dim3(256), 0, s, src, lds, dst, ldd, rows, cols);
     return hipGetLastError();
 }
 
 hipError_t launch_permute_cols(const float2 *in, const int64_t *perm, float2 *out, int64_t rows,
-                               int64_t cols, hipStream_t s) {
+                               int64_t cols, int32_t *bad, hipStream_t s) {
     if (rows <= 0 || cols <= 0) return hipSuccess;
     const unsigned gx = (unsigned)std::min<int64_t>((cols + 255) / 256, 64);
-    hipLaunchKernelGGL(permute_kernel, dim3(gx, (unsigned)rows), dim3(256), 0, s, in, perm, out, rows, cols);
+    const unsigned gy = (unsigned)std::min<int64_t>(rows, 65535);
+    hipLaunchKernelGGL(permute_kernel, dim3(gx, gy), dim3(256), 0, s, in, perm, out, rows, cols, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    if (((uintptr_t)p & 3) || (bytes & 3)) return hipErrorInvalidValue;
+    const int64_t words = (int64_t)(bytes / 4);
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((words / 4 + 255) / 256, 4096));
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks), dim3(256), 0, s, (uint32_t *)p, words);
     return hipGetLastError();
 }
 

@@ -351,23 +351,36 @@ def request_problem(req: Request, config_id: int = 5) -> Tuple[Problem, Layout, 
 # device-side generation (same recipe, torch on the GPU) for large request sizes
 # ----------------------------------------------------------------------------
 def device_problem(req: Request, device, config_id: int = 5):
-    """(D, U, theta0, layout, geometry) of a request, generated on `device`.
+    """(D, U, theta0, layout, geometry) of a request, generated on `device` (see device_generate)."""
+    geom = make_geometry(req.n_side, req.n_side, req.ns_mode)
+    lay = request_layout(req)
+    D, U, th = device_generate(geom, req.freq, 20.0, lay, config_id, 1000 + req.rid, device)
+    return D, U, th, lay, geom
+
+
+def device_workload_problem(wl: Workload, f_idx: int, device):
+    """(D, U, theta0) of frequency f_idx of a workload, generated on `device` (see device_generate);
+    the values differ from Workload.problem's (another generator) but follow the same recipe."""
+    return device_generate(wl.geometry(), float(wl.freqs[f_idx]), wl.snr_db, wl.layout(f_idx), wl.config_id,
+                           f_idx, device)
+
+
+def device_generate(geom: Geometry, freq: float, snr_db: float, lay: Layout, config_id: int, item: int, device):
+    """(D, U, theta0) generated on `device`.
 
     Same recipe as make_problem (homogeneous Green's functions, exact-SNR noise
     on U, 5 % noise on D, normalisation by 1/min distance), computed in
-    complex128 with torch's device generator seeded from (config, request),
+    complex128 with torch's device generator seeded from (config, item),
     returned as complex64 in natural receiver order.
     """
     import torch
-    geom = make_geometry(req.n_side, req.n_side, req.ns_mode)
-    lay = request_layout(req)
-    seed = int(np.random.SeedSequence(BASE_SEED, spawn_key=(config_id, 1000 + req.rid, P_REQUEST))
+    seed = int(np.random.SeedSequence(BASE_SEED, spawn_key=(config_id, item, P_REQUEST))
                .generate_state(1)[0])
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
     rec = torch.as_tensor(geom.rec_xyz, device=device)
     src = torch.as_tensor(geom.src_xyz, device=device)
-    w = 2.0 * math.pi * req.freq
+    w = 2.0 * math.pi * freq
     dsr = torch.cdist(src, rec)
     D_clean = torch.exp(-1j * w * dsr / VELOCITY) / dsr
     drr = torch.cdist(rec, rec)
@@ -380,7 +393,7 @@ def device_problem(req: Request, device, config_id: int = 5):
         return torch.complex(torch.randn(shape, generator=gen, device=device, dtype=torch.float64),
                              torch.randn(shape, generator=gen, device=device, dtype=torch.float64))
     n_u = cg(U_clean.shape)
-    U = U_clean + n_u * (torch.linalg.norm(U_clean) / (torch.linalg.norm(n_u) * 10.0 ** (20.0 / 20.0)))
+    U = U_clean + n_u * (torch.linalg.norm(U_clean) / (torch.linalg.norm(n_u) * 10.0 ** (snr_db / 20.0)))
     del n_u, U_clean
     n_d = cg(D_clean.shape)
     D = D_clean + n_d * (0.05 * torch.linalg.norm(D_clean) / torch.linalg.norm(n_d))
@@ -390,5 +403,4 @@ def device_problem(req: Request, device, config_id: int = 5):
     s = math.sqrt(1e-2 / 2.0)
     th = torch.complex(s * torch.randn(n, generator=gen, device=device, dtype=torch.float32),
                        s * torch.randn(n, generator=gen, device=device, dtype=torch.float32))
-    return ((D / alpha).to(torch.complex64).contiguous(), (U / alpha).to(torch.complex64).contiguous(),
-            th, lay, geom)
+    return (D / alpha).to(torch.complex64).contiguous(), (U / alpha).to(torch.complex64).contiguous(), th

@@ -42,8 +42,8 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_status_strings(lib):
-    for s in range(6):
-        assert lib.tlrmdd_status_string(s)
+    for s in range(7):
+        assert lib.tlrmdd_status_string(s) and lib.tlrmdd_status_string(s) != b"unknown status"
     assert lib.tlrmdd_status_string(0) == b"ok"
 
 
@@ -125,7 +125,7 @@ def test_ctypes_structs_match_the_header(tmp_path):
     if shutil.which("g++") is None or not os.path.isdir("/opt/rocm/include"):
         pytest.skip("g++ or the HIP headers are missing")
     structs = {"tlrmdd_layout": lib_mod.c_layout, "tlrmdd_opts": lib_mod.c_opts,
-               "tlrmdd_admm_opts": lib_mod.c_admm_opts}
+               "tlrmdd_admm_opts": lib_mod.c_admm_opts, "tlrmdd_kernel_stats": lib_mod.c_kernel_stats}
     cfield = {"lam": "lambda"}   # Python spelling -> C member
     lines = ['#include <cstdio>', '#include <cstddef>', '#include "tlrmdd.h"', 'int main() {']
     for cname, ct in structs.items():

@@ -177,6 +177,21 @@ int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *thet
                 double *f_dev, void *grad_out, int precision,
                 void *workspace, size_t ws_bytes, hipStream_t stream);
 
+/* tlrmdd_grad without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the scratch lives in a fixed device array of the
+ * library, TLRMDD_NOALLOC_SCRATCH_MIB MiB per GPU, held from the first call on
+ * a GPU until the process ends. The call allocates nothing (no hipMalloc, no
+ * hipFree, no host-pinned memory); the caller passes inputs and outputs as for
+ * tlrmdd_grad and still creates the plan beforehand. Returns TLRMDD_WORKSPACE
+ * when tlrmdd_workspace_bytes(plan, TLRMDD_OP_GRAD) exceeds the array (e.g.
+ * nr = ns = 1024 needs about 40 MiB and fits). Every call on one GPU shares that
+ * GPU's array: calls that overlap in time on one GPU (different streams, or
+ * threads) race and give wrong results; calls ordered on one stream are safe. */
+#define TLRMDD_NOALLOC_SCRATCH_MIB 64
+int tlrmdd_grad_noalloc(tlrmdd_plan plan, const void *D, const void *U, const void *theta,
+                        double *f_dev, void *grad_out, int precision, hipStream_t stream);
+
 /* Fixed-count solve of min f(theta) (+ lambda ||theta||^2) from theta_inout
  * (overwritten with theta_T). Each iteration: gradient from the tracked
  * residual, L-BFGS two-loop direction (real inner product Re<a,b>, pairs

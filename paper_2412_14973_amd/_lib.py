@@ -63,6 +63,7 @@ _SIGS = {
                                                                 ctypes.c_void_p]),
     "tlrmdd_grad": (ctypes.c_int, [ctypes.c_void_p] * 6 + [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                                                              ctypes.c_void_p]),
+    "tlrmdd_grad_noalloc": (ctypes.c_int, [ctypes.c_void_p] * 6 + [ctypes.c_int, ctypes.c_void_p]),
     "tlrmdd_solve": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.POINTER(c_opts), ctypes.c_void_p,
                                                               ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "tlrmdd_line_form": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(c_opts), ctypes.POINTER(ctypes.c_int),

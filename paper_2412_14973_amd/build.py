@@ -19,7 +19,8 @@ OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libtlrmdd.so")
 ARCH = os.environ.get("TLRMDD_ARCH", "gfx950")
 
-SOURCES = ["cgemm.hip", "cgemm3m.hip", "cgemm_bf16.hip", "tiles.hip", "vec.hip", "svd.hip", "tlr.hip", "api.cpp"]
+SOURCES = ["cgemm.hip", "cgemm3m.hip", "cgemm_bf16.hip", "tiles.hip", "vec.hip", "svd.hip", "tlr.hip", "api.cpp",
+           "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -159,71 +159,89 @@ def cpu_baseline(wl, budget_s):
 
 
 def serving(tl, torch, args):
-    """Poisson stream of per-frequency solves of uneven size: continuous batching
-    (FIFO admission by HBM budget, up to --max-active overlapping solves) against
-    the same stream solved one at a time. Inputs are generated on the device before
-    the clock starts; each request's work (Hilbert column gather + 100-iteration
-    solve) runs on its own stream. Results of the two runs must agree bit for bit."""
+    """Poisson stream of per-frequency solves of uneven size: continuous batching (FIFO admission
+    by HBM budget, up to --max-active overlapping solves) against the same stream solved one at a
+    time, then continuous batching at 0.5x and 0.9x of the measured capacity. Each request's inputs
+    are made on the device when it is admitted (same recipe, torch's device generator seeded per
+    request), on its own stream, followed by its Hilbert column gather and 100-iteration solve; the
+    inputs are freed when the solve completes, so the admission budget covers what requests really
+    hold. Results of the saturated runs must agree bit for bit."""
     import synth
     from paper_2412_14973_amd import serve
     prec = precision_info(tl, args.precision)[0]
     line = {"dense": tl.LINE_DENSE, "tile": tl.LINE_TILE, "tile-grad": tl.LINE_TILE_GRAD}[args.line_products]
-    reqs = synth.request_stream(args.requests, iters=args.iters or 100)
     dev = torch.device("cuda")
-    prepared = []
-    t0 = time.time()
+    iters = args.iters or 100
+    reqs = synth.request_stream(args.requests, rate=200.0, iters=iters)
+    perms = {}
+    plans = {}
     for r in reqs:
-        D, U, th, lay, geom = synth.device_problem(r, dev)
-        perm = torch.from_numpy(tl.hilbert_order(geom.rec_ix, geom.rec_iy)).to(dev)
-        plan = tl.Plan.from_layout(lay, geom.ns)
-        prepared.append((r, D, U, th, perm, plan))
-        form = tl.line_form(plan, prec, line)[0]
-        log(f"request {r.rid}: nr {geom.nr} ns {geom.ns} d {r.d} k {r.k} form {form} ({time.time() - t0:.1f}s)")
-    torch.cuda.synchronize()
+        if r.n_side not in perms:
+            g = synth.make_geometry(r.n_side, r.n_side)
+            perms[r.n_side] = torch.from_numpy(tl.hilbert_order(g.rec_ix, g.rec_iy)).to(dev)
+        geom = synth.make_geometry(r.n_side, r.n_side, r.ns_mode)
+        plans[r.rid] = tl.Plan.from_layout(synth.request_layout(r), geom.ns)
 
-    class Backend(serve.GpuBackend):
-        def start(self, req):
-            r, D, U, th, perm, plan = req
-            sidx = self.free_streams.pop(0)
-            stream = self.streams[sidx]
-            stream.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(stream):
-                Dh = tl.permute_columns(D, perm)
-                Uh = tl.permute_columns(U, perm)
-                theta, fh = tl.solve(plan, Dh, Uh, th, r.iters, precision=prec, line_products=line)
-                ev = torch.cuda.Event()
-                ev.record(stream)
-            return {"event": ev, "stream": sidx, "theta": theta, "fhist": fh, "keep": (Dh, Uh)}
+    def make(r):
+        def inputs():
+            D, U, th, _, _ = synth.device_problem(r, dev)
+            pd = perms[r.n_side]
+            return tl.permute_columns(D, pd), tl.permute_columns(U, pd), th
+        return inputs
 
-        def footprint(self, req):
-            r, D, U, th, perm, plan = req
-            return super().footprint(serve.SolveRequest(plan, D, U, th, r.iters, prec, line_products=line)) + \
-                2 * D.numel() * 8
+    def jobs_for(stream):
+        out = []
+        for r in stream:
+            p = plans[r.rid]
+            # transients of making the inputs (complex128 distances, fields, noise) and the natural-order
+            # complex64 copies next to the gathered ones
+            make_bytes = 72 * p.ns * p.nr + 56 * p.nr * p.nr + 16 * p.ns * p.nr
+            req = serve.SolveRequest(p, None, None, None, r.iters, prec, line_products=line, make_inputs=make(r),
+                                     make_bytes=make_bytes)
+            out.append(serve.Job(rid=r.rid, arrival=r.arrival, payload=req))
+        return out
 
-    out = {"metric": "TLR-MDD served solves/s, p50/p99 latency", "requests": len(reqs),
-           "arrival_rate_per_s": 200.0, "iters": reqs[0].iters, "precision": args.precision,
-           "line_products": args.line_products,
-           "forms": [tl.line_form(p[5], prec, line)[0] for p in prepared],
-           "hbm_budget_gib": args.hbm_budget_gib, "sizes": [[r.n_side ** 2, (r.n_side ** 2) // (2 if r.ns_mode == "half" else 1), r.d, r.k] for r in reqs]}
-    results = {}
-    for mode, active in (("one_at_a_time", 1), ("continuous", args.max_active)):
-        be = Backend(n_streams=max(active, 1))
-        jobs = [serve.Job(rid=p[0].rid, arrival=p[0].arrival, payload=p) for p in prepared]
+    def run(stream, active, label):
+        be = serve.GpuBackend(n_streams=max(active, 1))
+        jobs = jobs_for(stream)
         torch.cuda.synchronize()
         be.clock = serve.WallClock()
         srv = serve.Server(be, hbm_budget=int(args.hbm_budget_gib * 2 ** 30), max_active=active)
-        srv.run(jobs)
+        t0 = time.time()
+
+        def progress(job):
+            n = sum(1 for j in jobs if j.finished is not None)
+            if n % 16 == 0 or n == len(jobs):
+                log(f"{label}: {n}/{len(jobs)} solves done ({time.time() - t0:.0f} s)")
+        srv.run(jobs, on_done=progress)
         torch.cuda.synchronize()
-        out[mode] = serve.summarize(jobs)
-        out[mode]["max_active"] = active
-        out[mode]["peak_hbm_gib"] = srv.peak_in_use / 2 ** 30
-        results[mode] = {j.rid: j.result for j in jobs}
-        log(f"{mode}: {out[mode]}")
-    same = all(torch.equal(results["one_at_a_time"][k]["theta"], results["continuous"][k]["theta"])
-               and torch.equal(results["one_at_a_time"][k]["fhist"], results["continuous"][k]["fhist"])
-               for k in results["continuous"])
-    out["bitwise_same_alone_and_in_mix"] = bool(same)
+        res = serve.summarize(jobs)
+        res.update(max_active=active, peak_footprint_gib=srv.peak_in_use / 2 ** 30,
+                   admissions_waiting_for_memory=sum(1 for e in srv.log if e[1] == "wait_memory"),
+                   offered_rate_per_s=len(stream) / max(stream[-1].arrival - stream[0].arrival, 1e-9))
+        log(f"{label}: {res}")
+        return res, {j.rid: j.result for j in jobs}
+
+    out = {"metric": "TLR-MDD served solves/s, p50/p99 latency", "requests": len(reqs),
+           "arrival_rate_per_s": 200.0, "iters": iters, "precision": args.precision,
+           "line_products": args.line_products,
+           "forms": [tl.line_form(plans[r.rid], prec, line)[0] for r in reqs],
+           "hbm_budget_gib": args.hbm_budget_gib,
+           "sizes": [[r.n_side ** 2, (r.n_side ** 2) // (2 if r.ns_mode == "half" else 1), r.d, r.k] for r in reqs],
+           "inputs": "made on the device at admission (counted in the footprint), freed at completion"}
+    out["one_at_a_time"], res1 = run(reqs, 1, "one at a time")
+    out["continuous"], res2 = run(reqs, args.max_active, "continuous")
+    out["bitwise_same_alone_and_in_mix"] = bool(all(
+        torch.equal(res1[k]["theta"], res2[k]["theta"]) and torch.equal(res1[k]["fhist"], res2[k]["fhist"])
+        for k in res2))
     out["speedup_solves_per_s"] = out["continuous"]["solves_per_s"] / out["one_at_a_time"]["solves_per_s"]
+    cap = out["continuous"]["solves_per_s"]
+    for frac in args.sub_capacity:
+        rate = frac * cap
+        stream = synth.request_stream(args.requests, rate=rate, iters=iters)
+        assert [(r.n_side, r.ns_mode, r.d, r.k) for r in stream] == [(r.n_side, r.ns_mode, r.d, r.k) for r in reqs]
+        out[f"continuous_at_{frac:g}x_capacity"], _ = run(stream, args.max_active, f"continuous at {frac:g}x capacity")
+        out[f"continuous_at_{frac:g}x_capacity"]["arrival_rate_per_s"] = rate
     return out
 
 
@@ -347,67 +365,82 @@ def estimate(tl, torch, args):
 
 
 def error_table(tl, torch, args):
-    """Mixed-precision error table on the 64 x 64-receiver problem (nr 4096, ns 2048,
-    tile 256, rank 32) at 10 and 30 dB: FP32 and BF16x3 solves (and the three-product FP32 solve
-    with the tile-form line search and gradient) against the FP64 oracle."""
+    """Mixed-precision error table on the 64 x 64-receiver problem (nr 4096, ns 2048, tile 256,
+    rank 32, 100 iterations) at the given SNRs and frequency indices: the three-product FP32 solve
+    with the tile-form line search and gradient (the bench's default line), the four-product FP32
+    solve with the dense forms, and the BF16 hi+lo split, each against the FP64 oracle's solve, with
+    the oracle's predicted floors of rel_f beside them. The oracle's solves are read from
+    --oracle-refs (files of tests/golden/make_error_table_refs.py --full) when present there, else
+    run here."""
     import numpy as np
 
     import oracle as O
     import synth
     iters = args.iters or 100
     rows = []
-    R = args.resid_refresh
-    dense = tl.LINE_DENSE
-    variants = [("fp32", tl.FP32, 0, dense), ("bf16x3", tl.BF16X3, 0, dense)]
-    if R > 0:
-        variants += [(f"fp32_refresh{R}", tl.FP32, R, dense), (f"bf16x3_refresh{R}", tl.BF16X3, R, dense),
-                     (f"fp32_3m_refresh{R}", tl.FP32_3M, R, dense),
-                     (f"fp32_3m_tile_forms_refresh{R}", tl.FP32_3M, R, tl.LINE_TILE_GRAD)]
+    variants = [("fp32_3m_tile_forms", tl.FP32_3M, tl.LINE_TILE_GRAD), ("fp32_dense", tl.FP32, tl.LINE_DENSE),
+                ("bf16x3", tl.BF16X3, tl.LINE_TILE_GRAD)]
     for snr in [float(v) for v in args.error_snrs.split(",")]:
-        wl = synth.large(snr_db=snr, config_id=4)
-        f_idx = 10
-        geom = wl.geometry()
-        prob = wl.problem(f_idx, geom)
-        lay = wl.layout(f_idx)
-        T = O.tiling(lay.tile_size, lay.rank_off, lay.rank_diag)
-        D64 = prob.D.astype(np.complex64)
-        U64 = prob.U.astype(np.complex64)
-        th64 = wl.theta0(f_idx, lay).astype(np.complex64)
-        perm = tl.hilbert_order(geom.rec_ix, geom.rec_iy)
-        dev = torch.device("cuda")
-        pd = torch.from_numpy(perm).to(dev)
-        D = tl.permute_columns(torch.from_numpy(D64).to(dev), pd)
-        U = tl.permute_columns(torch.from_numpy(U64).to(dev), pd)
-        th = torch.from_numpy(th64).to(dev)
-        plan = tl.Plan.from_layout(lay, geom.ns)
-        res = {}
-        for name, prec, refresh, line in variants:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            thT, fh = tl.solve(plan, D, U, th, iters, precision=prec, resid_refresh=refresh, line_products=line)
-            torch.cuda.synchronize()
-            res[name] = (thT.cpu().numpy().astype(np.complex128), time.perf_counter() - t0)
-            log(f"snr {snr}: {name} solve {res[name][1]:.2f} s")
-        Do = D64.astype(np.complex128)[:, perm]
-        Uo = U64.astype(np.complex128)[:, perm]
-        t0 = time.perf_counter()
-
-        def progress(t, state):
-            if t % 10 == 0:
-                log(f"snr {snr}: oracle iteration {t}/{iters} ({time.perf_counter() - t0:.0f} s)")
-        ref = O.solve(T, Do, Uo, th64.astype(np.complex128), iters=iters, record=progress)
-        t_or = time.perf_counter() - t0
-        log(f"snr {snr}: oracle {t_or:.1f} s")
-        fo = O.objective(T, Do, Uo, ref.theta)[0]
-        Xo = O.assemble(T, ref.theta)
-        for name, (thg, tg) in res.items():
-            fg = O.objective(T, Do, Uo, thg)[0]
-            rows.append({"snr_db": snr, "freq_hz": float(wl.freqs[f_idx]), "precision": name, "iters": iters,
-                         "rel_f": abs(fg - fo) / fo,
-                         "rel_X": float(np.linalg.norm(O.assemble(T, thg) - Xo) / np.linalg.norm(Xo)),
-                         "rel_theta": float(np.linalg.norm(thg - ref.theta) / np.linalg.norm(ref.theta)),
-                         "f_oracle": fo, "f_gpu": fg, "gpu_s": tg, "oracle_s": t_or})
-    return {"error_table": rows, "workload": "nr4096_ns2048_d256_k32 (frequency index 10 of 32, 5-35 Hz)"}
+        for f_idx in [int(v) for v in args.error_freqs.split(",")]:
+            wl = synth.large(snr_db=snr, config_id=4)
+            geom = wl.geometry()
+            prob = wl.problem(f_idx, geom)
+            lay = wl.layout(f_idx)
+            T = O.tiling(lay.tile_size, lay.rank_off, lay.rank_diag)
+            D64 = prob.D.astype(np.complex64)
+            U64 = prob.U.astype(np.complex64)
+            th64 = wl.theta0(f_idx, lay).astype(np.complex64)
+            perm = tl.hilbert_order(geom.rec_ix, geom.rec_iy)
+            dev = torch.device("cuda")
+            pd = torch.from_numpy(perm).to(dev)
+            D = tl.permute_columns(torch.from_numpy(D64).to(dev), pd)
+            U = tl.permute_columns(torch.from_numpy(U64).to(dev), pd)
+            th = torch.from_numpy(th64).to(dev)
+            plan = tl.Plan.from_layout(lay, geom.ns)
+            res = {}
+            for name, prec, line in variants:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                thT, fh = tl.solve(plan, D, U, th, iters, precision=prec, line_products=line)
+                torch.cuda.synchronize()
+                res[name] = (thT.cpu().numpy().astype(np.complex128), time.perf_counter() - t0)
+                log(f"snr {snr} f {f_idx}: {name} solve {res[name][1]:.2f} s")
+            operm = O.hilbert_order(geom.rec_ix, geom.rec_iy)
+            Do = D64.astype(np.complex128)[:, operm]
+            Uo = U64.astype(np.complex128)[:, operm]
+            path = os.path.join(args.oracle_refs, f"error_table_nr4096_snr{int(snr)}_f{f_idx}.npz") \
+                if args.oracle_refs else None
+            if path and os.path.exists(path):
+                ref = np.load(path)
+                th_or, t_or = ref["theta"], float(ref["oracle_s"])
+                floors = (float(ref["floor_fp32"]), float(ref["floor_bf16_split"]))
+                log(f"snr {snr} f {f_idx}: oracle solve read from {path}")
+            else:
+                t0 = time.perf_counter()
+                th_or = O.solve(T, Do, Uo, th64.astype(np.complex128), iters=iters).theta
+                t_or = time.perf_counter() - t0
+                Xr = O.assemble(T, th_or)
+                r_or = Do @ Xr - Uo
+                floors = (O.predicted_objective_floor(Do, Xr, r_or, 2.0 ** -24),
+                          O.predicted_objective_floor(Do, Xr, r_or, 2.0 ** -16))
+                log(f"snr {snr} f {f_idx}: oracle {t_or:.1f} s")
+            fo = O.objective(T, Do, Uo, th_or)[0]
+            Xo = O.assemble(T, th_or)
+            for name, (thg, tg) in res.items():
+                fg = O.objective(T, Do, Uo, thg)[0]
+                rows.append({"snr_db": snr, "freq_index": f_idx, "freq_hz": float(wl.freqs[f_idx]),
+                             "precision": name, "iters": iters,
+                             "rel_f": abs(fg - fo) / fo,
+                             "rel_X": float(np.linalg.norm(O.assemble(T, thg) - Xo) / np.linalg.norm(Xo)),
+                             "rel_theta": float(np.linalg.norm(thg - th_or) / np.linalg.norm(th_or)),
+                             "predicted_floor_rel_f": floors[1] if name.startswith("bf16") else floors[0],
+                             "bar": 5e-3 if name.startswith("bf16") else 1e-5,
+                             "f_oracle": fo, "f_gpu": fg, "gpu_s": tg, "oracle_s": t_or})
+                log(f"  {rows[-1]}")
+    return {"error_table": rows,
+            "workload": "nr4096_ns2048_d256_k32 (config 4 seeds; frequency indices of the 32 over 5-35 Hz)",
+            "floors": "predicted_floor_rel_f: oracle.predicted_objective_floor (2 sqrt(nr) u || |D||X| || / ||r||; "
+                      "u = 2^-24 for the FP32 forms, 2^-16 for the BF16 split), an upper estimate"}
 
 
 def main():
@@ -418,7 +451,9 @@ def main():
     ap.add_argument("--workload", choices=["batched", "large", "serving", "estimate", "tlr"], default="batched")
     ap.add_argument("--estimate-freqs", type=int, default=6, help="estimate: frequencies sampled over the band")
     ap.add_argument("--bench-lambda", type=float, default=3.0, help="estimate: Tikhonov lambda of the benchmark solve")
-    ap.add_argument("--requests", type=int, default=16, help="serving: requests in the Poisson stream")
+    ap.add_argument("--requests", type=int, default=128, help="serving: requests in the Poisson stream")
+    ap.add_argument("--sub-capacity", type=lambda v: [float(x) for x in v.split(",") if x], default=[0.5, 0.9],
+                    help="serving: also serve the stream at these fractions of the measured capacity")
     ap.add_argument("--max-active", type=int, default=4, help="serving: concurrent solves")
     ap.add_argument("--hbm-budget-gib", type=float, default=96.0, help="serving: admission budget")
     ap.add_argument("--iters", type=int, default=None)
@@ -435,13 +470,15 @@ def main():
     ap.add_argument("--error-table", action="store_true",
                     help="per-frequency error of FP32 and BF16x3 solves against the FP64 oracle (large workload)")
     ap.add_argument("--error-snrs", default="10,30", help="error table: SNRs in dB")
+    ap.add_argument("--error-freqs", default="0,10,21,31", help="error table: frequency indices of the 32")
+    ap.add_argument("--oracle-refs", default=None,
+                    help="error table: directory of the oracle's reference solves "
+                         "(tests/golden/make_error_table_refs.py --full --out DIR)")
     ap.add_argument("--line-products", choices=["dense", "tile", "tile-grad"], default="tile-grad",
                     help="line search products from the assembled X1, X2, or in tile form where cheaper "
                          "(tile-grad: the gradient's products too)")
     ap.add_argument("--streams", type=int, default=1,
                     help="batched solve: sub-batches on their own streams (problem i in sub-batch i %% streams)")
-    ap.add_argument("--resid-refresh", type=int, default=20,
-                    help="error table: also an FP32 solve that recomputes r = D C(theta) - U every this many iterations")
     ap.add_argument("--no-extra", dest="extra", action="store_false",
                     help="batched workload: skip the nr 64 latency and nr 4096 throughput objects")
     ap.add_argument("--large-steps", type=int, default=2, help="timed steps of the nr 4096 object")

@@ -6,7 +6,11 @@ sizes and iteration count. The scheduler admits requests in arrival order
 (FIFO, no overtaking) as soon as a slot and enough of the HBM budget are free;
 an admitted solve keeps its inputs, factors and optimiser state resident and
 runs on its own HIP stream, so solves admitted at different times overlap on
-the device. A request whose footprint exceeds the whole budget is rejected.
+the device. A request's footprint counts everything it holds on the device
+while admitted: the solve workspace, theta in and out, the f-history, its
+inputs D and U and, when its inputs are produced at admission, the
+transient memory that takes. A request whose footprint exceeds the whole
+budget is rejected.
 
 The policy is independent of the device: `Server` drives a backend with
 `footprint(req)`, `start(req)`, `done(handle)`, `finish(handle)` and a clock.
@@ -46,9 +50,10 @@ class Server:
         self.max_active = int(max_active)
         self.in_use = 0
         self.peak_in_use = 0
-        self.log: List[tuple] = []   # (time, event, rid)
+        self.log: List[tuple] = []   # (time, event, rid); "wait_memory": the head waits for memory, not a slot
 
-    def run(self, jobs: List[Job], poll_interval: float = 2e-4) -> List[Job]:
+    def run(self, jobs: List[Job], poll_interval: float = 2e-4,
+            on_done: Optional[Callable[[Job], None]] = None) -> List[Job]:
         clock = self.backend.clock
         pending = collections.deque(sorted(jobs, key=lambda j: (j.arrival, j.rid)))
         active: Dict[int, tuple] = {}
@@ -63,6 +68,8 @@ class Server:
                     self.in_use -= job.footprint
                     del active[rid]
                     self.log.append((job.finished, "done", rid))
+                    if on_done is not None:
+                        on_done(job)
             # admissions in arrival order; the head waits if it does not fit yet
             while pending and pending[0].arrival <= now and len(active) < self.max_active:
                 job = pending[0]
@@ -74,6 +81,8 @@ class Server:
                     self.log.append((now, "reject", job.rid))
                     continue
                 if self.in_use + job.footprint > self.budget:
+                    if not self.log or self.log[-1][1:] != ("wait_memory", job.rid):
+                        self.log.append((now, "wait_memory", job.rid))
                     break
                 pending.popleft()
                 self.in_use += job.footprint
@@ -151,13 +160,17 @@ class VirtualClock:
 @dataclasses.dataclass
 class SolveRequest:
     plan: Any          # paper_2412_14973_amd.Plan
-    D: Any             # device complex64 ns x nr (Hilbert order)
+    D: Any             # device complex64 ns x nr (Hilbert order), or None: made at admission
     U: Any
     theta0: Any
     iters: int
     precision: int = 0
     lbfgs_m: int = 5
     line_products: int = 0    # LINE_DENSE, LINE_TILE or LINE_TILE_GRAD
+    # inputs produced at admission, on the request's stream: make_inputs() -> (D, U, theta0) as above;
+    # make_bytes: the device memory that takes beyond D, U and theta0 themselves (transients)
+    make_inputs: Optional[Callable[[], tuple]] = None
+    make_bytes: int = 0
 
 
 class GpuBackend:
@@ -174,12 +187,14 @@ class GpuBackend:
         self.free_streams = list(range(n_streams))
 
     def footprint(self, req: SolveRequest) -> int:
-        """Device bytes a solve keeps resident: workspace + theta + f-history (+ inputs)."""
+        """Device bytes a solve holds while admitted: the solve workspace, theta in and out, the
+        f-history, the inputs D and U, and the transients of making them at admission."""
         from . import _lib
         opts = self.make_opts(req.iters, lbfgs_m=req.lbfgs_m, precision=req.precision,
                               line_products=req.line_products)
         ws = req.plan.workspace_bytes(_lib.OP_SOLVE, opts)
-        return ws + 8 * req.plan.theta_size + 8 * (req.iters + 1)
+        inputs = 2 * 8 * req.plan.ns * req.plan.nr
+        return ws + 2 * 8 * req.plan.theta_size + 8 * (req.iters + 1) + inputs + int(req.make_bytes)
 
     def start(self, req: SolveRequest):
         from . import solve
@@ -188,11 +203,13 @@ class GpuBackend:
         stream = self.streams[sidx]
         stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(stream):
-            theta, fh = solve(req.plan, req.D, req.U, req.theta0, req.iters, lbfgs_m=req.lbfgs_m,
+            D, U, th0 = (req.D, req.U, req.theta0) if req.make_inputs is None else req.make_inputs()
+            theta, fh = solve(req.plan, D, U, th0, req.iters, lbfgs_m=req.lbfgs_m,
                               precision=req.precision, line_products=req.line_products)
             ev = torch.cuda.Event()
             ev.record(stream)
-        return {"event": ev, "stream": sidx, "theta": theta, "fhist": fh}
+        # the inputs stay referenced until the solve is finished (made ones are freed then)
+        return {"event": ev, "stream": sidx, "theta": theta, "fhist": fh, "inputs": (D, U, th0)}
 
     def done(self, handle) -> bool:
         return handle["event"].query()

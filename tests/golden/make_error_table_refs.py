@@ -10,8 +10,8 @@ compares with:
     oracle.predicted_objective_floor of D, C(theta_T), r_T;
   * ||theta_T|| and ||C(theta_T)||_F;
   * --full: theta_T itself (complex128); otherwise (the committed test references) theta_T and X_T
-    = C(theta_T) at seeded random positions (1/16 of theta's entries, 2^18 of X's), from which the
-    test estimates rel_theta and rel_X.
+    = C(theta_T) at seeded random positions (1/16 of theta's entries, 2^18 of X's; values rounded to
+    complex64), from which the test estimates rel_theta and rel_X.
 
 Usage: python tests/golden/make_error_table_refs.py --out DIR [--snrs 10,30] [--freqs 10] [--full]
 The committed tests/golden/error_table_nr4096_snr{10,30}_f10.npz were written with the defaults.
@@ -71,7 +71,9 @@ def reference(snr, f_idx, full, log=print):
         rng = np.random.default_rng(SAMPLE_SEED)
         ti = np.sort(rng.choice(ref.theta.size, ref.theta.size // THETA_SAMPLE_FRACTION, replace=False))
         xi = np.sort(rng.choice(X.size, X_SAMPLES, replace=False))
-        out.update(theta_idx=ti, theta_val=ref.theta[ti], X_idx=xi, X_val=X.reshape(-1)[xi])
+        # positions as int32, values rounded to complex64 (6e-8 relative, far below the 1e-5 bar)
+        out.update(theta_idx=ti.astype(np.int32), theta_val=ref.theta[ti].astype(np.complex64),
+                   X_idx=xi.astype(np.int32), X_val=X.reshape(-1)[xi].astype(np.complex64))
     return out
 
 

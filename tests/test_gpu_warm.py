@@ -113,3 +113,44 @@ def test_rank_invalid_arguments(tl):
         with pytest.raises(tl.TLRMDDError) as e:
             tl.tile_ranks(X, d, eps)
         assert e.value.status == 1
+
+
+# tile sizes the estimate workload runs (bench --workload estimate: 64, 128, 256 at nr = ns = 1024)
+@pytest.mark.parametrize("d,freq", [(128, 12.0), (256, 12.0), (128, 30.0), (256, 30.0)])
+def test_tile_ranks_large_tiles(tl, d, freq):
+    X = _green(32, freq, seed=5)
+    assert _margin(X.astype(np.complex128), d, 0.01) > 1e-9
+    ko, kd, v0 = tl.tile_ranks(torch.from_numpy(X).cuda(), d, 0.01)
+    _, ko_or, kd_or, v0o = O.tile_ranks(X.astype(np.complex128), d, 0.01)
+    print(f"d {d} f {freq}: ranks {list(ko)[:8]}... diagonal {list(kd)}")
+    assert list(ko) == ko_or and list(kd) == kd_or
+    assert v0 == pytest.approx(v0o, rel=1e-12)
+
+
+@pytest.mark.parametrize("freq", [6.0, 30.0])
+def test_choose_layout_estimate_candidates(tl, freq):
+    X = _green(32, freq, seed=6)
+    cand = [64, 128, 256]
+    for c in cand:
+        assert _margin(X.astype(np.complex128), c, 0.01) > 1e-9
+    d, sizes, ro, rd, ent = tl.choose_layout(torch.from_numpy(X).cuda(), cand, eps=0.01)
+    do, so, roo, rdo, ento = O.choose_layout(X.astype(np.complex128), cand, eps=0.01)
+    print(f"f {freq}: d {d} entries {list(ent)}")
+    assert d == do and list(sizes) == so and list(ro) == roo and list(rd) == rdo and list(ent) == ento
+
+
+@pytest.mark.parametrize("d", [128, 256])
+def test_warm_start_large_tiles(tl, d):
+    X = _green(32, 18.0, seed=7)
+    _, ko, kd, _ = O.tile_ranks(X.astype(np.complex128), d, 0.01)
+    sizes = O.split_sizes(X.shape[0], d)
+    ko = [max(1, k) for k in ko]
+    kd = [-1 if k >= (s + 1) // 2 else max(1, k) for k, s in zip(kd, sizes)]
+    T = O.tiling(sizes, ko, kd)
+    plan = tl.Plan(sizes, ko, kd, X.shape[0])
+    th = tl.warm_start(plan, torch.from_numpy(X).cuda()).cpu().numpy().astype(np.complex128)
+    tho = O.warm_start(T, X.astype(np.complex128))
+    Xg, Xo = O.assemble(T, th), O.assemble(T, tho)
+    rel = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
+    print(f"warm start d {d}: rel assembled {rel:.2e}")
+    assert rel <= 1e-6

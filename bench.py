@@ -193,9 +193,8 @@ def serving(tl, torch, args):
         out = []
         for r in stream:
             p = plans[r.rid]
-            # transients of making the inputs (complex128 distances, fields, noise) and the natural-order
-            # complex64 copies next to the gathered ones
-            make_bytes = 72 * p.ns * p.nr + 56 * p.nr * p.nr + 16 * p.ns * p.nr
+            # transients of making the inputs on the device and the natural-order copies
+            make_bytes = synth.device_generate_bytes(p.ns, p.nr)
             req = serve.SolveRequest(p, None, None, None, r.iters, prec, line_products=line, make_inputs=make(r),
                                      make_bytes=make_bytes)
             out.append(serve.Job(rid=r.rid, arrival=r.arrival, payload=req))
@@ -236,10 +235,11 @@ def serving(tl, torch, args):
         for k in res2))
     out["speedup_solves_per_s"] = out["continuous"]["solves_per_s"] / out["one_at_a_time"]["solves_per_s"]
     cap = out["continuous"]["solves_per_s"]
+    n_sub = args.sub_capacity_requests
     for frac in args.sub_capacity:
         rate = frac * cap
-        stream = synth.request_stream(args.requests, rate=rate, iters=iters)
-        assert [(r.n_side, r.ns_mode, r.d, r.k) for r in stream] == [(r.n_side, r.ns_mode, r.d, r.k) for r in reqs]
+        stream = synth.request_stream(n_sub, rate=rate, iters=iters)
+        assert [(r.n_side, r.ns_mode, r.d, r.k) for r in stream] == [(r.n_side, r.ns_mode, r.d, r.k) for r in reqs[:n_sub]]
         out[f"continuous_at_{frac:g}x_capacity"], _ = run(stream, args.max_active, f"continuous at {frac:g}x capacity")
         out[f"continuous_at_{frac:g}x_capacity"]["arrival_rate_per_s"] = rate
     return out
@@ -454,6 +454,8 @@ def main():
     ap.add_argument("--requests", type=int, default=128, help="serving: requests in the Poisson stream")
     ap.add_argument("--sub-capacity", type=lambda v: [float(x) for x in v.split(",") if x], default=[0.5, 0.9],
                     help="serving: also serve the stream at these fractions of the measured capacity")
+    ap.add_argument("--sub-capacity-requests", type=int, default=64,
+                    help="serving: requests (the stream's first ones) of the sub-capacity runs")
     ap.add_argument("--max-active", type=int, default=4, help="serving: concurrent solves")
     ap.add_argument("--hbm-budget-gib", type=float, default=96.0, help="serving: admission budget")
     ap.add_argument("--iters", type=int, default=None)

@@ -13,12 +13,15 @@
 // r^T is written by the kernel that updates r. Operands are pre-split into
 // separate hi and lo planes of interleaved complex BF16 (4 bytes per complex).
 //
-// Tiling: 256 threads = 4 waves (2 x 2), workgroup tile 128 rows x 128
-// complex columns, 8 complex k per stage. Operands go straight from global
+// Tiling: 512 threads = 8 waves (4 x 2), workgroup tile 256 rows x 128
+// complex columns, one workgroup per CU, 8 complex k per stage. At the BF16
+// rate a 128 x 128 tile needs about 13 TB/s of operand bandwidth from L2 and
+// the memory-side cache; the 256-row tile shares each B panel between twice
+// the rows and cuts that by a quarter. Operands go straight from global
 // memory to LDS (buffer_load ... lds, no staging registers) into a 4-stage
-// ring (four planes per stage: A hi/lo, B hi/lo, 16-byte chunks XOR-swizzled
-// so operand reads are bank-conflict free); loads run three stages ahead of
-// the matrix cores. A stage's twelve fragment reads are one inline-asm group
+// ring (four planes per stage: A hi/lo of 256 rows, B hi/lo of 128 rows,
+// 16-byte chunks XOR-swizzled so operand reads are bank-conflict free; 96 KiB);
+// loads run three stages ahead of the matrix cores. A stage's twelve fragment reads are one inline-asm group
 // with its own LDS wait: as plain loads the compiler, unable to tell the ring
 // buffers apart from the one the DMA just targeted, would wait for that DMA
 // too and undo the prefetch. Per stage each wave issues 2 x 4 x 3 MFMAs,
@@ -35,12 +38,15 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int BM = GEMM_BM, BN = GEMM_BN;
+constexpr int BM = 2 * GEMM_BM, BN = GEMM_BN;   // 256 x 128 (complex) workgroup tile
 constexpr int BKC = 8;                    // complex k per stage (= 16 real k = one MFMA)
 constexpr int ROWB = 32;                  // bytes per LDS row of a plane (8 complex BF16)
-constexpr int PLANE = 128 * ROWB;         // 4 KiB per plane
-constexpr int STAGE = 4 * PLANE;          // A hi, A lo, B hi, B lo
-constexpr int NSTAGE = 4;                 // LDS ring depth (64 KiB per workgroup)
+constexpr int PLANE_A = BM * ROWB;        // 8 KiB per A plane
+constexpr int PLANE_B = BN * ROWB;        // 4 KiB per B plane
+constexpr int OFF_AL = PLANE_A, OFF_BH = 2 * PLANE_A, OFF_BL = 2 * PLANE_A + PLANE_B;
+constexpr int STAGE = 2 * PLANE_A + 2 * PLANE_B;   // A hi, A lo, B hi, B lo: 24 KiB
+constexpr int NSTAGE = 4;                 // LDS ring depth (96 KiB per workgroup)
+constexpr int NTHREADS = 512;
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
@@ -53,7 +59,7 @@ __device__ __forceinline__ void wait_vm() {
 typedef __attribute__((address_space(3))) void *lds_ptr_t;
 
 template <int MODE>
-__global__ __launch_bounds__(256, 2) void cgemm_bf16x3_kernel(GemmArgsB g) {
+__global__ __launch_bounds__(NTHREADS, 1) void cgemm_bf16x3_kernel(GemmArgsB g) {
     // four distinct LDS objects (one per ring stage): reads of one stage and DMA into another are
     // then provably disjoint, so no conservative vmcnt wait is needed before the operand reads
     __shared__ __attribute__((aligned(1024))) unsigned char sm0[STAGE];
@@ -78,7 +84,7 @@ __global__ __launch_bounds__(256, 2) void cgemm_bf16x3_kernel(GemmArgsB g) {
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform (LDS DMA base in M0)
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave >> 1, wn = wave & 1;                   // wave rows 0..3, wave columns 0..1
 
     const __amdgpu_buffer_rsrc_t rAh = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(g.Ahi + z * g.sA * 2), (short)0, (int)g.bytesA, 0x00020000);
@@ -89,28 +95,33 @@ __global__ __launch_bounds__(256, 2) void cgemm_bf16x3_kernel(GemmArgsB g) {
     const __amdgpu_buffer_rsrc_t rBl = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(g.Blo + z * g.sB * 2), (short)0, (int)g.bytesB, 0x00020000);
 
-    // Direct global -> LDS loads: lane l of wave w fills the 16 bytes at (w * 64 + l) * 16 of
-    // each plane, i.e. row w*32 + l/2, stored chunk l&1. Chunks are XOR-swizzled by bit 3 of the
-    // row (stored = actual ^ ((row >> 3) & 1)) so the 16-byte operand reads hit distinct banks.
+    // Direct global -> LDS loads: lane l of wave w fills the 16 bytes at (w * 64 + l) * 16 of a
+    // plane, i.e. row w*32 + l/2, stored chunk l&1. Chunks are XOR-swizzled by bit 3 of the row
+    // (stored = actual ^ ((row >> 3) & 1)) so the 16-byte operand reads hit distinct banks. Every
+    // wave loads its 32 rows of both A planes; waves 0-3 load the B hi plane, waves 4-7 the B lo
+    // plane (32 rows each): three loads per wave and stage. Rows of A past M read as zero (buffer
+    // range), so a 256-row tile may overhang a matrix of 128 * odd rows.
     const int lrow = wave * 32 + (lane >> 1);
     const int lchunk = (lane & 1) ^ ((lrow >> 3) & 1);
     const uint32_t offA = (uint32_t)(((int64_t)(m0 + lrow) * g.lda) * 4 + lchunk * 16);
+    const int brow = (wave & 3) * 32 + (lane >> 1);
+    const bool b_lo = wave >= 4;
     uint32_t offB;
     {
-        int64_t row = n0 + lrow;
+        int64_t row = n0 + brow;
         if (MODE == GM_LINE) {
-            const int grp2 = lrow >> 5;
-            row = n0 + (grp2 >> 1) * 32 + (lrow & 31) + ((grp2 & 1) ? g.b2_rows : 0);
+            const int grp2 = brow >> 5;
+            row = n0 + (grp2 >> 1) * 32 + (brow & 31) + ((grp2 & 1) ? g.b2_rows : 0);
         }
-        offB = (uint32_t)(row * g.ldb * 4 + lchunk * 16);
+        offB = (uint32_t)(row * g.ldb * 4 + ((lane & 1) ^ ((brow >> 3) & 1)) * 16);
     }
+    const __amdgpu_buffer_rsrc_t rB = b_lo ? rBl : rBh;
+    const int dstB = (b_lo ? OFF_BL : OFF_BH) + (wave & 3) * 1024;
     auto issue = [&](unsigned char *buf, int kt) {
-        unsigned char *st = buf + wave * 1024;
         const int so = kt * BKC * 4;
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rAh, (lds_ptr_t)(st + 0 * PLANE), 16, (int)offA, so, 0, 0);
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rAl, (lds_ptr_t)(st + 1 * PLANE), 16, (int)offA, so, 0, 0);
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rBh, (lds_ptr_t)(st + 2 * PLANE), 16, (int)offB, so, 0, 0);
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rBl, (lds_ptr_t)(st + 3 * PLANE), 16, (int)offB, so, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rAh, (lds_ptr_t)(buf + wave * 1024), 16, (int)offA, so, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rAl, (lds_ptr_t)(buf + OFF_AL + wave * 1024), 16, (int)offA, so, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rB, (lds_ptr_t)(buf + dstB), 16, (int)offB, so, 0, 0);
     };
 
     floatx16 acc[2][4];
@@ -145,19 +156,21 @@ __global__ __launch_bounds__(256, 2) void cgemm_bf16x3_kernel(GemmArgsB g) {
         const uint32_t va = lds_addr(st) + a_off, vb = lds_addr(st) + b_off;
         u32x4 ah0, ah1, al0, al1, bh0, bh1, bh2, bh3, bl0, bl1, bl2, bl3;
         // all twelve fragment reads of the stage in flight together, waited in the same block
+        // A hi rows +0 / +32 at 0 / 1024, A lo at 8192 / 9216; B hi (16 rows per block) at 16384 + 512 bn,
+        // B lo at 20480 + 512 bn
         asm volatile(
             "ds_read_b128 %0, %12\n\t"
             "ds_read_b128 %1, %12 offset:1024\n\t"
-            "ds_read_b128 %2, %12 offset:4096\n\t"
-            "ds_read_b128 %3, %12 offset:5120\n\t"
-            "ds_read_b128 %4, %13 offset:8192\n\t"
-            "ds_read_b128 %5, %13 offset:8704\n\t"
-            "ds_read_b128 %6, %13 offset:9216\n\t"
-            "ds_read_b128 %7, %13 offset:9728\n\t"
-            "ds_read_b128 %8, %13 offset:12288\n\t"
-            "ds_read_b128 %9, %13 offset:12800\n\t"
-            "ds_read_b128 %10, %13 offset:13312\n\t"
-            "ds_read_b128 %11, %13 offset:13824\n\t"
+            "ds_read_b128 %2, %12 offset:8192\n\t"
+            "ds_read_b128 %3, %12 offset:9216\n\t"
+            "ds_read_b128 %4, %13 offset:16384\n\t"
+            "ds_read_b128 %5, %13 offset:16896\n\t"
+            "ds_read_b128 %6, %13 offset:17408\n\t"
+            "ds_read_b128 %7, %13 offset:17920\n\t"
+            "ds_read_b128 %8, %13 offset:20480\n\t"
+            "ds_read_b128 %9, %13 offset:20992\n\t"
+            "ds_read_b128 %10, %13 offset:21504\n\t"
+            "ds_read_b128 %11, %13 offset:22016\n\t"
             "s_waitcnt lgkmcnt(0)"
             : "=&v"(ah0), "=&v"(ah1), "=&v"(al0), "=&v"(al1), "=&v"(bh0), "=&v"(bh1), "=&v"(bh2), "=&v"(bh3),
               "=&v"(bl0), "=&v"(bl1), "=&v"(bl2), "=&v"(bl3)
@@ -186,9 +199,9 @@ __global__ __launch_bounds__(256, 2) void cgemm_bf16x3_kernel(GemmArgsB g) {
     // one ring step: stage kt (in `cur`) has landed once at most the loads of the two stages
     // issued after it are outstanding; then the buffer of stage kt-1 (`nxt`) takes stage kt+3
     auto step = [&](int kt, int nk, const unsigned char *cur, unsigned char *nxt) {
-        const int ahead = min(NSTAGE - 2, nk - 1 - kt);
-        if (ahead >= 2) wait_vm<8>();
-        else if (ahead == 1) wait_vm<4>();
+        const int ahead = min(NSTAGE - 2, nk - 1 - kt);   // stages issued after kt (3 loads each)
+        if (ahead >= 2) wait_vm<6>();
+        else if (ahead == 1) wait_vm<3>();
         else wait_vm<0>();
         // Bare barrier: each wave has waited for its own DMA of stage kt above, so after the
         // barrier the whole stage is in LDS, and every wave has finished reading stage kt-1.
@@ -219,17 +232,20 @@ __global__ __launch_bounds__(256, 2) void cgemm_bf16x3_kernel(GemmArgsB g) {
     ea.Me = g.Me;
     ea.Ne = g.Ne;
     ea.partials = g.partials ? g.partials + z * g.sP : nullptr;
-    gemm_epilogue<MODE>(acc, ea, m0, n0, pid);
+    ea.Mrows = g.M;
+    ea.slot_step = g.tiles_n;
+    // partial slots in the numbering of 128-row tiles (the finalisation sums M/128 x tiles_n slots)
+    gemm_epilogue<MODE, 4>(acc, ea, m0, n0, 2 * tm * g.tiles_n + tn);
 }
 
 }  // namespace
 
 hipError_t launch_cgemm_bf16(int mode, const GemmArgsB &a0, int batch, hipStream_t s) {
     GemmArgsB a = a0;
-    a.tiles_m = a.M / BM;
+    a.tiles_m = (a.M + BM - 1) / BM;
     a.tiles_n = (mode == GM_LINE) ? a.N / (BN / 2) : a.N / BN;
     if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
-    if (a.M % BM || a.N % BN || a.K % (BKC * NSTAGE) || a.K <= 0) return hipErrorInvalidValue;
+    if (a.M % GEMM_BM || a.N % BN || a.K % (BKC * NSTAGE) || a.K <= 0) return hipErrorInvalidValue;
     const int64_t bytesA = (int64_t)a.M * a.lda * 4;
     const int64_t rowsB = (mode == GM_LINE) ? a.b2_rows + a.N : a.N;
     const int64_t bytesB = rowsB * a.ldb * 4;
@@ -238,9 +254,9 @@ hipError_t launch_cgemm_bf16(int mode, const GemmArgsB &a0, int batch, hipStream
     a.bytesB = (uint32_t)bytesB;
     dim3 grid(a.tiles_m * a.tiles_n, batch);
     switch (mode) {
-        case GM_STORE: hipLaunchKernelGGL(cgemm_bf16x3_kernel<GM_STORE>, grid, dim3(256), 0, s, a); break;
-        case GM_RESID: hipLaunchKernelGGL(cgemm_bf16x3_kernel<GM_RESID>, grid, dim3(256), 0, s, a); break;
-        case GM_LINE:  hipLaunchKernelGGL(cgemm_bf16x3_kernel<GM_LINE>, grid, dim3(256), 0, s, a); break;
+        case GM_STORE: hipLaunchKernelGGL(cgemm_bf16x3_kernel<GM_STORE>, grid, dim3(NTHREADS), 0, s, a); break;
+        case GM_RESID: hipLaunchKernelGGL(cgemm_bf16x3_kernel<GM_RESID>, grid, dim3(NTHREADS), 0, s, a); break;
+        case GM_LINE:  hipLaunchKernelGGL(cgemm_bf16x3_kernel<GM_LINE>, grid, dim3(NTHREADS), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -28,21 +28,36 @@ struct EpiArgs {
     int64_t lde;
     int32_t Me, Ne;
     double *partials;  // this problem's partial sums
+    int32_t Mrows;     // rows of C (a 256-row tile may overhang it by 128; WROWS = 4 only)
+    int32_t slot_step; // WROWS = 4: partial slot of the second 128-row half = first + slot_step
 };
 
-// Epilogue of a 128 x 128 (complex) workgroup tile held as 4 waves x 2 x 4
-// accumulator blocks. GM_STORE: C = acc. GM_RESID: C = acc - E, partial
-// sum |C|^2. GM_LINE: blocks bn = 0,1 are a and bn = 2,3 are b at the same
-// columns; partial sums Re<r,a>, |a|^2, Re<r,b>, Re<a,b>, |b|^2. Partial sums
-// of 16 products are formed in FP32 registers and folded into FP64.
-template <int MODE>
+// Epilogue of a workgroup tile of WROWS x 64 rows and 128 complex columns held as 2 WROWS waves
+// (wave w: rows 64 (w / 2), columns 64 (w % 2)) of 2 x 4 accumulator blocks. GM_STORE: C = acc.
+// GM_RESID: C = acc - E, partial sum |C|^2. GM_LINE: blocks bn = 0,1 are a and bn = 2,3 are b at the
+// same columns; partial sums Re<r,a>, |a|^2, Re<r,b>, Re<a,b>, |b|^2. Partial sums of 16 products are
+// formed in FP32 registers and folded into FP64; each 128-row half's four waves are reduced in a
+// fixed order into one partial slot (WROWS = 2: slot pid; WROWS = 4: slots pid and pid + slot_step,
+// the second only when that half lies inside C).
+template <int MODE, int WROWS = 2>
 __device__ __forceinline__ void gemm_epilogue(floatx16 (&acc)[2][4], const EpiArgs &ea, int m0, int n0, int pid) {
-    __shared__ double red[4][5];
+    constexpr int NWAVE = 2 * WROWS;
+    __shared__ double red[NWAVE][5];
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int j32 = lane & 31;
+    // WROWS = 4: the waves of a 128-row half past the end of C write nothing
+    if (WROWS == 4 && m0 + wm * 64 >= ea.Mrows) {
+        if (MODE != GM_STORE) {
+            if (lane == 0)
+#pragma unroll
+                for (int s = 0; s < 5; ++s) red[wave][s] = 0.0;
+            __syncthreads();
+        }
+        return;
+    }
     // ---- epilogues ----
     float *C = reinterpret_cast<float *>(ea.C);
     const int64_t ldc2 = 2 * (int64_t)ea.ldc;
@@ -121,9 +136,17 @@ __device__ __forceinline__ void gemm_epilogue(floatx16 (&acc)[2][4], const EpiAr
         if (lane == 0) red[wave][s] = v;
     }
     __syncthreads();
-    if (t < NS) {
-        const double v = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
-        ea.partials[(int64_t)pid * NS + t] = v;
+    if (WROWS == 2) {
+        if (t < NS) {
+            const double v = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+            ea.partials[(int64_t)pid * NS + t] = v;
+        }
+    } else if (t < 2 * NS) {
+        const int h = t / NS, q = t % NS;
+        if (m0 + 128 * h < ea.Mrows) {
+            const double v = ((red[4 * h][q] + red[4 * h + 1][q]) + red[4 * h + 2][q]) + red[4 * h + 3][q];
+            ea.partials[(int64_t)(pid + h * ea.slot_step) * NS + q] = v;
+        }
     }
 }
 

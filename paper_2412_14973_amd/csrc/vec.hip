@@ -304,24 +304,23 @@ __global__ __launch_bounds__(256) void combine_kernel(const VecSeg *__restrict__
     const SolveScalars &s = sc[sg.prob];
     const double *c = coef + (int64_t)sg.prob * cstride;
     const int count = s.count;
-    double acc[4 * VQ];
+    // FP32 vectors and FP32 accumulation (the coefficients come from the FP64 two-loop on the Gram
+    // matrix and are rounded once to FP32), fixed order: g, then the pairs newest first
+    V16 r;
     {
         const V16 vg = ld16(g, sg);
-        const double cg = c[2 * m1];
+        const float cg = (float)c[2 * m1];
 #pragma unroll
-        for (int u = 0; u < 4 * VQ; ++u) acc[u] = cg * (double)vg.v[u];
+        for (int u = 0; u < 4 * VQ; ++u) r.v[u] = cg * vg.v[u];
     }
     for (int i = 0; i < count; ++i) {
         const int j = ring_slot(s, i, m1);
-        const double cs = c[j], cy = c[m1 + j];
+        const float cs = (float)c[j], cy = (float)c[m1 + j];
         const V16 sj = ld16(Sb + j * stride2, sg);
         const V16 yj = ld16(Yb + j * stride2, sg);
 #pragma unroll
-        for (int u = 0; u < 4 * VQ; ++u) acc[u] = fma(cy, (double)yj.v[u], fma(cs, (double)sj.v[u], acc[u]));
+        for (int u = 0; u < 4 * VQ; ++u) r.v[u] = fmaf(cy, yj.v[u], fmaf(cs, sj.v[u], r.v[u]));
     }
-    V16 r;
-#pragma unroll
-    for (int u = 0; u < 4 * VQ; ++u) r.v[u] = (float)acc[u];
     st16(p, sg, r);
 }
 

@@ -358,6 +358,13 @@ def device_problem(req: Request, device, config_id: int = 5):
     return D, U, th, lay, geom
 
 
+def device_generate_bytes(ns: int, nr: int) -> int:
+    """Upper estimate of the device memory device_generate holds at its peak beyond the permuted
+    complex64 D and U a caller keeps: distances, fields, noise and their temporaries (complex64),
+    and the natural-order outputs."""
+    return 64 * ns * nr + 28 * nr * nr
+
+
 def device_workload_problem(wl: Workload, f_idx: int, device):
     """(D, U, theta0) of frequency f_idx of a workload, generated on `device` (see device_generate);
     the values differ from Workload.problem's (another generator) but follow the same recipe."""
@@ -370,37 +377,39 @@ def device_generate(geom: Geometry, freq: float, snr_db: float, lay: Layout, con
 
     Same recipe as make_problem (homogeneous Green's functions, exact-SNR noise
     on U, 5 % noise on D, normalisation by 1/min distance), computed in
-    complex128 with torch's device generator seeded from (config, item),
-    returned as complex64 in natural receiver order.
+    complex64 with torch's device generator seeded from (config, item), in
+    natural receiver order. Everything stays on the device and is queued on the
+    current stream (no host synchronisation), so a server can make a request's
+    inputs when it admits the request without stalling its loop.
     """
     import torch
     seed = int(np.random.SeedSequence(BASE_SEED, spawn_key=(config_id, item, P_REQUEST))
                .generate_state(1)[0])
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
-    rec = torch.as_tensor(geom.rec_xyz, device=device)
-    src = torch.as_tensor(geom.src_xyz, device=device)
-    w = 2.0 * math.pi * freq
+    rec = torch.as_tensor(geom.rec_xyz, device=device, dtype=torch.float32)
+    src = torch.as_tensor(geom.src_xyz, device=device, dtype=torch.float32)
+    k = 2.0 * math.pi * freq / VELOCITY
     dsr = torch.cdist(src, rec)
-    D_clean = torch.exp(-1j * w * dsr / VELOCITY) / dsr
+    D_clean = torch.polar(1.0 / dsr, -k * dsr)
     drr = torch.cdist(rec, rec)
-    X_true = torch.exp(-1j * w * drr / VELOCITY) / (drr + X_TRUE_OFFSET)
+    X_true = torch.polar(1.0 / (drr + X_TRUE_OFFSET), -k * drr)
     X_true = 0.5 * (X_true + X_true.T)
     U_clean = D_clean @ X_true
     del X_true, drr
 
     def cg(shape):
-        return torch.complex(torch.randn(shape, generator=gen, device=device, dtype=torch.float64),
-                             torch.randn(shape, generator=gen, device=device, dtype=torch.float64))
+        return torch.complex(torch.randn(shape, generator=gen, device=device, dtype=torch.float32),
+                             torch.randn(shape, generator=gen, device=device, dtype=torch.float32))
     n_u = cg(U_clean.shape)
     U = U_clean + n_u * (torch.linalg.norm(U_clean) / (torch.linalg.norm(n_u) * 10.0 ** (snr_db / 20.0)))
     del n_u, U_clean
     n_d = cg(D_clean.shape)
     D = D_clean + n_d * (0.05 * torch.linalg.norm(D_clean) / torch.linalg.norm(n_d))
     del n_d, D_clean
-    alpha = 1.0 / float(dsr.min())
+    dmin = dsr.min()   # the normalisation 1 / alpha = min distance, kept on the device
     n = theta_length(lay)
     s = math.sqrt(1e-2 / 2.0)
     th = torch.complex(s * torch.randn(n, generator=gen, device=device, dtype=torch.float32),
                        s * torch.randn(n, generator=gen, device=device, dtype=torch.float32))
-    return (D / alpha).to(torch.complex64).contiguous(), (U / alpha).to(torch.complex64).contiguous(), th
+    return (D * dmin).contiguous(), (U * dmin).contiguous(), th

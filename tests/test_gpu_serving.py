@@ -131,7 +131,7 @@ def _c5_jobs(tl, prec, line):
             D, U, th, _, _ = synth.device_problem(r, dev)
             return tl.permute_columns(D, pd), tl.permute_columns(U, pd), th
         req = serve.SolveRequest(plan, None, None, None, iters, prec, line_products=line, make_inputs=inputs,
-                                 make_bytes=72 * plan.ns * plan.nr + 56 * plan.nr * plan.nr + 16 * plan.ns * plan.nr)
+                                 make_bytes=synth.device_generate_bytes(plan.ns, plan.nr))
         jobs.append(serve.Job(rid=rid, arrival=r.arrival, payload=req))
         reqs.append(r)
     return jobs, reqs

@@ -90,12 +90,10 @@ def precision_info(tl, name):
 
 
 TRAFFIC_RECORDS = {   # (precision, line-search form, product kind) -> (counter summary, kernel sources)
-    ("fp32", "dense", "gemm_line"): ("cgemm_line_traffic.json", ("cgemm.hip", "gemm_common.hpp")),
-    ("fp32_3m", "dense", "gemm_line"): ("cgemm3m_line_traffic.json", ("cgemm3m.hip", "gemm_common.hpp")),
     ("fp32_3m", "tile_grad", "gemm_line"): ("cgemm3m_line_traffic_tile.json", ("cgemm3m.hip", "gemm_common.hpp")),
     ("fp32_3m", "tile_grad", "gemm_adjoint"): ("cgemm3m_adjoint_traffic_tile.json",
                                                ("cgemm3m.hip", "gemm_common.hpp")),
-    ("bf16x3", "dense", "gemm_line"): ("cgemm_bf16_line_traffic.json", ("cgemm_bf16.hip", "gemm_common.hpp")),
+    ("bf16x3", "tile", "gemm_line"): ("cgemm_bf16_line_traffic.json", ("cgemm_bf16.hip", "gemm_common.hpp")),
 }
 
 
@@ -242,6 +240,9 @@ def serving(tl, torch, args):
         assert [(r.n_side, r.ns_mode, r.d, r.k) for r in stream] == [(r.n_side, r.ns_mode, r.d, r.k) for r in reqs[:n_sub]]
         out[f"continuous_at_{frac:g}x_capacity"], _ = run(stream, args.max_active, f"continuous at {frac:g}x capacity")
         out[f"continuous_at_{frac:g}x_capacity"]["arrival_rate_per_s"] = rate
+        if frac == min(args.sub_capacity) and args.sub_capacity_alone:
+            out[f"one_at_a_time_at_{frac:g}x_capacity"], _ = run(stream, 1, f"one at a time at {frac:g}x capacity")
+            out[f"one_at_a_time_at_{frac:g}x_capacity"]["arrival_rate_per_s"] = rate
     return out
 
 
@@ -454,6 +455,8 @@ def main():
     ap.add_argument("--requests", type=int, default=128, help="serving: requests in the Poisson stream")
     ap.add_argument("--sub-capacity", type=lambda v: [float(x) for x in v.split(",") if x], default=[0.5, 0.9],
                     help="serving: also serve the stream at these fractions of the measured capacity")
+    ap.add_argument("--no-sub-capacity-alone", dest="sub_capacity_alone", action="store_false",
+                    help="serving: skip the one-at-a-time run at the lowest sub-capacity rate")
     ap.add_argument("--sub-capacity-requests", type=int, default=64,
                     help="serving: requests (the stream's first ones) of the sub-capacity runs")
     ap.add_argument("--max-active", type=int, default=4, help="serving: concurrent solves")

@@ -198,12 +198,13 @@ def serving(tl, torch, args):
             out.append(serve.Job(rid=r.rid, arrival=r.arrival, payload=req))
         return out
 
-    def run(stream, active, label):
+    def run(stream, active, label, budget_gib=None):
         be = serve.GpuBackend(n_streams=max(active, 1))
         jobs = jobs_for(stream)
         torch.cuda.synchronize()
         be.clock = serve.WallClock()
-        srv = serve.Server(be, hbm_budget=int(args.hbm_budget_gib * 2 ** 30), max_active=active)
+        budget_gib = args.hbm_budget_gib if budget_gib is None else budget_gib
+        srv = serve.Server(be, hbm_budget=int(budget_gib * 2 ** 30), max_active=active)
         t0 = time.time()
 
         def progress(job):
@@ -213,7 +214,9 @@ def serving(tl, torch, args):
         srv.run(jobs, on_done=progress)
         torch.cuda.synchronize()
         res = serve.summarize(jobs)
-        res.update(max_active=active, peak_footprint_gib=srv.peak_in_use / 2 ** 30,
+        res.update(max_active=active, hbm_budget_gib=budget_gib, peak_footprint_gib=srv.peak_in_use / 2 ** 30,
+                   footprint_gib_min_max=[min(j.footprint for j in jobs) / 2 ** 30,
+                                          max(j.footprint for j in jobs) / 2 ** 30],
                    admissions_waiting_for_memory=sum(1 for e in srv.log if e[1] == "wait_memory"),
                    offered_rate_per_s=len(stream) / max(stream[-1].arrival - stream[0].arrival, 1e-9))
         log(f"{label}: {res}")
@@ -226,13 +229,36 @@ def serving(tl, torch, args):
            "hbm_budget_gib": args.hbm_budget_gib,
            "sizes": [[r.n_side ** 2, (r.n_side ** 2) // (2 if r.ns_mode == "half" else 1), r.d, r.k] for r in reqs],
            "inputs": "made on the device at admission (counted in the footprint), freed at completion"}
+    parts = set(args.serving_parts)
+    out["parts"] = sorted(parts)
+    if "saturated" not in parts:
+        if "sub" in parts and args.capacity is None:
+            raise SystemExit("--capacity is needed for the sub-capacity runs without the saturated ones")
+        out["capacity_solves_per_s"] = args.capacity
+        return _sub_capacity(out, run, synth, reqs, iters, args, args.capacity) if "sub" in parts else out
     out["one_at_a_time"], res1 = run(reqs, 1, "one at a time")
     out["continuous"], res2 = run(reqs, args.max_active, "continuous")
-    out["bitwise_same_alone_and_in_mix"] = bool(all(
-        torch.equal(res1[k]["theta"], res2[k]["theta"]) and torch.equal(res1[k]["fhist"], res2[k]["fhist"])
-        for k in res2))
+    def same(ra, rb):   # bitwise equal results of every request completed in both runs
+        common = [k for k in rb if ra.get(k) is not None and rb[k] is not None]
+        return bool(common) and all(torch.equal(ra[k]["theta"], rb[k]["theta"]) and
+                                    torch.equal(ra[k]["fhist"], rb[k]["fhist"]) for k in common)
+    out["bitwise_same_alone_and_in_mix"] = same(res1, res2)
     out["speedup_solves_per_s"] = out["continuous"]["solves_per_s"] / out["one_at_a_time"]["solves_per_s"]
-    cap = out["continuous"]["solves_per_s"]
+    if args.tight_budget_gib > 0 and "memory" in parts:
+        # the same stream under a budget that holds the largest request but not two of them together with
+        # others: admission waits on memory
+        out["continuous_memory_bound"], res3 = run(reqs, args.max_active, "continuous, memory-bound budget",
+                                                   args.tight_budget_gib)
+        out["bitwise_same_alone_and_memory_bound"] = same(res1, res3)
+        del res3
+    del res1, res2
+    if "sub" in parts:
+        _sub_capacity(out, run, synth, reqs, iters, args, out["continuous"]["solves_per_s"])
+    return out
+
+
+def _sub_capacity(out, run, synth, reqs, iters, args, cap):
+    """The first requests of the stream at fractions of the measured capacity (same shapes, slower arrivals)."""
     n_sub = args.sub_capacity_requests
     for frac in args.sub_capacity:
         rate = frac * cap
@@ -457,10 +483,18 @@ def main():
                     help="serving: also serve the stream at these fractions of the measured capacity")
     ap.add_argument("--no-sub-capacity-alone", dest="sub_capacity_alone", action="store_false",
                     help="serving: skip the one-at-a-time run at the lowest sub-capacity rate")
-    ap.add_argument("--sub-capacity-requests", type=int, default=64,
+    ap.add_argument("--sub-capacity-requests", type=int, default=32,
                     help="serving: requests (the stream's first ones) of the sub-capacity runs")
+    ap.add_argument("--serving-parts", type=lambda v: [x for x in v.split(",") if x],
+                    default=["saturated", "memory", "sub"],
+                    help="serving: saturated (one at a time and continuous at 200/s), memory (continuous under "
+                         "--tight-budget-gib), sub (the sub-capacity rates)")
+    ap.add_argument("--capacity", type=float, default=None,
+                    help="serving: measured capacity (solves/s) for the sub-capacity runs without the saturated ones")
     ap.add_argument("--max-active", type=int, default=4, help="serving: concurrent solves")
     ap.add_argument("--hbm-budget-gib", type=float, default=96.0, help="serving: admission budget")
+    ap.add_argument("--tight-budget-gib", type=float, default=64.0,
+                    help="serving: also serve the saturated stream under this budget (0: skip)")
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--nfreq", type=int, default=None)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -741,6 +775,12 @@ def measure_workload(tl, torch, args, wl, inputs, steps, warmup, prec, line_prod
         if ms > 0 and b > 0:
             hbm[row] = {"gbps": b / (ms * 1e-3) / 1e9, "frac_hbm": b / (ms * 1e-3) / HBM_PEAK,
                         "ms_per_step": ms / steps}
+            fl = sum(kt.flops[k] for k in kinds)
+            if fl > 0:
+                # tile products on the FP32 matrix cores beside the HBM traffic: the nearer roof binds
+                fm = fl / (ms * 1e-3) / PEAK["f32"]
+                hbm[row].update(tflops=fl / (ms * 1e-3) / 1e12, frac_mfma=fm,
+                                bound="mfma" if fm > hbm[row]["frac_hbm"] else "hbm")
     config = {"workload": wl.name if nfreq == len(wl.freqs) else f"{wl.name}[first {nfreq}]",
               "nr": nr, "ns": ns, "frequencies": nfreq, "iters": iters,
               "resid_refresh": tl.RESID_REFRESH, "streams": nstreams,

@@ -203,6 +203,10 @@ struct HostLayout {
     std::vector<int> koff;          // t order
     std::vector<TileDesc> tiles;    // diagonal tiles first, then sub-diagonal tiles in t order
     int64_t theta_size = 0;
+    // complex flops (8 per complex multiply-add) of the tile products: assembly of X, of X1 and X2
+    // (three products per tile), and the gradient contractions (two per sub-diagonal tile, one per
+    // Q Q^T tile); a Q Q^T product counts its d (d + 1) / 2 distinct entries
+    double asm_cflops = 0.0, asm_dir_cflops = 0.0, grad_cflops = 0.0;
 };
 
 int build_layout(const tlrmdd_layout *L, HostLayout &H) {
@@ -275,6 +279,17 @@ int build_layout(const tlrmdd_layout *L, HostLayout &H) {
             pos += (int64_t)td.k * td.dj;
         }
     H.theta_size = pos;
+    for (const TileDesc &td : H.tiles) {
+        const double di = td.di, dj = td.dj, k = td.k;
+        if (td.kind == TILE_LR) {
+            H.asm_cflops += 8.0 * di * dj * k;
+            H.grad_cflops += 16.0 * di * dj * k;
+        } else if (td.kind == TILE_QQ) {
+            H.asm_cflops += 4.0 * di * (di + 1.0) * k;
+            H.grad_cflops += 8.0 * di * dj * k;
+        }
+    }
+    H.asm_dir_cflops = 3.0 * H.asm_cflops;
     return TLRMDD_OK;
 }
 
@@ -1333,6 +1348,7 @@ struct Run {
     std::vector<int> grad_first;     // first gradient item of every problem, and the total
     int n_adj = 0;                   // problems before the tile-form gradient ranges (adjoint product)
     std::vector<double> theta_pre;   // complex unknowns of problems 0 .. p - 1 (true sizes)
+    std::vector<double> asm_pre, asm_dir_pre, grad_pre;   // tile-product complex flops, likewise
     // a second stream (default priority) on which the tile-form gradient runs beside the adjoint
     // product of the other problems, and the events that fork it from and join it to c.s
     hipStream_t side = nullptr;
@@ -1534,7 +1550,8 @@ int objective_fresh(Run &R, int record, double lam) {
         if ((e = clear_plane_padding(R))) return e;
         const int na = (R.single || R.n_adj == c.nprob) ? c.D.n_asm : R.asm_first[R.n_adj];
         const double nr = (double)c.nr;
-        HIP_TRY(timed(TLRMDD_K_ASSEMBLE, c.s, bytes_work(8.0 * (nr * nr * R.n_adj + R.theta_pre[R.n_adj])), [&] {
+        const Work wk = gemm_work(F_4M, R.asm_pre[R.n_adj], 8.0 * (nr * nr * R.n_adj + R.theta_pre[R.n_adj]));
+        HIP_TRY(timed(TLRMDD_K_ASSEMBLE, c.s, wk, [&] {
             return launch_assemble(false, c.D.tiles, c.D.asm_items, na, c.D.probs, (const float2 *)c.w.th,
                                    nullptr, R.X1, nullptr, c.s, c.bf16, R.x2w, c.lo_words());
         }));
@@ -1576,10 +1593,16 @@ int run_setup(Run &R, int op, int nprob, const tlrmdd_plan *plans, const void *c
     c.s = s;
     std::vector<const HostLayout *> Hs;
     R.theta_pre.assign(1, 0.0);
+    R.asm_pre.assign(1, 0.0);
+    R.asm_dir_pre.assign(1, 0.0);
+    R.grad_pre.assign(1, 0.0);
     for (int p = 0; p < nprob; ++p) {
         append_problem(R.T, plans[p]->H, p, (int64_t)p * 2 * c.ldk * c.ldk, c.ldk);
         Hs.push_back(&plans[p]->H);
         R.theta_pre.push_back(R.theta_pre.back() + (double)plans[p]->H.theta_size);
+        R.asm_pre.push_back(R.asm_pre.back() + plans[p]->H.asm_cflops);
+        R.asm_dir_pre.push_back(R.asm_dir_pre.back() + plans[p]->H.asm_dir_cflops);
+        R.grad_pre.push_back(R.grad_pre.back() + plans[p]->H.grad_cflops);
     }
     build_segments(R.T, Hs, c.lds, c.ldk);
     c.pstride = partial_stride(R.T, c.ldk, c.lds);
@@ -1707,7 +1730,7 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
             if ((st = gemm_adjoint(ca, c.w.r, R.X1, R.xstride))) return st;
             const int ng = (R.single || R.n_adj == c.nprob) ? c.D.n_grad : R.grad_first[R.n_adj];
             const double nr = (double)c.nr;
-            const Work wk = bytes_work(8.0 * (nr * nr * R.n_adj + 2.0 * R.theta_pre[R.n_adj]));
+            const Work wk = gemm_work(F_4M, R.grad_pre[R.n_adj], 8.0 * (nr * nr * R.n_adj + 2.0 * R.theta_pre[R.n_adj]));
             HIP_TRY(timed(TLRMDD_K_GRAD, s, wk, [&] {
                 return launch_grad(c.D.tiles, c.D.grad_items, ng, c.D.probs, R.X1, (const float2 *)c.w.th,
                                    (float2 *)R.gcur, s);
@@ -1748,7 +1771,8 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
             const int a0 = R.single ? 0 : R.asm_first[sg.p0];
             const int na = R.single ? c.D.n_asm : R.asm_first[sg.p0 + sg.np] - a0;
             const double nr = (double)c.nr;
-            const Work wk = bytes_work(16.0 * (nr * nr * sg.np + R.theta_pre[sg.p0 + sg.np] - R.theta_pre[sg.p0]));
+            const Work wk = gemm_work(F_4M, R.asm_dir_pre[sg.p0 + sg.np] - R.asm_dir_pre[sg.p0],
+                                      16.0 * (nr * nr * sg.np + R.theta_pre[sg.p0 + sg.np] - R.theta_pre[sg.p0]));
             HIP_TRY(timed(TLRMDD_K_ASSEMBLE_DIR, s, wk, [&] {
                 return launch_assemble(true, c.D.tiles, c.D.asm_items + a0, na, c.D.probs,
                                        (const float2 *)c.w.th, (const float2 *)c.w.p, R.X1, R.X2, s, c.bf16, R.x2w,
@@ -1909,7 +1933,7 @@ int tlrmdd_forward(tlrmdd_plan plan, const void *D, const void *U, const void *t
     if (c.ldk != c.nr) HIP_TRY(launch_fill_zero(c.w.XW, (size_t)c.ldk * c.ldk * sizeof(float2), stream));
     if ((st = stage(c, 0, (const float2 *)D, false))) return st;
     const double nr2 = (double)c.nr * (double)c.nr, thn = (double)plan->H.theta_size;
-    HIP_TRY(timed(TLRMDD_K_ASSEMBLE, stream, bytes_work(8.0 * (nr2 + thn)), [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
+    HIP_TRY(timed(TLRMDD_K_ASSEMBLE, stream, gemm_work(F_4M, plan->H.asm_cflops, 8.0 * (nr2 + thn)), [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
                             c.w.XW, nullptr, stream, c.bf16, 0, c.lo_words()); }));
     if ((st = gemm_resid(c, c.w.XW, 0, (const float2 *)U, c.nr, 0, c.w.r))) return st;
     FinArgs f = fin_args(FIN_F_OUT, c.w.sc);
@@ -1949,7 +1973,7 @@ int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *thet
     if (c.ldk != c.nr) HIP_TRY(launch_fill_zero(c.w.XW, (size_t)c.ldk * c.ldk * sizeof(float2), stream));
     if ((st = stage(c, 0, (const float2 *)D, true))) return st;
     const double nr2 = (double)c.nr * (double)c.nr, thn = (double)plan->H.theta_size;
-    HIP_TRY(timed(TLRMDD_K_ASSEMBLE, stream, bytes_work(8.0 * (nr2 + thn)), [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
+    HIP_TRY(timed(TLRMDD_K_ASSEMBLE, stream, gemm_work(F_4M, plan->H.asm_cflops, 8.0 * (nr2 + thn)), [&] { return launch_assemble(false, c.D.tiles, c.D.asm_items, c.D.n_asm, c.D.probs, (const float2 *)theta, nullptr,
                             c.w.XW, nullptr, stream, c.bf16, 0, c.lo_words()); }));
     if ((st = gemm_resid(c, c.w.XW, 0, (const float2 *)U, c.nr, 0, c.w.r))) return st;
     if ((st = split_r_transpose(c))) return st;
@@ -1960,7 +1984,7 @@ int tlrmdd_grad(tlrmdd_plan plan, const void *D, const void *U, const void *thet
     }
     // the assembled X is dead once r exists: W = D^H r reuses its storage
     if ((st = gemm_adjoint(c, c.w.r, c.w.XW, 0))) return st;
-    HIP_TRY(timed(TLRMDD_K_GRAD, stream, bytes_work(8.0 * (nr2 + 2.0 * thn)), [&] { return launch_grad(c.D.tiles, c.D.grad_items, c.D.n_grad, c.D.probs, c.w.XW, (const float2 *)theta,
+    HIP_TRY(timed(TLRMDD_K_GRAD, stream, gemm_work(F_4M, plan->H.grad_cflops, 8.0 * (nr2 + 2.0 * thn)), [&] { return launch_grad(c.D.tiles, c.D.grad_items, c.D.n_grad, c.D.probs, c.w.XW, (const float2 *)theta,
                         (float2 *)grad_out, stream); }));
     return TLRMDD_OK;
 }

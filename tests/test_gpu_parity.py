@@ -39,6 +39,13 @@ def _cases():
         # ranks above one 64-entry gradient item and one 32-entry assembly stage; ragged 32-wide last tile
         ("high_rank", lambda: from_geometry(18, 16, "half", 27.0, synth.uniform_layout(288, 128, 70, 50),
                                             4, "high_rank")),
+        # single-block tile pairs with 33-64 rank entries (two rank phases of the tile-pair gradient;
+        # the second half-filled) and Q Q^T tiles past 32 rank entries
+        ("two_phase", lambda: from_geometry(16, 12, "full", 31.0, synth.uniform_layout(192, 64, 45, 40),
+                                            5, "two_phase")),
+        # tiles of 100: every pair spans 2 x 2 blocks, the second 36 wide
+        ("partial_blocks", lambda: from_geometry(20, 15, "full", 13.0, synth.uniform_layout(300, 100, 20, 30),
+                                                 6, "partial_blocks", scale_theta=2.0)),
     ]
 
 

@@ -623,8 +623,9 @@ def device_inputs(wl, torch, tl, nfreq):
 
 
 def small_latency(tl, torch, prec, args):
-    """The nr 64 parity workload (8 frequencies, 50 iterations) as one batched solve: wall time per
-    iteration (launch-latency bound: about 20 launches per iteration)."""
+    """The nr 64 parity workload (8 frequencies, 50 iterations) as one batched solve and one frequency
+    alone: wall time per iteration (launch-latency bound: about 20 launches per iteration), called
+    through the library and replayed as recorded HIP graphs."""
     import synth
     wl = synth.small()
     geom, Ds, Us, ths, plans = build_inputs(wl, torch, tl, len(wl.freqs))
@@ -636,6 +637,34 @@ def small_latency(tl, torch, prec, args):
     for label, fn in (
             ("batched_8freq", lambda: tl.solve_batched(plans, Dh, Uh, ths, wl.iters, precision=prec)),
             ("single_freq", lambda: tl.solve(plans[0], Dh[0], Uh[0], ths[0], wl.iters, precision=prec))):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(10):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        med = ts[len(ts) // 2]
+        out[label] = {"us_per_iteration": med / wl.iters * 1e6, "ms_per_solve": med * 1e3}
+    # the same solves recorded once as HIP graphs and replayed (theta restored before each replay;
+    # the restoring copies are inside the timed region)
+    dev_fh = [torch.empty(wl.iters + 1, dtype=torch.float64, device=dev) for _ in ths]
+    thb = [t.clone() for t in ths]
+    gb = tl.solve_batched_graph(plans, Dh, Uh, thb, dev_fh, wl.iters, precision=prec)
+    th1 = ths[0].clone()
+    g1 = tl.solve_graph(plans[0], Dh[0], Uh[0], th1, dev_fh[0], wl.iters, precision=prec)
+
+    def replay_b():
+        for t, t0 in zip(thb, ths):
+            t.copy_(t0)
+        gb.launch()
+
+    def replay_1():
+        th1.copy_(ths[0])
+        g1.launch()
+    for label, fn in (("graph_batched_8freq", replay_b), ("graph_single_freq", replay_1)):
         fn()
         torch.cuda.synchronize()
         ts = []

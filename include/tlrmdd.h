@@ -405,6 +405,34 @@ typedef struct {
 int tlrmdd_timing_begin(void);
 int tlrmdd_timing_end(tlrmdd_kernel_stats *stats);
 
+/* ---- HIP graphs of library calls ------------------------------------------
+ * A fixed-count solve of one frequency (Theory section, eq. standard_solver: every
+ * frequency is its own problem) is a fixed sequence of launches; at small sizes its
+ * time is the launch latency. The calls made on `stream` between tlrmdd_graph_begin
+ * and tlrmdd_graph_end are recorded into a HIP graph instead of being run, and
+ * tlrmdd_graph_launch replays the whole sequence as one submission.
+ *   - `stream` must be a created stream, not the null stream. Capture is per thread
+ *     (relaxed mode); one capture may be open per thread.
+ *   - Every pointer a recorded call received (data, theta, f-history, workspace) is
+ *     baked into the graph: the caller keeps those buffers alive and unmoved until
+ *     tlrmdd_graph_destroy, and changes their contents between launches as needed
+ *     (a solve updates theta in place, so a fresh solve per launch means restoring
+ *     theta first). Host tables that a recorded call would upload (batched tables,
+ *     tile-form tables) are copied into pinned host memory owned by the graph.
+ *   - Calls whose results are host values (tlrmdd_tile_ranks, tlrmdd_choose_layout,
+ *     tlrmdd_warm_start) synchronise and cannot be recorded: they fail, and so does
+ *     the capture (tlrmdd_graph_end returns TLRMDD_HIP_ERROR and no graph).
+ *   - Kernel timing (tlrmdd_timing_*) does not see recorded calls.
+ * tlrmdd_graph_end always closes the capture opened on `stream`, also when a
+ * recorded call failed. Statuses: TLRMDD_INVALID_ARGUMENT for a null stream, a second
+ * begin on one thread, or an end without a begin on that stream; TLRMDD_HIP_ERROR
+ * when HIP refuses the capture or the instantiation. */
+typedef struct tlrmdd_graph_s *tlrmdd_graph;
+int tlrmdd_graph_begin(hipStream_t stream);
+int tlrmdd_graph_end(hipStream_t stream, tlrmdd_graph *graph_out);
+int tlrmdd_graph_launch(tlrmdd_graph graph, hipStream_t stream);
+int tlrmdd_graph_destroy(tlrmdd_graph graph);
+
 #ifdef __cplusplus
 }
 #endif

@@ -382,6 +382,77 @@ def warm_start(plan, X):
     return theta
 
 
+class Graph:
+    """Library calls recorded into a HIP graph (tlrmdd_graph_*): launch() replays them on the current
+    stream. The tensors the recorded calls use are held here, so their memory stays put."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep
+
+    def launch(self):
+        _lib.check(_lib.load().tlrmdd_graph_launch(self._h, _stream()), "tlrmdd_graph_launch")
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().tlrmdd_graph_destroy(self._h)
+            self._h = None
+
+
+def _record(call, keep):
+    """Run `call` (library calls only, on the current stream) under a graph capture on a stream of
+    its own, after the current stream's pending work; returns the Graph."""
+    lib = _lib.load()
+    cur = torch.cuda.current_stream()
+    side = torch.cuda.Stream()   # default priority; the null stream cannot be captured
+    side.wait_stream(cur)
+    h = ctypes.c_void_p()
+    with torch.cuda.stream(side):
+        s = _stream()
+        _lib.check(lib.tlrmdd_graph_begin(s), "tlrmdd_graph_begin")
+        try:
+            call()
+        finally:
+            st = lib.tlrmdd_graph_end(s, ctypes.byref(h))
+    _lib.check(st, "tlrmdd_graph_end")
+    cur.wait_stream(side)
+    return Graph(h, keep + [side])
+
+
+def solve_graph(plan, D, U, theta, fhist, iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0,
+                resid_refresh=RESID_REFRESH, workspace=None, line_products=LINE_DENSE):
+    """tlrmdd_solve recorded as a HIP graph: each launch() runs `iters` iterations from the current
+    contents of `theta` (updated in place) and writes `fhist`; restore theta for a fresh solve."""
+    _check_problem(plan, D, U, theta)
+    opts = make_opts(iters, optimizer, lbfgs_m, precision, lam, resid_refresh, line_products=line_products)
+    ws = workspace if workspace is not None else plan.workspace(_lib.OP_SOLVE, opts, device=D.device)
+
+    def call():
+        _lib.check(_lib.load().tlrmdd_solve(plan.handle, _ptr(D), _ptr(U), _ptr(theta), ctypes.byref(opts),
+                                            _ptr(fhist), _ptr(ws), ws.numel(), _stream()), "tlrmdd_solve")
+    return _record(call, [plan, D, U, theta, fhist, ws, opts])
+
+
+def solve_batched_graph(plans, Ds, Us, thetas, fhists, iters, optimizer=LBFGS, lbfgs_m=5, precision=FP32, lam=0.0,
+                        resid_refresh=RESID_REFRESH, workspace=None, streams=1, line_products=LINE_DENSE):
+    """tlrmdd_solve_batched recorded as a HIP graph (thetas updated in place at every launch)."""
+    n = len(plans)
+    for p, D, U, th in zip(plans, Ds, Us, thetas):
+        _check_problem(p, D, U, th)
+    opts = make_opts(iters, optimizer, lbfgs_m, precision, lam, resid_refresh, streams, line_products)
+    ws = workspace if workspace is not None else torch.empty(batched_workspace_bytes(plans, opts),
+                                                             dtype=torch.uint8, device=Ds[0].device)
+    V = ctypes.c_void_p * n
+    args = (V(*[p.handle.value for p in plans]), V(*[d.data_ptr() for d in Ds]), V(*[u.data_ptr() for u in Us]),
+            V(*[t.data_ptr() for t in thetas]), V(*[f.data_ptr() for f in fhists]))
+
+    def call():
+        _lib.check(_lib.load().tlrmdd_solve_batched(n, args[0], args[1], args[2], args[3], ctypes.byref(opts),
+                                                    args[4], _ptr(ws), ws.numel(), _stream()),
+                   "tlrmdd_solve_batched")
+    return _record(call, [list(plans), list(Ds), list(Us), list(thetas), list(fhists), ws, opts, args])
+
+
 class KernelTimer:
     """Context manager: per kernel kind the summed launch milliseconds (HIP events on the launch
     stream), launch count and the algorithmic work the library counted for those launches."""

@@ -103,6 +103,10 @@ _SIGS = {
     "tlrmdd_forward_tlr": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_size_t, ctypes.c_void_p]),
     "tlrmdd_timing_begin": (ctypes.c_int, []),
     "tlrmdd_timing_end": (ctypes.c_int, [ctypes.c_void_p]),
+    "tlrmdd_graph_begin": (ctypes.c_int, [ctypes.c_void_p]),
+    "tlrmdd_graph_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "tlrmdd_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "tlrmdd_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 (K_GEMM_RESID, K_GEMM_ADJOINT, K_GEMM_LINE, K_ASSEMBLE, K_ASSEMBLE_DIR, K_GRAD, K_LINE_PACK, K_LINE_TILE,
  K_GRAD_TILE, K_RESID_TILE, K_STAGE, K_PERMUTE, K_GRAM, K_COMBINE, K_THETA_UPDATE, K_RESID_UPDATE,

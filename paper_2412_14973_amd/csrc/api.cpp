@@ -98,9 +98,18 @@ hipEvent_t rec_event() {
     return e;
 }
 
+// An open graph capture on this thread (tlrmdd_graph_begin .. tlrmdd_graph_end): launches are
+// recorded, not timed, and host tables go to pinned buffers that the graph will own.
+struct Capture {
+    bool on = false;
+    hipStream_t stream = nullptr;
+    std::vector<char *> pinned;
+};
+thread_local Capture g_cap;
+
 template <class F>
 hipError_t timed(int kind, hipStream_t s, const Work &work, F &&launch) {
-    if (!g_rec.on) return launch();
+    if (!g_rec.on || g_cap.on) return launch();
     std::lock_guard<std::mutex> lk(g_rec.mu);
     hipEvent_t a = rec_event(), b = rec_event();
     if (a) (void)hipEventRecord(a, s);
@@ -153,6 +162,16 @@ class Upload {
 
 int Upload::commit(hipStream_t s) {
     if (img_.empty()) return TLRMDD_OK;
+    if (g_cap.on) {
+        // recorded copies read their source at every replay: a buffer of the graph's own
+        char *host = nullptr;
+        HIP_TRY(hipHostMalloc((void **)&host, img_.size(), hipHostMallocDefault));
+        g_cap.pinned.push_back(host);
+        std::memcpy(host, img_.data(), img_.size());
+        for (const Piece &p : pieces_)
+            if (p.bytes) HIP_TRY(hipMemcpyAsync(p.dst, host + p.off, p.bytes, hipMemcpyHostToDevice, s));
+        return TLRMDD_OK;
+    }
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_pinned.mu);
@@ -1198,6 +1217,8 @@ int fin(const Ctx &c, FinArgs f, const int32_t *counts, int ucount, int nsum) {
     return TLRMDD_OK;
 }
 
+// The dense products contract over the true length rounded up to the kernel's k step (16 complex,
+// 32 for the BF16 ring), not over the padded one: the padding is zero and would only add stages.
 int gemm_resid(const Ctx &c, const float2 *X, int64_t sX, const float2 *U, int64_t ldu, int64_t sU, float2 *r) {
     const double np = c.nprob, ns = (double)c.ns, nr = (double)c.nr;
     const Work wk = gemm_work(c.form(), 8.0 * ns * nr * nr * np, 8.0 * np * (3.0 * ns * nr + nr * nr));
@@ -1215,7 +1236,7 @@ int gemm_resid(const Ctx &c, const float2 *X, int64_t sX, const float2 *U, int64
         g.C = r; g.ldc = c.ldk; g.sC = c.lds * c.ldk;
         g.E = U; g.lde = ldu; g.sE = sU;
         g.partials = c.w.partials; g.sP = (int64_t)c.pstride;
-        g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
+        g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)round_up(c.nr, 32);
         g.Me = (int)c.ns; g.Ne = (int)c.nr;
         HIP_TRY(timed(TLRMDD_K_GEMM_RESID, c.s, wk, [&] { return launch_cgemm_bf16(GM_RESID, g, c.nprob, c.s); }));
         return TLRMDD_OK;
@@ -1226,7 +1247,7 @@ int gemm_resid(const Ctx &c, const float2 *X, int64_t sX, const float2 *U, int64
     g.C = r; g.ldc = c.ldk; g.sC = c.lds * c.ldk;
     g.E = U; g.lde = ldu; g.sE = sU;
     g.partials = c.w.partials; g.sP = (int64_t)c.pstride;   // one sum per workgroup
-    g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
+    g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)round_up(c.nr, GEMM_BK);
     g.Me = (int)c.ns; g.Ne = (int)c.nr;
     HIP_TRY(timed(TLRMDD_K_GEMM_RESID, c.s, wk, [&] {
         return c.p3m ? launch_cgemm3m(GM_RESID, g, c.nprob, c.s) : launch_cgemm(GM_RESID, g, c.nprob, c.s);
@@ -1248,7 +1269,7 @@ int gemm_adjoint(const Ctx &c, const float2 *r, float2 *W, int64_t sW) {
         g.Blo = reinterpret_cast<const uint16_t *>(c.w.rT + c.ldk * c.lds);
         g.ldb = c.lds; g.sB = 2 * c.ldk * c.lds;
         g.C = W; g.ldc = c.ldk; g.sC = sW;
-        g.M = (int)c.ldk; g.N = (int)c.ldk; g.K = (int)c.lds;
+        g.M = (int)c.ldk; g.N = (int)c.ldk; g.K = (int)round_up(c.ns, 32);
         HIP_TRY(timed(TLRMDD_K_GEMM_ADJOINT, c.s, wk, [&] { return launch_cgemm_bf16(GM_STORE, g, c.nprob, c.s); }));
         return TLRMDD_OK;
     }
@@ -1256,7 +1277,7 @@ int gemm_adjoint(const Ctx &c, const float2 *r, float2 *W, int64_t sW) {
     g.A = c.w.DHs; g.lda = c.lds; g.sA = c.ldk * c.lds;
     g.B = r; g.ldb = c.ldk; g.sB = c.lds * c.ldk;
     g.C = W; g.ldc = c.ldk; g.sC = sW;
-    g.M = (int)c.ldk; g.N = (int)c.ldk; g.K = (int)c.lds;
+    g.M = (int)c.ldk; g.N = (int)c.ldk; g.K = (int)round_up(c.ns, GEMM_BK);
     HIP_TRY(timed(TLRMDD_K_GEMM_ADJOINT, c.s, wk, [&] {
         return c.p3m ? launch_cgemm3m(GM_STORE, g, c.nprob, c.s) : launch_cgemm(GM_STORE, g, c.nprob, c.s);
     }));
@@ -1279,7 +1300,7 @@ int gemm_line(const Ctx &c, const float2 *X1, const float2 *X2, int64_t sX) {
         g.C = c.w.a; g.C2 = c.w.b; g.ldc = c.ldk; g.sC = c.lds * c.ldk;
         g.E = c.w.r; g.lde = c.ldk; g.sE = c.lds * c.ldk;
         g.partials = c.w.partials; g.sP = (int64_t)c.pstride * 5;
-        g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
+        g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)round_up(c.nr, 32);
         HIP_TRY(timed(TLRMDD_K_GEMM_LINE, c.s, wk, [&] { return launch_cgemm_bf16(GM_LINE, g, c.nprob, c.s); }));
         return TLRMDD_OK;
     }
@@ -1289,7 +1310,7 @@ int gemm_line(const Ctx &c, const float2 *X1, const float2 *X2, int64_t sX) {
     g.C = c.w.a; g.C2 = c.w.b; g.ldc = c.ldk; g.sC = c.lds * c.ldk;
     g.E = c.w.r; g.lde = c.ldk; g.sE = c.lds * c.ldk;
     g.partials = c.w.partials; g.sP = (int64_t)c.pstride * 5;
-    g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)c.ldk;
+    g.M = (int)c.lds; g.N = (int)c.ldk; g.K = (int)round_up(c.nr, GEMM_BK);
     HIP_TRY(timed(TLRMDD_K_GEMM_LINE, c.s, wk, [&] {
         return c.p3m ? launch_cgemm3m(GM_LINE, g, c.nprob, c.s) : launch_cgemm(GM_LINE, g, c.nprob, c.s);
     }));
@@ -2200,6 +2221,64 @@ int tlrmdd_timing_end(tlrmdd_kernel_stats *stats) {
     if (stats)
         for (int k = 0; k < TLRMDD_K_NKINDS; ++k) stats[k] = acc[k];
     return status;
+}
+
+// ---- HIP graphs of library calls ----
+struct tlrmdd_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<char *> pinned;   // host images read by the graph's copy nodes
+};
+
+static void graph_free(tlrmdd_graph g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    for (char *h : g->pinned) (void)hipHostFree(h);
+    delete g;
+}
+
+int tlrmdd_graph_begin(hipStream_t stream) {
+    g_last_error.clear();
+    if (!stream) return fail(TLRMDD_INVALID_ARGUMENT, "graph capture needs a created stream (not the null stream)");
+    if (g_cap.on) return fail(TLRMDD_INVALID_ARGUMENT, "a graph capture is already open on this thread");
+    HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
+    g_cap.on = true;
+    g_cap.stream = stream;
+    g_cap.pinned.clear();
+    return TLRMDD_OK;
+}
+
+int tlrmdd_graph_end(hipStream_t stream, tlrmdd_graph *graph_out) {
+    g_last_error.clear();
+    if (!graph_out) return fail(TLRMDD_INVALID_ARGUMENT, "graph_out is NULL");
+    *graph_out = nullptr;
+    if (!g_cap.on || g_cap.stream != stream)
+        return fail(TLRMDD_INVALID_ARGUMENT, "no graph capture open on this stream in this thread");
+    g_cap.on = false;
+    tlrmdd_graph g = new tlrmdd_graph_s;
+    g->pinned.swap(g_cap.pinned);
+    hipError_t e = hipStreamEndCapture(stream, &g->graph);
+    if (e == hipSuccess && !g->graph) e = hipErrorStreamCaptureInvalidated;
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        graph_free(g);
+        return fail(TLRMDD_HIP_ERROR, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    *graph_out = g;
+    return TLRMDD_OK;
+}
+
+int tlrmdd_graph_launch(tlrmdd_graph graph, hipStream_t stream) {
+    g_last_error.clear();
+    if (!graph) return fail(TLRMDD_INVALID_ARGUMENT, "graph is NULL");
+    HIP_TRY(hipGraphLaunch(graph->exec, stream));
+    return TLRMDD_OK;
+}
+
+int tlrmdd_graph_destroy(tlrmdd_graph graph) {
+    g_last_error.clear();
+    if (graph) graph_free(graph);
+    return TLRMDD_OK;
 }
 
 }  // extern "C"

@@ -463,19 +463,8 @@ __global__ __launch_bounds__(256) void resid_update_kernel(const VecSeg *__restr
 // ---------------------------------------------------------------------------
 // per-problem finalisation (one block per problem)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void finalize_kernel(FinArgs fa) {
-    __shared__ double red[4];
-    __shared__ double tot[6 * (MAX_LBFGS_M + 1)];
-    const int prob = blockIdx.x;
-    const int count = fa.counts ? fa.counts[prob] : fa.ucount;
-    const double *base = fa.partials + (int64_t)prob * fa.pstride * fa.nsum;
-    for (int k = 0; k < fa.nsum; ++k) {
-        double v = 0.0;
-        for (int i = threadIdx.x; i < count; i += 256) v += base[(int64_t)i * fa.nsum + k];
-        v = block_sum(v, red);
-        if (threadIdx.x == 0) tot[k] = v;
-    }
-    if (threadIdx.x != 0) return;
+// the scalar work of one problem (thread 0); G: the staged Gram matrix and coefficients (FIN_GRAM)
+__device__ __forceinline__ void finalize_scalars(const FinArgs &fa, int prob, const double *tot, double *Gs) {
     SolveScalars &s = fa.sc[prob];
     const int m1 = fa.m1;
     switch (fa.op) {
@@ -507,7 +496,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs fa) {
             break;
         case FIN_GRAM: {  // Gram entries of the newest pair and of g; direction coefficients
             const int nb = 2 * m1 + 1, ig = 2 * m1;
-            double *G = fa.gram + (int64_t)prob * fa.gstride;   // nb x nb, then nb coefficients
+            double *G = Gs;   // nb x nb, then nb coefficients
             double *cf = G + nb * nb;
             const int h = s.head;
             const double *th = tot + 6 * h;
@@ -599,6 +588,38 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs fa) {
         default: break;
     }
 }
+
+// The scalar work runs on one thread and is a chain of dependent steps, so everything it touches sits
+// in LDS first: the partial sums are reduced by the four waves at once (wave w takes sums w, w + 4,
+// ...: lanes stride over the slots, then one DPP wave reduction, a fixed order), and the Gram pass
+// stages the problem's Gram matrix and coefficient vector, which are written back afterwards.
+constexpr int FIN_NB = 2 * (MAX_LBFGS_M + 1) + 1;
+__global__ __launch_bounds__(256) void finalize_kernel(FinArgs fa) {
+    __shared__ double tot[6 * (MAX_LBFGS_M + 1)];
+    __shared__ double sG[FIN_NB * FIN_NB + FIN_NB];
+    const int prob = blockIdx.x;
+    const int count = fa.counts ? fa.counts[prob] : fa.ucount;
+    const double *base = fa.partials + (int64_t)prob * fa.pstride * fa.nsum;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = wv; k < fa.nsum; k += 4) {
+        double v = 0.0;
+        for (int i = lane; i < count; i += 64) v += base[(int64_t)i * fa.nsum + k];
+        v = wave_sum64(v);
+        if (lane == 0) tot[k] = v;
+    }
+    const int m1 = fa.m1;
+    const int gwords = (2 * m1 + 1) * (2 * m1 + 1) + 2 * m1 + 1;
+    double *Gg = fa.op == FIN_GRAM ? fa.gram + (int64_t)prob * fa.gstride : nullptr;
+    if (Gg)
+        for (int i = threadIdx.x; i < gwords; i += 256) sG[i] = Gg[i];
+    __syncthreads();
+    if (threadIdx.x == 0) finalize_scalars(fa, prob, tot, sG);
+    if (Gg) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < gwords; i += 256) Gg[i] = sG[i];
+    }
+}
+
 
 }  // namespace
 

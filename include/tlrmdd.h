@@ -114,7 +114,7 @@ typedef struct {
                                stages once per (tile size, padded rank) class;
                                TLRMDD_LINE_TILE_GRAD (2): as 1, and the gradient in tile form too
                                where its three products (3 Wg / nr of the adjoint product D^H r,
-                               Wg = nt kpad rounded up to 128) cost at most 0.6 of the adjoint
+                               Wg = nt kpad rounded up to 64) cost at most 0.6 of the adjoint
                                (0.3 in BF16X3 mode):
                                W_ij B_ij^H = D_:,i^H (r_:,j B_ij^H), A_ij^H W_ij = (D_:,i A_ij)^H r_:,j
                                with X_ij = A_ij B_ij (gradient equations); the adjoint product then

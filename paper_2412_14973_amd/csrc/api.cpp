@@ -572,7 +572,7 @@ struct LineClass {
 // Gradient in tile form (TLRMDD_LINE_TILE_GRAD). With W = D^H r and every tile pair a factor product
 // X_ij = A_ij B_ij, the gradient blocks are W_ij B_ij^H = D_:,i^H (r_:,j B_ij^H) and
 // A_ij^H W_ij = (D_:,i A_ij)^H r_:,j (gradient equations; the sum over both orders of a tile pair
-// forms W' = W + W^T). Three batched products of width Wg = nt kpad rounded up to 128:
+// forms W' = W + W^T). Three batched products of width Wg = nt kpad rounded up to 64:
 //   G1: S_j = r_:,j [B_0j^H | B_1j^H | ...], stored regrouped by tile row (Scol_i = [S_i0 | S_i1 | ...]);
 //   G2: GA_i = D_:,i^H Scol_i;   G3: GBT_j = r_:,j^T conj(P_th(:,j)), with P_th(ij) = D_:,i A_ij the theta
 //   half of the line search's stage 1 (carried to the updated theta by P_th += step P_p);
@@ -584,7 +584,8 @@ struct LineClass {
 constexpr double GRAD_TILE_MAX_COST = 0.6;
 constexpr int GRAD_TILE_KS = 4;
 static_assert(GEMM_PAD % (GRAD_TILE_KS * GEMM_BK) == 0, "every part of the padded ns is a whole number of k stages");
-int64_t grad_tile_width(const LineClass &lc) { return round_up((int64_t)lc.nt * lc.kpad, GEMM_BN); }
+// (the product kernel's tile stages take a last column tile of 64)
+int64_t grad_tile_width(const LineClass &lc) { return round_up((int64_t)lc.nt * lc.kpad, GEMM_BN / 2); }
 
 // Tile form is possible when all tiles have one size d (a multiple of 128), nr needs no padding and the
 // diagonal tiles are Q Q^T; problem_form decides whether the padded rank keeps the flops low enough.

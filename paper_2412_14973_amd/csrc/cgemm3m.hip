@@ -47,7 +47,8 @@ constexpr int STAGE = 2 * A_PLANE + 2 * B_PLANE;   // floats: re and im planes o
 // gradient (the same code; separate instantiations so that profiles tell them apart), 2 = a tile-form
 // gradient stage whose A is given transposed (a K x M source with row pitch lda, read along M like a
 // B tile) and whose B enters conjugated
-template <int MODE, int ROLE>
+// HALF (GM_STORE tile stages): the launch covers one column tile of 64 columns at g.n_half
+template <int MODE, int ROLE, bool HALF = false>
 __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
     __shared__ float sm[2][STAGE];
 
@@ -82,7 +83,11 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
     const int tm = first_m + (pid % per_group) % gsz;
     const int tn = (pid % per_group) / gsz;
     const int m0 = tm * BM;
-    const int n0 = (MODE == GM_LINE) ? tn * (BN / 2) : tn * BN;
+    // a 64-column tile: its four waves each take 32 rows of all 64 columns, and the other 64
+    // columns are not loaded
+    static_assert(!HALF || (MODE == GM_STORE && ROLE != 0), "64-column tiles: tile-stage GM_STORE only");
+    constexpr bool halfn = HALF;
+    const int n0 = HALF ? g.n_half : (MODE == GM_LINE) ? tn * (BN / 2) : tn * BN;
 
     const int t = threadIdx.x;
     const int lane = t & 63;
@@ -190,6 +195,11 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
         boff[0] = wn * 64 + j32;
         boff[1] = wn * 64 + 32 + j32;
     }
+    if (halfn) {   // rows wm*64 + wn*32 (one row block), columns 0 .. 63 (two column blocks)
+        aoff[0] = aoff[1] = wm * 64 + wn * 32 + j32;
+        boff[0] = j32;
+        boff[1] = 32 + j32;
+    }
     floatx16 acc[3][2][2];   // [T1, T2, T3][row block][column block]
 #pragma unroll
     for (int p = 0; p < 3; ++p)
@@ -205,14 +215,14 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
     constexpr bool SPLIT_K2 = MODE == GM_LINE && ROLE == 1;
     const int nk = g.K / BK;
     const int nk2 = (SPLIT_K2 && g.K2 > 0) ? g.K2 / BK : nk;
-    load(0, 0 < nk2);
-    store_lds(0, 0 < nk2);
+    load(0, 0 < nk2 && !halfn);
+    store_lds(0, 0 < nk2 && !halfn);
     __syncthreads();
     auto stage = [&](int kt, auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
         constexpr int NJ = FULL ? 2 : 1;   // column blocks with products in this stage
         const int buf = kt & 1;
-        if (kt + 1 < nk) load((kt + 1) * BK, kt + 1 < nk2);
+        if (kt + 1 < nk) load((kt + 1) * BK, kt + 1 < nk2 && !halfn);
         const float *ar = sm[buf], *ai = ar + A_PLANE;
         const float *br = ai + A_PLANE, *bi = br + B_PLANE;
         // operand fragments [A|B][re, im, re + im][block], double-buffered in registers: the
@@ -242,10 +252,12 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
 #pragma unroll
             for (int p = 0; p < 3; ++p)
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < 2; ++i) {
+                    if (i == 1 && halfn) continue;
 #pragma unroll
                     for (int j = 0; j < NJ; ++j)
                         acc[p][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[0][p][i], cur[1][p][j], acc[p][i][j], 0, 0, 0);
+                }
             if (kc + 2 < BK) {
                 sums(nxt);
 #pragma unroll
@@ -256,7 +268,7 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
                         for (int i = 0; i < 2; ++i) cur[o][p][i] = nxt[o][p][i];
             }
         }
-        if (kt + 1 < nk) store_lds(buf ^ 1, kt + 1 < nk2);
+        if (kt + 1 < nk) store_lds(buf ^ 1, kt + 1 < nk2 && !halfn);
         __syncthreads();
     };
     int kt = 0;
@@ -277,7 +289,8 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const int col = n0 + wn * 64 + 32 * j + j32;
+                if (i == 1 && halfn) continue;
+                const int col = n0 + (halfn ? 0 : wn * 64) + 32 * j + j32;
                 int64_t ccol = col;
                 if (ROLE != 0 && g.scat_kp > 0) {
                     if (col >= g.scat_lim) continue;
@@ -285,7 +298,7 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
                 }
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int row = m0 + wm * 64 + 32 * i + acc_row(r, lane);
+                    const int row = m0 + wm * 64 + (halfn ? wn * 32 : 32 * i) + acc_row(r, lane);
                     C[(int64_t)row * ldc + ccol] = cval(i, j, r);
                 }
             }
@@ -358,9 +371,14 @@ hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s
         return hipErrorInvalidValue;
     GemmArgs a = a0;
     a.tiles_m = a.M / BM;
+    // GM_STORE tile stages take N a multiple of 64: the whole 128-column tiles in one launch, a last
+    // column tile of 64 in a second one; all else whole tiles
+    const bool half_ok = mode == GM_STORE && tile_stage;
     a.tiles_n = (mode == GM_LINE) ? a.N / (BN / 2) : a.N / BN;
     if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
-    if (a.M % BM || a.N % BN || a.K % BK || a.K <= 0) return hipErrorInvalidValue;
+    if (a.M % BM || a.N % (half_ok ? BN / 2 : BN) || a.K % BK || a.K <= 0) return hipErrorInvalidValue;
+    const bool half_tile = half_ok && a.N % BN != 0;
+    a.n_half = a.tiles_n * BN;
     if (a.K2 < 0 || a.K2 > a.K || a.K2 % BK || (a.K2 && !(mode == GM_LINE && tile_stage)))
         return hipErrorInvalidValue;
     if (a.nz3 > 1 || a.nz4 > 1) {
@@ -385,6 +403,15 @@ hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s
     a.bytesA = (uint32_t)bytesA;
     a.bytesB = (uint32_t)bytesB;
     dim3 grid(a.tiles_m * a.tiles_n, batch);
+    if (half_tile) {
+        GemmArgs h = a;
+        h.tiles_n = 1;
+        const dim3 hgrid(a.tiles_m, batch);
+        if (role == GR_TILE_TA_CB) hipLaunchKernelGGL((cgemm3m_kernel<GM_STORE, 2, true>), hgrid, dim3(256), 0, s, h);
+        else hipLaunchKernelGGL((cgemm3m_kernel<GM_STORE, 1, true>), hgrid, dim3(256), 0, s, h);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess || a.tiles_n == 0) return e;
+    }
     switch (mode) {
         case GM_STORE:
             if (role == GR_TILE_TA_CB) hipLaunchKernelGGL((cgemm3m_kernel<GM_STORE, 2>), grid, dim3(256), 0, s, a);

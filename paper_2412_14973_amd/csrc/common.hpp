@@ -92,6 +92,7 @@ struct GemmArgs {
     // plain), which regroups blocks of scat_kp columns across batch entries
     int32_t scat_kp, scat_w, scat_lim;
     int64_t scat_js;
+    int32_t n_half;                  // GM_STORE tile stages: first column of a last 64-column tile (set by the launcher)
 };
 // roles of the three-product kernel: the solver's dense products; the tile-form stages; the same
 // with A given transposed (K x M source, row pitch lda) and B conjugated

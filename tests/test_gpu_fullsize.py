@@ -115,9 +115,8 @@ def bench_inputs(tl):
     return wl, plans, Ds, Us, ths, sample
 
 
-# the bench's default line runs the three-product form on one stream with the line search in tile form
-# where cheaper (frequencies 0 and 21 of the sample) and the gradient in tile form where cheaper
-# (frequency 0: tile 256)
+# the bench's default line runs the three-product form on one stream with the line search and the
+# gradient in tile form where cheaper (frequencies 0 and 21 of the sample: tile 256 and tile 128)
 @pytest.mark.parametrize("precision_name,line", [("FP32_3M", "LINE_DENSE"), ("FP32", "LINE_DENSE"),
                                                  ("FP32_3M", "LINE_TILE"), ("FP32_3M", "LINE_TILE_GRAD")])
 def test_batched_bench_configuration_sampled(tl, bench_inputs, precision_name, line):
@@ -126,7 +125,7 @@ def test_batched_bench_configuration_sampled(tl, bench_inputs, precision_name, l
     if line == "LINE_TILE":
         assert [tl.line_form(plans[i])[0] for i in sample] == [1, 1, 0, 0]
     if line == "LINE_TILE_GRAD":
-        assert [tl.line_form(plans[i], line_products=tl.LINE_TILE_GRAD)[0] for i in sample] == [2, 1, 0, 0]
+        assert [tl.line_form(plans[i], line_products=tl.LINE_TILE_GRAD)[0] for i in sample] == [2, 2, 0, 0]
     thT, fh = tl.solve_batched(plans, Ds, Us, ths, iters, precision=getattr(tl, precision_name),
                                line_products=getattr(tl, line))
     torch.cuda.synchronize()
@@ -146,7 +145,7 @@ def test_batched_bench_configuration_100_iterations(tl, bench_inputs):
     """The bench's default line for its full length: 100 iterations of all 64 frequencies (three-product
     FP32, tile-form line search where cheaper, tile-form gradient where cheaper, the residual
     recomputed from theta at iterations 20, 40, 60, 80, 100, P_theta carried between recomputes);
-    frequencies 0 (tile-form line search and gradient), 21 (tile-form line search), 42 and 63 (dense
+    frequencies 0 and 21 (tile-form line search and gradient: tiles 256 and 128), 42 and 63 (dense
     forms, tile 64 with dense diagonal tiles at 63) against 100 oracle iterations.
 
     The bar is 1e-5 in rel_f, rel_X, rel_theta and the f-history wherever FP32 arithmetic itself stays
@@ -158,7 +157,7 @@ def test_batched_bench_configuration_100_iterations(tl, bench_inputs):
     from fp32_reference import solve as solve32
     wl, plans, Ds, Us, ths, sample = bench_inputs
     iters = 100
-    assert [tl.line_form(plans[i], line_products=tl.LINE_TILE_GRAD)[0] for i in sample] == [2, 1, 0, 0]
+    assert [tl.line_form(plans[i], line_products=tl.LINE_TILE_GRAD)[0] for i in sample] == [2, 2, 0, 0]
     thT, fh = tl.solve_batched(plans, Ds, Us, ths, iters, precision=tl.FP32_3M, line_products=tl.LINE_TILE_GRAD)
     torch.cuda.synchronize()
 

@@ -78,9 +78,9 @@ def test_graph_batched_small_workload_replays_bitwise(tl):
 
 @pytest.mark.parametrize("streams", [1, 2])
 def test_graph_batched_tile_forms_replay_bitwise(tl, streams):
-    # 32 x 32 receivers, ns 512: four tiles of 256 (tile-form line search and gradient), eight tiles of
-    # 128 (tile-form line search, dense gradient) and dense diagonal tiles (dense forms); the recorded
-    # call uploads the tile-form tables
+    # 32 x 32 receivers, ns 512: four tiles of 256 and eight tiles of 128 (tile-form line search and
+    # gradient, two classes) and dense diagonal tiles (dense forms); the recorded call uploads the
+    # tile-form tables
     def case(seed, k_off, k_diag, tiles=(256,) * 4):
         nt = len(tiles)
         lay = synth.Layout(np.array(tiles), np.full(nt * (nt - 1) // 2, k_off), np.array(k_diag))
@@ -88,7 +88,7 @@ def test_graph_batched_tile_forms_replay_bitwise(tl, streams):
     devs = [to_device(c, tl, torch) for c in (case(51, 12, [9, 14, 5, 16]), case(52, 3, [-1, 4, 5, 6]),
                                               case(53, 20, [20] * 8, tiles=(128,) * 8))]
     plans, Ds, Us, ths = [d[0] for d in devs], [d[1] for d in devs], [d[2] for d in devs], [d[3] for d in devs]
-    assert [tl.line_form(p, tl.FP32_3M, tl.LINE_TILE_GRAD)[0] for p in plans] == [2, 0, 1]
+    assert [tl.line_form(p, tl.FP32_3M, tl.LINE_TILE_GRAD)[0] for p in plans] == [2, 0, 2]
     kw = dict(precision=tl.FP32_3M, line_products=tl.LINE_TILE_GRAD, streams=streams)
     iters = 12
     th_e, fh_e = tl.solve_batched(plans, Ds, Us, ths, iters, **kw)

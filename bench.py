@@ -93,7 +93,7 @@ TRAFFIC_RECORDS = {   # (precision, line-search form, product kind) -> (counter 
     ("fp32_3m", "tile_grad", "gemm_line"): ("cgemm3m_line_traffic_tile.json", ("cgemm3m.hip", "gemm_common.hpp")),
     ("fp32_3m", "tile_grad", "gemm_adjoint"): ("cgemm3m_adjoint_traffic_tile.json",
                                                ("cgemm3m.hip", "gemm_common.hpp")),
-    ("bf16x3", "tile", "gemm_line"): ("cgemm_bf16_line_traffic.json", ("cgemm_bf16.hip", "gemm_common.hpp")),
+    ("bf16x3", "tile_grad", "gemm_line"): ("cgemm_bf16_line_traffic.json", ("cgemm_bf16.hip", "gemm_common.hpp")),
 }
 
 

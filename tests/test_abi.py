@@ -144,3 +144,17 @@ def test_ctypes_structs_match_the_header(tmp_path):
         assert got[(cname, "sizeof")] == ctypes.sizeof(ct), cname
         for fname, _ in ct._fields_:
             assert got[(cname, fname)] == getattr(ct, fname).offset, (cname, fname)
+
+
+def test_graph_calls_reject_bad_arguments_without_a_device(lib):
+    """The HIP-graph calls check their arguments before any HIP call: a null stream cannot be
+    captured, nothing can be closed that was not opened, a null graph cannot be launched, and
+    destroying a null graph is a no-op."""
+    h = ctypes.c_void_p()
+    assert lib.tlrmdd_graph_begin(ctypes.c_void_p(0)) == lib_mod.INVALID_ARGUMENT
+    assert b"null stream" in lib.tlrmdd_last_error()
+    assert lib.tlrmdd_graph_end(ctypes.c_void_p(0), ctypes.byref(h)) == lib_mod.INVALID_ARGUMENT
+    assert h.value is None
+    assert lib.tlrmdd_graph_end(ctypes.c_void_p(0), None) == lib_mod.INVALID_ARGUMENT
+    assert lib.tlrmdd_graph_launch(ctypes.c_void_p(0), ctypes.c_void_p(0)) == lib_mod.INVALID_ARGUMENT
+    assert lib.tlrmdd_graph_destroy(ctypes.c_void_p(0)) == lib_mod.OK

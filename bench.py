@@ -588,6 +588,8 @@ def main():
         "objective": run["objective"],
     }
     if args.workload == "batched" and not admm and args.nfreq is None and args.extra:
+        log("tlrmdd_grad calls on the same inputs")
+        line["grad_calls"] = grad_calls(tl, torch, inputs, prec)
         log("nr 64 parity workload: microseconds per iteration")
         line["small_workload"] = small_latency(tl, torch, prec, args)
         log("nr 4096 workload (32 frequencies, inputs generated on the device)")
@@ -620,6 +622,33 @@ def device_inputs(wl, torch, tl, nfreq):
             torch.cuda.synchronize()
             log(f"device inputs {i + 1}/{nfreq} ({time.time() - t0:.1f}s)")
     return geom, Ds, Us, ths, plans
+
+
+def grad_calls(tl, torch, inputs, prec, passes=3):
+    """tlrmdd_grad called once per frequency of the workload (objective and gradient of one problem per
+    call: assembly, r = D X - U, W = D^H r, tile contractions, with D staged per call), calls per second
+    of wall time over `passes` passes of all frequencies."""
+    geom, Ds, Us, ths, plans = inputs
+    dev = torch.device("cuda")
+    perm = torch.from_numpy(tl.hilbert_order(geom.rec_ix, geom.rec_iy)).to(dev)
+    Dh = [tl.permute_columns(D, perm) for D in Ds]
+    Uh = [tl.permute_columns(U, perm) for U in Us]
+    ws = torch.empty(max(p.workspace_bytes(tl._lib.OP_GRAD) for p in plans), dtype=torch.uint8, device=dev)
+    for p, D, U, th in zip(plans, Dh, Uh, ths):   # warm-up pass
+        tl.grad(p, D, U, th, precision=prec, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(passes):
+        for p, D, U, th in zip(plans, Dh, Uh, ths):
+            tl.grad(p, D, U, th, precision=prec, workspace=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = passes * len(plans)
+    ns, nr = geom.ns, geom.nr
+    return {"calls_per_s": n / dt, "ms_per_call": dt / n * 1e3, "calls": n,
+            "dense_products_per_call": 2,
+            "complex_equiv_tflops_of_the_two_products": 2 * 8.0 * ns * nr * nr * n / dt / 1e12,
+            "note": "one frequency per call, D staged per call; inputs resident in HBM"}
 
 
 def small_latency(tl, torch, prec, args):

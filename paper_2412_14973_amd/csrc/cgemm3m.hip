@@ -24,6 +24,9 @@
 //     and r meet in one thread.
 // Epilogues as the four-product kernel: C; C = AB - U with FP64 partial sums of
 // |C|^2; a, b with the five line-search sums. K must be a multiple of 16.
+// The GM_STORE products of the tile forms may have N a multiple of 64: a last 64-column tile runs as
+// its own instantiation (HALF), in which each wave takes 32 rows of all 64 columns (one row block,
+// two column blocks) and the B tile's other 64 columns are not loaded.
 #include <algorithm>
 #include <type_traits>
 
@@ -378,7 +381,7 @@ hipError_t launch_cgemm3m(int mode, const GemmArgs &a0, int batch, hipStream_t s
     if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
     if (a.M % BM || a.N % (half_ok ? BN / 2 : BN) || a.K % BK || a.K <= 0) return hipErrorInvalidValue;
     const bool half_tile = half_ok && a.N % BN != 0;
-    a.n_half = a.tiles_n * BN;
+    a.n_half = half_tile ? a.tiles_n * BN : 0;
     if (a.K2 < 0 || a.K2 > a.K || a.K2 % BK || (a.K2 && !(mode == GM_LINE && tile_stage)))
         return hipErrorInvalidValue;
     if (a.nz3 > 1 || a.nz4 > 1) {

@@ -2251,14 +2251,18 @@ int tlrmdd_graph_begin(hipStream_t stream) {
 
 int tlrmdd_graph_end(hipStream_t stream, tlrmdd_graph *graph_out) {
     g_last_error.clear();
-    if (!graph_out) return fail(TLRMDD_INVALID_ARGUMENT, "graph_out is NULL");
-    *graph_out = nullptr;
+    if (graph_out) *graph_out = nullptr;
     if (!g_cap.on || g_cap.stream != stream)
         return fail(TLRMDD_INVALID_ARGUMENT, "no graph capture open on this stream in this thread");
+    // the capture is closed in every case below
     g_cap.on = false;
     tlrmdd_graph g = new tlrmdd_graph_s;
     g->pinned.swap(g_cap.pinned);
     hipError_t e = hipStreamEndCapture(stream, &g->graph);
+    if (!graph_out) {
+        graph_free(g);
+        return fail(TLRMDD_INVALID_ARGUMENT, "graph_out is NULL (the capture is closed, its graph dropped)");
+    }
     if (e == hipSuccess && !g->graph) e = hipErrorStreamCaptureInvalidated;
     if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {

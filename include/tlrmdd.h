@@ -405,6 +405,15 @@ typedef struct {
 int tlrmdd_timing_begin(void);
 int tlrmdd_timing_end(tlrmdd_kernel_stats *stats);
 
+/* tlrmdd_timing_begin restricted to some kinds: only launches of the kinds whose
+ * bit (1u << TLRMDD_K_*) is set in `kinds` are bracketed and counted; the others
+ * run as without timing and their stats read zero. Each bracketed launch adds two
+ * event records to its stream (a few microseconds of device time each), so timing
+ * one kind perturbs a run far less than timing all of them. Returns
+ * TLRMDD_INVALID_ARGUMENT for an empty set or a bit at or above TLRMDD_K_NKINDS.
+ * tlrmdd_timing_begin() equals this call with every kind's bit set. */
+int tlrmdd_timing_begin_kinds(uint32_t kinds);
+
 /* ---- HIP graphs of library calls ------------------------------------------
  * A fixed-count solve of one frequency (Theory section, eq. standard_solver: every
  * frequency is its own problem) is a fixed sequence of launches; at small sizes its

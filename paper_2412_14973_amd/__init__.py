@@ -455,10 +455,22 @@ def solve_batched_graph(plans, Ds, Us, thetas, fhists, iters, optimizer=LBFGS, l
 
 class KernelTimer:
     """Context manager: per kernel kind the summed launch milliseconds (HIP events on the launch
-    stream), launch count and the algorithmic work the library counted for those launches."""
+    stream), launch count and the algorithmic work the library counted for those launches.
+
+    kinds: names from KIND_NAMES to time (default: all); launches of the other kinds run untimed
+    and read zero, and each timed launch costs two event records on its stream."""
+
+    def __init__(self, kinds=None):
+        self.kinds = None if kinds is None else list(kinds)
 
     def __enter__(self):
-        _lib.check(_lib.load().tlrmdd_timing_begin(), "tlrmdd_timing_begin")
+        if self.kinds is None:
+            _lib.check(_lib.load().tlrmdd_timing_begin(), "tlrmdd_timing_begin")
+        else:
+            mask = 0
+            for k in self.kinds:
+                mask |= 1 << _lib.KIND_NAMES.index(k)
+            _lib.check(_lib.load().tlrmdd_timing_begin_kinds(mask), "tlrmdd_timing_begin_kinds")
         return self
 
     def __exit__(self, *exc):

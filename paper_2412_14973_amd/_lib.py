@@ -102,6 +102,7 @@ _SIGS = {
     "tlrmdd_workspace_bytes_tlr": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
     "tlrmdd_forward_tlr": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_size_t, ctypes.c_void_p]),
     "tlrmdd_timing_begin": (ctypes.c_int, []),
+    "tlrmdd_timing_begin_kinds": (ctypes.c_int, [ctypes.c_uint32]),
     "tlrmdd_timing_end": (ctypes.c_int, [ctypes.c_void_p]),
     "tlrmdd_graph_begin": (ctypes.c_int, [ctypes.c_void_p]),
     "tlrmdd_graph_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),

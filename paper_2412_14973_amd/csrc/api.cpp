@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -82,7 +83,7 @@ struct TimedLaunch {
 };
 struct Recorder {
     std::mutex mu;
-    bool on = false;
+    std::atomic<uint32_t> kinds{0};   // bit k set: launches of kind k are timed (0: timing off)
     std::vector<TimedLaunch> ev;
     std::vector<hipEvent_t> pool;
 } g_rec;
@@ -109,7 +110,7 @@ thread_local Capture g_cap;
 
 template <class F>
 hipError_t timed(int kind, hipStream_t s, const Work &work, F &&launch) {
-    if (!g_rec.on || g_cap.on) return launch();
+    if (!((g_rec.kinds.load(std::memory_order_relaxed) >> kind) & 1u) || g_cap.on) return launch();
     std::lock_guard<std::mutex> lk(g_rec.mu);
     hipEvent_t a = rec_event(), b = rec_event();
     if (a) (void)hipEventRecord(a, s);
@@ -2173,22 +2174,26 @@ int tlrmdd_solve_batched(int count, const tlrmdd_plan *plans, const void *const 
                        });
 }
 
-int tlrmdd_timing_begin(void) {
+int tlrmdd_timing_begin_kinds(uint32_t kinds) {
     g_last_error.clear();
+    if (kinds == 0 || (kinds >> TLRMDD_K_NKINDS) != 0)
+        return fail(TLRMDD_INVALID_ARGUMENT, "kinds: a non-empty set of bits below 1 << TLRMDD_K_NKINDS");
     std::lock_guard<std::mutex> lk(g_rec.mu);
     for (TimedLaunch &t : g_rec.ev) {
         g_rec.pool.push_back(t.a);
         g_rec.pool.push_back(t.b);
     }
     g_rec.ev.clear();
-    g_rec.on = true;
+    g_rec.kinds.store(kinds, std::memory_order_relaxed);
     return TLRMDD_OK;
 }
+
+int tlrmdd_timing_begin(void) { return tlrmdd_timing_begin_kinds((1u << TLRMDD_K_NKINDS) - 1u); }
 
 int tlrmdd_timing_end(tlrmdd_kernel_stats *stats) {
     g_last_error.clear();
     std::lock_guard<std::mutex> lk(g_rec.mu);
-    g_rec.on = false;
+    g_rec.kinds.store(0, std::memory_order_relaxed);
     tlrmdd_kernel_stats acc[TLRMDD_K_NKINDS];
     for (int k = 0; k < TLRMDD_K_NKINDS; ++k) {
         std::memset(&acc[k], 0, sizeof(acc[k]));

@@ -158,3 +158,18 @@ def test_graph_calls_reject_bad_arguments_without_a_device(lib):
     assert lib.tlrmdd_graph_end(ctypes.c_void_p(0), None) == lib_mod.INVALID_ARGUMENT
     assert lib.tlrmdd_graph_launch(ctypes.c_void_p(0), ctypes.c_void_p(0)) == lib_mod.INVALID_ARGUMENT
     assert lib.tlrmdd_graph_destroy(ctypes.c_void_p(0)) == lib_mod.OK
+
+
+def test_timing_kind_sets_without_a_device(lib):
+    """tlrmdd_timing_begin_kinds takes a non-empty set of kind bits below TLRMDD_K_NKINDS; with no
+    launch in between, timing_end reports zero for every kind."""
+    n = len(lib_mod.KIND_NAMES)
+    assert lib.tlrmdd_timing_begin_kinds(0) == lib_mod.INVALID_ARGUMENT
+    assert lib.tlrmdd_timing_begin_kinds(1 << n) == lib_mod.INVALID_ARGUMENT
+    assert lib.tlrmdd_timing_begin_kinds((1 << n) | 1) == lib_mod.INVALID_ARGUMENT
+    st = (lib_mod.c_kernel_stats * n)()
+    assert lib.tlrmdd_timing_begin_kinds(1 << lib_mod.KIND_NAMES.index("gemm_line")) == lib_mod.OK
+    assert lib.tlrmdd_timing_end(st) == lib_mod.OK
+    assert all(s.launches == 0 and s.ms == 0.0 and s.flop_dtype == lib_mod.DT_NONE for s in st)
+    assert lib.tlrmdd_timing_begin() == lib_mod.OK
+    assert lib.tlrmdd_timing_end(None) == lib_mod.OK

@@ -122,3 +122,9 @@ def test_graph_capture_argument_errors(tl):
     torch.cuda.synchronize()
     assert lib.tlrmdd_graph_destroy(h) == tl._lib.OK
     assert lib.tlrmdd_graph_launch(ctypes.c_void_p(0), sp) == tl._lib.INVALID_ARGUMENT
+    # a NULL graph_out is an error that still closes the capture: a new one opens on the stream
+    assert lib.tlrmdd_graph_begin(sp) == tl._lib.OK
+    assert lib.tlrmdd_graph_end(sp, None) == tl._lib.INVALID_ARGUMENT
+    assert lib.tlrmdd_graph_begin(sp) == tl._lib.OK
+    assert lib.tlrmdd_graph_end(sp, ctypes.byref(h)) == tl._lib.OK
+    assert lib.tlrmdd_graph_destroy(h) == tl._lib.OK

@@ -589,6 +589,8 @@ def main():
         "objective": run["objective"],
     }
     if args.workload == "batched" and not admm and args.nfreq is None and args.extra:
+        log("device copy reference")
+        line["copy_reference"] = copy_reference(torch)
         log("tlrmdd_grad calls on the same inputs")
         line["grad_calls"] = grad_calls(tl, torch, inputs, prec)
         log("nr 64 parity workload: microseconds per iteration")
@@ -624,6 +626,30 @@ def device_inputs(wl, torch, tl, nfreq):
             torch.cuda.synchronize()
             log(f"device inputs {i + 1}/{nfreq} ({time.time() - t0:.1f}s)")
     return geom, Ds, Us, ths, plans
+
+
+def copy_reference(torch, mib=1024, reps=5):
+    """A plain device-to-device copy (torch's copy kernel, `mib` MiB read and written per copy), timed
+    with events: the streaming rate this GPU reaches in practice, beside which the HBM-bound passes
+    (hbm_passes) are read."""
+    src = torch.ones(mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    b = 2.0 * (mib << 20)
+    del src, dst
+    return {"gbps": b / (ms * 1e-3) / 1e9, "frac_hbm": b / (ms * 1e-3) / HBM_PEAK, "ms": ms,
+            "bytes_per_copy": b,
+            "note": "torch copy_ of %d MiB (read + write), mean of %d: a library copy kernel, not tuned "
+                    "here; passes whose vectors partly stay in the 256 MB memory-side cache between kernels "
+                    "(theta-sized ones) can exceed it" % (mib, reps)}
 
 
 def grad_calls(tl, torch, inputs, prec, passes=3):

@@ -1397,8 +1397,10 @@ Ctx line_ctx(const Ctx &c, int p0, int np) {
 // Stage 1 of a tile range: pack the factor blocks of theta and of the direction `dir`, then
 // Pcol_(p,j) = [D_:,i A_dir(ij) ... | D_:,i A_th(ij) ...] (see LineTile), or the direction half only
 // (dir_only: the theta half is carried by P_th += step P_p in ranges with the tile-form gradient)
-int tile_stage1(Run &R, const LineSeg &sg, const float *dir, bool dir_only = false, bool theta_only = false) {
-    const Ctx c = line_ctx(R.c, sg.p0, sg.np);
+int tile_stage1(Run &R, const LineSeg &sg, const float *dir, bool dir_only = false, bool theta_only = false,
+                hipStream_t stream = nullptr) {
+    Ctx c = line_ctx(R.c, sg.p0, sg.np);
+    if (stream) c.s = stream;
     const LineTile &L = sg.lt;
     const LineClass &lc = L.lc;
     const int64_t NA = L.NA, d = lc.d, nt = lc.nt;
@@ -1427,10 +1429,11 @@ int tile_stage1(Run &R, const LineSeg &sg, const float *dir, bool dir_only = fal
 
 // [a | b] = D [X1 | X2] with the five line-search sums for the problems of a tile range (see LineTile).
 // dir_only: stage 1 forms the direction half only (the theta half is current, see tile_pcol_update).
-int line_products_tile(Run &R, const LineSeg &sg, bool dir_only = false) {
-    int st = tile_stage1(R, sg, R.c.w.p, dir_only);
+int line_products_tile(Run &R, const LineSeg &sg, bool dir_only = false, hipStream_t stream = nullptr) {
+    int st = tile_stage1(R, sg, R.c.w.p, dir_only, false, stream);
     if (st) return st;
-    const Ctx c = line_ctx(R.c, sg.p0, sg.np);
+    Ctx c = line_ctx(R.c, sg.p0, sg.np);
+    if (stream) c.s = stream;
     const LineTile &L = sg.lt;
     const LineClass &lc = L.lc;
     const int64_t NA = L.NA, d = lc.d, nt = lc.nt;
@@ -1806,16 +1809,33 @@ int run_iterate(Run &R, int iters, double lam, const float *cen, int record_base
             HIP_TRY(launch_pen(c.D.tsegs, nt, c.w.th, cen, c.w.p, c.w.partials, s));
             if ((st = fin(c, fin_args(FIN_LAMTERMS, c.w.sc), c.D.tcount, 0, 2))) return st;
         }
+        // With a side stream and several tile ranges, the tile ranges alternate between it and s once
+        // the dense ranges' product is enqueued, so that the small launches of two tile classes fill
+        // each other's last rounds of workgroups; the side stream is joined before the line sums.
+        int ntile = 0;
+        for (const LineSeg &sg : R.segs) ntile += sg.tile ? 1 : 0;
+        const bool tile_overlap = R.side && ntile > 1;
+        bool forked = false;
+        int itile = 0;
         for (const LineSeg &sg : R.segs) {
             // ranges with the tile-form gradient carry P_th from step to step (formed afresh with every
             // residual recompute, so its rounding accumulates over no more iterations than the tracked
             // residual's): stage 1 forms the direction half only where the halves fill whole tiles
             const bool dir_only = sg.tile && sg.lt.lc.grad && (sg.lt.lc.nt * sg.lt.lc.kpad) % GEMM_BN == 0;
-            if (sg.tile) st = line_products_tile(R, sg, dir_only);
+            if (sg.tile && tile_overlap && !forked) {
+                HIP_TRY(hipEventRecord(R.fork, s));
+                HIP_TRY(hipStreamWaitEvent(R.side, R.fork, 0));
+                forked = true;
+            }
+            if (sg.tile) st = line_products_tile(R, sg, dir_only, (tile_overlap && (itile++ & 1) == 0) ? R.side : s);
             else if (sg.np == c.nprob) st = gemm_line(c, R.X1, R.X2, R.xstride);
             else st = gemm_line(line_ctx(c, sg.p0, sg.np), R.X1 + sg.p0 * R.xstride, R.X2 + sg.p0 * R.xstride,
                                 R.xstride);
             if (st) return st;
+        }
+        if (forked) {
+            HIP_TRY(hipEventRecord(R.join, R.side));
+            HIP_TRY(hipStreamWaitEvent(s, R.join, 0));
         }
         {
             FinArgs f = fin_args(FIN_LINE, c.w.sc);

@@ -96,7 +96,8 @@ typedef struct {
                                tracked r accumulates FP32 rounding, 20 keeps long solves oracle-close */
     int32_t streams;        /* batched calls: 0 or 1 = all problems in one launch per phase on
                                `stream` (with one library-owned side stream on which the tile-form
-                               gradient runs beside the adjoint product of the other problems);
+                               gradient runs beside the adjoint product of the other problems, and
+                               every other tile-form line-search range beside the rest);
                                2..8 = problem i in sub-batch i % streams, each sub-batch on its own
                                stream (the first on `stream`, the others on streams the library
                                creates at default priority for each (device, caller stream) pair

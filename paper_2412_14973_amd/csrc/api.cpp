@@ -112,6 +112,8 @@ template <class F>
 hipError_t timed(int kind, hipStream_t s, const Work &work, F &&launch) {
     if (!((g_rec.kinds.load(std::memory_order_relaxed) >> kind) & 1u) || g_cap.on) return launch();
     std::lock_guard<std::mutex> lk(g_rec.mu);
+    // timing may have ended between the check and the lock: then the launch runs untimed
+    if (!((g_rec.kinds.load(std::memory_order_relaxed) >> kind) & 1u)) return launch();
     hipEvent_t a = rec_event(), b = rec_event();
     if (a) (void)hipEventRecord(a, s);
     hipError_t e = launch();

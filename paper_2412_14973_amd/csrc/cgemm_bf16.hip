@@ -70,8 +70,10 @@ __global__ __launch_bounds__(NTHREADS, 1) void cgemm_bf16x3_kernel(GemmArgsB g) 
     const int z = blockIdx.y;
     const int nb = gridDim.x;
     int pid = blockIdx.x;
+    // contiguous tile ranges per XCD, grouped by 2 tile rows: an XCD's 8 tiles of a 1024-row problem
+    // (4 row tiles of 256) are 2 rows x 4 columns, so it fetches half of A instead of all of it
     if ((nb & 7) == 0) pid = (pid & 7) * (nb >> 3) + (pid >> 3);
-    const int group_rows = 8;
+    const int group_rows = 2;
     const int per_group = group_rows * g.tiles_n;
     const int grp = pid / per_group;
     const int first_m = grp * group_rows;

@@ -412,17 +412,19 @@ __global__ __launch_bounds__(256) void theta_update_kernel(const VecSeg *__restr
                                                            double *__restrict__ part) {
     __shared__ double red[4];
     const VecSeg sg = segs[blockIdx.x];
+    // the vector loads need the segment only: they are in flight while the step is read
+    V16 v = ld16(th, sg);
+    V16 sp = ld16(p, sg);
     const SolveScalars &s = sc[sg.prob];
     const float a = (float)s.step;
     const bool frozen = s.frozen != 0;   // a non-finite step froze this problem: theta stays as is
-    V16 v = ld16(th, sg);
-    if (!frozen) {
-        V16 sp = ld16(p, sg);
 #pragma unroll
-        for (int u = 0; u < 4 * VQ; ++u) {
-            sp.v[u] = a * sp.v[u];
-            v.v[u] += sp.v[u];
-        }
+    for (int u = 0; u < 4 * VQ; ++u) {
+        sp.v[u] = a * sp.v[u];
+        const float nv = v.v[u] + sp.v[u];
+        v.v[u] = frozen ? v.v[u] : nv;
+    }
+    if (!frozen) {
         st16(th, sg, v);
         if (Sb) st16(Sb + s.head * stride2, sg, sp);
     }
@@ -443,18 +445,20 @@ __global__ __launch_bounds__(256) void resid_update_kernel(const VecSeg *__restr
                                                            double *__restrict__ part) {
     __shared__ double red[4];
     const VecSeg sg = segs[blockIdx.x];
-    const SolveScalars &s = sc[sg.prob];
-    // a non-finite step froze this problem: r stays as is (a and b read as 0, nothing written)
-    const bool frozen = s.frozen != 0;
-    const float al = frozen ? 0.f : (float)s.step;
-    const float al2 = frozen ? 0.f : (float)(s.step * s.step);
-    VecSeg sgu = sg;
-    if (frozen) sgu.n = 0;
+    // the vector loads need the segment only: they are in flight while the step is read
     V16 v = ld16(r, sg);
-    const V16 va = ld16(a, sgu), vb = ld16(b, sgu);
+    const V16 va = ld16(a, sg), vb = ld16(b, sg);
+    const SolveScalars &s = sc[sg.prob];
+    // a non-finite step froze this problem: r stays as is (the update is discarded, nothing written)
+    const bool frozen = s.frozen != 0;
+    const float al = (float)s.step;
+    const float al2 = (float)(s.step * s.step);
 #pragma unroll
-    for (int u = 0; u < 4 * VQ; ++u) v.v[u] += al * va.v[u] + al2 * vb.v[u];
-    st16(r, sgu, v);
+    for (int u = 0; u < 4 * VQ; ++u) {
+        const float nv = v.v[u] + (al * va.v[u] + al2 * vb.v[u]);
+        v.v[u] = frozen ? v.v[u] : nv;
+    }
+    if (!frozen) st16(r, sg, v);
     double acc[1] = {dot16(v, v)};
     block_sums<1>(acc, red);
     if (threadIdx.x == 0) part[sg.part] = acc[0];

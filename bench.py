@@ -13,7 +13,7 @@ three-real-product form on FP32 matrix cores (--precision fp32 for the
 four-product form, bf16x3 for the BF16 hi+lo split). The line search runs
 in tile form for the frequencies where that is cheaper (uniform tiles, Q Q^T
 diagonals, padded rank kpad with 2.5 kpad <= 0.6 d), and so does the gradient
-(its three products at most 0.6 of the adjoint product: tile 256 here);
+(its three products at most 0.6 of the adjoint product: the tile-256 and tile-128 classes here);
 --line-products tile keeps the dense gradient, dense the assembled X1, X2
 everywhere. Every phase is one launch for all 64 frequencies except the
 tile-form products: one dense launch for the frequencies that keep the dense
@@ -21,12 +21,15 @@ form, the tile-form stages per (tile size, padded rank) class.
 
 value = grad iterations per second = 64 * 100 * steps / seconds (each grad
 iteration: objective gradient, L-BFGS direction, exact line search, update).
-The roofline object describes the dominant kernel (the product kind with
-the most algorithmic flops: the line-search product [a | b] = D [X1 | X2]
-of the frequencies whose line search stays dense),
-timed with HIP events on its launch stream; achieved
-counts the algorithmic 8mnk complex flops (the 3M form executes 6mnk:
-executed_tflops / executed_frac).
+The roofline object describes the dominant kernel (the matrix-core product
+kind with the most time in one instrumented step before the timed region:
+the line-search product [a | b] = D [X1 | X2] of the frequencies whose line
+search stays dense), its launches timed with HIP events on their stream over
+the timed steps; achieved counts the real flops of the product form that
+runs (three-product FP32: 6 m n k, four-product: 8 m n k, BF16 split: 24 m n k
+BF16 flops) against that instruction type's peak, complex_equiv_tflops the
+8 m n k complex-equivalent rate, traffic the copy-calibrated HBM bytes of the
+committed counter runs while the kernel sources are unchanged.
 cpu_baseline is the FP64 oracle on a bounded sample of the same workload.
 """
 import argparse

@@ -394,9 +394,13 @@ class Graph:
         _lib.check(_lib.load().tlrmdd_graph_launch(self._h, _stream()), "tlrmdd_graph_launch")
 
     def __del__(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
-            _lib.load().tlrmdd_graph_destroy(self._h)
-            self._h = None
+        # as Plan: at interpreter exit the module globals may already be gone
+        try:
+            if getattr(self, "_h", None) is not None and self._h.value and _lib._lib is not None:
+                _lib._lib.tlrmdd_graph_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
 
 
 def _record(call, keep):

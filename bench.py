@@ -529,7 +529,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: frequencies are independent solves; "
-              "multi-GPU sharding is not part of this build (run with --gpus 1)", file=sys.stderr)
+              "multi-GPU sharding is not implemented (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
